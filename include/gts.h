@@ -1,0 +1,225 @@
+/*
+ * gts.h -- C ABI of the MI355X batched metric-tree search library (libgts.so).
+ *
+ * The library answers the two similarity queries of the GTS paper (Zhu et
+ * al., "GTS: GPU-based Tree Index for Fast Similarity Search", PACMMOD 2024)
+ * over a pivot-based metric tree kept in GPU memory:
+ *
+ *   MRQ(q, r)   = { o in O : d(q, o) <= r }                    (Definition 1)
+ *   MkNNQ(q, k) = k objects no farther from q than any other   (Definition 2)
+ *
+ * for the Euclidean metric on float32 vectors and the Levenshtein (edit)
+ * metric on byte strings, with streamed insertions and deletions (Sec. 4.3).
+ *
+ * Conventions for every call:
+ *   - Plain pointers only.  Each gts_objects says whether its arrays live in
+ *     host or device (HIP) memory; radius and k arrays are always host arrays.
+ *   - Inputs are borrowed for the duration of the call; build and insert copy
+ *     what they keep.  The caller owns a gts_index and releases it with
+ *     gts_destroy; results are owned by the library until gts_result_free.
+ *   - Every call returns a gts_status.  On failure the outputs are untouched
+ *     and gts_last_error() describes the failure (thread-local text).
+ *   - All GPU work of an index is ordered on the HIP stream given at build.
+ *     An index is not re-entrant: calls on one index must not overlap.
+ *   - Ties: answers are sorted by (distance, id) ascending, and a kNN answer
+ *     is the first min(k, number of live objects) objects in that order --
+ *     the paper's Definition 2 admits any such set; this fixes one.
+ *   - Distances: L2 answers carry Euclidean (not squared) float32 distances
+ *     computed directly from the float32 coordinates; edit answers carry
+ *     exact int32 distances.  An L2 range answer holds the objects whose
+ *     float32 distance is <= r.
+ */
+#ifndef GTS_H
+#define GTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gts_status;
+#define GTS_OK 0
+#define GTS_EINVAL (-1)   /* bad argument: null pointer, size, NaN radius ... */
+#define GTS_ENOMEM (-2)   /* device or host allocation failed, or the budget
+                             cannot hold even one query's intermediate data */
+#define GTS_EDEVICE (-3)  /* a HIP call failed (message carries its text)    */
+#define GTS_ENOTSUP (-4)  /* valid request this build does not support       */
+
+/* Metrics (Sec. 3: any metric; the paper evaluates L2 and edit distance). */
+#define GTS_L2_F32 1      /* Euclidean distance on float32 vectors            */
+#define GTS_EDIT_U8 2     /* Levenshtein distance, unit costs, on byte strings */
+
+/* Where an array lives. */
+#define GTS_HOST 0
+#define GTS_DEVICE 1
+
+/* Query execution forms. */
+#define GTS_MODE_BATCHED 0  /* whole batch through shared tiles (default)      */
+#define GTS_MODE_PLAIN 1    /* one query per workgroup, every stage fused      */
+
+/* A set of objects (or queries).
+ *   L2:   vecs = [n][dim] float32 row-major, finite values.
+ *   EDIT: chars = concatenated bytes, offsets = [n + 1] int64 start offsets
+ *         (offsets[0] = 0, non-decreasing); string i is
+ *         chars[offsets[i] .. offsets[i+1]).  Lengths must not exceed the
+ *         index's max_strlen (<= 255).
+ *   location: GTS_HOST or GTS_DEVICE for all arrays of the set. */
+typedef struct {
+    int64_t n;
+    int32_t dim;
+    int32_t location;
+    const float *vecs;
+    const uint8_t *chars;
+    const int64_t *offsets;
+} gts_objects;
+
+/* Index build options (all fields 0 -> defaults). */
+typedef struct {
+    uint64_t seed;           /* first-pivot choice of farthest-first traversal */
+    int32_t leaf_size;       /* max objects per leaf; 0 = the paper's height
+                                rule h = ceil(log_F(n + 1)) - 2 (Sec. 4.2)      */
+    int32_t max_strlen;      /* EDIT: longest accepted string (default 255)    */
+    int64_t cache_limit;     /* streamed inserts held in the cache list before
+                                the index is rebuilt (Sec. 4.3); default 4096  */
+    int64_t mem_budget_bytes;/* device bytes for a query batch's intermediate
+                                data; 0 = 1/4 of free device memory            */
+} gts_build_opts;
+
+/* Per-call query options (NULL -> defaults). */
+typedef struct {
+    int32_t mode;            /* GTS_MODE_BATCHED or GTS_MODE_PLAIN             */
+    int32_t result_location; /* GTS_HOST or GTS_DEVICE; default: the queries'  */
+    int64_t mem_budget_bytes;/* overrides the index's budget when > 0          */
+} gts_query_opts;
+
+/* Answers in CSR form: the answer of query i is entries
+ * offsets[i] .. offsets[i+1] of ids / dist.  Owned by the library. */
+typedef struct {
+    int64_t nq;
+    int64_t total;
+    int32_t location;        /* where offsets/ids/dist live                    */
+    int32_t metric;
+    int64_t *offsets;        /* [nq + 1]                                       */
+    int64_t *ids;            /* [total] object ids                             */
+    float *dist_f32;         /* [total] L2 distances (NULL for EDIT)           */
+    int32_t *dist_i32;       /* [total] edit distances (NULL for L2)           */
+    void *priv;              /* library bookkeeping; do not touch              */
+} gts_result;
+
+/* Work counters and stage times of the last query call on an index. */
+typedef struct {
+    int64_t nq;
+    int64_t node_tests;      /* (query, node) box tests evaluated              */
+    int64_t leaf_pairs;      /* surviving (query, leaf) pairs                   */
+    int64_t tile_pairs;      /* (object slab, query tile) units computed        */
+    int64_t candidates;      /* (query, object) pairs reaching verification    */
+    int64_t verified;        /* exact metric evaluations                       */
+    int64_t results;         /* answer entries                                 */
+    double ms_total;         /* wall time of the call                          */
+    double ms_stage[8];      /* device time per stage (GTS_STAGE_*)            */
+    int64_t groups;          /* query groups run one after another (>1 when the
+                                memory budget forced the two-stage split)      */
+} gts_stats;
+
+#define GTS_STAGE_PREP 0     /* query -> pivot distances, query tiles          */
+#define GTS_STAGE_BOUND 1    /* kNN radius bound                               */
+#define GTS_STAGE_NODES 2    /* node filtering                                  */
+#define GTS_STAGE_CANDS 3    /* object filtering / tile distances + compaction  */
+#define GTS_STAGE_GROUP 4    /* grouping candidates by query                    */
+#define GTS_STAGE_VERIFY 5   /* exact verification, selection and sorting       */
+#define GTS_STAGE_OUTPUT 6   /* CSR assembly                                    */
+#define GTS_STAGE_PLAIN 7    /* the fused one-query-per-workgroup kernel        */
+
+/* Index shape, for inspection and tests. */
+typedef struct {
+    int32_t metric, dim, num_pivots, fanout, levels, max_strlen;
+    int64_t n_indexed;       /* objects in the tree (live or deleted)           */
+    int64_t n_live;          /* live objects (tree + cache)                      */
+    int64_t n_cache;         /* live objects in the cache list                   */
+    int64_t n_nodes, n_leaves, n_slabs;
+    int64_t rebuilds;        /* rebuilds triggered by the cache limit            */
+    int64_t device_bytes;    /* device memory held by the index                  */
+} gts_index_info;
+
+typedef struct gts_index gts_index;
+
+/* Build an index over `objs` (ids 0..n-1 in input order).
+ * Follows the paper's construction (Sec. 4.2, Algorithms 1-3) with global
+ * pivots: num_pivots pivots by farthest-first traversal (the first one
+ * seeded), every object's distance to every pivot in a pivot table, and a
+ * balanced tree whose nodes split their objects equal-count into `fanout`
+ * children by distance to one pivot (Algorithm 3's rule: the last child
+ * takes the remainder).  Each node keeps the box of its objects' pivot
+ * distances.  Requires num_pivots in [1, 32], fanout in [2, 64], n >= 1.
+ * hip_stream: a hipStream_t (NULL = the null stream) used for all of the
+ * index's GPU work.  On success *out receives the new index. */
+gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_pivots,
+                           int32_t fanout, const gts_build_opts *opts, void *hip_stream,
+                           gts_index **out);
+
+/* Batched metric range query (Algorithm 4): answer i lists every live object
+ * o with d(Q_i, o) <= radius[i].  radius: host array [Q->n] of finite values
+ * >= 0 (for EDIT the integer part is used).  Q->n = 0 gives an empty answer.
+ * The two-stage budget (Sec. 5.1) splits the batch into groups run one after
+ * another when its intermediate data would exceed the budget; answers do not
+ * depend on it.  GTS_ENOMEM if one query alone cannot fit. */
+gts_status gts_range_query(gts_index *idx, const gts_objects *Q, const float *radius,
+                           const gts_query_opts *opts, gts_result *out);
+
+/* Batched metric kNN query (Algorithm 5 read as a range query whose radius is
+ * bounded first, Sec. 5.2): answer i holds the min(k[i], live) live objects
+ * nearest to Q_i in (distance, id) order.  k: host array [Q->n] of values
+ * >= 1. */
+gts_status gts_knn_query(gts_index *idx, const gts_objects *Q, const int32_t *k,
+                         const gts_query_opts *opts, gts_result *out);
+
+/* Mixed batch: query i is a kNN query when k != NULL and k[i] > 0, else a
+ * range query with radius[i] (radius may be NULL only when every k[i] > 0).
+ * Both kinds run through the same launches (Sec. 5: batched processing);
+ * answers follow the conventions of gts_range_query / gts_knn_query. */
+gts_status gts_search(gts_index *idx, const gts_objects *Q, const float *radius,
+                      const int32_t *k, const gts_query_opts *opts, gts_result *out);
+
+/* Streamed insertion (Sec. 4.3): the objects join the cache list, which every
+ * query scans by brute force; when the cache holds more than cache_limit
+ * objects the index is rebuilt over all live objects.  out_ids (host,
+ * [objs->n], may be NULL) receives the new ids, which increase and are never
+ * reused.  Ids stay below 2^31. */
+gts_status gts_insert(gts_index *idx, const gts_objects *objs, int64_t *out_ids);
+
+/* Streamed deletion (Sec. 4.3): an id in the cache list is removed from it;
+ * an id in the tree is marked and skipped by every later query.  ids: host
+ * array [n].  Unknown or already deleted ids are ignored; *n_deleted (may be
+ * NULL) receives the number actually deleted. */
+gts_status gts_delete(gts_index *idx, const int64_t *ids, int64_t n, int64_t *n_deleted);
+
+/* Copy a result into caller-provided buffers (same location kind as each
+ * pointer: dst_location GTS_HOST or GTS_DEVICE); any pointer may be NULL. */
+gts_status gts_result_copy(const gts_result *res, int32_t dst_location, int64_t *offsets,
+                           int64_t *ids, void *dist);
+
+/* Release a result's memory (safe on a zeroed or already freed result). */
+gts_status gts_result_free(gts_result *res);
+
+/* Release an index and all its device memory. */
+gts_status gts_destroy(gts_index *idx);
+
+/* Shape and counters of an index. */
+gts_status gts_get_info(const gts_index *idx, gts_index_info *out);
+
+/* Counters and stage times of the last query call on idx.  Stage times are
+ * recorded only while stage timing is enabled (gts_set_timing). */
+gts_status gts_get_stats(const gts_index *idx, gts_stats *out);
+
+/* Enable (1) or disable (0) per-stage HIP-event timing on idx. */
+gts_status gts_set_timing(gts_index *idx, int32_t enable);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *gts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GTS_H */

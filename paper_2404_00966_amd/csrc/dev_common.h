@@ -1,0 +1,167 @@
+// Device helpers shared by the kernels of libgts.so (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gts {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// bfloat16 (round to nearest even; inputs are finite)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// Wave primitives (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// exclusive prefix sum over the wave; *total receives the wave sum
+__device__ __forceinline__ int wave_excl_scan(int v, int *total)
+{
+    int lane = lane_id();
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Levenshtein distance by bit-parallel vertical deltas (Myers 1999; the
+// global-distance form where row 0 holds D[0][j] = j).  The pattern has up to
+// 64*W characters; peq[c * 4 + w] holds bit i of word w set iff pattern[64w+i]
+// == c (a 256-row table, 4 words per row).  Returns the exact distance when it
+// is <= cutoff, otherwise some value > cutoff (early exit as soon as the last
+// row proves the final distance exceeds cutoff: each remaining text character
+// can lower it by at most one).
+// ---------------------------------------------------------------------------
+template <int W, class PeqPtr>
+__device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_t *text, int tlen,
+                                              int cutoff)
+{
+    if (plen == 0) return tlen;
+    uint64_t VP[W], VN[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        int bits = plen - 64 * w;
+        VP[w] = bits >= 64 ? ~0ull : (bits > 0 ? ((1ull << bits) - 1ull) : 0ull);
+        VN[w] = 0ull;
+    }
+    const int topw = (plen - 1) >> 6;
+    const uint64_t topbit = 1ull << ((plen - 1) & 63);
+    int score = plen;
+    for (int j = 0; j < tlen; j++) {
+        const int c = text[j];
+        uint64_t Eq[W], Xv[W], Xh[W], HP[W], HN[W];
+        uint64_t carry = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            Eq[w] = peq[c * 4 + w];
+            Xv[w] = Eq[w] | VN[w];
+            uint64_t a = Eq[w] & VP[w];
+            uint64_t s = a + VP[w];
+            uint64_t c1 = s < a ? 1ull : 0ull;
+            uint64_t s2 = s + carry;
+            uint64_t c2 = s2 < s ? 1ull : 0ull;
+            carry = c1 | c2;
+            Xh[w] = (s2 ^ VP[w]) | Eq[w];
+            HP[w] = VN[w] | ~(Xh[w] | VP[w]);
+            HN[w] = VP[w] & Xh[w];
+        }
+        uint64_t hp_top = 0, hn_top = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++)
+            if (w == topw) { hp_top = HP[w]; hn_top = HN[w]; }
+        score += (hp_top & topbit) ? 1 : 0;
+        score -= (hn_top & topbit) ? 1 : 0;
+        // shift the horizontal deltas down one row; row 0 has delta +1
+#pragma unroll
+        for (int w = W - 1; w >= 0; w--) {
+            uint64_t inp = (w == 0) ? 1ull : (HP[w - 1] >> 63);
+            uint64_t inn = (w == 0) ? 0ull : (HN[w - 1] >> 63);
+            HP[w] = (HP[w] << 1) | inp;
+            HN[w] = (HN[w] << 1) | inn;
+        }
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            VP[w] = HN[w] | ~(Xv[w] | HP[w]);
+            VN[w] = HP[w] & Xv[w];
+        }
+        if (score - (tlen - 1 - j) > cutoff) return cutoff + 1;
+    }
+    return score;
+}
+
+template <class PeqPtr>
+__device__ __forceinline__ int myers_any(PeqPtr peq, int plen, const uint8_t *text, int tlen, int cutoff)
+{
+    if (plen <= 64) return myers_distance<1>(peq, plen, text, tlen, cutoff);
+    if (plen <= 128) return myers_distance<2>(peq, plen, text, tlen, cutoff);
+    if (plen <= 192) return myers_distance<3>(peq, plen, text, tlen, cutoff);
+    return myers_distance<4>(peq, plen, text, tlen, cutoff);
+}
+
+// ---------------------------------------------------------------------------
+// Bitonic sort of n (a power of two) 64-bit keys, ascending, by the whole
+// workgroup.  Works on LDS or global memory; begins and ends with a barrier.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void bitonic_sort(T *a, int n)
+{
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+                int lo = 2 * i - (i & (stride - 1));
+                int hi = lo + stride;
+                bool up = (lo & size) == 0;
+                T x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace dev
+}  // namespace gts

@@ -1,0 +1,204 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// libgts.so.  Nothing here is part of the C ABI (see include/gts.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gts.h"
+
+namespace gts {
+
+// ---------------------------------------------------------------------------
+// Errors: every internal failure throws gts::Error, which the C ABI layer
+// turns into a status and a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    gts_status status;
+    Error(gts_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void fail(gts_status s, const std::string &msg);
+
+#define GTS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::gts::fail(GTS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GTS_CHECK(cond, status, msg)                  \
+    do {                                              \
+        if (!(cond)) ::gts::fail((status), (msg));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Fixed shape parameters of the kernels.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;           // CDNA wavefront
+constexpr int kQTile = 64;          // queries per tile (one per lane of a wave)
+constexpr int kSlab = 256;          // objects per MFMA slab (4 waves x 64 rows)
+constexpr int kMaxPivots = 32;      // pivot table rows (padded to 8/16/32)
+constexpr int kMaxMfmaDim = 128;    // largest L2 dimension on the MFMA path
+constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
+constexpr int kSortCap = 4096;      // per-query keys sorted in LDS
+
+// Device buffer owned by the index (hipMalloc / hipFree).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b) {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            fail(GTS_ENOMEM, "hipMalloc(" + std::to_string(b) + " bytes): " + hipGetErrorString(e));
+        }
+        bytes = b;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// The index as it lives in HBM.  Objects are stored in leaf order: leaf j
+// covers positions [leaf_first[j], leaf_first[j] + leaf_cnt[j]).
+// ---------------------------------------------------------------------------
+struct Tree {
+    int32_t fanout = 2;
+    int32_t levels = 0;          // partition layers; leaves are at this depth
+    int64_t n_nodes = 1;         // (F^(levels+1) - 1) / (F - 1)
+    int64_t n_leaves = 1;        // F^levels
+    int64_t leaf0 = 0;           // node id of the first leaf
+    int32_t mpad = 8;            // pivot rows padded to 8, 16 or 32
+    DevBuf box_aos;              // float [n_nodes][2*mpad]: lo[0..mpad), hi[0..mpad)
+    DevBuf box_lo, box_hi;       // float [mpad][n_nodes] (node-major lanes)
+    DevBuf leaf_first, leaf_cnt; // int32 [n_leaves]
+};
+
+struct IndexData {
+    int32_t metric = GTS_L2_F32;
+    int64_t n = 0;               // objects in the tree (positions)
+    int32_t m = 0;               // pivots
+    // L2
+    int32_t dim = 0;             // D
+    int32_t dp = 0;              // float row stride of X32 (multiple of 4)
+    int32_t ksteps = 0;          // bf16 K-steps of 32 (D padded to 32*ksteps)
+    int64_t npad = 0;            // rows padded to a multiple of kSlab
+    DevBuf X32;                  // float [npad][dp]
+    DevBuf X16t;                 // bf16 MFMA A fragments [npad/16][ksteps][64][8]
+    DevBuf xn;                   // float [npad] ||x16||^2 (padding rows: +inf)
+    DevBuf xe;                   // float [npad] ||x16 - x32||
+    DevBuf P32;                  // float [m][dp] pivot vectors
+    DevBuf PT;                   // float [mpad][n] pivot distances (L2)
+    int64_t n_slabs = 0;
+    DevBuf slab_emax, slab_nmax; // float [n_slabs]
+    DevBuf slab_leaf_lo, slab_leaf_hi; // int32 [n_slabs]: leaves overlapping
+    // EDIT
+    int32_t max_strlen = kMaxStrlen;
+    DevBuf chars;                // uint8 [total] strings in leaf order
+    DevBuf soff;                 // int32 [n + 1]
+    DevBuf PTe;                  // uint8 [mpad][n] pivot distances (SoA)
+    DevBuf PTa;                  // uint8 [n][mpad] pivot distances (AoS)
+    DevBuf pchars;               // uint8 pivot strings
+    DevBuf poff;                 // int32 [m + 1]
+    std::vector<std::string> pivot_str;
+    // both
+    float pt_max = 0.f;          // largest pivot-table value
+    DevBuf ids;                  // uint32 [n] id at each position
+    DevBuf tomb;                 // uint32 [(n+31)/32] deleted positions
+    Tree tree;
+};
+
+// Streamed inserts not yet in the tree (the paper's cache list).
+struct CacheList {
+    int64_t cap = 0, count = 0;   // slots used (live or deleted)
+    DevBuf X32;                   // float [cap][dp] (L2)
+    DevBuf chars;                 // uint8 [cap * kMaxStrlen] (EDIT, fixed slots)
+    DevBuf slen;                  // int32 [cap]
+    DevBuf ids;                   // uint32 [cap]
+    DevBuf live;                  // uint32 [cap] 1 = live
+    std::vector<uint32_t> h_ids;
+    std::vector<uint8_t> h_live;
+    int64_t n_live = 0;           // live cached objects
+};
+
+// Host-side copy of everything needed to rebuild (the objects by id).
+struct HostObjects {
+    int32_t metric = GTS_L2_F32;
+    int32_t dim = 0;
+    std::vector<float> vecs;          // [count][dim]
+    std::vector<uint8_t> chars;
+    std::vector<int64_t> offsets{0};
+    std::vector<uint32_t> ids;        // id of each stored object
+    int64_t count() const { return (int64_t)ids.size(); }
+    void clear() { vecs.clear(); chars.clear(); offsets.assign(1, 0); ids.clear(); }
+    void append_from(const HostObjects &o, int64_t i) {
+        if (metric == GTS_L2_F32) {
+            vecs.insert(vecs.end(), o.vecs.begin() + i * dim, o.vecs.begin() + (i + 1) * dim);
+        } else {
+            chars.insert(chars.end(), o.chars.begin() + o.offsets[i], o.chars.begin() + o.offsets[i + 1]);
+            offsets.push_back((int64_t)chars.size());
+        }
+        ids.push_back(o.ids[i]);
+    }
+};
+
+// Build the tree and all device tables of `idx` over `objs` (ids given).
+void build_tree(gts_index *idx, const HostObjects &objs);
+// Rebuild over every live object (tree and cache), keeping ids.
+void rebuild(gts_index *idx);
+// Streamed updates.
+void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids);
+int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
+// Queries.
+void search(gts_index *idx, const gts_objects *Q, const float *radius, const int32_t *k,
+            const gts_query_opts *opts, gts_result *out);
+// Copy a user object set (host or device) into host memory with fresh ids
+// starting at first_id; validates values and lengths.
+void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out);
+
+}  // namespace gts
+
+// The opaque handle of the C ABI.
+struct gts_index {
+    hipStream_t stream = nullptr;
+    gts::IndexData data;
+    gts::CacheList cache;
+    gts::HostObjects host;             // objects of the tree, by position
+    gts::HostObjects cache_host;       // objects of the cache list, by slot
+    std::vector<uint8_t> h_tomb;       // host mirror of the tombstones
+    std::vector<int64_t> pos_of_id;    // id -> tree position (-1: not in tree)
+    std::vector<int64_t> slot_of_id;   // id -> cache slot (-1: not in cache)
+    hipEvent_t ev[9] = {};
+    int64_t next_id = 0;
+    int64_t n_deleted_tree = 0;
+    int64_t rebuilds = 0;
+    int32_t num_pivots = 0, fanout = 0;
+    gts_build_opts opts{};
+    bool timing = false;
+    gts_stats stats{};
+    // query workspace (grown on demand, reused across calls)
+    gts::DevBuf ws[40];
+};

@@ -1,0 +1,502 @@
+// Index construction and streamed updates (host orchestration; the distance
+// work runs in GPU kernels).
+//
+// Construction follows Sec. 4.2 with the pivots made global: m pivots are
+// chosen once by farthest-first traversal (Algorithm 2's FFT rule, first
+// pivot seeded), every object's distance to every pivot is kept in a pivot
+// table, and the tree is built layer by layer (Algorithm 1): each node sorts
+// its objects by distance to one pivot and hands them out equal-count to its
+// F children, the last child taking the remainder (Algorithm 3).  The pivot a
+// node splits on is the one whose distances spread widest inside the node.
+// Every node keeps the box [min, max] of its objects' distances to every
+// pivot, which is what the query-time filters test (Lemma 1 on all pivots).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "gts_internal.h"
+#include "kernels.h"
+
+namespace gts {
+
+namespace {
+
+uint64_t splitmix64(uint64_t *s)
+{
+    uint64_t z = (*s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+int pad_pivots(int m) { return m <= 8 ? 8 : (m <= 16 ? 16 : 32); }
+
+// Number of partition layers: the paper's height rule, or the smallest depth
+// whose average leaf holds at most leaf_size objects.
+int choose_levels(int64_t n, int F, int leaf_size)
+{
+    if (leaf_size > 0) {
+        int L = 0;
+        long double cap = 1.0L;
+        while ((long double)n / cap > (long double)leaf_size && L < 30) {
+            cap *= F;
+            L++;
+        }
+        return L;
+    }
+    int e = 0;
+    long double p = 1.0L;
+    while (p < (long double)(n + 1)) {
+        p *= F;
+        e++;
+    }
+    return std::max(0, e - 2);
+}
+
+template <class T> void upload(DevBuf &b, const std::vector<T> &v, hipStream_t st)
+{
+    b.alloc(std::max<size_t>(v.size() * sizeof(T), 16));
+    if (!v.empty()) GTS_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace
+
+void build_tree(gts_index *idx, const HostObjects &objs)
+{
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    Tree &t = d.tree;
+    const int64_t n = objs.count();
+    GTS_CHECK(n >= 1, GTS_EINVAL, "an index needs at least one object");
+    GTS_CHECK(n < (int64_t)1 << 31, GTS_ENOTSUP, "at most 2^31-1 objects per index");
+    const int m = idx->num_pivots;
+    const int F = idx->fanout;
+    const bool l2 = objs.metric == GTS_L2_F32;
+    d.metric = objs.metric;
+    d.n = n;
+    d.m = m;
+    t.mpad = pad_pivots(m);
+    const int mpad = t.mpad;
+    t.fanout = F;
+    t.levels = choose_levels(n, F, idx->opts.leaf_size);
+    {
+        long double nn = 0, lv = 1;
+        for (int l = 0; l <= t.levels; l++) {
+            nn += lv;
+            lv *= F;
+        }
+        GTS_CHECK(nn < (long double)(1 << 26), GTS_ENOTSUP, "tree too deep for this fanout (more than 2^26 nodes)");
+    }
+    t.n_nodes = 1;
+    t.n_leaves = 1;
+    t.leaf0 = 0;
+    for (int l = 0; l < t.levels; l++) {
+        t.leaf0 = t.leaf0 * F + 1;
+        t.n_leaves *= F;
+        t.n_nodes += t.n_leaves;
+    }
+
+    // ---- objects on the device in input order (temporary) -----------------
+    DevBuf in_x, in_chars, in_off, piv_buf, piv_off, dist_buf;
+    if (l2) {
+        d.dim = objs.dim;
+        d.dp = (objs.dim + 3) / 4 * 4;
+        d.ksteps = (objs.dim + 31) / 32;
+        in_x.alloc((size_t)n * d.dp * sizeof(float));
+        GTS_HIP(hipMemcpy2DAsync(in_x.p, d.dp * sizeof(float), objs.vecs.data(), objs.dim * sizeof(float),
+                                 objs.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
+        if (d.dp != d.dim)
+            GTS_HIP(hipMemset2DAsync(static_cast<char *>(in_x.p) + objs.dim * sizeof(float), d.dp * sizeof(float), 0,
+                                     (d.dp - d.dim) * sizeof(float), n, st));
+    } else {
+        upload(in_chars, objs.chars, st);
+        upload(in_off, objs.offsets, st);
+    }
+
+    // ---- pivots by farthest-first traversal -------------------------------
+    std::vector<float> PTin((size_t)m * n);       // [m][n], input order
+    std::vector<float> mind(n, INFINITY);
+    std::vector<int64_t> piv(m);
+    dist_buf.alloc((size_t)n * sizeof(float));
+    uint64_t rng = idx->opts.seed ? idx->opts.seed : 0x2404009660ULL;
+    int64_t next = (int64_t)(splitmix64(&rng) % (uint64_t)n);
+    for (int i = 0; i < m; i++) {
+        piv[i] = next;
+        if (l2) {
+            piv_buf.alloc((size_t)d.dp * sizeof(float));
+            GTS_HIP(hipMemcpyAsync(piv_buf.p, in_x.as<float>() + (size_t)next * d.dp, d.dp * sizeof(float),
+                                   hipMemcpyDeviceToDevice, st));
+            k::dist_l2_pivots(in_x.as<float>(), n, piv_buf.as<float>(), 1, 1, d.dp, dist_buf.as<float>(), 0, 1, st);
+        } else {
+            const int64_t a = objs.offsets[next], b = objs.offsets[next + 1];
+            std::vector<uint8_t> pc(objs.chars.begin() + a, objs.chars.begin() + b);
+            std::vector<int32_t> po{0, (int32_t)(b - a)};
+            upload(piv_buf, pc, st);
+            upload(piv_off, po, st);
+            k::dist_edit_pivots_f32(in_chars.as<uint8_t>(), in_off.as<int64_t>(), n, piv_buf.as<uint8_t>(),
+                                    piv_off.as<int32_t>(), 1, 1, dist_buf.as<float>(), 0, 1, st);
+        }
+        float *row = PTin.data() + (size_t)i * n;
+        GTS_HIP(hipMemcpyAsync(row, dist_buf.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        float best = -1.f;
+        int64_t arg = 0;
+        for (int64_t o = 0; o < n; o++) {
+            mind[o] = std::min(mind[o], row[o]);
+            if (mind[o] > best) {
+                best = mind[o];
+                arg = o;
+            }
+        }
+        next = arg;
+    }
+
+    // ---- layer-by-layer equal-count partition ------------------------------
+    std::vector<int64_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::vector<int64_t> nfirst(t.n_nodes, 0), ncnt(t.n_nodes, 0);
+    nfirst[0] = 0;
+    ncnt[0] = n;
+    int64_t first = 0, count = 1;
+    for (int l = 0; l < t.levels; l++) {
+        for (int64_t v = first; v < first + count; v++) {
+            const int64_t a = nfirst[v], sz = ncnt[v];
+            if (sz > 1) {
+                int best_i = 0;
+                float best_w = -1.f;
+                for (int i = 0; i < m; i++) {
+                    const float *row = PTin.data() + (size_t)i * n;
+                    float lo = INFINITY, hi = -INFINITY;
+                    for (int64_t j = a; j < a + sz; j++) {
+                        lo = std::min(lo, row[perm[j]]);
+                        hi = std::max(hi, row[perm[j]]);
+                    }
+                    if (hi - lo > best_w) {
+                        best_w = hi - lo;
+                        best_i = i;
+                    }
+                }
+                const float *row = PTin.data() + (size_t)best_i * n;
+                const std::vector<uint32_t> &ids = objs.ids;
+                std::sort(perm.begin() + a, perm.begin() + a + sz, [&](int64_t x, int64_t y) {
+                    if (row[x] != row[y]) return row[x] < row[y];
+                    return ids[x] < ids[y];
+                });
+            }
+            const int64_t avg = sz / F;
+            for (int j = 0; j < F; j++) {
+                const int64_t c = v * F + 1 + j;
+                nfirst[c] = a + j * avg;
+                ncnt[c] = (j < F - 1) ? avg : sz - avg * (F - 1);
+            }
+        }
+        first = first * F + 1;
+        count *= F;
+    }
+
+    // ---- node boxes over every pivot --------------------------------------
+    std::vector<float> lo((size_t)t.n_nodes * mpad, INFINITY), hi((size_t)t.n_nodes * mpad, -INFINITY);
+    for (int64_t j = 0; j < t.n_leaves; j++) {
+        const int64_t v = t.leaf0 + j;
+        for (int64_t p = nfirst[v]; p < nfirst[v] + ncnt[v]; p++) {
+            const int64_t o = perm[p];
+            for (int i = 0; i < m; i++) {
+                const float x = PTin[(size_t)i * n + o];
+                lo[v * mpad + i] = std::min(lo[v * mpad + i], x);
+                hi[v * mpad + i] = std::max(hi[v * mpad + i], x);
+            }
+        }
+    }
+    for (int64_t v = t.leaf0 - 1; v >= 0; v--)
+        for (int j = 0; j < F; j++) {
+            const int64_t c = v * F + 1 + j;
+            for (int i = 0; i < m; i++) {
+                lo[v * mpad + i] = std::min(lo[v * mpad + i], lo[c * mpad + i]);
+                hi[v * mpad + i] = std::max(hi[v * mpad + i], hi[c * mpad + i]);
+            }
+        }
+    for (int64_t v = 0; v < t.n_nodes; v++)
+        for (int i = m; i < mpad; i++)
+            if (ncnt[v] > 0) {
+                lo[v * mpad + i] = -INFINITY;
+                hi[v * mpad + i] = INFINITY;
+            }
+    std::vector<float> aos((size_t)t.n_nodes * 2 * mpad), blo((size_t)mpad * t.n_nodes), bhi((size_t)mpad * t.n_nodes);
+    for (int64_t v = 0; v < t.n_nodes; v++)
+        for (int i = 0; i < mpad; i++) {
+            aos[(size_t)v * 2 * mpad + i] = lo[v * mpad + i];
+            aos[(size_t)v * 2 * mpad + mpad + i] = hi[v * mpad + i];
+            blo[(size_t)i * t.n_nodes + v] = lo[v * mpad + i];
+            bhi[(size_t)i * t.n_nodes + v] = hi[v * mpad + i];
+        }
+    upload(t.box_aos, aos, st);
+    upload(t.box_lo, blo, st);
+    upload(t.box_hi, bhi, st);
+    std::vector<int32_t> lf(t.n_leaves), lc(t.n_leaves);
+    for (int64_t j = 0; j < t.n_leaves; j++) {
+        lf[j] = (int32_t)nfirst[t.leaf0 + j];
+        lc[j] = (int32_t)ncnt[t.leaf0 + j];
+    }
+    upload(t.leaf_first, lf, st);
+    upload(t.leaf_cnt, lc, st);
+
+    // ---- objects, pivot table and ids in leaf order ------------------------
+    HostObjects &h = idx->host;
+    h.metric = objs.metric;
+    h.dim = objs.dim;
+    h.clear();
+    for (int64_t p = 0; p < n; p++) h.append_from(objs, perm[p]);
+    std::vector<uint32_t> pid(n);
+    for (int64_t p = 0; p < n; p++) pid[p] = h.ids[p];
+    upload(d.ids, pid, st);
+    d.pt_max = 0.f;
+    for (float x : PTin) d.pt_max = std::max(d.pt_max, x);
+
+    if (l2) {
+        d.npad = (n + kSlab - 1) / kSlab * kSlab;
+        d.n_slabs = d.npad / kSlab;
+        d.X32.alloc((size_t)d.npad * d.dp * sizeof(float));
+        GTS_HIP(hipMemsetAsync(d.X32.p, 0, (size_t)d.npad * d.dp * sizeof(float), st));
+        GTS_HIP(hipMemcpy2DAsync(d.X32.p, d.dp * sizeof(float), h.vecs.data(), d.dim * sizeof(float),
+                                 d.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
+        d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
+        d.xn.alloc((size_t)d.npad * sizeof(float));
+        d.xe.alloc((size_t)d.npad * sizeof(float));
+        k::rows_bf16(d.X32.as<float>(), n, d.npad, d.dim, d.dp, d.ksteps, d.X16t.as<uint16_t>(), d.xn.as<float>(),
+                     d.xe.as<float>(), INFINITY, st);
+        std::vector<float> pt((size_t)mpad * n, 0.f);
+        for (int i = 0; i < m; i++)
+            for (int64_t p = 0; p < n; p++) pt[(size_t)i * n + p] = PTin[(size_t)i * n + perm[p]];
+        upload(d.PT, pt, st);
+        std::vector<float> pv((size_t)std::max(m, 1) * d.dp, 0.f);
+        for (int i = 0; i < m; i++)
+            std::copy(objs.vecs.begin() + piv[i] * d.dim, objs.vecs.begin() + (piv[i] + 1) * d.dim,
+                      pv.begin() + (size_t)i * d.dp);
+        upload(d.P32, pv, st);
+        // slab summaries: largest bf16 error and norm, leaves overlapping
+        std::vector<float> hxn(n), hxe(n);
+        GTS_HIP(hipMemcpyAsync(hxn.data(), d.xn.p, n * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(hxe.data(), d.xe.p, n * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        std::vector<float> se(d.n_slabs, 0.f), sn(d.n_slabs, 0.f);
+        std::vector<int32_t> sl(d.n_slabs, 0), sh(d.n_slabs, -1);
+        for (int64_t p = 0; p < n; p++) {
+            const int64_t s = p / kSlab;
+            se[s] = std::max(se[s], hxe[p]);
+            sn[s] = std::max(sn[s], std::sqrt(hxn[p]));
+        }
+        for (int64_t s = 0; s < d.n_slabs; s++) {
+            // rounding of the summaries themselves: a relative margin
+            se[s] = se[s] * 1.0001f + 1e-30f;
+            sn[s] = sn[s] * 1.0001f;
+            const int64_t a = s * kSlab, b = std::min<int64_t>(n, a + kSlab);   // [a, b)
+            int64_t l0 = std::upper_bound(lf.begin(), lf.end(), (int32_t)a) - lf.begin() - 1;
+            int64_t l1 = std::upper_bound(lf.begin(), lf.end(), (int32_t)(b - 1)) - lf.begin() - 1;
+            sl[s] = (int32_t)std::max<int64_t>(0, l0);
+            sh[s] = (int32_t)std::max<int64_t>(0, l1);
+        }
+        upload(d.slab_emax, se, st);
+        upload(d.slab_nmax, sn, st);
+        upload(d.slab_leaf_lo, sl, st);
+        upload(d.slab_leaf_hi, sh, st);
+    } else {
+        std::vector<int32_t> soff(n + 1);
+        for (int64_t p = 0; p <= n; p++) soff[p] = (int32_t)h.offsets[p];
+        upload(d.chars, h.chars, st);
+        upload(d.soff, soff, st);
+        std::vector<uint8_t> pte((size_t)mpad * n, 0), pta((size_t)n * mpad, 0);
+        for (int i = 0; i < m; i++)
+            for (int64_t p = 0; p < n; p++) {
+                const uint8_t v = (uint8_t)PTin[(size_t)i * n + perm[p]];
+                pte[(size_t)i * n + p] = v;
+                pta[(size_t)p * mpad + i] = v;
+            }
+        upload(d.PTe, pte, st);
+        upload(d.PTa, pta, st);
+        std::vector<uint8_t> pc;
+        std::vector<int32_t> po{0};
+        d.pivot_str.clear();
+        for (int i = 0; i < m; i++) {
+            const int64_t a = objs.offsets[piv[i]], b = objs.offsets[piv[i] + 1];
+            pc.insert(pc.end(), objs.chars.begin() + a, objs.chars.begin() + b);
+            po.push_back((int32_t)pc.size());
+            d.pivot_str.emplace_back(objs.chars.begin() + a, objs.chars.begin() + b);
+        }
+        upload(d.pchars, pc, st);
+        upload(d.poff, po, st);
+        d.npad = n;
+    }
+
+    // ---- tombstones and id maps --------------------------------------------
+    const int64_t words = (std::max(d.npad, n) + 31) / 32 + 1;
+    d.tomb.alloc((size_t)words * sizeof(uint32_t));
+    k::fill_u32(d.tomb.as<uint32_t>(), words, 0u, st);
+    idx->h_tomb.assign(n, 0);
+    idx->n_deleted_tree = 0;
+    uint32_t max_id = 0;
+    for (uint32_t id : h.ids) max_id = std::max(max_id, id);
+    idx->pos_of_id.assign(std::max<int64_t>((int64_t)max_id + 1, idx->next_id), -1);
+    for (int64_t p = 0; p < n; p++) idx->pos_of_id[h.ids[p]] = p;
+    GTS_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// Streamed updates (Sec. 4.3).
+// ---------------------------------------------------------------------------
+namespace {
+
+void cache_reserve(gts_index *idx, int64_t need)
+{
+    CacheList &c = idx->cache;
+    if (need <= c.cap) return;
+    int64_t cap = std::max<int64_t>(need, std::max<int64_t>(2 * c.cap, 64));
+    hipStream_t st = idx->stream;
+    const IndexData &d = idx->data;
+    auto grow = [&](DevBuf &b, size_t elem) {
+        DevBuf nb;
+        nb.alloc((size_t)cap * elem);
+        GTS_HIP(hipMemsetAsync(nb.p, 0, (size_t)cap * elem, st));
+        if (b.p && c.count) GTS_HIP(hipMemcpyAsync(nb.p, b.p, (size_t)c.count * elem, hipMemcpyDeviceToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        std::swap(b.p, nb.p);
+        std::swap(b.bytes, nb.bytes);
+    };
+    if (d.metric == GTS_L2_F32) grow(c.X32, (size_t)d.dp * sizeof(float));
+    else grow(c.chars, (size_t)kMaxStrlen);
+    grow(c.slen, sizeof(int32_t));
+    grow(c.ids, sizeof(uint32_t));
+    grow(c.live, sizeof(uint32_t));
+    c.cap = cap;
+}
+
+}  // namespace
+
+void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
+{
+    const int64_t n = objs.count();
+    if (n == 0) return;
+    GTS_CHECK(idx->next_id + n < ((int64_t)1 << 31), GTS_ENOTSUP, "id space exhausted (ids stay below 2^31)");
+    hipStream_t st = idx->stream;
+    CacheList &c = idx->cache;
+    const IndexData &d = idx->data;
+    cache_reserve(idx, c.count + n);
+    HostObjects &ch = idx->cache_host;
+    ch.metric = d.metric;
+    ch.dim = d.dim;
+    std::vector<uint32_t> nid(n), live(n, 1u);
+    std::vector<int32_t> len(n, 0);
+    for (int64_t i = 0; i < n; i++) {
+        nid[i] = (uint32_t)idx->next_id++;
+        if (out_ids) out_ids[i] = nid[i];
+    }
+    const int64_t s0 = c.count;
+    if (d.metric == GTS_L2_F32) {
+        GTS_HIP(hipMemcpy2DAsync(c.X32.as<float>() + (size_t)s0 * d.dp, d.dp * sizeof(float), objs.vecs.data(),
+                                 d.dim * sizeof(float), d.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<uint8_t> slots((size_t)n * kMaxStrlen, 0);
+        for (int64_t i = 0; i < n; i++) {
+            len[i] = (int32_t)(objs.offsets[i + 1] - objs.offsets[i]);
+            std::copy(objs.chars.begin() + objs.offsets[i], objs.chars.begin() + objs.offsets[i + 1],
+                      slots.begin() + (size_t)i * kMaxStrlen);
+        }
+        GTS_HIP(hipMemcpyAsync(c.chars.as<uint8_t>() + (size_t)s0 * kMaxStrlen, slots.data(), slots.size(),
+                               hipMemcpyHostToDevice, st));
+    }
+    GTS_HIP(hipMemcpyAsync(c.slen.as<int32_t>() + s0, len.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GTS_HIP(hipMemcpyAsync(c.ids.as<uint32_t>() + s0, nid.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GTS_HIP(hipMemcpyAsync(c.live.as<uint32_t>() + s0, live.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    if ((int64_t)idx->slot_of_id.size() < idx->next_id) idx->slot_of_id.resize(idx->next_id, -1);
+    if ((int64_t)idx->pos_of_id.size() < idx->next_id) idx->pos_of_id.resize(idx->next_id, -1);
+    for (int64_t i = 0; i < n; i++) {
+        ch.metric = objs.metric;
+        ch.dim = objs.dim;
+        if (objs.metric == GTS_L2_F32) {
+            ch.vecs.insert(ch.vecs.end(), objs.vecs.begin() + i * objs.dim, objs.vecs.begin() + (i + 1) * objs.dim);
+        } else {
+            ch.chars.insert(ch.chars.end(), objs.chars.begin() + objs.offsets[i],
+                            objs.chars.begin() + objs.offsets[i + 1]);
+            ch.offsets.push_back((int64_t)ch.chars.size());
+        }
+        ch.ids.push_back(nid[i]);
+        c.h_ids.push_back(nid[i]);
+        c.h_live.push_back(1);
+        idx->slot_of_id[nid[i]] = s0 + i;
+    }
+    c.count += n;
+    c.n_live += n;
+    const int64_t limit = idx->opts.cache_limit > 0 ? idx->opts.cache_limit : 4096;
+    if (c.n_live > limit) rebuild(idx);
+}
+
+int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n)
+{
+    hipStream_t st = idx->stream;
+    CacheList &c = idx->cache;
+    int64_t done = 0;
+    bool tree_changed = false;
+    for (int64_t i = 0; i < n; i++) {
+        const int64_t id = ids[i];
+        if (id < 0 || id >= idx->next_id) continue;
+        if (id < (int64_t)idx->slot_of_id.size() && idx->slot_of_id[id] >= 0) {
+            const int64_t s = idx->slot_of_id[id];
+            if (c.h_live[s]) {
+                c.h_live[s] = 0;
+                c.n_live--;
+                const uint32_t zero = 0;
+                GTS_HIP(hipMemcpyAsync(c.live.as<uint32_t>() + s, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+                GTS_HIP(hipStreamSynchronize(st));
+                idx->slot_of_id[id] = -1;
+                done++;
+            }
+            continue;
+        }
+        if (id < (int64_t)idx->pos_of_id.size() && idx->pos_of_id[id] >= 0) {
+            const int64_t p = idx->pos_of_id[id];
+            if (!idx->h_tomb[p]) {
+                idx->h_tomb[p] = 1;
+                idx->n_deleted_tree++;
+                tree_changed = true;
+                done++;
+            }
+        }
+    }
+    if (tree_changed) {
+        const IndexData &d = idx->data;
+        const int64_t words = (std::max(d.npad, d.n) + 31) / 32 + 1;
+        std::vector<uint32_t> bits(words, 0u);
+        for (int64_t p = 0; p < d.n; p++)
+            if (idx->h_tomb[p]) bits[p >> 5] |= 1u << (p & 31);
+        GTS_HIP(hipMemcpyAsync(d.tomb.p, bits.data(), words * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    }
+    return done;
+}
+
+// Rebuild over every live object (Sec. 4.3: when the cache list exceeds its
+// limit the whole index is reconstructed from the index and the cache).
+void rebuild(gts_index *idx)
+{
+    HostObjects all;
+    all.metric = idx->data.metric;
+    all.dim = idx->host.dim ? idx->host.dim : idx->cache_host.dim;
+    const HostObjects &h = idx->host;
+    for (int64_t p = 0; p < h.count(); p++)
+        if (!idx->h_tomb[p]) all.append_from(h, p);
+    const HostObjects &ch = idx->cache_host;
+    for (int64_t s = 0; s < ch.count(); s++)
+        if (idx->cache.h_live[s]) all.append_from(ch, s);
+    GTS_CHECK(all.count() >= 1, GTS_EINVAL, "cannot rebuild an index with no live objects");
+    build_tree(idx, all);
+    CacheList &c = idx->cache;
+    c.count = 0;
+    c.n_live = 0;
+    c.h_ids.clear();
+    c.h_live.clear();
+    idx->cache_host.clear();
+    std::fill(idx->slot_of_id.begin(), idx->slot_of_id.end(), -1);
+    idx->rebuilds++;
+}
+
+}  // namespace gts

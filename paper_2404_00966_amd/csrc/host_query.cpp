@@ -1,0 +1,560 @@
+// Query orchestration: one call runs a mixed batch of range and kNN queries
+// through the GPU stages, under the two-stage memory budget of Sec. 5.1.
+//
+//   prep     query -> pivot distances (Lemma 1 needs d(q, p) for every pivot),
+//            bf16 query fragments / match tables
+//   bound    kNN: an upper bound of the k-th distance (Sec. 5.2: kNN answered
+//            as a range query once that distance is bounded)
+//   nodes    layer-by-layer child test of every (query tile, node)
+//   cands    L2: bf16 MFMA distances over surviving (slab, tile) pairs;
+//            EDIT: Lemma 1 on every object of every surviving (leaf, tile)
+//   group    candidates grouped by query
+//   verify   exact distances, per-query selection, (distance, id) order
+//   output   CSR assembly
+//
+// When one batch's candidates would not fit the budget, the queries are split
+// into groups of whole 64-query tiles processed one after another (the
+// "second stage"); answers do not depend on the grouping.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "gts_internal.h"
+#include "kernels.h"
+
+namespace gts {
+
+namespace {
+
+enum Ws {
+    W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
+    W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
+    W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF
+};
+
+struct ResultPriv {
+    void *offsets = nullptr, *ids = nullptr, *dist = nullptr;
+    bool device = false;
+};
+
+template <class T> T *wsp(gts_index *idx, int slot, size_t count)
+{
+    idx->ws[slot].alloc(std::max<size_t>(count * sizeof(T), 64));
+    return idx->ws[slot].as<T>();
+}
+
+// Small device counters: [0] candidate count, [1] item count, [2] work counter
+constexpr int kSmallWords = 16;
+
+struct GroupOut {
+    std::vector<uint32_t> counts;  // per query of the group
+    DevBuf ids, dist;              // CSR pieces of the group
+    int64_t total = 0;
+};
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Reading user objects (host or device) into host memory, with validation.
+// ---------------------------------------------------------------------------
+void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out)
+{
+    GTS_CHECK(o != nullptr, GTS_EINVAL, "null object set");
+    GTS_CHECK(o->n >= 0, GTS_EINVAL, "negative object count");
+    GTS_CHECK(o->location == GTS_HOST || o->location == GTS_DEVICE, GTS_EINVAL, "bad location");
+    const hipMemcpyKind kind = o->location == GTS_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    out->metric = metric;
+    out->dim = dim;
+    out->clear();
+    const int64_t n = o->n;
+    if (metric == GTS_L2_F32) {
+        GTS_CHECK(o->dim == dim, GTS_EINVAL, "dimension mismatch");
+        if (n == 0) return;
+        GTS_CHECK(o->vecs != nullptr, GTS_EINVAL, "null vectors");
+        out->vecs.resize((size_t)n * dim);
+        GTS_HIP(hipMemcpy(out->vecs.data(), o->vecs, out->vecs.size() * sizeof(float), kind));
+        for (float v : out->vecs) GTS_CHECK(std::isfinite(v), GTS_EINVAL, "non-finite vector value");
+    } else {
+        if (n == 0) return;
+        GTS_CHECK(o->offsets != nullptr, GTS_EINVAL, "null string offsets");
+        out->offsets.resize(n + 1);
+        GTS_HIP(hipMemcpy(out->offsets.data(), o->offsets, (n + 1) * sizeof(int64_t), kind));
+        GTS_CHECK(out->offsets[0] == 0, GTS_EINVAL, "offsets[0] must be 0");
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t len = out->offsets[i + 1] - out->offsets[i];
+            GTS_CHECK(len >= 0, GTS_EINVAL, "offsets must be non-decreasing");
+            GTS_CHECK(len <= max_strlen, GTS_EINVAL,
+                      "string of length " + std::to_string(len) + " exceeds max_strlen " + std::to_string(max_strlen));
+        }
+        const int64_t total = out->offsets[n];
+        out->chars.resize(total);
+        if (total) {
+            GTS_CHECK(o->chars != nullptr, GTS_EINVAL, "null string bytes");
+            GTS_HIP(hipMemcpy(out->chars.data(), o->chars, total, kind));
+        }
+    }
+    out->ids.resize(n);
+}
+
+// ---------------------------------------------------------------------------
+// One query group [q0, q0 + ng): candidates -> verified, sorted answers.
+// Returns false when the candidates overflow `cap` (nothing produced).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Batch {
+    int64_t nq = 0;
+    bool any_knn = false;
+    int mode = GTS_MODE_BATCHED;
+};
+
+void rec(gts_index *idx, int i)
+{
+    if (idx->timing) GTS_HIP(hipEventRecord(idx->ev[i], idx->stream));
+}
+
+bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t cap, GroupOut *go,
+               double *stage_ms)
+{
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    Tree &t = d.tree;
+    const bool l2 = d.metric == GTS_L2_F32;
+    const int mpad = t.mpad;
+    k::TreeView tv{t.box_aos.as<float>(), t.box_lo.as<float>(), t.box_hi.as<float>(), t.leaf_first.as<int32_t>(),
+                   t.leaf_cnt.as<int32_t>(), t.n_nodes, t.n_leaves, t.leaf0, t.fanout, t.levels, mpad};
+    k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
+                 d.dim, d.dp, d.ksteps};
+    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
+    const int ntiles = (int)((ng + kQTile - 1) / kQTile);
+
+    float *QP = idx->ws[W_QP].as<float>() + q0 * mpad;
+    float *base = idx->ws[W_BASE].as<float>() + q0;
+    float *T = idx->ws[W_T].as<float>() + q0;
+    float *thr = idx->ws[W_THR].as<float>() + q0;
+    int32_t *kq = idx->ws[W_KQ].as<int32_t>() + q0;
+    k::QueryL2 qv{};
+    k::QueryEdit qe{};
+    if (l2) {
+        qv.Q32 = idx->ws[W_Q32].as<float>() + q0 * d.dp;
+        qv.Q16t = idx->ws[W_Q16].as<uint16_t>() + q0 * d.ksteps * 32;
+        qv.qn = idx->ws[W_QN].as<float>() + q0;
+        qv.qe = idx->ws[W_QE].as<float>() + q0;
+    } else {
+        qe.chars = idx->ws[W_QCHARS].as<uint8_t>();
+        qe.off = idx->ws[W_QOFF].as<int64_t>() + q0;
+        qe.peq = idx->ws[W_PEQ].as<uint64_t>() + q0 * 1024;
+    }
+    uint32_t *small = wsp<uint32_t>(idx, W_SMALL, kSmallWords);
+    unsigned long long *counters = idx->ws[W_COUNTERS].as<unsigned long long>();
+    k::fill_u32(small, kSmallWords, 0u, st);
+    k::Cand *cands = wsp<k::Cand>(idx, W_CANDS, cap);
+    const uint32_t *tomb = d.tomb.as<uint32_t>();
+
+    const bool plain = b.mode == GTS_MODE_PLAIN || (l2 && d.dim > kMaxMfmaDim);
+    rec(idx, 2);
+    if (plain) {
+        const int grid = (int)std::min<int64_t>(ng, 1024);
+        k::PlainArgs pa{};
+        pa.nq = ng;
+        pa.base = base;
+        pa.kq = kq;
+        pa.frontier = wsp<int32_t>(idx, W_FRONTIER, (size_t)grid * 2 * t.n_leaves);
+        pa.grid = grid;
+        pa.tomb = tomb;
+        pa.ids = d.ids.as<uint32_t>();
+        pa.out = cands;
+        pa.out_count = small + 0;
+        pa.out_cap = cap;
+        pa.counters = counters;
+        pa.delta = (float)((d.dim + 8) * 5.9604645e-8);
+        pa.pt_max = d.pt_max;
+        rec(idx, 3);
+        if (l2) k::plain_l2(tv, ov, d.P32.as<float>(), d.m, d.PT.as<float>(), qv.Q32, pa, st);
+        else k::plain_edit(tv, oe, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, d.PTe.as<uint8_t>(), qe, pa, st);
+        rec(idx, 4);
+    } else {
+        uint64_t *mask = wsp<uint64_t>(idx, W_MASK, (size_t)t.n_leaves * ntiles);
+        k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)t.n_leaves * ntiles * 2, 0u, st);
+        int32_t *items = nullptr;
+        const int64_t item_cap = t.n_leaves * ntiles;
+        if (!l2) items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
+        k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
+        rec(idx, 3);
+        if (l2) {
+            k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
+                           d.slab_leaf_hi.as<int32_t>(), d.n_slabs};
+            int dev = 0, cus = 256;
+            GTS_HIP(hipGetDevice(&dev));
+            GTS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            const int chunk = 64;
+            k::mfma_sweep(ov, sv, qv, T, ng, ntiles, mask, tomb, chunk, small + 2, cands, small + 0, cap, counters,
+                          cus * 2, st);
+        } else {
+            int32_t *qlen = idx->ws[W_QLEN].as<int32_t>() + q0;
+            k::edit_objfilter(tv, items, small + 1, item_cap, mask, ntiles, QP, thr, qlen, ng, d.PTa.as<uint8_t>(),
+                              d.soff.as<int32_t>(), tomb, cands, small + 0, cap, st);
+        }
+        rec(idx, 4);
+    }
+    // cache list: brute force, already verified
+    const CacheList &c = idx->cache;
+    if (c.n_live > 0) {
+        if (l2)
+            k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
+                             base, cands, small + 0, cap, st);
+        else
+            k::cache_scan_edit(qe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
+                               c.live.as<uint32_t>(), c.count, base, cands, small + 0, cap, st);
+    }
+    uint32_t h_small[kSmallWords];
+    GTS_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    const int64_t ncand = h_small[0];
+    if (ncand > cap) return false;
+    if (!plain && !l2 && (int64_t)h_small[1] > t.n_leaves * ntiles) fail(GTS_EDEVICE, "item list overflow");
+    idx->stats.candidates += ncand;
+    idx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
+
+    // ---- group by query ----------------------------------------------------
+    uint32_t *qcount = wsp<uint32_t>(idx, W_QCOUNT, ng + 1);
+    uint32_t *cursor = wsp<uint32_t>(idx, W_CURSOR, ng + 1);
+    int64_t *qoff = wsp<int64_t>(idx, W_QOFF64, ng + 1);
+    k::fill_u32(qcount, ng, 0u, st);
+    k::fill_u32(cursor, ng, 0u, st);
+    k::group_hist(cands, small + 0, cap, qcount, st);
+    k::scan_u32(qcount, ng, qoff, st);
+    k::Cand *grouped = wsp<k::Cand>(idx, W_GROUPED, std::max<int64_t>(ncand, 1));
+    k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, st);
+    rec(idx, 5);
+    std::vector<int64_t> h_qoff(ng + 1);
+    GTS_HIP(hipMemcpyAsync(h_qoff.data(), qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    // segments too long for LDS sort in power-of-two scratch runs
+    std::vector<int64_t> big(ng, -1);
+    int64_t scratch_words = 0;
+    bool any_big = false;
+    for (int64_t q = 0; q < ng; q++) {
+        const int64_t ns = h_qoff[q + 1] - h_qoff[q];
+        if (ns > kSortCap) {
+            int64_t p = 1;
+            while (p < ns) p <<= 1;
+            big[q] = scratch_words;
+            scratch_words += p;
+            any_big = true;
+        }
+    }
+    int64_t *big_off = nullptr;
+    uint64_t *scratch = nullptr;
+    if (any_big) {
+        big_off = wsp<int64_t>(idx, W_BIGOFF, ng);
+        GTS_HIP(hipMemcpyAsync(big_off, big.data(), ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        scratch = wsp<uint64_t>(idx, W_SCRATCH, scratch_words);
+    }
+
+    // ---- verify, select, order ------------------------------------------------
+    uint64_t *out_keys = wsp<uint64_t>(idx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
+    uint32_t *out_count = wsp<uint32_t>(idx, W_OUTCNT, ng + 1);
+    k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters};
+    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), st);
+    else k::verify_edit(va, oe, qe, st);
+    rec(idx, 6);
+
+    // ---- CSR piece of this group ---------------------------------------------
+    int64_t *res_off = wsp<int64_t>(idx, W_RESOFF, ng + 1);
+    k::scan_u32(out_count, ng, res_off, st);
+    go->counts.resize(ng);
+    GTS_HIP(hipMemcpyAsync(go->counts.data(), out_count, ng * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    int64_t total = 0;
+    GTS_HIP(hipMemcpyAsync(&total, res_off + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    go->total = total;
+    go->ids.alloc(std::max<int64_t>(total, 1) * sizeof(int64_t));
+    go->dist.alloc(std::max<int64_t>(total, 1) * sizeof(float));
+    k::csr_write(out_keys, qoff, out_count, res_off, ng, l2 ? 0 : 1, go->ids.as<int64_t>(), go->dist.as<float>(),
+                 go->dist.as<int32_t>(), st);
+    rec(idx, 7);
+    GTS_HIP(hipStreamSynchronize(st));
+    if (idx->timing) {
+        float ms;
+        const int stage_of[] = {-1, -1, -1, GTS_STAGE_NODES, GTS_STAGE_CANDS, GTS_STAGE_GROUP, GTS_STAGE_VERIFY,
+                                GTS_STAGE_OUTPUT};
+        for (int i = 3; i <= 7; i++) {
+            GTS_HIP(hipEventElapsedTime(&ms, idx->ev[i - 1], idx->ev[i]));
+            int s = stage_of[i];
+            if (plain && i == 4) s = GTS_STAGE_PLAIN;
+            stage_ms[s] += ms;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+void search(gts_index *idx, const gts_objects *Q, const float *radius, const int32_t *kin,
+            const gts_query_opts *opts, gts_result *out)
+{
+    const double t_start = now_ms();
+    GTS_CHECK(out != nullptr, GTS_EINVAL, "null result");
+    GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    const bool l2 = d.metric == GTS_L2_F32;
+    const int mpad = d.tree.mpad;
+    Batch b;
+    b.nq = Q->n;
+    GTS_CHECK(b.nq >= 0, GTS_EINVAL, "negative query count");
+    GTS_CHECK(b.nq < ((int64_t)1 << 31), GTS_ENOTSUP, "too many queries in one call");
+    b.mode = opts ? opts->mode : GTS_MODE_BATCHED;
+    GTS_CHECK(b.mode == GTS_MODE_BATCHED || b.mode == GTS_MODE_PLAIN, GTS_EINVAL, "bad mode");
+    const int rloc = opts && (opts->result_location == GTS_HOST || opts->result_location == GTS_DEVICE)
+                         ? opts->result_location
+                         : Q->location;
+    const int64_t nq = b.nq;
+    // per-query kind, radius, k
+    std::vector<int32_t> hk(nq, 0);
+    std::vector<float> hbase(nq, 0.f);
+    for (int64_t q = 0; q < nq; q++) {
+        const int kk = kin ? kin[q] : 0;
+        if (kin && kk < 0) fail(GTS_EINVAL, "k must be >= 1");
+        if (kk > 0) {
+            hk[q] = kk;
+            b.any_knn = true;
+        } else {
+            GTS_CHECK(radius != nullptr, GTS_EINVAL, "radius array required for range queries");
+            const float r = radius[q];
+            GTS_CHECK(std::isfinite(r) && r >= 0.f, GTS_EINVAL, "radius must be finite and >= 0");
+            hbase[q] = r;
+        }
+    }
+    idx->stats = gts_stats{};
+    idx->stats.nq = nq;
+    std::memset(out, 0, sizeof(*out));
+    out->nq = nq;
+    out->metric = d.metric;
+    out->location = rloc;
+    double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx->timing && !idx->ev[0])
+        for (int i = 0; i < 9; i++) GTS_HIP(hipEventCreate(&idx->ev[i]));
+    rec(idx, 0);
+
+    // ---- queries into the workspace -----------------------------------------------
+    const int64_t ntiles_all = (nq + kQTile - 1) / kQTile;
+    const int64_t nqpad = std::max<int64_t>(ntiles_all * kQTile, kQTile);
+    wsp<float>(idx, W_QP, (size_t)nqpad * mpad);
+    float *base = wsp<float>(idx, W_BASE, nqpad);
+    wsp<float>(idx, W_T, nqpad);
+    wsp<float>(idx, W_THR, nqpad);
+    int32_t *kq = wsp<int32_t>(idx, W_KQ, nqpad);
+    int32_t *home = wsp<int32_t>(idx, W_HOME, nqpad);
+    unsigned long long *counters = wsp<unsigned long long>(idx, W_COUNTERS, 8);
+    k::fill_u32(reinterpret_cast<uint32_t *>(counters), 16, 0u, st);
+    if (nq > 0) {
+        GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
+    const hipMemcpyKind in_kind = Q->location == GTS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    k::QueryL2 qv{};
+    k::QueryEdit qe{};
+    if (nq > 0 && l2) {
+        GTS_CHECK(Q->dim == d.dim, GTS_EINVAL, "query dimension differs from the index");
+        GTS_CHECK(Q->vecs != nullptr, GTS_EINVAL, "null query vectors");
+        if (Q->location == GTS_HOST)
+            for (int64_t i = 0; i < nq * d.dim; i++)
+                GTS_CHECK(std::isfinite(Q->vecs[i]), GTS_EINVAL, "non-finite query value");
+        float *Q32 = wsp<float>(idx, W_Q32, (size_t)nqpad * d.dp);
+        GTS_HIP(hipMemsetAsync(Q32, 0, (size_t)nqpad * d.dp * sizeof(float), st));
+        GTS_HIP(hipMemcpy2DAsync(Q32, d.dp * sizeof(float), Q->vecs, d.dim * sizeof(float), d.dim * sizeof(float), nq,
+                                 in_kind, st));
+        uint16_t *Q16 = wsp<uint16_t>(idx, W_Q16, (size_t)nqpad * d.ksteps * 32);
+        float *qn = wsp<float>(idx, W_QN, nqpad);
+        float *qerr = wsp<float>(idx, W_QE, nqpad);
+        k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, Q16, qn, qerr, 0.f, st);
+        k::dist_l2_pivots(Q32, nq, d.P32.as<float>(), d.m, mpad, d.dp, idx->ws[W_QP].as<float>(), 1, mpad, st);
+        qv = k::QueryL2{Q32, Q16, qn, qerr};
+    } else if (nq > 0) {
+        GTS_CHECK(Q->offsets != nullptr, GTS_EINVAL, "null query offsets");
+        std::vector<int64_t> hoff(nq + 1);
+        GTS_HIP(hipMemcpy(hoff.data(), Q->offsets, (nq + 1) * sizeof(int64_t),
+                          Q->location == GTS_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+        GTS_CHECK(hoff[0] == 0, GTS_EINVAL, "query offsets[0] must be 0");
+        std::vector<int32_t> qlen(nq);
+        for (int64_t q = 0; q < nq; q++) {
+            const int64_t len = hoff[q + 1] - hoff[q];
+            GTS_CHECK(len >= 0 && len <= d.max_strlen, GTS_EINVAL, "query string length out of range");
+            qlen[q] = (int32_t)len;
+        }
+        uint8_t *qc = wsp<uint8_t>(idx, W_QCHARS, std::max<int64_t>(hoff[nq], 1));
+        if (hoff[nq]) {
+            GTS_CHECK(Q->chars != nullptr, GTS_EINVAL, "null query bytes");
+            GTS_HIP(hipMemcpyAsync(qc, Q->chars, hoff[nq], in_kind, st));
+        }
+        int64_t *qo = wsp<int64_t>(idx, W_QOFF, nqpad + 1);
+        GTS_HIP(hipMemcpyAsync(qo, hoff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        int32_t *ql = wsp<int32_t>(idx, W_QLEN, nqpad);
+        GTS_HIP(hipMemcpyAsync(ql, qlen.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        uint64_t *peq = wsp<uint64_t>(idx, W_PEQ, (size_t)nqpad * 1024);
+        k::build_peq(qc, qo, nq, peq, st);
+        k::dist_edit_pivots_f32(qc, qo, nq, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, mpad,
+                                idx->ws[W_QP].as<float>(), 1, mpad, st);
+        qe = k::QueryEdit{qc, qo, peq};
+        GTS_HIP(hipStreamSynchronize(st));
+    }
+    rec(idx, 1);
+
+    // ---- kNN bound ------------------------------------------------------------------
+    k::TreeView tv{d.tree.box_aos.as<float>(), d.tree.box_lo.as<float>(), d.tree.box_hi.as<float>(),
+                   d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.tree.n_nodes,
+                   d.tree.n_leaves, d.tree.leaf0, d.tree.fanout, d.tree.levels, mpad};
+    if (nq > 0 && b.any_knn) {
+        const int win = 256;
+        if (l2) {
+            k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
+                         d.dim, d.dp, d.ksteps};
+            k::bound_l2(tv, ov, qv, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), win, base, home, st);
+        } else {
+            k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
+            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), win, base, home, st);
+        }
+    }
+    const float delta = (float)((d.dim + 8) * 5.9604645e-8);
+    if (nq > 0)
+        k::thresholds(base, idx->ws[W_QP].as<float>(), nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
+                      idx->ws[W_T].as<float>(), idx->ws[W_THR].as<float>(), st);
+    rec(idx, 2);
+    if (idx->timing && nq > 0) {
+        GTS_HIP(hipStreamSynchronize(st));
+        float ms;
+        GTS_HIP(hipEventElapsedTime(&ms, idx->ev[0], idx->ev[1]));
+        stage_ms[GTS_STAGE_PREP] += ms;
+        GTS_HIP(hipEventElapsedTime(&ms, idx->ev[1], idx->ev[2]));
+        stage_ms[GTS_STAGE_BOUND] += ms;
+    }
+
+    // ---- groups of whole tiles under the budget -------------------------------------
+    int64_t budget = opts && opts->mem_budget_bytes > 0 ? opts->mem_budget_bytes : idx->opts.mem_budget_bytes;
+    if (budget <= 0) budget = (int64_t)1 << 32;
+    const int64_t per_cand = 2 * (int64_t)sizeof(k::Cand) + (int64_t)sizeof(uint64_t);
+    int64_t cap = std::max<int64_t>(budget / per_cand, 1024);
+    std::vector<GroupOut> groups;
+    std::vector<std::pair<int64_t, int64_t>> todo;  // (q0, ng), processed front to back
+    if (nq > 0) todo.push_back({0, nq});
+    while (!todo.empty()) {
+        auto [q0, ng] = todo.front();
+        todo.erase(todo.begin());
+        GroupOut go;
+        if (run_group(idx, b, q0, ng, cap, &go, stage_ms)) {
+            groups.push_back(std::move(go));
+            continue;
+        }
+        const int64_t tiles = (ng + kQTile - 1) / kQTile;
+        GTS_CHECK(tiles > 1, GTS_ENOMEM,
+                  "the memory budget cannot hold the candidates of one 64-query tile; raise mem_budget_bytes");
+        const int64_t half = (tiles / 2) * kQTile;
+        todo.insert(todo.begin(), {q0 + half, ng - half});
+        todo.insert(todo.begin(), {q0, half});
+    }
+
+    // ---- final CSR --------------------------------------------------------------------
+    int64_t total = 0;
+    for (auto &g : groups) total += g.total;
+    std::vector<int64_t> offs(nq + 1, 0);
+    {
+        int64_t q = 0;
+        for (auto &g : groups)
+            for (uint32_t c : g.counts) {
+                offs[q + 1] = offs[q] + c;
+                q++;
+            }
+    }
+    auto *priv = new ResultPriv();
+    priv->device = rloc == GTS_DEVICE;
+    const size_t dist_bytes = std::max<int64_t>(total, 1) * sizeof(float);
+    const size_t id_bytes = std::max<int64_t>(total, 1) * sizeof(int64_t);
+    const size_t off_bytes = (nq + 1) * sizeof(int64_t);
+    hipError_t e1, e2, e3;
+    if (priv->device) {
+        e1 = hipMalloc(&priv->offsets, off_bytes);
+        e2 = hipMalloc(&priv->ids, id_bytes);
+        e3 = hipMalloc(&priv->dist, dist_bytes);
+    } else {
+        e1 = hipHostMalloc(&priv->offsets, off_bytes, hipHostMallocDefault);
+        e2 = hipHostMalloc(&priv->ids, id_bytes, hipHostMallocDefault);
+        e3 = hipHostMalloc(&priv->dist, dist_bytes, hipHostMallocDefault);
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        gts_result tmp{};
+        tmp.priv = priv;
+        if (priv->device) {
+            if (priv->offsets) (void)hipFree(priv->offsets);
+            if (priv->ids) (void)hipFree(priv->ids);
+            if (priv->dist) (void)hipFree(priv->dist);
+        } else {
+            if (priv->offsets) (void)hipHostFree(priv->offsets);
+            if (priv->ids) (void)hipHostFree(priv->ids);
+            if (priv->dist) (void)hipHostFree(priv->dist);
+        }
+        delete priv;
+        fail(GTS_ENOMEM, "result allocation failed");
+    }
+    const hipMemcpyKind to = priv->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    GTS_HIP(hipMemcpyAsync(priv->offsets, offs.data(), off_bytes,
+                           priv->device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
+    int64_t at = 0;
+    for (auto &g : groups) {
+        if (g.total) {
+            GTS_HIP(hipMemcpyAsync(static_cast<int64_t *>(priv->ids) + at, g.ids.p, g.total * sizeof(int64_t), to, st));
+            GTS_HIP(hipMemcpyAsync(static_cast<float *>(priv->dist) + at, g.dist.p, g.total * sizeof(float), to, st));
+        }
+        at += g.total;
+    }
+    GTS_HIP(hipStreamSynchronize(st));
+    out->total = total;
+    out->offsets = static_cast<int64_t *>(priv->offsets);
+    out->ids = static_cast<int64_t *>(priv->ids);
+    if (l2) out->dist_f32 = static_cast<float *>(priv->dist);
+    else out->dist_i32 = static_cast<int32_t *>(priv->dist);
+    out->priv = priv;
+
+    // ---- counters ----------------------------------------------------------------------
+    unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GTS_HIP(hipMemcpy(hc, counters, sizeof(hc), hipMemcpyDeviceToHost));
+    idx->stats.node_tests = (int64_t)hc[0];
+    if (idx->stats.leaf_pairs == 0) idx->stats.leaf_pairs = (int64_t)hc[1];
+    idx->stats.tile_pairs = (int64_t)hc[2];
+    idx->stats.verified = (int64_t)hc[3];
+    idx->stats.results = total;
+    for (int i = 0; i < 8; i++) idx->stats.ms_stage[i] = stage_ms[i];
+    idx->stats.groups = (int64_t)groups.size();
+    idx->stats.ms_total = now_ms() - t_start;
+}
+
+void free_result(gts_result *r)
+{
+    if (!r || !r->priv) return;
+    auto *p = static_cast<ResultPriv *>(r->priv);
+    if (p->device) {
+        if (p->offsets) (void)hipFree(p->offsets);
+        if (p->ids) (void)hipFree(p->ids);
+        if (p->dist) (void)hipFree(p->dist);
+    } else {
+        if (p->offsets) (void)hipHostFree(p->offsets);
+        if (p->ids) (void)hipHostFree(p->ids);
+        if (p->dist) (void)hipHostFree(p->dist);
+    }
+    delete p;
+    std::memset(r, 0, sizeof(*r));
+}
+
+bool result_on_device(const gts_result *r)
+{
+    return r && r->priv && static_cast<const ResultPriv *>(r->priv)->device;
+}
+
+}  // namespace gts

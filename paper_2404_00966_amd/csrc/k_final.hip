@@ -1,0 +1,302 @@
+// Candidate grouping by query, exact verification with per-query selection
+// and (distance, id) ordering, and CSR assembly.
+#include "dev_common.h"
+#include "gts_internal.h"
+#include "kernels.h"
+
+namespace gts {
+namespace k {
+
+enum { CNT_VERIFIED = 3 };
+
+__global__ void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
+                             uint32_t *__restrict__ qcount)
+{
+    int64_t n = *count;
+    if (n > cap) n = cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&qcount[c[i].q], 1u);
+}
+
+void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_group_hist, dim3(2048), dim3(256), 0, st, c, count, cap, qcount);
+}
+
+// Exclusive scan of n counts into out[0..n], one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *__restrict__ in, int64_t n,
+                                                   int64_t *__restrict__ out)
+{
+    __shared__ int64_t s[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t a = (int64_t)t * per;
+    const int64_t b = a + per < n ? a + per : n;
+    int64_t sum = 0;
+    for (int64_t i = a; i < b; i++) sum += in[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    int64_t run = s[t] - sum;
+    for (int64_t i = a; i < b; i++) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (t == 1023) out[n] = s[1023];
+}
+
+void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, in, n, out);
+}
+
+__global__ void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
+                                const int64_t *__restrict__ qoff, uint32_t *__restrict__ cursor,
+                                Cand *__restrict__ grouped)
+{
+    int64_t n = *count;
+    if (n > cap) n = cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const Cand cd = c[i];
+        const uint32_t slot = atomicAdd(&cursor[cd.q], 1u);
+        grouped[qoff[cd.q] + slot] = cd;
+    }
+}
+
+void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
+                   Cand *grouped, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped);
+}
+
+// Sort the keys of one query (in LDS or, for a large segment, in its
+// power-of-two scratch run) and write the first `keep` to out.
+__device__ void sort_and_emit(uint64_t *keys, int nk, int64_t cap, int k, uint64_t *out, uint32_t *out_count_q)
+{
+    const int P = dev::next_pow2(nk > 1 ? nk : 1);
+    for (int i = nk + threadIdx.x; i < P && i < cap; i += blockDim.x) keys[i] = ~0ull;
+    dev::bitonic_sort(keys, P);
+    const int nout = (k > 0 && k < nk) ? k : nk;
+    for (int j = threadIdx.x; j < nout; j += blockDim.x) out[j] = keys[j];
+    if (threadIdx.x == 0) *out_count_q = (uint32_t)nout;
+}
+
+// ---------------------------------------------------------------------------
+// L2: per query, one workgroup.  kNN queries first keep only candidates
+// whose distance interval can reach the k smallest upper bounds: from the
+// bf16 estimate e of d^2, d lies in [sqrt(e - eps) - eq - ex,
+// sqrt(e + eps) + eq + ex].  Then each kept candidate gets its exact float32
+// distance (direct difference, 16 lanes per candidate); range queries keep
+// d <= r, kNN queries keep everything; keys are sorted by (d, id).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr, const L2View &o, float eps_a,
+                                            float eps_b, float eps_c, float delta, float *lo, float *hi)
+{
+    if (c.pos < 0) {
+        const float d = __uint_as_float((uint32_t)(c.val >> 32));
+        *lo = d * (1.f - 2.f * delta);
+        *hi = d * (1.f + 2.f * delta);
+        return;
+    }
+    const float est = __uint_as_float((uint32_t)c.val);
+    const float xnn = o.xn[c.pos];
+    const float eps = eps_a * (qnn + xnn) + eps_b * sqrtf(qnn * xnn) + eps_c * fabsf(est);
+    const float err = qerr + o.xe[c.pos];
+    *hi = sqrtf(fmaxf(est + eps, 0.f)) + err;
+    *lo = sqrtf(fmaxf(est - eps, 0.f)) - err;
+}
+
+__global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
+                                                   float eps_b, float eps_c)
+{
+    __shared__ uint64_t s_keys[kSortCap];
+    __shared__ int s_n;
+    __shared__ float s_ub;
+    const int64_t q = blockIdx.x;
+    if (q >= a.nq) return;
+    const int64_t seg0 = a.qoff[q];
+    const int ns = (int)(a.qoff[q + 1] - seg0);
+    const int k = a.kq ? a.kq[q] : 0;
+    const float base = a.base[q];
+    const int64_t boff = a.big_off ? a.big_off[q] : -1;
+    const bool big = boff >= 0;
+    uint64_t *keys = big ? a.scratch + boff : s_keys;
+    const int64_t cap = big ? dev::next_pow2(ns) : kSortCap;
+    const float qnn = qv.qn[q];
+    const float qerr = qv.qe[q];
+    const Cand *g = a.grouped + seg0;
+
+    if (threadIdx.x == 0) {
+        s_n = 0;
+        s_ub = INFINITY;
+    }
+    if (k > 0 && ns > k && !big) {
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            float lo, hi;
+            l2_interval(g[i], qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            s_keys[i] = (uint64_t)__float_as_uint(hi);
+        }
+        const int P = dev::next_pow2(ns);
+        for (int i = ns + threadIdx.x; i < P; i += blockDim.x) s_keys[i] = ~0ull;
+        dev::bitonic_sort(s_keys, P);
+        if (threadIdx.x == 0) s_ub = __uint_as_float((uint32_t)s_keys[k - 1]) * (1.f + 4.f * delta);
+    }
+    __syncthreads();
+    const float ub = s_ub;
+    const int grp = threadIdx.x >> 4, sl = threadIdx.x & 15;
+    const float *qrow = qv.Q32 + (size_t)q * o.dp;
+    long long verified = 0;
+    for (int i0 = 0; i0 < ns; i0 += 16) {
+        const int i = i0 + grp;
+        const bool valid = i < ns;
+        Cand c;
+        c.q = 0;
+        c.pos = -1;
+        c.val = 0;
+        if (valid) c = g[i];
+        bool need = valid && c.pos >= 0;
+        if (need && k > 0 && ub < INFINITY) {
+            float lo, hi;
+            l2_interval(c, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            need = lo <= ub;
+        }
+        float acc = 0.f;
+        if (need) {
+            const float *x = o.X32 + (size_t)c.pos * o.dp;
+            for (int d = sl; d < o.dp; d += 16) {
+                const float df = qrow[d] - x[d];
+                acc = fmaf(df, df, acc);
+            }
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        if (sl == 0 && valid) {
+            bool keep = false;
+            uint64_t key = 0;
+            if (c.pos < 0) {
+                keep = true;
+                key = c.val;
+            } else if (need) {
+                verified++;
+                const float d = sqrtf(acc);
+                keep = k > 0 || d <= base;
+                key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
+            }
+            if (keep) {
+                const int slot = atomicAdd(&s_n, 1);
+                keys[slot] = key;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x % 16 == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    const int nk = s_n;
+    sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
+}
+
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, hipStream_t st)
+{
+    if (a.nq == 0) return;
+    const float u = 5.9604645e-8f;
+    const int D = o.ksteps * 32;
+    const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
+    hipLaunchKernelGGL(k_verify_l2, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c);
+}
+
+// ---------------------------------------------------------------------------
+// EDIT: per query, one workgroup; the query's match table sits in LDS and
+// every lane verifies one candidate (object string as the text) with the
+// early-exit cutoff floor(base); kept keys are sorted by (d, id).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, QueryEdit qv)
+{
+    __shared__ uint64_t s_keys[kSortCap];
+    __shared__ uint64_t s_peq[256 * 4];
+    __shared__ int s_n;
+    const int64_t q = blockIdx.x;
+    if (q >= a.nq) return;
+    const int64_t seg0 = a.qoff[q];
+    const int ns = (int)(a.qoff[q + 1] - seg0);
+    const int k = a.kq ? a.kq[q] : 0;
+    const int cut = (int)floorf(fminf(a.base[q], 1e6f));
+    const int64_t boff = a.big_off ? a.big_off[q] : -1;
+    const bool big = boff >= 0;
+    uint64_t *keys = big ? a.scratch + boff : s_keys;
+    const int64_t cap = big ? dev::next_pow2(ns) : kSortCap;
+    const Cand *g = a.grouped + seg0;
+    const uint64_t *pq = qv.peq + (size_t)q * 256 * 4;
+    for (int i = threadIdx.x; i < 256 * 4; i += blockDim.x) s_peq[i] = pq[i];
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const int plen = (int)(qv.off[q + 1] - qv.off[q]);
+    long long verified = 0;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+        const Cand c = g[i];
+        bool keep = false;
+        uint64_t key = 0;
+        if (c.pos < 0) {
+            keep = true;
+            key = c.val;
+        } else {
+            const int32_t s0 = o.soff[c.pos];
+            const int tl = o.soff[c.pos + 1] - s0;
+            verified++;
+            const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut);
+            if (d <= cut) {
+                keep = true;
+                key = ((uint64_t)(uint32_t)d << 32) | a.ids[c.pos];
+            }
+        }
+        if (keep) {
+            const int slot = atomicAdd(&s_n, 1);
+            keys[slot] = key;
+        }
+    }
+    __syncthreads();
+    if (verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    const int nk = s_n;
+    sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
+}
+
+void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st)
+{
+    if (a.nq == 0) return;
+    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
+}
+
+// ---------------------------------------------------------------------------
+// CSR assembly.
+// ---------------------------------------------------------------------------
+__global__ void k_csr_write(const uint64_t *__restrict__ out_keys, const int64_t *__restrict__ qoff,
+                            const uint32_t *__restrict__ out_count, const int64_t *__restrict__ res_off, int64_t nq,
+                            int is_edit, int64_t *__restrict__ ids, float *__restrict__ dist_f,
+                            int32_t *__restrict__ dist_i)
+{
+    const int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    const uint32_t cnt = out_count[q];
+    const int64_t src = qoff[q], dst = res_off[q];
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint64_t key = out_keys[src + j];
+        ids[dst + j] = (int64_t)(uint32_t)key;
+        const uint32_t hi = (uint32_t)(key >> 32);
+        if (is_edit) dist_i[dst + j] = (int32_t)hi;
+        else dist_f[dst + j] = __uint_as_float(hi);
+    }
+}
+
+void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,
+               int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_csr_write, dim3((unsigned)nq), dim3(64), 0, st, out_keys, qoff, out_count, res_off, nq,
+                       is_edit, ids, dist_f, dist_i);
+}
+
+}  // namespace k
+}  // namespace gts

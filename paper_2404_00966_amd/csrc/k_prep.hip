@@ -1,0 +1,219 @@
+// Preparation kernels: bf16 MFMA fragments of object / query rows with their
+// norms and rounding errors, distances to pivots (both metrics), and the
+// match-bit tables of query strings.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace gts {
+namespace k {
+
+// One thread per row.  Writes the row rounded to bf16 in the MFMA fragment
+// layout [row/16][kstep][lane][8] where lane = row%16 + 16*g holds columns
+// 32*kstep + 8*g .. +7 (zero beyond dim), plus ||x16||^2 and ||x16 - x||.
+// Rows >= rows_valid are padding: zero fragments, norm2 = pad_norm2, err = 0.
+__global__ void k_rows_bf16(const float *__restrict__ X, int64_t rows_valid, int64_t rows_pad, int dim,
+                            int stride, int ksteps, uint16_t *__restrict__ frag, float *__restrict__ norm2,
+                            float *__restrict__ err, float pad_norm2)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_pad) return;
+    const bool valid = r < rows_valid;
+    const float *x = X + (size_t)r * stride;
+    float n2 = 0.f, e2 = 0.f;
+    const int64_t g = r >> 4;
+    const int rr = (int)(r & 15);
+    for (int s = 0; s < ksteps; s++) {
+        for (int q4 = 0; q4 < 4; q4++) {
+            uint16_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                int c = 32 * s + 8 * q4 + e;
+                float v = (valid && c < dim) ? x[c] : 0.f;
+                h[e] = dev::f32_to_bf16(v);
+                float b = dev::bf16_to_f32(h[e]);
+                n2 = fmaf(b, b, n2);
+                float d = b - v;
+                e2 = fmaf(d, d, e2);
+            }
+            uint4 packed;
+            packed.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            packed.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+            packed.z = (uint32_t)h[4] | ((uint32_t)h[5] << 16);
+            packed.w = (uint32_t)h[6] | ((uint32_t)h[7] << 16);
+            size_t lane = (size_t)(rr + 16 * q4);
+            *reinterpret_cast<uint4 *>(frag + (((size_t)g * ksteps + s) * 64 + lane) * 8) = packed;
+        }
+    }
+    norm2[r] = valid ? n2 : pad_norm2;
+    err[r] = valid ? sqrtf(e2) : 0.f;
+}
+
+void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, int stride, int ksteps,
+               uint16_t *frag, float *norm2, float *err, float pad_norm2, hipStream_t st)
+{
+    if (rows_pad == 0) return;
+    int blocks = (int)((rows_pad + 255) / 256);
+    hipLaunchKernelGGL(k_rows_bf16, dim3(blocks), dim3(256), 0, st, X, rows_valid, rows_pad, dim, stride,
+                       ksteps, frag, norm2, err, pad_norm2);
+}
+
+// out[i * s_piv + r * s_row] = || X[r] - P[i] ||  (float32, direct difference,
+// rows of both padded to `stride` floats, a multiple of 4).  One thread per
+// (row, pivot).  Columns i in [m, mpad) get 0.
+__global__ void k_dist_l2_pivots(const float *__restrict__ X, int64_t rows, const float *__restrict__ P, int m,
+                                 int mpad, int stride, float *__restrict__ out, int64_t s_piv, int64_t s_row)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = blockIdx.y;
+    if (r >= rows) return;
+    float acc = 0.f;
+    if (i < m) {
+        const float4 *x = reinterpret_cast<const float4 *>(X + (size_t)r * stride);
+        const float4 *p = reinterpret_cast<const float4 *>(P + (size_t)i * stride);
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int c = 0; c < stride / 4; c++) {
+            float4 u = x[c], v = p[c];
+            float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+            a0 = fmaf(d0, d0, a0);
+            a1 = fmaf(d1, d1, a1);
+            a2 = fmaf(d2, d2, a2);
+            a3 = fmaf(d3, d3, a3);
+        }
+        acc = sqrtf((a0 + a1) + (a2 + a3));
+    }
+    out[(size_t)i * s_piv + (size_t)r * s_row] = acc;
+}
+
+void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpad, int stride, float *out,
+                    int64_t s_piv, int64_t s_row, hipStream_t st)
+{
+    if (rows == 0) return;
+    dim3 grid((unsigned)((rows + 255) / 256), (unsigned)mpad);
+    hipLaunchKernelGGL(k_dist_l2_pivots, grid, dim3(256), 0, st, X, rows, P, m, mpad, stride, out, s_piv, s_row);
+}
+
+// Edit distance of every string to pivot blockIdx.y: the pivot is the Myers
+// pattern (its 256 x 4 match table in LDS), each thread scans one string as
+// the text.  out[i * s_piv + r * s_row] = distance (float or int as given).
+template <class OutT>
+__global__ void k_dist_edit_pivots(const uint8_t *__restrict__ chars, const int64_t *__restrict__ off,
+                                   int64_t rows, const uint8_t *__restrict__ pchars, const int32_t *__restrict__ poff,
+                                   int m, OutT *__restrict__ out, int64_t s_piv, int64_t s_row)
+{
+    __shared__ uint64_t peq[256 * 4];
+    const int i = blockIdx.y;
+    for (int t = threadIdx.x; t < 256 * 4; t += blockDim.x) peq[t] = 0ull;
+    __syncthreads();
+    int plen = 0;
+    if (i < m) {
+        const int a = poff[i];
+        plen = poff[i + 1] - a;
+        for (int t = threadIdx.x; t < plen; t += blockDim.x)
+            atomicOr(reinterpret_cast<unsigned long long *>(&peq[pchars[a + t] * 4 + (t >> 6)]),
+                     (unsigned long long)(1ull << (t & 63)));
+    }
+    __syncthreads();
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    int d = 0;
+    if (i < m) {
+        const int64_t a = off[r];
+        const int tlen = (int)(off[r + 1] - a);
+        d = dev::myers_any(peq, plen, chars + a, tlen, 1 << 30);
+    }
+    out[(size_t)i * s_piv + (size_t)r * s_row] = (OutT)d;
+}
+
+void dist_edit_pivots_f32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
+                          const int32_t *poff, int m, int mpad, float *out, int64_t s_piv, int64_t s_row,
+                          hipStream_t st)
+{
+    if (rows == 0) return;
+    dim3 grid((unsigned)((rows + 255) / 256), (unsigned)mpad);
+    hipLaunchKernelGGL(k_dist_edit_pivots<float>, grid, dim3(256), 0, st, chars, off, rows, pchars, poff, m, out,
+                       s_piv, s_row);
+}
+
+void dist_edit_pivots_i32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
+                          const int32_t *poff, int m, int32_t *out, int64_t s_piv, int64_t s_row, hipStream_t st)
+{
+    if (rows == 0) return;
+    dim3 grid((unsigned)((rows + 255) / 256), (unsigned)m);
+    hipLaunchKernelGGL(k_dist_edit_pivots<int32_t>, grid, dim3(256), 0, st, chars, off, rows, pchars, poff, m,
+                       out, s_piv, s_row);
+}
+
+// Match-bit table of each query string: peq[q][c][w] bit b set iff
+// query[64w + b] == c.  One workgroup per query.
+__global__ void k_build_peq(const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int64_t nq,
+                            uint64_t *__restrict__ peq)
+{
+    int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    uint64_t *t = peq + (size_t)q * 256 * 4;
+    for (int c = threadIdx.x; c < 256 * 4; c += blockDim.x) t[c] = 0ull;
+    __syncthreads();
+    const int64_t a = off[q];
+    const int len = (int)(off[q + 1] - a);
+    for (int b = threadIdx.x; b < len; b += blockDim.x)
+        atomicOr(reinterpret_cast<unsigned long long *>(&t[chars[a + b] * 4 + (b >> 6)]),
+                 (unsigned long long)(1ull << (b & 63)));
+}
+
+void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *peq, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_build_peq, dim3((unsigned)nq), dim3(256), 0, st, chars, off, nq, peq);
+}
+
+// Per-query threshold for node and object filtering:
+//   L2:   thr = T + 2*delta*(max_i QP[q][i] + pt_max), T = base * (1 + 2*delta)
+//   EDIT: thr = floor(base)
+// where base is the range radius or the kNN bound and delta bounds the
+// relative float32 error of a direct-difference distance in `dim` dimensions.
+__global__ void k_thresholds(const float *__restrict__ base, const float *__restrict__ QP, int64_t nq, int mpad,
+                             int is_edit, float delta, float pt_max, float *__restrict__ T,
+                             float *__restrict__ thr)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    float b = base[q];
+    if (is_edit) {
+        float t = floorf(fminf(b, 1e6f));
+        T[q] = t;
+        thr[q] = t;
+        return;
+    }
+    float qmax = 0.f;
+    for (int i = 0; i < mpad; i++) qmax = fmaxf(qmax, QP[(size_t)q * mpad + i]);
+    float t = b * (1.f + 2.f * delta);
+    T[q] = t;
+    thr[q] = t + 2.f * delta * (qmax + pt_max);
+}
+
+void thresholds(const float *base, const float *QP, int64_t nq, int mpad, int is_edit, float delta, float pt_max,
+                float *T, float *thr, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_thresholds, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, base, QP, nq, mpad,
+                       is_edit, delta, pt_max, T, thr);
+}
+
+// Fill an int32 / uint64 array (a small kernel, so no memset node is needed
+// when the stream is captured).
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+}  // namespace k
+}  // namespace gts

@@ -1,0 +1,605 @@
+// Search kernels: node filtering, kNN radius bound, bf16 MFMA slab distances,
+// edit-distance object filtering and the cache-list scan.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace gts {
+namespace k {
+
+enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3 };
+
+// Largest box gap of a query (pivot distances qp) to node `node`:
+// max_i max(lo_i - qp_i, qp_i - hi_i).  A node whose gap exceeds the query's
+// threshold holds no object within it (Lemma 1 applied to every pivot).
+template <int MP>
+__device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t node, const float *qp)
+{
+    const float *b = box + (size_t)node * 2 * MP;
+    float g = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(b[i] - qp[i], qp[i] - b[MP + i]));
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Node filtering (Algorithms 4/5, the per-layer child test).  One wave per
+// (query tile, subtree rooted at level `split`); lane = query.  The tile's
+// surviving queries travel as a 64-bit lane mask, so a frontier element is
+// (node, mask); children are pushed on a per-wave LDS stack (depth-first keeps
+// the stack at most levels*(F-1)+1 deep).
+// ---------------------------------------------------------------------------
+constexpr int kStack = 640;
+
+template <int MP>
+__global__ __launch_bounds__(256) void k_node_filter(const float *__restrict__ box, int F, int levels, int split,
+                                                     int64_t nsub, int64_t leaf0, const float *__restrict__ QP,
+                                                     const float *__restrict__ thr, int64_t nq, int ntiles,
+                                                     uint64_t *__restrict__ leaf_mask, int32_t *__restrict__ items,
+                                                     uint32_t *__restrict__ item_count, int64_t item_cap,
+                                                     unsigned long long *__restrict__ counters)
+{
+    __shared__ int32_t s_node[4][kStack];
+    __shared__ uint64_t s_mask[4][kStack];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    if (gw >= (int64_t)ntiles * nsub) return;
+    const int tile = (int)(gw / nsub);
+    const int64_t sub = gw % nsub;
+    const int64_t q = (int64_t)tile * 64 + lane;
+    const bool act = q < nq;
+    float qp[MP];
+#pragma unroll
+    for (int i = 0; i < MP; i++) qp[i] = act ? QP[(size_t)q * MP + i] : 0.f;
+    const float th = act ? thr[q] : 0.f;
+    uint64_t mask = dev::ballot(act);
+    long long tests = 0;
+
+    // ancestors of the subtree root, levels 1..split
+    int64_t first = 0, span = 1;
+    for (int l = 0; l < split; l++) span *= F;
+    int64_t node = 0;
+    for (int l = 1; l <= split && mask; l++) {
+        first = first * F + 1;
+        span /= F;
+        node = first + sub / span;
+        tests += __popcll(mask);
+        mask &= dev::ballot(box_gap<MP>(box, node, qp) <= th);
+    }
+    if (split == 0) node = 0;
+    int sp = 0;
+    if (mask) {
+        s_node[wave][0] = (int32_t)node | (split << 27);
+        s_mask[wave][0] = mask;
+        sp = 1;
+    }
+    while (sp > 0) {
+        sp--;
+        const int32_t packed = s_node[wave][sp];
+        const uint64_t m = s_mask[wave][sp];
+        const int64_t v = packed & ((1 << 27) - 1);
+        const int lv = packed >> 27;
+        if (lv == levels) {
+            const int64_t leaf = v - leaf0;
+            if (lane == 0) {
+                leaf_mask[(size_t)leaf * ntiles + tile] = m;
+                if (items) {
+                    uint32_t idx = atomicAdd(item_count, 1u);
+                    if (idx < item_cap) {
+                        items[2 * (size_t)idx] = (int32_t)leaf;
+                        items[2 * (size_t)idx + 1] = tile;
+                    }
+                }
+            }
+            continue;
+        }
+        for (int c = F - 1; c >= 0; c--) {
+            const int64_t child = v * F + 1 + c;
+            tests += __popcll(m);
+            const uint64_t cm = m & dev::ballot(box_gap<MP>(box, child, qp) <= th);
+            if (cm) {
+                s_node[wave][sp] = (int32_t)child | ((lv + 1) << 27);
+                s_mask[wave][sp] = cm;
+                sp++;
+            }
+        }
+    }
+    if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
+}
+
+void node_filter(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles,
+                 uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
+                 unsigned long long *counters, hipStream_t st)
+{
+    if (nq == 0) return;
+    // split level: enough (tile, subtree) waves to fill the chip
+    int split = 0;
+    int64_t nsub = 1;
+    while (split < t.levels && (int64_t)ntiles * nsub < 8192) {
+        split++;
+        nsub *= t.fanout;
+    }
+    const int64_t waves = (int64_t)ntiles * nsub;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+#define NF_LAUNCH(MP)                                                                                       \
+    hipLaunchKernelGGL(k_node_filter<MP>, dim3(blocks), dim3(256), 0, st, t.box_aos, t.fanout, t.levels, split, \
+                       nsub, t.leaf0, QP, thr, nq, ntiles, leaf_mask, items, item_count, item_cap, counters)
+    if (t.mpad == 8) NF_LAUNCH(8);
+    else if (t.mpad == 16) NF_LAUNCH(16);
+    else NF_LAUNCH(32);
+#undef NF_LAUNCH
+}
+
+// ---------------------------------------------------------------------------
+// kNN radius bound (the range-query strategy of Sec. 5.2: a kNN query is a
+// range query once an upper bound of its k-th distance is known).  One
+// 64-thread workgroup per query: descend greedily to the child with the
+// smallest box gap, then take exact distances to a window of consecutive
+// positions starting at that leaf; the k-th smallest of those is >= the true
+// k-th distance.
+// ---------------------------------------------------------------------------
+constexpr int kWinMax = 1024;
+
+template <int MP>
+__device__ int64_t descend_home(const TreeView &t, const float *qp)
+{
+    const int lane = dev::lane_id();
+    int64_t node = 0;
+    for (int l = 1; l <= t.levels; l++) {
+        int64_t child = node * t.fanout + 1 + lane;
+        float g = INFINITY;
+        if (lane < t.fanout) g = box_gap<MP>(t.box_aos, child, qp);
+        float gmin = dev::wave_min(g);
+        uint64_t who = dev::ballot(g == gmin);
+        int best = who ? (__ffsll((long long)who) - 1) : 0;
+        node = node * t.fanout + 1 + best;
+    }
+    return node - t.leaf0;
+}
+
+template <int MP, bool EDIT>
+__global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, EditView oe, QueryEdit qe,
+                                              const float *__restrict__ QP, const int32_t *__restrict__ kq,
+                                              int64_t nq, const uint32_t *__restrict__ tomb, int win,
+                                              float *__restrict__ tq, int32_t *__restrict__ home)
+{
+    __shared__ float s_d[kWinMax];
+    const int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    const int lane = threadIdx.x;
+    float qp[MP];
+#pragma unroll
+    for (int i = 0; i < MP; i++) qp[i] = QP[(size_t)q * MP + i];
+    const int64_t leaf = descend_home<MP>(t, qp);
+    if (lane == 0) home[q] = (int32_t)leaf;
+    const int k = kq ? kq[q] : 0;
+    if (k <= 0) return;
+    const int64_t n = EDIT ? oe.n : o.n;
+    int W = k > win ? k : win;
+    if ((int64_t)W > n) W = (int)n;
+    if (W > kWinMax || k > W) {           // no bound cheaper than a full scan
+        if (lane == 0) tq[q] = INFINITY;
+        return;
+    }
+    int64_t a = t.leaf_first[leaf];
+    if (a + W > n) a = n - W;
+    const int Wp = dev::next_pow2(W);
+    for (int j = lane; j < Wp; j += 64) {
+        float d = INFINITY;
+        if (j < W) {
+            const int64_t p = a + j;
+            const bool dead = (tomb[p >> 5] >> (p & 31)) & 1u;
+            if (!dead) {
+                if (!EDIT) {
+                    const float4 *x = reinterpret_cast<const float4 *>(o.X32 + (size_t)p * o.dp);
+                    const float4 *y = reinterpret_cast<const float4 *>(ql.Q32 + (size_t)q * o.dp);
+                    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                    for (int c = 0; c < o.dp / 4; c++) {
+                        float4 u = x[c], v = y[c];
+                        float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+                        a0 = fmaf(d0, d0, a0);
+                        a1 = fmaf(d1, d1, a1);
+                        a2 = fmaf(d2, d2, a2);
+                        a3 = fmaf(d3, d3, a3);
+                    }
+                    d = sqrtf((a0 + a1) + (a2 + a3));
+                } else {
+                    const int32_t s0 = oe.soff[p];
+                    const int tl = oe.soff[p + 1] - s0;
+                    const int64_t qa = qe.off[q];
+                    const int plen = (int)(qe.off[q + 1] - qa);
+                    d = (float)dev::myers_any(qe.peq + (size_t)q * 256 * 4, plen, oe.chars + s0, tl, 1 << 30);
+                }
+            }
+        }
+        s_d[j] = d;
+    }
+    dev::bitonic_sort(s_d, Wp);
+    if (lane == 0) tq[q] = s_d[k - 1];
+}
+
+void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
+              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st)
+{
+    if (nq == 0) return;
+    EditView oe{};
+    QueryEdit qe{};
+#define BL(MP) \
+    hipLaunchKernelGGL((k_bound<MP, false>), dim3((unsigned)nq), dim3(64), 0, st, t, o, qv, oe, qe, QP, kq, nq, tomb, win, tq, home)
+    if (t.mpad == 8) BL(8);
+    else if (t.mpad == 16) BL(16);
+    else BL(32);
+#undef BL
+}
+
+void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
+                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st)
+{
+    if (nq == 0) return;
+    L2View ol{};
+    QueryL2 ql{};
+#define BE(MP) \
+    hipLaunchKernelGGL((k_bound<MP, true>), dim3((unsigned)nq), dim3(64), 0, st, t, ol, ql, o, qv, QP, kq, nq, tomb, win, tq, home)
+    if (t.mpad == 8) BE(8);
+    else if (t.mpad == 16) BE(16);
+    else BE(32);
+#undef BE
+}
+
+// ---------------------------------------------------------------------------
+// bf16 MFMA slab distances (L2 verification, first pass).
+//
+// Work unit: one slab of 256 consecutive tree positions against a chunk of
+// query tiles.  Each of the 4 waves keeps 64 objects (4 row blocks of 16)
+// as MFMA A fragments in registers for the whole unit; query tiles (64
+// queries = 4 column blocks of 16) stream through as B fragments.  With
+// v_mfma_f32_16x16x32_bf16, lane l of the output holds objects 4*(l/16)+e
+// (e = 0..3) of a row block and query l%16 of a column block.
+//
+// A pair is a candidate when its estimated squared distance
+// qn + xn - 2 q.x does not exceed (T + e_q + e_slab)^2 + eps, where T bounds
+// the true distance of any possible answer, e_q / e_slab bound the bf16
+// rounding of the query / objects (||x16 - x|| <= e), and eps bounds the
+// float32 error of the estimate.  So every answer is a candidate; the exact
+// float32 distance is computed later for candidates only.
+// ---------------------------------------------------------------------------
+constexpr int kRowTiles = 4;  // 16-row MFMA blocks per wave: slab = 4 waves x 64 rows
+static_assert(4 * 16 * kRowTiles == 256, "slab size must match the index layout");
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v)
+{
+    bf16x8_t r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+template <int KS, int RT>
+__global__ __launch_bounds__(256, 2) void k_mfma_sweep(
+    const uint4 *__restrict__ X16t, const float *__restrict__ xn, const uint4 *__restrict__ Q16t,
+    const float *__restrict__ qn, const float *__restrict__ qe, const float *__restrict__ T, int64_t nq,
+    int ntiles, const float *__restrict__ slab_emax, const float *__restrict__ slab_nmax,
+    const int32_t *__restrict__ slab_leaf_lo, const int32_t *__restrict__ slab_leaf_hi,
+    const uint64_t *__restrict__ leaf_mask, int64_t n, const uint32_t *__restrict__ tomb, int64_t n_items,
+    int chunk, int nchunks, uint32_t *__restrict__ work, Cand *__restrict__ cands,
+    uint32_t *__restrict__ cand_count, int64_t cand_cap, float eps_a, float eps_b, float eps_c,
+    unsigned long long *__restrict__ counters)
+{
+    constexpr int kRowsPerWave = 16 * RT;
+    constexpr int kSlabRows = 4 * kRowsPerWave;
+    __shared__ int s_item;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15;
+    const int rgrp = lane >> 4;
+    int64_t cur_slab = -1;
+    uint4 A[RT][KS];
+    float xr[RT][4];
+    long long pairs = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(work, 1u);
+        __syncthreads();
+        const int64_t item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int64_t slab = item / nchunks;
+        const int ch = (int)(item % nchunks);
+        const int64_t row0 = slab * kSlabRows + wave * kRowsPerWave;
+        if (slab != cur_slab) {
+            cur_slab = slab;
+            const int64_t g0 = row0 >> 4;
+#pragma unroll
+            for (int r = 0; r < RT; r++)
+#pragma unroll
+                for (int s = 0; s < KS; s++) A[r][s] = X16t[((g0 + r) * KS + s) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < RT; r++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) xr[r][e] = xn[row0 + 16 * r + 4 * rgrp + e];
+        }
+        const float emax = slab_emax[slab];
+        const float nmax = slab_nmax[slab];
+        const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
+        const int t0 = ch * chunk;
+        const int t1 = min(ntiles, t0 + chunk);
+        for (int t = t0; t < t1; t++) {
+            uint64_t mask = 0;
+            for (int l = l_lo; l <= l_hi; l++) mask |= leaf_mask[(size_t)l * ntiles + t];
+            if (!mask) continue;
+            pairs++;
+#pragma unroll 1
+            for (int c = 0; c < 4; c++) {
+                const uint32_t cm = (uint32_t)(mask >> (16 * c)) & 0xffffu;
+                if (!cm) continue;
+                const int64_t q = (int64_t)t * 64 + 16 * c + col;
+                float th = -INFINITY, qnn = 0.f;
+                if (q < nq && ((cm >> col) & 1u)) {
+                    qnn = qn[q];
+                    const float tq = T[q] + qe[q] + emax;
+                    const float T2 = tq * tq;
+                    const float eps = eps_a * (qnn + nmax * nmax) + eps_b * sqrtf(qnn) * nmax + eps_c * T2;
+                    th = T2 + eps - qnn;
+                }
+                uint4 B[KS];
+#pragma unroll
+                for (int s = 0; s < KS; s++) B[s] = Q16t[(((int64_t)t * 4 + c) * KS + s) * 64 + lane];
+                floatx4_t acc[RT];
+#pragma unroll
+                for (int r = 0; r < RT; r++) acc[r] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; s++)
+#pragma unroll
+                    for (int r = 0; r < RT; r++)
+                        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[r][s]), as_bf16x8(B[s]), acc[r],
+                                                                          0, 0, 0);
+                // candidate test: xn - 2 q.x <= (T + e_q + e_slab)^2 + eps - qn
+                uint32_t pm = 0;
+#pragma unroll
+                for (int r = 0; r < RT; r++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        pm |= (fmaf(-2.f, acc[r][e], xr[r][e]) <= th ? 1u : 0u) << (4 * r + e);
+                if (dev::ballot(pm != 0)) {
+                    // drop padding rows and deleted objects, then compact
+#pragma unroll
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            const int bit = 4 * r + e;
+                            if ((pm >> bit) & 1u) {
+                                const int64_t pos = row0 + 16 * r + 4 * rgrp + e;
+                                if (pos >= n || ((tomb[pos >> 5] >> (pos & 31)) & 1u)) pm &= ~(1u << bit);
+                            }
+                        }
+                    const int cnt = __popc(pm);
+                    int tot;
+                    const int off = dev::wave_excl_scan(cnt, &tot);
+                    uint32_t base = 0;
+                    if (lane == 0 && tot) base = atomicAdd(cand_count, (uint32_t)tot);
+                    base = __shfl(base, 0, 64);
+                    int j = 0;
+#pragma unroll
+                    for (int r = 0; r < RT; r++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) {
+                            if ((pm >> (4 * r + e)) & 1u) {
+                                const int64_t idx = (int64_t)base + off + j;
+                                j++;
+                                if (idx < cand_cap) {
+                                    Cand cd;
+                                    cd.q = (int32_t)q;
+                                    cd.pos = (int32_t)(row0 + 16 * r + 4 * rgrp + e);
+                                    cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], xr[r][e]) + qnn);
+                                    cands[idx] = cd;
+                                }
+                            }
+                        }
+                }
+            }
+        }
+    }
+    if (threadIdx.x == 0 && pairs) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)pairs);
+}
+
+void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *T, int64_t nq, int ntiles,
+                const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
+                uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
+                hipStream_t st)
+{
+    if (nq == 0 || s.n_slabs == 0) return;
+    const int nchunks = (ntiles + chunk - 1) / chunk;
+    const int64_t n_items = s.n_slabs * nchunks;
+    const float u = 5.9604645e-8f;  // 2^-24
+    const int D = o.ksteps * 32;
+    const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
+#define MS(KS)                                                                                                  \
+    hipLaunchKernelGGL((k_mfma_sweep<KS, kRowTiles>), dim3((unsigned)grid_blocks), dim3(256), 0, st,                         \
+                       reinterpret_cast<const uint4 *>(o.X16t), o.xn, reinterpret_cast<const uint4 *>(qv.Q16t), \
+                       qv.qn, qv.qe, T, nq, ntiles, s.emax, s.nmax, s.leaf_lo, s.leaf_hi, leaf_mask, o.n, tomb,  \
+                       n_items, chunk, nchunks, work, cands, cand_count, cand_cap, eps_a, eps_b, eps_c, counters)
+    switch (o.ksteps) {
+    case 1: MS(1); break;
+    case 2: MS(2); break;
+    case 3: MS(3); break;
+    default: MS(4); break;
+    }
+#undef MS
+}
+
+// ---------------------------------------------------------------------------
+// Edit-distance object filtering over surviving (leaf, tile) pairs.  One wave
+// per pair, lane = query.  Each object of the leaf is tested against every
+// surviving query of the tile with the length bound | |q| - |o| | <= d(q,o)
+// and Lemma 1 on every pivot (its row of the AoS pivot table is uniform
+// across the wave); passing lanes are compacted with a ballot.
+// ---------------------------------------------------------------------------
+template <int MP>
+__global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restrict__ items,
+                                                        const uint32_t *__restrict__ item_count, int64_t item_cap,
+                                                        const uint64_t *__restrict__ leaf_mask, int ntiles,
+                                                        const int32_t *__restrict__ leaf_first,
+                                                        const int32_t *__restrict__ leaf_cnt,
+                                                        const float *__restrict__ QP, const float *__restrict__ thr,
+                                                        const int32_t *__restrict__ qlen, int64_t nq,
+                                                        const uint8_t *__restrict__ PTa,
+                                                        const int32_t *__restrict__ soff,
+                                                        const uint32_t *__restrict__ tomb, Cand *__restrict__ cands,
+                                                        uint32_t *__restrict__ cand_count, int64_t cand_cap)
+{
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    int64_t nitems = *item_count;
+    if (nitems > item_cap) nitems = item_cap;
+    for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < nitems; it += (int64_t)gridDim.x * 4) {
+        const int leaf = items[2 * it];
+        const int tile = items[2 * it + 1];
+        const uint64_t mask = leaf_mask[(size_t)leaf * ntiles + tile];
+        const int64_t q = (int64_t)tile * 64 + lane;
+        const bool act = ((mask >> lane) & 1ull) && q < nq;
+        int qp[MP];
+        int th = -1, ql = 0;
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < MP; i++) qp[i] = (int)QP[(size_t)q * MP + i];
+            th = (int)thr[q];
+            ql = qlen[q];
+        } else {
+#pragma unroll
+            for (int i = 0; i < MP; i++) qp[i] = 0;
+        }
+        const int p0 = leaf_first[leaf];
+        const int p1 = p0 + leaf_cnt[leaf];
+        for (int p = p0; p < p1; p++) {
+            if ((tomb[p >> 5] >> (p & 31)) & 1u) continue;
+            const int olen = soff[p + 1] - soff[p];
+            bool pass = act && abs(ql - olen) <= th;
+            const uint8_t *row = PTa + (size_t)p * MP;
+#pragma unroll
+            for (int i = 0; i < MP; i++) pass = pass && abs(qp[i] - (int)row[i]) <= th;
+            const uint64_t b = dev::ballot(pass);
+            if (!b) continue;
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(cand_count, (uint32_t)__popcll(b));
+            base = __shfl(base, 0, 64);
+            if (pass) {
+                const int64_t idx = (int64_t)base + dev::lanes_below(b);
+                if (idx < cand_cap) {
+                    Cand cd;
+                    cd.q = (int32_t)q;
+                    cd.pos = p;
+                    cd.val = 0;
+                    cands[idx] = cd;
+                }
+            }
+        }
+    }
+}
+
+void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,
+                    const uint64_t *leaf_mask, int ntiles, const float *QP, const float *thr, const int32_t *qlen,
+                    int64_t nq, const uint8_t *PTa, const int32_t *soff, const uint32_t *tomb, Cand *cands,
+                    uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
+{
+    if (nq == 0) return;
+    const unsigned blocks = 2048;
+#define OF(MP)                                                                                                  \
+    hipLaunchKernelGGL(k_edit_objfilter<MP>, dim3(blocks), dim3(256), 0, st, items, item_count, item_cap,        \
+                       leaf_mask, ntiles, t.leaf_first, t.leaf_cnt, QP, thr, qlen, nq, PTa, soff, tomb, cands, \
+                       cand_count, cand_cap)
+    if (t.mpad == 8) OF(8);
+    else if (t.mpad == 16) OF(16);
+    else OF(32);
+#undef OF
+}
+
+// ---------------------------------------------------------------------------
+// Cache list (Sec. 4.3): brute force over every live cached object.
+// ---------------------------------------------------------------------------
+// L2: 16 lanes per (query, slot) pair, float32 direct difference.
+__global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp, const float *__restrict__ C32,
+                                const uint32_t *__restrict__ cids, const uint32_t *__restrict__ clive,
+                                int64_t ncache, const float *__restrict__ base, Cand *__restrict__ cands,
+                                uint32_t *__restrict__ cand_count, int64_t cand_cap)
+{
+    const int64_t pair = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int sl = threadIdx.x & 15;
+    const bool inb = pair < nq * ncache;
+    const int64_t q = inb ? pair / ncache : 0;
+    const int64_t c = inb ? pair % ncache : 0;
+    float acc = 0.f;
+    if (inb && clive[c]) {
+        const float *x = Q32 + (size_t)q * dp;
+        const float *y = C32 + (size_t)c * dp;
+        for (int i = sl; i < dp; i += 16) {
+            float d = x[i] - y[i];
+            acc = fmaf(d, d, acc);
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (sl == 0 && inb && clive[c]) {
+        const float d = sqrtf(acc);
+        if (d <= base[q]) {
+            uint32_t idx = atomicAdd(cand_count, 1u);
+            if (idx < cand_cap) {
+                Cand cd;
+                cd.q = (int32_t)q;
+                cd.pos = -1;
+                cd.val = ((uint64_t)__float_as_uint(d) << 32) | cids[c];
+                cands[idx] = cd;
+            }
+        }
+    }
+}
+
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
+                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, uint32_t *cand_count,
+                   int64_t cand_cap, hipStream_t st)
+{
+    if (nq == 0 || ncache == 0) return;
+    const int64_t threads = nq * ncache * 16;
+    hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Q32, nq, dp, C32,
+                       cids, clive, ncache, base, cands, cand_count, cand_cap);
+}
+
+// EDIT: one lane per (query, slot) pair, query as the pattern.
+__global__ void k_cache_scan_edit(QueryEdit qv, int64_t nq, const uint8_t *__restrict__ cchars, int cstride,
+                                  const int32_t *__restrict__ clen, const uint32_t *__restrict__ cids,
+                                  const uint32_t *__restrict__ clive, int64_t ncache, const float *__restrict__ base,
+                                  Cand *__restrict__ cands, uint32_t *__restrict__ cand_count, int64_t cand_cap)
+{
+    const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pair >= nq * ncache) return;
+    const int64_t q = pair / ncache, c = pair % ncache;
+    if (!clive[c]) return;
+    const int cut = (int)floorf(fminf(base[q], 1e6f));
+    const int plen = (int)(qv.off[q + 1] - qv.off[q]);
+    const int tl = clen[c];
+    if (abs(plen - tl) > cut) return;
+    const int d = dev::myers_any(qv.peq + (size_t)q * 256 * 4, plen, cchars + (size_t)c * cstride, tl, cut);
+    if (d <= cut) {
+        uint32_t idx = atomicAdd(cand_count, 1u);
+        if (idx < cand_cap) {
+            Cand cd;
+            cd.q = (int32_t)q;
+            cd.pos = -1;
+            cd.val = ((uint64_t)(uint32_t)d << 32) | cids[c];
+            cands[idx] = cd;
+        }
+    }
+}
+
+void cache_scan_edit(const QueryEdit &qv, int64_t nq, const uint8_t *cchars, int cstride, const int32_t *clen,
+                     const uint32_t *cids, const uint32_t *clive, int64_t ncache, const float *base, Cand *cands,
+                     uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
+{
+    if (nq == 0 || ncache == 0) return;
+    const int64_t threads = nq * ncache;
+    hipLaunchKernelGGL(k_cache_scan_edit, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, qv, nq, cchars,
+                       cstride, clen, cids, clive, ncache, base, cands, cand_count, cand_cap);
+}
+
+}  // namespace k
+}  // namespace gts

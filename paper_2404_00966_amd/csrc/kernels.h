@@ -1,0 +1,161 @@
+// Host-callable launchers of the libgts.so kernels (all asynchronous on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gts {
+namespace k {
+
+// A (query, object) pair on its way to the answer.
+//   pos >= 0 : candidate at tree position pos; val = float bits of an
+//              estimate of the squared distance (L2 tile path) or 0.
+//   pos <  0 : already verified; val = sort key (distance bits << 32 | id).
+struct Cand {
+    int32_t q;
+    int32_t pos;
+    uint64_t val;
+};
+
+// ---- preparation (k_prep.hip) ---------------------------------------------
+void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, int stride, int ksteps,
+               uint16_t *frag, float *norm2, float *err, float pad_norm2, hipStream_t st);
+void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpad, int stride, float *out,
+                    int64_t s_piv, int64_t s_row, hipStream_t st);
+void dist_edit_pivots_f32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
+                          const int32_t *poff, int m, int mpad, float *out, int64_t s_piv, int64_t s_row,
+                          hipStream_t st);
+void dist_edit_pivots_i32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
+                          const int32_t *poff, int m, int32_t *out, int64_t s_piv, int64_t s_row,
+                          hipStream_t st);
+void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *peq, hipStream_t st);
+void thresholds(const float *base, const float *QP, int64_t nq, int mpad, int is_edit, float delta,
+                float pt_max, float *T, float *thr, hipStream_t st);
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
+// ---- tree and candidates (k_search.hip) ------------------------------------
+struct TreeView {
+    const float *box_aos;      // [n_nodes][2*mpad]
+    const float *box_lo;       // [mpad][n_nodes]
+    const float *box_hi;       // [mpad][n_nodes]
+    const int32_t *leaf_first; // [n_leaves]
+    const int32_t *leaf_cnt;   // [n_leaves]
+    int64_t n_nodes, n_leaves, leaf0;
+    int fanout, levels, mpad;
+};
+
+// Depth-first node filtering, one wave per (query tile, subtree).  Writes
+// leaf_mask[leaf][tile] (bit = query lane survives the leaf's box) for every
+// leaf (zero when pruned) and, when items != nullptr, appends (leaf, tile)
+// for every surviving leaf.
+void node_filter(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles,
+                 uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
+                 unsigned long long *counters, hipStream_t st);
+
+// Greedy descent to each query's home leaf (smallest box gap per level);
+// for kNN queries (k[q] > 0) also the k-th smallest exact distance over a
+// window of at least max(k, win) consecutive tree positions starting at the
+// home leaf (deleted positions skipped; +inf if fewer than k are live).
+struct L2View {
+    const float *X32;          // [npad][dp]
+    const float *xn, *xe;      // [npad]
+    const uint16_t *X16t;      // fragments
+    int64_t n, npad;
+    int dim, dp, ksteps;
+};
+struct EditView {
+    const uint8_t *chars;      // leaf order
+    const int32_t *soff;       // [n + 1]
+    int64_t n;
+};
+struct QueryL2 {
+    const float *Q32;          // [nq][dp]
+    const uint16_t *Q16t;      // fragments
+    const float *qn, *qe;      // [nqpad]
+};
+struct QueryEdit {
+    const uint8_t *chars;
+    const int64_t *off;        // [nq + 1]
+    const uint64_t *peq;       // [nq][256][4]
+};
+
+void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
+              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st);
+void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
+                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st);
+
+// Slab x query-tile bf16 MFMA distances (persistent, work counter in `work`).
+struct SlabView {
+    const float *emax, *nmax;
+    const int32_t *leaf_lo, *leaf_hi;
+    int64_t n_slabs;
+};
+void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *T, int64_t nq, int ntiles,
+                const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
+                uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
+                hipStream_t st);
+
+// Edit-distance object filtering over (leaf, tile) items: length and pivot
+// lower bounds, wave-ballot compaction into candidates.
+void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,
+                    const uint64_t *leaf_mask, int ntiles, const float *QP, const float *thr, const int32_t *qlen,
+                    int64_t nq, const uint8_t *PTa, const int32_t *soff, const uint32_t *tomb, Cand *cands,
+                    uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+
+// Brute-force scan of the cache list; emits verified entries with d <= base.
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
+                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, uint32_t *cand_count,
+                   int64_t cand_cap, hipStream_t st);
+void cache_scan_edit(const QueryEdit &qv, int64_t nq, const uint8_t *cchars, int cstride, const int32_t *clen,
+                     const uint32_t *cids, const uint32_t *clive, int64_t ncache, const float *base, Cand *cands,
+                     uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+
+// ---- grouping, verification, output (k_final.hip) ---------------------------
+void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
+void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st);  // out[n+1]
+void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
+                   Cand *grouped, hipStream_t st);
+
+struct VerifyArgs {
+    const Cand *grouped;       // candidates grouped by query
+    const int64_t *qoff;       // [nq + 1]
+    const int64_t *big_off;    // [nq]: scratch offset (power-of-two run) or -1
+    uint64_t *scratch;         // big-segment sort space
+    const int32_t *kq;         // [nq] 0 = range
+    const float *base;         // [nq] range radius or kNN bound
+    const uint32_t *ids;       // [n] id per position
+    int64_t nq;
+    uint64_t *out_keys;        // same index space as grouped
+    uint32_t *out_count;       // [nq]
+    unsigned long long *counters;
+};
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, hipStream_t st);
+void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st);
+
+// CSR assembly: ids[res_off[q] + j] and dist from out_keys[qoff[q] + j].
+void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,
+               int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i, hipStream_t st);
+
+// ---- plain one-query-per-workgroup path (k_plain.hip) -----------------------
+struct PlainArgs {
+    int64_t nq;
+    const float *base;         // [nq] radius or kNN bound (distance units)
+    const int32_t *kq;         // [nq]
+    int32_t *frontier;         // [grid][2][n_leaves]
+    int grid;
+    const uint32_t *tomb;
+    const uint32_t *ids;       // [n] id per position
+    Cand *out;
+    uint32_t *out_count;
+    int64_t out_cap;
+    unsigned long long *counters;
+    float delta, pt_max;
+};
+void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const float *PT, const float *Q32,
+              const PlainArgs &a, hipStream_t st);
+void plain_edit(const TreeView &t, const EditView &o, const uint8_t *pchars, const int32_t *poff, int m,
+                const uint8_t *PTe, const QueryEdit &qv, const PlainArgs &a, hipStream_t st);
+
+}  // namespace k
+}  // namespace gts

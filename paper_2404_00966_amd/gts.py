@@ -1,0 +1,259 @@
+"""Python binding of libgts.so -- argument marshalling only.
+
+Every stage of a search runs in the library's HIP kernels; this module turns
+torch tensors / numpy arrays into the plain pointers of the C ABI
+(include/gts.h) and results back into torch tensors.  torch is imported first
+so the library binds to the HIP runtime torch already loaded.  There is no
+fallback: if libgts.so is missing or fails to load, an error is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgts.so")
+
+L2_F32, EDIT_U8 = 1, 2
+HOST, DEVICE = 0, 1
+MODE_BATCHED, MODE_PLAIN = 0, 1
+STAGES = ("prep", "bound", "nodes", "cands", "group", "verify", "output", "plain")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
+
+
+class GtsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gts status {status}: {msg}")
+        self.status = status
+
+
+class _Objects(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("location", C.c_int32),
+                ("vecs", C.c_void_p), ("chars", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+class _BuildOpts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("leaf_size", C.c_int32), ("max_strlen", C.c_int32),
+                ("cache_limit", C.c_int64), ("mem_budget_bytes", C.c_int64)]
+
+
+class _QueryOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("result_location", C.c_int32), ("mem_budget_bytes", C.c_int64)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("nq", C.c_int64), ("total", C.c_int64), ("location", C.c_int32), ("metric", C.c_int32),
+                ("offsets", C.c_void_p), ("ids", C.c_void_p), ("dist_f32", C.c_void_p),
+                ("dist_i32", C.c_void_p), ("priv", C.c_void_p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("nq", C.c_int64), ("node_tests", C.c_int64), ("leaf_pairs", C.c_int64),
+                ("tile_pairs", C.c_int64), ("candidates", C.c_int64), ("verified", C.c_int64),
+                ("results", C.c_int64), ("ms_total", C.c_double), ("ms_stage", C.c_double * 8),
+                ("groups", C.c_int64)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("metric", C.c_int32), ("dim", C.c_int32), ("num_pivots", C.c_int32), ("fanout", C.c_int32),
+                ("levels", C.c_int32), ("max_strlen", C.c_int32), ("n_indexed", C.c_int64),
+                ("n_live", C.c_int64), ("n_cache", C.c_int64), ("n_nodes", C.c_int64),
+                ("n_leaves", C.c_int64), ("n_slabs", C.c_int64), ("rebuilds", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+
+EXPORTS = ("gts_build_index", "gts_range_query", "gts_knn_query", "gts_search", "gts_insert", "gts_delete",
+           "gts_result_copy", "gts_result_free", "gts_destroy", "gts_get_info", "gts_get_stats",
+           "gts_set_timing", "gts_last_error")
+
+_lib = None
+
+
+def library():
+    """Load libgts.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.gts_build_index.argtypes = [P(_Objects), C.c_int32, C.c_int32, C.c_int32, P(_BuildOpts), C.c_void_p,
+                                      P(C.c_void_p)]
+        L.gts_search.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, C.c_void_p, P(_QueryOpts), P(_Result)]
+        L.gts_range_query.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, P(_QueryOpts), P(_Result)]
+        L.gts_knn_query.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, P(_QueryOpts), P(_Result)]
+        L.gts_insert.argtypes = [C.c_void_p, P(_Objects), C.c_void_p]
+        L.gts_delete.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.gts_result_copy.argtypes = [P(_Result), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gts_result_free.argtypes = [P(_Result)]
+        L.gts_destroy.argtypes = [C.c_void_p]
+        L.gts_get_info.argtypes = [C.c_void_p, P(_Info)]
+        L.gts_get_stats.argtypes = [C.c_void_p, P(_Stats)]
+        L.gts_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.gts_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "gts_last_error":
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise GtsError(status, library().gts_last_error().decode())
+
+
+class _Keep(list):
+    """Holds tensors alive for the duration of a call."""
+
+
+def _objects(data, metric, keep: _Keep) -> _Objects:
+    """torch tensor / numpy array (L2: [n, dim] float32) or (chars, offsets)
+    pair (EDIT) -> gts_objects.  CUDA tensors are passed as device pointers."""
+    o = _Objects()
+    if metric == L2_F32:
+        t = data if isinstance(data, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(data))
+        t = t.to(torch.float32).contiguous()
+        if t.dim() != 2:
+            raise ValueError("L2 objects must be a 2-D [n, dim] tensor")
+        keep.append(t)
+        o.n, o.dim = t.shape[0], t.shape[1]
+        o.location = DEVICE if t.is_cuda else HOST
+        o.vecs = t.data_ptr() if t.numel() else None
+    else:
+        chars, offsets = data
+        ct = chars if isinstance(chars, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(chars, np.uint8))
+        ot = offsets if isinstance(offsets, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(offsets, np.int64))
+        ct = ct.to(torch.uint8).contiguous()
+        ot = ot.to(torch.int64).contiguous()
+        if ct.numel() == 0:
+            ct = torch.zeros(1, dtype=torch.uint8, device=ot.device)
+        keep += [ct, ot]
+        o.n = ot.shape[0] - 1
+        o.location = DEVICE if ot.is_cuda else HOST
+        o.chars = ct.data_ptr()
+        o.offsets = ot.data_ptr()
+    return o
+
+
+class Result:
+    """CSR answers: query i's entries are offsets[i]:offsets[i+1] of ids/dist."""
+
+    def __init__(self, offsets, ids, dist):
+        self.offsets, self.ids, self.dist = offsets, ids, dist
+
+    def __len__(self):
+        return self.offsets.shape[0] - 1
+
+    def query(self, i):
+        a, b = int(self.offsets[i]), int(self.offsets[i + 1])
+        return self.ids[a:b], self.dist[a:b]
+
+    def to_lists(self):
+        off = self.offsets.cpu().numpy()
+        ids = self.ids.cpu().numpy()
+        dist = self.dist.cpu().numpy()
+        return [(ids[off[q]:off[q + 1]], dist[off[q]:off[q + 1]]) for q in range(len(off) - 1)]
+
+
+class Index:
+    """A GTS index in GPU memory (see include/gts.h for the semantics)."""
+
+    def __init__(self, objects, metric=L2_F32, num_pivots=8, fanout=8, leaf_size=0, seed=0, cache_limit=0,
+                 mem_budget_bytes=0, max_strlen=0, stream=None):
+        L = library()
+        self.metric = metric
+        keep = _Keep()
+        o = _objects(objects, metric, keep)
+        opts = _BuildOpts(seed, leaf_size, max_strlen, cache_limit, mem_budget_bytes)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        sptr = stream.cuda_stream if stream is not None else None
+        h = C.c_void_p()
+        _check(L.gts_build_index(C.byref(o), metric, num_pivots, fanout, C.byref(opts), sptr, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().gts_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries ------------------------------------------------------------
+    def search(self, queries, radius=None, k=None, mode=MODE_BATCHED, result="auto", mem_budget_bytes=0):
+        """Mixed batch: query i is kNN when k[i] > 0, else range with radius[i]."""
+        L = library()
+        keep = _Keep()
+        o = _objects(queries, self.metric, keep)
+        nq = o.n
+        r_arr = None if radius is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(radius, np.float32), (nq,)))
+        k_arr = None if k is None else np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+        if result == "auto":
+            rloc = o.location
+        else:
+            rloc = DEVICE if result == "device" else HOST
+        qo = _QueryOpts(mode, rloc, mem_budget_bytes)
+        res = _Result()
+        _check(L.gts_search(self._h, C.byref(o), None if r_arr is None else r_arr.ctypes.data,
+                            None if k_arr is None else k_arr.ctypes.data, C.byref(qo), C.byref(res)))
+        try:
+            dev = torch.device("cuda") if rloc == DEVICE else torch.device("cpu")
+            off = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+            ids = torch.empty(max(res.total, 0), dtype=torch.int64, device=dev)
+            dt = torch.float32 if self.metric == L2_F32 else torch.int32
+            dist = torch.empty(max(res.total, 0), dtype=dt, device=dev)
+            if rloc == DEVICE:
+                torch.cuda.current_stream().synchronize()
+            _check(L.gts_result_copy(C.byref(res), rloc, off.data_ptr(), ids.data_ptr() if res.total else None,
+                                     dist.data_ptr() if res.total else None))
+        finally:
+            L.gts_result_free(C.byref(res))
+        return Result(off, ids, dist)
+
+    def range(self, queries, radius, **kw):
+        return self.search(queries, radius=radius, k=None, **kw)
+
+    def knn(self, queries, k, **kw):
+        return self.search(queries, radius=None, k=k, **kw)
+
+    # -- updates ------------------------------------------------------------
+    def insert(self, objects):
+        keep = _Keep()
+        o = _objects(objects, self.metric, keep)
+        ids = np.zeros(max(o.n, 1), np.int64)
+        _check(library().gts_insert(self._h, C.byref(o), ids.ctypes.data))
+        return ids[:o.n]
+
+    def delete(self, ids):
+        a = np.ascontiguousarray(np.asarray(ids, np.int64).reshape(-1))
+        n = C.c_int64(0)
+        _check(library().gts_delete(self._h, a.ctypes.data if a.size else None, a.size, C.byref(n)))
+        return n.value
+
+    # -- inspection ----------------------------------------------------------
+    def info(self):
+        i = _Info()
+        _check(library().gts_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in _Info._fields_}
+
+    def stats(self):
+        s = _Stats()
+        _check(library().gts_get_stats(self._h, C.byref(s)))
+        d = {f: getattr(s, f) for f, _ in _Stats._fields_ if f != "ms_stage"}
+        d["ms_stage"] = {STAGES[i]: s.ms_stage[i] for i in range(8)}
+        return d
+
+    def set_timing(self, on=True):
+        _check(library().gts_set_timing(self._h, 1 if on else 0))
