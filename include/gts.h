@@ -112,7 +112,7 @@ typedef struct {
     int64_t nq;
     int64_t node_tests;      /* (query, node) box tests evaluated              */
     int64_t leaf_pairs;      /* surviving (query, leaf) pairs                   */
-    int64_t tile_pairs;      /* (object slab, query tile) units computed        */
+    int64_t tile_pairs;      /* (256-object slab, 16-query block) MFMA units    */
     int64_t candidates;      /* (query, object) pairs reaching verification    */
     int64_t verified;        /* exact metric evaluations                       */
     int64_t results;         /* answer entries                                 */

@@ -112,6 +112,11 @@ struct IndexData {
     DevBuf xe;                   // float [npad] ||x16 - x32||
     DevBuf P32;                  // float [m][dp] pivot vectors
     DevBuf PT;                   // float [mpad][n] pivot distances (L2)
+    int64_t lpad = 0;            // leaves padded to a multiple of 64
+    DevBuf PL32;                 // float [lpad][dp] leaf pivot vectors
+    DevBuf PL16t;                // bf16 fragments of the leaf pivots
+    DevBuf pln, ple;             // float [lpad] ||p16||^2 (+inf: empty) and ||p16 - p||
+    DevBuf leafR;                // float [lpad] max distance from the leaf pivot
     int64_t n_slabs = 0;
     DevBuf slab_emax, slab_nmax; // float [n_slabs]
     DevBuf slab_leaf_lo, slab_leaf_hi; // int32 [n_slabs]: leaves overlapping

@@ -53,10 +53,14 @@ int choose_levels(int64_t n, int F, int leaf_size)
     return std::max(0, e - 2);
 }
 
+// Blocking upload: the sources are often temporaries of the caller.
 template <class T> void upload(DevBuf &b, const std::vector<T> &v, hipStream_t st)
 {
     b.alloc(std::max<size_t>(v.size() * sizeof(T), 16));
-    if (!v.empty()) GTS_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    if (!v.empty()) {
+        GTS_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    }
 }
 
 }  // namespace
@@ -299,6 +303,60 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         upload(d.slab_nmax, sn, st);
         upload(d.slab_leaf_lo, sl, st);
         upload(d.slab_leaf_hi, sh, st);
+        // leaf pivots: the leaf's object nearest its centroid, and the largest
+        // distance from it to the leaf's objects (computed in double, then
+        // widened by a relative 1e-6 so it bounds the true value)
+        d.lpad = (t.n_leaves + 63) / 64 * 64;
+        std::vector<float> pl((size_t)d.lpad * d.dp, 0.f);
+        std::vector<float> R(d.lpad, -INFINITY);
+        std::vector<uint8_t> empty(d.lpad, 1);
+        std::vector<double> cen(d.dim);
+        for (int64_t j = 0; j < t.n_leaves; j++) {
+            const int64_t a = lf[j], cnt = lc[j];
+            if (cnt == 0) continue;
+            std::fill(cen.begin(), cen.end(), 0.0);
+            for (int64_t p = a; p < a + cnt; p++)
+                for (int c = 0; c < d.dim; c++) cen[c] += h.vecs[(size_t)p * d.dim + c];
+            for (int c = 0; c < d.dim; c++) cen[c] /= (double)cnt;
+            int64_t best = a;
+            double bd = INFINITY;
+            for (int64_t p = a; p < a + cnt; p++) {
+                double s2 = 0.0;
+                for (int c = 0; c < d.dim; c++) {
+                    const double df = h.vecs[(size_t)p * d.dim + c] - cen[c];
+                    s2 += df * df;
+                }
+                if (s2 < bd) {
+                    bd = s2;
+                    best = p;
+                }
+            }
+            double rmax = 0.0;
+            for (int64_t p = a; p < a + cnt; p++) {
+                double s2 = 0.0;
+                for (int c = 0; c < d.dim; c++) {
+                    const double df = (double)h.vecs[(size_t)p * d.dim + c] - (double)h.vecs[(size_t)best * d.dim + c];
+                    s2 += df * df;
+                }
+                rmax = std::max(rmax, std::sqrt(s2));
+            }
+            R[j] = (float)(rmax * (1.0 + 1e-6)) + 1e-30f;
+            empty[j] = 0;
+            std::copy(h.vecs.begin() + best * d.dim, h.vecs.begin() + (best + 1) * d.dim, pl.begin() + (size_t)j * d.dp);
+        }
+        upload(d.PL32, pl, st);
+        upload(d.leafR, R, st);
+        d.PL16t.alloc((size_t)d.lpad * d.ksteps * 32 * sizeof(uint16_t));
+        d.pln.alloc((size_t)d.lpad * sizeof(float));
+        d.ple.alloc((size_t)d.lpad * sizeof(float));
+        k::rows_bf16(d.PL32.as<float>(), d.lpad, d.lpad, d.dim, d.dp, d.ksteps, d.PL16t.as<uint16_t>(), d.pln.as<float>(),
+                     d.ple.as<float>(), INFINITY, st);
+        std::vector<float> hpln(d.lpad);
+        GTS_HIP(hipMemcpyAsync(hpln.data(), d.pln.p, d.lpad * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < d.lpad; j++)
+            if (empty[j]) hpln[j] = INFINITY;   // never a nearest leaf
+        upload(d.pln, hpln, st);
     } else {
         std::vector<int32_t> soff(n + 1);
         for (int64_t p = 0; p <= n; p++) soff[p] = (int32_t)h.offsets[p];

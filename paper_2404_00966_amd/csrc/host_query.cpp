@@ -13,7 +13,7 @@
 //   output   CSR assembly
 //
 // When one batch's candidates would not fit the budget, the queries are split
-// into groups of whole 64-query tiles processed one after another (the
+// into groups of whole 16-query blocks processed one after another (the
 // "second stage"); answers do not depend on the grouping.
 #include <algorithm>
 #include <chrono>
@@ -30,13 +30,20 @@ namespace {
 enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
-    W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF
+    W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT
 };
 
 struct ResultPriv {
     void *offsets = nullptr, *ids = nullptr, *dist = nullptr;
     bool device = false;
 };
+
+}  // namespace
+
+void free_result(gts_result *r);
+
+namespace {
 
 template <class T> T *wsp(gts_index *idx, int slot, size_t count)
 {
@@ -175,6 +182,8 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
         pa.counters = counters;
         pa.delta = (float)((d.dim + 8) * 5.9604645e-8);
         pa.pt_max = d.pt_max;
+        pa.leaf_piv32 = l2 && d.lpad > 0 ? d.PL32.as<float>() : nullptr;
+        pa.leafR = l2 && d.lpad > 0 ? d.leafR.as<float>() : nullptr;
         rec(idx, 3);
         if (l2) k::plain_l2(tv, ov, d.P32.as<float>(), d.m, d.PT.as<float>(), qv.Q32, pa, st);
         else k::plain_edit(tv, oe, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, d.PTe.as<uint8_t>(), qe, pa, st);
@@ -186,6 +195,9 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
         const int64_t item_cap = t.n_leaves * ntiles;
         if (!l2) items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
         k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
+        if (l2 && d.lpad > 0)
+            k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
+                         d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, st);
         rec(idx, 3);
         if (l2) {
             k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
@@ -206,12 +218,15 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     // cache list: brute force, already verified
     const CacheList &c = idx->cache;
     if (c.n_live > 0) {
-        if (l2)
+        if (l2) {
+            // emission cutoff: radius (range) or the widened bound T (kNN)
+            float *cut = idx->ws[W_CUT].as<float>() + q0;
             k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
-                             base, cands, small + 0, cap, st);
-        else
+                             cut, cands, small + 0, cap, st);
+        } else {
             k::cache_scan_edit(qe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
                                c.live.as<uint32_t>(), c.count, base, cands, small + 0, cap, st);
+        }
     }
     uint32_t h_small[kSmallWords];
     GTS_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
@@ -345,8 +360,10 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     rec(idx, 0);
 
     // ---- queries into the workspace -----------------------------------------------
+    // query rows padded by one extra tile: a group that starts inside a tile
+    // still reads whole tiles of fragments
     const int64_t ntiles_all = (nq + kQTile - 1) / kQTile;
-    const int64_t nqpad = std::max<int64_t>(ntiles_all * kQTile, kQTile);
+    const int64_t nqpad = ntiles_all * kQTile + kQTile;
     wsp<float>(idx, W_QP, (size_t)nqpad * mpad);
     float *base = wsp<float>(idx, W_BASE, nqpad);
     wsp<float>(idx, W_T, nqpad);
@@ -406,27 +423,115 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         qe = k::QueryEdit{qc, qo, peq};
         GTS_HIP(hipStreamSynchronize(st));
     }
-    rec(idx, 1);
-
-    // ---- kNN bound ------------------------------------------------------------------
+    // ---- home leaves and query order ----------------------------------------------
+    // Queries are grouped into tiles by their home leaf (nearest leaf pivot for
+    // L2, greedy box descent for edit distance) so that a tile's queries share
+    // surviving leaves; answers are returned in the caller's order.
     k::TreeView tv{d.tree.box_aos.as<float>(), d.tree.box_lo.as<float>(), d.tree.box_hi.as<float>(),
                    d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.tree.n_nodes,
                    d.tree.n_leaves, d.tree.leaf0, d.tree.fanout, d.tree.levels, mpad};
-    if (nq > 0 && b.any_knn) {
-        const int win = 256;
+    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
+    int32_t *near = nullptr;
+    std::vector<int32_t> perm;   // position i of the batch holds caller query perm[i]
+    bool permuted = false;
+    if (nq > 1) {
+        std::vector<int32_t> hh(nq);
+        if (l2 && d.lpad > 0) {
+            near = wsp<int32_t>(idx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
+            k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
+            std::vector<int32_t> hn((size_t)nq * k::kNearLeaves);
+            GTS_HIP(hipMemcpyAsync(hn.data(), near, hn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            GTS_HIP(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
+        } else if (!l2) {
+            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), nullptr, nq, d.tomb.as<uint32_t>(), 0, base, home, st);
+            GTS_HIP(hipMemcpyAsync(hh.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            GTS_HIP(hipStreamSynchronize(st));
+        }
+        perm.resize(nq);
+        for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
+        if (l2 ? d.lpad > 0 : true) {
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hh[x] < hh[y]; });
+            for (int64_t q = 0; q < nq && !permuted; q++) permuted = perm[q] != q;
+        }
+    }
+    if (permuted) {
+        int32_t *dperm = wsp<int32_t>(idx, W_PERM, nq);
+        GTS_HIP(hipMemcpyAsync(dperm, perm.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        std::vector<float> pb(nq);
+        std::vector<int32_t> pk(nq);
+        for (int64_t i = 0; i < nq; i++) {
+            pb[i] = hbase[perm[i]];
+            pk[i] = hk[perm[i]];
+        }
+        hbase.swap(pb);
+        hk.swap(pk);
+        GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        float *QPd = idx->ws[W_QP].as<float>();
+        float *tmpf = wsp<float>(idx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
+        k::gather_rows(QPd, dperm, nq, mpad, tmpf, st);
+        GTS_HIP(hipMemcpyAsync(QPd, tmpf, (size_t)nq * mpad * sizeof(float), hipMemcpyDeviceToDevice, st));
         if (l2) {
+            float *Q32 = const_cast<float *>(qv.Q32);
+            k::gather_rows(Q32, dperm, nq, d.dp, tmpf, st);
+            GTS_HIP(hipMemcpyAsync(Q32, tmpf, (size_t)nq * d.dp * sizeof(float), hipMemcpyDeviceToDevice, st));
+            k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
+                         const_cast<float *>(qv.qn), const_cast<float *>(qv.qe), 0.f, st);
+            if (near) {
+                int32_t *tmpi = wsp<int32_t>(idx, W_TMP2, (size_t)nq * k::kNearLeaves);
+                k::gather_i32(near, dperm, nq, k::kNearLeaves, tmpi, st);
+                GTS_HIP(hipMemcpyAsync(near, tmpi, (size_t)nq * k::kNearLeaves * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, st));
+            }
+        } else {
+            // strings in the new order, then their match tables and lengths
+            std::vector<int64_t> hoff(nq + 1);
+            GTS_HIP(hipMemcpyAsync(hoff.data(), qe.off, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            GTS_HIP(hipStreamSynchronize(st));
+            std::vector<int64_t> noff(nq + 1, 0);
+            std::vector<int32_t> nlen(nq);
+            for (int64_t i = 0; i < nq; i++) {
+                nlen[i] = (int32_t)(hoff[perm[i] + 1] - hoff[perm[i]]);
+                noff[i + 1] = noff[i] + nlen[i];
+            }
+            uint8_t *nc = wsp<uint8_t>(idx, W_TMP2, std::max<int64_t>(noff[nq], 1));
+            int64_t *no = reinterpret_cast<int64_t *>(wsp<float>(idx, W_TMP, (size_t)2 * (nq + 1)));
+            GTS_HIP(hipMemcpyAsync(no, noff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            k::gather_strings(qe.chars, qe.off, dperm, nq, no, nc, st);
+            uint8_t *qc = const_cast<uint8_t *>(qe.chars);
+            int64_t *qo = const_cast<int64_t *>(qe.off);
+            GTS_HIP(hipMemcpyAsync(qc, nc, std::max<int64_t>(noff[nq], 1), hipMemcpyDeviceToDevice, st));
+            GTS_HIP(hipMemcpyAsync(qo, no, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+            GTS_HIP(hipMemcpyAsync(idx->ws[W_QLEN].as<int32_t>(), nlen.data(), nq * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+            k::build_peq(qc, qo, nq, const_cast<uint64_t *>(qe.peq), st);
+            GTS_HIP(hipStreamSynchronize(st));
+        }
+    }
+    rec(idx, 1);
+
+    // ---- kNN bound ------------------------------------------------------------------
+    if (nq > 0 && b.any_knn) {
+        if (l2 && d.lpad > 0) {
+            if (!near) {
+                near = wsp<int32_t>(idx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
+                k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
+            }
+            k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
+                          d.dp, qv.Q32, kq, nq, d.tomb.as<uint32_t>(), 512, base, st);
+        } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
-            k::bound_l2(tv, ov, qv, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), win, base, home, st);
+            k::bound_l2(tv, ov, qv, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         } else {
-            k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
-            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), win, base, home, st);
+            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         }
     }
     const float delta = (float)((d.dim + 8) * 5.9604645e-8);
     if (nq > 0)
-        k::thresholds(base, idx->ws[W_QP].as<float>(), nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
-                      idx->ws[W_T].as<float>(), idx->ws[W_THR].as<float>(), st);
+        k::thresholds(base, idx->ws[W_QP].as<float>(), kq, nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
+                      idx->ws[W_T].as<float>(), idx->ws[W_THR].as<float>(), wsp<float>(idx, W_CUT, nqpad), st);
     rec(idx, 2);
     if (idx->timing && nq > 0) {
         GTS_HIP(hipStreamSynchronize(st));
@@ -453,25 +558,34 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             groups.push_back(std::move(go));
             continue;
         }
-        const int64_t tiles = (ng + kQTile - 1) / kQTile;
-        GTS_CHECK(tiles > 1, GTS_ENOMEM,
-                  "the memory budget cannot hold the candidates of one 64-query tile; raise mem_budget_bytes");
-        const int64_t half = (tiles / 2) * kQTile;
+        // split into halves of whole 16-query blocks (the bf16 fragment unit)
+        const int64_t blocks = (ng + 15) / 16;
+        GTS_CHECK(blocks > 1, GTS_ENOMEM,
+                  "the memory budget cannot hold the candidates of 16 queries; raise mem_budget_bytes");
+        const int64_t half = (blocks / 2) * 16;
         todo.insert(todo.begin(), {q0 + half, ng - half});
         todo.insert(todo.begin(), {q0, half});
     }
 
-    // ---- final CSR --------------------------------------------------------------------
+    // ---- final CSR (caller's query order) ------------------------------------------------
     int64_t total = 0;
     for (auto &g : groups) total += g.total;
-    std::vector<int64_t> offs(nq + 1, 0);
+    std::vector<int64_t> offs_b(nq + 1, 0);   // batch order
     {
         int64_t q = 0;
         for (auto &g : groups)
             for (uint32_t c : g.counts) {
-                offs[q + 1] = offs[q] + c;
+                offs_b[q + 1] = offs_b[q] + c;
                 q++;
             }
+    }
+    std::vector<int64_t> offs(nq + 1, 0);     // caller order
+    if (permuted) {
+        std::vector<int64_t> cnt(nq);
+        for (int64_t i = 0; i < nq; i++) cnt[perm[i]] = offs_b[i + 1] - offs_b[i];
+        for (int64_t q = 0; q < nq; q++) offs[q + 1] = offs[q] + cnt[q];
+    } else {
+        offs = offs_b;
     }
     auto *priv = new ResultPriv();
     priv->device = rloc == GTS_DEVICE;
@@ -491,28 +605,36 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         gts_result tmp{};
         tmp.priv = priv;
-        if (priv->device) {
-            if (priv->offsets) (void)hipFree(priv->offsets);
-            if (priv->ids) (void)hipFree(priv->ids);
-            if (priv->dist) (void)hipFree(priv->dist);
-        } else {
-            if (priv->offsets) (void)hipHostFree(priv->offsets);
-            if (priv->ids) (void)hipHostFree(priv->ids);
-            if (priv->dist) (void)hipHostFree(priv->dist);
-        }
-        delete priv;
+        free_result(&tmp);
         fail(GTS_ENOMEM, "result allocation failed");
+    }
+    // assemble on the device in batch order, un-permute, then place the result
+    int64_t *ids_b = wsp<int64_t>(idx, W_RES_IDS, std::max<int64_t>(total, 1));
+    uint32_t *dist_b = wsp<uint32_t>(idx, W_RES_DIST, std::max<int64_t>(total, 1));
+    int64_t at = 0;
+    for (auto &g : groups) {
+        if (g.total) {
+            GTS_HIP(hipMemcpyAsync(ids_b + at, g.ids.p, g.total * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+            GTS_HIP(hipMemcpyAsync(dist_b + at, g.dist.p, g.total * sizeof(float), hipMemcpyDeviceToDevice, st));
+        }
+        at += g.total;
+    }
+    int64_t *ids_c = ids_b;
+    uint32_t *dist_c = dist_b;
+    if (permuted && total > 0) {
+        ids_c = wsp<int64_t>(idx, W_RES_IDS2, total);
+        dist_c = wsp<uint32_t>(idx, W_RES_DIST2, total);
+        int64_t *doff = wsp<int64_t>(idx, W_OFF_ORIG, 2 * (nq + 1));
+        GTS_HIP(hipMemcpyAsync(doff, offs_b.data(), off_bytes, hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(doff + nq + 1, offs.data(), off_bytes, hipMemcpyHostToDevice, st));
+        k::unpermute(doff, doff + nq + 1, idx->ws[W_PERM].as<int32_t>(), nq, ids_b, dist_b, ids_c, dist_c, st);
     }
     const hipMemcpyKind to = priv->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     GTS_HIP(hipMemcpyAsync(priv->offsets, offs.data(), off_bytes,
                            priv->device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
-    int64_t at = 0;
-    for (auto &g : groups) {
-        if (g.total) {
-            GTS_HIP(hipMemcpyAsync(static_cast<int64_t *>(priv->ids) + at, g.ids.p, g.total * sizeof(int64_t), to, st));
-            GTS_HIP(hipMemcpyAsync(static_cast<float *>(priv->dist) + at, g.dist.p, g.total * sizeof(float), to, st));
-        }
-        at += g.total;
+    if (total) {
+        GTS_HIP(hipMemcpyAsync(priv->ids, ids_c, total * sizeof(int64_t), to, st));
+        GTS_HIP(hipMemcpyAsync(priv->dist, dist_c, total * sizeof(float), to, st));
     }
     GTS_HIP(hipStreamSynchronize(st));
     out->total = total;

@@ -1,0 +1,383 @@
+// Leaf-pivot kernels (L2): every leaf keeps one of its own objects as a
+// pivot p_L together with R_L = max over the leaf's objects o of d(o, p_L).
+// By Lemma 1 with that pivot, every o in L has d(q, o) >= d(q, p_L) - R_L, so
+// a leaf with d(q, p_L) - R_L > T holds no answer within T.  The distances
+// d(q, p_L) for all (query, leaf) pairs come from the same bf16 MFMA tiles as
+// the object distances, with a rigorous error margin.
+//
+//   k_leaf_near : the NB leaves whose pivots are nearest to each query (by the
+//                 bf16 estimate; a heuristic choice -- only used to pick
+//                 which exact distances bound the kNN radius and how queries
+//                 are grouped into tiles)
+//   k_leaf_ball : the leaf test above for every (64-query tile, leaf),
+//                 ANDed into the node filter's leaf masks
+//   k_bound_near: kNN radius bound: the k-th smallest exact float32 distance
+//                 over the objects of the nearest leaves
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace gts {
+namespace k {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16x8_t frag(uint4 v)
+{
+    bf16x8_t r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Nearest leaf pivots.  One wave per 16-query block (the MFMA B operand);
+// leaf pivots stream through as A fragments, 16 per MFMA row block.  Each
+// lane keeps a sorted top-NB of its 16 x (Lpad/16) estimates; the four lanes
+// holding the same query merge through LDS.
+// ---------------------------------------------------------------------------
+template <int KS, int NB>
+__global__ __launch_bounds__(256) void k_leaf_near(const uint4 *__restrict__ PL16t, const float *__restrict__ pln,
+                                                   int64_t lpad, const uint4 *__restrict__ Q16t, int64_t nq,
+                                                   int32_t *__restrict__ near)
+{
+    __shared__ float s_d[4][64][NB];
+    __shared__ int32_t s_l[4][64][NB];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t blk = (int64_t)blockIdx.x * 4 + wave;      // 16-query block
+    const bool live = blk * 16 < nq;
+    float bd[NB];
+    int32_t bl[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        bd[i] = INFINITY;
+        bl[i] = -1;
+    }
+    if (live) {
+        uint4 B[KS];
+#pragma unroll
+        for (int s = 0; s < KS; s++) B[s] = Q16t[(blk * KS + s) * 64 + lane];
+        const int rg = lane >> 4;
+        for (int64_t g = 0; g < lpad / 16; g++) {
+            floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; s++)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(PL16t[(g * KS + s) * 64 + lane]), frag(B[s]), acc,
+                                                               0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int32_t leaf = (int32_t)(16 * g + 4 * rg + e);
+                const float v = fmaf(-2.f, acc[e], pln[leaf]);   // d^2 - ||q||^2
+                if (v < bd[NB - 1]) {
+                    float cv = v;
+                    int32_t cl = leaf;
+#pragma unroll
+                    for (int i = 0; i < NB; i++) {
+                        if (cv < bd[i]) {
+                            const float td = bd[i];
+                            const int32_t tl = bl[i];
+                            bd[i] = cv;
+                            bl[i] = cl;
+                            cv = td;
+                            cl = tl;
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        s_d[wave][lane][i] = bd[i];
+        s_l[wave][lane][i] = bl[i];
+    }
+    __syncthreads();
+    if (!live || lane >= 16) return;
+    const int64_t q = blk * 16 + lane;
+    if (q >= nq) return;
+    // merge the four lists of this query (lanes lane, lane+16, lane+32, lane+48)
+    int idx[4] = {0, 0, 0, 0};
+    for (int i = 0; i < NB; i++) {
+        int best = -1;
+        float bv = INFINITY;
+        for (int j = 0; j < 4; j++) {
+            if (idx[j] < NB) {
+                const float v = s_d[wave][lane + 16 * j][idx[j]];
+                if (best < 0 || v < bv) {
+                    bv = v;
+                    best = j;
+                }
+            }
+        }
+        near[q * NB + i] = s_l[wave][lane + 16 * best][idx[best]];
+        idx[best]++;
+    }
+}
+
+void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps, const uint16_t *Q16t, int64_t nq,
+               int32_t *near, hipStream_t st)
+{
+    if (nq == 0) return;
+    const int64_t blocks16 = (nq + 15) / 16;
+    const unsigned grid = (unsigned)((blocks16 + 3) / 4);
+#define LN(KS)                                                                                              \
+    hipLaunchKernelGGL((k_leaf_near<KS, kNearLeaves>), dim3(grid), dim3(256), 0, st,                        \
+                       reinterpret_cast<const uint4 *>(PL16t), pln, lpad, reinterpret_cast<const uint4 *>(Q16t), \
+                       nq, near)
+    switch (ksteps) {
+    case 1: LN(1); break;
+    case 2: LN(2); break;
+    case 3: LN(3); break;
+    default: LN(4); break;
+    }
+#undef LN
+}
+
+// ---------------------------------------------------------------------------
+// Leaf ball test.  One wave per (64-query tile, 64-leaf group): 4 leaf row
+// blocks x 4 query column blocks of MFMA.  A (query, leaf) pair passes when
+// the lower bound of d(q, p_L) minus R_L does not exceed T_q; per leaf the 64
+// pass bits of the tile are assembled through LDS and ANDed into the mask.
+// ---------------------------------------------------------------------------
+template <int KS>
+__global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL16t, const float *__restrict__ pln,
+                                                   const float *__restrict__ ple, const float *__restrict__ leafR,
+                                                   int64_t n_leaves, int64_t ngroups, const uint4 *__restrict__ Q16t,
+                                                   const float *__restrict__ qn, const float *__restrict__ qe,
+                                                   const float *__restrict__ T, int64_t nq, int ntiles,
+                                                   uint64_t *__restrict__ leaf_mask, float eps_a, float eps_b)
+{
+    __shared__ uint16_t s_bits[4][64][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t w0 = (int64_t)blockIdx.x * 4 + wave;
+    const bool live = w0 < (int64_t)ntiles * ngroups;   // no early exit: the block meets a barrier below
+    const int64_t w = live ? w0 : 0;
+    const int tile = (int)(w / ngroups);
+    const int64_t lg = w % ngroups;
+    const int rg = lane >> 4, col = lane & 15;
+    uint4 A[4][KS];
+    float pn[4][4], pe[4][4], R[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+#pragma unroll
+        for (int s = 0; s < KS; s++) A[r][s] = PL16t[((lg * 4 + r) * KS + s) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int64_t leaf = lg * 64 + 16 * r + 4 * rg + e;
+            pn[r][e] = pln[leaf];
+            pe[r][e] = ple[leaf];
+            R[r][e] = leaf < n_leaves ? leafR[leaf] : -INFINITY;
+        }
+    }
+    for (int c = 0; c < 4; c++) {
+        const int64_t q = (int64_t)tile * 64 + 16 * c + col;
+        uint4 B[KS];
+#pragma unroll
+        for (int s = 0; s < KS; s++) B[s] = Q16t[(((int64_t)tile * 4 + c) * KS + s) * 64 + lane];
+        float qnn = 0.f, qerr = 0.f, tq = -INFINITY;
+        if (q < nq) {
+            qnn = qn[q];
+            qerr = qe[q];
+            tq = T[q];
+        }
+        floatx4_t acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[r] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(A[r][s]), frag(B[s]), acc[r], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float d2 = qnn + fmaf(-2.f, acc[r][e], pn[r][e]);
+                const float eps = eps_a * (qnn + pn[r][e]) + eps_b * sqrtf(qnn * pn[r][e]) + 8.f * 5.9604645e-8f * fabsf(d2);
+                const float lo = sqrtf(fmaxf(d2 - eps, 0.f)) - qerr - pe[r][e];
+                const bool pass = q < nq && lo - R[r][e] <= tq;
+                const uint64_t b = dev::ballot(pass);
+                // lanes 16j..16j+15 hold leaf 16r + 4j + e, queries 0..15
+                if (col == 0) s_bits[wave][16 * r + 4 * rg + e][c] = (uint16_t)(b >> (16 * rg));
+            }
+    }
+    __syncthreads();
+    const int64_t leaf = lg * 64 + lane;
+    if (live && leaf < n_leaves) {
+        const uint64_t m = (uint64_t)s_bits[wave][lane][0] | ((uint64_t)s_bits[wave][lane][1] << 16) |
+                           ((uint64_t)s_bits[wave][lane][2] << 32) | ((uint64_t)s_bits[wave][lane][3] << 48);
+        leaf_mask[(size_t)leaf * ntiles + tile] &= m;
+    }
+}
+
+void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
+               int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
+               int ntiles, uint64_t *leaf_mask, hipStream_t st)
+{
+    if (nq == 0 || n_leaves == 0) return;
+    const int64_t ngroups = (n_leaves + 63) / 64;
+    const int64_t waves = (int64_t)ntiles * ngroups;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    const float u = 5.9604645e-8f;
+    const int D = ksteps * 32;
+    const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u;
+#define LB(KS)                                                                                                 \
+    hipLaunchKernelGGL(k_leaf_ball<KS>, dim3(grid), dim3(256), 0, st, reinterpret_cast<const uint4 *>(PL16t), pln, \
+                       ple, leafR, n_leaves, ngroups, reinterpret_cast<const uint4 *>(Q16t), qn, qe, T, nq, ntiles, \
+                       leaf_mask, eps_a, eps_b)
+    switch (ksteps) {
+    case 1: LB(1); break;
+    case 2: LB(2); break;
+    case 3: LB(3); break;
+    default: LB(4); break;
+    }
+#undef LB
+}
+
+// ---------------------------------------------------------------------------
+// kNN radius bound from the nearest leaves: exact float32 distances to the
+// objects of the query's nearest leaves (in order, while at most kWinObj
+// objects and until at least max(k, target) were taken); the k-th smallest
+// live distance bounds the k-th nearest neighbour distance from above.
+// ---------------------------------------------------------------------------
+constexpr int kWinObj = 2048;
+
+__global__ __launch_bounds__(64) void k_bound_near(const int32_t *__restrict__ near, const int32_t *__restrict__ leaf_first,
+                                                   const int32_t *__restrict__ leaf_cnt, const float *__restrict__ X32,
+                                                   int dp, const float *__restrict__ Q32, const int32_t *__restrict__ kq,
+                                                   int64_t nq, const uint32_t *__restrict__ tomb, int target,
+                                                   float *__restrict__ tq)
+{
+    __shared__ float s_d[kWinObj];
+    const int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    const int k = kq[q];
+    if (k <= 0) return;
+    const int lane = threadIdx.x;
+    const int want = k > target ? k : target;
+    int count = 0;
+    const float4 *y = reinterpret_cast<const float4 *>(Q32 + (size_t)q * dp);
+    for (int i = 0; i < kNearLeaves && count < want; i++) {
+        const int32_t leaf = near[q * kNearLeaves + i];
+        if (leaf < 0) break;
+        const int cnt = leaf_cnt[leaf];
+        if (count + cnt > kWinObj) break;
+        const int p0 = leaf_first[leaf];
+        for (int j = lane; j < cnt; j += 64) {
+            const int p = p0 + j;
+            float d = INFINITY;
+            if (!((tomb[p >> 5] >> (p & 31)) & 1u)) {
+                const float4 *x = reinterpret_cast<const float4 *>(X32 + (size_t)p * dp);
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                for (int c = 0; c < dp / 4; c++) {
+                    const float4 u = x[c], v = y[c];
+                    const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+                    a0 = fmaf(d0, d0, a0);
+                    a1 = fmaf(d1, d1, a1);
+                    a2 = fmaf(d2, d2, a2);
+                    a3 = fmaf(d3, d3, a3);
+                }
+                d = sqrtf((a0 + a1) + (a2 + a3));
+            }
+            s_d[count + j] = d;
+        }
+        count += cnt;
+    }
+    if (count < k) {
+        if (lane == 0) tq[q] = INFINITY;
+        return;
+    }
+    const int P = dev::next_pow2(count);
+    for (int j = count + lane; j < P; j += 64) s_d[j] = INFINITY;
+    dev::bitonic_sort(s_d, P);
+    if (lane == 0) tq[q] = s_d[k - 1];
+}
+
+void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
+                const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
+                hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(64), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
+                       kq, nq, tomb, target, tq);
+}
+
+// ---------------------------------------------------------------------------
+// Query permutation helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_gather_rows(const float *__restrict__ src, const int32_t *__restrict__ perm, int64_t rows, int dp,
+                              float *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x;
+    if (i >= rows) return;
+    const float *s = src + (size_t)perm[i] * dp;
+    float *d = dst + (size_t)i * dp;
+    for (int c = threadIdx.x; c < dp; c += blockDim.x) d[c] = s[c];
+}
+
+void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st)
+{
+    if (rows == 0) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)rows), dim3(64), 0, st, src, perm, rows, dp, dst);
+}
+
+__global__ void k_gather_i32(const int32_t *__restrict__ src, const int32_t *__restrict__ perm, int64_t rows, int width,
+                             int32_t *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * width) return;
+    const int64_t r = i / width, c = i % width;
+    dst[i] = src[(size_t)perm[r] * width + c];
+}
+
+void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width, int32_t *dst, hipStream_t st)
+{
+    if (rows == 0) return;
+    const int64_t n = rows * width;
+    hipLaunchKernelGGL(k_gather_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, perm, rows, width, dst);
+}
+
+// Strings: dst string i <- src string perm[i] (dst offsets precomputed).
+__global__ void k_gather_strings(const uint8_t *__restrict__ src, const int64_t *__restrict__ src_off,
+                                 const int32_t *__restrict__ perm, int64_t n, const int64_t *__restrict__ dst_off,
+                                 uint8_t *__restrict__ dst)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const int64_t a = src_off[perm[i]], len = src_off[perm[i] + 1] - a, b = dst_off[i];
+    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) dst[b + j] = src[a + j];
+}
+
+void gather_strings(const uint8_t *src, const int64_t *src_off, const int32_t *perm, int64_t n, const int64_t *dst_off,
+                    uint8_t *dst, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_strings, dim3((unsigned)n), dim3(64), 0, st, src, src_off, perm, n, dst_off, dst);
+}
+
+// Answers computed in permuted query order -> original order:
+// dst segment of original query perm[i] <- src segment i.
+__global__ void k_unpermute(const int64_t *__restrict__ src_off, const int64_t *__restrict__ dst_off,
+                            const int32_t *__restrict__ perm, int64_t nq, const int64_t *__restrict__ src_ids,
+                            const uint32_t *__restrict__ src_dist, int64_t *__restrict__ dst_ids,
+                            uint32_t *__restrict__ dst_dist)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= nq) return;
+    const int64_t a = src_off[i], n = src_off[i + 1] - a;
+    const int64_t b = dst_off[perm[i]];
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        dst_ids[b + j] = src_ids[a + j];
+        dst_dist[b + j] = src_dist[a + j];
+    }
+}
+
+void unpermute(const int64_t *src_off, const int64_t *dst_off, const int32_t *perm, int64_t nq, const int64_t *src_ids,
+               const uint32_t *src_dist, int64_t *dst_ids, uint32_t *dst_dist, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_unpermute, dim3((unsigned)nq), dim3(64), 0, st, src_off, dst_off, perm, nq, src_ids, src_dist,
+                       dst_ids, dst_dist);
+}
+
+}  // namespace k
+}  // namespace gts

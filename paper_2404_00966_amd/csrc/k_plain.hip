@@ -85,7 +85,10 @@ __device__ __forceinline__ void emit_verified(const PlainArgs &a, int64_t q, uin
 // ---------------------------------------------------------------------------
 // L2
 // ---------------------------------------------------------------------------
-__device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, const float *qrow, float base,
+// cut: the emission cutoff -- the radius for range queries; for kNN queries
+// the bound widened to cover any float32 summation order (the final top-k
+// is taken when the answers are sorted).
+__device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, const float *qrow, float cut,
                                const int32_t *s_cand, int nc, long long *verified)
 {
     const int grp = threadIdx.x >> 4, sl = threadIdx.x & 15;
@@ -106,7 +109,7 @@ __device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, c
         if (sl == 0 && c < nc) {
             (*verified)++;
             const float d = sqrtf(acc);
-            if (d <= base) emit_verified(a, q, __float_as_uint(d), a.ids[p]);
+            if (d <= cut) emit_verified(a, q, __float_as_uint(d), a.ids[p]);
         }
     }
 }
@@ -148,8 +151,38 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
         for (int p = 0; p < MP; p++) qmax = fmaxf(qmax, s_qp[p]);
         const float T = base * (1.f + 2.f * a.delta);
         const float thr = T + 2.f * a.delta * (qmax + a.pt_max);
+        const float cut = a.kq[q] > 0 ? T : base;
         int32_t *lv = tree_frontier<MP>(t, s_qp, thr, fr0, fr1, &s_nf, &tests);
-        const int nf = s_nf;
+        int nf = s_nf;
+        if (a.leaf_piv32) {
+            // Lemma 1 with each surviving leaf's own pivot: the leaf is kept
+            // unless d(q, p_L) - R_L > T (16 lanes per leaf pivot distance)
+            int32_t *other = lv == fr0 ? fr1 : fr0;
+            __syncthreads();
+            if (threadIdx.x == 0) s_nf = 0;
+            __syncthreads();
+            const int grp = threadIdx.x >> 4, sl = threadIdx.x & 15;
+            for (int e0 = 0; e0 < nf; e0 += kPlainBlock / 16) {
+                const int e = e0 + grp;
+                const int32_t node = e < nf ? lv[e] : 0;
+                float acc = 0.f;
+                if (e < nf) {
+                    const float *pv = a.leaf_piv32 + (size_t)(node - t.leaf0) * o.dp;
+                    for (int dd = sl; dd < o.dp; dd += 16) {
+                        const float df = qrow[dd] - pv[dd];
+                        acc = fmaf(df, df, acc);
+                    }
+                }
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+                bool pass = false;
+                if (e < nf) pass = sqrtf(acc) * (1.f - 2.f * a.delta) - a.leafR[node - t.leaf0] <= T;
+                block_push(sl == 0 && pass, node, other, &s_nf);
+            }
+            __syncthreads();
+            nf = s_nf;
+            lv = other;
+        }
         leaves += nf;
         for (int e = 0; e < nf; e++) {
             const int64_t leaf = lv[e] - t.leaf0;
@@ -159,7 +192,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
                 __syncthreads();
                 const int nc = s_nc;
                 if (nc + kPlainBlock > kPlainCand) {
-                    plain_flush_l2(o, a, q, qrow, base, s_cand, nc, &verified);
+                    plain_flush_l2(o, a, q, qrow, cut, s_cand, nc, &verified);
                     __syncthreads();
                     if (threadIdx.x == 0) s_nc = 0;
                     __syncthreads();
@@ -178,7 +211,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
             }
         }
         __syncthreads();
-        plain_flush_l2(o, a, q, qrow, base, s_cand, s_nc, &verified);
+        plain_flush_l2(o, a, q, qrow, cut, s_cand, s_nc, &verified);
         __syncthreads();
     }
     if (threadIdx.x % 16 == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);

@@ -166,14 +166,15 @@ void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *p
     hipLaunchKernelGGL(k_build_peq, dim3((unsigned)nq), dim3(256), 0, st, chars, off, nq, peq);
 }
 
-// Per-query threshold for node and object filtering:
+// Per-query thresholds for node and object filtering:
 //   L2:   thr = T + 2*delta*(max_i QP[q][i] + pt_max), T = base * (1 + 2*delta)
-//   EDIT: thr = floor(base)
+//         cut = base (range) or T (kNN): the float32-distance emission cutoff
+//   EDIT: thr = T = cut = floor(base)
 // where base is the range radius or the kNN bound and delta bounds the
 // relative float32 error of a direct-difference distance in `dim` dimensions.
-__global__ void k_thresholds(const float *__restrict__ base, const float *__restrict__ QP, int64_t nq, int mpad,
-                             int is_edit, float delta, float pt_max, float *__restrict__ T,
-                             float *__restrict__ thr)
+__global__ void k_thresholds(const float *__restrict__ base, const float *__restrict__ QP, const int32_t *__restrict__ kq,
+                             int64_t nq, int mpad, int is_edit, float delta, float pt_max, float *__restrict__ T,
+                             float *__restrict__ thr, float *__restrict__ cut)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
@@ -182,6 +183,7 @@ __global__ void k_thresholds(const float *__restrict__ base, const float *__rest
         float t = floorf(fminf(b, 1e6f));
         T[q] = t;
         thr[q] = t;
+        cut[q] = t;
         return;
     }
     float qmax = 0.f;
@@ -189,14 +191,15 @@ __global__ void k_thresholds(const float *__restrict__ base, const float *__rest
     float t = b * (1.f + 2.f * delta);
     T[q] = t;
     thr[q] = t + 2.f * delta * (qmax + pt_max);
+    cut[q] = kq[q] > 0 ? t : b;
 }
 
-void thresholds(const float *base, const float *QP, int64_t nq, int mpad, int is_edit, float delta, float pt_max,
-                float *T, float *thr, hipStream_t st)
+void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t nq, int mpad, int is_edit, float delta,
+                float pt_max, float *T, float *thr, float *cut, hipStream_t st)
 {
     if (nq == 0) return;
-    hipLaunchKernelGGL(k_thresholds, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, base, QP, nq, mpad,
-                       is_edit, delta, pt_max, T, thr);
+    hipLaunchKernelGGL(k_thresholds, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, base, QP, kq, nq, mpad,
+                       is_edit, delta, pt_max, T, thr, cut);
 }
 
 // Fill an int32 / uint64 array (a small kernel, so no memset node is needed

@@ -328,11 +328,11 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
             uint64_t mask = 0;
             for (int l = l_lo; l <= l_hi; l++) mask |= leaf_mask[(size_t)l * ntiles + t];
             if (!mask) continue;
-            pairs++;
 #pragma unroll 1
             for (int c = 0; c < 4; c++) {
                 const uint32_t cm = (uint32_t)(mask >> (16 * c)) & 0xffffu;
                 if (!cm) continue;
+                pairs++;
                 const int64_t q = (int64_t)t * 64 + 16 * c + col;
                 float th = -INFINITY, qnn = 0.f;
                 if (q < nq && ((cm >> col) & 1u)) {
@@ -518,6 +518,7 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
 // Cache list (Sec. 4.3): brute force over every live cached object.
 // ---------------------------------------------------------------------------
 // L2: 16 lanes per (query, slot) pair, float32 direct difference.
+// cut[q]: range radius, or for kNN the widened bound T (any summation order)
 __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp, const float *__restrict__ C32,
                                 const uint32_t *__restrict__ cids, const uint32_t *__restrict__ clive,
                                 int64_t ncache, const float *__restrict__ base, Cand *__restrict__ cands,

@@ -30,8 +30,8 @@ void dist_edit_pivots_i32(const uint8_t *chars, const int64_t *off, int64_t rows
                           const int32_t *poff, int m, int32_t *out, int64_t s_piv, int64_t s_row,
                           hipStream_t st);
 void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *peq, hipStream_t st);
-void thresholds(const float *base, const float *QP, int64_t nq, int mpad, int is_edit, float delta,
-                float pt_max, float *T, float *thr, hipStream_t st);
+void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t nq, int mpad, int is_edit,
+                float delta, float pt_max, float *T, float *thr, float *cut, hipStream_t st);
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
 // ---- tree and candidates (k_search.hip) ------------------------------------
@@ -137,6 +137,23 @@ void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hi
 void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,
                int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i, hipStream_t st);
 
+// ---- leaf pivots (k_leaf.hip) -------------------------------------------------
+constexpr int kNearLeaves = 8;   // nearest leaf pivots kept per query
+void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps, const uint16_t *Q16t, int64_t nq,
+               int32_t *near, hipStream_t st);
+void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
+               int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
+               int ntiles, uint64_t *leaf_mask, hipStream_t st);
+void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
+                const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
+                hipStream_t st);
+void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st);
+void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width, int32_t *dst, hipStream_t st);
+void gather_strings(const uint8_t *src, const int64_t *src_off, const int32_t *perm, int64_t n, const int64_t *dst_off,
+                    uint8_t *dst, hipStream_t st);
+void unpermute(const int64_t *src_off, const int64_t *dst_off, const int32_t *perm, int64_t nq, const int64_t *src_ids,
+               const uint32_t *src_dist, int64_t *dst_ids, uint32_t *dst_dist, hipStream_t st);
+
 // ---- plain one-query-per-workgroup path (k_plain.hip) -----------------------
 struct PlainArgs {
     int64_t nq;
@@ -151,6 +168,8 @@ struct PlainArgs {
     int64_t out_cap;
     unsigned long long *counters;
     float delta, pt_max;
+    const float *leaf_piv32;   // [n_leaves][dp] leaf pivot vectors (L2; null: no leaf test)
+    const float *leafR;        // [n_leaves] largest pivot distance in the leaf
 };
 void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const float *PT, const float *Q32,
               const PlainArgs &a, hipStream_t st);

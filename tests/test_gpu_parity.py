@@ -212,7 +212,7 @@ def test_two_stage_budget_gives_same_answers(gts):
     assert idx.stats()["groups"] == 1
     cands = idx.stats()["candidates"]
     # a budget for about a third of the batch's candidates: several groups run
-    # one after another, each of whole 64-query tiles
+    # one after another, each of whole 16-query blocks
     small = idx.search(_dev(Q), radius=radius, k=k, mem_budget_bytes=40 * (cands // 3)).to_lists()
     assert idx.stats()["groups"] > 1
     for (a, b), (c, e) in zip(big, small):
