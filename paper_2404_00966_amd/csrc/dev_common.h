@@ -59,15 +59,16 @@ __device__ __forceinline__ float wave_min(float v)
 // ---------------------------------------------------------------------------
 // Levenshtein distance by bit-parallel vertical deltas (Myers 1999; the
 // global-distance form where row 0 holds D[0][j] = j).  The pattern has up to
-// 64*W characters; peq[c * 4 + w] holds bit i of word w set iff pattern[64w+i]
-// == c (a 256-row table, 4 words per row).  Returns the exact distance when it
-// is <= cutoff, otherwise some value > cutoff (early exit as soon as the last
-// row proves the final distance exceeds cutoff: each remaining text character
-// can lower it by at most one).
+// 64*W characters.  Bytes are first mapped to alphabet codes by lut (the
+// index's alphabet; bytes outside it share the last, all-zero row); peq[c*4+w]
+// holds bit i of word w set iff pattern[64w+i] has code c.  Returns the exact
+// distance when it is <= cutoff, otherwise some value > cutoff (early exit as
+// soon as the last row proves the final distance exceeds cutoff: each
+// remaining text character can lower it by at most one).
 // ---------------------------------------------------------------------------
-template <int W, class PeqPtr>
+template <int W, class PeqPtr, class LutPtr>
 __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_t *text, int tlen,
-                                              int cutoff)
+                                              int cutoff, LutPtr lut)
 {
     if (plen == 0) return tlen;
     uint64_t VP[W], VN[W];
@@ -81,7 +82,7 @@ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_
     const uint64_t topbit = 1ull << ((plen - 1) & 63);
     int score = plen;
     for (int j = 0; j < tlen; j++) {
-        const int c = text[j];
+        const int c = lut[text[j]];
         uint64_t Eq[W], Xv[W], Xh[W], HP[W], HN[W];
         uint64_t carry = 0;
 #pragma unroll
@@ -122,13 +123,27 @@ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_
     return score;
 }
 
-template <class PeqPtr>
-__device__ __forceinline__ int myers_any(PeqPtr peq, int plen, const uint8_t *text, int tlen, int cutoff)
+template <class PeqPtr, class LutPtr>
+__device__ __forceinline__ int myers_any(PeqPtr peq, int plen, const uint8_t *text, int tlen, int cutoff, LutPtr lut)
 {
-    if (plen <= 64) return myers_distance<1>(peq, plen, text, tlen, cutoff);
-    if (plen <= 128) return myers_distance<2>(peq, plen, text, tlen, cutoff);
-    if (plen <= 192) return myers_distance<3>(peq, plen, text, tlen, cutoff);
-    return myers_distance<4>(peq, plen, text, tlen, cutoff);
+    if (plen <= 64) return myers_distance<1>(peq, plen, text, tlen, cutoff, lut);
+    if (plen <= 128) return myers_distance<2>(peq, plen, text, tlen, cutoff, lut);
+    if (plen <= 192) return myers_distance<3>(peq, plen, text, tlen, cutoff, lut);
+    return myers_distance<4>(peq, plen, text, tlen, cutoff, lut);
+}
+
+// Set the match bits of one pattern in a table of `rows` codes (zeroed by the
+// caller); bytes outside the alphabet (code rows-1) set nothing, so they match
+// no text byte.  Threads stride over the pattern; atomic OR on the table.
+template <class Tab>
+__device__ __forceinline__ void peq_fill(Tab tab, const uint8_t *pat, int plen, const uint8_t *lut, int rows)
+{
+    for (int b = threadIdx.x; b < plen; b += blockDim.x) {
+        const int c = lut[pat[b]];
+        if (c < rows - 1)
+            atomicOr(reinterpret_cast<unsigned long long *>(&tab[c * 4 + (b >> 6)]),
+                     (unsigned long long)(1ull << (b & 63)));
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,8 @@ constexpr int kMaxPivots = 32;      // pivot table rows (padded to 8/16/32)
 constexpr int kMaxMfmaDim = 128;    // largest L2 dimension on the MFMA path
 constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
 constexpr int kSortCap = 4096;      // per-query keys sorted in LDS
+constexpr int kWorkspaceSlots = 48;   // named query buffers of an index
+constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 
 // Device buffer owned by the index (hipMalloc / hipFree).
 struct DevBuf {
@@ -129,6 +131,9 @@ struct IndexData {
     DevBuf pchars;               // uint8 pivot strings
     DevBuf poff;                 // int32 [m + 1]
     std::vector<std::string> pivot_str;
+    DevBuf cchars;               // uint8 centre strings, in chain order
+    DevBuf coff;                 // int32 [n_centres + 1]
+    int32_t n_centres = 0;
     // both
     float pt_max = 0.f;          // largest pivot-table value
     DevBuf ids;                  // uint32 [n] id at each position
@@ -174,6 +179,9 @@ struct HostObjects {
 void build_tree(gts_index *idx, const HostObjects &objs);
 // Rebuild over every live object (tree and cache), keeping ids.
 void rebuild(gts_index *idx);
+// Add the bytes of `chars` to the index alphabet (uploads the table when it
+// changes; blocking).
+void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars);
 // Streamed updates.
 void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids);
 int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
@@ -204,6 +212,13 @@ struct gts_index {
     gts_build_opts opts{};
     bool timing = false;
     gts_stats stats{};
+    // Byte alphabet of every string stored so far (EDIT): lut[b] is the code
+    // of byte b, or arows - 1 for a byte never stored (such a byte in a query
+    // matches nothing).  Codes only grow with inserts; nothing stored depends
+    // on them, every match table is built at query time.
+    bool alpha[256] = {};
+    gts::DevBuf lut;                   // uint8 [256]
+    int32_t arows = 1;
     // query workspace (grown on demand, reused across calls)
-    gts::DevBuf ws[40];
+    gts::DevBuf ws[gts::kWorkspaceSlots];
 };

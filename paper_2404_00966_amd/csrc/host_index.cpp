@@ -1,17 +1,20 @@
 // Index construction and streamed updates (host orchestration; the distance
 // work runs in GPU kernels).
 //
-// Construction follows Sec. 4.2 with the pivots made global: m pivots are
-// chosen once by farthest-first traversal (Algorithm 2's FFT rule, first
-// pivot seeded), every object's distance to every pivot is kept in a pivot
-// table, and the tree is built layer by layer (Algorithm 1): each node sorts
-// its objects by distance to one pivot and hands them out equal-count to its
-// F children, the last child taking the remainder (Algorithm 3).  The pivot a
-// node splits on is the one whose distances spread widest inside the node.
-// Every node keeps the box [min, max] of its objects' distances to every
-// pivot, which is what the query-time filters test (Lemma 1 on all pivots).
+// Construction follows Sec. 4.2.  m global pivots are chosen once by
+// farthest-first traversal (Algorithm 2's FFT rule, first pivot seeded) and
+// every object's distance to every one of them is kept in a pivot table.  The
+// tree is built layer by layer (Algorithm 1): each node picks its own pivots
+// among its objects (FFT again), orders its objects by nearest node pivot and
+// distance, and hands them out equal-count to its F children, the last child
+// taking the remainder (Algorithm 3).  Every node keeps the box [min, max] of
+// its objects' distances to every global pivot, which is what the query-time
+// filters test (Lemma 1 on all pivots at once).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "gts_internal.h"
@@ -30,6 +33,19 @@ uint64_t splitmix64(uint64_t *s)
 }
 
 int pad_pivots(int m) { return m <= 8 ? 8 : (m <= 16 ? 16 : 32); }
+
+// Stage timer for the build, printed to stderr when GTS_VERBOSE is set.
+struct StageClock {
+    bool on = std::getenv("GTS_VERBOSE") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char *what) {
+        if (!on) return;
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[gts build] %-28s %8.1f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
 
 // Number of partition layers: the paper's height rule, or the smallest depth
 // whose average leaf holds at most leaf_size objects.
@@ -65,11 +81,33 @@ template <class T> void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s
 
 }  // namespace
 
+void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars)
+{
+    bool seen[256] = {};
+    for (uint8_t b : chars) seen[b] = true;
+    bool grew = !idx->lut.p;
+    for (int b = 0; b < 256; b++)
+        if (seen[b] && !idx->alpha[b]) {
+            idx->alpha[b] = true;
+            grew = true;
+        }
+    if (!grew) return;
+    std::vector<uint8_t> lut(256);
+    int code = 0;
+    for (int b = 0; b < 256; b++)
+        if (idx->alpha[b]) lut[b] = (uint8_t)code++;
+    for (int b = 0; b < 256; b++)
+        if (!idx->alpha[b]) lut[b] = (uint8_t)code;   // the all-zero row
+    idx->arows = code + 1;
+    upload(idx->lut, lut, idx->stream);
+}
+
 void build_tree(gts_index *idx, const HostObjects &objs)
 {
     hipStream_t st = idx->stream;
     IndexData &d = idx->data;
     Tree &t = d.tree;
+    StageClock clock;
     const int64_t n = objs.count();
     GTS_CHECK(n >= 1, GTS_EINVAL, "an index needs at least one object");
     GTS_CHECK(n < (int64_t)1 << 31, GTS_ENOTSUP, "at most 2^31-1 objects per index");
@@ -113,10 +151,12 @@ void build_tree(gts_index *idx, const HostObjects &objs)
             GTS_HIP(hipMemset2DAsync(static_cast<char *>(in_x.p) + objs.dim * sizeof(float), d.dp * sizeof(float), 0,
                                      (d.dp - d.dim) * sizeof(float), n, st));
     } else {
+        alphabet_add(idx, objs.chars);
         upload(in_chars, objs.chars, st);
         upload(in_off, objs.offsets, st);
     }
 
+    clock.mark("upload");
     // ---- pivots by farthest-first traversal -------------------------------
     std::vector<float> PTin((size_t)m * n);       // [m][n], input order
     std::vector<float> mind(n, INFINITY);
@@ -138,7 +178,8 @@ void build_tree(gts_index *idx, const HostObjects &objs)
             upload(piv_buf, pc, st);
             upload(piv_off, po, st);
             k::dist_edit_pivots_f32(in_chars.as<uint8_t>(), in_off.as<int64_t>(), n, piv_buf.as<uint8_t>(),
-                                    piv_off.as<int32_t>(), 1, 1, dist_buf.as<float>(), 0, 1, st);
+                                    piv_off.as<int32_t>(), 1, 1, dist_buf.as<float>(), 0, 1, idx->lut.as<uint8_t>(),
+                                    idx->arows, st);
         }
         float *row = PTin.data() + (size_t)i * n;
         GTS_HIP(hipMemcpyAsync(row, dist_buf.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -155,49 +196,136 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         next = arg;
     }
 
-    // ---- layer-by-layer equal-count partition ------------------------------
+    clock.mark("global pivots + table");
+    // ---- leaf order: farthest-first centres, cells, chain, cuts ------------
+    // The shape of the tree is fixed (levels, fanout); the partition decides
+    // the order of the objects and where each leaf begins.  Every object joins
+    // the cell of its nearest farthest-first centre; cells are laid out along
+    // a nearest-neighbour chain of their centres and, inside a cell, objects
+    // by distance to the centre.  Leaf boundaries start equal-count and each
+    // moves to a cell boundary within half a leaf when there is one, so that
+    // leaves do not straddle clusters.  A node covers its F children's runs.
     std::vector<int64_t> perm(n);
-    std::iota(perm.begin(), perm.end(), 0);
     std::vector<int64_t> nfirst(t.n_nodes, 0), ncnt(t.n_nodes, 0);
-    nfirst[0] = 0;
-    ncnt[0] = n;
-    int64_t first = 0, count = 1;
-    for (int l = 0; l < t.levels; l++) {
-        for (int64_t v = first; v < first + count; v++) {
-            const int64_t a = nfirst[v], sz = ncnt[v];
-            if (sz > 1) {
-                int best_i = 0;
-                float best_w = -1.f;
-                for (int i = 0; i < m; i++) {
-                    const float *row = PTin.data() + (size_t)i * n;
-                    float lo = INFINITY, hi = -INFINITY;
-                    for (int64_t j = a; j < a + sz; j++) {
-                        lo = std::min(lo, row[perm[j]]);
-                        hi = std::max(hi, row[perm[j]]);
-                    }
-                    if (hi - lo > best_w) {
-                        best_w = hi - lo;
-                        best_i = i;
-                    }
-                }
-                const float *row = PTin.data() + (size_t)best_i * n;
-                const std::vector<uint32_t> &ids = objs.ids;
-                std::sort(perm.begin() + a, perm.begin() + a + sz, [&](int64_t x, int64_t y) {
-                    if (row[x] != row[y]) return row[x] < row[y];
-                    return ids[x] < ids[y];
-                });
+    {
+        const int K = (int)std::max<int64_t>(1, std::min<int64_t>({t.n_leaves / 8, (int64_t)kMaxCentres, n}));
+        DevBuf d_keys, d_cent, d_mind, d_near, d_cx, d_coff, d_coff32, d_dk;
+        std::vector<uint64_t> keys(K + 1, 0ull);
+        uint64_t crng = (idx->opts.seed ? idx->opts.seed : 0x2404009660ULL) ^ 0x5bd1e9955bd1e995ULL;
+        const int64_t first_centre = (int64_t)(splitmix64(&crng) % (uint64_t)n);
+        keys[0] = (uint64_t)(0xffffffffu - (uint32_t)first_centre);
+        upload(d_keys, keys, st);
+        d_cent.alloc((size_t)K * sizeof(int32_t));
+        d_mind.alloc((size_t)n * sizeof(float));
+        d_near.alloc((size_t)n * sizeof(int32_t));
+        if (l2)
+            k::fft_centers_l2(in_x.as<float>(), n, d.dp, K, d_keys.as<uint64_t>(), d_cent.as<int32_t>(),
+                              d_mind.as<float>(), d_near.as<int32_t>(), st);
+        else
+            k::fft_centers_edit(in_chars.as<uint8_t>(), in_off.as<int64_t>(), n, idx->lut.as<uint8_t>(), idx->arows,
+                                K, d_keys.as<uint64_t>(), d_cent.as<int32_t>(), d_mind.as<float>(),
+                                d_near.as<int32_t>(), st);
+        std::vector<int32_t> cent(K), nearc(n);
+        std::vector<float> cmind(n);
+        GTS_HIP(hipMemcpyAsync(cent.data(), d_cent.p, (size_t)K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(nearc.data(), d_near.p, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(cmind.data(), d_mind.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        clock.mark("centres");
+        // centre-to-centre distances, then the chain
+        std::vector<float> dk((size_t)K * K);
+        d_dk.alloc(dk.size() * sizeof(float));
+        std::vector<uint8_t> cc;
+        std::vector<int64_t> coff{0};
+        if (l2) {
+            std::vector<float> cx((size_t)K * d.dp, 0.f);
+            for (int c = 0; c < K; c++)
+                std::copy(objs.vecs.begin() + (size_t)cent[c] * d.dim, objs.vecs.begin() + (size_t)(cent[c] + 1) * d.dim,
+                          cx.begin() + (size_t)c * d.dp);
+            upload(d_cx, cx, st);
+            k::dist_l2_pivots(d_cx.as<float>(), K, d_cx.as<float>(), K, K, d.dp, d_dk.as<float>(), K, 1, st);
+        } else {
+            for (int c = 0; c < K; c++) {
+                cc.insert(cc.end(), objs.chars.begin() + objs.offsets[cent[c]],
+                          objs.chars.begin() + objs.offsets[cent[c] + 1]);
+                coff.push_back((int64_t)cc.size());
             }
-            const int64_t avg = sz / F;
-            for (int j = 0; j < F; j++) {
-                const int64_t c = v * F + 1 + j;
-                nfirst[c] = a + j * avg;
-                ncnt[c] = (j < F - 1) ? avg : sz - avg * (F - 1);
+            std::vector<int32_t> coff32(coff.begin(), coff.end());
+            if (cc.empty()) cc.push_back(0);
+            upload(d_cx, cc, st);
+            upload(d_coff, coff, st);
+            upload(d_coff32, coff32, st);
+            k::dist_edit_pivots_f32(d_cx.as<uint8_t>(), d_coff.as<int64_t>(), K, d_cx.as<uint8_t>(),
+                                    d_coff32.as<int32_t>(), K, K, d_dk.as<float>(), K, 1, idx->lut.as<uint8_t>(),
+                                    idx->arows, st);
+        }
+        GTS_HIP(hipMemcpyAsync(dk.data(), d_dk.p, dk.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> rank(K, -1), by_rank(K);
+        {
+            int at = 0;
+            rank[0] = 0;
+            by_rank[0] = 0;
+            for (int r = 1; r < K; r++) {
+                int best = -1;
+                for (int c = 0; c < K; c++)
+                    if (rank[c] < 0 && (best < 0 || dk[(size_t)at * K + c] < dk[(size_t)at * K + best])) best = c;
+                rank[best] = r;
+                by_rank[r] = best;
+                at = best;
             }
         }
-        first = first * F + 1;
-        count *= F;
+        if (!l2) {
+            // centre strings in chain order (queries look up their nearest one)
+            std::vector<uint8_t> rc;
+            std::vector<int32_t> ro{0};
+            for (int r = 0; r < K; r++) {
+                const int c = by_rank[r];
+                rc.insert(rc.end(), objs.chars.begin() + objs.offsets[cent[c]],
+                          objs.chars.begin() + objs.offsets[cent[c] + 1]);
+                ro.push_back((int32_t)rc.size());
+            }
+            if (rc.empty()) rc.push_back(0);
+            upload(d.cchars, rc, st);
+            upload(d.coff, ro, st);
+            d.n_centres = K;
+        }
+        std::iota(perm.begin(), perm.end(), 0);
+        std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+            const int32_t rx = rank[nearc[x]], ry = rank[nearc[y]];
+            if (rx != ry) return rx < ry;
+            if (cmind[x] != cmind[y]) return cmind[x] < cmind[y];
+            return objs.ids[x] < objs.ids[y];
+        });
+        // leaf cuts
+        std::vector<int64_t> bnd;   // positions where a new cell starts
+        for (int64_t p = 1; p < n; p++)
+            if (nearc[perm[p]] != nearc[perm[p - 1]]) bnd.push_back(p);
+        const int64_t L = t.n_leaves;
+        std::vector<int64_t> cut(L + 1, 0);
+        cut[L] = n;
+        for (int64_t i = 1; i < L; i++) {
+            const int64_t ideal = (int64_t)((long double)i * n / L);
+            int64_t c = std::max(ideal, cut[i - 1]);
+            auto it = std::lower_bound(bnd.begin(), bnd.end(), ideal);
+            int64_t best = -1;
+            if (it != bnd.end()) best = *it;
+            if (it != bnd.begin() && (best < 0 || ideal - *(it - 1) < best - ideal)) best = *(it - 1);
+            if (best >= 0 && 2 * std::llabs(best - ideal) * L <= n && best > cut[i - 1]) c = best;
+            cut[i] = std::min(c, n);
+        }
+        for (int64_t j2 = 0; j2 < L; j2++) {
+            nfirst[t.leaf0 + j2] = cut[j2];
+            ncnt[t.leaf0 + j2] = cut[j2 + 1] - cut[j2];
+        }
+        for (int64_t v = t.leaf0 - 1; v >= 0; v--) {
+            nfirst[v] = nfirst[v * F + 1];
+            ncnt[v] = 0;
+            for (int c = 0; c < F; c++) ncnt[v] += ncnt[v * F + 1 + c];
+        }
     }
 
+    clock.mark("partition");
     // ---- node boxes over every pivot --------------------------------------
     std::vector<float> lo((size_t)t.n_nodes * mpad, INFINITY), hi((size_t)t.n_nodes * mpad, -INFINITY);
     for (int64_t j = 0; j < t.n_leaves; j++) {
@@ -244,6 +372,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
     upload(t.leaf_first, lf, st);
     upload(t.leaf_cnt, lc, st);
 
+    clock.mark("boxes");
     // ---- objects, pivot table and ids in leaf order ------------------------
     HostObjects &h = idx->host;
     h.metric = objs.metric;
@@ -383,8 +512,16 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         upload(d.pchars, pc, st);
         upload(d.poff, po, st);
         d.npad = n;
+        // leaf pivots: the first object of each leaf; R_L from the GPU
+        d.lpad = t.n_leaves;
+        d.leafR.alloc((size_t)t.n_leaves * sizeof(float));
+        k::EditView ev{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), n, idx->lut.as<uint8_t>(), idx->arows};
+        k::leaf_radius_edit(ev, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
+                            d.leafR.as<float>(), st);
+        GTS_HIP(hipStreamSynchronize(st));
     }
 
+    clock.mark("layouts + leaf pivots");
     // ---- tombstones and id maps --------------------------------------------
     const int64_t words = (std::max(d.npad, n) + 31) / 32 + 1;
     d.tomb.alloc((size_t)words * sizeof(uint32_t));
@@ -396,6 +533,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
     idx->pos_of_id.assign(std::max<int64_t>((int64_t)max_id + 1, idx->next_id), -1);
     for (int64_t p = 0; p < n; p++) idx->pos_of_id[h.ids[p]] = p;
     GTS_HIP(hipStreamSynchronize(st));
+    clock.mark("tombstones + maps");
 }
 
 // ---------------------------------------------------------------------------
@@ -448,6 +586,7 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
         if (out_ids) out_ids[i] = nid[i];
     }
     const int64_t s0 = c.count;
+    if (d.metric != GTS_L2_F32) alphabet_add(idx, objs.chars);
     if (d.metric == GTS_L2_F32) {
         GTS_HIP(hipMemcpy2DAsync(c.X32.as<float>() + (size_t)s0 * d.dp, d.dp * sizeof(float), objs.vecs.data(),
                                  d.dim * sizeof(float), d.dim * sizeof(float), n, hipMemcpyHostToDevice, st));

@@ -31,8 +31,10 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_NEARC,
+    W_COUNT
 };
+static_assert(W_COUNT <= kWorkspaceSlots, "workspace slots of gts_index too few");
 
 struct ResultPriv {
     void *offsets = nullptr, *ids = nullptr, *dist = nullptr;
@@ -109,6 +111,14 @@ void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max
     out->ids.resize(n);
 }
 
+namespace k {
+void check_launch(const char *name)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(GTS_EDEVICE, std::string("kernel launch failed in ") + name + ": " + hipGetErrorString(e));
+}
+}  // namespace k
+
 // ---------------------------------------------------------------------------
 // One query group [q0, q0 + ng): candidates -> verified, sorted answers.
 // Returns false when the candidates overflow `cap` (nothing produced).
@@ -119,6 +129,7 @@ struct Batch {
     int64_t nq = 0;
     bool any_knn = false;
     int mode = GTS_MODE_BATCHED;
+    int max_qlen = 0;          // longest query string (EDIT)
 };
 
 void rec(gts_index *idx, int i)
@@ -138,7 +149,7 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
                    t.leaf_cnt.as<int32_t>(), t.n_nodes, t.n_leaves, t.leaf0, t.fanout, t.levels, mpad};
     k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                  d.dim, d.dp, d.ksteps};
-    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
+    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n, idx->lut.as<uint8_t>(), idx->arows};
     const int ntiles = (int)((ng + kQTile - 1) / kQTile);
 
     float *QP = idx->ws[W_QP].as<float>() + q0 * mpad;
@@ -156,7 +167,7 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     } else {
         qe.chars = idx->ws[W_QCHARS].as<uint8_t>();
         qe.off = idx->ws[W_QOFF].as<int64_t>() + q0;
-        qe.peq = idx->ws[W_PEQ].as<uint64_t>() + q0 * 1024;
+        qe.peq = idx->ws[W_PEQ].as<uint64_t>() + q0 * idx->arows * 4;
     }
     uint32_t *small = wsp<uint32_t>(idx, W_SMALL, kSmallWords);
     unsigned long long *counters = idx->ws[W_COUNTERS].as<unsigned long long>();
@@ -195,6 +206,9 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
         const int64_t item_cap = t.n_leaves * ntiles;
         if (!l2) items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
         k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
+        if (!l2 && d.lpad > 0)
+            k::edit_leaf_ball(oe, qe, idx->ws[W_QLEN].as<int32_t>() + q0, t.leaf_first.as<int32_t>(),
+                              d.leafR.as<float>(), t.n_leaves, T, ng, ntiles, b.max_qlen, mask, st);
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
                          d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, st);
@@ -206,7 +220,8 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
             GTS_HIP(hipGetDevice(&dev));
             GTS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             const int chunk = 64;
-            k::mfma_sweep(ov, sv, qv, T, ng, ntiles, mask, tomb, chunk, small + 2, cands, small + 0, cap, counters,
+            const float *tqe = idx->ws[W_TQE].as<float>() + q0;
+            k::mfma_sweep(ov, sv, qv, tqe, ng, ntiles, mask, tomb, chunk, small + 2, cands, small + 0, cap, counters,
                           cus * 2, st);
         } else {
             int32_t *qlen = idx->ws[W_QLEN].as<int32_t>() + q0;
@@ -224,7 +239,7 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
             k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
                              cut, cands, small + 0, cap, st);
         } else {
-            k::cache_scan_edit(qe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
+            k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
                                c.live.as<uint32_t>(), c.count, base, cands, small + 0, cap, st);
         }
     }
@@ -406,6 +421,7 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             const int64_t len = hoff[q + 1] - hoff[q];
             GTS_CHECK(len >= 0 && len <= d.max_strlen, GTS_EINVAL, "query string length out of range");
             qlen[q] = (int32_t)len;
+            b.max_qlen = std::max(b.max_qlen, (int)len);
         }
         uint8_t *qc = wsp<uint8_t>(idx, W_QCHARS, std::max<int64_t>(hoff[nq], 1));
         if (hoff[nq]) {
@@ -416,21 +432,22 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         GTS_HIP(hipMemcpyAsync(qo, hoff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
         int32_t *ql = wsp<int32_t>(idx, W_QLEN, nqpad);
         GTS_HIP(hipMemcpyAsync(ql, qlen.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        uint64_t *peq = wsp<uint64_t>(idx, W_PEQ, (size_t)nqpad * 1024);
-        k::build_peq(qc, qo, nq, peq, st);
+        uint64_t *peq = wsp<uint64_t>(idx, W_PEQ, (size_t)nqpad * idx->arows * 4);
+        k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, peq, st);
         k::dist_edit_pivots_f32(qc, qo, nq, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, mpad,
-                                idx->ws[W_QP].as<float>(), 1, mpad, st);
+                                idx->ws[W_QP].as<float>(), 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
         qe = k::QueryEdit{qc, qo, peq};
         GTS_HIP(hipStreamSynchronize(st));
     }
     // ---- home leaves and query order ----------------------------------------------
-    // Queries are grouped into tiles by their home leaf (nearest leaf pivot for
-    // L2, greedy box descent for edit distance) so that a tile's queries share
-    // surviving leaves; answers are returned in the caller's order.
+    // Queries are grouped into tiles by their home (nearest leaf pivot for L2,
+    // nearest cluster centre in chain order for edit distance) so that a
+    // tile's queries share surviving leaves; answers are returned in the
+    // caller's order.
     k::TreeView tv{d.tree.box_aos.as<float>(), d.tree.box_lo.as<float>(), d.tree.box_hi.as<float>(),
                    d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.tree.n_nodes,
                    d.tree.n_leaves, d.tree.leaf0, d.tree.fanout, d.tree.levels, mpad};
-    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n};
+    k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n, idx->lut.as<uint8_t>(), idx->arows};
     int32_t *near = nullptr;
     std::vector<int32_t> perm;   // position i of the batch holds caller query perm[i]
     bool permuted = false;
@@ -443,10 +460,16 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             GTS_HIP(hipMemcpyAsync(hn.data(), near, hn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
             for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
-        } else if (!l2) {
-            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), nullptr, nq, d.tomb.as<uint32_t>(), 0, base, home, st);
-            GTS_HIP(hipMemcpyAsync(hh.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        } else if (!l2 && d.n_centres > 0) {
+            uint64_t *best = wsp<uint64_t>(idx, W_NEARC, nq);
+            k::fill_u32(reinterpret_cast<uint32_t *>(best), 2 * nq, 0xffffffffu, st);
+            k::near_centre_edit(d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.n_centres, qe,
+                                idx->ws[W_QLEN].as<int32_t>(), idx->arows, idx->lut.as<uint8_t>(), nq, b.max_qlen,
+                                reinterpret_cast<unsigned long long *>(best), st);
+            std::vector<uint64_t> hb(nq);
+            GTS_HIP(hipMemcpyAsync(hb.data(), best, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < nq; q++) hh[q] = (int32_t)(uint32_t)hb[q];
         }
         perm.resize(nq);
         for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
@@ -505,7 +528,7 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             GTS_HIP(hipMemcpyAsync(qo, no, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
             GTS_HIP(hipMemcpyAsync(idx->ws[W_QLEN].as<int32_t>(), nlen.data(), nq * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
-            k::build_peq(qc, qo, nq, const_cast<uint64_t *>(qe.peq), st);
+            k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, const_cast<uint64_t *>(qe.peq), st);
             GTS_HIP(hipStreamSynchronize(st));
         }
     }
@@ -532,6 +555,7 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     if (nq > 0)
         k::thresholds(base, idx->ws[W_QP].as<float>(), kq, nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
                       idx->ws[W_T].as<float>(), idx->ws[W_THR].as<float>(), wsp<float>(idx, W_CUT, nqpad), st);
+    if (l2) k::sum_pad(idx->ws[W_T].as<float>(), qv.qe, nq, nqpad, wsp<float>(idx, W_TQE, nqpad), st);
     rec(idx, 2);
     if (idx->timing && nq > 0) {
         GTS_HIP(hipStreamSynchronize(st));

@@ -1,0 +1,221 @@
+// Build-time clustering that orders the objects before they are cut into
+// leaves, and the query-side lookup of the nearest cluster centre.
+//
+// The centres come from farthest-first traversal (the selection rule the
+// method uses for pivots, Sec. 4.1, run to many more centres): centre j + 1 is
+// the object farthest from centres 0..j.  One launch per centre; each launch
+// reads the previous argmax from device memory and leaves its own argmax
+// there, so the K launches run back to back without host round trips.
+//
+// Key of an object: (bits of its distance to the nearest centre so far) << 32
+// | (0xffffffff - index); the largest key is the farthest object, ties going
+// to the smallest index.  Distances are >= 0, so their float bits order as
+// unsigned integers.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace gts {
+namespace k {
+
+namespace {
+
+__device__ __forceinline__ uint64_t far_key(float d, int64_t i)
+{
+    return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
+}
+
+__device__ __forceinline__ int64_t key_index(uint64_t k) { return (int64_t)(0xffffffffu - (uint32_t)k); }
+
+// block-wide max of a 64-bit key, then one atomic per block
+__device__ __forceinline__ void block_max_atomic(uint64_t v, uint64_t *dst)
+{
+    __shared__ uint64_t s_w[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_w[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) m = s_w[w] > m ? s_w[w] : m;
+        atomicMax(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)m);
+    }
+}
+
+}  // namespace
+
+// Step j (L2): squared distance of every object to centre c_j = the argmax
+// left in keys[j]; nearest-centre bookkeeping; argmax into keys[j + 1].
+__global__ __launch_bounds__(256) void k_fft_step_l2(const float *__restrict__ X, int64_t n, int dp, int j,
+                                                     uint64_t *__restrict__ keys, int32_t *__restrict__ centers,
+                                                     float *__restrict__ mind, int32_t *__restrict__ near)
+{
+    const int64_t c = key_index(keys[j]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) centers[j] = (int32_t)c;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t key = 0;
+    if (o < n) {
+        const float4 *x = reinterpret_cast<const float4 *>(X + (size_t)o * dp);
+        const float4 *y = reinterpret_cast<const float4 *>(X + (size_t)c * dp);
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int i = 0; i < dp / 4; i++) {
+            const float4 u = x[i], v = y[i];
+            const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+            a0 = fmaf(d0, d0, a0);
+            a1 = fmaf(d1, d1, a1);
+            a2 = fmaf(d2, d2, a2);
+            a3 = fmaf(d3, d3, a3);
+        }
+        const float d = (a0 + a1) + (a2 + a3);
+        float m = mind[o];
+        if (j == 0 || d < m) {
+            m = d;
+            mind[o] = d;
+            near[o] = j;
+        }
+        key = far_key(m, o);
+    }
+    block_max_atomic(key, keys + j + 1);
+}
+
+// Step j (edit distance): the centre string is the Myers pattern (its match
+// table in LDS); an object's distance only matters when it is below its
+// current nearest-centre distance, which is the early-exit cutoff.
+__global__ __launch_bounds__(256) void k_fft_step_edit(const uint8_t *__restrict__ chars,
+                                                       const int64_t *__restrict__ off, int64_t n,
+                                                       const uint8_t *__restrict__ lut_g, int arows, int j,
+                                                       uint64_t *__restrict__ keys, int32_t *__restrict__ centers,
+                                                       float *__restrict__ mind, int32_t *__restrict__ near)
+{
+    __shared__ uint64_t s_peq[257 * 4];
+    __shared__ uint8_t s_lut[256];
+    const int64_t c = key_index(keys[j]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) centers[j] = (int32_t)c;
+    for (int i = threadIdx.x; i < arows * 4; i += blockDim.x) s_peq[i] = 0ull;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = lut_g[i];
+    __syncthreads();
+    const int64_t ca = off[c];
+    const int plen = (int)(off[c + 1] - ca);
+    dev::peq_fill(s_peq, chars + ca, plen, s_lut, arows);
+    __syncthreads();
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t key = 0;
+    if (o < n) {
+        float m = mind[o];
+        const int cutoff = j == 0 ? (1 << 30) : (int)m - 1;
+        if (cutoff >= 0) {
+            const int64_t a = off[o];
+            const int d = dev::myers_any(s_peq, plen, chars + a, (int)(off[o + 1] - a), cutoff, s_lut);
+            if (d <= cutoff) {
+                m = (float)d;
+                mind[o] = m;
+                near[o] = j;
+            }
+        }
+        key = far_key(m, o);
+    }
+    block_max_atomic(key, keys + j + 1);
+}
+
+void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, int32_t *centers, float *mind,
+                    int32_t *near, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    for (int j = 0; j < K; j++)
+        hipLaunchKernelGGL(k_fft_step_l2, dim3(grid), dim3(256), 0, st, X, n, dp, j, keys, centers, mind, near);
+    check_launch(__func__);
+}
+
+void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const uint8_t *lut, int arows, int K,
+                      uint64_t *keys, int32_t *centers, float *mind, int32_t *near, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    for (int j = 0; j < K; j++)
+        hipLaunchKernelGGL(k_fft_step_edit, dim3(grid), dim3(256), 0, st, chars, off, n, lut, arows, j, keys,
+                           centers, mind, near);
+    check_launch(__func__);
+}
+
+// ---------------------------------------------------------------------------
+// Nearest centre of each query string (edit distance): workgroup = (64-query
+// tile, chunk of kCentreChunk centres), lane = query (the Myers pattern, its
+// table in global memory), the centre string the common text staged as codes
+// in LDS.  The running best of the lane is the early-exit cutoff; the result
+// is merged per query with a 64-bit atomic min of (distance << 32 | centre).
+// ---------------------------------------------------------------------------
+constexpr int kCentreChunk = 128;
+
+template <int W>
+__global__ __launch_bounds__(256) void k_near_centre_edit(const uint8_t *__restrict__ cchars,
+                                                          const int32_t *__restrict__ coff, int K, QueryEdit qv,
+                                                          const int32_t *__restrict__ qlen, int rows,
+                                                          const uint8_t *__restrict__ lut_g, int64_t nq, int ntiles,
+                                                          unsigned long long *__restrict__ best)
+{
+    __shared__ uint8_t s_code[4][256];
+    __shared__ uint8_t s_lut[256];
+    const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
+    const int tile = (int)(blockIdx.x % ntiles);
+    const int chunk = (int)(blockIdx.x / ntiles);
+    const int64_t q = (int64_t)tile * 64 + lane;
+    const bool qok = q < nq;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = lut_g[i];
+    __syncthreads();
+    const int plen = qok ? qlen[q] : 0;
+    const uint64_t *tab = qv.peq + (size_t)(qok ? q : 0) * rows * 4;
+    int bd = 1 << 30, bc = 0;
+    for (int ci = wave; ci < kCentreChunk; ci += 4) {
+        const int c = chunk * kCentreChunk + ci;
+        if (c >= K) break;
+        const int s0 = coff[c];
+        const int tl = coff[c + 1] - s0;
+        for (int b = lane; b < tl; b += 64) s_code[wave][b] = s_lut[cchars[s0 + b]];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (qok && abs(plen - tl) < bd) {
+            struct G {
+                const uint64_t *t;
+                __device__ __forceinline__ uint64_t operator[](int i) const { return t[i]; }
+            };
+            struct I {
+                __device__ __forceinline__ int operator[](int x) const { return x; }
+            };
+            const int d = dev::myers_distance<W>(G{tab}, plen, s_code[wave], tl, bd - 1, I{});
+            if (d < bd) {
+                bd = d;
+                bc = c;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (qok && bd < (1 << 30))
+        atomicMin(best + q, ((unsigned long long)(uint32_t)bd << 32) | (unsigned long long)(uint32_t)bc);
+}
+
+void near_centre_edit(const uint8_t *cchars, const int32_t *coff, int K, const QueryEdit &qv, const int32_t *qlen,
+                      int rows, const uint8_t *lut, int64_t nq, int max_qlen, unsigned long long *best,
+                      hipStream_t st)
+{
+    if (nq == 0 || K == 0) return;
+    const int ntiles = (int)((nq + 63) / 64);
+    const int chunks = (K + kCentreChunk - 1) / kCentreChunk;
+    const unsigned grid = (unsigned)((int64_t)chunks * ntiles);
+    const int W = std::max(1, (max_qlen + 63) / 64);
+#define NC(WW)                                                                                                  \
+    hipLaunchKernelGGL(k_near_centre_edit<WW>, dim3(grid), dim3(256), 0, st, cchars, coff, K, qv, qlen, rows, lut, \
+                       nq, ntiles, best)
+    switch (W) {
+    case 1: NC(1); break;
+    case 2: NC(2); break;
+    case 3: NC(3); break;
+    default: NC(4); break;
+    }
+#undef NC
+    check_launch(__func__);
+}
+
+}  // namespace k
+}  // namespace gts

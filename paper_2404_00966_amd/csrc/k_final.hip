@@ -21,6 +21,7 @@ __global__ void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restr
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st)
 {
     hipLaunchKernelGGL(k_group_hist, dim3(2048), dim3(256), 0, st, c, count, cap, qcount);
+    check_launch(__func__);
 }
 
 // Exclusive scan of n counts into out[0..n], one workgroup of 1024 threads.
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *__restrict__ 
 void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, in, n, out);
+    check_launch(__func__);
 }
 
 __global__ void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
@@ -72,6 +74,7 @@ void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int6
                    Cand *grouped, hipStream_t st)
 {
     hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped);
+    check_launch(__func__);
 }
 
 // Sort the keys of one query (in LDS or, for a large segment, in its
@@ -206,6 +209,7 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
     hipLaunchKernelGGL(k_verify_l2, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c);
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,7 +220,8 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
 __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, QueryEdit qv)
 {
     __shared__ uint64_t s_keys[kSortCap];
-    __shared__ uint64_t s_peq[256 * 4];
+    __shared__ uint64_t s_peq[257 * 4];
+    __shared__ uint8_t s_lut[256];
     __shared__ int s_n;
     const int64_t q = blockIdx.x;
     if (q >= a.nq) return;
@@ -229,8 +234,9 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
     uint64_t *keys = big ? a.scratch + boff : s_keys;
     const int64_t cap = big ? dev::next_pow2(ns) : kSortCap;
     const Cand *g = a.grouped + seg0;
-    const uint64_t *pq = qv.peq + (size_t)q * 256 * 4;
-    for (int i = threadIdx.x; i < 256 * 4; i += blockDim.x) s_peq[i] = pq[i];
+    const uint64_t *pq = qv.peq + (size_t)q * o.rows * 4;
+    for (int i = threadIdx.x; i < o.rows * 4; i += blockDim.x) s_peq[i] = pq[i];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     const int plen = (int)(qv.off[q + 1] - qv.off[q]);
@@ -246,7 +252,7 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
             const int32_t s0 = o.soff[c.pos];
             const int tl = o.soff[c.pos + 1] - s0;
             verified++;
-            const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut);
+            const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut, s_lut);
             if (d <= cut) {
                 keep = true;
                 key = ((uint64_t)(uint32_t)d << 32) | a.ids[c.pos];
@@ -267,6 +273,7 @@ void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hi
 {
     if (a.nq == 0) return;
     hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,6 +303,7 @@ void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *ou
     if (nq == 0) return;
     hipLaunchKernelGGL(k_csr_write, dim3((unsigned)nq), dim3(64), 0, st, out_keys, qoff, out_count, res_off, nq,
                        is_edit, ids, dist_f, dist_i);
+    check_launch(__func__);
 }
 
 }  // namespace k

@@ -130,6 +130,7 @@ void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps
     default: LN(4); break;
     }
 #undef LN
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,6 +232,7 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
     default: LB(4); break;
     }
 #undef LB
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -299,6 +301,7 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
     if (nq == 0) return;
     hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(64), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
                        kq, nq, tomb, target, tq);
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -318,6 +321,7 @@ void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, fl
 {
     if (rows == 0) return;
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)rows), dim3(64), 0, st, src, perm, rows, dp, dst);
+    check_launch(__func__);
 }
 
 __global__ void k_gather_i32(const int32_t *__restrict__ src, const int32_t *__restrict__ perm, int64_t rows, int width,
@@ -334,6 +338,7 @@ void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width
     if (rows == 0) return;
     const int64_t n = rows * width;
     hipLaunchKernelGGL(k_gather_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, perm, rows, width, dst);
+    check_launch(__func__);
 }
 
 // Strings: dst string i <- src string perm[i] (dst offsets precomputed).
@@ -352,6 +357,7 @@ void gather_strings(const uint8_t *src, const int64_t *src_off, const int32_t *p
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_gather_strings, dim3((unsigned)n), dim3(64), 0, st, src, src_off, perm, n, dst_off, dst);
+    check_launch(__func__);
 }
 
 // Answers computed in permuted query order -> original order:
@@ -377,6 +383,7 @@ void unpermute(const int64_t *src_off, const int64_t *dst_off, const int32_t *pe
     if (nq == 0) return;
     hipLaunchKernelGGL(k_unpermute, dim3((unsigned)nq), dim3(64), 0, st, src_off, dst_off, perm, nq, src_ids, src_dist,
                        dst_ids, dst_dist);
+    check_launch(__func__);
 }
 
 }  // namespace k

@@ -229,6 +229,7 @@ void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const
     else if (t.mpad == 16) PL(16);
     else PL(32);
 #undef PL
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,14 +237,14 @@ void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const
 // pivots and objects are texts.
 // ---------------------------------------------------------------------------
 __device__ void plain_flush_edit(const EditView &o, const PlainArgs &a, int64_t q, const uint64_t *s_peq, int plen,
-                                 int cut, const int32_t *s_cand, int nc, long long *verified)
+                                 int cut, const int32_t *s_cand, int nc, long long *verified, const uint8_t *s_lut)
 {
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int32_t p = s_cand[c];
         const int32_t s0 = o.soff[p];
         const int tl = o.soff[p + 1] - s0;
         (*verified)++;
-        const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut);
+        const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut, s_lut);
         if (d <= cut) emit_verified(a, q, (uint32_t)d, a.ids[p]);
     }
 }
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_edit(TreeView t, EditView
                                                             const uint8_t *__restrict__ PTe, QueryEdit qv,
                                                             PlainArgs a)
 {
-    __shared__ uint64_t s_peq[256 * 4];
+    __shared__ uint64_t s_peq[257 * 4];
+    __shared__ uint8_t s_lut[256];
     __shared__ float s_qp[MP];
     __shared__ int32_t s_cand[kPlainCand];
     __shared__ int s_nc, s_nf;
@@ -264,18 +266,17 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_edit(TreeView t, EditView
     for (int64_t q = blockIdx.x; q < a.nq; q += gridDim.x) {
         const int64_t qa = qv.off[q];
         const int plen = (int)(qv.off[q + 1] - qa);
-        for (int i = threadIdx.x; i < 256 * 4; i += blockDim.x) s_peq[i] = 0ull;
+        for (int i = threadIdx.x; i < o.rows * 4; i += blockDim.x) s_peq[i] = 0ull;
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
         __syncthreads();
-        for (int b = threadIdx.x; b < plen; b += blockDim.x)
-            atomicOr(reinterpret_cast<unsigned long long *>(&s_peq[qv.chars[qa + b] * 4 + (b >> 6)]),
-                     (unsigned long long)(1ull << (b & 63)));
+        dev::peq_fill(s_peq, qv.chars + qa, plen, s_lut, o.rows);
         if (threadIdx.x == 0) s_nc = 0;
         __syncthreads();
         if (threadIdx.x < MP) {
             int d = 0;
             if ((int)threadIdx.x < m) {
                 const int32_t s0 = poff[threadIdx.x];
-                d = dev::myers_any(s_peq, plen, pchars + s0, poff[threadIdx.x + 1] - s0, 1 << 30);
+                d = dev::myers_any(s_peq, plen, pchars + s0, poff[threadIdx.x + 1] - s0, 1 << 30, s_lut);
             }
             s_qp[threadIdx.x] = (float)d;
         }
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_edit(TreeView t, EditView
                 __syncthreads();
                 const int nc = s_nc;
                 if (nc + kPlainBlock > kPlainCand) {
-                    plain_flush_edit(o, a, q, s_peq, plen, cut, s_cand, nc, &verified);
+                    plain_flush_edit(o, a, q, s_peq, plen, cut, s_cand, nc, &verified, s_lut);
                     __syncthreads();
                     if (threadIdx.x == 0) s_nc = 0;
                     __syncthreads();
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_edit(TreeView t, EditView
             }
         }
         __syncthreads();
-        plain_flush_edit(o, a, q, s_peq, plen, cut, s_cand, s_nc, &verified);
+        plain_flush_edit(o, a, q, s_peq, plen, cut, s_cand, s_nc, &verified, s_lut);
         __syncthreads();
     }
     if (verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
@@ -330,6 +331,7 @@ void plain_edit(const TreeView &t, const EditView &o, const uint8_t *pchars, con
     else if (t.mpad == 16) PE(16);
     else PE(32);
 #undef PE
+    check_launch(__func__);
 }
 
 }  // namespace k

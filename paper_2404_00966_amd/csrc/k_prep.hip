@@ -55,6 +55,7 @@ void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, in
     int blocks = (int)((rows_pad + 255) / 256);
     hipLaunchKernelGGL(k_rows_bf16, dim3(blocks), dim3(256), 0, st, X, rows_valid, rows_pad, dim, stride,
                        ksteps, frag, norm2, err, pad_norm2);
+    check_launch(__func__);
 }
 
 // out[i * s_piv + r * s_row] = || X[r] - P[i] ||  (float32, direct difference,
@@ -90,27 +91,28 @@ void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpa
     if (rows == 0) return;
     dim3 grid((unsigned)((rows + 255) / 256), (unsigned)mpad);
     hipLaunchKernelGGL(k_dist_l2_pivots, grid, dim3(256), 0, st, X, rows, P, m, mpad, stride, out, s_piv, s_row);
+    check_launch(__func__);
 }
 
 // Edit distance of every string to pivot blockIdx.y: the pivot is the Myers
-// pattern (its 256 x 4 match table in LDS), each thread scans one string as
-// the text.  out[i * s_piv + r * s_row] = distance (float or int as given).
-template <class OutT>
+// pattern (its match table in LDS), each thread scans one string as the text.
+// out[i * s_piv + r * s_row] = distance.
 __global__ void k_dist_edit_pivots(const uint8_t *__restrict__ chars, const int64_t *__restrict__ off,
                                    int64_t rows, const uint8_t *__restrict__ pchars, const int32_t *__restrict__ poff,
-                                   int m, OutT *__restrict__ out, int64_t s_piv, int64_t s_row)
+                                   int m, float *__restrict__ out, int64_t s_piv, int64_t s_row,
+                                   const uint8_t *__restrict__ lut_g, int arows)
 {
-    __shared__ uint64_t peq[256 * 4];
+    __shared__ uint64_t peq[257 * 4];
+    __shared__ uint8_t lut[256];
     const int i = blockIdx.y;
-    for (int t = threadIdx.x; t < 256 * 4; t += blockDim.x) peq[t] = 0ull;
+    for (int t = threadIdx.x; t < arows * 4; t += blockDim.x) peq[t] = 0ull;
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) lut[t] = lut_g[t];
     __syncthreads();
     int plen = 0;
     if (i < m) {
         const int a = poff[i];
         plen = poff[i + 1] - a;
-        for (int t = threadIdx.x; t < plen; t += blockDim.x)
-            atomicOr(reinterpret_cast<unsigned long long *>(&peq[pchars[a + t] * 4 + (t >> 6)]),
-                     (unsigned long long)(1ull << (t & 63)));
+        dev::peq_fill(peq, pchars + a, plen, lut, arows);
     }
     __syncthreads();
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,51 +121,43 @@ __global__ void k_dist_edit_pivots(const uint8_t *__restrict__ chars, const int6
     if (i < m) {
         const int64_t a = off[r];
         const int tlen = (int)(off[r + 1] - a);
-        d = dev::myers_any(peq, plen, chars + a, tlen, 1 << 30);
+        d = dev::myers_any(peq, plen, chars + a, tlen, 1 << 30, lut);
     }
-    out[(size_t)i * s_piv + (size_t)r * s_row] = (OutT)d;
+    out[(size_t)i * s_piv + (size_t)r * s_row] = (float)d;
 }
 
 void dist_edit_pivots_f32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
                           const int32_t *poff, int m, int mpad, float *out, int64_t s_piv, int64_t s_row,
-                          hipStream_t st)
+                          const uint8_t *lut, int arows, hipStream_t st)
 {
     if (rows == 0) return;
     dim3 grid((unsigned)((rows + 255) / 256), (unsigned)mpad);
-    hipLaunchKernelGGL(k_dist_edit_pivots<float>, grid, dim3(256), 0, st, chars, off, rows, pchars, poff, m, out,
-                       s_piv, s_row);
+    hipLaunchKernelGGL(k_dist_edit_pivots, grid, dim3(256), 0, st, chars, off, rows, pchars, poff, m, out, s_piv,
+                       s_row, lut, arows);
+    check_launch(__func__);
 }
 
-void dist_edit_pivots_i32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
-                          const int32_t *poff, int m, int32_t *out, int64_t s_piv, int64_t s_row, hipStream_t st)
-{
-    if (rows == 0) return;
-    dim3 grid((unsigned)((rows + 255) / 256), (unsigned)m);
-    hipLaunchKernelGGL(k_dist_edit_pivots<int32_t>, grid, dim3(256), 0, st, chars, off, rows, pchars, poff, m,
-                       out, s_piv, s_row);
-}
-
-// Match-bit table of each query string: peq[q][c][w] bit b set iff
-// query[64w + b] == c.  One workgroup per query.
+// Match-bit table of each query string over the index alphabet:
+// peq[q][c][w] bit b set iff query[64w + b] has code c.  One workgroup per
+// query.
 __global__ void k_build_peq(const uint8_t *__restrict__ chars, const int64_t *__restrict__ off, int64_t nq,
-                            uint64_t *__restrict__ peq)
+                            const uint8_t *__restrict__ lut, int arows, uint64_t *__restrict__ peq)
 {
     int64_t q = blockIdx.x;
     if (q >= nq) return;
-    uint64_t *t = peq + (size_t)q * 256 * 4;
-    for (int c = threadIdx.x; c < 256 * 4; c += blockDim.x) t[c] = 0ull;
+    uint64_t *t = peq + (size_t)q * arows * 4;
+    for (int c = threadIdx.x; c < arows * 4; c += blockDim.x) t[c] = 0ull;
     __syncthreads();
     const int64_t a = off[q];
-    const int len = (int)(off[q + 1] - a);
-    for (int b = threadIdx.x; b < len; b += blockDim.x)
-        atomicOr(reinterpret_cast<unsigned long long *>(&t[chars[a + b] * 4 + (b >> 6)]),
-                 (unsigned long long)(1ull << (b & 63)));
+    dev::peq_fill(t, chars + a, (int)(off[q + 1] - a), lut, arows);
 }
 
-void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *peq, hipStream_t st)
+void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, const uint8_t *lut, int arows, uint64_t *peq,
+               hipStream_t st)
 {
     if (nq == 0) return;
-    hipLaunchKernelGGL(k_build_peq, dim3((unsigned)nq), dim3(256), 0, st, chars, off, nq, peq);
+    hipLaunchKernelGGL(k_build_peq, dim3((unsigned)nq), dim3(256), 0, st, chars, off, nq, lut, arows, peq);
+    check_launch(__func__);
 }
 
 // Per-query thresholds for node and object filtering:
@@ -200,6 +194,24 @@ void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t n
     if (nq == 0) return;
     hipLaunchKernelGGL(k_thresholds, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, base, QP, kq, nq, mpad,
                        is_edit, delta, pt_max, T, thr, cut);
+    check_launch(__func__);
+}
+
+// out[q] = a[q] + b[q] for q < n, -inf for n <= q < npad (padding rows of a
+// query tile never pass a threshold).
+__global__ void k_sum_pad(const float *__restrict__ a, const float *__restrict__ b, int64_t n, int64_t npad,
+                          float *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npad) return;
+    out[q] = q < n ? a[q] + b[q] : -INFINITY;
+}
+
+void sum_pad(const float *a, const float *b, int64_t n, int64_t npad, float *out, hipStream_t st)
+{
+    if (npad == 0) return;
+    hipLaunchKernelGGL(k_sum_pad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, st, a, b, n, npad, out);
+    check_launch(__func__);
 }
 
 // Fill an int32 / uint64 array (a small kernel, so no memset node is needed
@@ -216,6 +228,7 @@ void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st)
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    check_launch(__func__);
 }
 
 }  // namespace k

@@ -128,6 +128,7 @@ void node_filter(const TreeView &t, const float *QP, const float *thr, int64_t n
     else if (t.mpad == 16) NF_LAUNCH(16);
     else NF_LAUNCH(32);
 #undef NF_LAUNCH
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,7 +209,8 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
                     const int tl = oe.soff[p + 1] - s0;
                     const int64_t qa = qe.off[q];
                     const int plen = (int)(qe.off[q + 1] - qa);
-                    d = (float)dev::myers_any(qe.peq + (size_t)q * 256 * 4, plen, oe.chars + s0, tl, 1 << 30);
+                    d = (float)dev::myers_any(qe.peq + (size_t)q * oe.rows * 4, plen, oe.chars + s0, tl, 1 << 30,
+                                              oe.lut);
                 }
             }
         }
@@ -230,6 +232,7 @@ void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float
     else if (t.mpad == 16) BL(16);
     else BL(32);
 #undef BL
+    check_launch(__func__);
 }
 
 void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
@@ -244,6 +247,7 @@ void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const
     else if (t.mpad == 16) BE(16);
     else BE(32);
 #undef BE
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,10 +280,22 @@ __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v)
     return r;
 }
 
+// Global -> LDS copies without registers (gfx950 global_load_lds): lane l of
+// the wave writes its `bytes` at lds_wave_base + l * bytes.
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void lds_dma16(const void *src, void *lds_wave_base)
+{
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_wave_base, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const void *src, void *lds_wave_base)
+{
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_wave_base, 4, 0, 0);
+}
+
 template <int KS, int RT>
 __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     const uint4 *__restrict__ X16t, const float *__restrict__ xn, const uint4 *__restrict__ Q16t,
-    const float *__restrict__ qn, const float *__restrict__ qe, const float *__restrict__ T, int64_t nq,
+    const float *__restrict__ qn, const float *__restrict__ tqe, int64_t nq,
     int ntiles, const float *__restrict__ slab_emax, const float *__restrict__ slab_nmax,
     const int32_t *__restrict__ slab_leaf_lo, const int32_t *__restrict__ slab_leaf_hi,
     const uint64_t *__restrict__ leaf_mask, int64_t n, const uint32_t *__restrict__ tomb, int64_t n_items,
@@ -289,7 +305,15 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
 {
     constexpr int kRowsPerWave = 16 * RT;
     constexpr int kSlabRows = 4 * kRowsPerWave;
-    __shared__ int s_item;
+    constexpr int kTileFrag = 4 * KS * 64;           // uint4 fragments of one 64-query tile
+    constexpr int kPer = kTileFrag / 256;            // fragments staged per thread
+    // LDS: two staging buffers of one query tile (B fragments, T + e_q and
+    // ||q16||^2 per query), and the item's list of active tiles with masks
+    __shared__ uint4 s_b[2][kTileFrag];
+    __shared__ float s_t[2][64], s_qn[2][64];
+    __shared__ int32_t s_tile[64];
+    __shared__ uint64_t s_tmask[64];
+    __shared__ int s_item, s_ntile;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15;
@@ -297,16 +321,46 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     int64_t cur_slab = -1;
     uint4 A[RT][KS];
     float xr[RT][4];
-    long long pairs = 0;
+    long long units = 0;
+    // stage query tile t into buffer b: every wave copies kPer 1 KB runs of
+    // fragments; waves 0 and 1 copy the two 256-byte parameter rows
+    auto stage = [&](int t, int b) {
+        const uint4 *src = Q16t + (int64_t)t * kTileFrag;
+#pragma unroll
+        for (int j = 0; j < kPer; j++)
+            lds_dma16(src + 256 * j + threadIdx.x, &s_b[b][256 * j + 64 * wave]);
+        if (wave == 0) lds_dma4(tqe + (int64_t)t * 64 + lane, &s_t[b][0]);
+        if (wave == 1) lds_dma4(qn + (int64_t)t * 64 + lane, &s_qn[b][0]);
+    };
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(work, 1u);
+        if (threadIdx.x == 0) {
+            s_item = (int)atomicAdd(work, 1u);
+            s_ntile = 0;
+        }
         __syncthreads();
         const int64_t item = s_item;
-        __syncthreads();
         if (item >= n_items) break;
         const int64_t slab = item / nchunks;
         const int ch = (int)(item % nchunks);
         const int64_t row0 = slab * kSlabRows + wave * kRowsPerWave;
+        const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
+        const int t0 = ch * chunk;
+        const int t1 = min(ntiles, t0 + chunk);
+        // active tiles of this chunk (some query of the tile survives a leaf
+        // of the slab): thread i checks tile t0 + i, a wave ballot compacts them
+        if (threadIdx.x < 64) {
+            const int t = t0 + (int)threadIdx.x;
+            uint64_t mask = 0;
+            if (t < t1)
+                for (int l = l_lo; l <= l_hi; l++) mask |= leaf_mask[(size_t)l * ntiles + t];
+            const uint64_t b = dev::ballot(mask != 0);
+            if (mask) {
+                const int slot = dev::lanes_below(b);
+                s_tile[slot] = t;
+                s_tmask[slot] = mask;
+            }
+            if (threadIdx.x == 0) s_ntile = __popcll(b);
+        }
         if (slab != cur_slab) {
             cur_slab = slab;
             const int64_t g0 = row0 >> 4;
@@ -319,32 +373,36 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
 #pragma unroll
                 for (int e = 0; e < 4; e++) xr[r][e] = xn[row0 + 16 * r + 4 * rgrp + e];
         }
+        __syncthreads();
+        const int ntl = s_ntile;
+        if (ntl == 0) continue;
         const float emax = slab_emax[slab];
         const float nmax = slab_nmax[slab];
-        const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
-        const int t0 = ch * chunk;
-        const int t1 = min(ntiles, t0 + chunk);
-        for (int t = t0; t < t1; t++) {
-            uint64_t mask = 0;
-            for (int l = l_lo; l <= l_hi; l++) mask |= leaf_mask[(size_t)l * ntiles + t];
-            if (!mask) continue;
+        stage(s_tile[0], 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int it = 0; it < ntl; it++) {
+            const int buf = it & 1;
+            const int t = s_tile[it];
+            const uint64_t mask = s_tmask[it];
+            if (it + 1 < ntl) stage(s_tile[it + 1], buf ^ 1);   // lands while this tile computes
 #pragma unroll 1
             for (int c = 0; c < 4; c++) {
                 const uint32_t cm = (uint32_t)(mask >> (16 * c)) & 0xffffu;
                 if (!cm) continue;
-                pairs++;
+                units++;
                 const int64_t q = (int64_t)t * 64 + 16 * c + col;
-                float th = -INFINITY, qnn = 0.f;
-                if (q < nq && ((cm >> col) & 1u)) {
-                    qnn = qn[q];
-                    const float tq = T[q] + qe[q] + emax;
+                float th = -INFINITY;
+                const float qnn = s_qn[buf][16 * c + col];
+                if (((cm >> col) & 1u) && q < nq) {
+                    const float tq = s_t[buf][16 * c + col] + emax;
                     const float T2 = tq * tq;
                     const float eps = eps_a * (qnn + nmax * nmax) + eps_b * sqrtf(qnn) * nmax + eps_c * T2;
                     th = T2 + eps - qnn;
                 }
                 uint4 B[KS];
 #pragma unroll
-                for (int s = 0; s < KS; s++) B[s] = Q16t[(((int64_t)t * 4 + c) * KS + s) * 64 + lane];
+                for (int s = 0; s < KS; s++) B[s] = s_b[buf][(c * KS + s) * 64 + lane];
                 floatx4_t acc[RT];
 #pragma unroll
                 for (int r = 0; r < RT; r++) acc[r] = floatx4_t{0.f, 0.f, 0.f, 0.f};
@@ -398,12 +456,14 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                         }
                 }
             }
+            __builtin_amdgcn_s_waitcnt(0);   // the next tile's copies have landed
+            __syncthreads();
         }
     }
-    if (threadIdx.x == 0 && pairs) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)pairs);
+    if (threadIdx.x % 64 == 0 && units) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)units);
 }
 
-void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *T, int64_t nq, int ntiles,
+void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
                 const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
                 uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
                 hipStream_t st)
@@ -417,7 +477,7 @@ void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const flo
 #define MS(KS)                                                                                                  \
     hipLaunchKernelGGL((k_mfma_sweep<KS, kRowTiles>), dim3((unsigned)grid_blocks), dim3(256), 0, st,                         \
                        reinterpret_cast<const uint4 *>(o.X16t), o.xn, reinterpret_cast<const uint4 *>(qv.Q16t), \
-                       qv.qn, qv.qe, T, nq, ntiles, s.emax, s.nmax, s.leaf_lo, s.leaf_hi, leaf_mask, o.n, tomb,  \
+                       qv.qn, tqe, nq, ntiles, s.emax, s.nmax, s.leaf_lo, s.leaf_hi, leaf_mask, o.n, tomb,      \
                        n_items, chunk, nchunks, work, cands, cand_count, cand_cap, eps_a, eps_b, eps_c, counters)
     switch (o.ksteps) {
     case 1: MS(1); break;
@@ -426,6 +486,7 @@ void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const flo
     default: MS(4); break;
     }
 #undef MS
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,6 +517,7 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
         const int leaf = items[2 * it];
         const int tile = items[2 * it + 1];
         const uint64_t mask = leaf_mask[(size_t)leaf * ntiles + tile];
+        if (mask == 0ull) continue;   // every query pruned by the leaf test
         const int64_t q = (int64_t)tile * 64 + lane;
         const bool act = ((mask >> lane) & 1ull) && q < nq;
         int qp[MP];
@@ -512,6 +574,7 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
     else if (t.mpad == 16) OF(16);
     else OF(32);
 #undef OF
+    check_launch(__func__);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,10 +626,11 @@ void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const
     const int64_t threads = nq * ncache * 16;
     hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Q32, nq, dp, C32,
                        cids, clive, ncache, base, cands, cand_count, cand_cap);
+    check_launch(__func__);
 }
 
 // EDIT: one lane per (query, slot) pair, query as the pattern.
-__global__ void k_cache_scan_edit(QueryEdit qv, int64_t nq, const uint8_t *__restrict__ cchars, int cstride,
+__global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const uint8_t *__restrict__ cchars, int cstride,
                                   const int32_t *__restrict__ clen, const uint32_t *__restrict__ cids,
                                   const uint32_t *__restrict__ clive, int64_t ncache, const float *__restrict__ base,
                                   Cand *__restrict__ cands, uint32_t *__restrict__ cand_count, int64_t cand_cap)
@@ -579,7 +643,7 @@ __global__ void k_cache_scan_edit(QueryEdit qv, int64_t nq, const uint8_t *__res
     const int plen = (int)(qv.off[q + 1] - qv.off[q]);
     const int tl = clen[c];
     if (abs(plen - tl) > cut) return;
-    const int d = dev::myers_any(qv.peq + (size_t)q * 256 * 4, plen, cchars + (size_t)c * cstride, tl, cut);
+    const int d = dev::myers_any(qv.peq + (size_t)q * o.rows * 4, plen, cchars + (size_t)c * cstride, tl, cut, o.lut);
     if (d <= cut) {
         uint32_t idx = atomicAdd(cand_count, 1u);
         if (idx < cand_cap) {
@@ -592,14 +656,15 @@ __global__ void k_cache_scan_edit(QueryEdit qv, int64_t nq, const uint8_t *__res
     }
 }
 
-void cache_scan_edit(const QueryEdit &qv, int64_t nq, const uint8_t *cchars, int cstride, const int32_t *clen,
-                     const uint32_t *cids, const uint32_t *clive, int64_t ncache, const float *base, Cand *cands,
-                     uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
+void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
+                     const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
+                     const float *base, Cand *cands, uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
 {
     if (nq == 0 || ncache == 0) return;
     const int64_t threads = nq * ncache;
-    hipLaunchKernelGGL(k_cache_scan_edit, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, qv, nq, cchars,
-                       cstride, clen, cids, clive, ncache, base, cands, cand_count, cand_cap);
+    hipLaunchKernelGGL(k_cache_scan_edit, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, qv, o, nq,
+                       cchars, cstride, clen, cids, clive, ncache, base, cands, cand_count, cand_cap);
+    check_launch(__func__);
 }
 
 }  // namespace k

@@ -8,6 +8,10 @@
 namespace gts {
 namespace k {
 
+// Raise the launch error left by the wrapper `name` (a bad grid or resource
+// request), so that it surfaces at its own call and not at a later one.
+void check_launch(const char *name);
+
 // A (query, object) pair on its way to the answer.
 //   pos >= 0 : candidate at tree position pos; val = float bits of an
 //              estimate of the squared distance (L2 tile path) or 0.
@@ -25,14 +29,13 @@ void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpa
                     int64_t s_piv, int64_t s_row, hipStream_t st);
 void dist_edit_pivots_f32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
                           const int32_t *poff, int m, int mpad, float *out, int64_t s_piv, int64_t s_row,
-                          hipStream_t st);
-void dist_edit_pivots_i32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
-                          const int32_t *poff, int m, int32_t *out, int64_t s_piv, int64_t s_row,
-                          hipStream_t st);
-void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, uint64_t *peq, hipStream_t st);
+                          const uint8_t *lut, int arows, hipStream_t st);
+void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, const uint8_t *lut, int arows, uint64_t *peq,
+               hipStream_t st);
 void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t nq, int mpad, int is_edit,
                 float delta, float pt_max, float *T, float *thr, float *cut, hipStream_t st);
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+void sum_pad(const float *a, const float *b, int64_t n, int64_t npad, float *out, hipStream_t st);
 
 // ---- tree and candidates (k_search.hip) ------------------------------------
 struct TreeView {
@@ -68,6 +71,8 @@ struct EditView {
     const uint8_t *chars;      // leaf order
     const int32_t *soff;       // [n + 1]
     int64_t n;
+    const uint8_t *lut;        // [256] byte -> alphabet code (rows-1: outside)
+    int rows;                  // alphabet size + 1 (rows of a match table)
 };
 struct QueryL2 {
     const float *Q32;          // [nq][dp]
@@ -77,7 +82,7 @@ struct QueryL2 {
 struct QueryEdit {
     const uint8_t *chars;
     const int64_t *off;        // [nq + 1]
-    const uint64_t *peq;       // [nq][256][4]
+    const uint64_t *peq;       // [nq][rows][4] match tables
 };
 
 void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
@@ -91,7 +96,9 @@ struct SlabView {
     const int32_t *leaf_lo, *leaf_hi;
     int64_t n_slabs;
 };
-void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *T, int64_t nq, int ntiles,
+// tqe[q] = T[q] + e_q (true-distance bound plus the query's bf16 error),
+// -inf on padding rows; valid for whole 64-query tiles.
+void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
                 const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
                 uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
                 hipStream_t st);
@@ -107,9 +114,31 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
 void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
                    const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, uint32_t *cand_count,
                    int64_t cand_cap, hipStream_t st);
-void cache_scan_edit(const QueryEdit &qv, int64_t nq, const uint8_t *cchars, int cstride, const int32_t *clen,
-                     const uint32_t *cids, const uint32_t *clive, int64_t ncache, const float *base, Cand *cands,
-                     uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
+                     const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
+                     const float *base, Cand *cands, uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+// Largest distance from each leaf's first object to the leaf's objects.
+void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_t *leaf_cnt, int64_t n_leaves,
+                      float *leafR, hipStream_t st);
+// Farthest-first centres over n objects (input order): keys[0] holds the
+// key of the first centre, keys[1..K] must be zero; on return centers[j] is
+// centre j, mind[o] the (squared, for L2) distance of object o to its nearest
+// centre and near[o] that centre's number.
+void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, int32_t *centers, float *mind,
+                    int32_t *near, hipStream_t st);
+void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const uint8_t *lut, int arows, int K,
+                      uint64_t *keys, int32_t *centers, float *mind, int32_t *near, hipStream_t st);
+// Nearest centre of each query string: best[q] (preset to all ones) becomes
+// min over centres c of (d(q, c) << 32 | c).
+void near_centre_edit(const uint8_t *cchars, const int32_t *coff, int K, const QueryEdit &qv, const int32_t *qlen,
+                      int rows, const uint8_t *lut, int64_t nq, int max_qlen, unsigned long long *best,
+                      hipStream_t st);
+// Edit-distance leaf test (Lemma 1 with each leaf's first object as its pivot):
+// clears mask bits of queries q with d(q, p_L) > T_q + R_L.  One workgroup per
+// (64-query tile, slice of leaves); the tile's match tables sit in LDS.
+void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
+                    const float *leafR, int64_t n_leaves, const float *T, int64_t nq, int ntiles, int max_qlen,
+                    uint64_t *leaf_mask, hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
