@@ -134,6 +134,10 @@ struct IndexData {
     DevBuf cchars;               // uint8 centre strings, in chain order
     DevBuf coff;                 // int32 [n_centres + 1]
     int32_t n_centres = 0;
+    DevBuf cellR;                // float [n_centres] covering radius of each cell
+    DevBuf cell_box;             // float [n_centres][2 * mpad] global pivot box
+    DevBuf cell_len;             // int32 [n_centres][2] string length range
+    DevBuf leaf_cell;            // int32 [n_leaves][2] first and last cell of a leaf
     // both
     float pt_max = 0.f;          // largest pivot-table value
     DevBuf ids;                  // uint32 [n] id at each position

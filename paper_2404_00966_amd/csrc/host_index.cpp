@@ -318,6 +318,48 @@ void build_tree(gts_index *idx, const HostObjects &objs)
             nfirst[t.leaf0 + j2] = cut[j2];
             ncnt[t.leaf0 + j2] = cut[j2 + 1] - cut[j2];
         }
+        if (!l2) {
+            // per cell: covering radius, pivot box and length range; per leaf:
+            // the cells it spans
+            std::vector<float> cR(K, -INFINITY), cbox((size_t)K * 2 * mpad);
+            std::vector<int32_t> clen((size_t)2 * K);
+            for (int r = 0; r < K; r++) {
+                for (int i = 0; i < mpad; i++) {
+                    cbox[(size_t)r * 2 * mpad + i] = i < m ? INFINITY : -INFINITY;
+                    cbox[(size_t)r * 2 * mpad + mpad + i] = i < m ? -INFINITY : INFINITY;
+                }
+                clen[2 * r] = INT32_MAX;
+                clen[2 * r + 1] = INT32_MIN;
+            }
+            for (int64_t p = 0; p < n; p++) {
+                const int64_t o = perm[p];
+                const int r = rank[nearc[o]];
+                cR[r] = std::max(cR[r], cmind[o]);
+                float *b = cbox.data() + (size_t)r * 2 * mpad;
+                for (int i = 0; i < m; i++) {
+                    const float x = PTin[(size_t)i * n + o];
+                    b[i] = std::min(b[i], x);
+                    b[mpad + i] = std::max(b[mpad + i], x);
+                }
+                const int32_t len = (int32_t)(objs.offsets[o + 1] - objs.offsets[o]);
+                clen[2 * r] = std::min(clen[2 * r], len);
+                clen[2 * r + 1] = std::max(clen[2 * r + 1], len);
+            }
+            std::vector<int32_t> lcell((size_t)2 * L);
+            for (int64_t j2 = 0; j2 < L; j2++) {
+                if (cut[j2 + 1] > cut[j2]) {
+                    lcell[2 * j2] = rank[nearc[perm[cut[j2]]]];
+                    lcell[2 * j2 + 1] = rank[nearc[perm[cut[j2 + 1] - 1]]];
+                } else {
+                    lcell[2 * j2] = 1;
+                    lcell[2 * j2 + 1] = 0;
+                }
+            }
+            upload(d.cellR, cR, st);
+            upload(d.cell_box, cbox, st);
+            upload(d.cell_len, clen, st);
+            upload(d.leaf_cell, lcell, st);
+        }
         for (int64_t v = t.leaf0 - 1; v >= 0; v--) {
             nfirst[v] = nfirst[v * F + 1];
             ncnt[v] = 0;

@@ -31,7 +31,7 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_NEARC,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_NEARC, W_CMASK,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "workspace slots of gts_index too few");
@@ -201,14 +201,22 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
         rec(idx, 4);
     } else {
         uint64_t *mask = wsp<uint64_t>(idx, W_MASK, (size_t)t.n_leaves * ntiles);
-        k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)t.n_leaves * ntiles * 2, 0u, st);
         int32_t *items = nullptr;
         const int64_t item_cap = t.n_leaves * ntiles;
-        if (!l2) items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
-        k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
-        if (!l2 && d.lpad > 0)
-            k::edit_leaf_ball(oe, qe, idx->ws[W_QLEN].as<int32_t>() + q0, t.leaf_first.as<int32_t>(),
-                              d.leafR.as<float>(), t.n_leaves, T, ng, ntiles, b.max_qlen, mask, st);
+        if (l2) {
+            k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)t.n_leaves * ntiles * 2, 0u, st);
+            k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
+        } else {
+            // cells, then leaves (every leaf mask written), then the item list
+            items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
+            uint64_t *cmask = wsp<uint64_t>(idx, W_CMASK, (size_t)d.n_centres * ntiles);
+            const int32_t *qlen = idx->ws[W_QLEN].as<int32_t>() + q0;
+            k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
+                           d.cell_len.as<int32_t>(), d.n_centres};
+            k::edit_cell_test(oe, qe, qlen, QP, mpad, T, ng, ntiles, b.max_qlen, cv, cmask, counters, st);
+            k::edit_leaf_ball(oe, qe, qlen, t.leaf_first.as<int32_t>(), d.leafR.as<float>(), d.leaf_cell.as<int32_t>(),
+                              t.n_leaves, cmask, T, ng, ntiles, b.max_qlen, mask, items, small + 1, item_cap, st);
+        }
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
                          d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, st);

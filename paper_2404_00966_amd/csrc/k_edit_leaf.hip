@@ -5,9 +5,10 @@
 // exact integers (bit-parallel Levenshtein), so the test needs no margin.
 //
 //   k_leaf_radius_edit : R_L at build time, one wave per leaf
-//   k_edit_leaf_ball   : the leaf test for every (64-query tile, leaf) pair
-//                        that survived the node filter; clears the mask bits
-//                        of the queries it prunes
+//   k_edit_cell_test   : the cell test for every (64-query tile, cell)
+//   k_edit_leaf_ball   : the leaf test for every (64-query tile, leaf) whose
+//                        cells passed; writes the leaf masks and the list of
+//                        (leaf, tile) pairs that object filtering walks
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -94,15 +95,20 @@ void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// Leaf test.  Workgroup = (tile, chunk of kLeafChunk leaves), four waves; the
-// 64 lanes of a wave are the tile's 64 queries (each the Myers pattern of its
-// own lane) and a wave walks its leaves one at a time: the pivot string is the
-// common text, staged as codes in LDS.  Per lane the cutoff is T_q + R_L, with
-// the early exit of the bit-parallel recurrence; the length difference alone
-// prunes first.  The tile's match tables sit in LDS when they fit (TAB), else
-// lanes read their own query's table from global memory.
+// Cell and leaf tests.  Workgroup = (64-query tile, chunk of cells or leaves),
+// four waves; the 64 lanes of a wave are the tile's queries (each the Myers
+// pattern of its own lane) and a wave walks its balls one at a time: the
+// ball's pivot string is the common text, staged as codes in LDS.  Per lane
+// the cutoff is T_q + R with the early exit of the bit-parallel recurrence;
+// cheaper tests go first.  The tile's match tables sit in LDS when they fit
+// (TAB), else lanes read their own query's table from global memory.
+//
+// Cells (the clusters that order the leaves) are tested first: a cell passes
+// for a query when its box over the global pivot distances (Lemma 1 on every
+// pivot), its string-length range and its centre ball all admit T_q.  A leaf
+// starts from the union of its cells' masks and then takes its own ball test.
 // ---------------------------------------------------------------------------
-constexpr int kLeafChunk = 256;
+constexpr int kBallChunk = 256;
 constexpr int kTileTabWords = 4096;   // 32 KiB of LDS
 
 struct GlobalPeq {
@@ -110,14 +116,48 @@ struct GlobalPeq {
     __device__ __forceinline__ uint64_t operator[](int i) const { return tab[i]; }
 };
 
-template <int W, bool TAB>
-__global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
-                                                        const int32_t *__restrict__ leaf_first,
-                                                        const float *__restrict__ leafR, int64_t n_leaves,
-                                                        const float *__restrict__ T, int64_t nq, int ntiles,
-                                                        uint64_t *__restrict__ leaf_mask)
+// The tile's match tables into LDS: s_tab[(c * W + w) * 64 + j] = word w of
+// code c of query tile*64 + j (zero for queries past nq).
+template <int W>
+__device__ __forceinline__ void load_tile_tab(uint64_t *s_tab, const QueryEdit &qv, int rows, int tile, int64_t nq)
 {
-    extern __shared__ uint64_t s_tab[];   // rows * W * 64 words when TAB
+    const int words = rows * W * 64;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) {
+        const int j = i & 63, w = (i >> 6) % W, c = (i >> 6) / W;
+        const int64_t qq = (int64_t)tile * 64 + j;
+        s_tab[i] = qq < nq ? qv.peq[((size_t)qq * rows + c) * 4 + w] : 0ull;
+    }
+}
+
+// Ball test of the wave's queries against one pivot string: lanes with `pass`
+// set keep it iff d(q, pivot) <= cut.  s_code is the wave's staging row.
+template <int W, bool TAB>
+__device__ __forceinline__ bool ball_pass(bool pass, const uint8_t *__restrict__ chars, int32_t s0, int tl, int plen,
+                                          int cut, uint8_t *s_code, const uint8_t *s_lut, const uint64_t *s_tab,
+                                          const uint64_t *gtab, int lane)
+{
+    for (int b = lane; b < tl; b += 64) s_code[b] = s_lut[chars[s0 + b]];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    pass = pass && abs(plen - tl) <= cut;
+    if (pass) {
+        int d;
+        if (TAB) d = dev::myers_distance<W>(TilePeq{s_tab, W, lane}, plen, s_code, tl, cut, NoLut{});
+        else d = dev::myers_distance<W>(GlobalPeq{gtab}, plen, s_code, tl, cut, NoLut{});
+        pass = d <= cut;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return pass;
+}
+
+template <int W, int MP, bool TAB>
+__global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
+                                                        const float *__restrict__ QP, const float *__restrict__ T,
+                                                        int64_t nq, int ntiles, CellView cv,
+                                                        uint64_t *__restrict__ cell_mask,
+                                                        unsigned long long *__restrict__ counters)
+{
+    extern __shared__ uint64_t s_tab[];
     __shared__ uint8_t s_code[4][256];
     __shared__ uint8_t s_lut[256];
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
@@ -126,65 +166,138 @@ __global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv
     const int64_t q = (int64_t)tile * 64 + lane;
     const bool qok = q < nq;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
-    if (TAB) {
-        // s_tab[(c * W + w) * 64 + j] = word w of code c of query tile*64 + j
-        const int words = o.rows * W * 64;
-        for (int i = threadIdx.x; i < words; i += blockDim.x) {
-            const int j = i & 63, w = (i >> 6) % W, c = (i >> 6) / W;
-            const int64_t qq = (int64_t)tile * 64 + j;
-            s_tab[i] = qq < nq ? qv.peq[((size_t)qq * o.rows + c) * 4 + w] : 0ull;
+    if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq);
+    __syncthreads();
+    const int plen = qok ? qlen[q] : 0;
+    const int tq = qok ? (int)T[q] : -1;
+    float qp[MP];
+#pragma unroll
+    for (int i = 0; i < MP; i++) qp[i] = qok ? QP[(size_t)q * MP + i] : 0.f;
+    const uint64_t *gtab = qv.peq + (size_t)(qok ? q : 0) * o.rows * 4;
+    long long tests = 0;
+    for (int64_t ci = wave; ci < kBallChunk; ci += 4) {
+        const int64_t c = chunk * kBallChunk + ci;
+        if (c >= cv.n) break;
+        const float *b = cv.box + (size_t)c * 2 * MP;
+        float g = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(b[i] - qp[i], qp[i] - b[MP + i]));
+        const int lmin = cv.len[2 * c], lmax = cv.len[2 * c + 1];
+        bool pass = qok && g <= (float)tq && lmin - plen <= tq && plen - lmax <= tq;
+        tests += qok ? 1 : 0;
+        const float R = cv.R[c];
+        if (dev::ballot(pass) != 0ull && R >= 0.f) {
+            const int32_t s0 = cv.off[c];
+            pass = ball_pass<W, TAB>(pass, cv.chars, s0, cv.off[c + 1] - s0, plen, tq + (int)R, s_code[wave], s_lut,
+                                     s_tab, gtab, lane);
+        } else {
+            pass = false;
         }
+        const uint64_t m = dev::ballot(pass);
+        if (lane == 0) cell_mask[(size_t)c * ntiles + tile] = m;
     }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) tests += __shfl_xor(tests, o2, 64);
+    if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
+}
+
+template <int W, bool TAB>
+__global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
+                                                        const int32_t *__restrict__ leaf_first,
+                                                        const float *__restrict__ leafR,
+                                                        const int32_t *__restrict__ leaf_cell, int64_t n_leaves,
+                                                        const uint64_t *__restrict__ cell_mask,
+                                                        const float *__restrict__ T, int64_t nq, int ntiles,
+                                                        uint64_t *__restrict__ leaf_mask, int32_t *__restrict__ items,
+                                                        uint32_t *__restrict__ item_count, int64_t item_cap)
+{
+    extern __shared__ uint64_t s_tab[];
+    __shared__ uint8_t s_code[4][256];
+    __shared__ uint8_t s_lut[256];
+    const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
+    const int tile = (int)(blockIdx.x % ntiles);
+    const int64_t chunk = blockIdx.x / ntiles;
+    const int64_t q = (int64_t)tile * 64 + lane;
+    const bool qok = q < nq;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
+    if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq);
     __syncthreads();
     const int plen = qok ? qlen[q] : 0;
     const int tq = qok ? (int)T[q] : -1;
     const uint64_t *gtab = qv.peq + (size_t)(qok ? q : 0) * o.rows * 4;
-    for (int64_t li = wave; li < kLeafChunk; li += 4) {
-        const int64_t leaf = chunk * kLeafChunk + li;
+    for (int64_t li = wave; li < kBallChunk; li += 4) {
+        const int64_t leaf = chunk * kBallChunk + li;
         if (leaf >= n_leaves) break;
-        uint64_t *slot = leaf_mask + (size_t)leaf * ntiles + tile;
-        const uint64_t m = *slot;
-        if (m == 0ull) continue;
+        uint64_t m = 0;
+        for (int c = leaf_cell[2 * leaf]; c <= leaf_cell[2 * leaf + 1]; c++) m |= cell_mask[(size_t)c * ntiles + tile];
         const float R = leafR[leaf];
-        if (R < 0.f) {
-            if (lane == 0) *slot = 0ull;
-            continue;
+        if (m != 0ull && R >= 0.f) {
+            const int32_t s0 = o.soff[leaf_first[leaf]];
+            const int tl = o.soff[leaf_first[leaf] + 1] - s0;
+            m = dev::ballot(ball_pass<W, TAB>((m >> lane) & 1ull, o.chars, s0, tl, plen, tq + (int)R, s_code[wave],
+                                              s_lut, s_tab, gtab, lane));
+        } else {
+            m = 0;
         }
-        const int32_t pf = leaf_first[leaf];
-        const int32_t s0 = o.soff[pf];
-        const int tl = o.soff[pf + 1] - s0;
-        for (int b = lane; b < tl; b += 64) s_code[wave][b] = s_lut[o.chars[s0 + b]];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int cut = tq + (int)R;
-        bool pass = ((m >> lane) & 1ull) && abs(plen - tl) <= cut;
-        if (pass) {
-            int d;
-            if (TAB) d = dev::myers_distance<W>(TilePeq{s_tab, W, lane}, plen, s_code[wave], tl, cut, NoLut{});
-            else d = dev::myers_distance<W>(GlobalPeq{gtab}, plen, s_code[wave], tl, cut, NoLut{});
-            pass = d <= cut;
+        if (lane == 0) {
+            leaf_mask[(size_t)leaf * ntiles + tile] = m;
+            if (m) {
+                const uint32_t idx = atomicAdd(item_count, 1u);
+                if (idx < item_cap) {
+                    items[2 * (size_t)idx] = (int32_t)leaf;
+                    items[2 * (size_t)idx + 1] = tile;
+                }
+            }
         }
-        const uint64_t nm = dev::ballot(pass);
-        if (lane == 0) *slot = nm;
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
+void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
+                    const float *T, int64_t nq, int ntiles, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    unsigned long long *counters, hipStream_t st)
+{
+    if (nq == 0 || cv.n == 0) return;
+    const int W = std::max(1, (max_qlen + 63) / 64);
+    const int64_t chunks = (cv.n + kBallChunk - 1) / kBallChunk;
+    const unsigned grid = (unsigned)(chunks * ntiles);
+    const bool tab = (int64_t)o.rows * W * 64 <= kTileTabWords;
+    const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
+#define CT(WW, MP, TB)                                                                                            \
+    hipLaunchKernelGGL((k_edit_cell_test<WW, MP, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, QP, T, nq,    \
+                       ntiles, cv, cell_mask, counters)
+#define CTM(WW, TB)                 \
+    if (mpad == 8) CT(WW, 8, TB);   \
+    else if (mpad == 16) CT(WW, 16, TB); \
+    else CT(WW, 32, TB);
+#define CTW(TB)                     \
+    switch (W) {                    \
+    case 1: CTM(1, TB) break;       \
+    case 2: CTM(2, TB) break;       \
+    case 3: CTM(3, TB) break;       \
+    default: CTM(4, TB) break;      \
+    }
+    if (tab) CTW(true) else CTW(false)
+#undef CTW
+#undef CTM
+#undef CT
+    check_launch(__func__);
+}
+
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
-                    const float *leafR, int64_t n_leaves, const float *T, int64_t nq, int ntiles, int max_qlen,
-                    uint64_t *leaf_mask, hipStream_t st)
+                    const float *leafR, const int32_t *leaf_cell, int64_t n_leaves, const uint64_t *cell_mask,
+                    const float *T, int64_t nq, int ntiles, int max_qlen, uint64_t *leaf_mask, int32_t *items,
+                    uint32_t *item_count, int64_t item_cap, hipStream_t st)
 {
     if (nq == 0 || n_leaves == 0) return;
     const int W = std::max(1, (max_qlen + 63) / 64);
-    const int64_t chunks = (n_leaves + kLeafChunk - 1) / kLeafChunk;
+    const int64_t chunks = (n_leaves + kBallChunk - 1) / kBallChunk;
     const unsigned grid = (unsigned)(chunks * ntiles);
     const bool tab = (int64_t)o.rows * W * 64 <= kTileTabWords;
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define EB(WW, TB)                                                                                                  \
     hipLaunchKernelGGL((k_edit_leaf_ball<WW, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, leaf_first, leafR, \
-                       n_leaves, T, nq, ntiles, leaf_mask)
-#define EBW(TB)             \
-    switch (W) {            \
+                       leaf_cell, n_leaves, cell_mask, T, nq, ntiles, leaf_mask, items, item_count, item_cap)
+#define EBW(TB)               \
+    switch (W) {              \
     case 1: EB(1, TB); break; \
     case 2: EB(2, TB); break; \
     case 3: EB(3, TB); break; \

@@ -7,7 +7,6 @@
 namespace gts {
 namespace k {
 
-enum { CNT_VERIFIED = 3 };
 
 __global__ void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
                              uint32_t *__restrict__ qcount)

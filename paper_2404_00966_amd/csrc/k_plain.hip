@@ -11,7 +11,6 @@
 namespace gts {
 namespace k {
 
-enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_VERIFIED = 3 };
 
 constexpr int kPlainCand = 1024;
 constexpr int kPlainBlock = 256;

@@ -6,7 +6,6 @@
 namespace gts {
 namespace k {
 
-enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3 };
 
 // Largest box gap of a query (pivot distances qp) to node `node`:
 // max_i max(lo_i - qp_i, qp_i - hi_i).  A node whose gap exceeds the query's

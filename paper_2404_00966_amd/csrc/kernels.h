@@ -8,6 +8,9 @@
 namespace gts {
 namespace k {
 
+// Slots of the device counters behind gts_stats.
+enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3 };
+
 // Raise the launch error left by the wrapper `name` (a bad grid or resource
 // request), so that it surfaces at its own call and not at a later one.
 void check_launch(const char *name);
@@ -133,12 +136,29 @@ void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const
 void near_centre_edit(const uint8_t *cchars, const int32_t *coff, int K, const QueryEdit &qv, const int32_t *qlen,
                       int rows, const uint8_t *lut, int64_t nq, int max_qlen, unsigned long long *best,
                       hipStream_t st);
-// Edit-distance leaf test (Lemma 1 with each leaf's first object as its pivot):
-// clears mask bits of queries q with d(q, p_L) > T_q + R_L.  One workgroup per
-// (64-query tile, slice of leaves); the tile's match tables sit in LDS.
+// Cells (the clusters that order the leaves, in chain order): centre
+// strings, covering radius, box over the global pivot distances and the
+// string-length range of each.
+struct CellView {
+    const uint8_t *chars;      // centre strings
+    const int32_t *off;        // [n + 1]
+    const float *R;            // [n] max distance centre -> member (-inf: empty)
+    const float *box;          // [n][2 * mpad]: lo[0..mpad), hi[0..mpad)
+    const int32_t *len;        // [n][2]: shortest and longest member
+    int64_t n;
+};
+// Cell test (Lemma 1 with each centre and with the global pivots): writes
+// cell_mask[cell][tile], the tile's queries that the cell may answer.
+void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
+                    const float *T, int64_t nq, int ntiles, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    unsigned long long *counters, hipStream_t st);
+// Leaf test (Lemma 1 with each leaf's first object as its pivot) on the
+// union of the leaf's cells' masks: writes leaf_mask[leaf][tile] for every
+// pair and appends the nonzero pairs to items.
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
-                    const float *leafR, int64_t n_leaves, const float *T, int64_t nq, int ntiles, int max_qlen,
-                    uint64_t *leaf_mask, hipStream_t st);
+                    const float *leafR, const int32_t *leaf_cell, int64_t n_leaves, const uint64_t *cell_mask,
+                    const float *T, int64_t nq, int ntiles, int max_qlen, uint64_t *leaf_mask, int32_t *items,
+                    uint32_t *item_count, int64_t item_cap, hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
