@@ -148,6 +148,118 @@ def cpu_baseline(args, l2data, np):
                       f"float64 brute force, {el:.1f}s"}
 
 
+def run_serving(args, gts, synth, torch, np):
+    """Serving mix: an L2 index (2M x 128) and a DNA index (200k strings)
+    behind one continuous-batching server, driven by an open-loop Poisson
+    trace: 70% kNN (k uniform 1..100), 25% range (selectivity log-uniform on
+    [0.001%, 0.1%], radius from the oracle's quantile table), 5% update
+    batches (1..N objects, insert or delete), each request on either index
+    with equal probability.  Latency runs from submission to answers on the
+    host.  A warm-up trace runs first on a separate server."""
+    radii = json.load(open(os.path.join(ROOT, "oracle", "radii.json")))
+    tl2, tdna = radii["serve_l2_2m_d128"], radii["serve_dna_200k"]
+    sel_grid = np.log(np.asarray(tl2["selectivity"]))
+    r_grid = np.asarray(tl2["radius_f32"])
+    within = np.asarray(tdna["within_r"])
+    t = time.perf_counter()
+    wl = synth.make_serving("serve_l2_2m_d128")
+    wd = synth.make_serving("serve_dna_200k")
+    log(f"serving workloads generated in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    il2 = gts.Index(torch.from_numpy(wl["objects"]).cuda(), gts.L2_F32, num_pivots=wl["pivots"],
+                    fanout=wl["fanout"], leaf_size=wl["leaf"], seed=wl["seed"], cache_limit=args.serve_cache)
+    oc, oo = wd["objects"]
+    idna = gts.Index((torch.from_numpy(oc).cuda(), torch.from_numpy(oo).cuda()), gts.EDIT_U8,
+                     num_pivots=wd["pivots"], fanout=wd["fanout"], seed=wd["seed"], cache_limit=args.serve_cache)
+    build_s = time.perf_counter() - t
+    log(f"serving indexes built in {build_s:.1f}s")
+    rng = np.random.default_rng(966007)
+    n_obj = [len(wl["objects"]), len(oo) - 1]
+    # liveness by id (ids are assigned in submission order, updates apply in order)
+    alive = [np.ones(2 * n_obj[0], bool), np.ones(2 * n_obj[1], bool)]
+    next_id = list(n_obj)
+    ins_used = [0, 0]
+    ql2 = wl["queries"]
+    qc, qo = wd["queries"]
+    ic, io = wd["inserts"]
+
+    def trace(seconds):
+        n = int(rng.poisson(args.serve_rate * seconds))
+        arr = np.cumsum(rng.exponential(1e3 / args.serve_rate, size=n))
+        reqs = []
+        for i in range(n):
+            ix = int(rng.integers(0, 2))
+            u = rng.random()
+            if u < 0.70 or u < 0.95:
+                if ix == 0:
+                    j = int(rng.integers(0, len(ql2)))
+                    q = ql2[j:j + 1]
+                else:
+                    j = int(rng.integers(0, len(qo) - 1))
+                    q = (qc[qo[j]:qo[j + 1]], np.array([0, qo[j + 1] - qo[j]], np.int64))
+                if u < 0.70:
+                    reqs.append(("knn", ix, q, int(rng.integers(1, 101))))
+                else:
+                    s = float(np.exp(rng.uniform(np.log(1e-5), np.log(1e-3))))
+                    if ix == 0:
+                        r = float(np.interp(np.log(s), sel_grid, r_grid))
+                    else:
+                        ok = np.nonzero(within <= s)[0]
+                        r = float(ok[-1]) if len(ok) else 0.0
+                    reqs.append(("range", ix, q, r))
+            else:
+                m = int(rng.integers(1, args.serve_update_max + 1))
+                if rng.random() < 0.5:
+                    if ix == 0:
+                        a = ins_used[0] % len(wl["inserts"])
+                        b = min(a + m, len(wl["inserts"]))
+                        objs = wl["inserts"][a:b]
+                        cnt = b - a
+                    else:
+                        a = ins_used[1] % (len(io) - 1)
+                        b = min(a + m, len(io) - 1)
+                        objs = (ic[io[a]:io[b]], io[a:b + 1] - io[a])
+                        cnt = b - a
+                    ins_used[ix] += cnt
+                    next_id[ix] += cnt
+                    if next_id[ix] > len(alive[ix]):
+                        alive[ix] = np.concatenate([alive[ix], np.ones(len(alive[ix]), bool)])
+                    reqs.append(("insert", ix, objs))
+                else:
+                    ids = []
+                    while len(ids) < m:
+                        c = rng.integers(0, next_id[ix], size=2 * m)
+                        c = np.unique(c[alive[ix][c]])
+                        take = c[: m - len(ids)]
+                        ids.extend(take.tolist())
+                        alive[ix][take] = False
+                    reqs.append(("delete", ix, np.array(ids[:m], np.int64)))
+        return reqs, arr
+
+    out = {}
+    for phase, secs in (("warmup", args.serve_warmup_s), ("measured", args.serve_s)):
+        reqs, arr = trace(secs)
+        log(f"{phase}: {len(reqs)} requests over {secs}s")
+        srv = gts.Server([il2, idna], lanes_per_index=args.serve_lanes, keep_results=False)
+        t = time.perf_counter()
+        srv.replay(reqs, arr)
+        srv.flush()
+        wall = time.perf_counter() - t
+        st = srv.stats()
+        srv.close()
+        kinds = {}
+        for q in reqs:
+            kinds[q[0]] = kinds.get(q[0], 0) + 1
+        out[phase] = dict(st, wall_s=wall, requests=len(reqs), kinds=kinds,
+                          offered_rate=len(reqs) / secs if secs else 0.0)
+        log(f"{phase}: {st}")
+    out["build_s"] = build_s
+    out["rebuilds"] = [il2.info()["rebuilds"], idna.info()["rebuilds"]]
+    il2.close()
+    idna.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,8 +267,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--queries", type=int, default=None, help="cap queries per kind (default: full)")
     ap.add_argument("--plain-queries", type=int, default=2000)
-    ap.add_argument("--cpu-queries", type=int, default=40)
+    ap.add_argument("--cpu-queries", type=int, default=1000)
     ap.add_argument("--skip-dna", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the batch benchmark")
+    ap.add_argument("--serve-rate", type=float, default=50000.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-s", type=float, default=4.0, help="measured trace length, s")
+    ap.add_argument("--serve-warmup-s", type=float, default=1.0)
+    ap.add_argument("--serve-update-max", type=int, default=1000)
+    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-cache", type=int, default=1 << 20, help="cache list limit of the serving indexes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path; "
@@ -170,6 +289,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gts.library()
+    if args.serving:
+        sv = run_serving(args, gts, synth, torch, np)
+        m = sv["measured"]
+        qps = m["queries"] / (m["span_ms"] * 1e-3) if m["span_ms"] > 0 else 0.0
+        line = {"metric": "queries/s, serving mix (2M x 128 L2 + 200k DNA, Poisson arrivals); p99 ms",
+                "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+                "ms_per_step": m["span_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "bf16-mfma/f32 (L2), int32 (edit)", "data": "synthetic (seeded mixture / DNA families)",
+                "config": {"workload": "serving_mix", "rate_per_s": args.serve_rate, "seconds": args.serve_s,
+                           "update_max": args.serve_update_max, "lanes_per_index": args.serve_lanes,
+                           "cache_limit": args.serve_cache},
+                "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"], "serving": sv}
+        print(json.dumps(line), flush=True)
+        return
     l2, l2data = run_l2(args, gts, synth, torch, np)
     log(f"l2: {l2['qps']:.0f} q/s, {l2['ms_per_step']:.2f} ms/step, stages {l2['stats']['ms_stage']}")
     dna = None

@@ -20,7 +20,8 @@
  *   - Every call returns a gts_status.  On failure the outputs are untouched
  *     and gts_last_error() describes the failure (thread-local text).
  *   - All GPU work of an index is ordered on the HIP stream given at build.
- *     An index is not re-entrant: calls on one index must not overlap.
+ *     An index is not re-entrant: calls on one index must not overlap
+ *     (concurrent use goes through a gts_server).
  *   - Ties: answers are sorted by (distance, id) ascending, and a kNN answer
  *     is the first min(k, number of live objects) objects in that order --
  *     the paper's Definition 2 admits any such set; this fixes one.
@@ -147,11 +148,12 @@ typedef struct gts_index gts_index;
 /* Build an index over `objs` (ids 0..n-1 in input order).
  * Follows the paper's construction (Sec. 4.2, Algorithms 1-3) with global
  * pivots: num_pivots pivots by farthest-first traversal (the first one
- * seeded), every object's distance to every pivot in a pivot table, and a
- * balanced tree whose nodes split their objects equal-count into `fanout`
- * children by distance to one pivot (Algorithm 3's rule: the last child
- * takes the remainder).  Each node keeps the box of its objects' pivot
- * distances.  Requires num_pivots in [1, 32], fanout in [2, 64], n >= 1.
+ * seeded) and every object's distance to every pivot in a pivot table; a
+ * balanced tree of `fanout`-way nodes over leaves of near-equal size, the
+ * objects ordered by cluster (farthest-first centres) so that leaves do not
+ * straddle clusters.  Each node keeps the box of its objects' pivot
+ * distances, each leaf a pivot of its own and its covering radius.
+ * Requires num_pivots in [1, 32], fanout in [2, 64], n >= 1.
  * hip_stream: a hipStream_t (NULL = the null stream) used for all of the
  * index's GPU work.  On success *out receives the new index. */
 gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_pivots,
@@ -217,6 +219,110 @@ gts_status gts_set_timing(gts_index *idx, int32_t enable);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *gts_last_error(void);
+
+/* ---- Serving: continuous batching over resident indexes -------------------
+ *
+ * A server owns worker threads over a set of built indexes (it does not own
+ * the indexes; destroy the server first).  Requests are submitted one at a
+ * time from any thread and complete asynchronously:
+ *
+ *   - Per index, requests take effect in submission order: a query sees
+ *     exactly the inserts and deletes submitted to its index before it (its
+ *     admission epoch).  An update waits for the index's batches in flight,
+ *     runs alone, and the queries behind it wait for it.
+ *   - Queries that queue up while others run are admitted together as the
+ *     next batch (continuous batching: range and kNN requests of any k mix in
+ *     one gts_search call), up to max_batch_queries, as soon as one of the
+ *     index's lanes is free.  Each lane has its own HIP stream and query
+ *     workspace, so batches of one index, and of different indexes, overlap
+ *     on the device.  A batch's intermediate data is bounded by
+ *     mem_budget_bytes through the two-stage split of gts_search.
+ *   - Answers are the same as gts_search gives for the request alone on the
+ *     index at its admission epoch. */
+typedef struct gts_server gts_server;
+
+#define GTS_REQ_RANGE 1
+#define GTS_REQ_KNN 2
+#define GTS_REQ_INSERT 3
+#define GTS_REQ_DELETE 4
+
+typedef struct {
+    int32_t index;           /* position in the server's index list            */
+    int32_t kind;            /* GTS_REQ_*                                      */
+    gts_objects objects;     /* RANGE/KNN: the queries; INSERT: the new objects
+                                (host or device; copied by gts_server_submit)  */
+    float radius;            /* RANGE: radius of every query of the request    */
+    int32_t k;               /* KNN: k of every query of the request (>= 1)    */
+    const int64_t *ids;      /* DELETE: host array [n_ids] (copied)            */
+    int64_t n_ids;
+    uint64_t tag;            /* returned unchanged in the completion            */
+} gts_request;
+
+typedef struct {
+    uint64_t ticket;         /* from gts_server_submit                          */
+    uint64_t tag;
+    int32_t kind;
+    gts_status status;       /* GTS_OK, or why this request failed              */
+    const char *error;       /* failure text ("" on success)                    */
+    gts_result result;       /* RANGE/KNN: host CSR over the request's queries  */
+    const int64_t *new_ids;  /* INSERT: [count] ids assigned                    */
+    int64_t count;           /* INSERT: objects inserted; DELETE: ids deleted   */
+    int64_t batch;           /* sequence number of the batch it ran in (-1: update) */
+    double t_submit_ms;      /* steady-clock milliseconds                       */
+    double t_start_ms;       /* its batch (or update) started                   */
+    double t_done_ms;        /* answers were on the host                        */
+    void *priv;
+} gts_completion;
+
+typedef struct {
+    int32_t lanes_per_index; /* concurrent batches per index (default 2)        */
+    int32_t max_batch_queries; /* queries per batch (default 16384)             */
+    int64_t mem_budget_bytes;/* per batch (0: the index's budget / lanes)       */
+    int32_t keep_results;    /* 0: record latencies and drop answers (no
+                                completions are queued); default 1 when the
+                                options pointer is NULL                         */
+} gts_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t queries;         /* query objects answered                         */
+    int64_t batches, updates;
+    double mean_batch_queries;
+    double p50_ms, p99_ms, max_ms; /* query requests: submit -> answers on host */
+    double span_ms;          /* first submit -> last completion                 */
+} gts_server_stats;
+
+/* Start a server over n_indexes built indexes.  opts may be NULL. */
+gts_status gts_server_create(gts_index *const *indexes, int32_t n_indexes, const gts_server_opts *opts,
+                             gts_server **out);
+
+/* Queue one request; *ticket (may be NULL) identifies its completion.
+ * GTS_EINVAL for a malformed request (nothing is queued). */
+gts_status gts_server_submit(gts_server *s, const gts_request *req, uint64_t *ticket);
+
+/* Submit n requests at the given arrival times (milliseconds after the call
+ * starts, non-decreasing), sleeping until each is due: an open-loop replay
+ * of a trace.  tickets (may be NULL): [n]. */
+gts_status gts_server_replay(gts_server *s, const gts_request *reqs, const double *arrival_ms, int64_t n,
+                             uint64_t *tickets);
+
+/* Take up to max completions, waiting up to wait_ms (0: do not wait, < 0:
+ * until at least one is available or nothing is pending).  Each taken
+ * completion must be released with gts_server_release. */
+gts_status gts_server_poll(gts_server *s, gts_completion *out, int32_t max, int32_t wait_ms, int32_t *n_out);
+
+/* Release a completion's memory. */
+gts_status gts_server_release(gts_completion *c);
+
+/* Wait until every submitted request has completed. */
+gts_status gts_server_flush(gts_server *s);
+
+/* Counters and latency percentiles since the server started. */
+gts_status gts_server_get_stats(gts_server *s, gts_server_stats *out);
+
+/* Finish every submitted request, stop the workers and free the server
+ * (completions not yet polled are released). */
+gts_status gts_server_destroy(gts_server *s);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // The C ABI of libgts.so (declared in include/gts.h): argument checks, error
 // text, and the lifetime of indexes and results.  No exception crosses it.
 #include <cstring>
+#include <functional>
 #include <string>
 
 #include "gts_internal.h"
@@ -38,6 +39,9 @@ template <class F> gts_status guarded(F &&f)
 }
 
 }  // namespace
+
+gts_status run_guarded(const std::function<void()> &f) { return guarded(f); }
+
 }  // namespace gts
 
 using namespace gts;
@@ -59,6 +63,7 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         if (metric == GTS_L2_F32) GTS_CHECK(objs->dim >= 1, GTS_EINVAL, "dim must be >= 1");
         auto idx = std::make_unique<gts_index>();
         idx->stream = static_cast<hipStream_t>(hip_stream);
+        idx->ctx.stream = idx->stream;
         if (opts) idx->opts = *opts;
         if (idx->opts.max_strlen <= 0 || idx->opts.max_strlen > kMaxStrlen) idx->opts.max_strlen = kMaxStrlen;
         if (idx->opts.cache_limit <= 0) idx->opts.cache_limit = 4096;
@@ -87,7 +92,7 @@ gts_status gts_search(gts_index *idx, const gts_objects *Q, const float *radius,
 {
     return guarded([&] {
         GTS_CHECK(idx != nullptr, GTS_EINVAL, "null index");
-        search(idx, Q, radius, k, opts, out);
+        search(idx, &idx->ctx, Q, radius, k, opts, out);
     });
 }
 
@@ -98,7 +103,7 @@ gts_status gts_range_query(gts_index *idx, const gts_objects *Q, const float *ra
         GTS_CHECK(idx != nullptr, GTS_EINVAL, "null index");
         GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
         GTS_CHECK(radius != nullptr || Q->n == 0, GTS_EINVAL, "null radius");
-        search(idx, Q, radius, nullptr, opts, out);
+        search(idx, &idx->ctx, Q, radius, nullptr, opts, out);
     });
 }
 
@@ -110,7 +115,7 @@ gts_status gts_knn_query(gts_index *idx, const gts_objects *Q, const int32_t *k,
         GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
         GTS_CHECK(k != nullptr || Q->n == 0, GTS_EINVAL, "null k");
         for (int64_t i = 0; i < Q->n; i++) GTS_CHECK(k[i] >= 1, GTS_EINVAL, "k must be >= 1");
-        search(idx, Q, nullptr, k, opts, out);
+        search(idx, &idx->ctx, Q, nullptr, k, opts, out);
     });
 }
 
@@ -165,8 +170,6 @@ gts_status gts_destroy(gts_index *idx)
         if (!idx) return;
         if (idx->stream) (void)hipStreamSynchronize(idx->stream);
         else (void)hipDeviceSynchronize();
-        for (auto &e : idx->ev)
-            if (e) (void)hipEventDestroy(e);
         delete idx;
     });
 }
@@ -204,7 +207,7 @@ gts_status gts_get_stats(const gts_index *idx, gts_stats *out)
 {
     return guarded([&] {
         GTS_CHECK(idx != nullptr && out != nullptr, GTS_EINVAL, "null argument");
-        *out = idx->stats;
+        *out = idx->ctx.stats;
     });
 }
 
@@ -212,7 +215,7 @@ gts_status gts_set_timing(gts_index *idx, int32_t enable)
 {
     return guarded([&] {
         GTS_CHECK(idx != nullptr, GTS_EINVAL, "null index");
-        idx->timing = enable != 0;
+        idx->ctx.timing = enable != 0;
     });
 }
 

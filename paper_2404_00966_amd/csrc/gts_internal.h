@@ -9,6 +9,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/gts.h"
@@ -138,6 +139,7 @@ struct IndexData {
     DevBuf cell_box;             // float [n_centres][2 * mpad] global pivot box
     DevBuf cell_len;             // int32 [n_centres][2] string length range
     DevBuf leaf_cell;            // int32 [n_leaves][2] first and last cell of a leaf
+    DevBuf cell_leaf;            // int32 [n_centres][2] first and last leaf of a cell
     // both
     float pt_max = 0.f;          // largest pivot-table value
     DevBuf ids;                  // uint32 [n] id at each position
@@ -183,14 +185,44 @@ struct HostObjects {
 void build_tree(gts_index *idx, const HostObjects &objs);
 // Rebuild over every live object (tree and cache), keeping ids.
 void rebuild(gts_index *idx);
+// Copy n rows of dim floats (src, packed) into device rows of dp floats
+// (dp >= dim; the dp - dim padding columns become zero).  Host sources are
+// copied as one contiguous transfer (packed to the padded width on the host
+// first when dp > dim) and have completed on return; device sources are
+// copied in stream order.
+void rows_to_device(float *dst, int dp, const float *src, int dim, int64_t n, bool src_on_device, hipStream_t st);
 // Add the bytes of `chars` to the index alphabet (uploads the table when it
 // changes; blocking).
 void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars);
 // Streamed updates.
 void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids);
 int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
+// Per-stream query state: the workspace, timing events and statistics of
+// the searches issued on one stream.  An index has a default context on its
+// own stream; more contexts let searches of one index run concurrently (the
+// index data is only read by a search).
+struct QueryCtx {
+    hipStream_t stream = nullptr;
+    DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
+    hipEvent_t ev[9] = {};
+    bool timing = false;
+    gts_stats stats{};
+    QueryCtx() = default;
+    QueryCtx(const QueryCtx &) = delete;
+    QueryCtx &operator=(const QueryCtx &) = delete;
+    ~QueryCtx()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+// Run f, turning exceptions into a status and this thread's error text (the
+// wrapper of every C-ABI entry point).
+gts_status run_guarded(const std::function<void()> &f);
+// Release a result allocated by search.
+void free_result(gts_result *r);
 // Queries.
-void search(gts_index *idx, const gts_objects *Q, const float *radius, const int32_t *k,
+void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *k,
             const gts_query_opts *opts, gts_result *out);
 // Copy a user object set (host or device) into host memory with fresh ids
 // starting at first_id; validates values and lengths.
@@ -208,14 +240,11 @@ struct gts_index {
     std::vector<uint8_t> h_tomb;       // host mirror of the tombstones
     std::vector<int64_t> pos_of_id;    // id -> tree position (-1: not in tree)
     std::vector<int64_t> slot_of_id;   // id -> cache slot (-1: not in cache)
-    hipEvent_t ev[9] = {};
     int64_t next_id = 0;
     int64_t n_deleted_tree = 0;
     int64_t rebuilds = 0;
     int32_t num_pivots = 0, fanout = 0;
     gts_build_opts opts{};
-    bool timing = false;
-    gts_stats stats{};
     // Byte alphabet of every string stored so far (EDIT): lut[b] is the code
     // of byte b, or arows - 1 for a byte never stored (such a byte in a query
     // matches nothing).  Codes only grow with inserts; nothing stored depends
@@ -223,6 +252,6 @@ struct gts_index {
     bool alpha[256] = {};
     gts::DevBuf lut;                   // uint8 [256]
     int32_t arows = 1;
-    // query workspace (grown on demand, reused across calls)
-    gts::DevBuf ws[gts::kWorkspaceSlots];
+    // the default query context (on `stream`)
+    gts::QueryCtx ctx;
 };

@@ -81,6 +81,25 @@ template <class T> void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s
 
 }  // namespace
 
+void rows_to_device(float *dst, int dp, const float *src, int dim, int64_t n, bool src_on_device, hipStream_t st)
+{
+    if (n == 0) return;
+    if (src_on_device) {
+        if (dp != dim) GTS_HIP(hipMemsetAsync(dst, 0, (size_t)n * dp * sizeof(float), st));
+        GTS_HIP(hipMemcpy2DAsync(dst, dp * sizeof(float), src, dim * sizeof(float), dim * sizeof(float), n,
+                                 hipMemcpyDeviceToDevice, st));
+    } else if (dp == dim) {
+        GTS_HIP(hipMemcpyAsync(dst, src, (size_t)n * dim * sizeof(float), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    } else {
+        std::vector<float> packed((size_t)n * dp, 0.f);
+        for (int64_t i = 0; i < n; i++)
+            std::copy(src + (size_t)i * dim, src + (size_t)(i + 1) * dim, &packed[(size_t)i * dp]);
+        GTS_HIP(hipMemcpyAsync(dst, packed.data(), packed.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    }
+}
+
 void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars)
 {
     bool seen[256] = {};
@@ -145,11 +164,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         d.dp = (objs.dim + 3) / 4 * 4;
         d.ksteps = (objs.dim + 31) / 32;
         in_x.alloc((size_t)n * d.dp * sizeof(float));
-        GTS_HIP(hipMemcpy2DAsync(in_x.p, d.dp * sizeof(float), objs.vecs.data(), objs.dim * sizeof(float),
-                                 objs.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
-        if (d.dp != d.dim)
-            GTS_HIP(hipMemset2DAsync(static_cast<char *>(in_x.p) + objs.dim * sizeof(float), d.dp * sizeof(float), 0,
-                                     (d.dp - d.dim) * sizeof(float), n, st));
+        rows_to_device(in_x.as<float>(), d.dp, objs.vecs.data(), objs.dim, n, false, st);
     } else {
         alphabet_add(idx, objs.chars);
         upload(in_chars, objs.chars, st);
@@ -359,6 +374,17 @@ void build_tree(gts_index *idx, const HostObjects &objs)
             upload(d.cell_box, cbox, st);
             upload(d.cell_len, clen, st);
             upload(d.leaf_cell, lcell, st);
+            std::vector<int32_t> cleaf((size_t)2 * K);
+            for (int r = 0; r < K; r++) {
+                cleaf[2 * r] = 1;
+                cleaf[2 * r + 1] = 0;
+            }
+            for (int64_t j2 = L - 1; j2 >= 0; j2--)
+                for (int r = lcell[2 * j2]; r <= lcell[2 * j2 + 1]; r++) {
+                    if (cleaf[2 * r] > cleaf[2 * r + 1]) cleaf[2 * r + 1] = (int32_t)j2;
+                    cleaf[2 * r] = (int32_t)j2;
+                }
+            upload(d.cell_leaf, cleaf, st);
         }
         for (int64_t v = t.leaf0 - 1; v >= 0; v--) {
             nfirst[v] = nfirst[v * F + 1];
@@ -432,8 +458,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         d.n_slabs = d.npad / kSlab;
         d.X32.alloc((size_t)d.npad * d.dp * sizeof(float));
         GTS_HIP(hipMemsetAsync(d.X32.p, 0, (size_t)d.npad * d.dp * sizeof(float), st));
-        GTS_HIP(hipMemcpy2DAsync(d.X32.p, d.dp * sizeof(float), h.vecs.data(), d.dim * sizeof(float),
-                                 d.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
+        rows_to_device(d.X32.as<float>(), d.dp, h.vecs.data(), d.dim, n, false, st);
         d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
         d.xn.alloc((size_t)d.npad * sizeof(float));
         d.xe.alloc((size_t)d.npad * sizeof(float));
@@ -630,8 +655,7 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     const int64_t s0 = c.count;
     if (d.metric != GTS_L2_F32) alphabet_add(idx, objs.chars);
     if (d.metric == GTS_L2_F32) {
-        GTS_HIP(hipMemcpy2DAsync(c.X32.as<float>() + (size_t)s0 * d.dp, d.dp * sizeof(float), objs.vecs.data(),
-                                 d.dim * sizeof(float), d.dim * sizeof(float), n, hipMemcpyHostToDevice, st));
+        rows_to_device(c.X32.as<float>() + (size_t)s0 * d.dp, d.dp, objs.vecs.data(), d.dim, n, false, st);
     } else {
         std::vector<uint8_t> slots((size_t)n * kMaxStrlen, 0);
         for (int64_t i = 0; i < n; i++) {

@@ -31,7 +31,7 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_NEARC, W_CMASK,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_CMASK0, W_CMASK, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "workspace slots of gts_index too few");
@@ -47,10 +47,10 @@ void free_result(gts_result *r);
 
 namespace {
 
-template <class T> T *wsp(gts_index *idx, int slot, size_t count)
+template <class T> T *wsp(QueryCtx *cx, int slot, size_t count)
 {
-    idx->ws[slot].alloc(std::max<size_t>(count * sizeof(T), 64));
-    return idx->ws[slot].as<T>();
+    cx->ws[slot].alloc(std::max<size_t>(count * sizeof(T), 64));
+    return cx->ws[slot].as<T>();
 }
 
 // Small device counters: [0] candidate count, [1] item count, [2] work counter
@@ -130,17 +130,18 @@ struct Batch {
     bool any_knn = false;
     int mode = GTS_MODE_BATCHED;
     int max_qlen = 0;          // longest query string (EDIT)
+    int64_t ntiles_all = 0;    // query tiles of the whole batch
 };
 
-void rec(gts_index *idx, int i)
+void rec(QueryCtx *cx, int i)
 {
-    if (idx->timing) GTS_HIP(hipEventRecord(idx->ev[i], idx->stream));
+    if (cx->timing) GTS_HIP(hipEventRecord(cx->ev[i], cx->stream));
 }
 
-bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t cap, GroupOut *go,
+bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t ng, int64_t cap, GroupOut *go,
                double *stage_ms)
 {
-    hipStream_t st = idx->stream;
+    hipStream_t st = cx->stream;
     IndexData &d = idx->data;
     Tree &t = d.tree;
     const bool l2 = d.metric == GTS_L2_F32;
@@ -152,38 +153,38 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n, idx->lut.as<uint8_t>(), idx->arows};
     const int ntiles = (int)((ng + kQTile - 1) / kQTile);
 
-    float *QP = idx->ws[W_QP].as<float>() + q0 * mpad;
-    float *base = idx->ws[W_BASE].as<float>() + q0;
-    float *T = idx->ws[W_T].as<float>() + q0;
-    float *thr = idx->ws[W_THR].as<float>() + q0;
-    int32_t *kq = idx->ws[W_KQ].as<int32_t>() + q0;
+    float *QP = cx->ws[W_QP].as<float>() + q0 * mpad;
+    float *base = cx->ws[W_BASE].as<float>() + q0;
+    float *T = cx->ws[W_T].as<float>() + q0;
+    float *thr = cx->ws[W_THR].as<float>() + q0;
+    int32_t *kq = cx->ws[W_KQ].as<int32_t>() + q0;
     k::QueryL2 qv{};
     k::QueryEdit qe{};
     if (l2) {
-        qv.Q32 = idx->ws[W_Q32].as<float>() + q0 * d.dp;
-        qv.Q16t = idx->ws[W_Q16].as<uint16_t>() + q0 * d.ksteps * 32;
-        qv.qn = idx->ws[W_QN].as<float>() + q0;
-        qv.qe = idx->ws[W_QE].as<float>() + q0;
+        qv.Q32 = cx->ws[W_Q32].as<float>() + q0 * d.dp;
+        qv.Q16t = cx->ws[W_Q16].as<uint16_t>() + q0 * d.ksteps * 32;
+        qv.qn = cx->ws[W_QN].as<float>() + q0;
+        qv.qe = cx->ws[W_QE].as<float>() + q0;
     } else {
-        qe.chars = idx->ws[W_QCHARS].as<uint8_t>();
-        qe.off = idx->ws[W_QOFF].as<int64_t>() + q0;
-        qe.peq = idx->ws[W_PEQ].as<uint64_t>() + q0 * idx->arows * 4;
+        qe.chars = cx->ws[W_QCHARS].as<uint8_t>();
+        qe.off = cx->ws[W_QOFF].as<int64_t>() + q0;
+        qe.peq = cx->ws[W_PEQ].as<uint64_t>() + q0 * idx->arows * 4;
     }
-    uint32_t *small = wsp<uint32_t>(idx, W_SMALL, kSmallWords);
-    unsigned long long *counters = idx->ws[W_COUNTERS].as<unsigned long long>();
+    uint32_t *small = wsp<uint32_t>(cx, W_SMALL, kSmallWords);
+    unsigned long long *counters = cx->ws[W_COUNTERS].as<unsigned long long>();
     k::fill_u32(small, kSmallWords, 0u, st);
-    k::Cand *cands = wsp<k::Cand>(idx, W_CANDS, cap);
+    k::Cand *cands = wsp<k::Cand>(cx, W_CANDS, cap);
     const uint32_t *tomb = d.tomb.as<uint32_t>();
 
     const bool plain = b.mode == GTS_MODE_PLAIN || (l2 && d.dim > kMaxMfmaDim);
-    rec(idx, 2);
+    rec(cx, 2);
     if (plain) {
         const int grid = (int)std::min<int64_t>(ng, 1024);
         k::PlainArgs pa{};
         pa.nq = ng;
         pa.base = base;
         pa.kq = kq;
-        pa.frontier = wsp<int32_t>(idx, W_FRONTIER, (size_t)grid * 2 * t.n_leaves);
+        pa.frontier = wsp<int32_t>(cx, W_FRONTIER, (size_t)grid * 2 * t.n_leaves);
         pa.grid = grid;
         pa.tomb = tomb;
         pa.ids = d.ids.as<uint32_t>();
@@ -195,55 +196,62 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
         pa.pt_max = d.pt_max;
         pa.leaf_piv32 = l2 && d.lpad > 0 ? d.PL32.as<float>() : nullptr;
         pa.leafR = l2 && d.lpad > 0 ? d.leafR.as<float>() : nullptr;
-        rec(idx, 3);
+        rec(cx, 3);
         if (l2) k::plain_l2(tv, ov, d.P32.as<float>(), d.m, d.PT.as<float>(), qv.Q32, pa, st);
         else k::plain_edit(tv, oe, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, d.PTe.as<uint8_t>(), qe, pa, st);
-        rec(idx, 4);
+        rec(cx, 4);
     } else {
-        uint64_t *mask = wsp<uint64_t>(idx, W_MASK, (size_t)t.n_leaves * ntiles);
+        uint64_t *mask = wsp<uint64_t>(cx, W_MASK, (size_t)t.n_leaves * ntiles);
         int32_t *items = nullptr;
         const int64_t item_cap = t.n_leaves * ntiles;
         if (l2) {
             k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)t.n_leaves * ntiles * 2, 0u, st);
             k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
         } else {
-            // cells, then leaves (every leaf mask written), then the item list
-            items = wsp<int32_t>(idx, W_ITEMS, (size_t)item_cap * 2);
-            uint64_t *cmask = wsp<uint64_t>(idx, W_CMASK, (size_t)d.n_centres * ntiles);
-            const int32_t *qlen = idx->ws[W_QLEN].as<int32_t>() + q0;
-            k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
-                           d.cell_len.as<int32_t>(), d.n_centres};
-            k::edit_cell_test(oe, qe, qlen, QP, mpad, T, ng, ntiles, b.max_qlen, cv, cmask, counters, st);
+            // leaves of the cells that passed (cell masks of the whole batch,
+            // this group's tiles from column q0 / 64), then the item list
+            items = wsp<int32_t>(cx, W_ITEMS, (size_t)item_cap * 2);
+            const uint64_t *cmask = cx->ws[W_CMASK].as<uint64_t>() + q0 / kQTile;
+            const int32_t *qlen = cx->ws[W_QLEN].as<int32_t>() + q0;
             k::edit_leaf_ball(oe, qe, qlen, t.leaf_first.as<int32_t>(), d.leafR.as<float>(), d.leaf_cell.as<int32_t>(),
-                              t.n_leaves, cmask, T, ng, ntiles, b.max_qlen, mask, items, small + 1, item_cap, st);
+                              d.cell_leaf.as<int32_t>(), d.n_centres, cmask, b.ntiles_all, T, ng, ntiles, b.max_qlen,
+                              mask, items, small + 1, item_cap, st);
         }
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
                          d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, st);
-        rec(idx, 3);
+        k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
+                       d.slab_leaf_hi.as<int32_t>(), d.n_slabs};
+        k::SweepWork sw{};
         if (l2) {
-            k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
-                           d.slab_leaf_hi.as<int32_t>(), d.n_slabs};
+            // the sweep's work list (timed with the node stage, so that the
+            // candidate stage is the MFMA sweep alone)
+            const int64_t pairs = d.n_slabs * ntiles;
+            const int64_t nitems = d.n_slabs * ((ntiles + k::kSweepItemTiles - 1) / k::kSweepItemTiles);
+            sw = k::SweepWork{wsp<int32_t>(cx, W_PAIR_TILE, pairs), wsp<uint64_t>(cx, W_PAIR_MASK, pairs),
+                              wsp<int4>(cx, W_SWEEP_ITEMS, nitems), small + 2};
+            k::slab_items(sv, mask, ntiles, sw, st);
+        }
+        rec(cx, 3);
+        if (l2) {
             int dev = 0, cus = 256;
             GTS_HIP(hipGetDevice(&dev));
             GTS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            const int chunk = 64;
-            const float *tqe = idx->ws[W_TQE].as<float>() + q0;
-            k::mfma_sweep(ov, sv, qv, tqe, ng, ntiles, mask, tomb, chunk, small + 2, cands, small + 0, cap, counters,
-                          cus * 2, st);
+            const float *tqe = cx->ws[W_TQE].as<float>() + q0;
+            k::mfma_sweep(ov, sv, qv, tqe, ng, ntiles, tomb, sw, cands, small + 0, cap, counters, cus * 2, st);
         } else {
-            int32_t *qlen = idx->ws[W_QLEN].as<int32_t>() + q0;
+            int32_t *qlen = cx->ws[W_QLEN].as<int32_t>() + q0;
             k::edit_objfilter(tv, items, small + 1, item_cap, mask, ntiles, QP, thr, qlen, ng, d.PTa.as<uint8_t>(),
                               d.soff.as<int32_t>(), tomb, cands, small + 0, cap, st);
         }
-        rec(idx, 4);
+        rec(cx, 4);
     }
     // cache list: brute force, already verified
     const CacheList &c = idx->cache;
     if (c.n_live > 0) {
         if (l2) {
             // emission cutoff: radius (range) or the widened bound T (kNN)
-            float *cut = idx->ws[W_CUT].as<float>() + q0;
+            float *cut = cx->ws[W_CUT].as<float>() + q0;
             k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
                              cut, cands, small + 0, cap, st);
         } else {
@@ -257,20 +265,20 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     const int64_t ncand = h_small[0];
     if (ncand > cap) return false;
     if (!plain && !l2 && (int64_t)h_small[1] > t.n_leaves * ntiles) fail(GTS_EDEVICE, "item list overflow");
-    idx->stats.candidates += ncand;
-    idx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
+    cx->stats.candidates += ncand;
+    cx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
 
     // ---- group by query ----------------------------------------------------
-    uint32_t *qcount = wsp<uint32_t>(idx, W_QCOUNT, ng + 1);
-    uint32_t *cursor = wsp<uint32_t>(idx, W_CURSOR, ng + 1);
-    int64_t *qoff = wsp<int64_t>(idx, W_QOFF64, ng + 1);
+    uint32_t *qcount = wsp<uint32_t>(cx, W_QCOUNT, ng + 1);
+    uint32_t *cursor = wsp<uint32_t>(cx, W_CURSOR, ng + 1);
+    int64_t *qoff = wsp<int64_t>(cx, W_QOFF64, ng + 1);
     k::fill_u32(qcount, ng, 0u, st);
     k::fill_u32(cursor, ng, 0u, st);
     k::group_hist(cands, small + 0, cap, qcount, st);
     k::scan_u32(qcount, ng, qoff, st);
-    k::Cand *grouped = wsp<k::Cand>(idx, W_GROUPED, std::max<int64_t>(ncand, 1));
+    k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, std::max<int64_t>(ncand, 1));
     k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, st);
-    rec(idx, 5);
+    rec(cx, 5);
     std::vector<int64_t> h_qoff(ng + 1);
     GTS_HIP(hipMemcpyAsync(h_qoff.data(), qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
@@ -291,21 +299,21 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     int64_t *big_off = nullptr;
     uint64_t *scratch = nullptr;
     if (any_big) {
-        big_off = wsp<int64_t>(idx, W_BIGOFF, ng);
+        big_off = wsp<int64_t>(cx, W_BIGOFF, ng);
         GTS_HIP(hipMemcpyAsync(big_off, big.data(), ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        scratch = wsp<uint64_t>(idx, W_SCRATCH, scratch_words);
+        scratch = wsp<uint64_t>(cx, W_SCRATCH, scratch_words);
     }
 
     // ---- verify, select, order ------------------------------------------------
-    uint64_t *out_keys = wsp<uint64_t>(idx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
-    uint32_t *out_count = wsp<uint32_t>(idx, W_OUTCNT, ng + 1);
+    uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
+    uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
     k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters};
     if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), st);
     else k::verify_edit(va, oe, qe, st);
-    rec(idx, 6);
+    rec(cx, 6);
 
     // ---- CSR piece of this group ---------------------------------------------
-    int64_t *res_off = wsp<int64_t>(idx, W_RESOFF, ng + 1);
+    int64_t *res_off = wsp<int64_t>(cx, W_RESOFF, ng + 1);
     k::scan_u32(out_count, ng, res_off, st);
     go->counts.resize(ng);
     GTS_HIP(hipMemcpyAsync(go->counts.data(), out_count, ng * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -317,14 +325,14 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
     go->dist.alloc(std::max<int64_t>(total, 1) * sizeof(float));
     k::csr_write(out_keys, qoff, out_count, res_off, ng, l2 ? 0 : 1, go->ids.as<int64_t>(), go->dist.as<float>(),
                  go->dist.as<int32_t>(), st);
-    rec(idx, 7);
+    rec(cx, 7);
     GTS_HIP(hipStreamSynchronize(st));
-    if (idx->timing) {
+    if (cx->timing) {
         float ms;
         const int stage_of[] = {-1, -1, -1, GTS_STAGE_NODES, GTS_STAGE_CANDS, GTS_STAGE_GROUP, GTS_STAGE_VERIFY,
                                 GTS_STAGE_OUTPUT};
         for (int i = 3; i <= 7; i++) {
-            GTS_HIP(hipEventElapsedTime(&ms, idx->ev[i - 1], idx->ev[i]));
+            GTS_HIP(hipEventElapsedTime(&ms, cx->ev[i - 1], cx->ev[i]));
             int s = stage_of[i];
             if (plain && i == 4) s = GTS_STAGE_PLAIN;
             stage_ms[s] += ms;
@@ -335,13 +343,13 @@ bool run_group(gts_index *idx, const Batch &b, int64_t q0, int64_t ng, int64_t c
 
 }  // namespace
 
-void search(gts_index *idx, const gts_objects *Q, const float *radius, const int32_t *kin,
+void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *kin,
             const gts_query_opts *opts, gts_result *out)
 {
     const double t_start = now_ms();
     GTS_CHECK(out != nullptr, GTS_EINVAL, "null result");
     GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
-    hipStream_t st = idx->stream;
+    hipStream_t st = cx->stream;
     IndexData &d = idx->data;
     const bool l2 = d.metric == GTS_L2_F32;
     const int mpad = d.tree.mpad;
@@ -371,29 +379,30 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             hbase[q] = r;
         }
     }
-    idx->stats = gts_stats{};
-    idx->stats.nq = nq;
+    cx->stats = gts_stats{};
+    cx->stats.nq = nq;
     std::memset(out, 0, sizeof(*out));
     out->nq = nq;
     out->metric = d.metric;
     out->location = rloc;
     double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (idx->timing && !idx->ev[0])
-        for (int i = 0; i < 9; i++) GTS_HIP(hipEventCreate(&idx->ev[i]));
-    rec(idx, 0);
+    if (cx->timing && !cx->ev[0])
+        for (int i = 0; i < 9; i++) GTS_HIP(hipEventCreate(&cx->ev[i]));
+    rec(cx, 0);
 
     // ---- queries into the workspace -----------------------------------------------
     // query rows padded by one extra tile: a group that starts inside a tile
     // still reads whole tiles of fragments
     const int64_t ntiles_all = (nq + kQTile - 1) / kQTile;
     const int64_t nqpad = ntiles_all * kQTile + kQTile;
-    wsp<float>(idx, W_QP, (size_t)nqpad * mpad);
-    float *base = wsp<float>(idx, W_BASE, nqpad);
-    wsp<float>(idx, W_T, nqpad);
-    wsp<float>(idx, W_THR, nqpad);
-    int32_t *kq = wsp<int32_t>(idx, W_KQ, nqpad);
-    int32_t *home = wsp<int32_t>(idx, W_HOME, nqpad);
-    unsigned long long *counters = wsp<unsigned long long>(idx, W_COUNTERS, 8);
+    b.ntiles_all = ntiles_all;
+    wsp<float>(cx, W_QP, (size_t)nqpad * mpad);
+    float *base = wsp<float>(cx, W_BASE, nqpad);
+    wsp<float>(cx, W_T, nqpad);
+    wsp<float>(cx, W_THR, nqpad);
+    int32_t *kq = wsp<int32_t>(cx, W_KQ, nqpad);
+    int32_t *home = wsp<int32_t>(cx, W_HOME, nqpad);
+    unsigned long long *counters = wsp<unsigned long long>(cx, W_COUNTERS, 8);
     k::fill_u32(reinterpret_cast<uint32_t *>(counters), 16, 0u, st);
     if (nq > 0) {
         GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
@@ -408,15 +417,14 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         if (Q->location == GTS_HOST)
             for (int64_t i = 0; i < nq * d.dim; i++)
                 GTS_CHECK(std::isfinite(Q->vecs[i]), GTS_EINVAL, "non-finite query value");
-        float *Q32 = wsp<float>(idx, W_Q32, (size_t)nqpad * d.dp);
+        float *Q32 = wsp<float>(cx, W_Q32, (size_t)nqpad * d.dp);
         GTS_HIP(hipMemsetAsync(Q32, 0, (size_t)nqpad * d.dp * sizeof(float), st));
-        GTS_HIP(hipMemcpy2DAsync(Q32, d.dp * sizeof(float), Q->vecs, d.dim * sizeof(float), d.dim * sizeof(float), nq,
-                                 in_kind, st));
-        uint16_t *Q16 = wsp<uint16_t>(idx, W_Q16, (size_t)nqpad * d.ksteps * 32);
-        float *qn = wsp<float>(idx, W_QN, nqpad);
-        float *qerr = wsp<float>(idx, W_QE, nqpad);
+        rows_to_device(Q32, d.dp, Q->vecs, d.dim, nq, Q->location == GTS_DEVICE, st);
+        uint16_t *Q16 = wsp<uint16_t>(cx, W_Q16, (size_t)nqpad * d.ksteps * 32);
+        float *qn = wsp<float>(cx, W_QN, nqpad);
+        float *qerr = wsp<float>(cx, W_QE, nqpad);
         k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, Q16, qn, qerr, 0.f, st);
-        k::dist_l2_pivots(Q32, nq, d.P32.as<float>(), d.m, mpad, d.dp, idx->ws[W_QP].as<float>(), 1, mpad, st);
+        k::dist_l2_pivots(Q32, nq, d.P32.as<float>(), d.m, mpad, d.dp, cx->ws[W_QP].as<float>(), 1, mpad, st);
         qv = k::QueryL2{Q32, Q16, qn, qerr};
     } else if (nq > 0) {
         GTS_CHECK(Q->offsets != nullptr, GTS_EINVAL, "null query offsets");
@@ -431,19 +439,19 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             qlen[q] = (int32_t)len;
             b.max_qlen = std::max(b.max_qlen, (int)len);
         }
-        uint8_t *qc = wsp<uint8_t>(idx, W_QCHARS, std::max<int64_t>(hoff[nq], 1));
+        uint8_t *qc = wsp<uint8_t>(cx, W_QCHARS, std::max<int64_t>(hoff[nq], 1));
         if (hoff[nq]) {
             GTS_CHECK(Q->chars != nullptr, GTS_EINVAL, "null query bytes");
             GTS_HIP(hipMemcpyAsync(qc, Q->chars, hoff[nq], in_kind, st));
         }
-        int64_t *qo = wsp<int64_t>(idx, W_QOFF, nqpad + 1);
+        int64_t *qo = wsp<int64_t>(cx, W_QOFF, nqpad + 1);
         GTS_HIP(hipMemcpyAsync(qo, hoff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        int32_t *ql = wsp<int32_t>(idx, W_QLEN, nqpad);
+        int32_t *ql = wsp<int32_t>(cx, W_QLEN, nqpad);
         GTS_HIP(hipMemcpyAsync(ql, qlen.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        uint64_t *peq = wsp<uint64_t>(idx, W_PEQ, (size_t)nqpad * idx->arows * 4);
+        uint64_t *peq = wsp<uint64_t>(cx, W_PEQ, (size_t)nqpad * idx->arows * 4);
         k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, peq, st);
         k::dist_edit_pivots_f32(qc, qo, nq, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, mpad,
-                                idx->ws[W_QP].as<float>(), 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
+                                cx->ws[W_QP].as<float>(), 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
         qe = k::QueryEdit{qc, qo, peq};
         GTS_HIP(hipStreamSynchronize(st));
     }
@@ -459,35 +467,46 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     int32_t *near = nullptr;
     std::vector<int32_t> perm;   // position i of the batch holds caller query perm[i]
     bool permuted = false;
+    // Edit distance (batched): the kNN bound, the thresholds and the cell test
+    // run in the caller's order; a query's home is its first passing cell, and
+    // the cell masks follow the queries into the grouped order.
+    const bool edit_cells = !l2 && b.mode == GTS_MODE_BATCHED && d.n_centres > 0 && nq > 0;
+    const float delta = (float)((d.dim + 8) * 5.9604645e-8);
+    k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
+                   d.cell_len.as<int32_t>(), d.n_centres};
+    uint64_t *cmask0 = nullptr;
+    if (edit_cells) {
+        if (b.any_knn)
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+        k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
+                      cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
+        cmask0 = wsp<uint64_t>(cx, W_CMASK0, (size_t)d.n_centres * ntiles_all);
+        k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
+                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, cmask0, counters, st);
+    }
     if (nq > 1) {
         std::vector<int32_t> hh(nq);
         if (l2 && d.lpad > 0) {
-            near = wsp<int32_t>(idx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
+            near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
             k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
             std::vector<int32_t> hn((size_t)nq * k::kNearLeaves);
             GTS_HIP(hipMemcpyAsync(hn.data(), near, hn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
             for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
-        } else if (!l2 && d.n_centres > 0) {
-            uint64_t *best = wsp<uint64_t>(idx, W_NEARC, nq);
-            k::fill_u32(reinterpret_cast<uint32_t *>(best), 2 * nq, 0xffffffffu, st);
-            k::near_centre_edit(d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.n_centres, qe,
-                                idx->ws[W_QLEN].as<int32_t>(), idx->arows, idx->lut.as<uint8_t>(), nq, b.max_qlen,
-                                reinterpret_cast<unsigned long long *>(best), st);
-            std::vector<uint64_t> hb(nq);
-            GTS_HIP(hipMemcpyAsync(hb.data(), best, nq * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        } else if (edit_cells) {
+            k::first_cell(cmask0, d.n_centres, nq, home, st);
+            GTS_HIP(hipMemcpyAsync(hh.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
-            for (int64_t q = 0; q < nq; q++) hh[q] = (int32_t)(uint32_t)hb[q];
         }
         perm.resize(nq);
         for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
-        if (l2 ? d.lpad > 0 : true) {
+        if (l2 ? d.lpad > 0 : edit_cells) {
             std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hh[x] < hh[y]; });
             for (int64_t q = 0; q < nq && !permuted; q++) permuted = perm[q] != q;
         }
     }
     if (permuted) {
-        int32_t *dperm = wsp<int32_t>(idx, W_PERM, nq);
+        int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
         GTS_HIP(hipMemcpyAsync(dperm, perm.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         std::vector<float> pb(nq);
         std::vector<int32_t> pk(nq);
@@ -497,10 +516,17 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         }
         hbase.swap(pb);
         hk.swap(pk);
-        GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
+        if (edit_cells && b.any_knn) {
+            // the kNN bounds are already in `base`: permute them on the device
+            float *tb = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, 1));
+            k::gather_rows(base, dperm, nq, 1, tb, st);
+            GTS_HIP(hipMemcpyAsync(base, tb, nq * sizeof(float), hipMemcpyDeviceToDevice, st));
+        } else {
+            GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
+        }
         GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        float *QPd = idx->ws[W_QP].as<float>();
-        float *tmpf = wsp<float>(idx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
+        float *QPd = cx->ws[W_QP].as<float>();
+        float *tmpf = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
         k::gather_rows(QPd, dperm, nq, mpad, tmpf, st);
         GTS_HIP(hipMemcpyAsync(QPd, tmpf, (size_t)nq * mpad * sizeof(float), hipMemcpyDeviceToDevice, st));
         if (l2) {
@@ -510,7 +536,7 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
             k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
                          const_cast<float *>(qv.qn), const_cast<float *>(qv.qe), 0.f, st);
             if (near) {
-                int32_t *tmpi = wsp<int32_t>(idx, W_TMP2, (size_t)nq * k::kNearLeaves);
+                int32_t *tmpi = wsp<int32_t>(cx, W_TMP2, (size_t)nq * k::kNearLeaves);
                 k::gather_i32(near, dperm, nq, k::kNearLeaves, tmpi, st);
                 GTS_HIP(hipMemcpyAsync(near, tmpi, (size_t)nq * k::kNearLeaves * sizeof(int32_t),
                                        hipMemcpyDeviceToDevice, st));
@@ -526,27 +552,35 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
                 nlen[i] = (int32_t)(hoff[perm[i] + 1] - hoff[perm[i]]);
                 noff[i + 1] = noff[i] + nlen[i];
             }
-            uint8_t *nc = wsp<uint8_t>(idx, W_TMP2, std::max<int64_t>(noff[nq], 1));
-            int64_t *no = reinterpret_cast<int64_t *>(wsp<float>(idx, W_TMP, (size_t)2 * (nq + 1)));
+            uint8_t *nc = wsp<uint8_t>(cx, W_TMP2, std::max<int64_t>(noff[nq], 1));
+            int64_t *no = reinterpret_cast<int64_t *>(wsp<float>(cx, W_TMP, (size_t)2 * (nq + 1)));
             GTS_HIP(hipMemcpyAsync(no, noff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
             k::gather_strings(qe.chars, qe.off, dperm, nq, no, nc, st);
             uint8_t *qc = const_cast<uint8_t *>(qe.chars);
             int64_t *qo = const_cast<int64_t *>(qe.off);
             GTS_HIP(hipMemcpyAsync(qc, nc, std::max<int64_t>(noff[nq], 1), hipMemcpyDeviceToDevice, st));
             GTS_HIP(hipMemcpyAsync(qo, no, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-            GTS_HIP(hipMemcpyAsync(idx->ws[W_QLEN].as<int32_t>(), nlen.data(), nq * sizeof(int32_t),
+            GTS_HIP(hipMemcpyAsync(cx->ws[W_QLEN].as<int32_t>(), nlen.data(), nq * sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
             k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, const_cast<uint64_t *>(qe.peq), st);
             GTS_HIP(hipStreamSynchronize(st));
         }
     }
-    rec(idx, 1);
+    if (edit_cells) {
+        uint64_t *cm = wsp<uint64_t>(cx, W_CMASK, (size_t)d.n_centres * ntiles_all);
+        if (permuted)
+            k::cell_mask_permute(cmask0, cx->ws[W_PERM].as<int32_t>(), d.n_centres, nq, cm, st);
+        else
+            GTS_HIP(hipMemcpyAsync(cm, cmask0, (size_t)d.n_centres * ntiles_all * sizeof(uint64_t),
+                                   hipMemcpyDeviceToDevice, st));
+    }
+    rec(cx, 1);
 
     // ---- kNN bound ------------------------------------------------------------------
-    if (nq > 0 && b.any_knn) {
+    if (nq > 0 && b.any_knn && !edit_cells) {
         if (l2 && d.lpad > 0) {
             if (!near) {
-                near = wsp<int32_t>(idx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
+                near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
                 k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
             }
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
@@ -554,23 +588,22 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
-            k::bound_l2(tv, ov, qv, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+            k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         } else {
-            k::bound_edit(tv, oe, qe, idx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         }
     }
-    const float delta = (float)((d.dim + 8) * 5.9604645e-8);
     if (nq > 0)
-        k::thresholds(base, idx->ws[W_QP].as<float>(), kq, nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
-                      idx->ws[W_T].as<float>(), idx->ws[W_THR].as<float>(), wsp<float>(idx, W_CUT, nqpad), st);
-    if (l2) k::sum_pad(idx->ws[W_T].as<float>(), qv.qe, nq, nqpad, wsp<float>(idx, W_TQE, nqpad), st);
-    rec(idx, 2);
-    if (idx->timing && nq > 0) {
+        k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
+                      cx->ws[W_T].as<float>(), cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
+    if (l2) k::sum_pad(cx->ws[W_T].as<float>(), qv.qe, nq, nqpad, wsp<float>(cx, W_TQE, nqpad), st);
+    rec(cx, 2);
+    if (cx->timing && nq > 0) {
         GTS_HIP(hipStreamSynchronize(st));
         float ms;
-        GTS_HIP(hipEventElapsedTime(&ms, idx->ev[0], idx->ev[1]));
+        GTS_HIP(hipEventElapsedTime(&ms, cx->ev[0], cx->ev[1]));
         stage_ms[GTS_STAGE_PREP] += ms;
-        GTS_HIP(hipEventElapsedTime(&ms, idx->ev[1], idx->ev[2]));
+        GTS_HIP(hipEventElapsedTime(&ms, cx->ev[1], cx->ev[2]));
         stage_ms[GTS_STAGE_BOUND] += ms;
     }
 
@@ -586,15 +619,15 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         auto [q0, ng] = todo.front();
         todo.erase(todo.begin());
         GroupOut go;
-        if (run_group(idx, b, q0, ng, cap, &go, stage_ms)) {
+        if (run_group(idx, cx, b, q0, ng, cap, &go, stage_ms)) {
             groups.push_back(std::move(go));
             continue;
         }
-        // split into halves of whole 16-query blocks (the bf16 fragment unit)
-        const int64_t blocks = (ng + 15) / 16;
+        // split into halves of whole 64-query tiles
+        const int64_t blocks = (ng + kQTile - 1) / kQTile;
         GTS_CHECK(blocks > 1, GTS_ENOMEM,
-                  "the memory budget cannot hold the candidates of 16 queries; raise mem_budget_bytes");
-        const int64_t half = (blocks / 2) * 16;
+                  "the memory budget cannot hold the candidates of 64 queries; raise mem_budget_bytes");
+        const int64_t half = (blocks / 2) * kQTile;
         todo.insert(todo.begin(), {q0 + half, ng - half});
         todo.insert(todo.begin(), {q0, half});
     }
@@ -641,8 +674,8 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
         fail(GTS_ENOMEM, "result allocation failed");
     }
     // assemble on the device in batch order, un-permute, then place the result
-    int64_t *ids_b = wsp<int64_t>(idx, W_RES_IDS, std::max<int64_t>(total, 1));
-    uint32_t *dist_b = wsp<uint32_t>(idx, W_RES_DIST, std::max<int64_t>(total, 1));
+    int64_t *ids_b = wsp<int64_t>(cx, W_RES_IDS, std::max<int64_t>(total, 1));
+    uint32_t *dist_b = wsp<uint32_t>(cx, W_RES_DIST, std::max<int64_t>(total, 1));
     int64_t at = 0;
     for (auto &g : groups) {
         if (g.total) {
@@ -654,12 +687,12 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     int64_t *ids_c = ids_b;
     uint32_t *dist_c = dist_b;
     if (permuted && total > 0) {
-        ids_c = wsp<int64_t>(idx, W_RES_IDS2, total);
-        dist_c = wsp<uint32_t>(idx, W_RES_DIST2, total);
-        int64_t *doff = wsp<int64_t>(idx, W_OFF_ORIG, 2 * (nq + 1));
+        ids_c = wsp<int64_t>(cx, W_RES_IDS2, total);
+        dist_c = wsp<uint32_t>(cx, W_RES_DIST2, total);
+        int64_t *doff = wsp<int64_t>(cx, W_OFF_ORIG, 2 * (nq + 1));
         GTS_HIP(hipMemcpyAsync(doff, offs_b.data(), off_bytes, hipMemcpyHostToDevice, st));
         GTS_HIP(hipMemcpyAsync(doff + nq + 1, offs.data(), off_bytes, hipMemcpyHostToDevice, st));
-        k::unpermute(doff, doff + nq + 1, idx->ws[W_PERM].as<int32_t>(), nq, ids_b, dist_b, ids_c, dist_c, st);
+        k::unpermute(doff, doff + nq + 1, cx->ws[W_PERM].as<int32_t>(), nq, ids_b, dist_b, ids_c, dist_c, st);
     }
     const hipMemcpyKind to = priv->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     GTS_HIP(hipMemcpyAsync(priv->offsets, offs.data(), off_bytes,
@@ -679,14 +712,14 @@ void search(gts_index *idx, const gts_objects *Q, const float *radius, const int
     // ---- counters ----------------------------------------------------------------------
     unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     GTS_HIP(hipMemcpy(hc, counters, sizeof(hc), hipMemcpyDeviceToHost));
-    idx->stats.node_tests = (int64_t)hc[0];
-    if (idx->stats.leaf_pairs == 0) idx->stats.leaf_pairs = (int64_t)hc[1];
-    idx->stats.tile_pairs = (int64_t)hc[2];
-    idx->stats.verified = (int64_t)hc[3];
-    idx->stats.results = total;
-    for (int i = 0; i < 8; i++) idx->stats.ms_stage[i] = stage_ms[i];
-    idx->stats.groups = (int64_t)groups.size();
-    idx->stats.ms_total = now_ms() - t_start;
+    cx->stats.node_tests = (int64_t)hc[0];
+    if (cx->stats.leaf_pairs == 0) cx->stats.leaf_pairs = (int64_t)hc[1];
+    cx->stats.tile_pairs = (int64_t)hc[2];
+    cx->stats.verified = (int64_t)hc[3];
+    cx->stats.results = total;
+    for (int i = 0; i < 8; i++) cx->stats.ms_stage[i] = stage_ms[i];
+    cx->stats.groups = (int64_t)groups.size();
+    cx->stats.ms_total = now_ms() - t_start;
 }
 
 void free_result(gts_result *r)

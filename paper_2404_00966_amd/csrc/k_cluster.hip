@@ -1,5 +1,5 @@
 // Build-time clustering that orders the objects before they are cut into
-// leaves, and the query-side lookup of the nearest cluster centre.
+// leaves.
 //
 // The centres come from farthest-first traversal (the selection rule the
 // method uses for pivots, Sec. 4.1, run to many more centres): centre j + 1 is
@@ -136,84 +136,6 @@ void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const
     for (int j = 0; j < K; j++)
         hipLaunchKernelGGL(k_fft_step_edit, dim3(grid), dim3(256), 0, st, chars, off, n, lut, arows, j, keys,
                            centers, mind, near);
-    check_launch(__func__);
-}
-
-// ---------------------------------------------------------------------------
-// Nearest centre of each query string (edit distance): workgroup = (64-query
-// tile, chunk of kCentreChunk centres), lane = query (the Myers pattern, its
-// table in global memory), the centre string the common text staged as codes
-// in LDS.  The running best of the lane is the early-exit cutoff; the result
-// is merged per query with a 64-bit atomic min of (distance << 32 | centre).
-// ---------------------------------------------------------------------------
-constexpr int kCentreChunk = 128;
-
-template <int W>
-__global__ __launch_bounds__(256) void k_near_centre_edit(const uint8_t *__restrict__ cchars,
-                                                          const int32_t *__restrict__ coff, int K, QueryEdit qv,
-                                                          const int32_t *__restrict__ qlen, int rows,
-                                                          const uint8_t *__restrict__ lut_g, int64_t nq, int ntiles,
-                                                          unsigned long long *__restrict__ best)
-{
-    __shared__ uint8_t s_code[4][256];
-    __shared__ uint8_t s_lut[256];
-    const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
-    const int tile = (int)(blockIdx.x % ntiles);
-    const int chunk = (int)(blockIdx.x / ntiles);
-    const int64_t q = (int64_t)tile * 64 + lane;
-    const bool qok = q < nq;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = lut_g[i];
-    __syncthreads();
-    const int plen = qok ? qlen[q] : 0;
-    const uint64_t *tab = qv.peq + (size_t)(qok ? q : 0) * rows * 4;
-    int bd = 1 << 30, bc = 0;
-    for (int ci = wave; ci < kCentreChunk; ci += 4) {
-        const int c = chunk * kCentreChunk + ci;
-        if (c >= K) break;
-        const int s0 = coff[c];
-        const int tl = coff[c + 1] - s0;
-        for (int b = lane; b < tl; b += 64) s_code[wave][b] = s_lut[cchars[s0 + b]];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (qok && abs(plen - tl) < bd) {
-            struct G {
-                const uint64_t *t;
-                __device__ __forceinline__ uint64_t operator[](int i) const { return t[i]; }
-            };
-            struct I {
-                __device__ __forceinline__ int operator[](int x) const { return x; }
-            };
-            const int d = dev::myers_distance<W>(G{tab}, plen, s_code[wave], tl, bd - 1, I{});
-            if (d < bd) {
-                bd = d;
-                bc = c;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    if (qok && bd < (1 << 30))
-        atomicMin(best + q, ((unsigned long long)(uint32_t)bd << 32) | (unsigned long long)(uint32_t)bc);
-}
-
-void near_centre_edit(const uint8_t *cchars, const int32_t *coff, int K, const QueryEdit &qv, const int32_t *qlen,
-                      int rows, const uint8_t *lut, int64_t nq, int max_qlen, unsigned long long *best,
-                      hipStream_t st)
-{
-    if (nq == 0 || K == 0) return;
-    const int ntiles = (int)((nq + 63) / 64);
-    const int chunks = (K + kCentreChunk - 1) / kCentreChunk;
-    const unsigned grid = (unsigned)((int64_t)chunks * ntiles);
-    const int W = std::max(1, (max_qlen + 63) / 64);
-#define NC(WW)                                                                                                  \
-    hipLaunchKernelGGL(k_near_centre_edit<WW>, dim3(grid), dim3(256), 0, st, cchars, coff, K, qv, qlen, rows, lut, \
-                       nq, ntiles, best)
-    switch (W) {
-    case 1: NC(1); break;
-    case 2: NC(2); break;
-    case 3: NC(3); break;
-    default: NC(4); break;
-    }
-#undef NC
     check_launch(__func__);
 }
 

@@ -154,7 +154,7 @@ template <int W, int MP, bool TAB>
 __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
                                                         const float *__restrict__ QP, const float *__restrict__ T,
                                                         int64_t nq, int ntiles, CellView cv,
-                                                        uint64_t *__restrict__ cell_mask,
+                                                        uint64_t *__restrict__ cell_mask, int64_t cm_stride,
                                                         unsigned long long *__restrict__ counters)
 {
     extern __shared__ uint64_t s_tab[];
@@ -194,18 +194,23 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
             pass = false;
         }
         const uint64_t m = dev::ballot(pass);
-        if (lane == 0) cell_mask[(size_t)c * ntiles + tile] = m;
+        if (lane == 0) cell_mask[(size_t)c * cm_stride + tile] = m;
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) tests += __shfl_xor(tests, o2, 64);
     if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
 }
 
+// Leaves are reached from the cells that passed: workgroup = (tile, chunk of
+// cells), a wave takes its passing cells one at a time and tests the leaves
+// the cell overlaps.  A leaf that spans several cells is tested once, by the
+// first of its cells that passed (its mask is the union over its cells).
 template <int W, bool TAB>
 __global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
                                                         const int32_t *__restrict__ leaf_first,
                                                         const float *__restrict__ leafR,
-                                                        const int32_t *__restrict__ leaf_cell, int64_t n_leaves,
-                                                        const uint64_t *__restrict__ cell_mask,
+                                                        const int32_t *__restrict__ leaf_cell,
+                                                        const int32_t *__restrict__ cell_leaf, int64_t n_cells,
+                                                        const uint64_t *__restrict__ cell_mask, int64_t cm_stride,
                                                         const float *__restrict__ T, int64_t nq, int ntiles,
                                                         uint64_t *__restrict__ leaf_mask, int32_t *__restrict__ items,
                                                         uint32_t *__restrict__ item_count, int64_t item_cap)
@@ -224,26 +229,28 @@ __global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv
     const int plen = qok ? qlen[q] : 0;
     const int tq = qok ? (int)T[q] : -1;
     const uint64_t *gtab = qv.peq + (size_t)(qok ? q : 0) * o.rows * 4;
-    for (int64_t li = wave; li < kBallChunk; li += 4) {
-        const int64_t leaf = chunk * kBallChunk + li;
-        if (leaf >= n_leaves) break;
-        uint64_t m = 0;
-        for (int c = leaf_cell[2 * leaf]; c <= leaf_cell[2 * leaf + 1]; c++) m |= cell_mask[(size_t)c * ntiles + tile];
-        const float R = leafR[leaf];
-        if (m != 0ull && R >= 0.f) {
+    for (int64_t ci = wave; ci < kBallChunk; ci += 4) {
+        const int64_t c = chunk * kBallChunk + ci;
+        if (c >= n_cells) break;
+        if (cell_mask[(size_t)c * cm_stride + tile] == 0ull) continue;
+        for (int leaf = cell_leaf[2 * c]; leaf <= cell_leaf[2 * c + 1]; leaf++) {
+            const int c0 = leaf_cell[2 * leaf], c1 = leaf_cell[2 * leaf + 1];
+            bool owner = true;
+            for (int e = c0; e < c; e++) owner = owner && cell_mask[(size_t)e * cm_stride + tile] == 0ull;
+            if (!owner) continue;
+            uint64_t m = 0;
+            for (int e = c; e <= c1; e++) m |= cell_mask[(size_t)e * cm_stride + tile];
+            const float R = leafR[leaf];
+            if (R < 0.f) continue;
             const int32_t s0 = o.soff[leaf_first[leaf]];
             const int tl = o.soff[leaf_first[leaf] + 1] - s0;
             m = dev::ballot(ball_pass<W, TAB>((m >> lane) & 1ull, o.chars, s0, tl, plen, tq + (int)R, s_code[wave],
                                               s_lut, s_tab, gtab, lane));
-        } else {
-            m = 0;
-        }
-        if (lane == 0) {
-            leaf_mask[(size_t)leaf * ntiles + tile] = m;
-            if (m) {
+            if (lane == 0 && m) {
+                leaf_mask[(size_t)leaf * ntiles + tile] = m;
                 const uint32_t idx = atomicAdd(item_count, 1u);
                 if (idx < item_cap) {
-                    items[2 * (size_t)idx] = (int32_t)leaf;
+                    items[2 * (size_t)idx] = leaf;
                     items[2 * (size_t)idx + 1] = tile;
                 }
             }
@@ -251,11 +258,68 @@ __global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv
     }
 }
 
+// home[q] = the first cell (in chain order) that passed for query q, or
+// n_cells when none did.  One workgroup per tile; threads stride over cells.
+__global__ __launch_bounds__(256) void k_first_cell(const uint64_t *__restrict__ cell_mask, int64_t n_cells,
+                                                    int ntiles, int64_t nq, int32_t *__restrict__ home)
+{
+    __shared__ int s_home[64];
+    const int tile = blockIdx.x;
+    if (threadIdx.x < 64) s_home[threadIdx.x] = (int)n_cells;
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < n_cells; c += blockDim.x) {
+        uint64_t w = cell_mask[(size_t)c * ntiles + tile];
+        while (w) {
+            const int j = __ffsll((unsigned long long)w) - 1;
+            w &= w - 1;
+            atomicMin(&s_home[j], (int)c);
+        }
+    }
+    __syncthreads();
+    const int64_t q = (int64_t)tile * 64 + threadIdx.x;
+    if (threadIdx.x < 64 && q < nq) home[q] = s_home[threadIdx.x];
+}
+
+// Cell masks in a new query order: query perm[i] of the old order is query i
+// of the new one.  dst is zeroed first; one thread per query.
+__global__ void k_cell_mask_permute(const uint64_t *__restrict__ src, const int32_t *__restrict__ perm,
+                                    int64_t n_cells, int ntiles, int64_t nq, unsigned long long *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int64_t qo = perm[i];
+    const int to = (int)(qo >> 6), bo = (int)(qo & 63);
+    const int tn = (int)(i >> 6);
+    const unsigned long long bit = 1ull << (i & 63);
+    for (int64_t c = 0; c < n_cells; c++)
+        if ((src[(size_t)c * ntiles + to] >> bo) & 1ull) atomicOr(dst + (size_t)c * ntiles + tn, bit);
+}
+
+void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t *home, hipStream_t st)
+{
+    if (nq == 0) return;
+    const int ntiles = (int)((nq + 63) / 64);
+    hipLaunchKernelGGL(k_first_cell, dim3(ntiles), dim3(256), 0, st, cell_mask, n_cells, ntiles, nq, home);
+    check_launch(__func__);
+}
+
+void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells, int64_t nq, uint64_t *dst,
+                       hipStream_t st)
+{
+    if (nq == 0) return;
+    const int ntiles = (int)((nq + 63) / 64);
+    fill_u32(reinterpret_cast<uint32_t *>(dst), n_cells * ntiles * 2, 0u, st);
+    hipLaunchKernelGGL(k_cell_mask_permute, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, src, perm,
+                       n_cells, ntiles, nq, reinterpret_cast<unsigned long long *>(dst));
+    check_launch(__func__);
+}
+
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int ntiles, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
                     unsigned long long *counters, hipStream_t st)
 {
     if (nq == 0 || cv.n == 0) return;
+    const int ntiles = (int)((nq + 63) / 64);
     const int W = std::max(1, (max_qlen + 63) / 64);
     const int64_t chunks = (cv.n + kBallChunk - 1) / kBallChunk;
     const unsigned grid = (unsigned)(chunks * ntiles);
@@ -263,7 +327,7 @@ void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define CT(WW, MP, TB)                                                                                            \
     hipLaunchKernelGGL((k_edit_cell_test<WW, MP, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, QP, T, nq,    \
-                       ntiles, cv, cell_mask, counters)
+                       ntiles, cv, cell_mask, (int64_t)ntiles, counters)
 #define CTM(WW, TB)                 \
     if (mpad == 8) CT(WW, 8, TB);   \
     else if (mpad == 16) CT(WW, 16, TB); \
@@ -283,19 +347,21 @@ void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
 }
 
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
-                    const float *leafR, const int32_t *leaf_cell, int64_t n_leaves, const uint64_t *cell_mask,
-                    const float *T, int64_t nq, int ntiles, int max_qlen, uint64_t *leaf_mask, int32_t *items,
-                    uint32_t *item_count, int64_t item_cap, hipStream_t st)
+                    const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
+                    const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
+                    int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
+                    hipStream_t st)
 {
-    if (nq == 0 || n_leaves == 0) return;
+    if (nq == 0 || n_cells == 0) return;
     const int W = std::max(1, (max_qlen + 63) / 64);
-    const int64_t chunks = (n_leaves + kBallChunk - 1) / kBallChunk;
+    const int64_t chunks = (n_cells + kBallChunk - 1) / kBallChunk;
     const unsigned grid = (unsigned)(chunks * ntiles);
     const bool tab = (int64_t)o.rows * W * 64 <= kTileTabWords;
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define EB(WW, TB)                                                                                                  \
     hipLaunchKernelGGL((k_edit_leaf_ball<WW, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, leaf_first, leafR, \
-                       leaf_cell, n_leaves, cell_mask, T, nq, ntiles, leaf_mask, items, item_count, item_cap)
+                       leaf_cell, cell_leaf, n_cells, cell_mask, cm_stride, T, nq, ntiles, leaf_mask, items,      \
+                       item_count, item_cap)
 #define EBW(TB)               \
     switch (W) {              \
     case 1: EB(1, TB); break; \

@@ -252,10 +252,12 @@ void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const
 // ---------------------------------------------------------------------------
 // bf16 MFMA slab distances (L2 verification, first pass).
 //
-// Work unit: one slab of 256 consecutive tree positions against a chunk of
-// query tiles.  Each of the 4 waves keeps 64 objects (4 row blocks of 16)
-// as MFMA A fragments in registers for the whole unit; query tiles (64
-// queries = 4 column blocks of 16) stream through as B fragments.  With
+// Work item: one slab of 256 consecutive tree positions against a list of
+// up to kItemTiles of its active query tiles (made by a pre-pass, so the
+// persistent sweep never scans inactive tiles).  Each of the 4 waves keeps 64
+// objects (4 row blocks of 16) as MFMA A fragments in registers for the whole
+// item; query tiles (64 queries = 4 column blocks of 16) stream through LDS
+// as B fragments, the next one copied while the current one computes.  With
 // v_mfma_f32_16x16x32_bf16, lane l of the output holds objects 4*(l/16)+e
 // (e = 0..3) of a row block and query l%16 of a column block.
 //
@@ -291,14 +293,70 @@ __device__ __forceinline__ void lds_dma4(const void *src, void *lds_wave_base)
     __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_wave_base, 4, 0, 0);
 }
 
+// Pre-pass: the active query tiles of every slab (some query of the tile
+// survives a leaf overlapping the slab) with the tile's union mask, written
+// as (tile, mask) pairs, and work items of at most kItemTiles pairs of one
+// slab.  One workgroup per slab: count, reserve with one atomic, then fill.
+constexpr int kItemTiles = kSweepItemTiles;
+
+__global__ __launch_bounds__(256) void k_slab_items(const int32_t *__restrict__ slab_leaf_lo,
+                                                    const int32_t *__restrict__ slab_leaf_hi, int64_t n_slabs,
+                                                    const uint64_t *__restrict__ leaf_mask, int ntiles,
+                                                    int32_t *__restrict__ pair_tile, uint64_t *__restrict__ pair_mask,
+                                                    uint32_t *__restrict__ pair_count, int4 *__restrict__ items,
+                                                    uint32_t *__restrict__ item_count)
+{
+    __shared__ int s_cnt[4];
+    __shared__ uint32_t s_base, s_fill;
+    const int64_t slab = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
+    auto tile_mask = [&](int t) {
+        uint64_t m = 0;
+        for (int l = l_lo; l <= l_hi; l++) m |= leaf_mask[(size_t)l * ntiles + t];
+        return m;
+    };
+    int cnt = 0;
+    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+        const int t = t0 + (int)threadIdx.x;
+        cnt += __popcll(dev::ballot(t < ntiles && tile_mask(t) != 0ull));
+    }
+    if (lane == 0) s_cnt[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int total = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        s_base = total ? atomicAdd(pair_count, (uint32_t)total) : 0u;
+        s_fill = 0;
+        const int nit = (total + kItemTiles - 1) / kItemTiles;
+        if (nit) {
+            const uint32_t i0 = atomicAdd(item_count, (uint32_t)nit);
+            for (int k = 0; k < nit; k++)
+                items[i0 + k] = make_int4((int)slab, (int)s_base + k * kItemTiles, min(kItemTiles, total - k * kItemTiles), 0);
+        }
+    }
+    __syncthreads();
+    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+        const int t = t0 + (int)threadIdx.x;
+        const uint64_t m = t < ntiles ? tile_mask(t) : 0ull;
+        const uint64_t b = dev::ballot(m != 0ull);
+        uint32_t at = 0;
+        if (lane == 0 && b) at = atomicAdd(&s_fill, (uint32_t)__popcll(b));
+        at = __shfl(at, 0, 64);
+        if (m) {
+            const uint32_t idx = s_base + at + (uint32_t)dev::lanes_below(b);
+            pair_tile[idx] = t;
+            pair_mask[idx] = m;
+        }
+    }
+}
+
 template <int KS, int RT>
 __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     const uint4 *__restrict__ X16t, const float *__restrict__ xn, const uint4 *__restrict__ Q16t,
-    const float *__restrict__ qn, const float *__restrict__ tqe, int64_t nq,
-    int ntiles, const float *__restrict__ slab_emax, const float *__restrict__ slab_nmax,
-    const int32_t *__restrict__ slab_leaf_lo, const int32_t *__restrict__ slab_leaf_hi,
-    const uint64_t *__restrict__ leaf_mask, int64_t n, const uint32_t *__restrict__ tomb, int64_t n_items,
-    int chunk, int nchunks, uint32_t *__restrict__ work, Cand *__restrict__ cands,
+    const float *__restrict__ qn, const float *__restrict__ tqe, int64_t nq, const float *__restrict__ slab_emax,
+    const float *__restrict__ slab_nmax, int64_t n, const uint32_t *__restrict__ tomb,
+    const int32_t *__restrict__ pair_tile, const uint64_t *__restrict__ pair_mask, const int4 *__restrict__ items,
+    const uint32_t *__restrict__ item_count, uint32_t *__restrict__ work, Cand *__restrict__ cands,
     uint32_t *__restrict__ cand_count, int64_t cand_cap, float eps_a, float eps_b, float eps_c,
     unsigned long long *__restrict__ counters)
 {
@@ -306,21 +364,37 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     constexpr int kSlabRows = 4 * kRowsPerWave;
     constexpr int kTileFrag = 4 * KS * 64;           // uint4 fragments of one 64-query tile
     constexpr int kPer = kTileFrag / 256;            // fragments staged per thread
+    constexpr int kCandBuf = 256;                    // per-wave candidate buffer
     // LDS: two staging buffers of one query tile (B fragments, T + e_q and
-    // ||q16||^2 per query), and the item's list of active tiles with masks
+    // ||q16||^2 per query) and a candidate buffer per wave
     __shared__ uint4 s_b[2][kTileFrag];
     __shared__ float s_t[2][64], s_qn[2][64];
-    __shared__ int32_t s_tile[64];
-    __shared__ uint64_t s_tmask[64];
-    __shared__ int s_item, s_ntile;
+    __shared__ Cand s_cand[4][kCandBuf];
+    __shared__ int4 s_item;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15;
     const int rgrp = lane >> 4;
+    const int64_t n_items = *item_count;
     int64_t cur_slab = -1;
     uint4 A[RT][KS];
     float xr[RT][4];
     long long units = 0;
+    Cand *cbuf = s_cand[wave];
+    int nb = 0;   // buffered candidates of this wave (wave-uniform)
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)nb);
+        base = __shfl(base, 0, 64);
+        for (int i = lane; i < nb; i += 64) {
+            const int64_t idx = (int64_t)base + i;
+            if (idx < cand_cap) cands[idx] = cbuf[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        nb = 0;
+    };
     // stage query tile t into buffer b: every wave copies kPer 1 KB runs of
     // fragments; waves 0 and 1 copy the two 256-byte parameter rows
     auto stage = [&](int t, int b) {
@@ -333,33 +407,15 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     };
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = (int)atomicAdd(work, 1u);
-            s_ntile = 0;
+            const uint32_t it = atomicAdd(work, 1u);
+            s_item = it < n_items ? items[it] : make_int4(-1, 0, 0, 0);
         }
         __syncthreads();
-        const int64_t item = s_item;
-        if (item >= n_items) break;
-        const int64_t slab = item / nchunks;
-        const int ch = (int)(item % nchunks);
+        const int4 item = s_item;
+        if (item.x < 0) break;
+        const int64_t slab = item.x;
+        const int p0 = item.y, ntl = item.z;
         const int64_t row0 = slab * kSlabRows + wave * kRowsPerWave;
-        const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
-        const int t0 = ch * chunk;
-        const int t1 = min(ntiles, t0 + chunk);
-        // active tiles of this chunk (some query of the tile survives a leaf
-        // of the slab): thread i checks tile t0 + i, a wave ballot compacts them
-        if (threadIdx.x < 64) {
-            const int t = t0 + (int)threadIdx.x;
-            uint64_t mask = 0;
-            if (t < t1)
-                for (int l = l_lo; l <= l_hi; l++) mask |= leaf_mask[(size_t)l * ntiles + t];
-            const uint64_t b = dev::ballot(mask != 0);
-            if (mask) {
-                const int slot = dev::lanes_below(b);
-                s_tile[slot] = t;
-                s_tmask[slot] = mask;
-            }
-            if (threadIdx.x == 0) s_ntile = __popcll(b);
-        }
         if (slab != cur_slab) {
             cur_slab = slab;
             const int64_t g0 = row0 >> 4;
@@ -372,19 +428,16 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
 #pragma unroll
                 for (int e = 0; e < 4; e++) xr[r][e] = xn[row0 + 16 * r + 4 * rgrp + e];
         }
-        __syncthreads();
-        const int ntl = s_ntile;
-        if (ntl == 0) continue;
         const float emax = slab_emax[slab];
         const float nmax = slab_nmax[slab];
-        stage(s_tile[0], 0);
+        stage(pair_tile[p0], 0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         for (int it = 0; it < ntl; it++) {
             const int buf = it & 1;
-            const int t = s_tile[it];
-            const uint64_t mask = s_tmask[it];
-            if (it + 1 < ntl) stage(s_tile[it + 1], buf ^ 1);   // lands while this tile computes
+            const int t = pair_tile[p0 + it];
+            const uint64_t mask = pair_mask[p0 + it];
+            if (it + 1 < ntl) stage(pair_tile[p0 + it + 1], buf ^ 1);   // lands while this tile computes
 #pragma unroll 1
             for (int c = 0; c < 4; c++) {
                 const uint32_t cm = (uint32_t)(mask >> (16 * c)) & 0xffffu;
@@ -419,7 +472,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                     for (int e = 0; e < 4; e++)
                         pm |= (fmaf(-2.f, acc[r][e], xr[r][e]) <= th ? 1u : 0u) << (4 * r + e);
                 if (dev::ballot(pm != 0)) {
-                    // drop padding rows and deleted objects, then compact
+                    // drop padding rows and deleted objects, then compact into
+                    // the wave's buffer (flushed with one atomic when full)
 #pragma unroll
                     for (int r = 0; r < RT; r++)
 #pragma unroll
@@ -433,51 +487,74 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                     const int cnt = __popc(pm);
                     int tot;
                     const int off = dev::wave_excl_scan(cnt, &tot);
-                    uint32_t base = 0;
-                    if (lane == 0 && tot) base = atomicAdd(cand_count, (uint32_t)tot);
-                    base = __shfl(base, 0, 64);
-                    int j = 0;
+                    if (nb + tot > kCandBuf) flush();
+                    if (tot > kCandBuf) {
+                        // more than a buffer at once (at most 64 x 16): direct
+                        uint32_t base = 0;
+                        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)tot);
+                        base = __shfl(base, 0, 64);
+                        int j = 0;
 #pragma unroll
-                    for (int r = 0; r < RT; r++)
+                        for (int r = 0; r < RT; r++)
 #pragma unroll
-                        for (int e = 0; e < 4; e++) {
-                            if ((pm >> (4 * r + e)) & 1u) {
-                                const int64_t idx = (int64_t)base + off + j;
-                                j++;
-                                if (idx < cand_cap) {
+                            for (int e = 0; e < 4; e++)
+                                if ((pm >> (4 * r + e)) & 1u) {
+                                    const int64_t idx = (int64_t)base + off + j++;
+                                    if (idx < cand_cap) {
+                                        Cand cd;
+                                        cd.q = (int32_t)q;
+                                        cd.pos = (int32_t)(row0 + 16 * r + 4 * rgrp + e);
+                                        cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], xr[r][e]) + qnn);
+                                        cands[idx] = cd;
+                                    }
+                                }
+                    } else {
+                        int j = 0;
+#pragma unroll
+                        for (int r = 0; r < RT; r++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                if ((pm >> (4 * r + e)) & 1u) {
                                     Cand cd;
                                     cd.q = (int32_t)q;
                                     cd.pos = (int32_t)(row0 + 16 * r + 4 * rgrp + e);
                                     cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], xr[r][e]) + qnn);
-                                    cands[idx] = cd;
+                                    cbuf[nb + off + j++] = cd;
                                 }
-                            }
-                        }
+                        nb += tot;
+                    }
                 }
             }
             __builtin_amdgcn_s_waitcnt(0);   // the next tile's copies have landed
             __syncthreads();
         }
     }
-    if (threadIdx.x % 64 == 0 && units) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)units);
+    if (nb) flush();
+    if (lane == 0 && units) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)units);
+}
+
+void slab_items(const SlabView &s, const uint64_t *leaf_mask, int ntiles, const SweepWork &w, hipStream_t st)
+{
+    fill_u32(w.counts, 3, 0u, st);   // pairs, items, work
+    if (s.n_slabs == 0 || ntiles == 0) return;
+    hipLaunchKernelGGL(k_slab_items, dim3((unsigned)s.n_slabs), dim3(256), 0, st, s.leaf_lo, s.leaf_hi, s.n_slabs,
+                       leaf_mask, ntiles, w.pair_tile, w.pair_mask, w.counts + 0, w.items, w.counts + 1);
+    check_launch(__func__);
 }
 
 void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
-                const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
-                uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
-                hipStream_t st)
+                const uint32_t *tomb, const SweepWork &w, Cand *cands, uint32_t *cand_count, int64_t cand_cap,
+                unsigned long long *counters, int grid_blocks, hipStream_t st)
 {
     if (nq == 0 || s.n_slabs == 0) return;
-    const int nchunks = (ntiles + chunk - 1) / chunk;
-    const int64_t n_items = s.n_slabs * nchunks;
     const float u = 5.9604645e-8f;  // 2^-24
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
-#define MS(KS)                                                                                                  \
-    hipLaunchKernelGGL((k_mfma_sweep<KS, kRowTiles>), dim3((unsigned)grid_blocks), dim3(256), 0, st,                         \
-                       reinterpret_cast<const uint4 *>(o.X16t), o.xn, reinterpret_cast<const uint4 *>(qv.Q16t), \
-                       qv.qn, tqe, nq, ntiles, s.emax, s.nmax, s.leaf_lo, s.leaf_hi, leaf_mask, o.n, tomb,      \
-                       n_items, chunk, nchunks, work, cands, cand_count, cand_cap, eps_a, eps_b, eps_c, counters)
+#define MS(KS)                                                                                                    \
+    hipLaunchKernelGGL((k_mfma_sweep<KS, kRowTiles>), dim3((unsigned)grid_blocks), dim3(256), 0, st,                \
+                       reinterpret_cast<const uint4 *>(o.X16t), o.xn, reinterpret_cast<const uint4 *>(qv.Q16t),   \
+                       qv.qn, tqe, nq, s.emax, s.nmax, o.n, tomb, w.pair_tile, w.pair_mask, w.items, w.counts + 1, \
+                       w.counts + 2, cands, cand_count, cand_cap, eps_a, eps_b, eps_c, counters)
     switch (o.ksteps) {
     case 1: MS(1); break;
     case 2: MS(2); break;
@@ -493,8 +570,12 @@ void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const flo
 // per pair, lane = query.  Each object of the leaf is tested against every
 // surviving query of the tile with the length bound | |q| - |o| | <= d(q,o)
 // and Lemma 1 on every pivot (its row of the AoS pivot table is uniform
-// across the wave); passing lanes are compacted with a ballot.
+// across the wave); passing lanes are compacted with a ballot into a per-wave
+// LDS buffer, which is flushed with one atomic reservation when full and at
+// the end (one atomic per kObjBuf candidates instead of one per object).
 // ---------------------------------------------------------------------------
+constexpr int kObjBuf = 512;
+
 template <int MP>
 __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restrict__ items,
                                                         const uint32_t *__restrict__ item_count, int64_t item_cap,
@@ -508,15 +589,38 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
                                                         const uint32_t *__restrict__ tomb, Cand *__restrict__ cands,
                                                         uint32_t *__restrict__ cand_count, int64_t cand_cap)
 {
+    __shared__ int2 s_buf[4][kObjBuf];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    int2 *buf = s_buf[wave];
+    int nb = 0;   // buffered candidates (wave-uniform)
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)nb);
+        base = __shfl(base, 0, 64);
+        for (int i = lane; i < nb; i += 64) {
+            const int64_t idx = (int64_t)base + i;
+            if (idx < cand_cap) {
+                const int2 e = buf[i];
+                Cand cd;
+                cd.q = e.x;
+                cd.pos = e.y;
+                cd.val = 0;
+                cands[idx] = cd;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        nb = 0;
+    };
     int64_t nitems = *item_count;
     if (nitems > item_cap) nitems = item_cap;
     for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < nitems; it += (int64_t)gridDim.x * 4) {
         const int leaf = items[2 * it];
         const int tile = items[2 * it + 1];
         const uint64_t mask = leaf_mask[(size_t)leaf * ntiles + tile];
-        if (mask == 0ull) continue;   // every query pruned by the leaf test
+        if (mask == 0ull) continue;
         const int64_t q = (int64_t)tile * 64 + lane;
         const bool act = ((mask >> lane) & 1ull) && q < nq;
         int qp[MP];
@@ -541,21 +645,13 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
             for (int i = 0; i < MP; i++) pass = pass && abs(qp[i] - (int)row[i]) <= th;
             const uint64_t b = dev::ballot(pass);
             if (!b) continue;
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(cand_count, (uint32_t)__popcll(b));
-            base = __shfl(base, 0, 64);
-            if (pass) {
-                const int64_t idx = (int64_t)base + dev::lanes_below(b);
-                if (idx < cand_cap) {
-                    Cand cd;
-                    cd.q = (int32_t)q;
-                    cd.pos = p;
-                    cd.val = 0;
-                    cands[idx] = cd;
-                }
-            }
+            const int c = __popcll(b);
+            if (nb + c > kObjBuf) flush();
+            if (pass) buf[nb + dev::lanes_below(b)] = make_int2((int)q, p);
+            nb += c;
         }
     }
+    if (nb) flush();
 }
 
 void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,

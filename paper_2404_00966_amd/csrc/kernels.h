@@ -101,10 +101,21 @@ struct SlabView {
 };
 // tqe[q] = T[q] + e_q (true-distance bound plus the query's bf16 error),
 // -inf on padding rows; valid for whole 64-query tiles.
+// Sweep workspace: (tile, mask) pairs of active (slab, tile) combinations,
+// capacity n_slabs * ntiles; items (slab, first pair, count, -), capacity
+// n_slabs * ceil(ntiles / kItemTiles); counts[3] (pairs, items, work cursor).
+constexpr int kSweepItemTiles = 32;
+struct SweepWork {
+    int32_t *pair_tile;
+    uint64_t *pair_mask;
+    int4 *items;
+    uint32_t *counts;
+};
+// The sweep's work list from the leaf masks (resets w.counts).
+void slab_items(const SlabView &s, const uint64_t *leaf_mask, int ntiles, const SweepWork &w, hipStream_t st);
 void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
-                const uint64_t *leaf_mask, const uint32_t *tomb, int chunk, uint32_t *work, Cand *cands,
-                uint32_t *cand_count, int64_t cand_cap, unsigned long long *counters, int grid_blocks,
-                hipStream_t st);
+                const uint32_t *tomb, const SweepWork &w, Cand *cands, uint32_t *cand_count, int64_t cand_cap,
+                unsigned long long *counters, int grid_blocks, hipStream_t st);
 
 // Edit-distance object filtering over (leaf, tile) items: length and pivot
 // lower bounds, wave-ballot compaction into candidates.
@@ -131,11 +142,6 @@ void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, in
                     int32_t *near, hipStream_t st);
 void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const uint8_t *lut, int arows, int K,
                       uint64_t *keys, int32_t *centers, float *mind, int32_t *near, hipStream_t st);
-// Nearest centre of each query string: best[q] (preset to all ones) becomes
-// min over centres c of (d(q, c) << 32 | c).
-void near_centre_edit(const uint8_t *cchars, const int32_t *coff, int K, const QueryEdit &qv, const int32_t *qlen,
-                      int rows, const uint8_t *lut, int64_t nq, int max_qlen, unsigned long long *best,
-                      hipStream_t st);
 // Cells (the clusters that order the leaves, in chain order): centre
 // strings, covering radius, box over the global pivot distances and the
 // string-length range of each.
@@ -147,18 +153,26 @@ struct CellView {
     const int32_t *len;        // [n][2]: shortest and longest member
     int64_t n;
 };
-// Cell test (Lemma 1 with each centre and with the global pivots): writes
-// cell_mask[cell][tile], the tile's queries that the cell may answer.
+// Cell test (Lemma 1 with each centre and with the global pivots) for nq
+// queries in tiles of 64: writes cell_mask[cell][tile], the tile's queries
+// that the cell may answer.
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int ntiles, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
                     unsigned long long *counters, hipStream_t st);
+// First passing cell of each query (n_cells when none passed).
+void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t *home, hipStream_t st);
+// Cell masks in a new query order (query perm[i] becomes query i).
+void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells, int64_t nq, uint64_t *dst,
+                       hipStream_t st);
 // Leaf test (Lemma 1 with each leaf's first object as its pivot) on the
-// union of the leaf's cells' masks: writes leaf_mask[leaf][tile] for every
-// pair and appends the nonzero pairs to items.
+// leaves of the cells that passed, with the union of the leaf's cells' masks
+// (cell_mask rows of cm_stride words, the group's first tile at column 0):
+// writes leaf_mask[leaf][tile] and the list of nonzero (leaf, tile) pairs.
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
-                    const float *leafR, const int32_t *leaf_cell, int64_t n_leaves, const uint64_t *cell_mask,
-                    const float *T, int64_t nq, int ntiles, int max_qlen, uint64_t *leaf_mask, int32_t *items,
-                    uint32_t *item_count, int64_t item_cap, hipStream_t st);
+                    const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
+                    const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
+                    int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
+                    hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);

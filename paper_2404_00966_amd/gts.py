@@ -66,9 +66,38 @@ class _Info(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+REQ_RANGE, REQ_KNN, REQ_INSERT, REQ_DELETE = 1, 2, 3, 4
+
+
+class _Request(C.Structure):
+    _fields_ = [("index", C.c_int32), ("kind", C.c_int32), ("objects", _Objects), ("radius", C.c_float),
+                ("k", C.c_int32), ("ids", C.c_void_p), ("n_ids", C.c_int64), ("tag", C.c_uint64)]
+
+
+class _Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("tag", C.c_uint64), ("kind", C.c_int32), ("status", C.c_int32),
+                ("error", C.c_char_p), ("result", _Result), ("new_ids", C.c_void_p), ("count", C.c_int64),
+                ("batch", C.c_int64), ("t_submit_ms", C.c_double), ("t_start_ms", C.c_double),
+                ("t_done_ms", C.c_double), ("priv", C.c_void_p)]
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("lanes_per_index", C.c_int32), ("max_batch_queries", C.c_int32),
+                ("mem_budget_bytes", C.c_int64), ("keep_results", C.c_int32)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queries", C.c_int64), ("batches", C.c_int64), ("updates", C.c_int64),
+                ("mean_batch_queries", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("span_ms", C.c_double)]
+
+
 EXPORTS = ("gts_build_index", "gts_range_query", "gts_knn_query", "gts_search", "gts_insert", "gts_delete",
            "gts_result_copy", "gts_result_free", "gts_destroy", "gts_get_info", "gts_get_stats",
-           "gts_set_timing", "gts_last_error")
+           "gts_set_timing", "gts_last_error", "gts_server_create", "gts_server_submit", "gts_server_replay",
+           "gts_server_poll", "gts_server_release", "gts_server_flush", "gts_server_get_stats",
+           "gts_server_destroy")
 
 _lib = None
 
@@ -94,6 +123,14 @@ def library():
         L.gts_get_info.argtypes = [C.c_void_p, P(_Info)]
         L.gts_get_stats.argtypes = [C.c_void_p, P(_Stats)]
         L.gts_set_timing.argtypes = [C.c_void_p, C.c_int32]
+        L.gts_server_create.argtypes = [C.c_void_p, C.c_int32, P(_ServerOpts), P(C.c_void_p)]
+        L.gts_server_submit.argtypes = [C.c_void_p, P(_Request), P(C.c_uint64)]
+        L.gts_server_replay.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.gts_server_poll.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, P(C.c_int32)]
+        L.gts_server_release.argtypes = [P(_Completion)]
+        L.gts_server_flush.argtypes = [C.c_void_p]
+        L.gts_server_get_stats.argtypes = [C.c_void_p, P(_ServerStats)]
+        L.gts_server_destroy.argtypes = [C.c_void_p]
         L.gts_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "gts_last_error":
@@ -257,3 +294,115 @@ class Index:
 
     def set_timing(self, on=True):
         _check(library().gts_set_timing(self._h, 1 if on else 0))
+
+
+class Server:
+    """Continuous-batching server over built indexes (include/gts.h,
+    gts_server_*).  Requests: ("range", index_no, queries, r),
+    ("knn", index_no, queries, k), ("insert", index_no, objects),
+    ("delete", index_no, ids).  Completions come back as dicts with host
+    numpy answers; a query request's answers are a list of (ids, dist) per
+    query of the request."""
+
+    def __init__(self, indexes, lanes_per_index=2, max_batch_queries=16384, mem_budget_bytes=0,
+                 keep_results=True):
+        L = library()
+        self._indexes = list(indexes)
+        self._metrics = [ix.metric for ix in self._indexes]
+        arr = (C.c_void_p * len(self._indexes))(*[ix._h.value for ix in self._indexes])
+        opts = _ServerOpts(lanes_per_index, max_batch_queries, mem_budget_bytes, 1 if keep_results else 0)
+        h = C.c_void_p()
+        _check(L.gts_server_create(arr, len(self._indexes), C.byref(opts), C.byref(h)))
+        self._h = h
+
+    def _request(self, req, keep):
+        kind, index_no = req[0], req[1]
+        r = _Request()
+        r.index = index_no
+        # an index number out of range is the library's to reject
+        metric = self._metrics[index_no] if 0 <= index_no < len(self._metrics) else self._metrics[0]
+        if kind == "range":
+            r.kind, r.objects, r.radius = REQ_RANGE, _objects(req[2], metric, keep), float(req[3])
+        elif kind == "knn":
+            r.kind, r.objects, r.k = REQ_KNN, _objects(req[2], metric, keep), int(req[3])
+        elif kind == "insert":
+            r.kind, r.objects = REQ_INSERT, _objects(req[2], metric, keep)
+        elif kind == "delete":
+            a = np.ascontiguousarray(np.asarray(req[2], np.int64).reshape(-1))
+            keep.append(a)
+            r.kind, r.ids, r.n_ids = REQ_DELETE, (a.ctypes.data if a.size else None), a.size
+        else:
+            raise ValueError(f"unknown request kind {kind!r}")
+        r.tag = int(req[4]) if len(req) > 4 else 0
+        return r
+
+    def submit(self, req):
+        """Queue one request tuple; returns its ticket."""
+        keep = _Keep()
+        r = self._request(req, keep)
+        t = C.c_uint64(0)
+        _check(library().gts_server_submit(self._h, C.byref(r), C.byref(t)))
+        return t.value
+
+    def replay(self, reqs, arrival_ms):
+        """Open-loop replay: submit reqs[i] at arrival_ms[i] after the call
+        starts (the library sleeps between submissions).  Returns tickets."""
+        keep = _Keep()
+        arr = (_Request * len(reqs))(*[self._request(q, keep) for q in reqs])
+        t = np.ascontiguousarray(np.asarray(arrival_ms, np.float64))
+        tickets = np.zeros(max(len(reqs), 1), np.uint64)
+        _check(library().gts_server_replay(self._h, C.addressof(arr), t.ctypes.data, len(reqs),
+                                           tickets.ctypes.data))
+        return tickets[:len(reqs)]
+
+    def poll(self, max_items=256, wait_ms=-1):
+        """Take up to max_items completions (wait_ms < 0: until one is ready
+        or nothing is pending)."""
+        L = library()
+        buf = (_Completion * max_items)()
+        n = C.c_int32(0)
+        _check(L.gts_server_poll(self._h, C.addressof(buf), max_items, wait_ms, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            d = {"ticket": c.ticket, "tag": c.tag, "kind": c.kind, "status": c.status,
+                 "error": (c.error or b"").decode(), "batch": c.batch, "count": c.count,
+                 "t_submit_ms": c.t_submit_ms, "t_start_ms": c.t_start_ms, "t_done_ms": c.t_done_ms}
+            if c.status == OK and c.kind in (REQ_RANGE, REQ_KNN):
+                res = c.result
+                nq = res.nq
+                off = np.ctypeslib.as_array(C.cast(res.offsets, C.POINTER(C.c_int64)), (nq + 1,)).copy()
+                tot = int(res.total)
+                ids = np.ctypeslib.as_array(C.cast(res.ids, C.POINTER(C.c_int64)), (tot,)).copy() if tot else \
+                    np.zeros(0, np.int64)
+                if res.metric == L2_F32:
+                    dist = np.ctypeslib.as_array(C.cast(res.dist_f32, C.POINTER(C.c_float)), (tot,)).copy() \
+                        if tot else np.zeros(0, np.float32)
+                else:
+                    dist = np.ctypeslib.as_array(C.cast(res.dist_i32, C.POINTER(C.c_int32)), (tot,)).copy() \
+                        if tot else np.zeros(0, np.int32)
+                d["answers"] = [(ids[off[q]:off[q + 1]], dist[off[q]:off[q + 1]]) for q in range(nq)]
+            if c.status == OK and c.kind == REQ_INSERT and c.count:
+                d["new_ids"] = np.ctypeslib.as_array(C.cast(c.new_ids, C.POINTER(C.c_int64)), (c.count,)).copy()
+            L.gts_server_release(C.byref(c))
+            out.append(d)
+        return out
+
+    def flush(self):
+        _check(library().gts_server_flush(self._h))
+
+    def stats(self):
+        s = _ServerStats()
+        _check(library().gts_server_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().gts_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

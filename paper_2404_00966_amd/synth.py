@@ -184,6 +184,34 @@ WORKLOADS = {
 }
 
 
+# Serving mix: an L2 index and a DNA index served together under an
+# open-loop request trace.  Query pools and insert pools are fresh draws of the
+# same distributions (held-out rows of the mixture, held-out mutants).
+SERVING = {
+    "serve_l2_2m_d128": dict(kind="l2", seed=966005, n=2_000_000, dim=128, components=100, lo=-5.0, hi=5.0,
+                             sigma=1.0, query_pool=20_000, insert_pool=400_000, pivots=16, fanout=16, leaf=256),
+    "serve_dna_200k": dict(kind="dna", seed=966006, n_seeds=400, per_seed=500, min_len=64, max_len=128,
+                           rate=0.05, queries_per_seed=110, query_pool=4_000, pivots=8, fanout=8, leaf=0),
+}
+
+
+def make_serving(name: str):
+    """Objects, a query pool and an insert pool of a serving index."""
+    w = dict(SERVING[name])
+    if w["kind"] == "l2":
+        d = gaussian_mixture(w["seed"], w["n"] + w["insert_pool"], w["dim"], w["components"], w["lo"], w["hi"],
+                             w["sigma"], w["query_pool"], 0)
+        w.update(objects=d["objects"][:w["n"]], inserts=d["objects"][w["n"]:], queries=d["range_queries"])
+        return w
+    d = dna_families(w["seed"], w["n_seeds"], w["per_seed"], w["min_len"], w["max_len"], w["rate"],
+                     w["queries_per_seed"])
+    qc, qo = d["queries"]
+    k = w["query_pool"]
+    w.update(objects=d["objects"], queries=(qc[:qo[k]].copy(), qo[:k + 1].copy()),
+             inserts=(qc[qo[k]:].copy(), (qo[k:] - qo[k]).copy()))
+    return w
+
+
 def make_workload(name: str, scale: float = 1.0, queries: int | None = None):
     """Draw a named workload.  ``scale`` < 1 shrinks the object count (and the
     family count for DNA) for quick tests; ``queries`` keeps only that many

@@ -66,3 +66,37 @@ def test_dna_500k_full_batch_sampled():
     sc, so = synth.strings_from_bytes(items)
     ref = O.range_bf(O.ObjectSet(strings=(chars, off)), O.ObjectSet(strings=(sc, so)), float(w["radius"]))
     check_exact([res[i] for i in sel], ref)
+
+
+def test_l2_4m_d96_knn_bf16_sampled():
+    """4M x 96, 50,000 kNN queries (k = 32) through the bf16 MFMA path with
+    float32 rechecks: sampled queries against the float64 oracle, the largest
+    relative distance error over every returned pair of the sample, and the
+    float32 plain path on the same sample."""
+    import torch
+
+    from paper_2404_00966_amd import gts
+
+    w = synth.WORKLOADS["l2_4m_d96"]
+    d = synth.make_workload("l2_4m_d96")
+    X = d["objects"]
+    KQ = d["knn_queries"]
+    print("[case] l2_4m_d96 knn batch", flush=True)
+    idx = gts.Index(torch.from_numpy(X).cuda(), gts.L2_F32, num_pivots=w["pivots"], fanout=w["fanout"],
+                    leaf_size=w["leaf"], seed=w["seed"])
+    res = idx.knn(torch.from_numpy(KQ).cuda(), w["k"]).to_lists()
+    assert len(res) == len(KQ) and all(len(ids) == w["k"] for ids, _ in res)
+    rng = np.random.default_rng(2)
+    ks = rng.choice(len(KQ), SAMPLE, replace=False)
+    sample = [res[i] for i in ks]
+    check_knn(sample, O.knn_bf(O.ObjectSet(vecs=X), O.ObjectSet(vecs=KQ[ks]), w["k"]), X, KQ[ks], w["k"])
+    worst = 0.0
+    for (ids, dist), q in zip(sample, KQ[ks]):
+        exact = np.sqrt(((X[ids].astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1))
+        worst = max(worst, float(np.max(np.abs(dist.astype(np.float64) - exact) / np.maximum(exact, 1e-30))))
+    print(f"[metric] l2_4m_d96 max relative distance error vs float64: {worst:.3e}", flush=True)
+    assert worst <= 1e-5
+    plain = idx.knn(torch.from_numpy(KQ[ks]).cuda(), w["k"], mode=gts.MODE_PLAIN).to_lists()
+    idx.close()
+    for (a, b), (c, e) in zip(sample, plain):
+        assert np.array_equal(a, c) and np.array_equal(b, e)

@@ -136,6 +136,57 @@ def test_edit_edge_strings(gts):
     idx.close()
 
 
+def test_edit_alphabet_growth_and_foreign_bytes(gts):
+    """Query bytes absent from the index match nothing; bytes first seen in
+    an insert join the alphabet (cache scan, then the rebuilt tree)."""
+    rng = np.random.default_rng(7)
+    base = [bytes(rng.choice(list(b"ACGT"), int(rng.integers(0, 60))).tolist()) for _ in range(400)]
+    extra = [b"ACGN" * 5, b"NNNN", b"Z" + b"ACGT" * 3, bytes(range(1, 60)), b"ACGTNACGTN"]
+    q_items = [b"ACGN", b"NNNZ", b"\xff\xfeACG", b"ACGTACGT", bytes(range(1, 50)), b"", b"ZACGTACG"] + base[:70]
+    qc, qo = synth.strings_from_bytes(q_items)
+    qs = O.ObjectSet(strings=(qc, qo))
+    _say("edit_alphabet")
+    idx = gts.Index(synth.strings_from_bytes(base), gts.EDIT_U8, num_pivots=4, fanout=4, cache_limit=6, seed=3)
+    new_ids = idx.insert(synth.strings_from_bytes(extra))           # stays in the cache list
+    assert list(new_ids) == list(range(400, 405))
+    for step in ("cache", "rebuilt"):
+        items = base + extra
+        objs = O.ObjectSet(strings=synth.strings_from_bytes(items))
+        for mode in MODES:
+            for r in (0, 2, 6, 20):
+                check_exact(idx.range((qc, qo), float(r), mode=_mode(gts, mode), result="host").to_lists(),
+                            O.range_bf(objs, qs, float(r)))
+            for k in (1, 5, 30):
+                check_exact(idx.knn((qc, qo), k, mode=_mode(gts, mode), result="host").to_lists(),
+                            O.knn_bf(objs, qs, k))
+        if step == "cache":
+            more = [b"NNZZ", b"ACGTZ" * 4]
+            idx.insert(synth.strings_from_bytes(more))                 # past the limit: rebuild
+            extra = extra + more
+            assert idx.info()["rebuilds"] == 1
+    idx.close()
+
+
+def test_edit_full_byte_alphabet(gts):
+    """Every byte value occurs: the widest match tables (257 rows)."""
+    rng = np.random.default_rng(8)
+    items = [bytes(rng.integers(0, 256, int(rng.integers(0, 120))).astype(np.uint8).tolist()) for _ in range(600)]
+    items += [bytes(range(0, 255)), bytes(range(1, 256))]
+    q_items = [bytes(bytearray(s[:100])[::-1]) for s in items[:40]] + [items[5], items[-1], b"\x00" * 10]
+    chars, off = synth.strings_from_bytes(items)
+    qc, qo = synth.strings_from_bytes(q_items)
+    objs, qs = O.ObjectSet(strings=(chars, off)), O.ObjectSet(strings=(qc, qo))
+    _say("edit_full_alphabet")
+    idx = gts.Index((_dev(chars), _dev(off)), gts.EDIT_U8, num_pivots=5, fanout=4, seed=5)
+    for mode in MODES:
+        for r in (0, 3, 60, 130):
+            check_exact(idx.range((_dev(qc), _dev(qo)), float(r), mode=_mode(gts, mode)).to_lists(),
+                        O.range_bf(objs, qs, float(r)))
+        for k in (1, 7):
+            check_exact(idx.knn((_dev(qc), _dev(qo)), k, mode=_mode(gts, mode)).to_lists(), O.knn_bf(objs, qs, k))
+    idx.close()
+
+
 def _live_set_l2(X, ids_all, live_ids):
     rows = {int(i): r for r, i in enumerate(ids_all)}
     sel = [rows[i] for i in sorted(live_ids)]
@@ -212,7 +263,7 @@ def test_two_stage_budget_gives_same_answers(gts):
     assert idx.stats()["groups"] == 1
     cands = idx.stats()["candidates"]
     # a budget for about a third of the batch's candidates: several groups run
-    # one after another, each of whole 16-query blocks
+    # one after another, each of whole 64-query tiles
     small = idx.search(_dev(Q), radius=radius, k=k, mem_budget_bytes=40 * (cands // 3)).to_lists()
     assert idx.stats()["groups"] > 1
     for (a, b), (c, e) in zip(big, small):

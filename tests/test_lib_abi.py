@@ -52,3 +52,34 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(gts._QueryOpts) == 16
     assert ctypes.sizeof(gts._Result) == 64
     assert ctypes.sizeof(gts._Stats) == 7 * 8 + 8 + 64 + 8
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every ctypes mirror has the size and field offsets that a C compiler
+    gives the header's struct (gcc on the header itself)."""
+    import shutil
+    import subprocess
+
+    from paper_2404_00966_amd import gts
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"gts_objects": gts._Objects, "gts_build_opts": gts._BuildOpts, "gts_query_opts": gts._QueryOpts,
+               "gts_result": gts._Result, "gts_stats": gts._Stats, "gts_index_info": gts._Info,
+               "gts_request": gts._Request, "gts_completion": gts._Completion,
+               "gts_server_opts": gts._ServerOpts, "gts_server_stats": gts._ServerStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gts.h"', "int main(void) {"]
+    expect = []
+    for cname, cls in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+            expect.append(getattr(cls, f).offset)
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
