@@ -205,8 +205,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         int32_t *items = nullptr;
         const int64_t item_cap = t.n_leaves * ntiles;
         if (l2) {
-            k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)t.n_leaves * ntiles * 2, 0u, st);
-            k::node_filter(tv, QP, thr, ng, ntiles, mask, items, small + 1, item_cap, counters, st);
+            k::leaf_box(tv, QP, thr, ng, ntiles, mask, counters, st);
         } else {
             // leaves of the cells that passed (cell masks of the whole batch,
             // this group's tiles from column q0 / 64), then the item list
@@ -215,7 +214,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             const int32_t *qlen = cx->ws[W_QLEN].as<int32_t>() + q0;
             k::edit_leaf_ball(oe, qe, qlen, t.leaf_first.as<int32_t>(), d.leafR.as<float>(), d.leaf_cell.as<int32_t>(),
                               d.cell_leaf.as<int32_t>(), d.n_centres, cmask, b.ntiles_all, T, ng, ntiles, b.max_qlen,
-                              mask, items, small + 1, item_cap, st);
+                              mask, items, small + 1, item_cap, t.n_leaves, st);
         }
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,

@@ -6,9 +6,9 @@
 //
 //   k_leaf_radius_edit : R_L at build time, one wave per leaf
 //   k_edit_cell_test   : the cell test for every (64-query tile, cell)
-//   k_edit_leaf_ball   : the leaf test for every (64-query tile, leaf) whose
-//                        cells passed; writes the leaf masks and the list of
-//                        (leaf, tile) pairs that object filtering walks
+//   k_edit_leaf_query  : the leaf test for every (query, leaf of a cell that
+//                        passed for it); writes the leaf masks and the list
+//                        of (leaf, tile) pairs that object filtering walks
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -200,58 +200,71 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
     if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
 }
 
-// Leaves are reached from the cells that passed: workgroup = (tile, chunk of
-// cells), a wave takes its passing cells one at a time and tests the leaves
-// the cell overlaps.  A leaf that spans several cells is tested once, by the
-// first of its cells that passed (its mask is the union over its cells).
-template <int W, bool TAB>
-__global__ __launch_bounds__(256) void k_edit_leaf_ball(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
-                                                        const int32_t *__restrict__ leaf_first,
-                                                        const float *__restrict__ leafR,
-                                                        const int32_t *__restrict__ leaf_cell,
-                                                        const int32_t *__restrict__ cell_leaf, int64_t n_cells,
-                                                        const uint64_t *__restrict__ cell_mask, int64_t cm_stride,
-                                                        const float *__restrict__ T, int64_t nq, int ntiles,
-                                                        uint64_t *__restrict__ leaf_mask, int32_t *__restrict__ items,
-                                                        uint32_t *__restrict__ item_count, int64_t item_cap)
+// Leaves are reached from the cells that passed, query by query: one wave per
+// query (its match table in LDS), lanes over the leaves of each cell that
+// passed for it, each lane scanning its leaf pivot as the text with the
+// cutoff T_q + R_L.  A leaf that spans several cells is tested from the first
+// of them that passed.  A passing (query, leaf) pair sets the query's bit in
+// leaf_mask[leaf][tile]; the first bit set in a word appends (leaf, tile) to
+// the item list (leaf_mask starts zeroed).
+template <int W>
+__global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
+                                                         const float *__restrict__ T,
+                                                         const int32_t *__restrict__ leaf_first,
+                                                         const float *__restrict__ leafR,
+                                                         const int32_t *__restrict__ leaf_cell,
+                                                         const int32_t *__restrict__ cell_leaf, int64_t n_cells,
+                                                         const uint64_t *__restrict__ cell_mask, int64_t cm_stride,
+                                                         int64_t nq, int ntiles,
+                                                         unsigned long long *__restrict__ leaf_mask,
+                                                         int32_t *__restrict__ items, uint32_t *__restrict__ item_count,
+                                                         int64_t item_cap)
 {
-    extern __shared__ uint64_t s_tab[];
-    __shared__ uint8_t s_code[4][256];
+    extern __shared__ uint64_t s_tabs[];   // 4 x rows x 4 words
     __shared__ uint8_t s_lut[256];
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
-    const int tile = (int)(blockIdx.x % ntiles);
-    const int64_t chunk = blockIdx.x / ntiles;
-    const int64_t q = (int64_t)tile * 64 + lane;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     const bool qok = q < nq;
+    uint64_t *tab = s_tabs + (size_t)wave * o.rows * 4;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
-    if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq);
+    if (qok)
+        for (int i = lane; i < o.rows * 4; i += 64) tab[i] = qv.peq[(size_t)q * o.rows * 4 + i];
     __syncthreads();
-    const int plen = qok ? qlen[q] : 0;
-    const int tq = qok ? (int)T[q] : -1;
-    const uint64_t *gtab = qv.peq + (size_t)(qok ? q : 0) * o.rows * 4;
-    for (int64_t ci = wave; ci < kBallChunk; ci += 4) {
-        const int64_t c = chunk * kBallChunk + ci;
-        if (c >= n_cells) break;
-        if (cell_mask[(size_t)c * cm_stride + tile] == 0ull) continue;
-        for (int leaf = cell_leaf[2 * c]; leaf <= cell_leaf[2 * c + 1]; leaf++) {
-            const int c0 = leaf_cell[2 * leaf], c1 = leaf_cell[2 * leaf + 1];
-            bool owner = true;
-            for (int e = c0; e < c; e++) owner = owner && cell_mask[(size_t)e * cm_stride + tile] == 0ull;
-            if (!owner) continue;
-            uint64_t m = 0;
-            for (int e = c; e <= c1; e++) m |= cell_mask[(size_t)e * cm_stride + tile];
-            const float R = leafR[leaf];
-            if (R < 0.f) continue;
-            const int32_t s0 = o.soff[leaf_first[leaf]];
-            const int tl = o.soff[leaf_first[leaf] + 1] - s0;
-            m = dev::ballot(ball_pass<W, TAB>((m >> lane) & 1ull, o.chars, s0, tl, plen, tq + (int)R, s_code[wave],
-                                              s_lut, s_tab, gtab, lane));
-            if (lane == 0 && m) {
-                leaf_mask[(size_t)leaf * ntiles + tile] = m;
-                const uint32_t idx = atomicAdd(item_count, 1u);
-                if (idx < item_cap) {
-                    items[2 * (size_t)idx] = leaf;
-                    items[2 * (size_t)idx + 1] = tile;
+    if (!qok) return;
+    const int plen = qlen[q];
+    const int tq = (int)T[q];
+    const int tile = (int)(q >> 6);
+    const uint64_t bit = 1ull << (q & 63);
+    auto passed = [&](int64_t c) { return (cell_mask[(size_t)c * cm_stride + tile] & bit) != 0ull; };
+    for (int64_t c0 = 0; c0 < n_cells; c0 += 64) {
+        uint64_t b = dev::ballot(c0 + lane < n_cells && passed(c0 + lane));
+        while (b) {
+            const int64_t c = c0 + __ffsll((unsigned long long)b) - 1;
+            b &= b - 1;
+            const int l_lo = cell_leaf[2 * c], l_hi = cell_leaf[2 * c + 1];
+            for (int l0 = l_lo; l0 <= l_hi; l0 += 64) {
+                const int leaf = l0 + lane;
+                bool ok = leaf <= l_hi;
+                if (ok)
+                    for (int e = leaf_cell[2 * leaf]; e < c; e++) ok = ok && !passed(e);
+                const float R = ok ? leafR[leaf] : -1.f;
+                ok = ok && R >= 0.f;
+                if (ok) {
+                    const int32_t s0 = o.soff[leaf_first[leaf]];
+                    const int tl = o.soff[leaf_first[leaf] + 1] - s0;
+                    const int cut = tq + (int)R;
+                    ok = abs(plen - tl) <= cut &&
+                         dev::myers_distance<W>(tab, plen, o.chars + s0, tl, cut, s_lut) <= cut;
+                }
+                if (ok) {
+                    const unsigned long long old = atomicOr(leaf_mask + (size_t)leaf * ntiles + tile, bit);
+                    if (old == 0ull) {
+                        const uint32_t idx = atomicAdd(item_count, 1u);
+                        if (idx < item_cap) {
+                            items[2 * (size_t)idx] = leaf;
+                            items[2 * (size_t)idx + 1] = tile;
+                        }
+                    }
                 }
             }
         }
@@ -350,28 +363,25 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
                     const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
                     const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
                     int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
-                    hipStream_t st)
+                    int64_t n_leaves, hipStream_t st)
 {
+    fill_u32(reinterpret_cast<uint32_t *>(leaf_mask), n_leaves * ntiles * 2, 0u, st);
     if (nq == 0 || n_cells == 0) return;
     const int W = std::max(1, (max_qlen + 63) / 64);
-    const int64_t chunks = (n_cells + kBallChunk - 1) / kBallChunk;
-    const unsigned grid = (unsigned)(chunks * ntiles);
-    const bool tab = (int64_t)o.rows * W * 64 <= kTileTabWords;
-    const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
-#define EB(WW, TB)                                                                                                  \
-    hipLaunchKernelGGL((k_edit_leaf_ball<WW, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, leaf_first, leafR, \
-                       leaf_cell, cell_leaf, n_cells, cell_mask, cm_stride, T, nq, ntiles, leaf_mask, items,      \
-                       item_count, item_cap)
-#define EBW(TB)               \
-    switch (W) {              \
-    case 1: EB(1, TB); break; \
-    case 2: EB(2, TB); break; \
-    case 3: EB(3, TB); break; \
-    default: EB(4, TB); break; \
+    const unsigned grid = (unsigned)((nq + 3) / 4);
+    const size_t shm = (size_t)4 * o.rows * 4 * sizeof(uint64_t);
+    auto *lm = reinterpret_cast<unsigned long long *>(leaf_mask);
+#define EQ(WW)                                                                                                 \
+    hipLaunchKernelGGL(k_edit_leaf_query<WW>, dim3(grid), dim3(256), shm, st, o, qv, qlen, T, leaf_first, leafR, \
+                       leaf_cell, cell_leaf, n_cells, cell_mask, cm_stride, nq, ntiles, lm, items, item_count,  \
+                       item_cap)
+    switch (W) {
+    case 1: EQ(1); break;
+    case 2: EQ(2); break;
+    case 3: EQ(3); break;
+    default: EQ(4); break;
     }
-    if (tab) EBW(true) else EBW(false)
-#undef EBW
-#undef EB
+#undef EQ
     check_launch(__func__);
 }
 

@@ -21,112 +21,62 @@ __device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Node filtering (Algorithms 4/5, the per-layer child test).  One wave per
-// (query tile, subtree rooted at level `split`); lane = query.  The tile's
-// surviving queries travel as a 64-bit lane mask, so a frontier element is
-// (node, mask); children are pushed on a per-wave LDS stack (depth-first keeps
-// the stack at most levels*(F-1)+1 deep).
+// Node filtering at leaf granularity (the child test of Algorithms 4/5 with
+// the global pivots, Lemma 1): a node's box contains the boxes of all its
+// descendants, so a leaf survives the walk from the root exactly when its
+// own box admits the query; testing every leaf directly prunes the same
+// (query, leaf) pairs without the level-by-level walk.  One wave per (64
+// leaves, query tile): lane = leaf, its box in registers; the tile's queries
+// stream through as wave-uniform pivot distances, each lane collecting its
+// 64-bit query mask.  Writes leaf_mask[leaf][tile] for every leaf and tile.
 // ---------------------------------------------------------------------------
-constexpr int kStack = 640;
-
 template <int MP>
-__global__ __launch_bounds__(256) void k_node_filter(const float *__restrict__ box, int F, int levels, int split,
-                                                     int64_t nsub, int64_t leaf0, const float *__restrict__ QP,
-                                                     const float *__restrict__ thr, int64_t nq, int ntiles,
-                                                     uint64_t *__restrict__ leaf_mask, int32_t *__restrict__ items,
-                                                     uint32_t *__restrict__ item_count, int64_t item_cap,
-                                                     unsigned long long *__restrict__ counters)
+__global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box, int64_t leaf0, int64_t n_leaves,
+                                                  const float *__restrict__ QP, const float *__restrict__ thr,
+                                                  int64_t nq, int ntiles, uint64_t *__restrict__ leaf_mask,
+                                                  unsigned long long *__restrict__ counters)
 {
-    __shared__ int32_t s_node[4][kStack];
-    __shared__ uint64_t s_mask[4][kStack];
-    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
-    if (gw >= (int64_t)ntiles * nsub) return;
-    const int tile = (int)(gw / nsub);
-    const int64_t sub = gw % nsub;
-    const int64_t q = (int64_t)tile * 64 + lane;
-    const bool act = q < nq;
-    float qp[MP];
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int tile = dev::uniform((int)(w % ntiles));
+    const int64_t lg = w / ntiles;
+    const int64_t leaf = lg * 64 + lane;
+    if (lg * 64 >= n_leaves) return;
+    float lo[MP], hi[MP];
+    const bool lok = leaf < n_leaves;
 #pragma unroll
-    for (int i = 0; i < MP; i++) qp[i] = act ? QP[(size_t)q * MP + i] : 0.f;
-    const float th = act ? thr[q] : 0.f;
-    uint64_t mask = dev::ballot(act);
-    long long tests = 0;
-
-    // ancestors of the subtree root, levels 1..split
-    int64_t first = 0, span = 1;
-    for (int l = 0; l < split; l++) span *= F;
-    int64_t node = 0;
-    for (int l = 1; l <= split && mask; l++) {
-        first = first * F + 1;
-        span /= F;
-        node = first + sub / span;
-        tests += __popcll(mask);
-        mask &= dev::ballot(box_gap<MP>(box, node, qp) <= th);
+    for (int i = 0; i < MP; i++) {
+        lo[i] = lok ? box[(size_t)(leaf0 + leaf) * 2 * MP + i] : INFINITY;
+        hi[i] = lok ? box[(size_t)(leaf0 + leaf) * 2 * MP + MP + i] : -INFINITY;
     }
-    if (split == 0) node = 0;
-    int sp = 0;
-    if (mask) {
-        s_node[wave][0] = (int32_t)node | (split << 27);
-        s_mask[wave][0] = mask;
-        sp = 1;
+    const int64_t q0 = (int64_t)tile * 64;
+    const int nt = (int)min<int64_t>(64, nq - q0);
+    uint64_t m = 0;
+    for (int j = 0; j < nt; j++) {
+        const float *qp = QP + (size_t)(q0 + j) * MP;
+        const float th = thr[q0 + j];
+        float g = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(lo[i] - qp[i], qp[i] - hi[i]));
+        m |= (g <= th ? 1ull : 0ull) << j;
     }
-    while (sp > 0) {
-        sp--;
-        const int32_t packed = s_node[wave][sp];
-        const uint64_t m = s_mask[wave][sp];
-        const int64_t v = packed & ((1 << 27) - 1);
-        const int lv = packed >> 27;
-        if (lv == levels) {
-            const int64_t leaf = v - leaf0;
-            if (lane == 0) {
-                leaf_mask[(size_t)leaf * ntiles + tile] = m;
-                if (items) {
-                    uint32_t idx = atomicAdd(item_count, 1u);
-                    if (idx < item_cap) {
-                        items[2 * (size_t)idx] = (int32_t)leaf;
-                        items[2 * (size_t)idx + 1] = tile;
-                    }
-                }
-            }
-            continue;
-        }
-        for (int c = F - 1; c >= 0; c--) {
-            const int64_t child = v * F + 1 + c;
-            tests += __popcll(m);
-            const uint64_t cm = m & dev::ballot(box_gap<MP>(box, child, qp) <= th);
-            if (cm) {
-                s_node[wave][sp] = (int32_t)child | ((lv + 1) << 27);
-                s_mask[wave][sp] = cm;
-                sp++;
-            }
-        }
-    }
-    if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
+    if (lok) leaf_mask[(size_t)leaf * ntiles + tile] = m;
+    if (lane == 0) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)nt * (unsigned long long)min<int64_t>(64, n_leaves - lg * 64));
 }
 
-void node_filter(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles,
-                 uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
-                 unsigned long long *counters, hipStream_t st)
+void leaf_box(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles, uint64_t *leaf_mask,
+              unsigned long long *counters, hipStream_t st)
 {
-    if (nq == 0) return;
-    // split level: enough (tile, subtree) waves to fill the chip
-    int split = 0;
-    int64_t nsub = 1;
-    while (split < t.levels && (int64_t)ntiles * nsub < 8192) {
-        split++;
-        nsub *= t.fanout;
-    }
-    const int64_t waves = (int64_t)ntiles * nsub;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-#define NF_LAUNCH(MP)                                                                                       \
-    hipLaunchKernelGGL(k_node_filter<MP>, dim3(blocks), dim3(256), 0, st, t.box_aos, t.fanout, t.levels, split, \
-                       nsub, t.leaf0, QP, thr, nq, ntiles, leaf_mask, items, item_count, item_cap, counters)
-    if (t.mpad == 8) NF_LAUNCH(8);
-    else if (t.mpad == 16) NF_LAUNCH(16);
-    else NF_LAUNCH(32);
-#undef NF_LAUNCH
+    if (nq == 0 || t.n_leaves == 0) return;
+    const int64_t waves = ((t.n_leaves + 63) / 64) * ntiles;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+#define LBX(MP)                                                                                                  \
+    hipLaunchKernelGGL(k_leaf_box<MP>, dim3(grid), dim3(256), 0, st, t.box_aos, t.leaf0, t.n_leaves, QP, thr, nq, \
+                       ntiles, leaf_mask, counters)
+    if (t.mpad == 8) LBX(8);
+    else if (t.mpad == 16) LBX(16);
+    else LBX(32);
+#undef LBX
     check_launch(__func__);
 }
 

@@ -51,13 +51,10 @@ struct TreeView {
     int fanout, levels, mpad;
 };
 
-// Depth-first node filtering, one wave per (query tile, subtree).  Writes
-// leaf_mask[leaf][tile] (bit = query lane survives the leaf's box) for every
-// leaf (zero when pruned) and, when items != nullptr, appends (leaf, tile)
-// for every surviving leaf.
-void node_filter(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles,
-                 uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
-                 unsigned long long *counters, hipStream_t st);
+// Node filtering at leaf granularity: leaf_mask[leaf][tile] (bit = query
+// lane whose global-pivot distances the leaf's box admits) for every leaf.
+void leaf_box(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles, uint64_t *leaf_mask,
+              unsigned long long *counters, hipStream_t st);
 
 // Greedy descent to each query's home leaf (smallest box gap per level);
 // for kNN queries (k[q] > 0) also the k-th smallest exact distance over a
@@ -164,15 +161,15 @@ void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t 
 // Cell masks in a new query order (query perm[i] becomes query i).
 void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells, int64_t nq, uint64_t *dst,
                        hipStream_t st);
-// Leaf test (Lemma 1 with each leaf's first object as its pivot) on the
-// leaves of the cells that passed, with the union of the leaf's cells' masks
-// (cell_mask rows of cm_stride words, the group's first tile at column 0):
-// writes leaf_mask[leaf][tile] and the list of nonzero (leaf, tile) pairs.
+// Leaf test (Lemma 1 with each leaf's first object as its pivot) for every
+// (query, leaf of a cell that passed for it) (cell_mask rows of cm_stride
+// words, the group's first tile at column 0): zeroes and fills
+// leaf_mask[leaf][tile] and lists the nonzero (leaf, tile) pairs.
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
                     const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
                     const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
                     int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
-                    hipStream_t st);
+                    int64_t n_leaves, hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
