@@ -31,7 +31,7 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_CMASK0, W_CMASK, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_CMASK0, W_CMASK, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "workspace slots of gts_index too few");
@@ -409,6 +409,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     }
     const hipMemcpyKind in_kind = Q->location == GTS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     k::QueryL2 qv{};
+    std::vector<int32_t> hqlen;   // query string lengths (EDIT), caller order
     k::QueryEdit qe{};
     if (nq > 0 && l2) {
         GTS_CHECK(Q->dim == d.dim, GTS_EINVAL, "query dimension differs from the index");
@@ -431,7 +432,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         GTS_HIP(hipMemcpy(hoff.data(), Q->offsets, (nq + 1) * sizeof(int64_t),
                           Q->location == GTS_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
         GTS_CHECK(hoff[0] == 0, GTS_EINVAL, "query offsets[0] must be 0");
-        std::vector<int32_t> qlen(nq);
+        std::vector<int32_t> &qlen = hqlen;
+        qlen.resize(nq);
         for (int64_t q = 0; q < nq; q++) {
             const int64_t len = hoff[q + 1] - hoff[q];
             GTS_CHECK(len >= 0 && len <= d.max_strlen, GTS_EINVAL, "query string length out of range");
@@ -474,14 +476,24 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
                    d.cell_len.as<int32_t>(), d.n_centres};
     uint64_t *cmask0 = nullptr;
+    // the cell test runs on the queries in length order, so that the tiles'
+    // patterns have similar word counts; pos_of[q] = position of query q
+    std::vector<int32_t> order, pos_of;
     if (edit_cells) {
+        order.resize(nq);
+        pos_of.resize(nq);
+        for (int64_t q = 0; q < nq; q++) order[q] = (int32_t)q;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hqlen[x] < hqlen[y]; });
+        for (int64_t p = 0; p < nq; p++) pos_of[order[p]] = (int32_t)p;
+        int32_t *dorder = wsp<int32_t>(cx, W_ORDER, nq);
+        GTS_HIP(hipMemcpyAsync(dorder, order.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         if (b.any_knn)
             k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
         cmask0 = wsp<uint64_t>(cx, W_CMASK0, (size_t)d.n_centres * ntiles_all);
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
-                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, cmask0, counters, st);
+                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, cmask0, counters, dorder, st);
     }
     if (nq > 1) {
         std::vector<int32_t> hh(nq);
@@ -494,8 +506,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
         } else if (edit_cells) {
             k::first_cell(cmask0, d.n_centres, nq, home, st);
-            GTS_HIP(hipMemcpyAsync(hh.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            std::vector<int32_t> hp(nq);
+            GTS_HIP(hipMemcpyAsync(hp.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
+            for (int64_t p = 0; p < nq; p++) hh[order[p]] = hp[p];
         }
         perm.resize(nq);
         for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
@@ -566,12 +580,24 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         }
     }
     if (edit_cells) {
+        // cell masks from length order to the batch order: batch position i
+        // holds caller query perm[i], tested at position pos_of[perm[i]]
         uint64_t *cm = wsp<uint64_t>(cx, W_CMASK, (size_t)d.n_centres * ntiles_all);
-        if (permuted)
-            k::cell_mask_permute(cmask0, cx->ws[W_PERM].as<int32_t>(), d.n_centres, nq, cm, st);
-        else
+        std::vector<int32_t> comp(nq);
+        bool ident = true;
+        for (int64_t i = 0; i < nq; i++) {
+            comp[i] = pos_of[permuted ? perm[i] : i];
+            ident = ident && comp[i] == i;
+        }
+        if (ident) {
             GTS_HIP(hipMemcpyAsync(cm, cmask0, (size_t)d.n_centres * ntiles_all * sizeof(uint64_t),
                                    hipMemcpyDeviceToDevice, st));
+        } else {
+            int32_t *dcomp = wsp<int32_t>(cx, W_ORDER, nq);
+            GTS_HIP(hipMemcpyAsync(dcomp, comp.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            k::cell_mask_permute(cmask0, dcomp, d.n_centres, nq, cm, st);
+            GTS_HIP(hipStreamSynchronize(st));   // comp is a host temporary
+        }
     }
     rec(cx, 1);
 

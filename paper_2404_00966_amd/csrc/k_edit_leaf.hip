@@ -117,24 +117,29 @@ struct GlobalPeq {
 };
 
 // The tile's match tables into LDS: s_tab[(c * W + w) * 64 + j] = word w of
-// code c of query tile*64 + j (zero for queries past nq).
+// code c of the tile's query j (zero for positions past nq); position p of
+// the tile order holds query order[p] (order may be null: the identity).
 template <int W>
-__device__ __forceinline__ void load_tile_tab(uint64_t *s_tab, const QueryEdit &qv, int rows, int tile, int64_t nq)
+__device__ __forceinline__ void load_tile_tab(uint64_t *s_tab, const QueryEdit &qv, int rows, int tile, int64_t nq,
+                                              const int32_t *__restrict__ order)
 {
     const int words = rows * W * 64;
     for (int i = threadIdx.x; i < words; i += blockDim.x) {
         const int j = i & 63, w = (i >> 6) % W, c = (i >> 6) / W;
         const int64_t qq = (int64_t)tile * 64 + j;
-        s_tab[i] = qq < nq ? qv.peq[((size_t)qq * rows + c) * 4 + w] : 0ull;
+        const int64_t qi = qq < nq ? (order ? order[qq] : qq) : 0;
+        s_tab[i] = qq < nq ? qv.peq[((size_t)qi * rows + c) * 4 + w] : 0ull;
     }
 }
 
 // Ball test of the wave's queries against one pivot string: lanes with `pass`
 // set keep it iff d(q, pivot) <= cut.  s_code is the wave's staging row.
+// W is the table layout's word count; the recurrence runs on wt <= W words,
+// the longest pattern of the wave (wave-uniform).
 template <int W, bool TAB>
 __device__ __forceinline__ bool ball_pass(bool pass, const uint8_t *__restrict__ chars, int32_t s0, int tl, int plen,
                                           int cut, uint8_t *s_code, const uint8_t *s_lut, const uint64_t *s_tab,
-                                          const uint64_t *gtab, int lane)
+                                          const uint64_t *gtab, int lane, int wt)
 {
     for (int b = lane; b < tl; b += 64) s_code[b] = s_lut[chars[s0 + b]];
     __builtin_amdgcn_wave_barrier();
@@ -142,8 +147,19 @@ __device__ __forceinline__ bool ball_pass(bool pass, const uint8_t *__restrict__
     pass = pass && abs(plen - tl) <= cut;
     if (pass) {
         int d;
-        if (TAB) d = dev::myers_distance<W>(TilePeq{s_tab, W, lane}, plen, s_code, tl, cut, NoLut{});
-        else d = dev::myers_distance<W>(GlobalPeq{gtab}, plen, s_code, tl, cut, NoLut{});
+        if (TAB) {
+            const TilePeq t{s_tab, W, lane};
+            if (W >= 2 && wt <= 1) d = dev::myers_distance<1>(t, plen, s_code, tl, cut, NoLut{});
+            else if (W >= 3 && wt <= 2) d = dev::myers_distance<2>(t, plen, s_code, tl, cut, NoLut{});
+            else if (W >= 4 && wt <= 3) d = dev::myers_distance<3>(t, plen, s_code, tl, cut, NoLut{});
+            else d = dev::myers_distance<W>(t, plen, s_code, tl, cut, NoLut{});
+        } else {
+            const GlobalPeq t{gtab};
+            if (W >= 2 && wt <= 1) d = dev::myers_distance<1>(t, plen, s_code, tl, cut, NoLut{});
+            else if (W >= 3 && wt <= 2) d = dev::myers_distance<2>(t, plen, s_code, tl, cut, NoLut{});
+            else if (W >= 4 && wt <= 3) d = dev::myers_distance<3>(t, plen, s_code, tl, cut, NoLut{});
+            else d = dev::myers_distance<W>(t, plen, s_code, tl, cut, NoLut{});
+        }
         pass = d <= cut;
     }
     __builtin_amdgcn_wave_barrier();
@@ -155,7 +171,8 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
                                                         const float *__restrict__ QP, const float *__restrict__ T,
                                                         int64_t nq, int ntiles, CellView cv,
                                                         uint64_t *__restrict__ cell_mask, int64_t cm_stride,
-                                                        unsigned long long *__restrict__ counters)
+                                                        unsigned long long *__restrict__ counters,
+                                                        const int32_t *__restrict__ order)
 {
     extern __shared__ uint64_t s_tab[];
     __shared__ uint8_t s_code[4][256];
@@ -163,13 +180,17 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
     const int tile = (int)(blockIdx.x % ntiles);
     const int64_t chunk = blockIdx.x / ntiles;
-    const int64_t q = (int64_t)tile * 64 + lane;
-    const bool qok = q < nq;
+    const int64_t p = (int64_t)tile * 64 + lane;   // position in the tile order
+    const bool qok = p < nq;
+    const int64_t q = qok ? (order ? order[p] : p) : 0;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
-    if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq);
+    if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq, order);
     __syncthreads();
     const int plen = qok ? qlen[q] : 0;
     const int tq = qok ? (int)T[q] : -1;
+    int wt = (plen + 63) >> 6;
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) wt = max(wt, __shfl_xor(wt, o2, 64));
     float qp[MP];
 #pragma unroll
     for (int i = 0; i < MP; i++) qp[i] = qok ? QP[(size_t)q * MP + i] : 0.f;
@@ -189,7 +210,7 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
         if (dev::ballot(pass) != 0ull && R >= 0.f) {
             const int32_t s0 = cv.off[c];
             pass = ball_pass<W, TAB>(pass, cv.chars, s0, cv.off[c + 1] - s0, plen, tq + (int)R, s_code[wave], s_lut,
-                                     s_tab, gtab, lane);
+                                     s_tab, gtab, lane, wt);
         } else {
             pass = false;
         }
@@ -329,7 +350,7 @@ void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells
 
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
                     const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
-                    unsigned long long *counters, hipStream_t st)
+                    unsigned long long *counters, const int32_t *order, hipStream_t st)
 {
     if (nq == 0 || cv.n == 0) return;
     const int ntiles = (int)((nq + 63) / 64);
@@ -340,7 +361,7 @@ void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define CT(WW, MP, TB)                                                                                            \
     hipLaunchKernelGGL((k_edit_cell_test<WW, MP, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, QP, T, nq,    \
-                       ntiles, cv, cell_mask, (int64_t)ntiles, counters)
+                       ntiles, cv, cell_mask, (int64_t)ntiles, counters, order)
 #define CTM(WW, TB)                 \
     if (mpad == 8) CT(WW, 8, TB);   \
     else if (mpad == 16) CT(WW, 16, TB); \

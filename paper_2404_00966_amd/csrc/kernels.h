@@ -151,11 +151,12 @@ struct CellView {
     int64_t n;
 };
 // Cell test (Lemma 1 with each centre and with the global pivots) for nq
-// queries in tiles of 64: writes cell_mask[cell][tile], the tile's queries
+// queries in tiles of 64, position p holding query order[p] (order may be
+// null: the identity): writes cell_mask[cell][tile], the tile's positions
 // that the cell may answer.
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
                     const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
-                    unsigned long long *counters, hipStream_t st);
+                    unsigned long long *counters, const int32_t *order, hipStream_t st);
 // First passing cell of each query (n_cells when none passed).
 void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t *home, hipStream_t st);
 // Cell masks in a new query order (query perm[i] becomes query i).
