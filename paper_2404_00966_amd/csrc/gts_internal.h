@@ -49,7 +49,7 @@ constexpr int kMaxPivots = 32;      // pivot table rows (padded to 8/16/32)
 constexpr int kMaxMfmaDim = 128;    // largest L2 dimension on the MFMA path
 constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
 constexpr int kSortCap = 4096;      // per-query keys sorted in LDS
-constexpr int kWorkspaceSlots = 48;   // named query buffers of an index
+constexpr int kWorkspaceSlots = 64;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 
 // Device buffer owned by the index (hipMalloc / hipFree).

@@ -31,10 +31,10 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_CMASK0, W_CMASK, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
     W_COUNT
 };
-static_assert(W_COUNT <= kWorkspaceSlots, "workspace slots of gts_index too few");
+static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
 
 struct ResultPriv {
     void *offsets = nullptr, *ids = nullptr, *dist = nullptr;
@@ -210,11 +210,11 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             // leaves of the cells that passed (cell masks of the whole batch,
             // this group's tiles from column q0 / 64), then the item list
             items = wsp<int32_t>(cx, W_ITEMS, (size_t)item_cap * 2);
-            const uint64_t *cmask = cx->ws[W_CMASK].as<uint64_t>() + q0 / kQTile;
             const int32_t *qlen = cx->ws[W_QLEN].as<int32_t>() + q0;
             k::edit_leaf_ball(oe, qe, qlen, t.leaf_first.as<int32_t>(), d.leafR.as<float>(), d.leaf_cell.as<int32_t>(),
-                              d.cell_leaf.as<int32_t>(), d.n_centres, cmask, b.ntiles_all, T, ng, ntiles, b.max_qlen,
-                              mask, items, small + 1, item_cap, t.n_leaves, st);
+                              d.cell_leaf.as<int32_t>(), d.n_centres,
+                              cx->ws[W_QCELLS].as<int32_t>() + q0 * k::kQueryCells, cx->ws[W_QCNT].as<int32_t>() + q0,
+                              T, ng, ntiles, b.max_qlen, mask, items, small + 1, item_cap, t.n_leaves, st);
         }
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
@@ -475,7 +475,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     const float delta = (float)((d.dim + 8) * 5.9604645e-8);
     k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
                    d.cell_len.as<int32_t>(), d.n_centres};
-    uint64_t *cmask0 = nullptr;
+    int32_t *qcells0 = nullptr, *qcnt0 = nullptr;   // passing cells per position of the length order
     // the cell test runs on the queries in length order, so that the tiles'
     // patterns have similar word counts; pos_of[q] = position of query q
     std::vector<int32_t> order, pos_of;
@@ -491,9 +491,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
-        cmask0 = wsp<uint64_t>(cx, W_CMASK0, (size_t)d.n_centres * ntiles_all);
+        qcells0 = wsp<int32_t>(cx, W_QCELLS0, (size_t)nq * k::kQueryCells);
+        qcnt0 = wsp<int32_t>(cx, W_QCNT0, nq);
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
-                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, cmask0, counters, dorder, st);
+                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, qcells0, qcnt0, counters, dorder, st);
     }
     if (nq > 1) {
         std::vector<int32_t> hh(nq);
@@ -505,7 +506,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             GTS_HIP(hipStreamSynchronize(st));
             for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
         } else if (edit_cells) {
-            k::first_cell(cmask0, d.n_centres, nq, home, st);
+            k::first_cell(qcells0, qcnt0, d.n_centres, nq, home, st);
             std::vector<int32_t> hp(nq);
             GTS_HIP(hipMemcpyAsync(hp.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             GTS_HIP(hipStreamSynchronize(st));
@@ -580,24 +581,16 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         }
     }
     if (edit_cells) {
-        // cell masks from length order to the batch order: batch position i
+        // cell lists from length order to the batch order: batch position i
         // holds caller query perm[i], tested at position pos_of[perm[i]]
-        uint64_t *cm = wsp<uint64_t>(cx, W_CMASK, (size_t)d.n_centres * ntiles_all);
         std::vector<int32_t> comp(nq);
-        bool ident = true;
-        for (int64_t i = 0; i < nq; i++) {
-            comp[i] = pos_of[permuted ? perm[i] : i];
-            ident = ident && comp[i] == i;
-        }
-        if (ident) {
-            GTS_HIP(hipMemcpyAsync(cm, cmask0, (size_t)d.n_centres * ntiles_all * sizeof(uint64_t),
-                                   hipMemcpyDeviceToDevice, st));
-        } else {
-            int32_t *dcomp = wsp<int32_t>(cx, W_ORDER, nq);
-            GTS_HIP(hipMemcpyAsync(dcomp, comp.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-            k::cell_mask_permute(cmask0, dcomp, d.n_centres, nq, cm, st);
-            GTS_HIP(hipStreamSynchronize(st));   // comp is a host temporary
-        }
+        for (int64_t i = 0; i < nq; i++) comp[i] = pos_of[permuted ? perm[i] : i];
+        int32_t *dcomp = wsp<int32_t>(cx, W_ORDER, nq);
+        GTS_HIP(hipMemcpyAsync(dcomp, comp.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        k::gather_i32(qcells0, dcomp, nq, k::kQueryCells, wsp<int32_t>(cx, W_QCELLS, (size_t)nq * k::kQueryCells),
+                      st);
+        k::gather_i32(qcnt0, dcomp, nq, 1, wsp<int32_t>(cx, W_QCNT, nq), st);
+        GTS_HIP(hipStreamSynchronize(st));   // comp is a host temporary
     }
     rec(cx, 1);
 

@@ -170,7 +170,7 @@ template <int W, int MP, bool TAB>
 __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
                                                         const float *__restrict__ QP, const float *__restrict__ T,
                                                         int64_t nq, int ntiles, CellView cv,
-                                                        uint64_t *__restrict__ cell_mask, int64_t cm_stride,
+                                                        int32_t *__restrict__ qcells, int32_t *__restrict__ qcnt,
                                                         unsigned long long *__restrict__ counters,
                                                         const int32_t *__restrict__ order)
 {
@@ -214,20 +214,23 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
         } else {
             pass = false;
         }
-        const uint64_t m = dev::ballot(pass);
-        if (lane == 0) cell_mask[(size_t)c * cm_stride + tile] = m;
+        if (pass) {
+            const int slot = atomicAdd(&qcnt[p], 1);
+            if (slot < kQueryCells) qcells[(size_t)p * kQueryCells + slot] = (int32_t)c;
+        }
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) tests += __shfl_xor(tests, o2, 64);
     if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
 }
 
 // Leaves are reached from the cells that passed, query by query: one wave per
-// query (its match table in LDS), lanes over the leaves of each cell that
-// passed for it, each lane scanning its leaf pivot as the text with the
+// query (its match table in LDS), lanes over the leaves of each cell on the
+// query's list, each lane scanning its leaf pivot as the text with the
 // cutoff T_q + R_L.  A leaf that spans several cells is tested from the first
-// of them that passed.  A passing (query, leaf) pair sets the query's bit in
-// leaf_mask[leaf][tile]; the first bit set in a word appends (leaf, tile) to
-// the item list (leaf_mask starts zeroed).
+// of them on the list.  A query whose list overflowed takes every cell.  A
+// passing (query, leaf) pair sets the query's bit in leaf_mask[leaf][tile];
+// the first bit set in a word appends (leaf, tile) to the item list
+// (leaf_mask starts zeroed).
 template <int W>
 __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
                                                          const float *__restrict__ T,
@@ -235,56 +238,73 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
                                                          const float *__restrict__ leafR,
                                                          const int32_t *__restrict__ leaf_cell,
                                                          const int32_t *__restrict__ cell_leaf, int64_t n_cells,
-                                                         const uint64_t *__restrict__ cell_mask, int64_t cm_stride,
-                                                         int64_t nq, int ntiles,
+                                                         const int32_t *__restrict__ qcells,
+                                                         const int32_t *__restrict__ qcnt, int64_t nq, int ntiles,
                                                          unsigned long long *__restrict__ leaf_mask,
                                                          int32_t *__restrict__ items, uint32_t *__restrict__ item_count,
                                                          int64_t item_cap)
 {
     extern __shared__ uint64_t s_tabs[];   // 4 x rows x 4 words
     __shared__ uint8_t s_lut[256];
+    __shared__ int32_t s_cells[4][kQueryCells];
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     const bool qok = q < nq;
     uint64_t *tab = s_tabs + (size_t)wave * o.rows * 4;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
-    if (qok)
+    int cnt = 0;
+    if (qok) {
         for (int i = lane; i < o.rows * 4; i += 64) tab[i] = qv.peq[(size_t)q * o.rows * 4 + i];
+        cnt = qcnt[q];
+        for (int i = lane; i < min(cnt, kQueryCells); i += 64) s_cells[wave][i] = qcells[(size_t)q * kQueryCells + i];
+    }
     __syncthreads();
-    if (!qok) return;
+    if (!qok || cnt == 0) return;
+    const bool all = cnt > kQueryCells;   // the list overflowed: every cell
+    const int ncell = all ? (int)n_cells : cnt;
     const int plen = qlen[q];
+    const int wq = (plen + 63) >> 6;
     const int tq = (int)T[q];
     const int tile = (int)(q >> 6);
-    const uint64_t bit = 1ull << (q & 63);
-    auto passed = [&](int64_t c) { return (cell_mask[(size_t)c * cm_stride + tile] & bit) != 0ull; };
-    for (int64_t c0 = 0; c0 < n_cells; c0 += 64) {
-        uint64_t b = dev::ballot(c0 + lane < n_cells && passed(c0 + lane));
-        while (b) {
-            const int64_t c = c0 + __ffsll((unsigned long long)b) - 1;
-            b &= b - 1;
-            const int l_lo = cell_leaf[2 * c], l_hi = cell_leaf[2 * c + 1];
-            for (int l0 = l_lo; l0 <= l_hi; l0 += 64) {
-                const int leaf = l0 + lane;
-                bool ok = leaf <= l_hi;
-                if (ok)
-                    for (int e = leaf_cell[2 * leaf]; e < c; e++) ok = ok && !passed(e);
-                const float R = ok ? leafR[leaf] : -1.f;
-                ok = ok && R >= 0.f;
-                if (ok) {
-                    const int32_t s0 = o.soff[leaf_first[leaf]];
-                    const int tl = o.soff[leaf_first[leaf] + 1] - s0;
-                    const int cut = tq + (int)R;
-                    ok = abs(plen - tl) <= cut &&
-                         dev::myers_distance<W>(tab, plen, o.chars + s0, tl, cut, s_lut) <= cut;
+    const unsigned long long bit = 1ull << (q & 63);
+    auto listed = [&](int e) {
+        if (all) return true;
+        bool f = false;
+        for (int i = 0; i < cnt; i++) f = f || s_cells[wave][i] == e;
+        return f;
+    };
+    for (int ci = 0; ci < ncell; ci++) {
+        const int c = all ? ci : s_cells[wave][ci];
+        const int l_lo = cell_leaf[2 * c], l_hi = cell_leaf[2 * c + 1];
+        for (int l0 = l_lo; l0 <= l_hi; l0 += 64) {
+            const int leaf = l0 + lane;
+            bool ok = leaf <= l_hi;
+            if (ok)
+                for (int e = leaf_cell[2 * leaf]; e < c; e++) ok = ok && !listed(e);
+            const float R = ok ? leafR[leaf] : -1.f;
+            ok = ok && R >= 0.f;
+            if (ok) {
+                const int32_t s0 = o.soff[leaf_first[leaf]];
+                const int tl = o.soff[leaf_first[leaf] + 1] - s0;
+                const int cut = tq + (int)R;
+                if (abs(plen - tl) > cut) {
+                    ok = false;
+                } else {
+                    int d;
+                    if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(tab, plen, o.chars + s0, tl, cut, s_lut);
+                    else if (W >= 3 && wq <= 2) d = dev::myers_distance<2>(tab, plen, o.chars + s0, tl, cut, s_lut);
+                    else if (W >= 4 && wq <= 3) d = dev::myers_distance<3>(tab, plen, o.chars + s0, tl, cut, s_lut);
+                    else d = dev::myers_distance<W>(tab, plen, o.chars + s0, tl, cut, s_lut);
+                    ok = d <= cut;
                 }
-                if (ok) {
-                    const unsigned long long old = atomicOr(leaf_mask + (size_t)leaf * ntiles + tile, bit);
-                    if (old == 0ull) {
-                        const uint32_t idx = atomicAdd(item_count, 1u);
-                        if (idx < item_cap) {
-                            items[2 * (size_t)idx] = leaf;
-                            items[2 * (size_t)idx + 1] = tile;
-                        }
+            }
+            if (ok) {
+                const unsigned long long old = atomicOr(leaf_mask + (size_t)leaf * ntiles + tile, bit);
+                if (old == 0ull) {
+                    const uint32_t idx = atomicAdd(item_count, 1u);
+                    if (idx < item_cap) {
+                        items[2 * (size_t)idx] = leaf;
+                        items[2 * (size_t)idx + 1] = tile;
                     }
                 }
             }
@@ -292,67 +312,38 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
     }
 }
 
-// home[q] = the first cell (in chain order) that passed for query q, or
-// n_cells when none did.  One workgroup per tile; threads stride over cells.
-__global__ __launch_bounds__(256) void k_first_cell(const uint64_t *__restrict__ cell_mask, int64_t n_cells,
-                                                    int ntiles, int64_t nq, int32_t *__restrict__ home)
+// home[q] = the first cell (in chain order) on query q's list, n_cells when
+// the list is empty, 0 when it overflowed.  One thread per query.
+__global__ void k_first_cell(const int32_t *__restrict__ qcells, const int32_t *__restrict__ qcnt, int64_t n_cells,
+                             int64_t nq, int32_t *__restrict__ home)
 {
-    __shared__ int s_home[64];
-    const int tile = blockIdx.x;
-    if (threadIdx.x < 64) s_home[threadIdx.x] = (int)n_cells;
-    __syncthreads();
-    for (int64_t c = threadIdx.x; c < n_cells; c += blockDim.x) {
-        uint64_t w = cell_mask[(size_t)c * ntiles + tile];
-        while (w) {
-            const int j = __ffsll((unsigned long long)w) - 1;
-            w &= w - 1;
-            atomicMin(&s_home[j], (int)c);
-        }
-    }
-    __syncthreads();
-    const int64_t q = (int64_t)tile * 64 + threadIdx.x;
-    if (threadIdx.x < 64 && q < nq) home[q] = s_home[threadIdx.x];
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int cnt = qcnt[q];
+    int h = (int)n_cells;
+    if (cnt > kQueryCells) h = 0;
+    else
+        for (int i = 0; i < cnt; i++) h = min(h, qcells[(size_t)q * kQueryCells + i]);
+    home[q] = h;
 }
 
-// Cell masks in a new query order: query perm[i] of the old order is query i
-// of the new one.  dst is zeroed first; one thread per query.
-__global__ void k_cell_mask_permute(const uint64_t *__restrict__ src, const int32_t *__restrict__ perm,
-                                    int64_t n_cells, int ntiles, int64_t nq, unsigned long long *__restrict__ dst)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nq) return;
-    const int64_t qo = perm[i];
-    const int to = (int)(qo >> 6), bo = (int)(qo & 63);
-    const int tn = (int)(i >> 6);
-    const unsigned long long bit = 1ull << (i & 63);
-    for (int64_t c = 0; c < n_cells; c++)
-        if ((src[(size_t)c * ntiles + to] >> bo) & 1ull) atomicOr(dst + (size_t)c * ntiles + tn, bit);
-}
-
-void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t *home, hipStream_t st)
+void first_cell(const int32_t *qcells, const int32_t *qcnt, int64_t n_cells, int64_t nq, int32_t *home,
+                hipStream_t st)
 {
     if (nq == 0) return;
-    const int ntiles = (int)((nq + 63) / 64);
-    hipLaunchKernelGGL(k_first_cell, dim3(ntiles), dim3(256), 0, st, cell_mask, n_cells, ntiles, nq, home);
+    hipLaunchKernelGGL(k_first_cell, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, qcells, qcnt, n_cells,
+                       nq, home);
     check_launch(__func__);
 }
 
-void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells, int64_t nq, uint64_t *dst,
-                       hipStream_t st)
-{
-    if (nq == 0) return;
-    const int ntiles = (int)((nq + 63) / 64);
-    fill_u32(reinterpret_cast<uint32_t *>(dst), n_cells * ntiles * 2, 0u, st);
-    hipLaunchKernelGGL(k_cell_mask_permute, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, src, perm,
-                       n_cells, ntiles, nq, reinterpret_cast<unsigned long long *>(dst));
-    check_launch(__func__);
-}
 
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, int32_t *qcells, int32_t *qcnt,
                     unsigned long long *counters, const int32_t *order, hipStream_t st)
 {
-    if (nq == 0 || cv.n == 0) return;
+    if (nq == 0) return;
+    fill_u32(reinterpret_cast<uint32_t *>(qcnt), nq, 0u, st);
+    if (cv.n == 0) return;
     const int ntiles = (int)((nq + 63) / 64);
     const int W = std::max(1, (max_qlen + 63) / 64);
     const int64_t chunks = (cv.n + kBallChunk - 1) / kBallChunk;
@@ -361,7 +352,7 @@ void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define CT(WW, MP, TB)                                                                                            \
     hipLaunchKernelGGL((k_edit_cell_test<WW, MP, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, QP, T, nq,    \
-                       ntiles, cv, cell_mask, (int64_t)ntiles, counters, order)
+                       ntiles, cv, qcells, qcnt, counters, order)
 #define CTM(WW, TB)                 \
     if (mpad == 8) CT(WW, 8, TB);   \
     else if (mpad == 16) CT(WW, 16, TB); \
@@ -382,7 +373,7 @@ void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
 
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
                     const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
-                    const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
+                    const int32_t *qcells, const int32_t *qcnt, const float *T, int64_t nq, int ntiles,
                     int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
                     int64_t n_leaves, hipStream_t st)
 {
@@ -394,8 +385,7 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
     auto *lm = reinterpret_cast<unsigned long long *>(leaf_mask);
 #define EQ(WW)                                                                                                 \
     hipLaunchKernelGGL(k_edit_leaf_query<WW>, dim3(grid), dim3(256), shm, st, o, qv, qlen, T, leaf_first, leafR, \
-                       leaf_cell, cell_leaf, n_cells, cell_mask, cm_stride, nq, ntiles, lm, items, item_count,  \
-                       item_cap)
+                       leaf_cell, cell_leaf, n_cells, qcells, qcnt, nq, ntiles, lm, items, item_count, item_cap)
     switch (W) {
     case 1: EQ(1); break;
     case 2: EQ(2); break;

@@ -150,25 +150,25 @@ struct CellView {
     const int32_t *len;        // [n][2]: shortest and longest member
     int64_t n;
 };
+// Passing cells kept per query; a query with more takes every cell.
+constexpr int kQueryCells = 64;
 // Cell test (Lemma 1 with each centre and with the global pivots) for nq
 // queries in tiles of 64, position p holding query order[p] (order may be
-// null: the identity): writes cell_mask[cell][tile], the tile's positions
-// that the cell may answer.
+// null: the identity): qcnt[p] = number of passing cells, qcells[p][0..63]
+// the first kQueryCells of them (in no particular order).
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int max_qlen, const CellView &cv, uint64_t *cell_mask,
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, int32_t *qcells, int32_t *qcnt,
                     unsigned long long *counters, const int32_t *order, hipStream_t st);
-// First passing cell of each query (n_cells when none passed).
-void first_cell(const uint64_t *cell_mask, int64_t n_cells, int64_t nq, int32_t *home, hipStream_t st);
-// Cell masks in a new query order (query perm[i] becomes query i).
-void cell_mask_permute(const uint64_t *src, const int32_t *perm, int64_t n_cells, int64_t nq, uint64_t *dst,
-                       hipStream_t st);
+// First (chain-order) passing cell of each position: n_cells when none
+// passed, 0 when the list overflowed.
+void first_cell(const int32_t *qcells, const int32_t *qcnt, int64_t n_cells, int64_t nq, int32_t *home,
+                hipStream_t st);
 // Leaf test (Lemma 1 with each leaf's first object as its pivot) for every
-// (query, leaf of a cell that passed for it) (cell_mask rows of cm_stride
-// words, the group's first tile at column 0): zeroes and fills
-// leaf_mask[leaf][tile] and lists the nonzero (leaf, tile) pairs.
+// (query, leaf of a cell on its list): zeroes and fills leaf_mask[leaf][tile]
+// and lists the nonzero (leaf, tile) pairs.
 void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const int32_t *leaf_first,
                     const float *leafR, const int32_t *leaf_cell, const int32_t *cell_leaf, int64_t n_cells,
-                    const uint64_t *cell_mask, int64_t cm_stride, const float *T, int64_t nq, int ntiles,
+                    const int32_t *qcells, const int32_t *qcnt, const float *T, int64_t nq, int ntiles,
                     int max_qlen, uint64_t *leaf_mask, int32_t *items, uint32_t *item_count, int64_t item_cap,
                     int64_t n_leaves, hipStream_t st);
 
