@@ -112,6 +112,11 @@ void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max
 }
 
 namespace k {
+void require(bool ok, const char *what)
+{
+    if (!ok) fail(GTS_ENOTSUP, what);
+}
+
 void check_launch(const char *name)
 {
     const hipError_t e = hipGetLastError();

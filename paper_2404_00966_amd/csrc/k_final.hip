@@ -153,47 +153,63 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     const int grp = threadIdx.x >> 4, sl = threadIdx.x & 15;
     const float *qrow = qv.Q32 + (size_t)q * o.dp;
     long long verified = 0;
-    for (int i0 = 0; i0 < ns; i0 += 16) {
-        const int i = i0 + grp;
-        const bool valid = i < ns;
-        Cand c;
-        c.q = 0;
-        c.pos = -1;
-        c.val = 0;
-        if (valid) c = g[i];
+    // two candidates per 16-lane group and step, both rows in flight together
+    auto emit = [&](bool valid, const Cand &c, bool need, float acc) {
+        if (sl != 0 || !valid) return;
+        bool keep = false;
+        uint64_t key = 0;
+        if (c.pos < 0) {
+            keep = true;
+            key = c.val;
+        } else if (need) {
+            verified++;
+            const float d = sqrtf(acc);
+            keep = k > 0 || d <= base;
+            key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
+        }
+        if (keep) {
+            const int slot = atomicAdd(&s_n, 1);
+            keys[slot] = key;
+        }
+    };
+    auto needs = [&](bool valid, const Cand &c) {
         bool need = valid && c.pos >= 0;
         if (need && k > 0 && ub < INFINITY) {
             float lo, hi;
             l2_interval(c, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
             need = lo <= ub;
         }
-        float acc = 0.f;
-        if (need) {
-            const float *x = o.X32 + (size_t)c.pos * o.dp;
+        return need;
+    };
+    for (int i0 = 0; i0 < ns; i0 += 32) {
+        const int ia = i0 + grp, ib = i0 + 16 + grp;
+        const bool va = ia < ns, vb = ib < ns;
+        Cand ca, cb;
+        ca.q = cb.q = 0;
+        ca.pos = cb.pos = -1;
+        ca.val = cb.val = 0;
+        if (va) ca = g[ia];
+        if (vb) cb = g[ib];
+        const bool na = needs(va, ca), nb = needs(vb, cb);
+        const float *xa = na ? o.X32 + (size_t)ca.pos * o.dp : qrow;
+        const float *xb = nb ? o.X32 + (size_t)cb.pos * o.dp : qrow;
+        float acca = 0.f, accb = 0.f;
+        if (na || nb) {
             for (int d = sl; d < o.dp; d += 16) {
-                const float df = qrow[d] - x[d];
-                acc = fmaf(df, df, acc);
+                const float qd = qrow[d];
+                const float dfa = qd - xa[d];
+                const float dfb = qd - xb[d];
+                acca = fmaf(dfa, dfa, acca);
+                accb = fmaf(dfb, dfb, accb);
             }
         }
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-        if (sl == 0 && valid) {
-            bool keep = false;
-            uint64_t key = 0;
-            if (c.pos < 0) {
-                keep = true;
-                key = c.val;
-            } else if (need) {
-                verified++;
-                const float d = sqrtf(acc);
-                keep = k > 0 || d <= base;
-                key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
-            }
-            if (keep) {
-                const int slot = atomicAdd(&s_n, 1);
-                keys[slot] = key;
-            }
+        for (int off = 8; off > 0; off >>= 1) {
+            acca += __shfl_xor(acca, off, 16);
+            accb += __shfl_xor(accb, off, 16);
         }
+        emit(va, ca, na, acca);
+        emit(vb, cb, nb, accb);
     }
     __syncthreads();
     if (threadIdx.x % 16 == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);

@@ -243,55 +243,77 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
 // ---------------------------------------------------------------------------
 constexpr int kWinObj = 2048;
 
-__global__ __launch_bounds__(64) void k_bound_near(const int32_t *__restrict__ near, const int32_t *__restrict__ leaf_first,
-                                                   const int32_t *__restrict__ leaf_cnt, const float *__restrict__ X32,
-                                                   int dp, const float *__restrict__ Q32, const int32_t *__restrict__ kq,
-                                                   int64_t nq, const uint32_t *__restrict__ tomb, int target,
-                                                   float *__restrict__ tq)
+__global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ near,
+                                                    const int32_t *__restrict__ leaf_first,
+                                                    const int32_t *__restrict__ leaf_cnt, const float *__restrict__ X32,
+                                                    int dp, const float *__restrict__ Q32,
+                                                    const int32_t *__restrict__ kq, int64_t nq,
+                                                    const uint32_t *__restrict__ tomb, int target,
+                                                    float *__restrict__ tq)
 {
     __shared__ float s_d[kWinObj];
+    __shared__ int s_first[kNearLeaves], s_start[kNearLeaves + 1];
+    __shared__ int s_nl;
     const int64_t q = blockIdx.x;
     if (q >= nq) return;
     const int k = kq[q];
     if (k <= 0) return;
-    const int lane = threadIdx.x;
-    const int want = k > target ? k : target;
-    int count = 0;
-    const float4 *y = reinterpret_cast<const float4 *>(Q32 + (size_t)q * dp);
-    for (int i = 0; i < kNearLeaves && count < want; i++) {
-        const int32_t leaf = near[q * kNearLeaves + i];
-        if (leaf < 0) break;
-        const int cnt = leaf_cnt[leaf];
-        if (count + cnt > kWinObj) break;
-        const int p0 = leaf_first[leaf];
-        for (int j = lane; j < cnt; j += 64) {
-            const int p = p0 + j;
-            float d = INFINITY;
-            if (!((tomb[p >> 5] >> (p & 31)) & 1u)) {
-                const float4 *x = reinterpret_cast<const float4 *>(X32 + (size_t)p * dp);
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                for (int c = 0; c < dp / 4; c++) {
-                    const float4 u = x[c], v = y[c];
-                    const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
-                    a0 = fmaf(d0, d0, a0);
-                    a1 = fmaf(d1, d1, a1);
-                    a2 = fmaf(d2, d2, a2);
-                    a3 = fmaf(d3, d3, a3);
-                }
-                d = sqrtf((a0 + a1) + (a2 + a3));
-            }
-            s_d[count + j] = d;
+    // the window: the nearest leaves in order, while at most kWinObj objects
+    // and until at least max(k, target) were taken
+    if (threadIdx.x == 0) {
+        const int want = k > target ? k : target;
+        int count = 0, nl = 0;
+        s_start[0] = 0;
+        for (int i = 0; i < kNearLeaves && count < want; i++) {
+            const int32_t leaf = near[q * kNearLeaves + i];
+            if (leaf < 0) break;
+            const int cnt = leaf_cnt[leaf];
+            if (count + cnt > kWinObj) break;
+            s_first[nl] = leaf_first[leaf];
+            count += cnt;
+            s_start[++nl] = count;
         }
-        count += cnt;
+        s_nl = nl;
     }
+    __syncthreads();
+    const int nl = s_nl, count = s_start[nl];
     if (count < k) {
-        if (lane == 0) tq[q] = INFINITY;
+        if (threadIdx.x == 0) tq[q] = INFINITY;
         return;
     }
+    // 16 lanes per object, strided coordinates, query slice in registers
+    const int sl = threadIdx.x & 15;
+    float qr[8];
+#pragma unroll
+    for (int t = 0; t < 8; t++) qr[t] = sl + 16 * t < dp ? Q32[(size_t)q * dp + sl + 16 * t] : 0.f;
+    for (int j0 = 0; j0 < count; j0 += 16) {
+        const int j = j0 + (int)(threadIdx.x >> 4);
+        const bool ok = j < count;
+        int p = 0;
+        if (ok) {
+            int e = 0;
+            while (e + 1 < nl && s_start[e + 1] <= j) e++;
+            p = s_first[e] + (j - s_start[e]);
+        }
+        const bool live = ok && !((tomb[p >> 5] >> (p & 31)) & 1u);
+        float acc = 0.f;
+        if (live) {
+            const float *x = X32 + (size_t)p * dp;
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                if (sl + 16 * t < dp) {
+                    const float df = qr[t] - x[sl + 16 * t];
+                    acc = fmaf(df, df, acc);
+                }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+        if (ok && sl == 0) s_d[j] = live ? sqrtf(acc) : INFINITY;
+    }
     const int P = dev::next_pow2(count);
-    for (int j = count + lane; j < P; j += 64) s_d[j] = INFINITY;
+    for (int j = count + threadIdx.x; j < P; j += blockDim.x) s_d[j] = INFINITY;
     dev::bitonic_sort(s_d, P);
-    if (lane == 0) tq[q] = s_d[k - 1];
+    if (threadIdx.x == 0) tq[q] = s_d[k - 1];
 }
 
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
@@ -299,7 +321,8 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
                 hipStream_t st)
 {
     if (nq == 0) return;
-    hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(64), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
+    require(dp <= 128, "bound_near: rows wider than 128 floats");
+    hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
                        kq, nq, tomb, target, tq);
     check_launch(__func__);
 }

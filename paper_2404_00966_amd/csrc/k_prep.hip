@@ -59,38 +59,39 @@ void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, in
 }
 
 // out[i * s_piv + r * s_row] = || X[r] - P[i] ||  (float32, direct difference,
-// rows of both padded to `stride` floats, a multiple of 4).  One thread per
-// (row, pivot).  Columns i in [m, mpad) get 0.
-__global__ void k_dist_l2_pivots(const float *__restrict__ X, int64_t rows, const float *__restrict__ P, int m,
-                                 int mpad, int stride, float *__restrict__ out, int64_t s_piv, int64_t s_row)
+// rows of both padded to `stride` floats).  16 lanes per (row, pivot) pair,
+// each summing a strided slice of the coordinates (coalesced 64-byte runs),
+// then a 16-lane reduction.  Columns i in [m, mpad) get 0.
+__global__ __launch_bounds__(256) void k_dist_l2_pivots(const float *__restrict__ X, int64_t rows,
+                                                        const float *__restrict__ P, int m, int mpad, int stride,
+                                                        float *__restrict__ out, int64_t s_piv, int64_t s_row)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
-    if (r >= rows) return;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int sl = threadIdx.x & 15;
+    const int64_t r = g / mpad;
+    const int i = (int)(g % mpad);
+    const bool ok = r < rows;
     float acc = 0.f;
-    if (i < m) {
-        const float4 *x = reinterpret_cast<const float4 *>(X + (size_t)r * stride);
-        const float4 *p = reinterpret_cast<const float4 *>(P + (size_t)i * stride);
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        for (int c = 0; c < stride / 4; c++) {
-            float4 u = x[c], v = p[c];
-            float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
-            a0 = fmaf(d0, d0, a0);
-            a1 = fmaf(d1, d1, a1);
-            a2 = fmaf(d2, d2, a2);
-            a3 = fmaf(d3, d3, a3);
+    if (ok && i < m) {
+        const float *x = X + (size_t)r * stride;
+        const float *p = P + (size_t)i * stride;
+        for (int c = sl; c < stride; c += 16) {
+            const float df = x[c] - p[c];
+            acc = fmaf(df, df, acc);
         }
-        acc = sqrtf((a0 + a1) + (a2 + a3));
     }
-    out[(size_t)i * s_piv + (size_t)r * s_row] = acc;
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (ok && sl == 0) out[(size_t)i * s_piv + (size_t)r * s_row] = i < m ? sqrtf(acc) : 0.f;
 }
 
 void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpad, int stride, float *out,
                     int64_t s_piv, int64_t s_row, hipStream_t st)
 {
     if (rows == 0) return;
-    dim3 grid((unsigned)((rows + 255) / 256), (unsigned)mpad);
-    hipLaunchKernelGGL(k_dist_l2_pivots, grid, dim3(256), 0, st, X, rows, P, m, mpad, stride, out, s_piv, s_row);
+    const int64_t threads = rows * mpad * 16;
+    hipLaunchKernelGGL(k_dist_l2_pivots, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, rows, P, m,
+                       mpad, stride, out, s_piv, s_row);
     check_launch(__func__);
 }
 

@@ -14,6 +14,9 @@ enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED 
 // Raise the launch error left by the wrapper `name` (a bad grid or resource
 // request), so that it surfaces at its own call and not at a later one.
 void check_launch(const char *name);
+// Raise a not-supported error naming `what` unless ok (a launcher's own
+// precondition on its arguments).
+void require(bool ok, const char *what);
 
 // A (query, object) pair on its way to the answer.
 //   pos >= 0 : candidate at tree position pos; val = float bits of an

@@ -63,6 +63,30 @@ def test_l2_10k_d16(gts, mode):
     idx.close()
 
 
+@pytest.mark.parametrize("kind", ["l2", "edit"])
+def test_segments_beyond_the_lds_sort(gts, kind):
+    """Queries whose candidate lists exceed what one workgroup sorts in LDS
+    (thousands of answers each) take the global-memory sort."""
+    _say(f"big segments {kind}")
+    if kind == "l2":
+        d = synth.gaussian_mixture(61, 12000, 8, 2, -1.0, 1.0, 1.0, 12, 12)
+        X, RQ, KQ = d["objects"], d["range_queries"], d["knn_queries"]
+        idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=4, fanout=4, leaf_size=64, seed=3)
+        objs = O.ObjectSet(vecs=X)
+        r = 3.0
+        check_range(idx.range(_dev(RQ), r).to_lists(), O.range_bf(objs, O.ObjectSet(vecs=RQ), r), X, RQ, r)
+        check_knn(idx.knn(_dev(KQ), 5000).to_lists(), O.knn_bf(objs, O.ObjectSet(vecs=KQ), 5000), X, KQ, 5000)
+    else:
+        items = synth.random_strings(62, 9000, 4, 9, b"AC")
+        q = synth.random_strings(63, 10, 4, 9, b"AC")
+        idx = gts.Index(items, gts.EDIT_U8, num_pivots=3, fanout=4, seed=4)
+        objs, qs = O.ObjectSet(strings=items), O.ObjectSet(strings=q)
+        check_exact(idx.range(q, 3.0, result="host").to_lists(), O.range_bf(objs, qs, 3.0))
+        check_exact(idx.knn(q, 4000, result="host").to_lists(), O.knn_bf(objs, qs, 4000))
+    assert max(len(a) for a, _ in idx.range(_dev(RQ) if kind == "l2" else q, 3.0, result="host").to_lists()) > 2048
+    idx.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("n,dim", [(1, 3), (5, 3), (40, 3), (300, 33), (700, 2)])
 def test_l2_tiny_exhaustive(gts, mode, n, dim):
