@@ -260,6 +260,52 @@ def run_serving(args, gts, synth, torch, np):
     return out
 
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (each scaled by
+# what the counters read for a plain 256 MiB device copy), per kernel, for
+# the kernel source as profiled; None once the kernel has changed since.
+TRAFFIC_BYTES = {"k_verify_l2": 1114161638, "k_mfma_sweep": 416380325}
+
+
+def rooflines(st, dim):
+    """Roofline points of the kernels behind the timed stages of one search
+    call (stage times are HIP-event times on the index's stream; each stage
+    is one kernel).  Algorithmic work per launch:
+      k_mfma_sweep: every (query, object) pair of the computed (256-object
+        slab, 16-query block) units, 2 * D flop each (D = dim rounded up to
+        32);
+      k_verify_l2: per candidate its 16-byte record and the 8 bytes of its
+        norm and rounding error, per float32 recheck one object row (4 * dim
+        bytes), per answer its 8-byte key."""
+    dk = (dim + 31) // 32 * 32
+    out = {}
+    ms = st["ms_stage"]["cands"]
+    flops = 2.0 * dk * st["tile_pairs"] * 16 * 256
+    a = flops / (ms * 1e-3) / 1e12 if ms > 0 else None
+    out["k_mfma_sweep"] = {"bound": "mfma", "achieved": a, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": a / BF16_PEAK_TFLOPS if a else None, "traffic": TRAFFIC_BYTES["k_mfma_sweep"],
+                           "work_per_launch": flops, "launch_ms": ms,
+                           "work": "(256-object slab, 16-query block) units x 16 x 256 pairs x 2*Dk flop"}
+    ms = st["ms_stage"]["verify"]
+    byts = 24.0 * st["candidates"] + 4.0 * dim * st["verified"] + 8.0 * st["results"]
+    a = byts / (ms * 1e-3) / 1e9 if ms > 0 else None
+    out["k_verify_l2"] = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": a / HBM_PEAK_GBS if a else None, "traffic": TRAFFIC_BYTES["k_verify_l2"],
+                          "work_per_launch": byts, "launch_ms": ms,
+                          "work": "24 B per candidate + 4*dim B per float32 recheck + 8 B per answer"}
+    return out
+
+
+def calibrate_copy(torch):
+    """A plain device copy of 256 MiB (one copy kernel), for scaling the
+    profiler's HBM byte counters."""
+    x = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log("calibration copy: 268435456 bytes read, 268435456 written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,8 +313,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--queries", type=int, default=None, help="cap queries per kind (default: full)")
     ap.add_argument("--plain-queries", type=int, default=2000)
-    ap.add_argument("--cpu-queries", type=int, default=1000)
+    ap.add_argument("--cpu-queries", type=int, default=1600)
     ap.add_argument("--skip-dna", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run one 256 MiB device copy first (profiling)")
     ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the batch benchmark")
     ap.add_argument("--serve-rate", type=float, default=50000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-s", type=float, default=4.0, help="measured trace length, s")
@@ -289,6 +336,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gts.library()
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     if args.serving:
         sv = run_serving(args, gts, synth, torch, np)
         m = sv["measured"]
@@ -311,17 +360,10 @@ def main():
         log(f"dna: {dna['qps']:.0f} q/s, {dna['ms_per_step']:.2f} ms/step, stages {dna['stats']['ms_stage']}")
 
     st = l2["stats"]
-    # dominant kernel: the bf16 MFMA slab sweep (stage "cands"); its work is
-    # every (query, object) pair of the computed (256-object slab, 16-query
-    # block) units, 2 * 128 flops each
-    mfma_ms = st["ms_stage"]["cands"]
-    pairs = st["tile_pairs"] * 16 * 256
-    flops = 2.0 * 128 * pairs
-    achieved = flops / (mfma_ms * 1e-3) / 1e12 if mfma_ms > 0 else None
-    roof = {"bound": "mfma", "kernel": "k_mfma_sweep", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": (achieved / BF16_PEAK_TFLOPS) if achieved else None, "traffic": None,
-            "flops_per_launch": flops, "launch_ms": mfma_ms,
-            "work": "(256-object slab, 16-query block) units x 16 x 256 pairs x 2*128 flop"}
+    roofs = rooflines(st, l2["dim"])
+    # the roofline reported is the one of the kernel that takes longest
+    dom = max(roofs, key=lambda name: roofs[name]["launch_ms"])
+    roof = dict(roofs[dom], kernel=dom)
     cpu = None
     if args.cpu_queries > 0:
         log("cpu baseline (oracle brute force) ...")
@@ -351,6 +393,7 @@ def main():
         "plain_qps": l2.get("plain_qps"),
         "plain_queries": l2.get("plain_queries"),
         "roofline": roof,
+        "rooflines": roofs,
         "cpu_baseline": cpu,
     }
     if dna:
