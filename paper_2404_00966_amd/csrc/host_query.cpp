@@ -31,7 +31,7 @@ enum Ws {
     W_Q32, W_Q16, W_QN, W_QE, W_QP, W_BASE, W_T, W_THR, W_KQ, W_HOME, W_QCHARS, W_QOFF, W_PEQ, W_QLEN,
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
-    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS,
+    W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
@@ -312,7 +312,16 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
     uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
     k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters};
-    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), st);
+    std::vector<int32_t> blk_q;   // L2: queries beyond one wave's share
+    if (l2)
+        for (int64_t q = 0; q < ng; q++)
+            if (h_qoff[q + 1] - h_qoff[q] > kWaveSortCap) blk_q.push_back((int32_t)q);
+    int32_t *dblk = nullptr;
+    if (!blk_q.empty()) {
+        dblk = wsp<int32_t>(cx, W_BLKQ, blk_q.size());
+        GTS_HIP(hipMemcpyAsync(dblk, blk_q.data(), blk_q.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    }
+    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)blk_q.size(), st);
     else k::verify_edit(va, oe, qe, st);
     rec(cx, 6);
 

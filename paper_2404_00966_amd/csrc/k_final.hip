@@ -113,14 +113,14 @@ __device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr
     *lo = sqrtf(fmaxf(est - eps, 0.f)) - err;
 }
 
-__global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
-                                                   float eps_b, float eps_c)
+// One workgroup for query q (its candidates more than one wave verifies):
+// kNN interval selection by a sort of the upper ends, rechecks by 16-lane
+// groups, keys sorted in LDS (s_keys, kSortCap) or in the query's scratch run.
+__device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
+                                float eps_b, float eps_c, int64_t q, uint64_t *s_keys)
 {
-    __shared__ uint64_t s_keys[kSortCap];
     __shared__ int s_n;
     __shared__ float s_ub;
-    const int64_t q = blockIdx.x;
-    if (q >= a.nq) return;
     const int64_t seg0 = a.qoff[q];
     const int ns = (int)(a.qoff[q + 1] - seg0);
     const int k = a.kq ? a.kq[q] : 0;
@@ -217,13 +217,182 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
 
-void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, hipStream_t st)
+// Bitonic sort of n (a power of two) keys in LDS by one wave (lanes in
+// lockstep: a wave barrier orders the passes).
+__device__ void wave_bitonic_sort(uint64_t *a, int n)
+{
+    const int lane = threadIdx.x & 63;
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i < (n >> 1); i += 64) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave for query q (at most kWaveSortCap candidates).  kNN: the k-th
+// smallest upper interval end over the candidates, found by a 32-step
+// binary search over the float bits (counting with ballots), bounds the
+// answer set; only candidates whose lower end can reach it are rechecked.
+// Rechecks: 16 lanes per candidate, two candidates per group in flight, the
+// same strided float32 sum as every other exact L2 distance here.  Kept keys
+// are compacted with ballots into the wave's LDS run and sorted there.
+__device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
+                               float eps_b, float eps_c, int64_t q, uint64_t *keys)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t seg0 = a.qoff[q];
+    const int ns = (int)(a.qoff[q + 1] - seg0);
+    const int k = a.kq ? a.kq[q] : 0;
+    const float base = a.base[q];
+    const float qnn = qv.qn[q];
+    const float qerr = qv.qe[q];
+    const Cand *g = a.grouped + seg0;
+    float ub = INFINITY;
+    if (k > 0 && ns > k) {
+        for (int i = lane; i < ns; i += 64) {
+            float lo, hi;
+            l2_interval(g[i], qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            keys[i] = __float_as_uint(hi);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // smallest v with #{hi <= v} >= k (hi >= 0, so float order = bit order)
+        uint32_t lo_v = 0u, hi_v = 0xffffffffu;
+        while (lo_v < hi_v) {
+            const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
+            int c = 0;
+            for (int i0 = 0; i0 < ns; i0 += 64) {
+                const int i = i0 + lane;
+                c += __popcll(dev::ballot(i < ns && (uint32_t)keys[i] <= mid));
+            }
+            if (c >= k) hi_v = mid;
+            else lo_v = mid + 1u;
+        }
+        ub = __uint_as_float(lo_v) * (1.f + 4.f * delta);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const int grp = lane >> 4, sl = lane & 15;
+    const float *qrow = qv.Q32 + (size_t)q * o.dp;
+    long long verified = 0;
+    int nk = 0;
+    for (int i0 = 0; i0 < ns; i0 += 8) {
+        const int ia = i0 + grp, ib = i0 + 4 + grp;
+        const bool va = ia < ns, vb = ib < ns;
+        Cand ca, cb;
+        ca.q = cb.q = 0;
+        ca.pos = cb.pos = -1;
+        ca.val = cb.val = 0;
+        if (va) ca = g[ia];
+        if (vb) cb = g[ib];
+        bool na = va && ca.pos >= 0, nb = vb && cb.pos >= 0;
+        if (k > 0 && ub < INFINITY) {
+            float lo, hi;
+            if (na) {
+                l2_interval(ca, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                na = lo <= ub;
+            }
+            if (nb) {
+                l2_interval(cb, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                nb = lo <= ub;
+            }
+        }
+        const float *xa = na ? o.X32 + (size_t)ca.pos * o.dp : qrow;
+        const float *xb = nb ? o.X32 + (size_t)cb.pos * o.dp : qrow;
+        float acca = 0.f, accb = 0.f;
+        if (na || nb) {
+            for (int d = sl; d < o.dp; d += 16) {
+                const float qd = qrow[d];
+                const float dfa = qd - xa[d];
+                const float dfb = qd - xb[d];
+                acca = fmaf(dfa, dfa, acca);
+                accb = fmaf(dfb, dfb, accb);
+            }
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            acca += __shfl_xor(acca, off, 16);
+            accb += __shfl_xor(accb, off, 16);
+        }
+        auto decide = [&](bool valid, const Cand &c, bool need, float acc, uint64_t *key) {
+            if (!valid) return false;
+            if (c.pos < 0) {
+                *key = c.val;
+                return true;
+            }
+            if (!need) return false;
+            verified++;
+            const float d = sqrtf(acc);
+            *key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
+            return k > 0 || d <= base;
+        };
+        uint64_t ka = 0, kb = 0;
+        const bool keepa = sl == 0 && decide(va, ca, na, acca, &ka);
+        const bool keepb = sl == 0 && decide(vb, cb, nb, accb, &kb);
+        const uint64_t ma = dev::ballot(keepa), mb = dev::ballot(keepb);
+        if (keepa) keys[nk + dev::lanes_below(ma)] = ka;
+        nk += __popcll(ma);
+        if (keepb) keys[nk + dev::lanes_below(mb)] = kb;
+        nk += __popcll(mb);
+    }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
+    if (lane == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    const int P = dev::next_pow2(nk > 1 ? nk : 1);
+    for (int i = nk + lane; i < P; i += 64) keys[i] = ~0ull;
+    wave_bitonic_sort(keys, P);
+    const int nout = (k > 0 && k < nk) ? k : nk;
+    for (int j = lane; j < nout; j += 64) a.out_keys[seg0 + j] = keys[j];
+    if (lane == 0) a.out_count[q] = (uint32_t)nout;
+}
+
+// One launch for both forms: workgroups [0, n_blk) take the queries of
+// blk_q (more than kWaveSortCap candidates) one each, the rest take four
+// queries each, one per wave, skipping those; the long workgroups start first
+// and overlap the bulk of the work.
+__global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
+                                                   float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
+                                                   int n_blk)
+{
+    __shared__ uint64_t s_mem[kSortCap];
+    static_assert(4 * kWaveSortCap <= kSortCap, "wave runs must fit the workgroup's LDS");
+    if ((int)blockIdx.x < n_blk) {
+        verify_l2_block(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem);
+        return;
+    }
+    const int wave = threadIdx.x >> 6;
+    const int64_t q = (int64_t)(blockIdx.x - n_blk) * 4 + wave;
+    if (q >= a.nq) return;
+    const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
+    if (ns > kWaveSortCap) return;
+    verify_l2_wave(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap);
+}
+
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
+               hipStream_t st)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
-    hipLaunchKernelGGL(k_verify_l2, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c);
+    const unsigned grid = (unsigned)(n_blk + (a.nq + 3) / 4);
+    hipLaunchKernelGGL(k_verify_l2, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q, n_blk);
     check_launch(__func__);
 }
 

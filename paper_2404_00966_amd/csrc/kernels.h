@@ -194,7 +194,9 @@ struct VerifyArgs {
     uint32_t *out_count;       // [nq]
     unsigned long long *counters;
 };
-void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, hipStream_t st);
+// blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
+               hipStream_t st);
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st);
 
 // CSR assembly: ids[res_off[q] + j] and dist from out_keys[qoff[q] + j].
