@@ -121,6 +121,11 @@ typedef struct {
     double ms_stage[8];      /* device time per stage (GTS_STAGE_*)            */
     int64_t groups;          /* query groups run one after another (>1 when the
                                 memory budget forced the two-stage split)      */
+    int64_t bound_window;    /* L2 kNN: objects per query that bound the k-th
+                                distance in this call (the tuned knob)         */
+    int64_t tuning;          /* 1 while the query context is still trying
+                                settings (answers are exact either way)        */
+    int64_t bound_evals;     /* exact distances computed for the kNN bounds   */
 } gts_stats;
 
 #define GTS_STAGE_PREP 0     /* query -> pivot distances, query tiles          */

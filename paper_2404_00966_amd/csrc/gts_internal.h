@@ -202,12 +202,49 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
 // the searches issued on one stream.  An index has a default context on its
 // own stream; more contexts let searches of one index run concurrently (the
 // index data is only read by a search).
+// Online tuning of the L2 kNN bound window (objects per query whose exact
+// distances bound the k-th distance): a small window is cheap but gives a
+// loose bound and more candidates downstream, a large one the reverse.  The
+// context tries each setting on a few batches, keeps the one with the lowest
+// time per query, and tries again when the batch size moves by more than 4x.
+// Answers do not depend on the setting.
+struct BoundTuner {
+    static constexpr int kChoices = 4;
+    static constexpr int kTrials = 2;         // batches per setting
+    static constexpr int kWindow[kChoices] = {128, 256, 512, 1024};
+    int trial = 0;                            // next trial; kChoices*kTrials: done
+    double ms_per_q[kChoices] = {};
+    int best = 2;
+    int64_t tuned_nq = 0;
+    int pick(int64_t nq)
+    {
+        if (trial >= kChoices * kTrials && (nq > 4 * tuned_nq || 4 * nq < tuned_nq)) {
+            trial = 0;
+            for (double &v : ms_per_q) v = 0.0;
+        }
+        return trial < kChoices * kTrials ? trial % kChoices : best;
+    }
+    void record(int choice, int64_t nq, double ms)
+    {
+        if (trial >= kChoices * kTrials || choice != trial % kChoices) return;
+        ms_per_q[choice] += ms / (double)nq;
+        if (++trial == kChoices * kTrials) {
+            best = 0;
+            for (int c = 1; c < kChoices; c++)
+                if (ms_per_q[c] < ms_per_q[best]) best = c;
+            tuned_nq = nq;
+        }
+    }
+    bool tuning() const { return trial < kChoices * kTrials; }
+};
+
 struct QueryCtx {
     hipStream_t stream = nullptr;
     DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
     hipEvent_t ev[9] = {};
     bool timing = false;
     gts_stats stats{};
+    BoundTuner tuner;
     QueryCtx() = default;
     QueryCtx(const QueryCtx &) = delete;
     QueryCtx &operator=(const QueryCtx &) = delete;

@@ -360,6 +360,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             const gts_query_opts *opts, gts_result *out)
 {
     const double t_start = now_ms();
+    int tune_choice = -1;   // the bound window tried in this call (L2 kNN)
     GTS_CHECK(out != nullptr, GTS_EINVAL, "null result");
     GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
     hipStream_t st = cx->stream;
@@ -615,8 +616,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                 near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
                 k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
             }
+            tune_choice = cx->tuner.pick(nq);
+            const int window = BoundTuner::kWindow[tune_choice];
+            cx->stats.bound_window = window;
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
-                          d.dp, qv.Q32, kq, nq, d.tomb.as<uint32_t>(), 512, base, st);
+                          d.dp, qv.Q32, kq, nq, d.tomb.as<uint32_t>(), window, base, counters, st);
         } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
@@ -748,10 +752,13 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     if (cx->stats.leaf_pairs == 0) cx->stats.leaf_pairs = (int64_t)hc[1];
     cx->stats.tile_pairs = (int64_t)hc[2];
     cx->stats.verified = (int64_t)hc[3];
+    cx->stats.bound_evals = (int64_t)hc[4];
     cx->stats.results = total;
     for (int i = 0; i < 8; i++) cx->stats.ms_stage[i] = stage_ms[i];
     cx->stats.groups = (int64_t)groups.size();
     cx->stats.ms_total = now_ms() - t_start;
+    if (tune_choice >= 0) cx->tuner.record(tune_choice, nq, cx->stats.ms_total);
+    cx->stats.tuning = cx->tuner.tuning() ? 1 : 0;
 }
 
 void free_result(gts_result *r)

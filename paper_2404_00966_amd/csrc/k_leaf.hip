@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
                                                     int dp, const float *__restrict__ Q32,
                                                     const int32_t *__restrict__ kq, int64_t nq,
                                                     const uint32_t *__restrict__ tomb, int target,
-                                                    float *__restrict__ tq)
+                                                    float *__restrict__ tq, unsigned long long *__restrict__ counters)
 {
     __shared__ float s_d[kWinObj];
     __shared__ int s_first[kNearLeaves], s_start[kNearLeaves + 1];
@@ -277,6 +277,7 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
     }
     __syncthreads();
     const int nl = s_nl, count = s_start[nl];
+    if (threadIdx.x == 0) atomicAdd(&counters[CNT_BOUND_EVALS], (unsigned long long)count);
     if (count < k) {
         if (threadIdx.x == 0) tq[q] = INFINITY;
         return;
@@ -318,12 +319,12 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
 
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
-                hipStream_t st)
+                unsigned long long *counters, hipStream_t st)
 {
     if (nq == 0) return;
     require(dp <= 128, "bound_near: rows wider than 128 floats");
     hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
-                       kq, nq, tomb, target, tq);
+                       kq, nq, tomb, target, tq, counters);
     check_launch(__func__);
 }
 

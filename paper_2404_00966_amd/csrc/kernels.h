@@ -9,7 +9,7 @@ namespace gts {
 namespace k {
 
 // Slots of the device counters behind gts_stats.
-enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3 };
+enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3, CNT_BOUND_EVALS = 4 };
 
 // Raise the launch error left by the wrapper `name` (a bad grid or resource
 // request), so that it surfaces at its own call and not at a later one.
@@ -212,7 +212,7 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
                int ntiles, uint64_t *leaf_mask, hipStream_t st);
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
-                hipStream_t st);
+                unsigned long long *counters, hipStream_t st);
 void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st);
 void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width, int32_t *dst, hipStream_t st);
 void gather_strings(const uint8_t *src, const int64_t *src_off, const int32_t *perm, int64_t n, const int64_t *dst_off,

@@ -55,7 +55,8 @@ class _Stats(C.Structure):
     _fields_ = [("nq", C.c_int64), ("node_tests", C.c_int64), ("leaf_pairs", C.c_int64),
                 ("tile_pairs", C.c_int64), ("candidates", C.c_int64), ("verified", C.c_int64),
                 ("results", C.c_int64), ("ms_total", C.c_double), ("ms_stage", C.c_double * 8),
-                ("groups", C.c_int64)]
+                ("groups", C.c_int64), ("bound_window", C.c_int64), ("tuning", C.c_int64),
+                ("bound_evals", C.c_int64)]
 
 
 class _Info(C.Structure):
