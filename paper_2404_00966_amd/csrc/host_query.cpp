@@ -32,6 +32,7 @@ enum Ws {
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
+    W_SORT_TMP, W_HOME2,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
@@ -511,51 +512,42 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
                           cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, qcells0, qcnt0, counters, dorder, st);
     }
-    if (nq > 1) {
+    if (nq > 1 && l2 && d.lpad > 0) {
+        // home = nearest leaf pivot; the order comes from a device sort
+        near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
+        k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
+        const size_t tb = k::home_sort_bytes(nq, d.lpad);
+        int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
+        k::home_sort(near, nq, d.lpad, reinterpret_cast<uint32_t *>(home), wsp<uint32_t>(cx, W_HOME2, nq), dperm,
+                     wsp<uint8_t>(cx, W_SORT_TMP, tb), tb, st);
+        permuted = true;
+    } else if (nq > 1 && edit_cells) {
         std::vector<int32_t> hh(nq);
-        if (l2 && d.lpad > 0) {
-            near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
-            k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
-            std::vector<int32_t> hn((size_t)nq * k::kNearLeaves);
-            GTS_HIP(hipMemcpyAsync(hn.data(), near, hn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            GTS_HIP(hipStreamSynchronize(st));
-            for (int64_t q = 0; q < nq; q++) hh[q] = hn[(size_t)q * k::kNearLeaves];
-        } else if (edit_cells) {
-            k::first_cell(qcells0, qcnt0, d.n_centres, nq, home, st);
-            std::vector<int32_t> hp(nq);
-            GTS_HIP(hipMemcpyAsync(hp.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            GTS_HIP(hipStreamSynchronize(st));
-            for (int64_t p = 0; p < nq; p++) hh[order[p]] = hp[p];
-        }
+        k::first_cell(qcells0, qcnt0, d.n_centres, nq, home, st);
+        std::vector<int32_t> hp(nq);
+        GTS_HIP(hipMemcpyAsync(hp.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        for (int64_t p = 0; p < nq; p++) hh[order[p]] = hp[p];
         perm.resize(nq);
         for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
-        if (l2 ? d.lpad > 0 : edit_cells) {
-            std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hh[x] < hh[y]; });
-            for (int64_t q = 0; q < nq && !permuted; q++) permuted = perm[q] != q;
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hh[x] < hh[y]; });
+        for (int64_t q = 0; q < nq && !permuted; q++) permuted = perm[q] != q;
+        if (permuted) {
+            int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
+            GTS_HIP(hipMemcpyAsync(dperm, perm.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         }
     }
     if (permuted) {
-        int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
-        GTS_HIP(hipMemcpyAsync(dperm, perm.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        std::vector<float> pb(nq);
-        std::vector<int32_t> pk(nq);
-        for (int64_t i = 0; i < nq; i++) {
-            pb[i] = hbase[perm[i]];
-            pk[i] = hk[perm[i]];
-        }
-        hbase.swap(pb);
-        hk.swap(pk);
-        if (edit_cells && b.any_knn) {
-            // the kNN bounds are already in `base`: permute them on the device
-            float *tb = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, 1));
-            k::gather_rows(base, dperm, nq, 1, tb, st);
-            GTS_HIP(hipMemcpyAsync(base, tb, nq * sizeof(float), hipMemcpyDeviceToDevice, st));
-        } else {
-            GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
-        }
-        GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        // everything per query follows the permutation on the device
+        const int32_t *dperm = cx->ws[W_PERM].as<int32_t>();
+        float *tb = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
+        k::gather_rows(base, dperm, nq, 1, tb, st);
+        GTS_HIP(hipMemcpyAsync(base, tb, nq * sizeof(float), hipMemcpyDeviceToDevice, st));
+        int32_t *tk = wsp<int32_t>(cx, W_TMP2, std::max<size_t>((size_t)nq * k::kNearLeaves, (size_t)nq));
+        k::gather_i32(kq, dperm, nq, 1, tk, st);
+        GTS_HIP(hipMemcpyAsync(kq, tk, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
         float *QPd = cx->ws[W_QP].as<float>();
-        float *tmpf = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
+        float *tmpf = tb;
         k::gather_rows(QPd, dperm, nq, mpad, tmpf, st);
         GTS_HIP(hipMemcpyAsync(QPd, tmpf, (size_t)nq * mpad * sizeof(float), hipMemcpyDeviceToDevice, st));
         if (l2) {
@@ -565,7 +557,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
                          const_cast<float *>(qv.qn), const_cast<float *>(qv.qe), 0.f, st);
             if (near) {
-                int32_t *tmpi = wsp<int32_t>(cx, W_TMP2, (size_t)nq * k::kNearLeaves);
+                int32_t *tmpi = wsp<int32_t>(cx, W_TMP2, std::max<size_t>((size_t)nq * k::kNearLeaves, (size_t)nq));
                 k::gather_i32(near, dperm, nq, k::kNearLeaves, tmpi, st);
                 GTS_HIP(hipMemcpyAsync(near, tmpi, (size_t)nq * k::kNearLeaves * sizeof(int32_t),
                                        hipMemcpyDeviceToDevice, st));
@@ -681,6 +673,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             }
     }
     std::vector<int64_t> offs(nq + 1, 0);     // caller order
+    if (permuted && perm.empty()) {
+        perm.resize(nq);   // the order was made on the device
+        GTS_HIP(hipMemcpyAsync(perm.data(), cx->ws[W_PERM].p, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    }
     if (permuted) {
         std::vector<int64_t> cnt(nq);
         for (int64_t i = 0; i < nq; i++) cnt[perm[i]] = offs_b[i + 1] - offs_b[i];

@@ -8,13 +8,40 @@ namespace gts {
 namespace k {
 
 
-__global__ void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
-                             uint32_t *__restrict__ qcount)
+// Runs of equal query among a wave's 64 consecutive candidates (the sweep
+// writes each lane's hits of one tile next to each other): the first lane of
+// a run makes one atomic for the whole run.  *head_lane = first lane of this
+// lane's run; returns the run length at its first lane, 0 elsewhere.
+__device__ __forceinline__ int query_run(int32_t q, bool valid, int *head_lane)
+{
+    const int lane = dev::lane_id();
+    const int32_t prev = __shfl_up(q, 1, 64);
+    const bool head = valid && (lane == 0 || prev != q);
+    // both ballots by the whole wave, before any lane leaves
+    const uint64_t hm = dev::ballot(head);
+    const int nvalid = __popcll(dev::ballot(valid));          // valid lanes form a prefix
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    *head_lane = 63 - __clzll((long long)(hm & upto));
+    if (!head) return 0;
+    const uint64_t after = hm & ~upto;
+    const int end = after ? __ffsll((long long)after) - 1 : nvalid;
+    return end - lane;
+}
+
+__global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
+                                                    int64_t cap, uint32_t *__restrict__ qcount)
 {
     int64_t n = *count;
     if (n > cap) n = cap;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&qcount[c[i].q], 1u);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
+        const int64_t i = b0 + dev::lane_id();
+        const bool valid = i < n;
+        const int32_t q = valid ? c[i].q : -1;
+        int hl;
+        const int len = query_run(q, valid, &hl);
+        if (len) atomicAdd(&qcount[q], (uint32_t)len);
+    }
 }
 
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st)
@@ -56,16 +83,26 @@ void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
     check_launch(__func__);
 }
 
-__global__ void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count, int64_t cap,
-                                const int64_t *__restrict__ qoff, uint32_t *__restrict__ cursor,
-                                Cand *__restrict__ grouped)
+__global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
+                                                       int64_t cap, const int64_t *__restrict__ qoff,
+                                                       uint32_t *__restrict__ cursor, Cand *__restrict__ grouped)
 {
     int64_t n = *count;
     if (n > cap) n = cap;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const Cand cd = c[i];
-        const uint32_t slot = atomicAdd(&cursor[cd.q], 1u);
-        grouped[qoff[cd.q] + slot] = cd;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = dev::lane_id();
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
+        const int64_t i = b0 + lane;
+        const bool valid = i < n;
+        Cand cd;
+        cd.q = -1;
+        if (valid) cd = c[i];
+        int hl;
+        const int len = query_run(cd.q, valid, &hl);
+        uint32_t base = 0;
+        if (len) base = atomicAdd(&cursor[cd.q], (uint32_t)len);
+        base = __shfl(base, hl, 64);
+        if (valid) grouped[qoff[cd.q] + base + (uint32_t)(lane - hl)] = cd;
     }
 }
 
@@ -376,8 +413,13 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
         verify_l2_block(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem);
         return;
     }
+    // wave mode: past the workgroup-mode blocks (rounded up to 8), XCD x
+    // takes the x-th contiguous eighth of the 4-query blocks
     const int wave = threadIdx.x >> 6;
-    const int64_t q = (int64_t)(blockIdx.x - n_blk) * 4 + wave;
+    const int nb8 = (n_blk + 7) & ~7;
+    if ((int)blockIdx.x < nb8) return;
+    const int64_t w = blockIdx.x - nb8, per = (gridDim.x - nb8) >> 3;
+    const int64_t q = ((w & 7) * per + (w >> 3)) * 4 + wave;
     if (q >= a.nq) return;
     const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
     if (ns > kWaveSortCap) return;
@@ -391,7 +433,7 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
-    const unsigned grid = (unsigned)(n_blk + (a.nq + 3) / 4);
+    const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
     hipLaunchKernelGGL(k_verify_l2, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q, n_blk);
     check_launch(__func__);
 }
@@ -407,7 +449,10 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
     __shared__ uint64_t s_peq[257 * 4];
     __shared__ uint8_t s_lut[256];
     __shared__ int s_n;
-    const int64_t q = blockIdx.x;
+    // gridDim.x is a multiple of 8: XCD x takes the x-th contiguous eighth of
+    // the queries, whose neighbours share candidates in that XCD's L2
+    const int64_t per = gridDim.x >> 3;
+    const int64_t q = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (q >= a.nq) return;
     const int64_t seg0 = a.qoff[q];
     const int ns = (int)(a.qoff[q + 1] - seg0);
@@ -456,7 +501,7 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st)
 {
     if (a.nq == 0) return;
-    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
+    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)((a.nq + 7) / 8 * 8)), dim3(256), 0, st, a, o, qv);
     check_launch(__func__);
 }
 

@@ -30,10 +30,12 @@ __device__ __forceinline__ bf16x8_t frag(uint4 v)
 }
 
 // ---------------------------------------------------------------------------
-// Nearest leaf pivots.  One wave per 16-query block (the MFMA B operand);
-// leaf pivots stream through as A fragments, 16 per MFMA row block.  Each
-// lane keeps a sorted top-NB of its 16 x (Lpad/16) estimates; the four lanes
-// holding the same query merge through LDS.
+// Nearest leaf pivots.  One workgroup per 16-query block (the MFMA B operand,
+// in registers); its four waves split the leaf pivots, which stream through
+// as A fragments, 16 per MFMA row block, the next block's fragments loading
+// while the current one is multiplied.  Each lane keeps a sorted top-NB of
+// its estimates (insertion by selects, no branches per slot); the 16 lists
+// holding one query (4 lanes x 4 waves) merge through LDS.
 // ---------------------------------------------------------------------------
 template <int KS, int NB>
 __global__ __launch_bounds__(256) void k_leaf_near(const uint4 *__restrict__ PL16t, const float *__restrict__ pln,
@@ -43,8 +45,7 @@ __global__ __launch_bounds__(256) void k_leaf_near(const uint4 *__restrict__ PL1
     __shared__ float s_d[4][64][NB];
     __shared__ int32_t s_l[4][64][NB];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t blk = (int64_t)blockIdx.x * 4 + wave;      // 16-query block
-    const bool live = blk * 16 < nq;
+    const int64_t blk = blockIdx.x;                        // 16-query block
     float bd[NB];
     int32_t bl[NB];
 #pragma unroll
@@ -52,38 +53,49 @@ __global__ __launch_bounds__(256) void k_leaf_near(const uint4 *__restrict__ PL1
         bd[i] = INFINITY;
         bl[i] = -1;
     }
-    if (live) {
-        uint4 B[KS];
+    uint4 B[KS];
 #pragma unroll
-        for (int s = 0; s < KS; s++) B[s] = Q16t[(blk * KS + s) * 64 + lane];
-        const int rg = lane >> 4;
-        for (int64_t g = 0; g < lpad / 16; g++) {
-            floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < KS; s++) B[s] = Q16t[(blk * KS + s) * 64 + lane];
+    const int rg = lane >> 4;
+    const int64_t G = lpad / 16;
+    uint4 A[KS];
+    if (wave < G) {
 #pragma unroll
-            for (int s = 0; s < KS; s++)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(PL16t[(g * KS + s) * 64 + lane]), frag(B[s]), acc,
-                                                               0, 0, 0);
+        for (int s = 0; s < KS; s++) A[s] = PL16t[((int64_t)wave * KS + s) * 64 + lane];
+    }
+    for (int64_t g = wave; g < G; g += 4) {
+        uint4 An[KS];
+        const int64_t gn = g + 4 < G ? g + 4 : g;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int32_t leaf = (int32_t)(16 * g + 4 * rg + e);
-                const float v = fmaf(-2.f, acc[e], pln[leaf]);   // d^2 - ||q||^2
-                if (v < bd[NB - 1]) {
-                    float cv = v;
-                    int32_t cl = leaf;
+        for (int s = 0; s < KS; s++) An[s] = PL16t[(gn * KS + s) * 64 + lane];
+        float pv[4];
 #pragma unroll
-                    for (int i = 0; i < NB; i++) {
-                        if (cv < bd[i]) {
-                            const float td = bd[i];
-                            const int32_t tl = bl[i];
-                            bd[i] = cv;
-                            bl[i] = cl;
-                            cv = td;
-                            cl = tl;
-                        }
-                    }
+        for (int e = 0; e < 4; e++) pv[e] = pln[16 * g + 4 * rg + e];
+        floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(A[s]), frag(B[s]), acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int32_t leaf = (int32_t)(16 * g + 4 * rg + e);
+            const float v = fmaf(-2.f, acc[e], pv[e]);   // d^2 - ||q||^2
+            if (v < bd[NB - 1]) {
+                float cv = v;
+                int32_t cl = leaf;
+#pragma unroll
+                for (int i = 0; i < NB; i++) {
+                    const bool lt = cv < bd[i];
+                    const float td = lt ? bd[i] : cv;
+                    const int32_t tl = lt ? bl[i] : cl;
+                    bd[i] = lt ? cv : bd[i];
+                    bl[i] = lt ? cl : bl[i];
+                    cv = td;
+                    cl = tl;
                 }
             }
         }
+#pragma unroll
+        for (int s = 0; s < KS; s++) A[s] = An[s];
     }
 #pragma unroll
     for (int i = 0; i < NB; i++) {
@@ -91,25 +103,34 @@ __global__ __launch_bounds__(256) void k_leaf_near(const uint4 *__restrict__ PL1
         s_l[wave][lane][i] = bl[i];
     }
     __syncthreads();
-    if (!live || lane >= 16) return;
+    if (wave != 0 || lane >= 16) return;
     const int64_t q = blk * 16 + lane;
     if (q >= nq) return;
-    // merge the four lists of this query (lanes lane, lane+16, lane+32, lane+48)
-    int idx[4] = {0, 0, 0, 0};
+    // merge the 16 lists of this query: list j = (wave j >> 2, lane lane + 16 (j & 3))
+    int idx[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) idx[j] = 0;
     for (int i = 0; i < NB; i++) {
         int best = -1;
         float bv = INFINITY;
-        for (int j = 0; j < 4; j++) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
             if (idx[j] < NB) {
-                const float v = s_d[wave][lane + 16 * j][idx[j]];
+                const float v = s_d[j >> 2][lane + 16 * (j & 3)][idx[j]];
                 if (best < 0 || v < bv) {
                     bv = v;
                     best = j;
                 }
             }
         }
-        near[q * NB + i] = s_l[wave][lane + 16 * best][idx[best]];
-        idx[best]++;
+        int32_t leaf = -1;
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if (j == best) {
+                leaf = s_l[j >> 2][lane + 16 * (j & 3)][idx[j]];
+                idx[j]++;
+            }
+        near[q * NB + i] = leaf;
     }
 }
 
@@ -117,8 +138,7 @@ void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps
                int32_t *near, hipStream_t st)
 {
     if (nq == 0) return;
-    const int64_t blocks16 = (nq + 15) / 16;
-    const unsigned grid = (unsigned)((blocks16 + 3) / 4);
+    const unsigned grid = (unsigned)((nq + 15) / 16);
 #define LN(KS)                                                                                              \
     hipLaunchKernelGGL((k_leaf_near<KS, kNearLeaves>), dim3(grid), dim3(256), 0, st,                        \
                        reinterpret_cast<const uint4 *>(PL16t), pln, lpad, reinterpret_cast<const uint4 *>(Q16t), \
@@ -240,8 +260,16 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
 // objects of the query's nearest leaves (in order, while at most kWinObj
 // objects and until at least max(k, target) were taken); the k-th smallest
 // live distance bounds the k-th nearest neighbour distance from above.
+//
+// One workgroup per query.  The queries arrive sorted by home leaf, so
+// neighbouring queries read the same leaves: consecutive queries go to the
+// same XCD (workgroups are dealt to the 8 XCDs round robin), where the second
+// read of a leaf hits that XCD's L2.  The window plan is one wave-wide scan;
+// object rows and tombstone words of kBoundUnroll objects per 16-lane group
+// are loaded before any of them is used.
 // ---------------------------------------------------------------------------
 constexpr int kWinObj = 2048;
+constexpr int kBoundUnroll = 4;
 
 __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ near,
                                                     const int32_t *__restrict__ leaf_first,
@@ -254,26 +282,35 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
     __shared__ float s_d[kWinObj];
     __shared__ int s_first[kNearLeaves], s_start[kNearLeaves + 1];
     __shared__ int s_nl;
-    const int64_t q = blockIdx.x;
+    // gridDim.x is a multiple of 8: XCD x (= blockIdx.x % 8) takes the x-th
+    // contiguous eighth of the queries
+    const int64_t per = gridDim.x >> 3;
+    const int64_t q = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (q >= nq) return;
     const int k = kq[q];
     if (k <= 0) return;
-    // the window: the nearest leaves in order, while at most kWinObj objects
-    // and until at least max(k, target) were taken
-    if (threadIdx.x == 0) {
+    // the window: a prefix of the nearest leaves; each condition that ends it
+    // (a missing leaf, more than kWinObj objects, max(k, target) reached) is
+    // monotone along the list, so lane i is in the window iff it passes all
+    if (threadIdx.x < 64) {
+        const int i = (int)threadIdx.x;
+        const int32_t leaf = i < kNearLeaves ? near[q * kNearLeaves + i] : -1;
+        const int cnt = leaf >= 0 ? leaf_cnt[leaf] : 0;
+        const int first = leaf >= 0 ? leaf_first[leaf] : 0;
+        int total;
+        const int excl = dev::wave_excl_scan(cnt, &total);
+        const uint64_t missing = dev::ballot(leaf < 0);
         const int want = k > target ? k : target;
-        int count = 0, nl = 0;
-        s_start[0] = 0;
-        for (int i = 0; i < kNearLeaves && count < want; i++) {
-            const int32_t leaf = near[q * kNearLeaves + i];
-            if (leaf < 0) break;
-            const int cnt = leaf_cnt[leaf];
-            if (count + cnt > kWinObj) break;
-            s_first[nl] = leaf_first[leaf];
-            count += cnt;
-            s_start[++nl] = count;
+        const bool in = (missing & ((2ull << i) - 1ull)) == 0 && excl + cnt <= kWinObj && excl < want;
+        const uint64_t inm = dev::ballot(in);
+        if (in) {
+            s_first[i] = first;
+            s_start[i + 1] = excl + cnt;
         }
-        s_nl = nl;
+        if (i == 0) {
+            s_start[0] = 0;
+            s_nl = __popcll(inm);
+        }
     }
     __syncthreads();
     const int nl = s_nl, count = s_start[nl];
@@ -283,33 +320,44 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
         return;
     }
     // 16 lanes per object, strided coordinates, query slice in registers
-    const int sl = threadIdx.x & 15;
+    const int sl = threadIdx.x & 15, grp = (int)(threadIdx.x >> 4);
     float qr[8];
 #pragma unroll
     for (int t = 0; t < 8; t++) qr[t] = sl + 16 * t < dp ? Q32[(size_t)q * dp + sl + 16 * t] : 0.f;
-    for (int j0 = 0; j0 < count; j0 += 16) {
-        const int j = j0 + (int)(threadIdx.x >> 4);
-        const bool ok = j < count;
-        int p = 0;
-        if (ok) {
-            int e = 0;
-            while (e + 1 < nl && s_start[e + 1] <= j) e++;
-            p = s_first[e] + (j - s_start[e]);
-        }
-        const bool live = ok && !((tomb[p >> 5] >> (p & 31)) & 1u);
-        float acc = 0.f;
-        if (live) {
+    for (int j0 = 0; j0 < count; j0 += 16 * kBoundUnroll) {
+        float xv[kBoundUnroll][8];
+        uint32_t tw[kBoundUnroll];
+        int pos[kBoundUnroll];
+#pragma unroll
+        for (int u = 0; u < kBoundUnroll; u++) {
+            const int j = j0 + 16 * u + grp;
+            int p = 0;
+            if (j < count) {
+                int e = 0;
+                while (e + 1 < nl && s_start[e + 1] <= j) e++;
+                p = s_first[e] + (j - s_start[e]);
+            }
+            pos[u] = p;
             const float *x = X32 + (size_t)p * dp;
 #pragma unroll
-            for (int t = 0; t < 8; t++)
-                if (sl + 16 * t < dp) {
-                    const float df = qr[t] - x[sl + 16 * t];
-                    acc = fmaf(df, df, acc);
-                }
+            for (int t = 0; t < 8; t++) xv[u][t] = j < count && sl + 16 * t < dp ? x[sl + 16 * t] : 0.f;
+            tw[u] = j < count ? tomb[p >> 5] : 0u;
         }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-        if (ok && sl == 0) s_d[j] = live ? sqrtf(acc) : INFINITY;
+        for (int u = 0; u < kBoundUnroll; u++) {
+            const int j = j0 + 16 * u + grp;
+            // coordinates beyond dp are zero on both sides: fmaf(0, 0, acc) == acc
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const float df = qr[t] - xv[u][t];
+                acc = fmaf(df, df, acc);
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            const bool dead = (tw[u] >> (pos[u] & 31)) & 1u;
+            if (j < count && sl == 0) s_d[j] = dead ? INFINITY : sqrtf(acc);
+        }
     }
     const int P = dev::next_pow2(count);
     for (int j = count + threadIdx.x; j < P; j += blockDim.x) s_d[j] = INFINITY;
@@ -323,7 +371,8 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
 {
     if (nq == 0) return;
     require(dp <= 128, "bound_near: rows wider than 128 floats");
-    hipLaunchKernelGGL(k_bound_near, dim3((unsigned)nq), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
+    const unsigned grid = (unsigned)((nq + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_bound_near, dim3(grid), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
                        kq, nq, tomb, target, tq, counters);
     check_launch(__func__);
 }

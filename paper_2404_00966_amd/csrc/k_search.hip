@@ -21,58 +21,118 @@ __device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Node filtering at leaf granularity (the child test of Algorithms 4/5 with
-// the global pivots, Lemma 1): a node's box contains the boxes of all its
-// descendants, so a leaf survives the walk from the root exactly when its
-// own box admits the query; testing every leaf directly prunes the same
-// (query, leaf) pairs without the level-by-level walk.  One wave per (64
-// leaves, query tile): lane = leaf, its box in registers; the tile's queries
-// stream through as wave-uniform pivot distances, each lane collecting its
-// 64-bit query mask.  Writes leaf_mask[leaf][tile] for every leaf and tile.
+// Node filtering (the child test of Algorithms 4/5 with the global pivots,
+// Lemma 1) down to the leaves, for every (64-query tile, leaf).  A node's box
+// contains the boxes of its children (minima and maxima over the same
+// objects), so a child can only pass where its parent passes: the walk from
+// the root keeps exactly the leaves whose own box admits the query.  Here
+// the leaves' parents are tested first and the leaves below a parent that no
+// query of the tile passes are not tested at all -- the same masks as the
+// full walk, without its per-level launches.
+//
+// Lane = query: a workgroup is four 64-query tiles (one per wave, the pivot
+// distances and threshold of its query in registers) and a range of leaves,
+// whose boxes and parent boxes pass through LDS in chunks of 64 leaves and
+// are read as broadcasts.  One ballot per tested node gives the tile's 64-bit
+// query mask; lane j keeps the mask of the chunk's leaf j and stores it.
+// Writes leaf_mask[leaf][tile] for every leaf and tile.  `group` is the
+// fanout when it divides 64 (the chunk then holds whole sibling groups),
+// else 64 with no parent test.
 // ---------------------------------------------------------------------------
 template <int MP>
+__device__ __forceinline__ float box_gap_lds(const float *bx, const float *qp)
+{
+    float g = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(bx[i] - qp[i], qp[i] - bx[MP + i]));
+    return g;
+}
+
+template <int MP>
 __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box, int64_t leaf0, int64_t n_leaves,
-                                                  const float *__restrict__ QP, const float *__restrict__ thr,
-                                                  int64_t nq, int ntiles, uint64_t *__restrict__ leaf_mask,
+                                                  int group, bool parents, const float *__restrict__ QP,
+                                                  const float *__restrict__ thr, int64_t nq, int ntiles,
+                                                  int64_t leaves_per_blk, int64_t n_split,
+                                                  uint64_t *__restrict__ leaf_mask,
                                                   unsigned long long *__restrict__ counters)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int tile = dev::uniform((int)(w % ntiles));
-    const int64_t lg = w / ntiles;
-    const int64_t leaf = lg * 64 + lane;
-    if (lg * 64 >= n_leaves) return;
-    float lo[MP], hi[MP];
-    const bool lok = leaf < n_leaves;
+    constexpr int kChunkVec = 64 * 2 * MP / 4;              // float4 per chunk of 64 boxes
+    constexpr int kPerThread = (kChunkVec + 255) / 256;
+    __shared__ float4 s_box4[kChunkVec];
+    __shared__ float s_par[32 * 2 * MP];                    // parents of the chunk (group >= 2)
+    const float *s_box = reinterpret_cast<const float *>(s_box4);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tg = blockIdx.x / n_split, sp = blockIdx.x % n_split;
+    const int tile = (int)(tg * 4 + wave);
+    const bool live = tile < ntiles;                       // no early exit: barriers below
+    const int64_t q = (int64_t)tile * 64 + lane;
+    const bool qok = live && q < nq;
+    float qp[MP];
 #pragma unroll
-    for (int i = 0; i < MP; i++) {
-        lo[i] = lok ? box[(size_t)(leaf0 + leaf) * 2 * MP + i] : INFINITY;
-        hi[i] = lok ? box[(size_t)(leaf0 + leaf) * 2 * MP + MP + i] : -INFINITY;
-    }
-    const int64_t q0 = (int64_t)tile * 64;
-    const int nt = (int)min<int64_t>(64, nq - q0);
-    uint64_t m = 0;
-    for (int j = 0; j < nt; j++) {
-        const float *qp = QP + (size_t)(q0 + j) * MP;
-        const float th = thr[q0 + j];
-        float g = -INFINITY;
+    for (int i = 0; i < MP; i++) qp[i] = qok ? QP[(size_t)q * MP + i] : 0.f;
+    const float th = qok ? thr[q] : -INFINITY;
+    const int64_t lb = sp * leaves_per_blk;
+    const int64_t le = min<int64_t>(n_leaves, lb + leaves_per_blk);
+    long long tests = 0;
+    for (int64_t c0 = lb; c0 < le; c0 += 64) {
+        const int nl = (int)min<int64_t>(64, le - c0);
+        const int np = (nl + group - 1) / group;
+        __syncthreads();
+        // all loads of the chunk are issued before the first is waited for
+        const float4 *src = reinterpret_cast<const float4 *>(box + (size_t)(leaf0 + c0) * 2 * MP);
+        const int nv = nl * 2 * MP / 4;
+        float4 tv[kPerThread];
 #pragma unroll
-        for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(lo[i] - qp[i], qp[i] - hi[i]));
-        m |= (g <= th ? 1ull : 0ull) << j;
+        for (int u = 0; u < kPerThread; u++) {
+            const int i = u * 256 + (int)threadIdx.x;
+            tv[u] = i < nv ? src[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const int64_t par0 = (leaf0 + c0 - 1) / group;      // parent of the chunk's first leaf
+#pragma unroll
+        for (int u = 0; u < kPerThread; u++) {
+            const int i = u * 256 + (int)threadIdx.x;
+            if (i < kChunkVec) s_box4[i] = tv[u];
+        }
+        if (parents)
+            for (int i = threadIdx.x; i < np * 2 * MP; i += blockDim.x) s_par[i] = box[(size_t)par0 * 2 * MP + i];
+        __syncthreads();
+        uint64_t mine = 0;
+        for (int pg = 0; pg < np; pg++) {
+            const int j0 = pg * group, j1 = min(nl, j0 + group);
+            if (parents) {
+                tests++;
+                if (!dev::ballot(box_gap_lds<MP>(s_par + pg * 2 * MP, qp) <= th)) continue;
+            }
+            tests += j1 - j0;
+            for (int j = j0; j < j1; j++) {
+                const uint64_t m = dev::ballot(box_gap_lds<MP>(s_box + j * 2 * MP, qp) <= th);
+                mine = lane == j ? m : mine;
+            }
+        }
+        if (live && lane < nl) leaf_mask[(size_t)(c0 + lane) * ntiles + tile] = mine;
     }
-    if (lok) leaf_mask[(size_t)leaf * ntiles + tile] = m;
-    if (lane == 0) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)nt * (unsigned long long)min<int64_t>(64, n_leaves - lg * 64));
+    if (live && lane == 0 && tests)
+        atomicAdd(&counters[CNT_NODE_TESTS],
+                  (unsigned long long)min<int64_t>(64, nq - (int64_t)tile * 64) * (unsigned long long)tests);
 }
 
 void leaf_box(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles, uint64_t *leaf_mask,
               unsigned long long *counters, hipStream_t st)
 {
     if (nq == 0 || t.n_leaves == 0) return;
-    const int64_t waves = ((t.n_leaves + 63) / 64) * ntiles;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
+    // about 2048 workgroups: leaf ranges of whole 64-leaf chunks
+    const int64_t tgroups = (ntiles + 3) / 4, chunks = (t.n_leaves + 63) / 64;
+    const int64_t per = std::max<int64_t>(1, chunks * tgroups / 2048);
+    const int64_t lpb = 64 * per;
+    const int64_t n_split = (t.n_leaves + lpb - 1) / lpb;
+    const unsigned grid = (unsigned)(tgroups * n_split);
+    // sibling groups align with the 64-leaf chunks when the fanout divides 64
+    // (leaf0 - 1 is a multiple of the fanout)
+    const bool parents = t.levels >= 1 && t.fanout >= 2 && 64 % t.fanout == 0;
+    const int group = parents ? t.fanout : 64;
 #define LBX(MP)                                                                                                  \
-    hipLaunchKernelGGL(k_leaf_box<MP>, dim3(grid), dim3(256), 0, st, t.box_aos, t.leaf0, t.n_leaves, QP, thr, nq, \
-                       ntiles, leaf_mask, counters)
+    hipLaunchKernelGGL(k_leaf_box<MP>, dim3(grid), dim3(256), 0, st, t.box_aos, t.leaf0, t.n_leaves, group,     \
+                       parents, QP, thr, nq, ntiles, lpb, n_split, leaf_mask, counters)
     if (t.mpad == 8) LBX(8);
     else if (t.mpad == 16) LBX(16);
     else LBX(32);

@@ -207,6 +207,11 @@ void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *ou
 constexpr int kNearLeaves = 8;   // nearest leaf pivots kept per query
 void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps, const uint16_t *Q16t, int64_t nq,
                int32_t *near, hipStream_t st);
+// Stable sort of the queries by home leaf (near[q * kNearLeaves], keys in
+// [0, n_keys)): perm[i] = query at position i (k_sort.hip).
+size_t home_sort_bytes(int64_t nq, int64_t n_keys);
+void home_sort(const int32_t *near, int64_t nq, int64_t n_keys, uint32_t *keys, uint32_t *keys_sorted,
+               int32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t st);
 void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
                int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
                int ntiles, uint64_t *leaf_mask, hipStream_t st);
