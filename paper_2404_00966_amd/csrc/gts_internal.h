@@ -48,8 +48,9 @@ constexpr int kSlab = 256;          // objects per MFMA slab (4 waves x 64 rows)
 constexpr int kMaxPivots = 32;      // pivot table rows (padded to 8/16/32)
 constexpr int kMaxMfmaDim = 128;    // largest L2 dimension on the MFMA path
 constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
-constexpr int kSortCap = 2048;      // per-query keys sorted in LDS (more: global scratch)
-constexpr int kWaveSortCap = 512;   // per-query keys verified and sorted by one wave
+constexpr int kSortCap = 2048;      // edit distance: per-query keys sorted in LDS (more: global scratch)
+constexpr int kSortCapL2 = 4096;    // L2: per-query keys sorted in LDS (more: global scratch)
+constexpr int kWaveSortCap = 1024;  // L2: per-query keys verified and sorted by one wave
 constexpr int kWorkspaceSlots = 64;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 

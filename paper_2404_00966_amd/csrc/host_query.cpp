@@ -291,9 +291,10 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     std::vector<int64_t> big(ng, -1);
     int64_t scratch_words = 0;
     bool any_big = false;
+    const int64_t sort_cap = l2 ? kSortCapL2 : kSortCap;
     for (int64_t q = 0; q < ng; q++) {
         const int64_t ns = h_qoff[q + 1] - h_qoff[q];
-        if (ns > kSortCap) {
+        if (ns > sort_cap) {
             int64_t p = 1;
             while (p < ns) p <<= 1;
             big[q] = scratch_words;
@@ -512,7 +513,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
                           cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, qcells0, qcnt0, counters, dorder, st);
     }
-    if (nq > 1 && l2 && d.lpad > 0) {
+    // the nearest-leaf search and the leaf-window kNN bound run on bf16 MFMA
+    // fragments of at most kMaxMfmaDim coordinates; wider rows use the tree
+    // descent bound and keep the caller's order
+    const bool leaf_mfma = l2 && d.lpad > 0 && d.dim <= kMaxMfmaDim;
+    if (nq > 1 && leaf_mfma) {
         // home = nearest leaf pivot; the order comes from a device sort
         near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
         k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
@@ -603,7 +608,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
 
     // ---- kNN bound ------------------------------------------------------------------
     if (nq > 0 && b.any_knn && !edit_cells) {
-        if (l2 && d.lpad > 0) {
+        if (leaf_mfma) {
             if (!near) {
                 near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
                 k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);

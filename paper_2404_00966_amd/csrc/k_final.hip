@@ -150,106 +150,209 @@ __device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr
     *lo = sqrtf(fmaxf(est - eps, 0.f)) - err;
 }
 
-// One workgroup for query q (its candidates more than one wave verifies):
-// kNN interval selection by a sort of the upper ends, rechecks by 16-lane
-// groups, keys sorted in LDS (s_keys, kSortCap) or in the query's scratch run.
-__device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
-                                float eps_b, float eps_c, int64_t q, uint64_t *s_keys)
-{
-    __shared__ int s_n;
-    __shared__ float s_ub;
-    const int64_t seg0 = a.qoff[q];
-    const int ns = (int)(a.qoff[q + 1] - seg0);
-    const int k = a.kq ? a.kq[q] : 0;
-    const float base = a.base[q];
-    const int64_t boff = a.big_off ? a.big_off[q] : -1;
-    const bool big = boff >= 0;
-    uint64_t *keys = big ? a.scratch + boff : s_keys;
-    const int64_t cap = big ? dev::next_pow2(ns) : kSortCap;
-    const float qnn = qv.qn[q];
-    const float qerr = qv.qe[q];
-    const Cand *g = a.grouped + seg0;
+// Exact float32 rechecks of the candidates [i0, i1) of query q by one wave.
+// The candidates stream in steps of 64 (one per lane), the next step loading
+// while the current one is decided: cache entries, whose distance is already
+// known, are kept at once; a kNN candidate whose lower interval end exceeds
+// the bound ub is dropped; the positions that need a recheck go through a
+// ring of 128 entries in LDS, and every 16 of them make a batch: 16 lanes
+// per candidate, four candidates per 16-lane group, rows and ids all
+// requested before any is used, the same strided float32 sum as every other
+// exact L2 distance here (the query slice in registers when the row has at
+// most 128 floats).  emit(keep, key) takes every lane's decision and is
+// called by the whole wave.
+constexpr int kChunk = kWaveSortCap / 64;    // 64-candidate steps per block-mode chunk
+constexpr int kRing = 128;
 
-    if (threadIdx.x == 0) {
-        s_n = 0;
-        s_ub = INFINITY;
-    }
-    if (k > 0 && ns > k && !big) {
-        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-            float lo, hi;
-            l2_interval(g[i], qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
-            s_keys[i] = (uint64_t)__float_as_uint(hi);
+struct RecheckCtx {
+    const float *qrow;
+    float qr[8];
+    float qnn, qerr, base, ub;
+    int k;
+    bool sel;                                // ub in force (kNN)
+};
+
+template <bool kShort, class Emit>
+__device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View &o, const RecheckCtx &rc,
+                                              float delta, float eps_a, float eps_b, float eps_c, const Cand *g,
+                                              int i0, int i1, int32_t *ring, long long *verified, Emit &emit)
+{
+    const int lane = threadIdx.x & 63, grp = lane >> 4, sl = lane & 15;
+    const int nu = (i1 - i0 + 63) >> 6;
+    int head = 0, tail = 0;                      // ring cursors (wave-uniform)
+    auto batch = [&](int cnt) __attribute__((always_inline)) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int32_t p[4];
+        bool nd[4];
+#pragma unroll
+        for (int uu = 0; uu < 4; uu++) {
+            const int j = 4 * uu + grp;
+            nd[uu] = j < cnt;
+            p[uu] = nd[uu] ? ring[(head + j) & (kRing - 1)] : 0;
         }
-        const int P = dev::next_pow2(ns);
-        for (int i = ns + threadIdx.x; i < P; i += blockDim.x) s_keys[i] = ~0ull;
-        dev::bitonic_sort(s_keys, P);
-        if (threadIdx.x == 0) s_ub = __uint_as_float((uint32_t)s_keys[k - 1]) * (1.f + 4.f * delta);
-    }
-    __syncthreads();
-    const float ub = s_ub;
-    const int grp = threadIdx.x >> 4, sl = threadIdx.x & 15;
-    const float *qrow = qv.Q32 + (size_t)q * o.dp;
-    long long verified = 0;
-    // two candidates per 16-lane group and step, both rows in flight together
-    auto emit = [&](bool valid, const Cand &c, bool need, float acc) {
-        if (sl != 0 || !valid) return;
-        bool keep = false;
-        uint64_t key = 0;
-        if (c.pos < 0) {
-            keep = true;
-            key = c.val;
-        } else if (need) {
-            verified++;
-            const float d = sqrtf(acc);
-            keep = k > 0 || d <= base;
-            key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
-        }
-        if (keep) {
-            const int slot = atomicAdd(&s_n, 1);
-            keys[slot] = key;
-        }
-    };
-    auto needs = [&](bool valid, const Cand &c) {
-        bool need = valid && c.pos >= 0;
-        if (need && k > 0 && ub < INFINITY) {
-            float lo, hi;
-            l2_interval(c, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
-            need = lo <= ub;
-        }
-        return need;
-    };
-    for (int i0 = 0; i0 < ns; i0 += 32) {
-        const int ia = i0 + grp, ib = i0 + 16 + grp;
-        const bool va = ia < ns, vb = ib < ns;
-        Cand ca, cb;
-        ca.q = cb.q = 0;
-        ca.pos = cb.pos = -1;
-        ca.val = cb.val = 0;
-        if (va) ca = g[ia];
-        if (vb) cb = g[ib];
-        const bool na = needs(va, ca), nb = needs(vb, cb);
-        const float *xa = na ? o.X32 + (size_t)ca.pos * o.dp : qrow;
-        const float *xb = nb ? o.X32 + (size_t)cb.pos * o.dp : qrow;
-        float acca = 0.f, accb = 0.f;
-        if (na || nb) {
+        uint32_t idv[4];
+        float acc[4];
+#pragma unroll
+        for (int uu = 0; uu < 4; uu++) idv[uu] = nd[uu] && sl == 0 ? a.ids[p[uu]] : 0u;
+        if (kShort) {
+            float xv[4][8];
+#pragma unroll
+            for (int uu = 0; uu < 4; uu++) {
+                const float *x = o.X32 + (size_t)p[uu] * o.dp;
+#pragma unroll
+                for (int t = 0; t < 8; t++) xv[uu][t] = nd[uu] && sl + 16 * t < o.dp ? x[sl + 16 * t] : 0.f;
+            }
+            // coordinates beyond dp are zero on both sides: fmaf(0, 0, acc) == acc
+#pragma unroll
+            for (int uu = 0; uu < 4; uu++) {
+                acc[uu] = 0.f;
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    const float df = rc.qr[t] - xv[uu][t];
+                    acc[uu] = fmaf(df, df, acc[uu]);
+                }
+            }
+        } else {
+            const float *x[4];
+#pragma unroll
+            for (int uu = 0; uu < 4; uu++) {
+                acc[uu] = 0.f;
+                x[uu] = nd[uu] ? o.X32 + (size_t)p[uu] * o.dp : rc.qrow;
+            }
             for (int d = sl; d < o.dp; d += 16) {
-                const float qd = qrow[d];
-                const float dfa = qd - xa[d];
-                const float dfb = qd - xb[d];
-                acca = fmaf(dfa, dfa, acca);
-                accb = fmaf(dfb, dfb, accb);
+                const float qd = rc.qrow[d];
+#pragma unroll
+                for (int uu = 0; uu < 4; uu++) {
+                    const float df = qd - x[uu][d];
+                    acc[uu] = fmaf(df, df, acc[uu]);
+                }
             }
         }
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            acca += __shfl_xor(acca, off, 16);
-            accb += __shfl_xor(accb, off, 16);
+        for (int uu = 0; uu < 4; uu++)
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) acc[uu] += __shfl_xor(acc[uu], off, 16);
+#pragma unroll
+        for (int uu = 0; uu < 4; uu++) {
+            const bool mine = nd[uu] && sl == 0;
+            const float d = sqrtf(acc[uu]);
+            if (mine) (*verified)++;
+            emit(mine && (rc.k > 0 || d <= rc.base), ((uint64_t)__float_as_uint(d) << 32) | idv[uu]);
         }
-        emit(va, ca, na, acca);
-        emit(vb, cb, nb, accb);
+    };
+    // one 64-candidate step at a time, the next step's candidates loading
+    // while this one is staged and its full batches run
+    auto load = [&](int u, Cand *c) __attribute__((always_inline)) {
+        const int i = i0 + lane + 64 * u;
+        c->q = 0;
+        c->pos = -1;
+        c->val = 0;
+        if (i < i1) *c = g[i];
+        return i < i1;
+    };
+    Cand cn;
+    bool vn = load(0, &cn);
+    for (int u = 0; u < nu; u++) {
+        const Cand c = cn;
+        const bool v = vn;
+        if (u + 1 < nu) vn = load(u + 1, &cn);
+        bool need = v && c.pos >= 0;
+        if (need && rc.sel && rc.ub < INFINITY) {
+            float lo, hi;
+            l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            need = lo <= rc.ub;
+        }
+        emit(v && c.pos < 0, c.val);                 // known distance (cache list)
+        const uint64_t m = dev::ballot(need);
+        if (need) ring[(tail + dev::lanes_below(m)) & (kRing - 1)] = c.pos;
+        tail += __popcll(m);
+        while (tail - head >= 16) {
+            batch(16);
+            head += 16;
+        }
+    }
+    if (tail > head) batch(tail - head);
+}
+
+// One workgroup for query q (more candidates than one wave takes).  kNN:
+// the k-th smallest upper interval end, found by a 32-step binary search
+// over the float bits with block-wide counts of the values held in LDS,
+// bounds the answer set (when the candidates fit the LDS run).  The waves
+// recheck chunks of 64 * kChunk candidates in turn; kept keys are compacted
+// per wave (one LDS atomic reserves the wave's slots) and sorted in LDS
+// (s_keys, kSortCapL2) or in the query's scratch run.
+template <bool kShort>
+__device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
+                                float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring)
+{
+    __shared__ int s_n, s_cnt;
+    const int64_t seg0 = a.qoff[q];
+    const int ns = (int)(a.qoff[q + 1] - seg0);
+    const int k = a.kq ? a.kq[q] : 0;
+    const int64_t boff = a.big_off ? a.big_off[q] : -1;
+    const bool big = boff >= 0;
+    uint64_t *keys = big ? a.scratch + boff : s_keys;
+    const int64_t cap = big ? dev::next_pow2(ns) : kSortCapL2;
+    const Cand *g = a.grouped + seg0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    RecheckCtx rc;
+    rc.qrow = qv.Q32 + (size_t)q * o.dp;
+    rc.qnn = qv.qn[q];
+    rc.qerr = qv.qe[q];
+    rc.base = a.base[q];
+    rc.k = k;
+    rc.ub = INFINITY;
+    rc.sel = k > 0 && ns > k && !big;
+    if (threadIdx.x == 0) s_n = 0;
+    if (rc.sel) {
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            float lo, hi;
+            l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            s_keys[i] = (uint64_t)__float_as_uint(hi);
+        }
+        // smallest v with #{hi <= v} >= k (hi >= 0: float order = bit order)
+        uint32_t lo_v = 0u, hi_v = 0xffffffffu;
+        while (lo_v < hi_v) {
+            const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            int c = 0;
+            for (int i = threadIdx.x; i < ns; i += blockDim.x) c += (uint32_t)s_keys[i] <= mid ? 1 : 0;
+#pragma unroll
+            for (int o2 = 32; o2 > 0; o2 >>= 1) c += __shfl_xor(c, o2, 64);
+            if (lane == 0 && c) atomicAdd(&s_cnt, c);
+            __syncthreads();
+            if (s_cnt >= k) hi_v = mid;
+            else lo_v = mid + 1u;
+            __syncthreads();
+        }
+        rc.ub = __uint_as_float(lo_v) * (1.f + 4.f * delta);
     }
     __syncthreads();
-    if (threadIdx.x % 16 == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    const int sl = lane & 15;
+    if (kShort) {
+#pragma unroll
+        for (int t = 0; t < 8; t++) rc.qr[t] = sl + 16 * t < o.dp ? rc.qrow[sl + 16 * t] : 0.f;
+    }
+    long long verified = 0;
+    auto emit = [&](bool keep, uint64_t key) __attribute__((always_inline)) {
+        const uint64_t m = dev::ballot(keep);
+        if (m) {
+            int slot0 = 0;
+            if (lane == 0) slot0 = atomicAdd(&s_n, __popcll(m));
+            slot0 = __shfl(slot0, 0, 64);
+            if (keep) keys[slot0 + dev::lanes_below(m)] = key;
+        }
+    };
+    const int nw = (int)(blockDim.x >> 6);
+    for (int c0 = wave * 64 * kChunk; c0 < ns; c0 += nw * 64 * kChunk)
+        recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
+                              &verified, emit);
+    __syncthreads();
+    for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
+    if (lane == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
     const int nk = s_n;
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
@@ -283,115 +386,73 @@ __device__ void wave_bitonic_sort(uint64_t *a, int n)
 
 // One wave for query q (at most kWaveSortCap candidates).  kNN: the k-th
 // smallest upper interval end over the candidates, found by a 32-step
-// binary search over the float bits (counting with ballots), bounds the
-// answer set; only candidates whose lower end can reach it are rechecked.
-// Rechecks: 16 lanes per candidate, two candidates per group in flight, the
-// same strided float32 sum as every other exact L2 distance here.  Kept keys
-// are compacted with ballots into the wave's LDS run and sorted there.
+// binary search over the float bits (counting with ballots over the values
+// each lane holds in registers), bounds the answer set; then one chunk of
+// rechecks (above).  Kept keys are compacted with ballots into the wave's
+// LDS run and sorted there.
+template <bool kShort>
 __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
-                               float eps_b, float eps_c, int64_t q, uint64_t *keys)
+                               float eps_b, float eps_c, int64_t q, uint64_t *keys, int32_t *ring)
 {
     const int lane = threadIdx.x & 63;
     const int64_t seg0 = a.qoff[q];
     const int ns = (int)(a.qoff[q + 1] - seg0);
     const int k = a.kq ? a.kq[q] : 0;
-    const float base = a.base[q];
-    const float qnn = qv.qn[q];
-    const float qerr = qv.qe[q];
     const Cand *g = a.grouped + seg0;
-    float ub = INFINITY;
-    if (k > 0 && ns > k) {
-        for (int i = lane; i < ns; i += 64) {
-            float lo, hi;
-            l2_interval(g[i], qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
-            keys[i] = __float_as_uint(hi);
+    RecheckCtx rc;
+    rc.qrow = qv.Q32 + (size_t)q * o.dp;
+    rc.qnn = qv.qn[q];
+    rc.qerr = qv.qe[q];
+    rc.base = a.base[q];
+    rc.k = k;
+    rc.ub = INFINITY;
+    rc.sel = k > 0 && ns > k;
+    if (rc.sel) {
+        uint32_t hv[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; u++) {
+            const int i = lane + 64 * u;
+            hv[u] = 0xffffffffu;
+            if (i < ns) {
+                float lo, hi;
+                l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                hv[u] = __float_as_uint(hi);
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // smallest v with #{hi <= v} >= k (hi >= 0, so float order = bit order)
+        // smallest v with #{hi <= v} >= k (hi >= 0, so float order = bit order;
+        // the padding 0xffffffff is never counted: mid < 0xffffffff)
+        const int nu = (ns + 63) >> 6;
         uint32_t lo_v = 0u, hi_v = 0xffffffffu;
         while (lo_v < hi_v) {
             const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
             int c = 0;
-            for (int i0 = 0; i0 < ns; i0 += 64) {
-                const int i = i0 + lane;
-                c += __popcll(dev::ballot(i < ns && (uint32_t)keys[i] <= mid));
-            }
+#pragma unroll
+            for (int u = 0; u < kChunk; u++)
+                if (u < nu) c += __popcll(dev::ballot(hv[u] <= mid));
             if (c >= k) hi_v = mid;
             else lo_v = mid + 1u;
         }
-        ub = __uint_as_float(lo_v) * (1.f + 4.f * delta);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        rc.ub = __uint_as_float(lo_v) * (1.f + 4.f * delta);
     }
-    const int grp = lane >> 4, sl = lane & 15;
-    const float *qrow = qv.Q32 + (size_t)q * o.dp;
+    const int sl = lane & 15;
+    if (kShort) {
+#pragma unroll
+        for (int t = 0; t < 8; t++) rc.qr[t] = sl + 16 * t < o.dp ? rc.qrow[sl + 16 * t] : 0.f;
+    }
     long long verified = 0;
     int nk = 0;
-    for (int i0 = 0; i0 < ns; i0 += 8) {
-        const int ia = i0 + grp, ib = i0 + 4 + grp;
-        const bool va = ia < ns, vb = ib < ns;
-        Cand ca, cb;
-        ca.q = cb.q = 0;
-        ca.pos = cb.pos = -1;
-        ca.val = cb.val = 0;
-        if (va) ca = g[ia];
-        if (vb) cb = g[ib];
-        bool na = va && ca.pos >= 0, nb = vb && cb.pos >= 0;
-        if (k > 0 && ub < INFINITY) {
-            float lo, hi;
-            if (na) {
-                l2_interval(ca, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
-                na = lo <= ub;
-            }
-            if (nb) {
-                l2_interval(cb, qnn, qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
-                nb = lo <= ub;
-            }
-        }
-        const float *xa = na ? o.X32 + (size_t)ca.pos * o.dp : qrow;
-        const float *xb = nb ? o.X32 + (size_t)cb.pos * o.dp : qrow;
-        float acca = 0.f, accb = 0.f;
-        if (na || nb) {
-            for (int d = sl; d < o.dp; d += 16) {
-                const float qd = qrow[d];
-                const float dfa = qd - xa[d];
-                const float dfb = qd - xb[d];
-                acca = fmaf(dfa, dfa, acca);
-                accb = fmaf(dfb, dfb, accb);
-            }
-        }
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            acca += __shfl_xor(acca, off, 16);
-            accb += __shfl_xor(accb, off, 16);
-        }
-        auto decide = [&](bool valid, const Cand &c, bool need, float acc, uint64_t *key) {
-            if (!valid) return false;
-            if (c.pos < 0) {
-                *key = c.val;
-                return true;
-            }
-            if (!need) return false;
-            verified++;
-            const float d = sqrtf(acc);
-            *key = ((uint64_t)__float_as_uint(d) << 32) | a.ids[c.pos];
-            return k > 0 || d <= base;
-        };
-        uint64_t ka = 0, kb = 0;
-        const bool keepa = sl == 0 && decide(va, ca, na, acca, &ka);
-        const bool keepb = sl == 0 && decide(vb, cb, nb, accb, &kb);
-        const uint64_t ma = dev::ballot(keepa), mb = dev::ballot(keepb);
-        if (keepa) keys[nk + dev::lanes_below(ma)] = ka;
-        nk += __popcll(ma);
-        if (keepb) keys[nk + dev::lanes_below(mb)] = kb;
-        nk += __popcll(mb);
-    }
+    auto emit = [&](bool keep, uint64_t key) __attribute__((always_inline)) {
+        const uint64_t m = dev::ballot(keep);
+        if (keep) keys[nk + dev::lanes_below(m)] = key;
+        nk += __popcll(m);
+    };
+    recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, emit);
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
     if (lane == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
     const int P = dev::next_pow2(nk > 1 ? nk : 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int i = nk + lane; i < P; i += 64) keys[i] = ~0ull;
     wave_bitonic_sort(keys, P);
     const int nout = (k > 0 && k < nk) ? k : nk;
@@ -403,14 +464,17 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 // blk_q (more than kWaveSortCap candidates) one each, the rest take four
 // queries each, one per wave, skipping those; the long workgroups start first
 // and overlap the bulk of the work.
+template <bool kShort>
 __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
                                                    float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
                                                    int n_blk)
 {
-    __shared__ uint64_t s_mem[kSortCap];
-    static_assert(4 * kWaveSortCap <= kSortCap, "wave runs must fit the workgroup's LDS");
+    __shared__ uint64_t s_mem[kSortCapL2];
+    __shared__ int32_t s_ring[4][kRing];
+    static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
     if ((int)blockIdx.x < n_blk) {
-        verify_l2_block(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem);
+        verify_l2_block<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
+                                s_ring[threadIdx.x >> 6]);
         return;
     }
     // wave mode: past the workgroup-mode blocks (rounded up to 8), XCD x
@@ -423,7 +487,7 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     if (q >= a.nq) return;
     const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
     if (ns > kWaveSortCap) return;
-    verify_l2_wave(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap);
+    verify_l2_wave<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave]);
 }
 
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
@@ -434,7 +498,12 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
     const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
-    hipLaunchKernelGGL(k_verify_l2, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q, n_blk);
+    if (o.dp <= 128)
+        hipLaunchKernelGGL(k_verify_l2<true>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q,
+                           n_blk);
+    else
+        hipLaunchKernelGGL(k_verify_l2<false>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c,
+                           blk_q, n_blk);
     check_launch(__func__);
 }
 
@@ -449,10 +518,9 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
     __shared__ uint64_t s_peq[257 * 4];
     __shared__ uint8_t s_lut[256];
     __shared__ int s_n;
-    // gridDim.x is a multiple of 8: XCD x takes the x-th contiguous eighth of
-    // the queries, whose neighbours share candidates in that XCD's L2
-    const int64_t per = gridDim.x >> 3;
-    const int64_t q = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // one query per workgroup in batch order: the Myers work per query varies
+    // a lot, and interleaving the queries over the XCDs balances it
+    const int64_t q = blockIdx.x;
     if (q >= a.nq) return;
     const int64_t seg0 = a.qoff[q];
     const int ns = (int)(a.qoff[q + 1] - seg0);
@@ -501,7 +569,7 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st)
 {
     if (a.nq == 0) return;
-    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)((a.nq + 7) / 8 * 8)), dim3(256), 0, st, a, o, qv);
+    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
     check_launch(__func__);
 }
 

@@ -138,6 +138,7 @@ void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps
                int32_t *near, hipStream_t st)
 {
     if (nq == 0) return;
+    require(ksteps >= 1 && ksteps <= 4, "leaf_near: rows wider than 128 floats");
     const unsigned grid = (unsigned)((nq + 15) / 16);
 #define LN(KS)                                                                                              \
     hipLaunchKernelGGL((k_leaf_near<KS, kNearLeaves>), dim3(grid), dim3(256), 0, st,                        \
@@ -235,6 +236,7 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
                int ntiles, uint64_t *leaf_mask, hipStream_t st)
 {
     if (nq == 0 || n_leaves == 0) return;
+    require(ksteps >= 1 && ksteps <= 4, "leaf_ball: rows wider than 128 floats");
     const int64_t ngroups = (n_leaves + 63) / 64;
     const int64_t waves = (int64_t)ntiles * ngroups;
     const unsigned grid = (unsigned)((waves + 3) / 4);

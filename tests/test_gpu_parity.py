@@ -63,6 +63,25 @@ def test_l2_10k_d16(gts, mode):
     idx.close()
 
 
+@pytest.mark.parametrize("dim", [129, 200])
+def test_l2_wide_rows(gts, dim):
+    """Rows wider than the MFMA path (more than 128 floats) take the float32
+    path in either mode, and its verification loops over the row."""
+    d = synth.gaussian_mixture(70 + dim, 3000, dim, 5, -4.0, 4.0, 1.0, 30, 30)
+    X, RQ, KQ = d["objects"], d["range_queries"], d["knn_queries"]
+    objs = O.ObjectSet(vecs=X)
+    # a radius that holds about 40 answers around the first range query
+    r = float(O.knn_bf(objs, O.ObjectSet(vecs=RQ[:1]), 40)[0][1][-1])
+    _say(f"l2 wide rows dim={dim} r={r}")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=6, fanout=4, leaf_size=64, seed=dim)
+    Q = np.concatenate([RQ, KQ])
+    k = np.array([0] * len(RQ) + [12] * len(KQ), np.int32)
+    res = idx.search(_dev(Q), radius=np.full(len(Q), r, np.float32), k=k).to_lists()
+    check_range(res[:30], O.range_bf(objs, O.ObjectSet(vecs=RQ), r), X, RQ, r)
+    check_knn(res[30:], O.knn_bf(objs, O.ObjectSet(vecs=KQ), 12), X, KQ, 12)
+    idx.close()
+
+
 @pytest.mark.parametrize("kind", ["l2", "edit"])
 def test_segments_beyond_the_lds_sort(gts, kind):
     """Queries whose candidate lists exceed what one workgroup sorts in LDS
