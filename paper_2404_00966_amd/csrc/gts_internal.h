@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -242,6 +243,8 @@ struct BoundTuner {
 struct QueryCtx {
     hipStream_t stream = nullptr;
     DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
+    void *pin = nullptr;               // pinned host staging for small device-to-host reads
+    size_t pin_bytes = 0;
     hipEvent_t ev[9] = {};
     bool timing = false;
     gts_stats stats{};
@@ -249,10 +252,27 @@ struct QueryCtx {
     QueryCtx() = default;
     QueryCtx(const QueryCtx &) = delete;
     QueryCtx &operator=(const QueryCtx &) = delete;
+    // at least `bytes` of pinned host memory (grown, never shrunk)
+    void *pinned(size_t bytes)
+    {
+        if (bytes > pin_bytes) {
+            if (pin) (void)hipHostFree(pin);
+            pin = nullptr;
+            pin_bytes = 0;
+            const size_t want = std::max<size_t>(bytes, (size_t)1 << 16);
+            if (hipHostMalloc(&pin, want, hipHostMallocDefault) != hipSuccess) {
+                pin = nullptr;
+                return nullptr;
+            }
+            pin_bytes = want;
+        }
+        return pin;
+    }
     ~QueryCtx()
     {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (pin) (void)hipHostFree(pin);
     }
 };
 // Run f, turning exceptions into a status and this thread's error text (the

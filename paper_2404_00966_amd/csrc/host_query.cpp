@@ -32,7 +32,7 @@ enum Ws {
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
-    W_SORT_TMP, W_HOME2,
+    W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
@@ -57,10 +57,85 @@ template <class T> T *wsp(QueryCtx *cx, int slot, size_t count)
 // Small device counters: [0] candidate count, [1] item count, [2] work counter
 constexpr int kSmallWords = 16;
 
+// Pinned host staging of one search call: device-to-host the permutation
+// (nq int32), the small counters, the group's segment offsets, counts and
+// the statistics counters; host-to-device the workgroup-mode query list, the
+// scratch offsets and the result offsets.
+struct PinLayout {
+    size_t perm = 0, small = 0, qoff = 0, counts = 0, counters = 0, blk = 0, big = 0, offs = 0, bytes = 0;
+    explicit PinLayout(int64_t nq)
+    {
+        auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+        small = up((size_t)nq * sizeof(int32_t));
+        qoff = small + 256;
+        counts = up(qoff + (size_t)(nq + 1) * sizeof(int64_t));
+        counters = up(counts + (size_t)(nq + 1) * sizeof(uint32_t));
+        blk = counters + 256;                                   // host-to-device: workgroup-mode queries
+        big = up(blk + (size_t)(nq + 1) * sizeof(int32_t));    // scratch offsets
+        offs = up(big + (size_t)(nq + 1) * sizeof(int64_t));   // result offsets
+        bytes = up(offs + (size_t)(nq + 1) * sizeof(int64_t));
+    }
+};
+
+// Result storage: offsets, ids and distances in one allocation (freed here
+// unless released to a result).
+struct ResultMem {
+    void *p = nullptr;
+    bool device = false;
+    size_t id_at = 0, dist_at = 0, bytes = 0;
+    int64_t cap = 0;                // ids / distances it holds
+    ResultMem() = default;
+    ResultMem(const ResultMem &) = delete;
+    ResultMem &operator=(const ResultMem &) = delete;
+    ResultMem(ResultMem &&o) noexcept { *this = std::move(o); }
+    ResultMem &operator=(ResultMem &&o) noexcept
+    {
+        if (this != &o) {
+            reset();
+            p = o.p;
+            device = o.device;
+            id_at = o.id_at;
+            dist_at = o.dist_at;
+            bytes = o.bytes;
+            cap = o.cap;
+            o.p = nullptr;
+        }
+        return *this;
+    }
+    void *release()
+    {
+        void *r = p;
+        p = nullptr;
+        return r;
+    }
+    void reset()
+    {
+        if (p) (void)(device ? hipFree(p) : hipHostFree(p));
+        p = nullptr;
+    }
+    ~ResultMem() { reset(); }
+};
+
+ResultMem result_alloc(int64_t nq, int64_t entries, bool device)
+{
+    ResultMem m;
+    m.device = device;
+    const size_t off_bytes = (nq + 1) * sizeof(int64_t);
+    m.cap = std::max<int64_t>(entries, 1);
+    m.id_at = (off_bytes + 255) / 256 * 256;
+    m.dist_at = m.id_at + ((size_t)m.cap * sizeof(int64_t) + 255) / 256 * 256;
+    m.bytes = m.dist_at + (size_t)m.cap * sizeof(float);
+    const hipError_t e = device ? hipMalloc(&m.p, m.bytes) : hipHostMalloc(&m.p, m.bytes, hipHostMallocDefault);
+    if (e != hipSuccess) m.p = nullptr;
+    return m;
+}
+
 struct GroupOut {
     std::vector<uint32_t> counts;  // per query of the group
-    DevBuf ids, dist;              // CSR pieces of the group
+    DevBuf ids, dist;              // CSR pieces of the group (unless direct)
     int64_t total = 0;
+    bool direct = false;           // sorted keys left in the workspace (W_OUTKEYS, W_QOFF64, W_OUTCNT)
+    ResultMem pre;                 // direct: result storage for every candidate, allocated while verify runs
 };
 
 double now_ms()
@@ -144,8 +219,8 @@ void rec(QueryCtx *cx, int i)
     if (cx->timing) GTS_HIP(hipEventRecord(cx->ev[i], cx->stream));
 }
 
-bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t ng, int64_t cap, GroupOut *go,
-               double *stage_ms)
+bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t ng, int64_t cap, bool direct,
+               bool result_on_device, uint8_t *pin, const PinLayout &pl, GroupOut *go, double *stage_ms)
 {
     hipStream_t st = cx->stream;
     IndexData &d = idx->data;
@@ -264,16 +339,10 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
                                c.live.as<uint32_t>(), c.count, base, cands, small + 0, cap, st);
         }
     }
-    uint32_t h_small[kSmallWords];
-    GTS_HIP(hipMemcpyAsync(h_small, small, sizeof(h_small), hipMemcpyDeviceToHost, st));
-    GTS_HIP(hipStreamSynchronize(st));
-    const int64_t ncand = h_small[0];
-    if (ncand > cap) return false;
-    if (!plain && !l2 && (int64_t)h_small[1] > t.n_leaves * ntiles) fail(GTS_EDEVICE, "item list overflow");
-    cx->stats.candidates += ncand;
-    cx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
-
     // ---- group by query ----------------------------------------------------
+    // No host round trip before the grouping: the scatter writes at most the
+    // grouped buffer's current capacity, and a larger candidate count (known
+    // at the next synchronisation) grows it and scatters again.
     uint32_t *qcount = wsp<uint32_t>(cx, W_QCOUNT, ng + 1);
     uint32_t *cursor = wsp<uint32_t>(cx, W_CURSOR, ng + 1);
     int64_t *qoff = wsp<int64_t>(cx, W_QOFF64, ng + 1);
@@ -281,19 +350,38 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     k::fill_u32(cursor, ng, 0u, st);
     k::group_hist(cands, small + 0, cap, qcount, st);
     k::scan_u32(qcount, ng, qoff, st);
-    k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, std::max<int64_t>(ncand, 1));
-    k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, st);
+    int64_t gcap = std::max<int64_t>((int64_t)(cx->ws[W_GROUPED].bytes / sizeof(k::Cand)),
+                                     std::min<int64_t>(cap, (int64_t)1 << 20));
+    k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, gcap);
+    k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, gcap, st);
     rec(cx, 5);
-    std::vector<int64_t> h_qoff(ng + 1);
-    GTS_HIP(hipMemcpyAsync(h_qoff.data(), qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    uint32_t *h_small = reinterpret_cast<uint32_t *>(pin + pl.small);
+    int64_t *h_qoff_pin = reinterpret_cast<int64_t *>(pin + pl.qoff);
+    GTS_HIP(hipMemcpyAsync(h_small, small, kSmallWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
-    // segments too long for LDS sort in power-of-two scratch runs
-    std::vector<int64_t> big(ng, -1);
+    const int64_t ncand = h_small[0];
+    if (ncand > cap) return false;
+    if (!plain && !l2 && (int64_t)h_small[1] > t.n_leaves * ntiles) fail(GTS_EDEVICE, "item list overflow");
+    cx->stats.candidates += ncand;
+    cx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
+    const int64_t *h_qoff = h_qoff_pin;   // read in place (no fresh host pages per call)
+    if (ncand > gcap) {
+        grouped = wsp<k::Cand>(cx, W_GROUPED, ncand);
+        k::fill_u32(cursor, ng, 0u, st);
+        k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, ncand, st);
+    }
+    // segments too long for LDS sort in power-of-two scratch runs; the lists
+    // are written straight into the pinned staging
+    int64_t *big = reinterpret_cast<int64_t *>(pin + pl.big);
+    int32_t *blk_q = reinterpret_cast<int32_t *>(pin + pl.blk);   // L2: queries beyond one wave's share
+    int64_t n_blk = 0;
     int64_t scratch_words = 0;
     bool any_big = false;
     const int64_t sort_cap = l2 ? kSortCapL2 : kSortCap;
     for (int64_t q = 0; q < ng; q++) {
         const int64_t ns = h_qoff[q + 1] - h_qoff[q];
+        big[q] = -1;
         if (ns > sort_cap) {
             int64_t p = 1;
             while (p < ns) p <<= 1;
@@ -301,12 +389,13 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             scratch_words += p;
             any_big = true;
         }
+        if (l2 && ns > kWaveSortCap) blk_q[n_blk++] = (int32_t)q;
     }
     int64_t *big_off = nullptr;
     uint64_t *scratch = nullptr;
     if (any_big) {
         big_off = wsp<int64_t>(cx, W_BIGOFF, ng);
-        GTS_HIP(hipMemcpyAsync(big_off, big.data(), ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(big_off, big, ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
         scratch = wsp<uint64_t>(cx, W_SCRATCH, scratch_words);
     }
 
@@ -314,34 +403,44 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
     uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
     k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters};
-    std::vector<int32_t> blk_q;   // L2: queries beyond one wave's share
-    if (l2)
-        for (int64_t q = 0; q < ng; q++)
-            if (h_qoff[q + 1] - h_qoff[q] > kWaveSortCap) blk_q.push_back((int32_t)q);
     int32_t *dblk = nullptr;
-    if (!blk_q.empty()) {
-        dblk = wsp<int32_t>(cx, W_BLKQ, blk_q.size());
-        GTS_HIP(hipMemcpyAsync(dblk, blk_q.data(), blk_q.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (n_blk > 0) {
+        dblk = wsp<int32_t>(cx, W_BLKQ, n_blk);
+        GTS_HIP(hipMemcpyAsync(dblk, blk_q, n_blk * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
-    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)blk_q.size(), st);
+    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, st);
     else k::verify_edit(va, oe, qe, st);
     rec(cx, 6);
+    // the host waits for verify next: allocate the result meanwhile, sized for
+    // every candidate (an upper bound of the answers) unless that is large
+    if (direct && ncand * (int64_t)(sizeof(int64_t) + sizeof(float)) <= ((int64_t)256 << 20))
+        go->pre = result_alloc(b.nq, ncand, result_on_device);
 
-    // ---- CSR piece of this group ---------------------------------------------
-    int64_t *res_off = wsp<int64_t>(cx, W_RESOFF, ng + 1);
-    k::scan_u32(out_count, ng, res_off, st);
-    go->counts.resize(ng);
-    GTS_HIP(hipMemcpyAsync(go->counts.data(), out_count, ng * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    int64_t total = 0;
-    GTS_HIP(hipMemcpyAsync(&total, res_off + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    GTS_HIP(hipStreamSynchronize(st));
-    go->total = total;
-    go->ids.alloc(std::max<int64_t>(total, 1) * sizeof(int64_t));
-    go->dist.alloc(std::max<int64_t>(total, 1) * sizeof(float));
-    k::csr_write(out_keys, qoff, out_count, res_off, ng, l2 ? 0 : 1, go->ids.as<int64_t>(), go->dist.as<float>(),
-                 go->dist.as<int32_t>(), st);
+    // ---- counts of this group; its CSR piece unless the keys stay -----------
+    go->direct = direct;
+    if (direct && go->pre.p && result_on_device) {
+        // the whole result is assembled on the device: no counts to the host
+        go->total = -1;
+    } else {
+        uint32_t *h_counts = reinterpret_cast<uint32_t *>(pin + pl.counts);
+        GTS_HIP(hipMemcpyAsync(h_counts, out_count, ng * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        go->counts.assign(h_counts, h_counts + ng);
+        int64_t total = 0;
+        for (int64_t q = 0; q < ng; q++) total += h_counts[q];
+        go->total = total;
+    }
+    const int64_t total = go->total;
+    if (!direct) {
+        int64_t *res_off = wsp<int64_t>(cx, W_RESOFF, ng + 1);
+        k::scan_u32(out_count, ng, res_off, st);
+        go->ids.alloc(std::max<int64_t>(total, 1) * sizeof(int64_t));
+        go->dist.alloc(std::max<int64_t>(total, 1) * sizeof(float));
+        k::csr_write(out_keys, qoff, out_count, res_off, ng, l2 ? 0 : 1, go->ids.as<int64_t>(),
+                     go->dist.as<float>(), go->dist.as<int32_t>(), st);
+    }
     rec(cx, 7);
-    GTS_HIP(hipStreamSynchronize(st));
+    if (cx->timing) GTS_HIP(hipStreamSynchronize(st));
     if (cx->timing) {
         float ms;
         const int stage_of[] = {-1, -1, -1, GTS_STAGE_NODES, GTS_STAGE_CANDS, GTS_STAGE_GROUP, GTS_STAGE_VERIFY,
@@ -543,30 +642,31 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         }
     }
     if (permuted) {
-        // everything per query follows the permutation on the device
+        // everything per query follows the permutation on the device: one
+        // gather into partner buffers, which then trade places with the
+        // originals (no copies back)
         const int32_t *dperm = cx->ws[W_PERM].as<int32_t>();
-        float *tb = wsp<float>(cx, W_TMP, (size_t)nqpad * std::max(mpad, l2 ? d.dp : 1));
-        k::gather_rows(base, dperm, nq, 1, tb, st);
-        GTS_HIP(hipMemcpyAsync(base, tb, nq * sizeof(float), hipMemcpyDeviceToDevice, st));
-        int32_t *tk = wsp<int32_t>(cx, W_TMP2, std::max<size_t>((size_t)nq * k::kNearLeaves, (size_t)nq));
-        k::gather_i32(kq, dperm, nq, 1, tk, st);
-        GTS_HIP(hipMemcpyAsync(kq, tk, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-        float *QPd = cx->ws[W_QP].as<float>();
-        float *tmpf = tb;
-        k::gather_rows(QPd, dperm, nq, mpad, tmpf, st);
-        GTS_HIP(hipMemcpyAsync(QPd, tmpf, (size_t)nq * mpad * sizeof(float), hipMemcpyDeviceToDevice, st));
+        float *pb = wsp<float>(cx, W_PBASE, nqpad);
+        int32_t *pk = wsp<int32_t>(cx, W_PKQ, nqpad);
+        float *pqp = wsp<float>(cx, W_PQP, (size_t)nqpad * mpad);
+        float *pq32 = l2 ? wsp<float>(cx, W_PQ32, (size_t)nqpad * d.dp) : nullptr;
+        int32_t *pnear = near ? wsp<int32_t>(cx, W_PNEAR, (size_t)nqpad * k::kNearLeaves) : nullptr;
+        k::permute_queries(dperm, nq, base, pb, kq, pk, cx->ws[W_QP].as<float>(), pqp, mpad, l2 ? qv.Q32 : nullptr,
+                           pq32, d.dp, near, pnear, k::kNearLeaves, st);
+        std::swap(cx->ws[W_BASE], cx->ws[W_PBASE]);
+        std::swap(cx->ws[W_KQ], cx->ws[W_PKQ]);
+        std::swap(cx->ws[W_QP], cx->ws[W_PQP]);
+        base = cx->ws[W_BASE].as<float>();
+        kq = cx->ws[W_KQ].as<int32_t>();
+        if (near) {
+            std::swap(cx->ws[W_NEAR], cx->ws[W_PNEAR]);
+            near = cx->ws[W_NEAR].as<int32_t>();
+        }
         if (l2) {
-            float *Q32 = const_cast<float *>(qv.Q32);
-            k::gather_rows(Q32, dperm, nq, d.dp, tmpf, st);
-            GTS_HIP(hipMemcpyAsync(Q32, tmpf, (size_t)nq * d.dp * sizeof(float), hipMemcpyDeviceToDevice, st));
-            k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
+            std::swap(cx->ws[W_Q32], cx->ws[W_PQ32]);
+            qv.Q32 = cx->ws[W_Q32].as<float>();
+            k::rows_bf16(qv.Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
                          const_cast<float *>(qv.qn), const_cast<float *>(qv.qe), 0.f, st);
-            if (near) {
-                int32_t *tmpi = wsp<int32_t>(cx, W_TMP2, std::max<size_t>((size_t)nq * k::kNearLeaves, (size_t)nq));
-                k::gather_i32(near, dperm, nq, k::kNearLeaves, tmpi, st);
-                GTS_HIP(hipMemcpyAsync(near, tmpi, (size_t)nq * k::kNearLeaves * sizeof(int32_t),
-                                       hipMemcpyDeviceToDevice, st));
-            }
         } else {
             // strings in the new order, then their match tables and lengths
             std::vector<int64_t> hoff(nq + 1);
@@ -648,11 +748,18 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     std::vector<GroupOut> groups;
     std::vector<std::pair<int64_t, int64_t>> todo;  // (q0, ng), processed front to back
     if (nq > 0) todo.push_back({0, nq});
+    const PinLayout pl(nq);
+    uint8_t *pin = static_cast<uint8_t *>(cx->pinned(pl.bytes));
+    GTS_CHECK(pin != nullptr, GTS_ENOMEM, "pinned host staging allocation failed");
+    if (permuted && perm.empty())   // the order was made on the device: its copy lands by the next sync
+        GTS_HIP(hipMemcpyAsync(pin + pl.perm, cx->ws[W_PERM].p, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     while (!todo.empty()) {
         auto [q0, ng] = todo.front();
         todo.erase(todo.begin());
         GroupOut go;
-        if (run_group(idx, cx, b, q0, ng, cap, &go, stage_ms)) {
+        // the whole batch in one group leaves its sorted keys in the workspace
+        const bool direct = q0 == 0 && ng == nq;
+        if (run_group(idx, cx, b, q0, ng, cap, direct, rloc == GTS_DEVICE, pin, pl, &go, stage_ms)) {
             groups.push_back(std::move(go));
             continue;
         }
@@ -666,79 +773,119 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     }
 
     // ---- final CSR (caller's query order) ------------------------------------------------
+    unsigned long long *hc = reinterpret_cast<unsigned long long *>(pin + pl.counters);
+    if (groups.size() == 1 && groups[0].total < 0) {
+        // one group, result on the device, storage made while verify ran:
+        // caller-order counts, their scan (the result's offsets) and the keys
+        // written in place, then one synchronisation for the total
+        ResultMem rm = std::move(groups[0].pre);
+        auto *priv = new ResultPriv();
+        priv->device = true;
+        priv->offsets = rm.p;
+        priv->ids = static_cast<uint8_t *>(rm.p) + rm.id_at;
+        priv->dist = static_cast<uint8_t *>(rm.p) + rm.dist_at;
+        rm.release();
+        out->priv = priv;
+        int64_t *doffs = static_cast<int64_t *>(priv->offsets);
+        uint32_t *cc = reinterpret_cast<uint32_t *>(wsp<int32_t>(cx, W_TMP2, nq));
+        const int32_t *dperm = permuted ? cx->ws[W_PERM].as<int32_t>() : nullptr;
+        k::perm_counts(cx->ws[W_OUTCNT].as<uint32_t>(), dperm, nq, cc, st);
+        k::scan_u32(cc, nq, doffs, st);
+        k::emit_result(cx->ws[W_OUTKEYS].as<uint64_t>(), cx->ws[W_QOFF64].as<int64_t>(),
+                       cx->ws[W_OUTCNT].as<uint32_t>(), dperm, doffs, nq, l2 ? 0 : 1,
+                       static_cast<int64_t *>(priv->ids), static_cast<float *>(priv->dist),
+                       static_cast<int32_t *>(priv->dist), st);
+        int64_t *htot = reinterpret_cast<int64_t *>(pin + pl.offs);
+        GTS_HIP(hipMemcpyAsync(htot, doffs + nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(hc, counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        out->total = *htot;
+        out->offsets = doffs;
+        out->ids = static_cast<int64_t *>(priv->ids);
+        if (l2) out->dist_f32 = static_cast<float *>(priv->dist);
+        else out->dist_i32 = static_cast<int32_t *>(priv->dist);
+    } else {
+    // position i of the batch holds caller query pm[i]
+    const int32_t *pm = !permuted ? nullptr
+                        : perm.empty() ? reinterpret_cast<const int32_t *>(pin + pl.perm) : perm.data();
     int64_t total = 0;
     for (auto &g : groups) total += g.total;
-    std::vector<int64_t> offs_b(nq + 1, 0);   // batch order
+    int64_t *offs = reinterpret_cast<int64_t *>(pin + pl.offs);   // caller order, built in place
     {
-        int64_t q = 0;
+        offs[0] = 0;
+        int64_t i = 0;
         for (auto &g : groups)
             for (uint32_t c : g.counts) {
-                offs_b[q + 1] = offs_b[q] + c;
-                q++;
+                offs[(pm ? pm[i] : i) + 1] = c;
+                i++;
             }
+        for (int64_t q = 0; q < nq; q++) offs[q + 1] += offs[q];
     }
-    std::vector<int64_t> offs(nq + 1, 0);     // caller order
-    if (permuted && perm.empty()) {
-        perm.resize(nq);   // the order was made on the device
-        GTS_HIP(hipMemcpyAsync(perm.data(), cx->ws[W_PERM].p, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipStreamSynchronize(st));
-    }
-    if (permuted) {
-        std::vector<int64_t> cnt(nq);
-        for (int64_t i = 0; i < nq; i++) cnt[perm[i]] = offs_b[i + 1] - offs_b[i];
-        for (int64_t q = 0; q < nq; q++) offs[q + 1] = offs[q] + cnt[q];
-    } else {
-        offs = offs_b;
-    }
-    auto *priv = new ResultPriv();
-    priv->device = rloc == GTS_DEVICE;
-    const size_t dist_bytes = std::max<int64_t>(total, 1) * sizeof(float);
-    const size_t id_bytes = std::max<int64_t>(total, 1) * sizeof(int64_t);
+    // one allocation holds offsets, ids and distances (made while verify ran
+    // when the batch was one group)
     const size_t off_bytes = (nq + 1) * sizeof(int64_t);
-    hipError_t e1, e2, e3;
-    if (priv->device) {
-        e1 = hipMalloc(&priv->offsets, off_bytes);
-        e2 = hipMalloc(&priv->ids, id_bytes);
-        e3 = hipMalloc(&priv->dist, dist_bytes);
+    ResultMem rm;
+    if (groups.size() == 1 && groups[0].pre.p && groups[0].pre.cap >= total) rm = std::move(groups[0].pre);
+    else rm = result_alloc(nq, total, rloc == GTS_DEVICE);
+    GTS_CHECK(rm.p != nullptr, GTS_ENOMEM, "result allocation failed");
+    auto *priv = new ResultPriv();
+    priv->device = rm.device;
+    priv->offsets = rm.p;
+    priv->ids = static_cast<uint8_t *>(rm.p) + rm.id_at;
+    priv->dist = static_cast<uint8_t *>(rm.p) + rm.dist_at;
+    rm.release();
+    const int is_edit = l2 ? 0 : 1;
+    // device copy of the caller-order offsets (the result's own array when it
+    // lives on the device)
+    int64_t *doffs = priv->device ? static_cast<int64_t *>(priv->offsets) : wsp<int64_t>(cx, W_OFF_ORIG, nq + 1);
+    GTS_HIP(hipMemcpyAsync(doffs, offs, off_bytes, hipMemcpyHostToDevice, st));
+    if (!priv->device) std::memcpy(priv->offsets, offs, off_bytes);
+    int64_t *ids_d = priv->device ? static_cast<int64_t *>(priv->ids)
+                                  : wsp<int64_t>(cx, W_RES_IDS, std::max<int64_t>(total, 1));
+    uint32_t *dist_d = priv->device ? static_cast<uint32_t *>(priv->dist)
+                                    : wsp<uint32_t>(cx, W_RES_DIST, std::max<int64_t>(total, 1));
+    const int32_t *dperm = permuted ? cx->ws[W_PERM].as<int32_t>() : nullptr;
+    if (groups.size() == 1 && groups[0].direct) {
+        k::emit_result(cx->ws[W_OUTKEYS].as<uint64_t>(), cx->ws[W_QOFF64].as<int64_t>(),
+                       cx->ws[W_OUTCNT].as<uint32_t>(), dperm, doffs, nq, is_edit, ids_d,
+                       reinterpret_cast<float *>(dist_d), reinterpret_cast<int32_t *>(dist_d), st);
     } else {
-        e1 = hipHostMalloc(&priv->offsets, off_bytes, hipHostMallocDefault);
-        e2 = hipHostMalloc(&priv->ids, id_bytes, hipHostMallocDefault);
-        e3 = hipHostMalloc(&priv->dist, dist_bytes, hipHostMallocDefault);
-    }
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        gts_result tmp{};
-        tmp.priv = priv;
-        free_result(&tmp);
-        fail(GTS_ENOMEM, "result allocation failed");
-    }
-    // assemble on the device in batch order, un-permute, then place the result
-    int64_t *ids_b = wsp<int64_t>(cx, W_RES_IDS, std::max<int64_t>(total, 1));
-    uint32_t *dist_b = wsp<uint32_t>(cx, W_RES_DIST, std::max<int64_t>(total, 1));
-    int64_t at = 0;
-    for (auto &g : groups) {
-        if (g.total) {
-            GTS_HIP(hipMemcpyAsync(ids_b + at, g.ids.p, g.total * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-            GTS_HIP(hipMemcpyAsync(dist_b + at, g.dist.p, g.total * sizeof(float), hipMemcpyDeviceToDevice, st));
+        // group pieces in batch order, then un-permuted into place
+        std::vector<int64_t> offs_b(nq + 1, 0);
+        {
+            int64_t q = 0;
+            for (auto &g : groups)
+                for (uint32_t c : g.counts) {
+                    offs_b[q + 1] = offs_b[q] + c;
+                    q++;
+                }
         }
-        at += g.total;
+        int64_t *ids_b = wsp<int64_t>(cx, W_RES_IDS2, std::max<int64_t>(total, 1));
+        uint32_t *dist_b = wsp<uint32_t>(cx, W_RES_DIST2, std::max<int64_t>(total, 1));
+        int64_t at = 0;
+        for (auto &g : groups) {
+            if (g.total) {
+                GTS_HIP(hipMemcpyAsync(ids_b + at, g.ids.p, g.total * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+                GTS_HIP(hipMemcpyAsync(dist_b + at, g.dist.p, g.total * sizeof(float), hipMemcpyDeviceToDevice, st));
+            }
+            at += g.total;
+        }
+        if (total > 0) {
+            if (permuted) {
+                int64_t *dob = wsp<int64_t>(cx, W_RESOFF, nq + 1);
+                GTS_HIP(hipMemcpyAsync(dob, offs_b.data(), off_bytes, hipMemcpyHostToDevice, st));
+                k::unpermute(dob, doffs, dperm, nq, ids_b, dist_b, ids_d, dist_d, st);
+            } else {
+                GTS_HIP(hipMemcpyAsync(ids_d, ids_b, total * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+                GTS_HIP(hipMemcpyAsync(dist_d, dist_b, total * sizeof(float), hipMemcpyDeviceToDevice, st));
+            }
+        }
     }
-    int64_t *ids_c = ids_b;
-    uint32_t *dist_c = dist_b;
-    if (permuted && total > 0) {
-        ids_c = wsp<int64_t>(cx, W_RES_IDS2, total);
-        dist_c = wsp<uint32_t>(cx, W_RES_DIST2, total);
-        int64_t *doff = wsp<int64_t>(cx, W_OFF_ORIG, 2 * (nq + 1));
-        GTS_HIP(hipMemcpyAsync(doff, offs_b.data(), off_bytes, hipMemcpyHostToDevice, st));
-        GTS_HIP(hipMemcpyAsync(doff + nq + 1, offs.data(), off_bytes, hipMemcpyHostToDevice, st));
-        k::unpermute(doff, doff + nq + 1, cx->ws[W_PERM].as<int32_t>(), nq, ids_b, dist_b, ids_c, dist_c, st);
+    if (!priv->device && total > 0) {
+        GTS_HIP(hipMemcpyAsync(priv->ids, ids_d, total * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(priv->dist, dist_d, total * sizeof(float), hipMemcpyDeviceToHost, st));
     }
-    const hipMemcpyKind to = priv->device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    GTS_HIP(hipMemcpyAsync(priv->offsets, offs.data(), off_bytes,
-                           priv->device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
-    if (total) {
-        GTS_HIP(hipMemcpyAsync(priv->ids, ids_c, total * sizeof(int64_t), to, st));
-        GTS_HIP(hipMemcpyAsync(priv->dist, dist_c, total * sizeof(float), to, st));
-    }
+    GTS_HIP(hipMemcpyAsync(hc, counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
     out->total = total;
     out->offsets = static_cast<int64_t *>(priv->offsets);
@@ -746,16 +893,15 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     if (l2) out->dist_f32 = static_cast<float *>(priv->dist);
     else out->dist_i32 = static_cast<int32_t *>(priv->dist);
     out->priv = priv;
+    }
 
     // ---- counters ----------------------------------------------------------------------
-    unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GTS_HIP(hipMemcpy(hc, counters, sizeof(hc), hipMemcpyDeviceToHost));
     cx->stats.node_tests = (int64_t)hc[0];
     if (cx->stats.leaf_pairs == 0) cx->stats.leaf_pairs = (int64_t)hc[1];
     cx->stats.tile_pairs = (int64_t)hc[2];
     cx->stats.verified = (int64_t)hc[3];
     cx->stats.bound_evals = (int64_t)hc[4];
-    cx->stats.results = total;
+    cx->stats.results = out->total;
     for (int i = 0; i < 8; i++) cx->stats.ms_stage[i] = stage_ms[i];
     cx->stats.groups = (int64_t)groups.size();
     cx->stats.ms_total = now_ms() - t_start;
@@ -767,15 +913,8 @@ void free_result(gts_result *r)
 {
     if (!r || !r->priv) return;
     auto *p = static_cast<ResultPriv *>(r->priv);
-    if (p->device) {
-        if (p->offsets) (void)hipFree(p->offsets);
-        if (p->ids) (void)hipFree(p->ids);
-        if (p->dist) (void)hipFree(p->dist);
-    } else {
-        if (p->offsets) (void)hipHostFree(p->offsets);
-        if (p->ids) (void)hipHostFree(p->ids);
-        if (p->dist) (void)hipHostFree(p->dist);
-    }
+    // one allocation starting at the offsets holds the whole result
+    if (p->offsets) (void)(p->device ? hipFree(p->offsets) : hipHostFree(p->offsets));
     delete p;
     std::memset(r, 0, sizeof(*r));
 }

@@ -85,7 +85,8 @@ void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
 
 __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
                                                        int64_t cap, const int64_t *__restrict__ qoff,
-                                                       uint32_t *__restrict__ cursor, Cand *__restrict__ grouped)
+                                                       uint32_t *__restrict__ cursor, Cand *__restrict__ grouped,
+                                                       int64_t grouped_cap)
 {
     int64_t n = *count;
     if (n > cap) n = cap;
@@ -102,14 +103,16 @@ __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ 
         uint32_t base = 0;
         if (len) base = atomicAdd(&cursor[cd.q], (uint32_t)len);
         base = __shfl(base, hl, 64);
-        if (valid) grouped[qoff[cd.q] + base + (uint32_t)(lane - hl)] = cd;
+        const int64_t dst = valid ? qoff[cd.q] + base + (uint32_t)(lane - hl) : grouped_cap;
+        if (dst < grouped_cap) grouped[dst] = cd;
     }
 }
 
 void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
-                   Cand *grouped, hipStream_t st)
+                   Cand *grouped, int64_t grouped_cap, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped);
+    hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped,
+                       grouped_cap);
     check_launch(__func__);
 }
 
@@ -592,6 +595,48 @@ __global__ void k_csr_write(const uint64_t *__restrict__ out_keys, const int64_t
         if (is_edit) dist_i[dst + j] = (int32_t)hi;
         else dist_f[dst + j] = __uint_as_float(hi);
     }
+}
+
+__global__ void k_perm_counts(const uint32_t *__restrict__ out_count, const int32_t *__restrict__ perm, int64_t nq,
+                              uint32_t *__restrict__ cc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nq) cc[perm ? perm[i] : i] = out_count[i];
+}
+
+void perm_counts(const uint32_t *out_count, const int32_t *perm, int64_t nq, uint32_t *cc, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_perm_counts, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, out_count, perm, nq, cc);
+    check_launch(__func__);
+}
+
+__global__ void k_emit_result(const uint64_t *__restrict__ out_keys, const int64_t *__restrict__ qoff,
+                              const uint32_t *__restrict__ out_count, const int32_t *__restrict__ perm,
+                              const int64_t *__restrict__ dst_off, int64_t nq, int is_edit, int64_t *__restrict__ ids,
+                              float *__restrict__ dist_f, int32_t *__restrict__ dist_i)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= nq) return;
+    const uint32_t cnt = out_count[i];
+    const int64_t src = qoff[i], dst = dst_off[perm ? perm[i] : i];
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint64_t key = out_keys[src + j];
+        ids[dst + j] = (int64_t)(uint32_t)key;
+        const uint32_t hi = (uint32_t)(key >> 32);
+        if (is_edit) dist_i[dst + j] = (int32_t)hi;
+        else dist_f[dst + j] = __uint_as_float(hi);
+    }
+}
+
+void emit_result(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int32_t *perm,
+                 const int64_t *dst_off, int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i,
+                 hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_emit_result, dim3((unsigned)nq), dim3(64), 0, st, out_keys, qoff, out_count, perm, dst_off,
+                       nq, is_edit, ids, dist_f, dist_i);
+    check_launch(__func__);
 }
 
 void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,

@@ -176,12 +176,20 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
     const int tile = (int)(w / ngroups);
     const int64_t lg = w % ngroups;
     const int rg = lane >> 4, col = lane & 15;
+    // the box test's verdicts for this tile: only 16-query blocks with a
+    // surviving (query, leaf) pair in this leaf group are tested again
+    const int64_t my_leaf = lg * 64 + lane;
+    const uint64_t box_m = live && my_leaf < n_leaves ? leaf_mask[(size_t)my_leaf * ntiles + tile] : 0ull;
+    uint64_t box_any = 0;                                 // bit c: some leaf keeps a query of block c
+#pragma unroll
+    for (int c = 0; c < 4; c++) box_any |= dev::ballot(((box_m >> (16 * c)) & 0xffffull) != 0) ? (1ull << c) : 0ull;
     uint4 A[4][KS];
     float pn[4][4], pe[4][4], R[4][4];
 #pragma unroll
     for (int r = 0; r < 4; r++) {
 #pragma unroll
-        for (int s = 0; s < KS; s++) A[r][s] = PL16t[((lg * 4 + r) * KS + s) * 64 + lane];
+        for (int s = 0; s < KS; s++)
+            A[r][s] = box_any ? PL16t[((lg * 4 + r) * KS + s) * 64 + lane] : make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int64_t leaf = lg * 64 + 16 * r + 4 * rg + e;
@@ -191,6 +199,15 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
         }
     }
     for (int c = 0; c < 4; c++) {
+        if (!((box_any >> c) & 1ull)) {
+            // every pair of this block already failed the box test
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                if (col == 0)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) s_bits[wave][16 * r + 4 * rg + e][c] = 0;
+            continue;
+        }
         const int64_t q = (int64_t)tile * 64 + 16 * c + col;
         uint4 B[KS];
 #pragma unroll
@@ -223,11 +240,10 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
             }
     }
     __syncthreads();
-    const int64_t leaf = lg * 64 + lane;
-    if (live && leaf < n_leaves) {
+    if (live && my_leaf < n_leaves && box_m) {
         const uint64_t m = (uint64_t)s_bits[wave][lane][0] | ((uint64_t)s_bits[wave][lane][1] << 16) |
                            ((uint64_t)s_bits[wave][lane][2] << 32) | ((uint64_t)s_bits[wave][lane][3] << 48);
-        leaf_mask[(size_t)leaf * ntiles + tile] &= m;
+        leaf_mask[(size_t)my_leaf * ntiles + tile] = box_m & m;
     }
 }
 
@@ -413,6 +429,36 @@ void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width
     if (rows == 0) return;
     const int64_t n = rows * width;
     hipLaunchKernelGGL(k_gather_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, perm, rows, width, dst);
+    check_launch(__func__);
+}
+
+__global__ void k_permute_queries(const int32_t *__restrict__ perm, int64_t nq, const float *__restrict__ base_s,
+                                  float *__restrict__ base_d, const int32_t *__restrict__ kq_s,
+                                  int32_t *__restrict__ kq_d, const float *__restrict__ qp_s, float *__restrict__ qp_d,
+                                  int mpad, const float *__restrict__ q32_s, float *__restrict__ q32_d, int dp,
+                                  const int32_t *__restrict__ near_s, int32_t *__restrict__ near_d, int nnear)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= nq) return;
+    const int64_t p = perm[i];
+    if (threadIdx.x == 0) {
+        base_d[i] = base_s[p];
+        kq_d[i] = kq_s[p];
+    }
+    for (int c = threadIdx.x; c < mpad; c += blockDim.x) qp_d[i * mpad + c] = qp_s[p * mpad + c];
+    if (q32_s)
+        for (int c = threadIdx.x; c < dp; c += blockDim.x) q32_d[i * dp + c] = q32_s[p * dp + c];
+    if (near_s)
+        for (int c = threadIdx.x; c < nnear; c += blockDim.x) near_d[i * nnear + c] = near_s[p * nnear + c];
+}
+
+void permute_queries(const int32_t *perm, int64_t nq, const float *base_s, float *base_d, const int32_t *kq_s,
+                     int32_t *kq_d, const float *qp_s, float *qp_d, int mpad, const float *q32_s, float *q32_d,
+                     int dp, const int32_t *near_s, int32_t *near_d, int nnear, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_permute_queries, dim3((unsigned)nq), dim3(64), 0, st, perm, nq, base_s, base_d, kq_s, kq_d,
+                       qp_s, qp_d, mpad, q32_s, q32_d, dp, near_s, near_d, nnear);
     check_launch(__func__);
 }
 

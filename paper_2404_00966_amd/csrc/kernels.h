@@ -178,8 +178,10 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
 // ---- grouping, verification, output (k_final.hip) ---------------------------
 void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
 void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st);  // out[n+1]
+// Writes only entries below grouped_cap (a larger candidate count is
+// scattered again into a larger buffer).
 void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
-                   Cand *grouped, hipStream_t st);
+                   Cand *grouped, int64_t grouped_cap, hipStream_t st);
 
 struct VerifyArgs {
     const Cand *grouped;       // candidates grouped by query
@@ -199,6 +201,16 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
                hipStream_t st);
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st);
 
+// cc[perm[i]] = out_count[i] (cc[i] without perm): answer counts in the
+// caller's query order.
+void perm_counts(const uint32_t *out_count, const int32_t *perm, int64_t nq, uint32_t *cc, hipStream_t st);
+// Result in the caller's query order straight from the sorted keys: batch
+// query i (caller query perm[i], or i without perm) writes its out_count[i]
+// keys from out_keys[qoff[i]] to ids / dist at dst_off[caller query].
+void emit_result(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int32_t *perm,
+                 const int64_t *dst_off, int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i,
+                 hipStream_t st);
+
 // CSR assembly: ids[res_off[q] + j] and dist from out_keys[qoff[q] + j].
 void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,
                int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i, hipStream_t st);
@@ -207,6 +219,13 @@ void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *ou
 constexpr int kNearLeaves = 8;   // nearest leaf pivots kept per query
 void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps, const uint16_t *Q16t, int64_t nq,
                int32_t *near, hipStream_t st);
+// Every per-query array into the batch order in one launch: row i of each
+// destination <- row perm[i] of its source (base, k, pivot distances of
+// width mpad, float32 rows of width dp, nearest leaves of width nnear; a
+// null source is skipped).
+void permute_queries(const int32_t *perm, int64_t nq, const float *base_s, float *base_d, const int32_t *kq_s,
+                     int32_t *kq_d, const float *qp_s, float *qp_d, int mpad, const float *q32_s, float *q32_d,
+                     int dp, const int32_t *near_s, int32_t *near_d, int nnear, hipStream_t st);
 // Stable sort of the queries by home leaf (near[q * kNearLeaves], keys in
 // [0, n_keys)): perm[i] = query at position i (k_sort.hip).
 size_t home_sort_bytes(int64_t nq, int64_t n_keys);
