@@ -291,18 +291,6 @@ __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v)
     return r;
 }
 
-// Global -> LDS copies without registers (gfx950 global_load_lds): lane l of
-// the wave writes its `bytes` at lds_wave_base + l * bytes.
-typedef __attribute__((address_space(3))) void lds_void;
-__device__ __forceinline__ void lds_dma16(const void *src, void *lds_wave_base)
-{
-    __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_wave_base, 16, 0, 0);
-}
-__device__ __forceinline__ void lds_dma4(const void *src, void *lds_wave_base)
-{
-    __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_wave_base, 4, 0, 0);
-}
-
 // Pre-pass: the active query tiles of every slab (some query of the tile
 // survives a leaf overlapping the slab) with the tile's union mask, written
 // as (tile, mask) pairs, and work items of at most kItemTiles pairs of one
@@ -389,6 +377,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     int64_t cur_slab = -1;
     uint4 A[RT][KS];
     float xr[RT][4];
+    uint32_t live16 = 0;
     long long units = 0;
     Cand *cbuf = s_cand[wave];
     int nb = 0;   // buffered candidates of this wave (wave-uniform)
@@ -405,15 +394,25 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
         __builtin_amdgcn_wave_barrier();
         nb = 0;
     };
-    // stage query tile t into buffer b: every wave copies kPer 1 KB runs of
-    // fragments; waves 0 and 1 copy the two 256-byte parameter rows
-    auto stage = [&](int t, int b) {
+    // query tile t through registers into LDS buffer b: every wave fetches
+    // kPer 1 KB runs of fragments, waves 0 and 1 the two 256-byte parameter
+    // rows.  The fetch of the next tile is issued before the current one
+    // computes and written to LDS after it (plain loads: the LDS reads of the
+    // current tile never wait on them).
+    uint4 rs[kPer];
+    float rt = 0.f, rq = 0.f;
+    auto fetch = [&](int t) __attribute__((always_inline)) {
         const uint4 *src = Q16t + (int64_t)t * kTileFrag;
 #pragma unroll
-        for (int j = 0; j < kPer; j++)
-            lds_dma16(src + 256 * j + threadIdx.x, &s_b[b][256 * j + 64 * wave]);
-        if (wave == 0) lds_dma4(tqe + (int64_t)t * 64 + lane, &s_t[b][0]);
-        if (wave == 1) lds_dma4(qn + (int64_t)t * 64 + lane, &s_qn[b][0]);
+        for (int j = 0; j < kPer; j++) rs[j] = src[256 * j + threadIdx.x];
+        if (wave == 0) rt = tqe[(int64_t)t * 64 + lane];
+        if (wave == 1) rq = qn[(int64_t)t * 64 + lane];
+    };
+    auto put = [&](int b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < kPer; j++) s_b[b][256 * j + threadIdx.x] = rs[j];
+        if (wave == 0) s_t[b][lane] = rt;
+        if (wave == 1) s_qn[b][lane] = rq;
     };
     for (;;) {
         if (threadIdx.x == 0) {
@@ -436,18 +435,36 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
 #pragma unroll
             for (int r = 0; r < RT; r++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) xr[r][e] = xn[row0 + 16 * r + 4 * rgrp + e];
+                for (int e = 0; e < 4; e++) xr[r][e] = -0.5f * xn[row0 + 16 * r + 4 * rgrp + e];
+            // this lane's 16 rows that are real, live objects (the wave's 64
+            // rows span two tombstone words)
+            const int64_t wd = row0 >> 5, nwords = (n + 31) >> 5;
+            const uint32_t tw0 = wd < nwords ? tomb[wd] : ~0u, tw1 = wd + 1 < nwords ? tomb[wd + 1] : ~0u;
+            live16 = 0;
+#pragma unroll
+            for (int r = 0; r < RT; r++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int lr = 16 * r + 4 * rgrp + e;
+                    const bool dead = ((lr < 32 ? tw0 >> lr : tw1 >> (lr - 32)) & 1u) || row0 + lr >= n;
+                    live16 |= (dead ? 0u : 1u) << (4 * r + e);
+                }
         }
         const float emax = slab_emax[slab];
         const float nmax = slab_nmax[slab];
-        stage(pair_tile[p0], 0);
-        __builtin_amdgcn_s_waitcnt(0);
+        // the item's (tile, query mask) list in registers, lane j holding pair j
+        const int my_tile = lane < ntl ? pair_tile[p0 + lane] : 0;
+        const uint64_t my_mask = lane < ntl ? pair_mask[p0 + lane] : 0ull;
+        fetch(__shfl(my_tile, 0, 64));
+        put(0);
         __syncthreads();
         for (int it = 0; it < ntl; it++) {
             const int buf = it & 1;
-            const int t = pair_tile[p0 + it];
-            const uint64_t mask = pair_mask[p0 + it];
-            if (it + 1 < ntl) stage(pair_tile[p0 + it + 1], buf ^ 1);   // lands while this tile computes
+            const int t = __shfl(my_tile, it, 64);
+            const uint64_t mask = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(my_mask >> 32), it, 64) << 32) |
+                                  (uint32_t)__shfl((int)(uint32_t)my_mask, it, 64);
+            const bool more = it + 1 < ntl;
+            if (more) fetch(__shfl(my_tile, it + 1, 64));   // lands while this tile computes
 #pragma unroll 1
             for (int c = 0; c < 4; c++) {
                 const uint32_t cm = (uint32_t)(mask >> (16 * c)) & 0xffffu;
@@ -465,35 +482,36 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                 uint4 B[KS];
 #pragma unroll
                 for (int s = 0; s < KS; s++) B[s] = s_b[buf][(c * KS + s) * 64 + lane];
+                // the accumulators start at -||x||^2 / 2, so the MFMA leaves
+                // a = q.x - ||x||^2 / 2 and the test below is one compare:
+                // xn - 2 q.x <= th  <=>  a >= -th / 2 (both scalings exact)
                 floatx4_t acc[RT];
 #pragma unroll
-                for (int r = 0; r < RT; r++) acc[r] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+                for (int r = 0; r < RT; r++) acc[r] = floatx4_t{xr[r][0], xr[r][1], xr[r][2], xr[r][3]};
 #pragma unroll
                 for (int s = 0; s < KS; s++)
 #pragma unroll
                     for (int r = 0; r < RT; r++)
                         acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[r][s]), as_bf16x8(B[s]), acc[r],
                                                                           0, 0, 0);
-                // candidate test: xn - 2 q.x <= (T + e_q + e_slab)^2 + eps - qn
-                uint32_t pm = 0;
+                // candidate test: xn - 2 q.x <= (T + e_q + e_slab)^2 + eps - qn;
+                // one ballot per output element (a compare into a scalar mask),
+                // the per-lane bits only when some pair passes
+                const float thh = -0.5f * th;
+                uint64_t anyp = 0;
 #pragma unroll
                 for (int r = 0; r < RT; r++)
 #pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        pm |= (fmaf(-2.f, acc[r][e], xr[r][e]) <= th ? 1u : 0u) << (4 * r + e);
-                if (dev::ballot(pm != 0)) {
-                    // drop padding rows and deleted objects, then compact into
-                    // the wave's buffer (flushed with one atomic when full)
+                    for (int e = 0; e < 4; e++) anyp |= dev::ballot(acc[r][e] >= thh);
+                if (anyp) {
+                    uint32_t pm = 0;
 #pragma unroll
                     for (int r = 0; r < RT; r++)
 #pragma unroll
-                        for (int e = 0; e < 4; e++) {
-                            const int bit = 4 * r + e;
-                            if ((pm >> bit) & 1u) {
-                                const int64_t pos = row0 + 16 * r + 4 * rgrp + e;
-                                if (pos >= n || ((tomb[pos >> 5] >> (pos & 31)) & 1u)) pm &= ~(1u << bit);
-                            }
-                        }
+                        for (int e = 0; e < 4; e++) pm |= (acc[r][e] >= thh ? 1u : 0u) << (4 * r + e);
+                    // drop padding rows and deleted objects, then compact into
+                    // the wave's buffer (flushed with one atomic when full)
+                    pm &= live16;
                     const int cnt = __popc(pm);
                     int tot;
                     const int off = dev::wave_excl_scan(cnt, &tot);
@@ -514,7 +532,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                                         Cand cd;
                                         cd.q = (int32_t)q;
                                         cd.pos = (int32_t)(row0 + 16 * r + 4 * rgrp + e);
-                                        cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], xr[r][e]) + qnn);
+                                        cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], qnn));
                                         cands[idx] = cd;
                                     }
                                 }
@@ -528,14 +546,14 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                                     Cand cd;
                                     cd.q = (int32_t)q;
                                     cd.pos = (int32_t)(row0 + 16 * r + 4 * rgrp + e);
-                                    cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], xr[r][e]) + qnn);
+                                    cd.val = (uint64_t)__float_as_uint(fmaf(-2.f, acc[r][e], qnn));
                                     cbuf[nb + off + j++] = cd;
                                 }
                         nb += tot;
                     }
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0);   // the next tile's copies have landed
+            if (more) put(buf ^ 1);
             __syncthreads();
         }
     }
