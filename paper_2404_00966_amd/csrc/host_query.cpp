@@ -70,7 +70,7 @@ struct PinLayout {
         qoff = small + 256;
         counts = up(qoff + (size_t)(nq + 1) * sizeof(int64_t));
         counters = up(counts + (size_t)(nq + 1) * sizeof(uint32_t));
-        blk = counters + 256;                                   // host-to-device: workgroup-mode queries
+        blk = up(counters + (size_t)k::kCounterWords * sizeof(uint64_t));   // host-to-device: workgroup-mode queries
         big = up(blk + (size_t)(nq + 1) * sizeof(int32_t));    // scratch offsets
         offs = up(big + (size_t)(nq + 1) * sizeof(int64_t));   // result offsets
         bytes = up(offs + (size_t)(nq + 1) * sizeof(int64_t));
@@ -517,8 +517,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     wsp<float>(cx, W_THR, nqpad);
     int32_t *kq = wsp<int32_t>(cx, W_KQ, nqpad);
     int32_t *home = wsp<int32_t>(cx, W_HOME, nqpad);
-    unsigned long long *counters = wsp<unsigned long long>(cx, W_COUNTERS, 8);
-    k::fill_u32(reinterpret_cast<uint32_t *>(counters), 16, 0u, st);
+    unsigned long long *counters = wsp<unsigned long long>(cx, W_COUNTERS, k::kCounterWords);
+    k::fill_u32(reinterpret_cast<uint32_t *>(counters), 2 * k::kCounterWords, 0u, st);
     if (nq > 0) {
         GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
         GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -797,7 +797,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                        static_cast<int32_t *>(priv->dist), st);
         int64_t *htot = reinterpret_cast<int64_t *>(pin + pl.offs);
         GTS_HIP(hipMemcpyAsync(htot, doffs + nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipMemcpyAsync(hc, counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(hc, counters, k::kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         GTS_HIP(hipStreamSynchronize(st));
         out->total = *htot;
         out->offsets = doffs;
@@ -885,7 +885,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         GTS_HIP(hipMemcpyAsync(priv->ids, ids_d, total * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GTS_HIP(hipMemcpyAsync(priv->dist, dist_d, total * sizeof(float), hipMemcpyDeviceToHost, st));
     }
-    GTS_HIP(hipMemcpyAsync(hc, counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipMemcpyAsync(hc, counters, k::kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
     out->total = total;
     out->offsets = static_cast<int64_t *>(priv->offsets);
@@ -896,6 +896,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     }
 
     // ---- counters ----------------------------------------------------------------------
+    for (int c = 0; c < k::kCounters; c++) {   // sum the stripes into hc[c]
+        unsigned long long v = 0;
+        for (int j = 0; j < k::kStripes; j++) v += hc[((size_t)c * k::kStripes + j) * k::kStripeStride];
+        hc[c] = v;   // slots 1..7 lie in the padding of counter 0's first stripe
+    }
     cx->stats.node_tests = (int64_t)hc[0];
     if (cx->stats.leaf_pairs == 0) cx->stats.leaf_pairs = (int64_t)hc[1];
     cx->stats.tile_pairs = (int64_t)hc[2];

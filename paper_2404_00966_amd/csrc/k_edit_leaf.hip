@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
         }
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) tests += __shfl_xor(tests, o2, 64);
-    if (lane == 0 && tests) atomicAdd(&counters[CNT_NODE_TESTS], (unsigned long long)tests);
+    if (lane == 0 && tests) count_add(counters, CNT_NODE_TESTS, (unsigned long long)tests);
 }
 
 // Leaves are reached from the cells that passed, query by query: one wave per

@@ -355,7 +355,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
                               &verified, emit);
     __syncthreads();
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
-    if (lane == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
     const int nk = s_n;
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
@@ -451,7 +451,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
     };
     recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, emit);
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
-    if (lane == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
     const int P = dev::next_pow2(nk > 1 ? nk : 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
         }
     }
     __syncthreads();
-    if (verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
+    if (verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
     const int nk = s_n;
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }

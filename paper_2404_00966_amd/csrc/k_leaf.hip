@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
     }
     __syncthreads();
     const int nl = s_nl, count = s_start[nl];
-    if (threadIdx.x == 0) atomicAdd(&counters[CNT_BOUND_EVALS], (unsigned long long)count);
+    if (threadIdx.x == 0) count_add(counters, CNT_BOUND_EVALS, (unsigned long long)count);
     if (count < k) {
         if (threadIdx.x == 0) tq[q] = INFINITY;
         return;

@@ -213,9 +213,9 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
         plain_flush_l2(o, a, q, qrow, cut, s_cand, s_nc, &verified);
         __syncthreads();
     }
-    if (threadIdx.x % 16 == 0 && verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
-    if (threadIdx.x == 0 && leaves) atomicAdd(&a.counters[CNT_LEAF_PAIRS], (unsigned long long)leaves);
-    if (tests) atomicAdd(&a.counters[CNT_NODE_TESTS], (unsigned long long)tests);
+    if (threadIdx.x % 16 == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
+    if (threadIdx.x == 0 && leaves) count_add(a.counters, CNT_LEAF_PAIRS, (unsigned long long)leaves);
+    if (tests) count_add(a.counters, CNT_NODE_TESTS, (unsigned long long)tests);
 }
 
 void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const float *PT, const float *Q32,
@@ -314,9 +314,9 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_edit(TreeView t, EditView
         plain_flush_edit(o, a, q, s_peq, plen, cut, s_cand, s_nc, &verified, s_lut);
         __syncthreads();
     }
-    if (verified) atomicAdd(&a.counters[CNT_VERIFIED], (unsigned long long)verified);
-    if (threadIdx.x == 0 && leaves) atomicAdd(&a.counters[CNT_LEAF_PAIRS], (unsigned long long)leaves);
-    if (tests) atomicAdd(&a.counters[CNT_NODE_TESTS], (unsigned long long)tests);
+    if (verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
+    if (threadIdx.x == 0 && leaves) count_add(a.counters, CNT_LEAF_PAIRS, (unsigned long long)leaves);
+    if (tests) count_add(a.counters, CNT_NODE_TESTS, (unsigned long long)tests);
 }
 
 void plain_edit(const TreeView &t, const EditView &o, const uint8_t *pchars, const int32_t *poff, int m,

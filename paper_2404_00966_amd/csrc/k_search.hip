@@ -112,8 +112,7 @@ __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box,
         if (live && lane < nl) leaf_mask[(size_t)(c0 + lane) * ntiles + tile] = mine;
     }
     if (live && lane == 0 && tests)
-        atomicAdd(&counters[CNT_NODE_TESTS],
-                  (unsigned long long)min<int64_t>(64, nq - (int64_t)tile * 64) * (unsigned long long)tests);
+        count_add(counters, CNT_NODE_TESTS, (unsigned long long)min<int64_t>(64, nq - (int64_t)tile * 64) * (unsigned long long)tests);
 }
 
 void leaf_box(const TreeView &t, const float *QP, const float *thr, int64_t nq, int ntiles, uint64_t *leaf_mask,
@@ -294,8 +293,12 @@ __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v)
 // Pre-pass: the active query tiles of every slab (some query of the tile
 // survives a leaf overlapping the slab) with the tile's union mask, written
 // as (tile, mask) pairs, and work items of at most kItemTiles pairs of one
-// slab.  One workgroup per slab: count, reserve with one atomic, then fill.
+// slab.  One workgroup per kSlabsPerBlock slabs: count, reserve the pairs
+// and items of all of them with one atomic each (not one per slab: the
+// counters are shared by the whole grid), then fill.
 constexpr int kItemTiles = kSweepItemTiles;
+
+constexpr int kSlabsPerBlock = 16;
 
 __global__ __launch_bounds__(256) void k_slab_items(const int32_t *__restrict__ slab_leaf_lo,
                                                     const int32_t *__restrict__ slab_leaf_hi, int64_t n_slabs,
@@ -304,46 +307,64 @@ __global__ __launch_bounds__(256) void k_slab_items(const int32_t *__restrict__ 
                                                     uint32_t *__restrict__ pair_count, int4 *__restrict__ items,
                                                     uint32_t *__restrict__ item_count)
 {
-    __shared__ int s_cnt[4];
-    __shared__ uint32_t s_base, s_fill;
-    const int64_t slab = blockIdx.x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int l_lo = slab_leaf_lo[slab], l_hi = slab_leaf_hi[slab];
-    auto tile_mask = [&](int t) {
+    __shared__ uint32_t s_cnt[kSlabsPerBlock], s_pbase[kSlabsPerBlock], s_fill[kSlabsPerBlock];
+    const int64_t slab0 = (int64_t)blockIdx.x * kSlabsPerBlock;
+    const int ns = (int)min<int64_t>(kSlabsPerBlock, n_slabs - slab0);
+    const int lane = threadIdx.x & 63;
+    auto tile_mask = [&](int l_lo, int l_hi, int t) {
         uint64_t m = 0;
         for (int l = l_lo; l <= l_hi; l++) m |= leaf_mask[(size_t)l * ntiles + t];
         return m;
     };
-    int cnt = 0;
-    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
-        const int t = t0 + (int)threadIdx.x;
-        cnt += __popcll(dev::ballot(t < ntiles && tile_mask(t) != 0ull));
+    if (threadIdx.x < kSlabsPerBlock) {
+        s_cnt[threadIdx.x] = 0;
+        s_fill[threadIdx.x] = 0;
     }
-    if (lane == 0) s_cnt[wave] = cnt;
     __syncthreads();
+    for (int j = 0; j < ns; j++) {
+        const int l_lo = slab_leaf_lo[slab0 + j], l_hi = slab_leaf_hi[slab0 + j];
+        int cnt = 0;
+        for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+            const int t = t0 + (int)threadIdx.x;
+            cnt += __popcll(dev::ballot(t < ntiles && tile_mask(l_lo, l_hi, t) != 0ull));
+        }
+        if (lane == 0 && cnt) atomicAdd(&s_cnt[j], (uint32_t)cnt);
+    }
+    __syncthreads();
+    // one reservation of pairs and one of items for the block's slabs
     if (threadIdx.x == 0) {
-        const int total = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-        s_base = total ? atomicAdd(pair_count, (uint32_t)total) : 0u;
-        s_fill = 0;
-        const int nit = (total + kItemTiles - 1) / kItemTiles;
-        if (nit) {
-            const uint32_t i0 = atomicAdd(item_count, (uint32_t)nit);
-            for (int k = 0; k < nit; k++)
-                items[i0 + k] = make_int4((int)slab, (int)s_base + k * kItemTiles, min(kItemTiles, total - k * kItemTiles), 0);
+        uint32_t total = 0, nit = 0;
+        for (int j = 0; j < ns; j++) {
+            total += s_cnt[j];
+            nit += (s_cnt[j] + kItemTiles - 1) / kItemTiles;
+        }
+        const uint32_t pb = total ? atomicAdd(pair_count, total) : 0u;
+        uint32_t ib = nit ? atomicAdd(item_count, nit) : 0u;
+        uint32_t at = pb;
+        for (int j = 0; j < ns; j++) {
+            s_pbase[j] = at;
+            const int c = (int)s_cnt[j];
+            for (int k = 0; k * kItemTiles < c; k++)
+                items[ib++] = make_int4((int)(slab0 + j), (int)(at + k * kItemTiles), min(kItemTiles, c - k * kItemTiles), 0);
+            at += (uint32_t)c;
         }
     }
     __syncthreads();
-    for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
-        const int t = t0 + (int)threadIdx.x;
-        const uint64_t m = t < ntiles ? tile_mask(t) : 0ull;
-        const uint64_t b = dev::ballot(m != 0ull);
-        uint32_t at = 0;
-        if (lane == 0 && b) at = atomicAdd(&s_fill, (uint32_t)__popcll(b));
-        at = __shfl(at, 0, 64);
-        if (m) {
-            const uint32_t idx = s_base + at + (uint32_t)dev::lanes_below(b);
-            pair_tile[idx] = t;
-            pair_mask[idx] = m;
+    for (int j = 0; j < ns; j++) {
+        if (s_cnt[j] == 0) continue;
+        const int l_lo = slab_leaf_lo[slab0 + j], l_hi = slab_leaf_hi[slab0 + j];
+        for (int t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+            const int t = t0 + (int)threadIdx.x;
+            const uint64_t m = t < ntiles ? tile_mask(l_lo, l_hi, t) : 0ull;
+            const uint64_t b = dev::ballot(m != 0ull);
+            uint32_t at = 0;
+            if (lane == 0 && b) at = atomicAdd(&s_fill[j], (uint32_t)__popcll(b));
+            at = __shfl(at, 0, 64);
+            if (m) {
+                const uint32_t idx = s_pbase[j] + at + (uint32_t)dev::lanes_below(b);
+                pair_tile[idx] = t;
+                pair_mask[idx] = m;
+            }
         }
     }
 }
@@ -558,14 +579,15 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
         }
     }
     if (nb) flush();
-    if (lane == 0 && units) atomicAdd(&counters[CNT_TILE_PAIRS], (unsigned long long)units);
+    if (lane == 0 && units) count_add(counters, CNT_TILE_PAIRS, (unsigned long long)units);
 }
 
 void slab_items(const SlabView &s, const uint64_t *leaf_mask, int ntiles, const SweepWork &w, hipStream_t st)
 {
     fill_u32(w.counts, 3, 0u, st);   // pairs, items, work
     if (s.n_slabs == 0 || ntiles == 0) return;
-    hipLaunchKernelGGL(k_slab_items, dim3((unsigned)s.n_slabs), dim3(256), 0, st, s.leaf_lo, s.leaf_hi, s.n_slabs,
+    const unsigned grid = (unsigned)((s.n_slabs + kSlabsPerBlock - 1) / kSlabsPerBlock);
+    hipLaunchKernelGGL(k_slab_items, dim3(grid), dim3(256), 0, st, s.leaf_lo, s.leaf_hi, s.n_slabs,
                        leaf_mask, ntiles, w.pair_tile, w.pair_mask, w.counts + 0, w.items, w.counts + 1);
     check_launch(__func__);
 }

@@ -10,6 +10,17 @@ namespace k {
 
 // Slots of the device counters behind gts_stats.
 enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3, CNT_BOUND_EVALS = 4 };
+constexpr int kCounters = 8;
+// Each counter is striped over kStripes words a cache line apart: a
+// workgroup adds to stripe blockIdx.x % kStripes, so thousands of
+// workgroups do not queue on one address.  The host sums the stripes.
+constexpr int kStripes = 64;
+constexpr int kStripeStride = 16;                       // 16 x 8 bytes = one 128-byte line
+constexpr int kCounterWords = kCounters * kStripes * kStripeStride;
+__device__ __forceinline__ void count_add(unsigned long long *counters, int which, unsigned long long v)
+{
+    atomicAdd(&counters[((size_t)which * kStripes + blockIdx.x % kStripes) * kStripeStride], v);
+}
 
 // Raise the launch error left by the wrapper `name` (a bad grid or resource
 // request), so that it surfaces at its own call and not at a later one.
