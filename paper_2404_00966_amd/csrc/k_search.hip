@@ -408,9 +408,13 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(cand_count, (uint32_t)nb);
         base = __shfl(base, 0, 64);
+        // whole 16-byte records (one dwordx4 store per lane), so the flushed
+        // run is written as full lines
+        const uint4 *src = reinterpret_cast<const uint4 *>(cbuf);
+        uint4 *dst = reinterpret_cast<uint4 *>(cands);
         for (int i = lane; i < nb; i += 64) {
             const int64_t idx = (int64_t)base + i;
-            if (idx < cand_cap) cands[idx] = cbuf[i];
+            if (idx < cand_cap) dst[idx] = src[i];
         }
         __builtin_amdgcn_wave_barrier();
         nb = 0;

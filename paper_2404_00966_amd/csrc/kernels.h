@@ -33,11 +33,12 @@ void require(bool ok, const char *what);
 //   pos >= 0 : candidate at tree position pos; val = float bits of an
 //              estimate of the squared distance (L2 tile path) or 0.
 //   pos <  0 : already verified; val = sort key (distance bits << 32 | id).
-struct Cand {
+struct alignas(16) Cand {
     int32_t q;
     int32_t pos;
     uint64_t val;
 };
+static_assert(sizeof(Cand) == 16, "a candidate is one 16-byte record");
 
 // ---- preparation (k_prep.hip) ---------------------------------------------
 void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, int stride, int ksteps,
