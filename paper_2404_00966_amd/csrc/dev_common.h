@@ -62,64 +62,100 @@ __device__ __forceinline__ float wave_min(float v)
 // 64*W characters.  Bytes are first mapped to alphabet codes by lut (the
 // index's alphabet; bytes outside it share the last, all-zero row); peq[c*4+w]
 // holds bit i of word w set iff pattern[64w+i] has code c.  Returns the exact
-// distance when it is <= cutoff, otherwise some value > cutoff (early exit as
-// soon as the last row proves the final distance exceeds cutoff: each
-// remaining text character can lower it by at most one).
+// distance when it is <= cutoff, otherwise some value > cutoff.
+//
+// Early exit: with m = plen and n = tlen, every alignment path crosses column
+// j at some row i and still needs at least |(m - i) - (n - j)| operations;
+// vertically adjacent cells differ by at most one, so the final distance is
+// at least D[i*][j] on the row i* = j + m - n that ends on the last cell's
+// diagonal.  That value is read off the vertical deltas every kChunk columns
+// (the text characters of a chunk are loaded together, so a text in global
+// memory costs one load latency per chunk, not per character).
 // ---------------------------------------------------------------------------
+template <int W, class PeqPtr>
+__device__ __forceinline__ void myers_column(PeqPtr peq, int c, uint64_t (&VP)[W], uint64_t (&VN)[W], int topw,
+                                             uint64_t topbit, int &score)
+{
+    uint64_t Xv[W], HP[W], HN[W];
+    uint64_t carry = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const uint64_t Eq = peq[c * 4 + w];
+        Xv[w] = Eq | VN[w];
+        const uint64_t a = Eq & VP[w];
+        const uint64_t s = a + VP[w];
+        const uint64_t c1 = s < a ? 1ull : 0ull;
+        const uint64_t s2 = s + carry;
+        const uint64_t c2 = s2 < s ? 1ull : 0ull;
+        carry = c1 | c2;
+        const uint64_t Xh = (s2 ^ VP[w]) | Eq;
+        HP[w] = VN[w] | ~(Xh | VP[w]);
+        HN[w] = VP[w] & Xh;
+    }
+    uint64_t hp_top = 0, hn_top = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (w == topw) { hp_top = HP[w]; hn_top = HN[w]; }
+    score += (hp_top & topbit) ? 1 : 0;
+    score -= (hn_top & topbit) ? 1 : 0;
+    // shift the horizontal deltas down one row; row 0 has delta +1
+#pragma unroll
+    for (int w = W - 1; w >= 0; w--) {
+        const uint64_t inp = (w == 0) ? 1ull : (HP[w - 1] >> 63);
+        const uint64_t inn = (w == 0) ? 0ull : (HN[w - 1] >> 63);
+        HP[w] = (HP[w] << 1) | inp;
+        HN[w] = (HN[w] << 1) | inn;
+    }
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        VP[w] = HN[w] | ~(Xv[w] | HP[w]);
+        VN[w] = HP[w] & Xv[w];
+    }
+}
+
+// D[i][j] of the current column j: D[0][j] = j plus the vertical deltas of
+// rows 1..i (bit r of VP/VN is the delta from row r to row r+1).
+template <int W>
+__device__ __forceinline__ int myers_row_value(const uint64_t (&VP)[W], const uint64_t (&VN)[W], int j, int i)
+{
+    int v = j;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const int bits = i - 64 * w;
+        const uint64_t m = bits >= 64 ? ~0ull : (bits > 0 ? ((1ull << bits) - 1ull) : 0ull);
+        v += __popcll(VP[w] & m) - __popcll(VN[w] & m);
+    }
+    return v;
+}
+
 template <int W, class PeqPtr, class LutPtr>
 __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_t *text, int tlen,
                                               int cutoff, LutPtr lut)
 {
     if (plen == 0) return tlen;
+    if (plen - tlen > cutoff || tlen - plen > cutoff) return cutoff + 1;
     uint64_t VP[W], VN[W];
 #pragma unroll
     for (int w = 0; w < W; w++) {
-        int bits = plen - 64 * w;
+        const int bits = plen - 64 * w;
         VP[w] = bits >= 64 ? ~0ull : (bits > 0 ? ((1ull << bits) - 1ull) : 0ull);
         VN[w] = 0ull;
     }
     const int topw = (plen - 1) >> 6;
     const uint64_t topbit = 1ull << ((plen - 1) & 63);
     int score = plen;
-    for (int j = 0; j < tlen; j++) {
-        const int c = lut[text[j]];
-        uint64_t Eq[W], Xv[W], Xh[W], HP[W], HN[W];
-        uint64_t carry = 0;
+    constexpr int kChunk = 8;
+    int j = 0;
+    for (; j + kChunk <= tlen; j += kChunk) {
+        int cs[kChunk];
 #pragma unroll
-        for (int w = 0; w < W; w++) {
-            Eq[w] = peq[c * 4 + w];
-            Xv[w] = Eq[w] | VN[w];
-            uint64_t a = Eq[w] & VP[w];
-            uint64_t s = a + VP[w];
-            uint64_t c1 = s < a ? 1ull : 0ull;
-            uint64_t s2 = s + carry;
-            uint64_t c2 = s2 < s ? 1ull : 0ull;
-            carry = c1 | c2;
-            Xh[w] = (s2 ^ VP[w]) | Eq[w];
-            HP[w] = VN[w] | ~(Xh[w] | VP[w]);
-            HN[w] = VP[w] & Xh[w];
-        }
-        uint64_t hp_top = 0, hn_top = 0;
+        for (int u = 0; u < kChunk; u++) cs[u] = lut[text[j + u]];
 #pragma unroll
-        for (int w = 0; w < W; w++)
-            if (w == topw) { hp_top = HP[w]; hn_top = HN[w]; }
-        score += (hp_top & topbit) ? 1 : 0;
-        score -= (hn_top & topbit) ? 1 : 0;
-        // shift the horizontal deltas down one row; row 0 has delta +1
-#pragma unroll
-        for (int w = W - 1; w >= 0; w--) {
-            uint64_t inp = (w == 0) ? 1ull : (HP[w - 1] >> 63);
-            uint64_t inn = (w == 0) ? 0ull : (HN[w - 1] >> 63);
-            HP[w] = (HP[w] << 1) | inp;
-            HN[w] = (HN[w] << 1) | inn;
-        }
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            VP[w] = HN[w] | ~(Xv[w] | HP[w]);
-            VN[w] = HP[w] & Xv[w];
-        }
-        if (score - (tlen - 1 - j) > cutoff) return cutoff + 1;
+        for (int u = 0; u < kChunk; u++) myers_column<W>(peq, cs[u], VP, VN, topw, topbit, score);
+        const int is = j + kChunk + plen - tlen;   // in (.., plen]
+        if (is > 0 && myers_row_value<W>(VP, VN, j + kChunk, is) > cutoff) return cutoff + 1;
     }
+    for (; j < tlen; j++) myers_column<W>(peq, lut[text[j]], VP, VN, topw, topbit, score);
     return score;
 }
 
