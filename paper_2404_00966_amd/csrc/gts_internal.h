@@ -143,6 +143,9 @@ struct IndexData {
     DevBuf cell_len;             // int32 [n_centres][2] string length range
     DevBuf leaf_cell;            // int32 [n_leaves][2] first and last cell of a leaf
     DevBuf cell_leaf;            // int32 [n_centres][2] first and last leaf of a cell
+    DevBuf cell_dist;            // uint8 [n_centres][n_centres] centre-to-centre distances
+    DevBuf qg_off;               // int32 [kQgramBuckets + 1] centres per q-gram bucket (CSR)
+    DevBuf qg_cell;              // int32 centres (chain rank) listed by bucket
     // both
     float pt_max = 0.f;          // largest pivot-table value
     DevBuf ids;                  // uint32 [n] id at each position

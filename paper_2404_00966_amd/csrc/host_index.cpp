@@ -304,6 +304,35 @@ void build_tree(gts_index *idx, const HostObjects &objs)
             upload(d.cchars, rc, st);
             upload(d.coff, ro, st);
             d.n_centres = K;
+            // centre-to-centre distances in chain order (strings of at most
+            // kMaxStrlen bytes: every distance fits a byte), and the q-gram
+            // buckets of the centre strings (CSR, ranks ascending per bucket)
+            std::vector<uint8_t> cdist((size_t)K * K);
+            for (int r1 = 0; r1 < K; r1++)
+                for (int r2 = 0; r2 < K; r2++) {
+                    const float v = dk[(size_t)by_rank[r1] * K + by_rank[r2]];
+                    k::require(v >= 0.f && v <= 255.f, "build: centre distance outside 0..255");
+                    cdist[(size_t)r1 * K + r2] = (uint8_t)v;
+                }
+            upload(d.cell_dist, cdist, st);
+            std::vector<uint64_t> ent;   // (bucket << 32) | rank
+            for (int r = 0; r < K; r++) {
+                const int len = ro[r + 1] - ro[r];
+                const size_t e0 = ent.size();
+                for (int p = 0; p + k::kQgram <= len; p++)
+                    ent.push_back(((uint64_t)k::qgram_bucket(rc.data() + ro[r] + p) << 32) | (uint32_t)r);
+                std::sort(ent.begin() + e0, ent.end());
+                ent.erase(std::unique(ent.begin() + e0, ent.end()), ent.end());
+            }
+            std::sort(ent.begin(), ent.end());
+            std::vector<int32_t> qoff(k::kQgramBuckets + 1, 0), qcell(std::max<size_t>(ent.size(), 1), 0);
+            for (size_t e = 0; e < ent.size(); e++) {
+                qoff[(ent[e] >> 32) + 1]++;
+                qcell[e] = (int32_t)(uint32_t)ent[e];
+            }
+            for (int b2 = 0; b2 < k::kQgramBuckets; b2++) qoff[b2 + 1] += qoff[b2];
+            upload(d.qg_off, qoff, st);
+            upload(d.qg_cell, qcell, st);
         }
         std::iota(perm.begin(), perm.end(), 0);
         std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {

@@ -32,7 +32,7 @@ enum Ws {
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
-    W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR,
+    W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
@@ -590,7 +590,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     const bool edit_cells = !l2 && b.mode == GTS_MODE_BATCHED && d.n_centres > 0 && nq > 0;
     const float delta = (float)((d.dim + 8) * 5.9604645e-8);
     k::CellView cv{d.cchars.as<uint8_t>(), d.coff.as<int32_t>(), d.cellR.as<float>(), d.cell_box.as<float>(),
-                   d.cell_len.as<int32_t>(), d.n_centres};
+                   d.cell_len.as<int32_t>(), d.n_centres, d.cell_dist.as<uint8_t>(), d.qg_off.as<int32_t>(),
+                   d.qg_cell.as<int32_t>()};
     int32_t *qcells0 = nullptr, *qcnt0 = nullptr;   // passing cells per position of the length order
     // the cell test runs on the queries in length order, so that the tiles'
     // patterns have similar word counts; pos_of[q] = position of query q
@@ -609,8 +610,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
         qcells0 = wsp<int32_t>(cx, W_QCELLS0, (size_t)nq * k::kQueryCells);
         qcnt0 = wsp<int32_t>(cx, W_QCNT0, nq);
+        int32_t *piv = wsp<int32_t>(cx, W_PIV, (size_t)2 * nq);
+        k::edit_pivot(oe, qe, nq, cv, piv, piv + nq, st);
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
-                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, qcells0, qcnt0, counters, dorder, st);
+                          cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, piv, piv + nq, qcells0, qcnt0, counters,
+                          dorder, st);
     }
     // the nearest-leaf search and the leaf-window kNN bound run on bf16 MFMA
     // fragments of at most kMaxMfmaDim coordinates; wider rows use the tree

@@ -95,20 +95,17 @@ void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// Cell and leaf tests.  Workgroup = (64-query tile, chunk of cells or leaves),
-// four waves; the 64 lanes of a wave are the tile's queries (each the Myers
-// pattern of its own lane) and a wave walks its balls one at a time: the
-// ball's pivot string is the common text, staged as codes in LDS.  Per lane
-// the cutoff is T_q + R with the early exit of the bit-parallel recurrence;
-// cheaper tests go first.  The tile's match tables sit in LDS when they fit
-// (TAB), else lanes read their own query's table from global memory.
-//
-// Cells (the clusters that order the leaves) are tested first: a cell passes
-// for a query when its box over the global pivot distances (Lemma 1 on every
-// pivot), its string-length range and its centre ball all admit T_q.  A leaf
-// starts from the union of its cells' masks and then takes its own ball test.
+// Cell test.  Workgroup = (64-query tile, 256 cells), one cell per lane: the
+// lane keeps its cell's box, length range and radius in registers and walks
+// the tile's queries, whose pivot distances, lengths, thresholds and pivot
+// centres sit in LDS (every lane reads the same entry: a broadcast).  A cell
+// passes the cheap tests for a query when its box over the global pivot
+// distances (Lemma 1 on every pivot), its string-length range and Lemma 1
+// with the query's pivot centre admit T_q; those (query, cell) pairs then take
+// the exact ball test d(q, centre) <= T_q + R_c in the lane that holds the
+// cell, the query's match table in LDS when the tile's tables fit (TAB), the
+// centre string as the text.
 // ---------------------------------------------------------------------------
-constexpr int kBallChunk = 256;
 constexpr int kTileTabWords = 4096;   // 32 KiB of LDS
 
 struct GlobalPeq {
@@ -132,95 +129,97 @@ __device__ __forceinline__ void load_tile_tab(uint64_t *s_tab, const QueryEdit &
     }
 }
 
-// Ball test of the wave's queries against one pivot string: lanes with `pass`
-// set keep it iff d(q, pivot) <= cut.  s_code is the wave's staging row.
-// W is the table layout's word count; the recurrence runs on wt <= W words,
-// the longest pattern of the wave (wave-uniform).
-template <int W, bool TAB>
-__device__ __forceinline__ bool ball_pass(bool pass, const uint8_t *__restrict__ chars, int32_t s0, int tl, int plen,
-                                          int cut, uint8_t *s_code, const uint8_t *s_lut, const uint64_t *s_tab,
-                                          const uint64_t *gtab, int lane, int wt)
-{
-    for (int b = lane; b < tl; b += 64) s_code[b] = s_lut[chars[s0 + b]];
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    pass = pass && abs(plen - tl) <= cut;
-    if (pass) {
-        int d;
-        if (TAB) {
-            const TilePeq t{s_tab, W, lane};
-            if (W >= 2 && wt <= 1) d = dev::myers_distance<1>(t, plen, s_code, tl, cut, NoLut{});
-            else if (W >= 3 && wt <= 2) d = dev::myers_distance<2>(t, plen, s_code, tl, cut, NoLut{});
-            else if (W >= 4 && wt <= 3) d = dev::myers_distance<3>(t, plen, s_code, tl, cut, NoLut{});
-            else d = dev::myers_distance<W>(t, plen, s_code, tl, cut, NoLut{});
-        } else {
-            const GlobalPeq t{gtab};
-            if (W >= 2 && wt <= 1) d = dev::myers_distance<1>(t, plen, s_code, tl, cut, NoLut{});
-            else if (W >= 3 && wt <= 2) d = dev::myers_distance<2>(t, plen, s_code, tl, cut, NoLut{});
-            else if (W >= 4 && wt <= 3) d = dev::myers_distance<3>(t, plen, s_code, tl, cut, NoLut{});
-            else d = dev::myers_distance<W>(t, plen, s_code, tl, cut, NoLut{});
-        }
-        pass = d <= cut;
-    }
-    __builtin_amdgcn_wave_barrier();
-    return pass;
-}
-
 template <int W, int MP, bool TAB>
 __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv, const int32_t *__restrict__ qlen,
                                                         const float *__restrict__ QP, const float *__restrict__ T,
                                                         int64_t nq, int ntiles, CellView cv,
+                                                        const int32_t *__restrict__ piv,
+                                                        const int32_t *__restrict__ pivd,
                                                         int32_t *__restrict__ qcells, int32_t *__restrict__ qcnt,
                                                         unsigned long long *__restrict__ counters,
                                                         const int32_t *__restrict__ order)
 {
     extern __shared__ uint64_t s_tab[];
-    __shared__ uint8_t s_code[4][256];
+    __shared__ float s_qp[64][MP];
+    __shared__ int s_q[64], s_plen[64], s_tq[64], s_hc[64], s_hd[64];
     __shared__ uint8_t s_lut[256];
-    const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
     const int tile = (int)(blockIdx.x % ntiles);
     const int64_t chunk = blockIdx.x / ntiles;
-    const int64_t p = (int64_t)tile * 64 + lane;   // position in the tile order
-    const bool qok = p < nq;
-    const int64_t q = qok ? (order ? order[p] : p) : 0;
+    const int nj = (int)min((int64_t)64, nq - (int64_t)tile * 64);
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) {
+        const int64_t p = (int64_t)tile * 64 + j;
+        const bool ok = j < nj;
+        const int64_t q = ok ? (order ? order[p] : p) : 0;
+        const int h = ok && piv ? piv[q] : -1;
+        s_q[j] = (int)q;
+        s_plen[j] = ok ? qlen[q] : 0;
+        s_tq[j] = ok ? (int)T[q] : -1;
+        s_hc[j] = h;
+        s_hd[j] = h >= 0 ? pivd[q] : 0;
+    }
+    for (int i = threadIdx.x; i < 64 * MP; i += blockDim.x) {
+        const int j = i / MP;
+        const int64_t p = (int64_t)tile * 64 + j;
+        s_qp[j][i % MP] = j < nj ? QP[(size_t)(order ? order[p] : p) * MP + i % MP] : 0.f;
+    }
     for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
     if (TAB) load_tile_tab<W>(s_tab, qv, o.rows, tile, nq, order);
     __syncthreads();
-    const int plen = qok ? qlen[q] : 0;
-    const int tq = qok ? (int)T[q] : -1;
-    int wt = (plen + 63) >> 6;
-#pragma unroll
-    for (int o2 = 32; o2 > 0; o2 >>= 1) wt = max(wt, __shfl_xor(wt, o2, 64));
-    float qp[MP];
-#pragma unroll
-    for (int i = 0; i < MP; i++) qp[i] = qok ? QP[(size_t)q * MP + i] : 0.f;
-    const uint64_t *gtab = qv.peq + (size_t)(qok ? q : 0) * o.rows * 4;
-    long long tests = 0;
-    for (int64_t ci = wave; ci < kBallChunk; ci += 4) {
-        const int64_t c = chunk * kBallChunk + ci;
-        if (c >= cv.n) break;
+    const int64_t c = chunk * 256 + threadIdx.x;
+    const float R = c < cv.n ? cv.R[c] : -INFINITY;
+    long long tests = c < cv.n ? nj : 0;
+    uint64_t m = 0ull;   // bit j: query j passed the cheap tests
+    if (R >= 0.f) {
+        float lo[MP], hi[MP];
         const float *b = cv.box + (size_t)c * 2 * MP;
-        float g = -INFINITY;
 #pragma unroll
-        for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(b[i] - qp[i], qp[i] - b[MP + i]));
-        const int lmin = cv.len[2 * c], lmax = cv.len[2 * c + 1];
-        bool pass = qok && g <= (float)tq && lmin - plen <= tq && plen - lmax <= tq;
-        tests += qok ? 1 : 0;
-        const float R = cv.R[c];
-        if (dev::ballot(pass) != 0ull && R >= 0.f) {
-            const int32_t s0 = cv.off[c];
-            pass = ball_pass<W, TAB>(pass, cv.chars, s0, cv.off[c + 1] - s0, plen, tq + (int)R, s_code[wave], s_lut,
-                                     s_tab, gtab, lane, wt);
-        } else {
-            pass = false;
+        for (int i = 0; i < MP; i++) {
+            lo[i] = b[i];
+            hi[i] = b[MP + i];
         }
-        if (pass) {
-            const int slot = atomicAdd(&qcnt[p], 1);
-            if (slot < kQueryCells) qcells[(size_t)p * kQueryCells + slot] = (int32_t)c;
+        const int lmin = cv.len[2 * c], lmax = cv.len[2 * c + 1], ri = (int)R;
+#pragma unroll 8
+        for (int j = 0; j < nj; j++) {
+            const int tq = s_tq[j], pl = s_plen[j], h = s_hc[j];
+            float g = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(lo[i] - s_qp[j][i], s_qp[j][i] - hi[i]));
+            bool pass = g <= (float)tq && lmin - pl <= tq && pl - lmax <= tq;
+            if (h >= 0) pass = pass && abs((int)cv.dist[(size_t)h * cv.n + c] - s_hd[j]) <= tq + ri;
+            m |= pass ? (1ull << j) : 0ull;
+        }
+        if (m) {
+            const int32_t s0 = cv.off[c];
+            const int tl = cv.off[c + 1] - s0;
+            const uint8_t *text = cv.chars + s0;
+            while (m) {
+                const int j = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                const int pl = s_plen[j], cut = s_tq[j] + ri, wq = (pl + 63) >> 6;
+                int d;
+                if (TAB) {
+                    const TilePeq t{s_tab, W, j};
+                    if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(t, pl, text, tl, cut, s_lut);
+                    else if (W >= 3 && wq <= 2) d = dev::myers_distance<2>(t, pl, text, tl, cut, s_lut);
+                    else if (W >= 4 && wq <= 3) d = dev::myers_distance<3>(t, pl, text, tl, cut, s_lut);
+                    else d = dev::myers_distance<W>(t, pl, text, tl, cut, s_lut);
+                } else {
+                    const GlobalPeq t{qv.peq + (size_t)s_q[j] * o.rows * 4};
+                    if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(t, pl, text, tl, cut, s_lut);
+                    else if (W >= 3 && wq <= 2) d = dev::myers_distance<2>(t, pl, text, tl, cut, s_lut);
+                    else if (W >= 4 && wq <= 3) d = dev::myers_distance<3>(t, pl, text, tl, cut, s_lut);
+                    else d = dev::myers_distance<W>(t, pl, text, tl, cut, s_lut);
+                }
+                if (d <= cut) {
+                    const int64_t p = (int64_t)tile * 64 + j;
+                    const int slot = atomicAdd(&qcnt[p], 1);
+                    if (slot < kQueryCells) qcells[(size_t)p * kQueryCells + slot] = (int32_t)c;
+                }
+            }
         }
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) tests += __shfl_xor(tests, o2, 64);
-    if (lane == 0 && tests) count_add(counters, CNT_NODE_TESTS, (unsigned long long)tests);
+    if (dev::lane_id() == 0 && tests) count_add(counters, CNT_NODE_TESTS, (unsigned long long)tests);
 }
 
 // Leaves are reached from the cells that passed, query by query: one wave per
@@ -314,6 +313,84 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
 
 // home[q] = the first cell (in chain order) on query q's list, n_cells when
 // the list is empty, 0 when it overflowed.  One thread per query.
+// Pivot centre per query: one wave per query.  Lanes stride over the query's
+// q-grams and add one vote to every centre listed in the q-gram's bucket
+// (LDS counters, one row of n_cells per wave); the four centres with the most
+// votes (ties: lower rank) get an exact distance, one lane each, and the
+// nearest of them is the pivot.  No vote at all (a query shorter than a
+// q-gram, or sharing none): no pivot.
+__global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, int64_t nq, CellView cv,
+                                                    int32_t *__restrict__ piv, int32_t *__restrict__ pivd)
+{
+    extern __shared__ uint32_t s_votes[];
+    const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    if (q >= nq) return;   // no block-wide barrier below
+    const int nc = (int)cv.n;
+    uint32_t *votes = s_votes + (size_t)wave * nc;
+    for (int i = lane; i < nc; i += 64) votes[i] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    const int64_t s0 = qv.off[q];
+    const int plen = (int)(qv.off[q + 1] - s0);
+    const uint8_t *str = qv.chars + s0;
+    for (int p = lane; p + kQgram <= plen; p += 64) {
+        const uint32_t b = qgram_bucket(str + p);
+        const int e1 = cv.qg_off[b + 1];
+        for (int e = cv.qg_off[b]; e < e1; e++) atomicAdd(&votes[cv.qg_cell[e]], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int mine = -1;   // lane t < 4 takes the t-th best centre
+    for (int t = 0; t < 4; t++) {
+        uint64_t best = 0ull;   // (votes << 32) | ~rank: larger is better
+        for (int i = lane; i < nc; i += 64) {
+            const uint64_t key = ((uint64_t)votes[i] << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
+            best = key > best ? key : best;
+        }
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+            const uint64_t other = __shfl_xor(best, o2, 64);
+            best = other > best ? other : best;
+        }
+        if ((best >> 32) == 0ull) break;   // wave-uniform
+        const int r = (int)(0xffffffffu - (uint32_t)best);
+        if (lane == t) mine = r;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) votes[r] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    uint64_t key = ~0ull;   // (distance << 32) | rank: smaller is better
+    if (mine >= 0) {
+        const int32_t c0 = cv.off[mine];
+        const int d = dev::myers_any(qv.peq + (size_t)q * o.rows * 4, plen, cv.chars + c0, cv.off[mine + 1] - c0,
+                                     1 << 30, o.lut);
+        key = ((uint64_t)(uint32_t)d << 32) | (uint32_t)mine;
+    }
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+        const uint64_t other = __shfl_xor(key, o2, 64);
+        key = other < key ? other : key;
+    }
+    if (lane == 0) {
+        piv[q] = key == ~0ull ? -1 : (int32_t)(uint32_t)key;
+        pivd[q] = key == ~0ull ? 0 : (int32_t)(key >> 32);
+    }
+}
+
+void edit_pivot(const EditView &o, const QueryEdit &qv, int64_t nq, const CellView &cv, int32_t *piv,
+                int32_t *pivd, hipStream_t st)
+{
+    if (nq == 0) return;
+    require(cv.n > 0 && cv.n <= 4096 && cv.dist && cv.qg_off && cv.qg_cell, "edit_pivot: no centre tables");
+    const size_t shm = (size_t)4 * cv.n * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_edit_pivot, dim3((unsigned)((nq + 3) / 4)), dim3(256), shm, st, o, qv, nq, cv, piv, pivd);
+    check_launch(__func__);
+}
+
 __global__ void k_first_cell(const int32_t *__restrict__ qcells, const int32_t *__restrict__ qcnt, int64_t n_cells,
                              int64_t nq, int32_t *__restrict__ home)
 {
@@ -338,21 +415,22 @@ void first_cell(const int32_t *qcells, const int32_t *qcnt, int64_t n_cells, int
 
 
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int max_qlen, const CellView &cv, int32_t *qcells, int32_t *qcnt,
-                    unsigned long long *counters, const int32_t *order, hipStream_t st)
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, const int32_t *piv,
+                    const int32_t *pivd, int32_t *qcells, int32_t *qcnt, unsigned long long *counters,
+                    const int32_t *order, hipStream_t st)
 {
     if (nq == 0) return;
     fill_u32(reinterpret_cast<uint32_t *>(qcnt), nq, 0u, st);
     if (cv.n == 0) return;
     const int ntiles = (int)((nq + 63) / 64);
     const int W = std::max(1, (max_qlen + 63) / 64);
-    const int64_t chunks = (cv.n + kBallChunk - 1) / kBallChunk;
+    const int64_t chunks = (cv.n + 255) / 256;
     const unsigned grid = (unsigned)(chunks * ntiles);
     const bool tab = (int64_t)o.rows * W * 64 <= kTileTabWords;
     const size_t shm = tab ? (size_t)o.rows * W * 64 * sizeof(uint64_t) : 0;
 #define CT(WW, MP, TB)                                                                                            \
     hipLaunchKernelGGL((k_edit_cell_test<WW, MP, TB>), dim3(grid), dim3(256), shm, st, o, qv, qlen, QP, T, nq,    \
-                       ntiles, cv, qcells, qcnt, counters, order)
+                       ntiles, cv, piv, pivd, qcells, qcnt, counters, order)
 #define CTM(WW, TB)                 \
     if (mpad == 8) CT(WW, 8, TB);   \
     else if (mpad == 16) CT(WW, 16, TB); \

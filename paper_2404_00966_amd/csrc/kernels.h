@@ -164,16 +164,42 @@ struct CellView {
     const float *box;          // [n][2 * mpad]: lo[0..mpad), hi[0..mpad)
     const int32_t *len;        // [n][2]: shortest and longest member
     int64_t n;
+    const uint8_t *dist;       // [n][n] centre-to-centre distances
+    const int32_t *qg_off;     // [kQgramBuckets + 1]
+    const int32_t *qg_cell;    // centres whose string holds a q-gram of each bucket
 };
+// q-gram buckets of the centre strings: a q-gram (kQgram consecutive bytes)
+// hashes to one of kQgramBuckets buckets; each bucket lists the centres
+// holding a q-gram of that bucket.  Only the choice of a query's pivot centre
+// depends on it (by vote count), never an answer.
+constexpr int kQgram = 8;
+constexpr int kQgramBits = 16;
+constexpr int kQgramBuckets = 1 << kQgramBits;
+__host__ __device__ inline uint32_t qgram_bucket(const uint8_t *s)
+{
+    uint32_t h = 0;
+    for (int u = 0; u < kQgram; u++) h = h * 0x9E3779B1u + (uint32_t)s[u] + 1u;
+    return h >> (32 - kQgramBits);
+}
+// Pivot centre of each query: among the (up to) four centres sharing the most
+// q-gram buckets with it, the nearest by exact edit distance; piv[q] = its
+// chain rank (-1: no shared bucket) and pivd[q] = d(q, centre).  With it the
+// cell test applies Lemma 1 with that centre as the pivot:
+// d(q, o) >= |d(q, h) - d(h, c)| - R_c for every member o of cell c.
+void edit_pivot(const EditView &o, const QueryEdit &qv, int64_t nq, const CellView &cv, int32_t *piv,
+                int32_t *pivd, hipStream_t st);
 // Passing cells kept per query; a query with more takes every cell.
 constexpr int kQueryCells = 64;
-// Cell test (Lemma 1 with each centre and with the global pivots) for nq
-// queries in tiles of 64, position p holding query order[p] (order may be
-// null: the identity): qcnt[p] = number of passing cells, qcells[p][0..63]
-// the first kQueryCells of them (in no particular order).
+// Cell test (Lemma 1 with each centre, with the query's pivot centre and
+// with the global pivots) for nq queries in tiles of 64, position p holding
+// query order[p] (order may be null: the identity); piv/pivd are indexed by
+// query (piv may be null: no pivot centre).  qcnt[p] = number of passing
+// cells, qcells[p][0..63] the first kQueryCells of them (in no particular
+// order).
 void edit_cell_test(const EditView &o, const QueryEdit &qv, const int32_t *qlen, const float *QP, int mpad,
-                    const float *T, int64_t nq, int max_qlen, const CellView &cv, int32_t *qcells, int32_t *qcnt,
-                    unsigned long long *counters, const int32_t *order, hipStream_t st);
+                    const float *T, int64_t nq, int max_qlen, const CellView &cv, const int32_t *piv,
+                    const int32_t *pivd, int32_t *qcells, int32_t *qcnt, unsigned long long *counters,
+                    const int32_t *order, hipStream_t st);
 // First (chain-order) passing cell of each position: n_cells when none
 // passed, 0 when the list overflowed.
 void first_cell(const int32_t *qcells, const int32_t *qcnt, int64_t n_cells, int64_t nq, int32_t *home,
