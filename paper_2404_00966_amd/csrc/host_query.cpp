@@ -32,7 +32,7 @@ enum Ws {
     W_MASK, W_ITEMS, W_SMALL, W_CANDS, W_GROUPED, W_QCOUNT, W_QOFF64, W_OUTKEYS, W_OUTCNT, W_RESOFF, W_SCRATCH,
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
-    W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV,
+    W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV, W_POSOF, W_HOMEC, W_PLEN, W_POFF, W_PCHARS,
     W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
@@ -60,9 +60,12 @@ constexpr int kSmallWords = 16;
 // Pinned host staging of one search call: device-to-host the permutation
 // (nq int32), the small counters, the group's segment offsets, counts and
 // the statistics counters; host-to-device the workgroup-mode query list, the
-// scratch offsets and the result offsets.
+// scratch offsets and the result offsets, and (edit distance) the query
+// offsets, lengths, length order and positions in it.  Regions are disjoint,
+// so no host write waits for an earlier copy.
 struct PinLayout {
-    size_t perm = 0, small = 0, qoff = 0, counts = 0, counters = 0, blk = 0, big = 0, offs = 0, bytes = 0;
+    size_t perm = 0, small = 0, qoff = 0, counts = 0, counters = 0, blk = 0, big = 0, offs = 0;
+    size_t in_off = 0, in_len = 0, in_ord = 0, in_pos = 0, bytes = 0;
     explicit PinLayout(int64_t nq)
     {
         auto up = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -73,7 +76,11 @@ struct PinLayout {
         blk = up(counters + (size_t)k::kCounterWords * sizeof(uint64_t));   // host-to-device: workgroup-mode queries
         big = up(blk + (size_t)(nq + 1) * sizeof(int32_t));    // scratch offsets
         offs = up(big + (size_t)(nq + 1) * sizeof(int64_t));   // result offsets
-        bytes = up(offs + (size_t)(nq + 1) * sizeof(int64_t));
+        in_off = up(offs + (size_t)(nq + 1) * sizeof(int64_t));
+        in_len = up(in_off + (size_t)(nq + 1) * sizeof(int64_t));
+        in_ord = up(in_len + (size_t)nq * sizeof(int32_t));
+        in_pos = up(in_ord + (size_t)nq * sizeof(int32_t));
+        bytes = up(in_pos + (size_t)nq * sizeof(int32_t));
     }
 };
 
@@ -504,6 +511,9 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     if (cx->timing && !cx->ev[0])
         for (int i = 0; i < 9; i++) GTS_HIP(hipEventCreate(&cx->ev[i]));
     rec(cx, 0);
+    const PinLayout pl(nq);
+    uint8_t *pin = static_cast<uint8_t *>(cx->pinned(pl.bytes));
+    GTS_CHECK(pin != nullptr, GTS_ENOMEM, "pinned host staging allocation failed");
 
     // ---- queries into the workspace -----------------------------------------------
     // query rows padded by one extra tile: a group that starts inside a tile
@@ -525,7 +535,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     }
     const hipMemcpyKind in_kind = Q->location == GTS_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     k::QueryL2 qv{};
-    std::vector<int32_t> hqlen;   // query string lengths (EDIT), caller order
+    const int32_t *hqlen = nullptr;   // query string lengths (EDIT), caller order, pinned
     k::QueryEdit qe{};
     if (nq > 0 && l2) {
         GTS_CHECK(Q->dim == d.dim, GTS_EINVAL, "query dimension differs from the index");
@@ -544,12 +554,12 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         qv = k::QueryL2{Q32, Q16, qn, qerr};
     } else if (nq > 0) {
         GTS_CHECK(Q->offsets != nullptr, GTS_EINVAL, "null query offsets");
-        std::vector<int64_t> hoff(nq + 1);
-        GTS_HIP(hipMemcpy(hoff.data(), Q->offsets, (nq + 1) * sizeof(int64_t),
+        int64_t *hoff = reinterpret_cast<int64_t *>(pin + pl.in_off);
+        GTS_HIP(hipMemcpy(hoff, Q->offsets, (nq + 1) * sizeof(int64_t),
                           Q->location == GTS_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
         GTS_CHECK(hoff[0] == 0, GTS_EINVAL, "query offsets[0] must be 0");
-        std::vector<int32_t> &qlen = hqlen;
-        qlen.resize(nq);
+        int32_t *qlen = reinterpret_cast<int32_t *>(pin + pl.in_len);
+        hqlen = qlen;
         for (int64_t q = 0; q < nq; q++) {
             const int64_t len = hoff[q + 1] - hoff[q];
             GTS_CHECK(len >= 0 && len <= d.max_strlen, GTS_EINVAL, "query string length out of range");
@@ -562,15 +572,14 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             GTS_HIP(hipMemcpyAsync(qc, Q->chars, hoff[nq], in_kind, st));
         }
         int64_t *qo = wsp<int64_t>(cx, W_QOFF, nqpad + 1);
-        GTS_HIP(hipMemcpyAsync(qo, hoff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(qo, hoff, (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
         int32_t *ql = wsp<int32_t>(cx, W_QLEN, nqpad);
-        GTS_HIP(hipMemcpyAsync(ql, qlen.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(ql, qlen, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         uint64_t *peq = wsp<uint64_t>(cx, W_PEQ, (size_t)nqpad * idx->arows * 4);
         k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, peq, st);
         k::dist_edit_pivots_f32(qc, qo, nq, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, mpad,
                                 cx->ws[W_QP].as<float>(), 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
         qe = k::QueryEdit{qc, qo, peq};
-        GTS_HIP(hipStreamSynchronize(st));
     }
     // ---- home leaves and query order ----------------------------------------------
     // Queries are grouped into tiles by their home (nearest leaf pivot for L2,
@@ -582,8 +591,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                    d.tree.n_leaves, d.tree.leaf0, d.tree.fanout, d.tree.levels, mpad};
     k::EditView oe{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), d.n, idx->lut.as<uint8_t>(), idx->arows};
     int32_t *near = nullptr;
-    std::vector<int32_t> perm;   // position i of the batch holds caller query perm[i]
-    bool permuted = false;
+    bool permuted = false;   // position i of the batch holds caller query perm[i] (W_PERM)
     // Edit distance (batched): the kNN bound, the thresholds and the cell test
     // run in the caller's order; a query's home is its first passing cell, and
     // the cell masks follow the queries into the grouped order.
@@ -593,17 +601,25 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                    d.cell_len.as<int32_t>(), d.n_centres, d.cell_dist.as<uint8_t>(), d.qg_off.as<int32_t>(),
                    d.qg_cell.as<int32_t>()};
     int32_t *qcells0 = nullptr, *qcnt0 = nullptr;   // passing cells per position of the length order
-    // the cell test runs on the queries in length order, so that the tiles'
-    // patterns have similar word counts; pos_of[q] = position of query q
-    std::vector<int32_t> order, pos_of;
+    // the cell test runs on the queries in length order (a stable counting
+    // sort), so that the tiles' patterns have similar word counts; dpos[q] =
+    // position of query q in that order
+    int32_t *dpos = nullptr;
     if (edit_cells) {
-        order.resize(nq);
-        pos_of.resize(nq);
-        for (int64_t q = 0; q < nq; q++) order[q] = (int32_t)q;
-        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hqlen[x] < hqlen[y]; });
-        for (int64_t p = 0; p < nq; p++) pos_of[order[p]] = (int32_t)p;
+        int32_t *order = reinterpret_cast<int32_t *>(pin + pl.in_ord);
+        int32_t *pos_of = reinterpret_cast<int32_t *>(pin + pl.in_pos);
+        std::vector<int64_t> at(kMaxStrlen + 2, 0);
+        for (int64_t q = 0; q < nq; q++) at[hqlen[q] + 1]++;
+        for (int l = 0; l <= kMaxStrlen; l++) at[l + 1] += at[l];
+        for (int64_t q = 0; q < nq; q++) {
+            const int64_t p = at[hqlen[q]]++;
+            order[p] = (int32_t)q;
+            pos_of[q] = (int32_t)p;
+        }
         int32_t *dorder = wsp<int32_t>(cx, W_ORDER, nq);
-        GTS_HIP(hipMemcpyAsync(dorder, order.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        GTS_HIP(hipMemcpyAsync(dorder, order, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        dpos = wsp<int32_t>(cx, W_POSOF, nq);
+        GTS_HIP(hipMemcpyAsync(dpos, pos_of, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         if (b.any_knn)
             k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
@@ -626,24 +642,21 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
         const size_t tb = k::home_sort_bytes(nq, d.lpad);
         int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
-        k::home_sort(near, nq, d.lpad, reinterpret_cast<uint32_t *>(home), wsp<uint32_t>(cx, W_HOME2, nq), dperm,
+        k::home_sort(near, k::kNearLeaves, nq, d.lpad, reinterpret_cast<uint32_t *>(home),
+                     wsp<uint32_t>(cx, W_HOME2, nq), dperm,
                      wsp<uint8_t>(cx, W_SORT_TMP, tb), tb, st);
         permuted = true;
     } else if (nq > 1 && edit_cells) {
-        std::vector<int32_t> hh(nq);
+        // home = first passing cell in chain order (per position of the length
+        // order, then per query); the batch order is a stable device sort by it
         k::first_cell(qcells0, qcnt0, d.n_centres, nq, home, st);
-        std::vector<int32_t> hp(nq);
-        GTS_HIP(hipMemcpyAsync(hp.data(), home, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipStreamSynchronize(st));
-        for (int64_t p = 0; p < nq; p++) hh[order[p]] = hp[p];
-        perm.resize(nq);
-        for (int64_t q = 0; q < nq; q++) perm[q] = (int32_t)q;
-        std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hh[x] < hh[y]; });
-        for (int64_t q = 0; q < nq && !permuted; q++) permuted = perm[q] != q;
-        if (permuted) {
-            int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
-            GTS_HIP(hipMemcpyAsync(dperm, perm.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        }
+        int32_t *homec = wsp<int32_t>(cx, W_HOMEC, nq);
+        k::gather_i32(home, dpos, nq, 1, homec, st);
+        const size_t tb = k::home_sort_bytes(nq, (int64_t)d.n_centres + 1);
+        int32_t *dperm = wsp<int32_t>(cx, W_PERM, nq);
+        k::home_sort(homec, 1, nq, (int64_t)d.n_centres + 1, reinterpret_cast<uint32_t *>(home),
+                     wsp<uint32_t>(cx, W_HOME2, nq), dperm, wsp<uint8_t>(cx, W_SORT_TMP, tb), tb, st);
+        permuted = true;
     }
     if (permuted) {
         // everything per query follows the permutation on the device: one
@@ -672,41 +685,35 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             k::rows_bf16(qv.Q32, nq, nqpad, d.dim, d.dp, d.ksteps, const_cast<uint16_t *>(qv.Q16t),
                          const_cast<float *>(qv.qn), const_cast<float *>(qv.qe), 0.f, st);
         } else {
-            // strings in the new order, then their match tables and lengths
-            std::vector<int64_t> hoff(nq + 1);
-            GTS_HIP(hipMemcpyAsync(hoff.data(), qe.off, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-            GTS_HIP(hipStreamSynchronize(st));
-            std::vector<int64_t> noff(nq + 1, 0);
-            std::vector<int32_t> nlen(nq);
-            for (int64_t i = 0; i < nq; i++) {
-                nlen[i] = (int32_t)(hoff[perm[i] + 1] - hoff[perm[i]]);
-                noff[i + 1] = noff[i] + nlen[i];
-            }
-            uint8_t *nc = wsp<uint8_t>(cx, W_TMP2, std::max<int64_t>(noff[nq], 1));
-            int64_t *no = reinterpret_cast<int64_t *>(wsp<float>(cx, W_TMP, (size_t)2 * (nq + 1)));
-            GTS_HIP(hipMemcpyAsync(no, noff.data(), (nq + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-            k::gather_strings(qe.chars, qe.off, dperm, nq, no, nc, st);
-            uint8_t *qc = const_cast<uint8_t *>(qe.chars);
-            int64_t *qo = const_cast<int64_t *>(qe.off);
-            GTS_HIP(hipMemcpyAsync(qc, nc, std::max<int64_t>(noff[nq], 1), hipMemcpyDeviceToDevice, st));
-            GTS_HIP(hipMemcpyAsync(qo, no, (nq + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-            GTS_HIP(hipMemcpyAsync(cx->ws[W_QLEN].as<int32_t>(), nlen.data(), nq * sizeof(int32_t),
-                                   hipMemcpyHostToDevice, st));
-            k::build_peq(qc, qo, nq, idx->lut.as<uint8_t>(), idx->arows, const_cast<uint64_t *>(qe.peq), st);
-            GTS_HIP(hipStreamSynchronize(st));
+            // strings in the new order: lengths gathered, offsets scanned,
+            // bytes gathered; then their match tables (all on the device)
+            const int64_t total = reinterpret_cast<const int64_t *>(pin + pl.in_off)[nq];
+            int32_t *nlen = wsp<int32_t>(cx, W_PLEN, nqpad);
+            int64_t *noff = wsp<int64_t>(cx, W_POFF, nqpad + 1);
+            uint8_t *nchars = wsp<uint8_t>(cx, W_PCHARS, std::max<int64_t>(total, 1));
+            k::gather_i32(cx->ws[W_QLEN].as<int32_t>(), dperm, nq, 1, nlen, st);
+            k::scan_u32(reinterpret_cast<const uint32_t *>(nlen), nq, noff, st);
+            k::gather_strings(qe.chars, qe.off, dperm, nq, noff, nchars, st);
+            k::build_peq(nchars, noff, nq, idx->lut.as<uint8_t>(), idx->arows, const_cast<uint64_t *>(qe.peq), st);
+            std::swap(cx->ws[W_QLEN], cx->ws[W_PLEN]);
+            std::swap(cx->ws[W_QOFF], cx->ws[W_POFF]);
+            std::swap(cx->ws[W_QCHARS], cx->ws[W_PCHARS]);
+            qe.chars = nchars;
+            qe.off = noff;
         }
     }
     if (edit_cells) {
         // cell lists from length order to the batch order: batch position i
-        // holds caller query perm[i], tested at position pos_of[perm[i]]
-        std::vector<int32_t> comp(nq);
-        for (int64_t i = 0; i < nq; i++) comp[i] = pos_of[permuted ? perm[i] : i];
-        int32_t *dcomp = wsp<int32_t>(cx, W_ORDER, nq);
-        GTS_HIP(hipMemcpyAsync(dcomp, comp.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        // holds caller query perm[i], tested at position dpos[perm[i]]
+        const int32_t *dcomp = dpos;
+        if (permuted) {
+            int32_t *c2 = wsp<int32_t>(cx, W_ORDER, nq);
+            k::gather_i32(dpos, cx->ws[W_PERM].as<int32_t>(), nq, 1, c2, st);
+            dcomp = c2;
+        }
         k::gather_i32(qcells0, dcomp, nq, k::kQueryCells, wsp<int32_t>(cx, W_QCELLS, (size_t)nq * k::kQueryCells),
                       st);
         k::gather_i32(qcnt0, dcomp, nq, 1, wsp<int32_t>(cx, W_QCNT, nq), st);
-        GTS_HIP(hipStreamSynchronize(st));   // comp is a host temporary
     }
     rec(cx, 1);
 
@@ -752,10 +759,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     std::vector<GroupOut> groups;
     std::vector<std::pair<int64_t, int64_t>> todo;  // (q0, ng), processed front to back
     if (nq > 0) todo.push_back({0, nq});
-    const PinLayout pl(nq);
-    uint8_t *pin = static_cast<uint8_t *>(cx->pinned(pl.bytes));
-    GTS_CHECK(pin != nullptr, GTS_ENOMEM, "pinned host staging allocation failed");
-    if (permuted && perm.empty())   // the order was made on the device: its copy lands by the next sync
+    if (permuted)   // the order was made on the device: its copy lands by the next sync
         GTS_HIP(hipMemcpyAsync(pin + pl.perm, cx->ws[W_PERM].p, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     while (!todo.empty()) {
         auto [q0, ng] = todo.front();
@@ -810,8 +814,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         else out->dist_i32 = static_cast<int32_t *>(priv->dist);
     } else {
     // position i of the batch holds caller query pm[i]
-    const int32_t *pm = !permuted ? nullptr
-                        : perm.empty() ? reinterpret_cast<const int32_t *>(pin + pl.perm) : perm.data();
+    const int32_t *pm = !permuted ? nullptr : reinterpret_cast<const int32_t *>(pin + pl.perm);
     int64_t total = 0;
     for (auto &g : groups) total += g.total;
     int64_t *offs = reinterpret_cast<int64_t *>(pin + pl.offs);   // caller order, built in place

@@ -1,7 +1,7 @@
-// Query order by home leaf on the device: a stable radix sort of the home
-// keys (rocPRIM) carrying the query index, so the permutation is the same on
-// every run and no host round trip sits between the nearest-leaf search and
-// the first kernel that reads the queries in the new order.
+// Query order by home (leaf or cell) on the device: a stable radix sort of
+// the home keys (rocPRIM) carrying the query index, so the permutation is the
+// same on every run and no host round trip sits between the search for the
+// homes and the first kernel that reads the queries in the new order.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 
@@ -10,10 +10,10 @@
 namespace gts {
 namespace k {
 
-__global__ void k_home_keys(const int32_t *__restrict__ near, int64_t nq, uint32_t *__restrict__ key)
+__global__ void k_home_keys(const int32_t *__restrict__ home, int stride, int64_t nq, uint32_t *__restrict__ key)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nq) key[q] = (uint32_t)near[q * kNearLeaves];
+    if (q < nq) key[q] = (uint32_t)home[q * stride];
 }
 
 static int key_bits(int64_t n_keys)
@@ -35,12 +35,12 @@ size_t home_sort_bytes(int64_t nq, int64_t n_keys)
     return bytes;
 }
 
-void home_sort(const int32_t *near, int64_t nq, int64_t n_keys, uint32_t *keys, uint32_t *keys_sorted,
+void home_sort(const int32_t *home, int stride, int64_t nq, int64_t n_keys, uint32_t *keys, uint32_t *keys_sorted,
                int32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t st)
 {
     if (nq == 0) return;
-    require(n_keys > 0 && n_keys < ((int64_t)1 << 31), "home_sort: key range out of bounds");
-    hipLaunchKernelGGL(k_home_keys, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, near, nq, keys);
+    require(n_keys > 0 && n_keys < ((int64_t)1 << 31) && stride >= 1, "home_sort: key range out of bounds");
+    hipLaunchKernelGGL(k_home_keys, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, home, stride, nq, keys);
     check_launch(__func__);
     size_t bytes = tmp_bytes;
     const hipError_t e = rocprim::radix_sort_pairs(tmp, bytes, keys, keys_sorted,

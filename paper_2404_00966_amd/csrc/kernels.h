@@ -264,10 +264,11 @@ void leaf_near(const uint16_t *PL16t, const float *pln, int64_t lpad, int ksteps
 void permute_queries(const int32_t *perm, int64_t nq, const float *base_s, float *base_d, const int32_t *kq_s,
                      int32_t *kq_d, const float *qp_s, float *qp_d, int mpad, const float *q32_s, float *q32_d,
                      int dp, const int32_t *near_s, int32_t *near_d, int nnear, hipStream_t st);
-// Stable sort of the queries by home leaf (near[q * kNearLeaves], keys in
-// [0, n_keys)): perm[i] = query at position i (k_sort.hip).
+// Stable sort of the queries by home (home[q * stride], keys in [0, n_keys)):
+// perm[i] = query at position i (k_sort.hip).  keys may alias home when
+// stride is 1.
 size_t home_sort_bytes(int64_t nq, int64_t n_keys);
-void home_sort(const int32_t *near, int64_t nq, int64_t n_keys, uint32_t *keys, uint32_t *keys_sorted,
+void home_sort(const int32_t *home, int stride, int64_t nq, int64_t n_keys, uint32_t *keys, uint32_t *keys_sorted,
                int32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t st);
 void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
                int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
