@@ -223,10 +223,12 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
 }
 
 // Leaves are reached from the cells that passed, query by query: one wave per
-// query (its match table in LDS), lanes over the leaves of each cell on the
-// query's list, each lane scanning its leaf pivot as the text with the
-// cutoff T_q + R_L.  A leaf that spans several cells is tested from the first
-// of them on the list.  A query whose list overflowed takes every cell.  A
+// query (its match table in LDS).  The (cell, leaf) pairs of the query's list
+// are numbered across the cells (a wave prefix sum of their leaf counts in
+// LDS) and dealt to the lanes 64 at a time, each lane scanning its leaf pivot
+// as the text with the cutoff T_q + R_L.  A leaf that spans several cells is
+// tested from the first of them on the list.  A query whose list overflowed
+// takes every leaf once.  A
 // passing (query, leaf) pair sets the query's bit in leaf_mask[leaf][tile];
 // the first bit set in a word appends (leaf, tile) to the item list
 // (leaf_mask starts zeroed).
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
                                                          const float *__restrict__ leafR,
                                                          const int32_t *__restrict__ leaf_cell,
                                                          const int32_t *__restrict__ cell_leaf, int64_t n_cells,
-                                                         const int32_t *__restrict__ qcells,
+                                                         int64_t n_leaves, const int32_t *__restrict__ qcells,
                                                          const int32_t *__restrict__ qcnt, int64_t nq, int ntiles,
                                                          unsigned long long *__restrict__ leaf_mask,
                                                          int32_t *__restrict__ items, uint32_t *__restrict__ item_count,
@@ -246,6 +248,7 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
     extern __shared__ uint64_t s_tabs[];   // 4 x rows x 4 words
     __shared__ uint8_t s_lut[256];
     __shared__ int32_t s_cells[4][kQueryCells];
+    __shared__ int32_t s_pre[4][kQueryCells + 1];   // leaf pairs before each listed cell
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     const bool qok = q < nq;
@@ -259,27 +262,53 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
     }
     __syncthreads();
     if (!qok || cnt == 0) return;
-    const bool all = cnt > kQueryCells;   // the list overflowed: every cell
-    const int ncell = all ? (int)n_cells : cnt;
+    const bool all = cnt > kQueryCells;   // the list overflowed: every leaf
     const int plen = qlen[q];
     const int wq = (plen + 63) >> 6;
     const int tq = (int)T[q];
     const int tile = (int)(q >> 6);
     const unsigned long long bit = 1ull << (q & 63);
+    int total;
+    if (all) {
+        total = (int)n_leaves;
+    } else {
+        int nl = 0;
+        if (lane < cnt) {
+            const int c = s_cells[wave][lane];
+            nl = max(0, cell_leaf[2 * c + 1] - cell_leaf[2 * c] + 1);
+        }
+        const int ex = dev::wave_excl_scan(nl, &total);
+        if (lane < cnt) s_pre[wave][lane] = ex;
+        if (lane == 0) s_pre[wave][cnt] = total;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     auto listed = [&](int e) {
-        if (all) return true;
         bool f = false;
         for (int i = 0; i < cnt; i++) f = f || s_cells[wave][i] == e;
         return f;
     };
-    for (int ci = 0; ci < ncell; ci++) {
-        const int c = all ? ci : s_cells[wave][ci];
-        const int l_lo = cell_leaf[2 * c], l_hi = cell_leaf[2 * c + 1];
-        for (int l0 = l_lo; l0 <= l_hi; l0 += 64) {
-            const int leaf = l0 + lane;
-            bool ok = leaf <= l_hi;
-            if (ok)
+    for (int i0 = 0; i0 < total; i0 += 64) {
+        const int i = i0 + lane;
+        bool ok = i < total;
+        int leaf = 0;
+        if (ok) {
+            if (all) {
+                leaf = i;
+            } else {
+                int lo = 0, hi = cnt - 1;   // the listed cell whose pair range holds i
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[wave][mid] <= i) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int c = s_cells[wave][lo];
+                leaf = cell_leaf[2 * c] + (i - s_pre[wave][lo]);
                 for (int e = leaf_cell[2 * leaf]; e < c; e++) ok = ok && !listed(e);
+            }
+        }
+        {
             const float R = ok ? leafR[leaf] : -1.f;
             ok = ok && R >= 0.f;
             if (ok) {
@@ -311,8 +340,6 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
     }
 }
 
-// home[q] = the first cell (in chain order) on query q's list, n_cells when
-// the list is empty, 0 when it overflowed.  One thread per query.
 // Pivot centre per query: one wave per query.  Lanes stride over the query's
 // q-grams and add one vote to every centre listed in the q-gram's bucket
 // (LDS counters, one row of n_cells per wave); the four centres with the most
@@ -391,6 +418,8 @@ void edit_pivot(const EditView &o, const QueryEdit &qv, int64_t nq, const CellVi
     check_launch(__func__);
 }
 
+// home[q] = the first cell (in chain order) on query q's list, n_cells when
+// the list is empty, 0 when it overflowed.  One thread per query.
 __global__ void k_first_cell(const int32_t *__restrict__ qcells, const int32_t *__restrict__ qcnt, int64_t n_cells,
                              int64_t nq, int32_t *__restrict__ home)
 {
@@ -457,13 +486,15 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
 {
     fill_u32(reinterpret_cast<uint32_t *>(leaf_mask), n_leaves * ntiles * 2, 0u, st);
     if (nq == 0 || n_cells == 0) return;
+    require(n_leaves < ((int64_t)1 << 31), "edit_leaf_ball: too many leaves");
     const int W = std::max(1, (max_qlen + 63) / 64);
     const unsigned grid = (unsigned)((nq + 3) / 4);
     const size_t shm = (size_t)4 * o.rows * 4 * sizeof(uint64_t);
     auto *lm = reinterpret_cast<unsigned long long *>(leaf_mask);
 #define EQ(WW)                                                                                                 \
     hipLaunchKernelGGL(k_edit_leaf_query<WW>, dim3(grid), dim3(256), shm, st, o, qv, qlen, T, leaf_first, leafR, \
-                       leaf_cell, cell_leaf, n_cells, qcells, qcnt, nq, ntiles, lm, items, item_count, item_cap)
+                       leaf_cell, cell_leaf, n_cells, n_leaves, qcells, qcnt, nq, ntiles, lm, items, item_count,  \
+                       item_cap)
     switch (W) {
     case 1: EQ(1); break;
     case 2: EQ(2); break;
