@@ -159,9 +159,81 @@ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_
     return score;
 }
 
+// Banded form for cutoffs k <= 63 (one 64-bit word whatever the pattern
+// length).  An alignment of cost <= k only visits diagonals j - i in [lo, hi]
+// with |j - i| + |j - i - (n - m)| <= k, at most k + 1 of them, so a window
+// of 64 consecutive rows that moves down one row per column (top row r_j =
+// max(1, j - hi)) holds every cell such an alignment visits.  Cells outside
+// the window enter as upper bounds (vertical delta +1 below it, horizontal
+// delta +1 above it, no carry from above), so every computed value is at
+// least the true one and equals it for a cell whose optimal alignment stays
+// in the band: the result is exact when it is <= k and above k otherwise.
+// The value of the window's top cell is carried from column to column; the
+// early exit reads the cell on the last cell's diagonal as in
+// myers_distance.  nw = words per code held by peq (bits past the pattern
+// are zero).
+template <class PeqPtr, class LutPtr>
+__device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen, int cutoff,
+                                            LutPtr lut)
+{
+    if (plen == 0) return tlen;
+    const int delta = tlen - plen;
+    const int ad = delta < 0 ? -delta : delta;
+    if (ad > cutoff) return cutoff + 1;
+    const int hi = (delta > 0 ? delta : 0) + ((cutoff - ad) >> 1);   // top diagonal of the band
+    const int tstar = hi - delta;   // window bit of the last cell's diagonal once the window moves
+    uint64_t VP = ~0ull, VN = 0ull;
+    int top = 1;   // D[r_j][j]; before the first column D[1][0] = 1
+    auto column = [&](int j, int c) {   // j: 1-based column
+        const bool shift = j > hi + 1;
+        if (shift) {
+            VP = (VP >> 1) | (1ull << 63);
+            VN >>= 1;
+        }
+        const int s0 = shift ? j - hi - 1 : 0;   // 0-based pattern index of the window's top row
+        const int w0 = s0 >> 6, sh = s0 & 63;
+        const uint64_t a = w0 < nw ? peq[c * 4 + w0] : 0ull;
+        const uint64_t b = w0 + 1 < nw ? peq[c * 4 + w0 + 1] : 0ull;
+        const uint64_t Eq = sh ? ((a >> sh) | (b << (64 - sh))) : a;
+        const uint64_t Xv = Eq | VN;
+        const uint64_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
+        uint64_t HP = VN | ~(Xh | VP);
+        uint64_t HN = VP & Xh;
+        HP = (HP << 1) | 1ull;
+        HN <<= 1;
+        VP = HN | ~(Xv | HP);
+        VN = HP & Xv;
+        const int vd0 = (int)(VP & 1ull) - (int)(VN & 1ull);
+        top = shift ? top + 1 + vd0 : j + vd0;
+    };
+    // D[r_j + t][j] - D[r_j][j] for t in 1..63
+    auto below = [&](int t) {
+        const uint64_t m = (2ull << t) - 2ull;
+        return __popcll(VP & m) - __popcll(VN & m);
+    };
+    constexpr int kChunk = 8;
+    int j = 0;
+    for (; j + kChunk <= tlen; j += kChunk) {
+        int cs[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; u++) cs[u] = lut[text[j + u]];
+#pragma unroll
+        for (int u = 0; u < kChunk; u++) column(j + u + 1, cs[u]);
+        const int jj = j + kChunk;
+        const int t = jj > hi + 1 ? tstar : jj - delta - 1;   // the last cell's diagonal in the window
+        if (t >= 0 && top + (t > 0 ? below(t) : 0) > cutoff) return cutoff + 1;
+    }
+    for (; j < tlen; j++) column(j + 1, lut[text[j]]);
+    const int rn = tlen > hi + 1 ? tlen - hi : 1;
+    const int tm = plen - rn;
+    const int d = top + (tm > 0 ? below(tm) : 0);
+    return d <= cutoff ? d : cutoff + 1;
+}
+
 template <class PeqPtr, class LutPtr>
 __device__ __forceinline__ int myers_any(PeqPtr peq, int plen, const uint8_t *text, int tlen, int cutoff, LutPtr lut)
 {
+    if (cutoff <= 63) return myers_banded(peq, 4, plen, text, tlen, cutoff, lut);
     if (plen <= 64) return myers_distance<1>(peq, plen, text, tlen, cutoff, lut);
     if (plen <= 128) return myers_distance<2>(peq, plen, text, tlen, cutoff, lut);
     if (plen <= 192) return myers_distance<3>(peq, plen, text, tlen, cutoff, lut);

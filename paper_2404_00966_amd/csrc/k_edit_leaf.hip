@@ -197,7 +197,11 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
                 m &= m - 1ull;
                 const int pl = s_plen[j], cut = s_tq[j] + ri, wq = (pl + 63) >> 6;
                 int d;
-                if (TAB) {
+                if (cut <= 63) {
+                    if (TAB) d = dev::myers_banded(TilePeq{s_tab, W, j}, W, pl, text, tl, cut, s_lut);
+                    else d = dev::myers_banded(GlobalPeq{qv.peq + (size_t)s_q[j] * o.rows * 4}, 4, pl, text, tl, cut,
+                                               s_lut);
+                } else if (TAB) {
                     const TilePeq t{s_tab, W, j};
                     if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(t, pl, text, tl, cut, s_lut);
                     else if (W >= 3 && wq <= 2) d = dev::myers_distance<2>(t, pl, text, tl, cut, s_lut);
@@ -319,7 +323,8 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
                     ok = false;
                 } else {
                     int d;
-                    if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(tab, plen, o.chars + s0, tl, cut, s_lut);
+                    if (cut <= 63) d = dev::myers_banded(tab, 4, plen, o.chars + s0, tl, cut, s_lut);
+                    else if (W >= 2 && wq <= 1) d = dev::myers_distance<1>(tab, plen, o.chars + s0, tl, cut, s_lut);
                     else if (W >= 3 && wq <= 2) d = dev::myers_distance<2>(tab, plen, o.chars + s0, tl, cut, s_lut);
                     else if (W >= 4 && wq <= 3) d = dev::myers_distance<3>(tab, plen, o.chars + s0, tl, cut, s_lut);
                     else d = dev::myers_distance<W>(tab, plen, o.chars + s0, tl, cut, s_lut);
