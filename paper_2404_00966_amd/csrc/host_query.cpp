@@ -218,6 +218,7 @@ struct Batch {
     bool any_knn = false;
     int mode = GTS_MODE_BATCHED;
     int max_qlen = 0;          // longest query string (EDIT)
+    float max_radius = 0.f;    // largest range radius
     int64_t ntiles_all = 0;    // query tiles of the whole batch
 };
 
@@ -416,7 +417,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         GTS_HIP(hipMemcpyAsync(dblk, blk_q, n_blk * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
     if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, st);
-    else k::verify_edit(va, oe, qe, st);
+    else k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
     // every candidate (an upper bound of the answers) unless that is large
@@ -499,6 +500,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             const float r = radius[q];
             GTS_CHECK(std::isfinite(r) && r >= 0.f, GTS_EINVAL, "radius must be finite and >= 0");
             hbase[q] = r;
+            b.max_radius = std::max(b.max_radius, r);
         }
     }
     cx->stats = gts_stats{};

@@ -513,8 +513,11 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
 // ---------------------------------------------------------------------------
 // EDIT: per query, one workgroup; the query's match table sits in LDS and
 // every lane verifies one candidate (object string as the text) with the
-// early-exit cutoff floor(base); kept keys are sorted by (d, id).
+// early-exit cutoff floor(base); kept keys are sorted by (d, id).  kBand:
+// every cutoff of the launch is at most 63, so only the banded one-word
+// recurrence is compiled in (fewer registers, more waves in flight).
 // ---------------------------------------------------------------------------
+template <bool kBand>
 __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, QueryEdit qv)
 {
     __shared__ uint64_t s_keys[kSortCap];
@@ -552,7 +555,8 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
             const int32_t s0 = o.soff[c.pos];
             const int tl = o.soff[c.pos + 1] - s0;
             verified++;
-            const int d = dev::myers_any(s_peq, plen, o.chars + s0, tl, cut, s_lut);
+            const int d = kBand ? dev::myers_banded(s_peq, 4, plen, o.chars + s0, tl, cut, s_lut)
+                                : dev::myers_any(s_peq, plen, o.chars + s0, tl, cut, s_lut);
             if (d <= cut) {
                 keep = true;
                 key = ((uint64_t)(uint32_t)d << 32) | a.ids[c.pos];
@@ -569,10 +573,11 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
 
-void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st)
+void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st)
 {
     if (a.nq == 0) return;
-    hipLaunchKernelGGL(k_verify_edit, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
+    if (band_only) hipLaunchKernelGGL(k_verify_edit<true>, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
+    else hipLaunchKernelGGL(k_verify_edit<false>, dim3((unsigned)a.nq), dim3(256), 0, st, a, o, qv);
     check_launch(__func__);
 }
 

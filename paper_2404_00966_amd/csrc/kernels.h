@@ -237,7 +237,8 @@ struct VerifyArgs {
 // blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
                hipStream_t st);
-void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, hipStream_t st);
+// band_only: every cutoff floor(base[q]) of the launch is at most 63.
+void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
 // cc[perm[i]] = out_count[i] (cc[i] without perm): answer counts in the
 // caller's query order.
