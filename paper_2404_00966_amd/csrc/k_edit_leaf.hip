@@ -347,10 +347,12 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
 
 // Pivot centre per query: one wave per query.  Lanes stride over the query's
 // q-grams and add one vote to every centre listed in the q-gram's bucket
-// (LDS counters, one row of n_cells per wave); the four centres with the most
-// votes (ties: lower rank) get an exact distance, one lane each, and the
-// nearest of them is the pivot.  No vote at all (a query shorter than a
-// q-gram, or sharing none): no pivot.
+// (16-bit LDS counters, two per word, one row of n_cells per wave; a query
+// has fewer than 2^16 q-grams); the four centres with the most votes (ties:
+// lower rank) get their distance, one lane each, exact up to 63 (banded
+// recurrence), and the nearest of them is the pivot.  No vote at all (a
+// query shorter than a q-gram, or sharing none) or no centre within 63: no
+// pivot.
 __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, int64_t nq, CellView cv,
                                                     int32_t *__restrict__ piv, int32_t *__restrict__ pivd)
 {
@@ -359,8 +361,9 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     if (q >= nq) return;   // no block-wide barrier below
     const int nc = (int)cv.n;
-    uint32_t *votes = s_votes + (size_t)wave * nc;
-    for (int i = lane; i < nc; i += 64) votes[i] = 0u;
+    const int nw = (nc + 1) >> 1;
+    uint32_t *votes = s_votes + (size_t)wave * nw;
+    for (int i = lane; i < nw; i += 64) votes[i] = 0u;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const int64_t s0 = qv.off[q];
@@ -369,7 +372,10 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
     for (int p = lane; p + kQgram <= plen; p += 64) {
         const uint32_t b = qgram_bucket(str + p);
         const int e1 = cv.qg_off[b + 1];
-        for (int e = cv.qg_off[b]; e < e1; e++) atomicAdd(&votes[cv.qg_cell[e]], 1u);
+        for (int e = cv.qg_off[b]; e < e1; e++) {
+            const int r = cv.qg_cell[e];
+            atomicAdd(&votes[r >> 1], (r & 1) ? 65536u : 1u);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -377,9 +383,12 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
     int mine = -1;   // lane t < 4 takes the t-th best centre
     for (int t = 0; t < 4; t++) {
         uint64_t best = 0ull;   // (votes << 32) | ~rank: larger is better
-        for (int i = lane; i < nc; i += 64) {
-            const uint64_t key = ((uint64_t)votes[i] << 32) | (uint64_t)(0xffffffffu - (uint32_t)i);
-            best = key > best ? key : best;
+        for (int i = lane; i < nw; i += 64) {
+            const uint32_t v = votes[i];
+            const uint64_t k0 = ((uint64_t)(v & 0xffffu) << 32) | (uint64_t)(0xffffffffu - (uint32_t)(2 * i));
+            const uint64_t k1 = ((uint64_t)(v >> 16) << 32) | (uint64_t)(0xffffffffu - (uint32_t)(2 * i + 1));
+            best = k0 > best ? k0 : best;
+            best = k1 > best ? k1 : best;
         }
 #pragma unroll
         for (int o2 = 32; o2 > 0; o2 >>= 1) {
@@ -390,7 +399,7 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
         const int r = (int)(0xffffffffu - (uint32_t)best);
         if (lane == t) mine = r;
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) votes[r] = 0u;
+        if (lane == 0) votes[r >> 1] &= (r & 1) ? 0x0000ffffu : 0xffff0000u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -398,9 +407,9 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
     uint64_t key = ~0ull;   // (distance << 32) | rank: smaller is better
     if (mine >= 0) {
         const int32_t c0 = cv.off[mine];
-        const int d = dev::myers_any(qv.peq + (size_t)q * o.rows * 4, plen, cv.chars + c0, cv.off[mine + 1] - c0,
-                                     1 << 30, o.lut);
-        key = ((uint64_t)(uint32_t)d << 32) | (uint32_t)mine;
+        const int d = dev::myers_banded(qv.peq + (size_t)q * o.rows * 4, 4, plen, cv.chars + c0,
+                                        cv.off[mine + 1] - c0, 63, o.lut);
+        if (d <= 63) key = ((uint64_t)(uint32_t)d << 32) | (uint32_t)mine;
     }
 #pragma unroll
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
@@ -418,7 +427,7 @@ void edit_pivot(const EditView &o, const QueryEdit &qv, int64_t nq, const CellVi
 {
     if (nq == 0) return;
     require(cv.n > 0 && cv.n <= 4096 && cv.dist && cv.qg_off && cv.qg_cell, "edit_pivot: no centre tables");
-    const size_t shm = (size_t)4 * cv.n * sizeof(uint32_t);
+    const size_t shm = (size_t)4 * ((cv.n + 1) / 2) * sizeof(uint32_t);
     hipLaunchKernelGGL(k_edit_pivot, dim3((unsigned)((nq + 3) / 4)), dim3(256), shm, st, o, qv, nq, cv, piv, pivd);
     check_launch(__func__);
 }
