@@ -70,10 +70,12 @@ __device__ __forceinline__ float wave_min(float v)
 // at least D[i*][j] on the row i* = j + m - n that ends on the last cell's
 // diagonal.  That value is read off the vertical deltas every kChunk columns
 // (the text characters of a chunk are loaded together, so a text in global
-// memory costs one load latency per chunk, not per character).
+// memory costs one load latency per chunk, not per character).  The
+// recurrences are host-callable too, so that they can be checked against the
+// dynamic programme without a GPU.
 // ---------------------------------------------------------------------------
 template <int W, class PeqPtr>
-__device__ __forceinline__ void myers_column(PeqPtr peq, int c, uint64_t (&VP)[W], uint64_t (&VN)[W], int topw,
+__host__ __device__ __forceinline__ void myers_column(PeqPtr peq, int c, uint64_t (&VP)[W], uint64_t (&VN)[W], int topw,
                                              uint64_t topbit, int &score)
 {
     uint64_t Xv[W], HP[W], HN[W];
@@ -116,20 +118,20 @@ __device__ __forceinline__ void myers_column(PeqPtr peq, int c, uint64_t (&VP)[W
 // D[i][j] of the current column j: D[0][j] = j plus the vertical deltas of
 // rows 1..i (bit r of VP/VN is the delta from row r to row r+1).
 template <int W>
-__device__ __forceinline__ int myers_row_value(const uint64_t (&VP)[W], const uint64_t (&VN)[W], int j, int i)
+__host__ __device__ __forceinline__ int myers_row_value(const uint64_t (&VP)[W], const uint64_t (&VN)[W], int j, int i)
 {
     int v = j;
 #pragma unroll
     for (int w = 0; w < W; w++) {
         const int bits = i - 64 * w;
         const uint64_t m = bits >= 64 ? ~0ull : (bits > 0 ? ((1ull << bits) - 1ull) : 0ull);
-        v += __popcll(VP[w] & m) - __popcll(VN[w] & m);
+        v += __builtin_popcountll(VP[w] & m) - __builtin_popcountll(VN[w] & m);
     }
     return v;
 }
 
 template <int W, class PeqPtr, class LutPtr>
-__device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_t *text, int tlen,
+__host__ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_t *text, int tlen,
                                               int cutoff, LutPtr lut)
 {
     if (plen == 0) return tlen;
@@ -173,7 +175,7 @@ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, const uint8_
 // myers_distance.  nw = words per code held by peq (bits past the pattern
 // are zero).
 template <class PeqPtr, class LutPtr>
-__device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen, int cutoff,
+__host__ __device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen, int cutoff,
                                             LutPtr lut)
 {
     if (plen == 0) return tlen;
@@ -209,7 +211,7 @@ __device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const 
     // D[r_j + t][j] - D[r_j][j] for t in 1..63
     auto below = [&](int t) {
         const uint64_t m = (2ull << t) - 2ull;
-        return __popcll(VP & m) - __popcll(VN & m);
+        return __builtin_popcountll(VP & m) - __builtin_popcountll(VN & m);
     };
     constexpr int kChunk = 8;
     int j = 0;

@@ -58,3 +58,18 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_myers_recurrences_match_dynamic_programme(tmp_path):
+    """The device's bit-parallel Levenshtein recurrences (full width, and the
+    banded one-word form used for cutoffs up to 63) are host-callable: compile
+    them for the host and compare with the dynamic programme on random and
+    mutated string pairs (exact distance within the cutoff, above it
+    otherwise)."""
+    exe = tmp_path / "myers_host"
+    subprocess.run(["hipcc", "-O2", "-std=c++17", "--offload-host-only", "-x", "hip",
+                    os.path.join(ROOT, "tests", "myers_host.cpp"), "-o", str(exe)], check=True,
+                   capture_output=True)
+    for seed in (1, 2):
+        r = subprocess.run([str(exe), str(seed), "60000"], capture_output=True, text=True)
+        assert r.returncode == 0 and r.stdout.startswith("ok"), r.stdout + r.stderr
