@@ -688,21 +688,45 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
 #pragma unroll
             for (int i = 0; i < MP; i++) qp[i] = 0;
         }
+        // the leaf's objects are staged 64 at a time, one per lane (length,
+        // tombstone, pivot-table row), and broadcast to the tile's queries
         const int p0 = leaf_first[leaf];
-        const int p1 = p0 + leaf_cnt[leaf];
-        for (int p = p0; p < p1; p++) {
-            if ((tomb[p >> 5] >> (p & 31)) & 1u) continue;
-            const int olen = soff[p + 1] - soff[p];
-            bool pass = act && abs(ql - olen) <= th;
-            const uint8_t *row = PTa + (size_t)p * MP;
+        const int cnt = leaf_cnt[leaf];
+        for (int b0 = 0; b0 < cnt; b0 += 64) {
+            const int po = p0 + b0 + lane;
+            const bool have = b0 + lane < cnt;
+            int olen_l = 0;
+            bool live_l = false;
+            uint32_t rw[MP / 4];
+            if (have) {
+                live_l = !((tomb[po >> 5] >> (po & 31)) & 1u);
+                olen_l = soff[po + 1] - soff[po];
+                const uint32_t *r32 = reinterpret_cast<const uint32_t *>(PTa + (size_t)po * MP);
 #pragma unroll
-            for (int i = 0; i < MP; i++) pass = pass && abs(qp[i] - (int)row[i]) <= th;
-            const uint64_t b = dev::ballot(pass);
-            if (!b) continue;
-            const int c = __popcll(b);
-            if (nb + c > kObjBuf) flush();
-            if (pass) buf[nb + dev::lanes_below(b)] = make_int2((int)q, p);
-            nb += c;
+                for (int k2 = 0; k2 < MP / 4; k2++) rw[k2] = r32[k2];
+            } else {
+#pragma unroll
+                for (int k2 = 0; k2 < MP / 4; k2++) rw[k2] = 0u;
+            }
+            uint64_t lv = dev::ballot(live_l);
+            while (lv) {
+                const int i = __ffsll((unsigned long long)lv) - 1;
+                lv &= lv - 1ull;
+                const int olen = __shfl(olen_l, i, 64);
+                bool pass = act && abs(ql - olen) <= th;
+#pragma unroll
+                for (int k2 = 0; k2 < MP / 4; k2++) {
+                    const uint32_t w = __shfl(rw[k2], i, 64);
+#pragma unroll
+                    for (int u = 0; u < 4; u++) pass = pass && abs(qp[4 * k2 + u] - (int)((w >> (8 * u)) & 0xffu)) <= th;
+                }
+                const uint64_t bq = dev::ballot(pass);
+                if (!bq) continue;
+                const int c = __popcll(bq);
+                if (nb + c > kObjBuf) flush();
+                if (pass) buf[nb + dev::lanes_below(bq)] = make_int2((int)q, p0 + b0 + i);
+                nb += c;
+            }
         }
     }
     if (nb) flush();
