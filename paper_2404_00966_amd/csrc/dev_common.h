@@ -161,11 +161,12 @@ __host__ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, con
     return score;
 }
 
-// Banded form for cutoffs k <= 63 (one 64-bit word whatever the pattern
-// length).  An alignment of cost <= k only visits diagonals j - i in [lo, hi]
-// with |j - i| + |j - i - (n - m)| <= k, at most k + 1 of them, so a window
-// of 64 consecutive rows that moves down one row per column (top row r_j =
-// max(1, j - hi)) holds every cell such an alignment visits.  Cells outside
+// Banded form for cutoffs k <= 63: one word of B bits whatever the pattern
+// length (B = 32 for k <= 31, else 64).  An alignment of cost <= k only
+// visits diagonals j - i in [lo, hi] with |j - i| + |j - i - (n - m)| <= k,
+// at most k + 1 <= B of them, so a window of B consecutive rows that moves
+// down one row per column (top row r_j = max(1, j - hi)) holds every cell
+// such an alignment visits.  Cells outside
 // the window enter as upper bounds (vertical delta +1 below it, horizontal
 // delta +1 above it, no carry from above), so every computed value is at
 // least the true one and equals it for a cell whose optimal alignment stays
@@ -174,44 +175,47 @@ __host__ __device__ __forceinline__ int myers_distance(PeqPtr peq, int plen, con
 // early exit reads the cell on the last cell's diagonal as in
 // myers_distance.  nw = words per code held by peq (bits past the pattern
 // are zero).
-template <class PeqPtr, class LutPtr>
-__host__ __device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen, int cutoff,
-                                            LutPtr lut)
+template <class T, class PeqPtr, class LutPtr>
+__host__ __device__ __forceinline__ int myers_banded_w(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen,
+                                                       int cutoff, LutPtr lut)
 {
+    constexpr int B = 8 * (int)sizeof(T);   // window rows; requires cutoff <= B - 1
     if (plen == 0) return tlen;
     const int delta = tlen - plen;
     const int ad = delta < 0 ? -delta : delta;
     if (ad > cutoff) return cutoff + 1;
     const int hi = (delta > 0 ? delta : 0) + ((cutoff - ad) >> 1);   // top diagonal of the band
     const int tstar = hi - delta;   // window bit of the last cell's diagonal once the window moves
-    uint64_t VP = ~0ull, VN = 0ull;
+    T VP = (T)~(T)0, VN = 0;
     int top = 1;   // D[r_j][j]; before the first column D[1][0] = 1
     auto column = [&](int j, int c) {   // j: 1-based column
-        const bool shift = j > hi + 1;
-        if (shift) {
-            VP = (VP >> 1) | (1ull << 63);
-            VN >>= 1;
-        }
-        const int s0 = shift ? j - hi - 1 : 0;   // 0-based pattern index of the window's top row
+        // branch-free: the window moves (sft = 1) once j > hi + 1; both table
+        // words are loaded from clamped indexes and zeroed past the table
+        const int sft = j > hi + 1 ? 1 : 0;
+        VP = (T)((VP >> sft) | ((T)sft << (B - 1)));
+        VN >>= sft;
+        const int s0 = min(max(0, j - hi - 1), 255);   // 0-based pattern index of the top row (texts <= 255)
         const int w0 = s0 >> 6, sh = s0 & 63;
-        const uint64_t a = w0 < nw ? peq[c * 4 + w0] : 0ull;
-        const uint64_t b = w0 + 1 < nw ? peq[c * 4 + w0 + 1] : 0ull;
-        const uint64_t Eq = sh ? ((a >> sh) | (b << (64 - sh))) : a;
-        const uint64_t Xv = Eq | VN;
-        const uint64_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
-        uint64_t HP = VN | ~(Xh | VP);
-        uint64_t HN = VP & Xh;
-        HP = (HP << 1) | 1ull;
-        HN <<= 1;
-        VP = HN | ~(Xv | HP);
+        uint64_t a = peq[c * 4 + min(w0, nw - 1)];
+        uint64_t b = peq[c * 4 + min(w0 + 1, nw - 1)];
+        a = w0 < nw ? a : 0ull;
+        b = w0 + 1 < nw ? b : 0ull;
+        const T Eq = (T)((a >> sh) | ((b << 1) << (63 - sh)));   // bits s0 .. s0+B-1
+        const T Xv = Eq | VN;
+        const T Xh = (T)((T)((Eq & VP) + VP) ^ VP) | Eq;
+        T HP = (T)(VN | (T)~(Xh | VP));
+        T HN = VP & Xh;
+        HP = (T)((T)(HP << 1) | (T)1);
+        HN = (T)(HN << 1);
+        VP = (T)(HN | (T)~(Xv | HP));
         VN = HP & Xv;
-        const int vd0 = (int)(VP & 1ull) - (int)(VN & 1ull);
-        top = shift ? top + 1 + vd0 : j + vd0;
+        const int vd0 = (int)(VP & (T)1) - (int)(VN & (T)1);
+        top = (sft ? top + 1 : j) + vd0;
     };
-    // D[r_j + t][j] - D[r_j][j] for t in 1..63
+    // D[r_j + t][j] - D[r_j][j] for t in 1..B-1
     auto below = [&](int t) {
-        const uint64_t m = (2ull << t) - 2ull;
-        return __builtin_popcountll(VP & m) - __builtin_popcountll(VN & m);
+        const T m = (T)((T)((T)2 << t) - (T)2);
+        return __builtin_popcountll((uint64_t)(VP & m)) - __builtin_popcountll((uint64_t)(VN & m));
     };
     constexpr int kChunk = 8;
     int j = 0;
@@ -230,6 +234,14 @@ __host__ __device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int ple
     const int tm = plen - rn;
     const int d = top + (tm > 0 ? below(tm) : 0);
     return d <= cutoff ? d : cutoff + 1;
+}
+
+template <class PeqPtr, class LutPtr>
+__host__ __device__ __forceinline__ int myers_banded(PeqPtr peq, int nw, int plen, const uint8_t *text, int tlen,
+                                                     int cutoff, LutPtr lut)
+{
+    if (cutoff <= 31) return myers_banded_w<uint32_t>(peq, nw, plen, text, tlen, cutoff, lut);
+    return myers_banded_w<uint64_t>(peq, nw, plen, text, tlen, cutoff, lut);
 }
 
 template <class PeqPtr, class LutPtr>
