@@ -622,14 +622,15 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         GTS_HIP(hipMemcpyAsync(dorder, order, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
         dpos = wsp<int32_t>(cx, W_POSOF, nq);
         GTS_HIP(hipMemcpyAsync(dpos, pos_of, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        int32_t *piv = wsp<int32_t>(cx, W_PIV, (size_t)2 * nq);
+        k::edit_pivot(oe, qe, nq, cv, piv, piv + nq, st);
         if (b.any_knn)
-            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, piv,
+                          d.cell_leaf.as<int32_t>(), st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
         qcells0 = wsp<int32_t>(cx, W_QCELLS0, (size_t)nq * k::kQueryCells);
         qcnt0 = wsp<int32_t>(cx, W_QCNT0, nq);
-        int32_t *piv = wsp<int32_t>(cx, W_PIV, (size_t)2 * nq);
-        k::edit_pivot(oe, qe, nq, cv, piv, piv + nq, st);
         k::edit_cell_test(oe, qe, cx->ws[W_QLEN].as<int32_t>(), cx->ws[W_QP].as<float>(), mpad,
                           cx->ws[W_T].as<float>(), nq, b.max_qlen, cv, piv, piv + nq, qcells0, qcnt0, counters,
                           dorder, st);
@@ -736,7 +737,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                          d.dim, d.dp, d.ksteps};
             k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
         } else {
-            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, nullptr,
+                          nullptr, st);
         }
     }
     if (nq > 0)

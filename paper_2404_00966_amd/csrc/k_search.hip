@@ -170,7 +170,9 @@ template <int MP, bool EDIT>
 __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, EditView oe, QueryEdit qe,
                                               const float *__restrict__ QP, const int32_t *__restrict__ kq,
                                               int64_t nq, const uint32_t *__restrict__ tomb, int win,
-                                              float *__restrict__ tq, int32_t *__restrict__ home)
+                                              float *__restrict__ tq, int32_t *__restrict__ home,
+                                              const int32_t *__restrict__ piv,
+                                              const int32_t *__restrict__ cell_leaf)
 {
     __shared__ float s_d[kWinMax];
     const int64_t q = blockIdx.x;
@@ -190,7 +192,15 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
         if (lane == 0) tq[q] = INFINITY;
         return;
     }
-    int64_t a = t.leaf_first[leaf];
+    // the window starts at the home leaf, or (edit distance, when the query
+    // has a pivot centre) at the first object of that centre's cell, whose
+    // objects run in order of distance to the centre
+    int64_t wl = leaf;
+    if (piv && cell_leaf) {
+        const int h = piv[q];
+        if (h >= 0 && cell_leaf[2 * h] <= cell_leaf[2 * h + 1]) wl = cell_leaf[2 * h];
+    }
+    int64_t a = t.leaf_first[wl];
     if (a + W > n) a = n - W;
     const int Wp = dev::next_pow2(W);
     for (int j = lane; j < Wp; j += 64) {
@@ -235,7 +245,8 @@ void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float
     EditView oe{};
     QueryEdit qe{};
 #define BL(MP) \
-    hipLaunchKernelGGL((k_bound<MP, false>), dim3((unsigned)nq), dim3(64), 0, st, t, o, qv, oe, qe, QP, kq, nq, tomb, win, tq, home)
+    hipLaunchKernelGGL((k_bound<MP, false>), dim3((unsigned)nq), dim3(64), 0, st, t, o, qv, oe, qe, QP, kq, nq, tomb, win, tq, \
+                       home, nullptr, nullptr)
     if (t.mpad == 8) BL(8);
     else if (t.mpad == 16) BL(16);
     else BL(32);
@@ -244,13 +255,15 @@ void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float
 }
 
 void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
-                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st)
+                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, const int32_t *piv,
+                const int32_t *cell_leaf, hipStream_t st)
 {
     if (nq == 0) return;
     L2View ol{};
     QueryL2 ql{};
 #define BE(MP) \
-    hipLaunchKernelGGL((k_bound<MP, true>), dim3((unsigned)nq), dim3(64), 0, st, t, ol, ql, o, qv, QP, kq, nq, tomb, win, tq, home)
+    hipLaunchKernelGGL((k_bound<MP, true>), dim3((unsigned)nq), dim3(64), 0, st, t, ol, ql, o, qv, QP, kq, nq, tomb, win, tq, \
+                       home, piv, cell_leaf)
     if (t.mpad == 8) BE(8);
     else if (t.mpad == 16) BE(16);
     else BE(32);

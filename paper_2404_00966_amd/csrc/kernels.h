@@ -102,8 +102,11 @@ struct QueryEdit {
 
 void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
               int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st);
+// piv/cell_leaf (may be null): a query with a pivot centre h takes its window
+// from the first object of cell h instead of its home leaf.
 void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
-                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st);
+                int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, const int32_t *piv,
+                const int32_t *cell_leaf, hipStream_t st);
 
 // Slab x query-tile bf16 MFMA distances (persistent, work counter in `work`).
 struct SlabView {
