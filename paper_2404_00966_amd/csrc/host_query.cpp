@@ -625,7 +625,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         int32_t *piv = wsp<int32_t>(cx, W_PIV, (size_t)2 * nq);
         k::edit_pivot(oe, qe, nq, cv, piv, piv + nq, st);
         if (b.any_knn)
-            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, piv,
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 512, base, home, piv,
                           d.cell_leaf.as<int32_t>(), st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);

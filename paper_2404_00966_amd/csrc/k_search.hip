@@ -193,14 +193,19 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
         return;
     }
     // the window starts at the home leaf, or (edit distance, when the query
-    // has a pivot centre) at the first object of that centre's cell, whose
-    // objects run in order of distance to the centre
-    int64_t wl = leaf;
+    // has a pivot centre) is centred on that centre's cell: a family split
+    // over two cells sits in neighbouring cells of the chain order, so a
+    // small cell still gets its sibling's objects into the window
+    int64_t a = t.leaf_first[leaf];
     if (piv && cell_leaf) {
         const int h = piv[q];
-        if (h >= 0 && cell_leaf[2 * h] <= cell_leaf[2 * h + 1]) wl = cell_leaf[2 * h];
+        if (h >= 0 && cell_leaf[2 * h] <= cell_leaf[2 * h + 1]) {
+            const int l1 = cell_leaf[2 * h + 1];
+            const int64_t c0 = t.leaf_first[cell_leaf[2 * h]], c1 = (int64_t)t.leaf_first[l1] + t.leaf_cnt[l1];
+            a = (c0 + c1) / 2 - W / 2;
+            if (a < 0) a = 0;
+        }
     }
-    int64_t a = t.leaf_first[wl];
     if (a + W > n) a = n - W;
     const int Wp = dev::next_pow2(W);
     for (int j = lane; j < Wp; j += 64) {
