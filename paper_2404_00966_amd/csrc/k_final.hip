@@ -290,7 +290,7 @@ template <bool kShort>
 __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
                                 float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring)
 {
-    __shared__ int s_n, s_cnt;
+    __shared__ int s_n;
     const int64_t seg0 = a.qoff[q];
     const int ns = (int)(a.qoff[q + 1] - seg0);
     const int k = a.kq ? a.kq[q] : 0;
@@ -315,23 +315,45 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
             l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
             s_keys[i] = (uint64_t)__float_as_uint(hi);
         }
-        // smallest v with #{hi <= v} >= k (hi >= 0: float order = bit order)
-        uint32_t lo_v = 0u, hi_v = 0xffffffffu;
-        while (lo_v < hi_v) {
-            const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
-            if (threadIdx.x == 0) s_cnt = 0;
+        // the k-th smallest hi (hi >= 0: float order = bit order) by a radix
+        // select, 8-bit digits from the top: per round a 256-bin LDS
+        // histogram of the keys matching the digits chosen so far, then wave
+        // 0 finds the digit holding the k-th
+        __shared__ uint32_t s_hist[256];
+        __shared__ uint32_t s_pick[2];
+        uint32_t prefix = 0u, pmask = 0u, kk = (uint32_t)k;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int i = threadIdx.x; i < 256; i += blockDim.x) s_hist[i] = 0u;
             __syncthreads();
-            int c = 0;
-            for (int i = threadIdx.x; i < ns; i += blockDim.x) c += (uint32_t)s_keys[i] <= mid ? 1 : 0;
+            for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+                const uint32_t v = (uint32_t)s_keys[i];
+                if ((v & pmask) == prefix) atomicAdd(&s_hist[(v >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (wave == 0) {
+                uint32_t c[4];
+                int sum = 0;
 #pragma unroll
-            for (int o2 = 32; o2 > 0; o2 >>= 1) c += __shfl_xor(c, o2, 64);
-            if (lane == 0 && c) atomicAdd(&s_cnt, c);
+                for (int u = 0; u < 4; u++) {
+                    c[u] = s_hist[4 * lane + u];
+                    sum += (int)c[u];
+                }
+                int total;
+                uint32_t before = (uint32_t)dev::wave_excl_scan(sum, &total);
+                if (before < kk && kk <= before + (uint32_t)sum) {
+                    int u = 0;
+                    while (before + c[u] < kk) before += c[u++];
+                    s_pick[0] = (uint32_t)(4 * lane + u);
+                    s_pick[1] = kk - before;
+                }
+            }
             __syncthreads();
-            if (s_cnt >= k) hi_v = mid;
-            else lo_v = mid + 1u;
+            prefix |= s_pick[0] << shift;
+            pmask |= 255u << shift;
+            kk = s_pick[1];
             __syncthreads();
         }
-        rc.ub = __uint_as_float(lo_v) * (1.f + 4.f * delta);
+        rc.ub = __uint_as_float(prefix) * (1.f + 4.f * delta);
     }
     __syncthreads();
     const int sl = lane & 15;
