@@ -271,7 +271,7 @@ def run_serving(args, gts, synth, torch, np):
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (each scaled by
 # what the counters read for a plain 256 MiB device copy), per kernel, for
 # the kernel source as profiled; None once the kernel has changed since.
-TRAFFIC_BYTES = {"k_verify_l2": 685023266, "k_mfma_sweep": 623095938, "k_bound_near": 710100679}
+TRAFFIC_BYTES = {"k_verify_l2": 687348230, "k_mfma_sweep": 623453968, "k_bound_near": 712193269}
 
 
 def rooflines(st, dim):

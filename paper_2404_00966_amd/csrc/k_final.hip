@@ -54,27 +54,52 @@ void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qco
 __global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *__restrict__ in, int64_t n,
                                                    int64_t *__restrict__ out)
 {
-    __shared__ int64_t s[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t a = (int64_t)t * per;
-    const int64_t b = a + per < n ? a + per : n;
-    int64_t sum = 0;
-    for (int64_t i = a; i < b; i++) sum += in[i];
-    s[t] = sum;
+    // one workgroup, tiles of 4096 entries (4 consecutive per thread): wave
+    // scans of the per-thread sums, then of the 16 wave totals, plus the
+    // running total of the earlier tiles
+    __shared__ int64_t s_w[16];
+    __shared__ int64_t s_carry;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) s_carry = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int64_t v = t >= off ? s[t - off] : 0;
+    for (int64_t base = 0; base < n; base += 4096) {
+        int64_t v[4], sum = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t i = base + 4 * t + u;
+            v[u] = i < n ? (int64_t)in[i] : 0;
+            sum += v[u];
+        }
+        int64_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wv] = x;
         __syncthreads();
-        s[t] += v;
+        if (wv == 0) {
+            int64_t w = lane < 16 ? s_w[lane] : 0;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const int64_t y = __shfl_up(w, o, 64);
+                if (lane >= o) w += y;
+            }
+            if (lane < 16) s_w[lane] = w;
+        }
+        __syncthreads();
+        int64_t run = s_carry + (wv ? s_w[wv - 1] : 0) + x - sum;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t i = base + 4 * t + u;
+            if (i < n) out[i] = run;
+            run += v[u];
+        }
+        __syncthreads();
+        if (t == 1023) s_carry = run;
         __syncthreads();
     }
-    int64_t run = s[t] - sum;
-    for (int64_t i = a; i < b; i++) {
-        out[i] = run;
-        run += in[i];
-    }
-    if (t == 1023) out[n] = s[1023];
+    if (t == 0) out[n] = s_carry;
 }
 
 void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
