@@ -726,7 +726,10 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
 #pragma unroll
                 for (int k2 = 0; k2 < MP / 4; k2++) rw[k2] = 0u;
             }
-            uint64_t lv = dev::ballot(live_l);
+            // each lane (query) collects the staged objects it keeps, then
+            // writes them contiguously: the candidate stream holds runs of
+            // one query, which the grouping by query counts once per run
+            uint64_t lv = dev::ballot(live_l), mine = 0ull;
             while (lv) {
                 const int i = __ffsll((unsigned long long)lv) - 1;
                 lv &= lv - 1ull;
@@ -738,13 +741,33 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
 #pragma unroll
                     for (int u = 0; u < 4; u++) pass = pass && abs(qp[4 * k2 + u] - (int)((w >> (8 * u)) & 0xffu)) <= th;
                 }
-                const uint64_t bq = dev::ballot(pass);
-                if (!bq) continue;
-                const int c = __popcll(bq);
-                if (nb + c > kObjBuf) flush();
-                if (pass) buf[nb + dev::lanes_below(bq)] = make_int2((int)q, p0 + b0 + i);
-                nb += c;
+                mine |= pass ? (1ull << i) : 0ull;
             }
+            int total;
+            const int before = dev::wave_excl_scan(__popcll(mine), &total);
+            if (total == 0) continue;
+            if (nb + total > kObjBuf) flush();
+            if (total > kObjBuf) {   // more than the buffer holds: straight to memory
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(cand_count, (uint32_t)total);
+                base = __shfl(base, 0, 64);
+                int at = before;
+                for (uint64_t m2 = mine; m2; m2 &= m2 - 1ull, at++) {
+                    const int64_t idx = (int64_t)base + at;
+                    if (idx < cand_cap) {
+                        Cand cd;
+                        cd.q = (int32_t)q;
+                        cd.pos = p0 + b0 + (__ffsll((unsigned long long)m2) - 1);
+                        cd.val = 0;
+                        cands[idx] = cd;
+                    }
+                }
+                continue;
+            }
+            int at = nb + before;
+            for (uint64_t m2 = mine; m2; m2 &= m2 - 1ull, at++)
+                buf[at] = make_int2((int)q, p0 + b0 + (__ffsll((unsigned long long)m2) - 1));
+            nb += total;
         }
     }
     if (nb) flush();
