@@ -356,14 +356,21 @@ __global__ __launch_bounds__(256) void k_edit_leaf_query(EditView o, QueryEdit q
 __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, int64_t nq, CellView cv,
                                                     int32_t *__restrict__ piv, int32_t *__restrict__ pivd)
 {
+    // LDS: per wave nw vote words (nw even), then per wave the query's match
+    // table (rows x 4 words), which the four distances read per character
     extern __shared__ uint32_t s_votes[];
+    __shared__ uint8_t s_lut[256];
     const int wave = dev::uniform((int)(threadIdx.x >> 6)), lane = dev::lane_id();
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) s_lut[i] = o.lut[i];
+    __syncthreads();
     if (q >= nq) return;   // no block-wide barrier below
     const int nc = (int)cv.n;
-    const int nw = (nc + 1) >> 1;
+    const int nw = ((nc + 1) >> 1) + (((nc + 1) >> 1) & 1);
     uint32_t *votes = s_votes + (size_t)wave * nw;
+    uint64_t *tab = reinterpret_cast<uint64_t *>(s_votes + (size_t)4 * nw) + (size_t)wave * o.rows * 4;
     for (int i = lane; i < nw; i += 64) votes[i] = 0u;
+    for (int i = lane; i < o.rows * 4; i += 64) tab[i] = qv.peq[(size_t)q * o.rows * 4 + i];
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const int64_t s0 = qv.off[q];
@@ -407,8 +414,8 @@ __global__ __launch_bounds__(256) void k_edit_pivot(EditView o, QueryEdit qv, in
     uint64_t key = ~0ull;   // (distance << 32) | rank: smaller is better
     if (mine >= 0) {
         const int32_t c0 = cv.off[mine];
-        const int d = dev::myers_banded(qv.peq + (size_t)q * o.rows * 4, 4, plen, cv.chars + c0,
-                                        cv.off[mine + 1] - c0, 63, o.lut);
+        const int d = dev::myers_banded(static_cast<const uint64_t *>(tab), 4, plen, cv.chars + c0,
+                                        cv.off[mine + 1] - c0, 63, static_cast<const uint8_t *>(s_lut));
         if (d <= 63) key = ((uint64_t)(uint32_t)d << 32) | (uint32_t)mine;
     }
 #pragma unroll
@@ -427,7 +434,9 @@ void edit_pivot(const EditView &o, const QueryEdit &qv, int64_t nq, const CellVi
 {
     if (nq == 0) return;
     require(cv.n > 0 && cv.n <= 4096 && cv.dist && cv.qg_off && cv.qg_cell, "edit_pivot: no centre tables");
-    const size_t shm = (size_t)4 * ((cv.n + 1) / 2) * sizeof(uint32_t);
+    const int64_t nw = (cv.n + 1) / 2 + ((cv.n + 1) / 2) % 2;
+    const size_t shm = (size_t)4 * nw * sizeof(uint32_t) + (size_t)4 * o.rows * 4 * sizeof(uint64_t);
+    require(shm <= 65536, "edit_pivot: vote and table rows exceed the workgroup's LDS");
     hipLaunchKernelGGL(k_edit_pivot, dim3((unsigned)((nq + 3) / 4)), dim3(256), shm, st, o, qv, nq, cv, piv, pivd);
     check_launch(__func__);
 }
