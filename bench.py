@@ -251,6 +251,16 @@ def run_serving(args, gts, synth, torch, np):
         srv = gts.Server([il2, idna], lanes_per_index=args.serve_lanes, keep_results=False)
         t = time.perf_counter()
         srv.replay(reqs, arr)
+        # drain, reporting the server's own completion count while it works
+        last = time.perf_counter()
+        while True:
+            st = srv.stats()
+            if st["completed"] + st["failed"] >= len(reqs):
+                break
+            time.sleep(0.05)
+            if time.perf_counter() - last >= 10.0:
+                log(f"{phase}: {st['completed']} of {len(reqs)} requests completed")
+                last = time.perf_counter()
         srv.flush()
         wall = time.perf_counter() - t
         st = srv.stats()
