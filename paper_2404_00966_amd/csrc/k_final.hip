@@ -28,6 +28,33 @@ __device__ __forceinline__ int query_run(int32_t q, bool valid, int *head_lane)
     return end - lane;
 }
 
+// Ascending bitonic sort of one 64-bit key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t key)
+{
+    const int lane = dev::lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t other = __shfl_xor(key, stride, 64);
+            const bool take_min = ((lane & size) == 0) == ((lane & stride) == 0);
+            key = take_min ? (other < key ? other : key) : (other > key ? other : key);
+        }
+    return key;
+}
+
+// Number of runs of equal queries among the wave's 64 lanes.
+__device__ __forceinline__ int query_runs(int32_t q)
+{
+    const int32_t prev = __shfl_up(q, 1, 64);
+    return __popcll(dev::ballot(dev::lane_id() == 0 || prev != q));
+}
+
+// Grouping by query: a wave whose 64 candidates hold many runs sorts them by
+// query first (invalid lanes, query -1, last), so every query of the window
+// counts once however the producer interleaved them; the order inside a
+// query's group is free (verification sorts by (distance, id)).
+constexpr int kSortRuns = 16;
 __global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
                                                     int64_t cap, uint32_t *__restrict__ qcount)
 {
@@ -36,8 +63,11 @@ __global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, 
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
         const int64_t i = b0 + dev::lane_id();
-        const bool valid = i < n;
-        const int32_t q = valid ? c[i].q : -1;
+        const int32_t q0 = i < n ? c[i].q : -1;
+        const int32_t q = query_runs(q0) > kSortRuns
+                              ? (int32_t)(uint32_t)(wave_sort64((uint64_t)(uint32_t)q0 << 32) >> 32)
+                              : q0;
+        const bool valid = q != -1;
         int hl;
         const int len = query_run(q, valid, &hl);
         if (len) atomicAdd(&qcount[q], (uint32_t)len);
@@ -119,10 +149,22 @@ __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ 
     const int lane = dev::lane_id();
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
         const int64_t i = b0 + lane;
-        const bool valid = i < n;
-        Cand cd;
-        cd.q = -1;
-        if (valid) cd = c[i];
+        Cand c0;
+        c0.q = -1;
+        c0.pos = 0;
+        c0.val = 0;
+        if (i < n) c0 = c[i];
+        // sort the wave's candidates by query, then take each record from
+        // the lane that loaded it
+        Cand cd = c0;
+        if (query_runs(c0.q) > kSortRuns) {   // wave-uniform
+            const uint64_t key = wave_sort64(((uint64_t)(uint32_t)c0.q << 32) | (uint32_t)lane);
+            const int src = (int)(key & 63u);
+            cd.q = (int32_t)(uint32_t)(key >> 32);
+            cd.pos = __shfl(c0.pos, src, 64);
+            cd.val = __shfl(c0.val, src, 64);
+        }
+        const bool valid = cd.q != -1;
         int hl;
         const int len = query_run(cd.q, valid, &hl);
         uint32_t base = 0;
