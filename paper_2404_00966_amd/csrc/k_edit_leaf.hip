@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_edit_cell_test(EditView o, QueryEdit qv
             hi[i] = b[MP + i];
         }
         const int lmin = cv.len[2 * c], lmax = cv.len[2 * c + 1], ri = (int)R;
-#pragma unroll 8
+#pragma unroll 16
         for (int j = 0; j < nj; j++) {
             const int tq = s_tq[j], pl = s_plen[j], h = s_hc[j];
             float g = -INFINITY;
