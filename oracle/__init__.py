@@ -48,6 +48,8 @@ def lib():
             _b.build()
         L = C.CDLL(_LIB_PATH)
         P = C.POINTER
+        L.orc_set_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_l2.restype = C.c_double
         L.orc_l2.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_edit.restype = C.c_int32
@@ -73,6 +75,12 @@ def lib():
                                   P(_Result), C.c_void_p]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the brute-force loops (0: query only); returns the count
+    in force."""
+    return lib().orc_set_threads(int(n))
 
 
 def _ptr(a):

@@ -17,13 +17,16 @@
  *     scan.  Definition 2 admits any k-set under ties; the oracle fixes the
  *     first min(k, n) objects in ascending (distance, id) order.
  *  3. A separate GTS-literal tree search following the paper's index and
- *     query algorithms (Sec. 4.2-4.3 and Algorithms 1-5), with the readings
+ *     query algorithms (Sec. 4.2-4.3 and 5.1-5.2, Algorithms 1-5), with the readings
  *     stated at each function.  It must return exactly what 2 returns; the
  *     tests check that, which also checks the readings.
  *
  * Parity pins live in tests/test_oracle_pins.py.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -54,6 +57,19 @@ typedef struct {
 static int64_t set_id(const orc_set *s, int64_t i) { return s->ids ? s->ids[i] : i; }
 
 /* Euclidean distance: sqrt(sum_i (x_i - y_i)^2) with every step in double. */
+/* Threads of the brute-force loops (timing on a given core count; results
+ * do not depend on it).  Returns the count now in force. */
+int32_t orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 double orc_l2(const float *x, const float *y, int32_t dim)
 {
     double acc = 0.0;
