@@ -4,29 +4,98 @@ Default workload (one step = one mixed batch through the whole search path):
   l2_1m_d128: 1,000,000 x 128 float32 vectors (100-component Gaussian
   mixture), 16 pivots, fanout 16, leaf 256; 10,000 kNN queries (k = 16) plus
   10,000 range queries at the 0.01% distance quantile, in one call.
-Reported alongside (same JSON line, key "dna_500k"): 500,000 DNA strings
-(1,000 families x 500 mutants), 8 pivots, fanout 8; 10,000 range queries
-r = 8 per step.
+Reported alongside in the same JSON line:
+  dna_500k: 500,000 DNA strings (1,000 families x 500 mutants), 8 pivots,
+    fanout 8; 10,000 range queries r = 8 per step;
+  l2_4m_d96: 4,000,000 x 96 (1,000 components, sigma 0.5), 50,000 kNN
+    queries k = 32, bf16-guarded against float32 selection.
 
-Inputs are resident in HBM before timing; a step is gts_search on the whole
-batch with answers left in device memory.  Prints ONE JSON line.
+`value` is the device-resident rate: queries and index in HBM when the timed
+region starts, answers left in device memory.  Each workload also reports
+the rate with the queries handed over in pinned host memory and the answers
+returned to host memory (PCIe included), the plain one-query-per-workgroup
+form and the float32 selection over the same whole batch, and distance
+evaluations per second.  Prints ONE JSON line.
+
+`python bench.py --pmc-summary DIR_FETCH DIR_WRITE` turns two rocprofv3
+counter runs (FETCH_SIZE, WRITE_SIZE) of this script into the HBM traffic
+summary kept under profiles/ (read back here as `traffic`).
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+CSRC = os.path.join(ROOT, "paper_2404_00966_amd", "csrc")
 
 METRIC = "queries/s oracle-exact: 1M×128 L2 kNN k=16, 500k DNA edit range r=8; p99 ms"
-BF16_PEAK_TFLOPS = 2500.0       # MI355X dense bf16 MFMA
+# MI355X published peaks
+BF16_PEAK_TFLOPS = 2500.0       # dense bf16 MFMA
+FP32_PEAK_TFLOPS = 157.3        # fp32 vector (FMA = 2 flop)
 HBM_PEAK_GBS = 8000.0
+# plain VALU issue: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# source files whose text decides each kernel's code (a profile's traffic
+# figure is used only while they are unchanged)
+KERNEL_SOURCES = {
+    "k_verify_l2": ["k_final.hip"],
+    "k_mfma_sweep": ["k_search.hip"],
+    "k_bound_near": ["k_leaf.hip"],
+    "k_leaf_box": ["k_search.hip"],
+    "k_l2_objfilter": ["k_filter32.hip"],
+    "k_edit_objfilter": ["k_search.hip"],
+    "k_verify_edit": ["k_final.hip"],
+}
+COMMON_SOURCES = ["dev_common.h", "kernels.h", "gts_internal.h"]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha16(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel] + COMMON_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_traffic():
+    """{workload: {kernel: entry}} from the JSON blocks of profiles/hbm_traffic__*.md."""
+    out = {}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic__*.md"))):
+        text = open(path).read()
+        for block in re.findall(r"```json\n(.*?)\n```", text, flags=re.S):
+            try:
+                d = json.loads(block)
+            except ValueError:
+                continue
+            out.setdefault(d.get("workload", ""), {}).update(d.get("kernels", {}))
+    return out
+
+
+_TRAFFIC = None
+
+
+def traffic(workload, kernel):
+    """Measured HBM bytes per launch of `kernel` on `workload`, or None when no
+    profile holds it or its source changed since the profile was taken."""
+    global _TRAFFIC
+    if _TRAFFIC is None:
+        _TRAFFIC = profile_traffic()
+    e = _TRAFFIC.get(workload, {}).get(kernel)
+    if not e or e.get("source_sha16") != source_sha16(kernel):
+        return None
+    return e.get("bytes")
 
 
 def timed_steps(fn, steps, warmup):
@@ -53,6 +122,20 @@ def pct(v, p):
     return float(np.percentile(np.asarray(v), p)) if v else None
 
 
+def same_answers(a, b):
+    """Element-by-element equality of two results (ids and distances)."""
+    import torch
+
+    return (torch.equal(a.offsets.cpu(), b.offsets.cpu()) and torch.equal(a.ids.cpu(), b.ids.cpu())
+            and torch.equal(a.dist.cpu(), b.dist.cpu()))
+
+
+def dist_evals(st, m):
+    """Exact metric evaluations of one call: query-to-pivot distances, the
+    kNN bound windows and the verified candidates (cache scans included)."""
+    return st["nq"] * m + st["bound_evals"] + st["verified"]
+
+
 def run_l2(args, gts, synth, torch, np):
     w = synth.WORKLOADS["l2_1m_d128"]
     radii = json.load(open(os.path.join(ROOT, "oracle", "radii.json")))
@@ -61,10 +144,12 @@ def run_l2(args, gts, synth, torch, np):
     d = synth.make_workload("l2_1m_d128", queries=args.queries)
     log(f"l2_1m_d128 generated in {time.perf_counter() - t:.1f}s")
     X = torch.from_numpy(d["objects"]).cuda()
-    Q = torch.from_numpy(np.concatenate([d["knn_queries"], d["range_queries"]])).cuda()
+    Qh = torch.from_numpy(np.concatenate([d["knn_queries"], d["range_queries"]])).pin_memory()
+    Q = Qh.cuda()
     nk, nr = len(d["knn_queries"]), len(d["range_queries"])
+    nq = nk + nr
     k = np.array([w["k"]] * nk + [0] * nr, np.int32)
-    radius = np.full(nk + nr, r, np.float32)
+    radius = np.full(nq, r, np.float32)
     torch.cuda.synchronize()
     t = time.perf_counter()
     idx = gts.Index(X, gts.L2_F32, num_pivots=w["pivots"], fanout=w["fanout"], leaf_size=w["leaf"],
@@ -79,24 +164,30 @@ def run_l2(args, gts, synth, torch, np):
             break
     log(f"tuning finished after {tune_calls} calls")
     total, per = timed_steps(lambda: idx.search(Q, radius=radius, k=k, result="device"), args.steps, args.warmup)
-    nq = nk + nr
-    qps = nq * args.steps / total
+    ms = total * 1e3 / args.steps
     # one more step with stage timing on, for the stage split and the roofline
     idx.set_timing(True)
-    idx.search(Q, radius=radius, k=k, result="device")
+    ref = idx.search(Q, radius=radius, k=k, result="device")
     st = idx.stats()
     idx.set_timing(False)
-    out = {"qps": qps, "ms_per_step": total * 1e3 / args.steps, "per_step_ms": per, "build_s": build_s,
-           "stats": st, "nq": nq, "r": r, "k": w["k"], "n": d["n"], "dim": w["dim"],
-           "tuned": {"bound_window": st["bound_window"], "tuning_calls": tune_calls}}
-    if args.plain_queries > 0:
-        sub = slice(0, args.plain_queries // 2)
-        Qp = torch.cat([Q[:nk][sub], Q[nk:][sub]])
-        kp = np.concatenate([k[:nk][sub], k[nk:][sub]])
-        rp = np.concatenate([radius[:nk][sub], radius[nk:][sub]])
-        tp, _ = timed_steps(lambda: idx.search(Qp, radius=rp, k=kp, mode=gts.MODE_PLAIN, result="device"), 1, 0)
-        out["plain_qps"] = len(kp) / tp
-        out["plain_queries"] = len(kp)
+    out = {"qps": nq * args.steps / total, "ms_per_step": ms, "per_step_ms": per, "build_s": build_s,
+           "stats": st, "nq": nq, "r": r, "k": w["k"], "n": d["n"], "dim": w["dim"], "m": w["pivots"],
+           "tuned": {"bound_window": st["bound_window"], "tuning_calls": tune_calls},
+           "dist_evals_per_s": dist_evals(st, w["pivots"]) / (ms * 1e-3)}
+    if args.side_steps > 0:
+        # PCIe included: queries from pinned host memory, answers to host memory
+        th, perh = timed_steps(lambda: idx.search(Qh, radius=radius, k=k, result="host"), args.side_steps, 1)
+        out["host_to_host"] = {"qps": nq * args.side_steps / th, "ms_per_step": th * 1e3 / args.side_steps,
+                               "p99_ms": pct(perh, 99)}
+        # the same whole batch in the plain form and with float32 selection
+        for name, kw in (("plain", {"mode": gts.MODE_PLAIN}), ("fp32_selection", {"precision": gts.FP32})):
+            res = []
+            tp, _ = timed_steps(lambda: res.append(idx.search(Q, radius=radius, k=k, result="device", **kw)),
+                                args.side_steps, 1)
+            out[name] = {"qps": nq * args.side_steps / tp, "ms_per_step": tp * 1e3 / args.side_steps,
+                         "same_answers": same_answers(ref, res[-1]),
+                         "candidates": idx.stats()["candidates"], "verified": idx.stats()["verified"]}
+            log(f"l2 {name}: {out[name]}")
     idx.close()
     return out, d
 
@@ -110,7 +201,8 @@ def run_dna(args, gts, synth, torch, np):
     qc, qo = d["queries"]
     nq = len(qo) - 1
     oc, oo = torch.from_numpy(chars).cuda(), torch.from_numpy(off).cuda()
-    qct, qot = torch.from_numpy(qc).cuda(), torch.from_numpy(qo).cuda()
+    qch, qoh = torch.from_numpy(qc).pin_memory(), torch.from_numpy(qo).pin_memory()
+    qct, qot = qch.cuda(), qoh.cuda()
     torch.cuda.synchronize()
     t = time.perf_counter()
     idx = gts.Index((oc, oo), gts.EDIT_U8, num_pivots=w["pivots"], fanout=w["fanout"], seed=w["seed"])
@@ -119,43 +211,148 @@ def run_dna(args, gts, synth, torch, np):
     radius = np.full(nq, float(w["radius"]), np.float32)
     total, per = timed_steps(lambda: idx.search((qct, qot), radius=radius, result="device"), args.steps,
                              args.warmup)
+    ms = total * 1e3 / args.steps
     idx.set_timing(True)
-    idx.search((qct, qot), radius=radius, result="device")
+    ref = idx.search((qct, qot), radius=radius, result="device")
     st = idx.stats()
     idx.set_timing(False)
-    out = {"qps": nq * args.steps / total, "ms_per_step": total * 1e3 / args.steps, "per_step_ms": per,
-           "build_s": build_s, "stats": st, "nq": nq}
-    if args.plain_queries > 0:
-        m = min(nq, args.plain_queries)
-        tp, _ = timed_steps(lambda: idx.search((qct, qot[: m + 1]), radius=radius[:m], mode=gts.MODE_PLAIN,
-                                               result="device"), 1, 0)
-        out["plain_qps"] = m / tp
-        out["plain_queries"] = m
+    out = {"qps": nq * args.steps / total, "ms_per_step": ms, "per_step_ms": per, "build_s": build_s,
+           "stats": st, "nq": nq, "dist_evals_per_s": dist_evals(st, w["pivots"]) / (ms * 1e-3)}
+    if args.side_steps > 0:
+        th, perh = timed_steps(lambda: idx.search((qch, qoh), radius=radius, result="host"), args.side_steps, 1)
+        out["host_to_host"] = {"qps": nq * args.side_steps / th, "ms_per_step": th * 1e3 / args.side_steps,
+                               "p99_ms": pct(perh, 99)}
+        res = []
+        tp, _ = timed_steps(lambda: res.append(idx.search((qct, qot), radius=radius, mode=gts.MODE_PLAIN,
+                                                          result="device")), max(1, args.side_steps // 2), 1)
+        out["plain"] = {"qps": nq * max(1, args.side_steps // 2) / tp,
+                        "ms_per_step": tp * 1e3 / max(1, args.side_steps // 2),
+                        "same_answers": same_answers(ref, res[-1])}
+        log(f"dna plain: {out['plain']}")
     idx.close()
     return out, d
 
 
-def cpu_baseline(args, l2data, np):
-    """The oracle's brute force (test infrastructure) on a bounded sample of
-    the same workload, on the host cores."""
+def run_l4m(args, gts, synth, torch, np):
+    """4M x 96, 50,000 kNN (k = 32): bf16-guarded selection against float32
+    selection and the plain form on the whole batch, and the largest
+    relative distance error of a sample of answers against float64."""
+    w = synth.WORKLOADS["l2_4m_d96"]
+    t = time.perf_counter()
+    d = synth.make_workload("l2_4m_d96", queries=args.queries)
+    log(f"l2_4m_d96 generated in {time.perf_counter() - t:.1f}s")
+    X = d["objects"]
+    KQ = d["knn_queries"]
+    nq = len(KQ)
+    idx = gts.Index(torch.from_numpy(X).cuda(), gts.L2_F32, num_pivots=w["pivots"], fanout=w["fanout"],
+                    leaf_size=w["leaf"], seed=w["seed"])
+    Q = torch.from_numpy(KQ).cuda()
+    for _ in range(16):
+        idx.knn(Q, w["k"], result="device")
+        if idx.stats()["tuning"] == 0:
+            break
+    steps = max(2, args.side_steps)
+    total, per = timed_steps(lambda: idx.knn(Q, w["k"], result="device"), steps, 1)
+    idx.set_timing(True)
+    ref = idx.knn(Q, w["k"], result="device")
+    st = idx.stats()
+    idx.set_timing(False)
+    out = {"qps": nq * steps / total, "ms_per_step": total * 1e3 / steps, "p99_ms": pct(per, 99), "nq": nq,
+           "k": w["k"], "stats": st}
+    for name, kw in (("fp32_selection", {"precision": gts.FP32}), ("plain", {"mode": gts.MODE_PLAIN})):
+        res = []
+        tp, _ = timed_steps(lambda: res.append(idx.knn(Q, w["k"], result="device", **kw)), 1, 1)
+        out[name] = {"qps": nq / tp, "ms_per_step": tp * 1e3, "same_answers": same_answers(ref, res[-1])}
+        log(f"l2_4m_d96 {name}: {out[name]}")
+    idx.close()
+    lists = ref.to_lists()
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for i in rng.choice(nq, 64, replace=False):
+        ids, dist = lists[i]
+        exact = np.sqrt(((X[ids].astype(np.float64) - KQ[i].astype(np.float64)) ** 2).sum(axis=1))
+        worst = max(worst, float(np.max(np.abs(dist.astype(np.float64) - exact) / np.maximum(exact, 1e-30))))
+    out["max_rel_err_vs_f64"] = worst
+    out["rel_err_sample"] = "every answer of 64 random queries"
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, l2data, dnadata, np):
+    """The oracle (test infrastructure) on bounded samples of the same
+    workloads, on the host cores: the float64 brute force on every core and
+    on one core, the brute-force Wagner-Fischer on the DNA set, and the
+    GTS-literal CPU tree search with its distance-evaluation counts."""
     import oracle as O
 
     radii = json.load(open(os.path.join(ROOT, "oracle", "radii.json")))
     r = radii["l2_1m_d128"]["radius_f32"]
+    X = l2data["objects"]
+    n = len(X)
+    objs = O.ObjectSet(vecs=X)
+    cores = O.set_threads(0)
+
+    def l2_bf(m):
+        kq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["knn_queries"][:m]))
+        rq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["range_queries"][:m]))
+        t = time.perf_counter()
+        O.knn_bf(objs, kq, 16)
+        O.range_bf(objs, rq, r)
+        return time.perf_counter() - t
+
     m = args.cpu_queries // 2
-    objs = O.ObjectSet(vecs=l2data["objects"])
-    kq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["knn_queries"][:m]))
-    rq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["range_queries"][:m]))
+    el = l2_bf(m)
+    out = {"value": 2 * m / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
+           "sample": f"{m} kNN (k=16) + {m} range queries of l2_1m_d128 over all {n:,} x 128 objects, "
+                     f"float64 brute force, {el:.1f}s",
+           "cpu_model": cpu_model(), "dist_evals_per_s": 2 * m * n / el}
+    m1 = max(1, args.cpu_queries // 100)
+    O.set_threads(1)
+    el1 = l2_bf(m1)
+    O.set_threads(cores)
+    out["one_core"] = {"value": 2 * m1 / el1, "cores": 1, "dist_evals_per_s": 2 * m1 * n / el1,
+                       "sample": f"{m1} kNN + {m1} range queries, {el1:.1f}s"}
+    # GTS-literal tree (Algorithms 1-5 on the CPU): build, then sampled queries
     t = time.perf_counter()
-    O.knn_bf(objs, kq, 16)
-    O.range_bf(objs, rq, r)
-    el = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": 2 * m / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"{m} kNN (k=16) + {m} range queries over all 1,000,000 x 128 objects, "
-                      f"float64 brute force, {el:.1f}s"}
+    tree = O.GtsTree(objs, 16, seed=1)
+    tb = time.perf_counter() - t
+    kq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["knn_queries"][:m1]))
+    rq = O.ObjectSet(vecs=np.ascontiguousarray(l2data["range_queries"][:m1]))
+    t = time.perf_counter()
+    _, ek = tree.knn(kq, 16)
+    _, er = tree.range(rq, r)
+    tt = time.perf_counter() - t
+    ev = np.concatenate([ek, er])
+    out["gts_tree"] = {"value": 2 * m1 / tt, "cores": 1, "build_s": tb,
+                       "dist_evals_per_query": float(ev.mean()), "fraction_of_n": float(ev.mean() / n),
+                       "dist_evals_per_s": float(ev.sum() / tt),
+                       "sample": f"{m1} kNN + {m1} range queries, single-threaded, {tt:.1f}s"}
+    if dnadata is not None:
+        from paper_2404_00966_amd import synth
 
-
+        chars, off = dnadata["objects"]
+        qc, qo = dnadata["queries"]
+        md = max(1, args.cpu_dna_queries)
+        sc, so = synth.strings_from_bytes([qc[qo[i]:qo[i + 1]].tobytes() for i in range(md)])
+        eo = O.ObjectSet(strings=(chars, off))
+        t = time.perf_counter()
+        O.range_bf(eo, O.ObjectSet(strings=(sc, so)), 8.0)
+        ed = time.perf_counter() - t
+        nd = len(off) - 1
+        out["dna_500k"] = {"value": md / ed, "unit": "queries/s", "cores": cores,
+                           "dist_evals_per_s": md * nd / ed,
+                           "sample": f"{md} range queries (r=8) over all {nd:,} strings, full Wagner-Fischer, "
+                                     f"{ed:.1f}s"}
+    return out
 def run_serving(args, gts, synth, torch, np):
     """Serving mix: an L2 index (2M x 128) and a DNA index (200k strings)
     behind one continuous-batching server, driven by an open-loop Poisson
@@ -278,47 +475,99 @@ def run_serving(args, gts, synth, torch, np):
     return out
 
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (each scaled by
-# what the counters read for a plain 256 MiB device copy), per kernel, for
-# the kernel source as profiled; None once the kernel has changed since.
-TRAFFIC_BYTES = {"k_verify_l2": 687348230, "k_mfma_sweep": 623453968, "k_bound_near": 712193269}
 
 
-def rooflines(st, dim):
-    """Roofline points of the kernels behind the timed stages of one search
-    call (stage times are HIP-event times on the index's stream; each stage
-    is one kernel).  Algorithmic work per launch:
-      k_mfma_sweep: every (query, object) pair of the computed (256-object
-        slab, 16-query block) units, 2 * D flop each (D = dim rounded up to
-        32);
+def _roof(bound, achieved, peak, unit, work, launch_ms, what, traffic_bytes=None):
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak if achieved else None, "traffic": traffic_bytes, "work_per_launch": work,
+            "launch_ms": launch_ms, "work": what}
+
+
+def rooflines_l2(st, dim, workload):
+    """Roofline points of the kernels behind the single-kernel stages of one
+    search call (stage times are HIP-event times on the index's stream).
+    Algorithmic work per launch:
+      k_mfma_sweep: 2 * Dk flop (Dk = dim rounded up to 32) per (query,
+        object) pair inside the surviving (query, leaf) pairs -- the method's
+        own pairs; the dense-equivalent figure counts every pair of the
+        computed (256-object slab, 16-query block) units instead;
       k_verify_l2: per candidate its 16-byte record and the 8 bytes of its
         norm and rounding error, per float32 recheck one object row (4 * dim
         bytes), per answer its 8-byte key;
-      k_bound_near: one object row (4 * dim bytes) per distance of the kNN
-        bound windows."""
+      k_bound_near: the HBM bytes the profiler measured for it (its windows
+        overlap across neighbouring queries, so the rows it computes with are
+        mostly L2 hits), and 3 * dim flop per exact distance."""
     dk = (dim + 31) // 32 * 32
+    ms = st["ms_stage"]
     out = {}
-    ms = st["ms_stage"]["cands"]
-    flops = 2.0 * dk * st["tile_pairs"] * 16 * 256
-    a = flops / (ms * 1e-3) / 1e12 if ms > 0 else None
-    out["k_mfma_sweep"] = {"bound": "mfma", "achieved": a, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": a / BF16_PEAK_TFLOPS if a else None, "traffic": TRAFFIC_BYTES["k_mfma_sweep"],
-                           "work_per_launch": flops, "launch_ms": ms,
-                           "work": "(256-object slab, 16-query block) units x 16 x 256 pairs x 2*Dk flop"}
-    ms = st["ms_stage"]["verify"]
+    t = ms["cands"]
+    own = 2.0 * dk * st["own_pairs"]
+    dense = 2.0 * dk * st["tile_pairs"] * 16 * 256
+    a = own / (t * 1e-3) / 1e12 if t > 0 else None
+    out["k_mfma_sweep"] = _roof("mfma", a, BF16_PEAK_TFLOPS, "TFLOP/s", own, t,
+                                "2*Dk flop per (query, object) pair inside the surviving (query, leaf) pairs",
+                                traffic(workload, "k_mfma_sweep"))
+    ad = dense / (t * 1e-3) / 1e12 if t > 0 else None
+    out["k_mfma_sweep"]["dense_equivalent"] = {
+        "achieved": ad, "frac": ad / BF16_PEAK_TFLOPS if ad else None, "work_per_launch": dense,
+        "work": "every pair of the computed (256-object slab, 16-query block) units, 2*Dk flop each"}
+    t = ms["verify"]
     byts = 24.0 * st["candidates"] + 4.0 * dim * st["verified"] + 8.0 * st["results"]
-    a = byts / (ms * 1e-3) / 1e9 if ms > 0 else None
-    out["k_verify_l2"] = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": a / HBM_PEAK_GBS if a else None, "traffic": TRAFFIC_BYTES["k_verify_l2"],
-                          "work_per_launch": byts, "launch_ms": ms,
-                          "work": "24 B per candidate + 4*dim B per float32 recheck + 8 B per answer"}
-    ms = st["ms_stage"]["bound"]
-    byts = 4.0 * dim * st["bound_evals"]
-    a = byts / (ms * 1e-3) / 1e9 if ms > 0 else None
-    out["k_bound_near"] = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": a / HBM_PEAK_GBS if a else None, "traffic": TRAFFIC_BYTES["k_bound_near"],
-                           "work_per_launch": byts, "launch_ms": ms,
-                           "work": "4*dim B per distance of the kNN bound windows"}
+    a = byts / (t * 1e-3) / 1e9 if t > 0 else None
+    out["k_verify_l2"] = _roof("hbm", a, HBM_PEAK_GBS, "GB/s", byts, t,
+                               "24 B per candidate + 4*dim B per float32 recheck + 8 B per answer",
+                               traffic(workload, "k_verify_l2"))
+    t = ms["bound"]
+    tb = traffic(workload, "k_bound_near")
+    a = tb / (t * 1e-3) / 1e9 if tb and t > 0 else None
+    out["k_bound_near"] = _roof("hbm", a, HBM_PEAK_GBS, "GB/s", tb, t,
+                                "measured HBM bytes of the launch (profile); null when the profile is stale", tb)
+    fl = 3.0 * dim * st["bound_evals"]
+    af = fl / (t * 1e-3) / 1e12 if t > 0 else None
+    out["k_bound_near"]["fp32"] = {"achieved": af, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": af / FP32_PEAK_TFLOPS if af else None, "work_per_launch": fl,
+                                   "work": "3*dim flop per exact distance of the kNN bound windows"}
+    return out
+
+
+def rooflines_fp32_filter(st, mpad, workload):
+    """k_l2_objfilter (float32 selection): per staged object its column of the
+    pivot table (4 * mpad bytes) and 4 bytes of tombstone/position data, per
+    candidate its 16-byte record; ALU work 3 * mpad per (query, object) test."""
+    t = st["ms_stage"]["cands"]
+    byts = (4.0 * mpad + 4.0) * st["filter_objects"] + 16.0 * st["candidates"]
+    a = byts / (t * 1e-3) / 1e9 if t > 0 else None
+    r = _roof("hbm", a, HBM_PEAK_GBS, "GB/s", byts, t,
+              "(4*mpad + 4) B per staged object + 16 B per candidate", traffic("l2_1m_d128", "k_l2_objfilter"))
+    ops = 3.0 * mpad * st["own_pairs"]
+    ao = ops / (t * 1e-3) / 1e12 if t > 0 else None
+    r["alu"] = {"achieved": ao, "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": ao / VALU_PEAK_TOPS if ao else None,
+                "work_per_launch": ops, "work": "3*mpad VALU ops per (query, object) test"}
+    return r
+
+
+def rooflines_dna(st, mpad, workload):
+    """k_edit_objfilter: per staged object its mpad-byte pivot-table row and 8
+    bytes of offsets and tombstones, per candidate its 16-byte record;
+    k_verify_edit is VALU-bound: its instruction count comes from the
+    profiler (SQ_INSTS_VALU) when a fresh profile holds it."""
+    out = {}
+    t = st["ms_stage"]["cands"]
+    byts = (mpad + 8.0) * st["filter_objects"] + 16.0 * st["candidates"]
+    a = byts / (t * 1e-3) / 1e9 if t > 0 else None
+    out["k_edit_objfilter"] = _roof("hbm", a, HBM_PEAK_GBS, "GB/s", byts, t,
+                                    "(mpad + 8) B per staged object + 16 B per candidate",
+                                    traffic(workload, "k_edit_objfilter"))
+    t = st["ms_stage"]["verify"]
+    global _TRAFFIC
+    if _TRAFFIC is None:
+        _TRAFFIC = profile_traffic()
+    e = _TRAFFIC.get(workload, {}).get("k_verify_edit", {})
+    insts = e.get("valu_insts") if e.get("source_sha16") == source_sha16("k_verify_edit") else None
+    a = insts * 64 / (t * 1e-3) / 1e12 if insts and t > 0 else None
+    out["k_verify_edit"] = _roof("alu", a, VALU_PEAK_TOPS, "T lane-ops/s", insts, t,
+                                 "wave64 VALU instructions of the launch x 64 lanes (profile)",
+                                 traffic(workload, "k_verify_edit"))
     return out
 
 
@@ -333,16 +582,86 @@ def calibrate_copy(torch):
     log("calibration copy: 268435456 bytes read, 268435456 written")
 
 
+def _kernel_base(name):
+    m = re.search(r"\b(k_[A-Za-z0-9_]+)", name)
+    if m:
+        return m.group(1)
+    return "copy" if "copyBuffer" in name or "copy" in name.lower() else name[:40]
+
+
+def _counter_rows(d):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def pmc_summary(dirs, workload, last, command):
+    """Markdown summary (with a JSON block bench.py reads back) of rocprofv3
+    counter runs: per kernel the mean of its last `last` dispatches per
+    counter, HBM bytes scaled by what FETCH_SIZE / WRITE_SIZE read for the
+    256 MiB calibration copy."""
+    per = {}     # (kernel, counter) -> [(dispatch, value)]
+    for d in dirs:
+        for r in _counter_rows(d):
+            k = _kernel_base(r.get("Kernel_Name", ""))
+            c = r.get("Counter_Name", "")
+            per.setdefault((k, c), []).append((int(r.get("Dispatch_Id", 0)), float(r.get("Counter_Value", 0))))
+    copy_bytes = 268435456.0
+    factor = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [v for _, v in per.get(("copy", c), [])]
+        if vals:
+            factor[c] = copy_bytes / (max(vals) * 1024.0)
+    kernels = {}
+    for (k, c), vals in sorted(per.items()):
+        if k == "copy" or k not in KERNEL_SOURCES:
+            continue
+        vals.sort()
+        tail = [v for _, v in vals[-last:]]
+        e = kernels.setdefault(k, {"source_sha16": source_sha16(k), "dispatches": len(vals)})
+        key = {"FETCH_SIZE": "fetch_kib", "WRITE_SIZE": "write_kib", "SQ_INSTS_VALU": "valu_insts"}.get(c, c)
+        e[key] = sum(tail) / len(tail)
+    for k, e in kernels.items():
+        if "fetch_kib" in e and "write_kib" in e and factor.get("FETCH_SIZE") and factor.get("WRITE_SIZE"):
+            e["bytes"] = int(e["fetch_kib"] * 1024 * factor["FETCH_SIZE"] + e["write_kib"] * 1024 * factor["WRITE_SIZE"])
+    lines = [f"# HBM traffic and counters per launch (rocprofv3 PMC): {workload}", "",
+             "Commands (repository root, one MI355X), one counter group per run:", "", "```", *command, "```", "",
+             "Calibration: one device copy of 268,435,456 bytes (`--calibrate-copy`); scale factors "
+             + ", ".join(f"{c} x {v:.4f}" for c, v in factor.items()) + " (bytes per counted KiB / 1024).", "",
+             f"Per launch: the mean of the last {last} dispatches of each kernel.  `bench.py` uses these figures as "
+             "`traffic` only while the kernel's source hash matches `source_sha16`.", "",
+             "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM bytes (MB) | SQ_INSTS_VALU |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for k, e in sorted(kernels.items()):
+        fk, wk, b, vi = e.get("fetch_kib"), e.get("write_kib"), e.get("bytes"), e.get("valu_insts")
+        lines.append(f"| `{k}` | {e['dispatches']} | {fk if fk is None else f'{fk:,.1f}'} | "
+                     f"{wk if wk is None else f'{wk:,.1f}'} | {b if b is None else f'{b / 1e6:,.1f}'} | "
+                     f"{vi if vi is None else f'{vi:,.0f}'} |")
+    lines += ["", "```json", json.dumps({"workload": workload, "copy_factor": factor, "kernels": kernels}, indent=1),
+              "```", ""]
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--queries", type=int, default=None, help="cap queries per kind (default: full)")
-    ap.add_argument("--plain-queries", type=int, default=2000)
-    ap.add_argument("--cpu-queries", type=int, default=1600)
+    ap.add_argument("--side-steps", type=int, default=2,
+                    help="steps of the host-to-host, plain and float32-selection legs (0: skip them)")
+    ap.add_argument("--cpu-queries", type=int, default=800, help="L2 queries of the all-core oracle sample")
+    ap.add_argument("--cpu-dna-queries", type=int, default=8)
     ap.add_argument("--skip-dna", action="store_true")
+    ap.add_argument("--skip-c4", action="store_true", help="skip the 4M x 96 kNN leg")
     ap.add_argument("--calibrate-copy", action="store_true", help="run one 256 MiB device copy first (profiling)")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                    help="summarise rocprofv3 counter runs in DIR... (no GPU work)")
+    ap.add_argument("--pmc-workload", default="l2_1m_d128")
+    ap.add_argument("--pmc-last", type=int, default=2)
+    ap.add_argument("--pmc-command", action="append", default=[])
     ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the batch benchmark")
     ap.add_argument("--serve-rate", type=float, default=50000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-s", type=float, default=4.0, help="measured trace length, s")
@@ -351,6 +670,9 @@ def main():
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--serve-cache", type=int, default=1 << 20, help="cache list limit of the serving indexes")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary, args.pmc_workload, args.pmc_last, args.pmc_command))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
@@ -381,20 +703,24 @@ def main():
         return
     l2, l2data = run_l2(args, gts, synth, torch, np)
     log(f"l2: {l2['qps']:.0f} q/s, {l2['ms_per_step']:.2f} ms/step, stages {l2['stats']['ms_stage']}")
-    dna = None
+    dna, dnadata = None, None
     if not args.skip_dna:
-        dna, _ = run_dna(args, gts, synth, torch, np)
+        dna, dnadata = run_dna(args, gts, synth, torch, np)
         log(f"dna: {dna['qps']:.0f} q/s, {dna['ms_per_step']:.2f} ms/step, stages {dna['stats']['ms_stage']}")
+    c4 = None
+    if not args.skip_c4:
+        c4 = run_l4m(args, gts, synth, torch, np)
+        log(f"l2_4m_d96: {c4['qps']:.0f} q/s, {c4['ms_per_step']:.2f} ms/step")
 
     st = l2["stats"]
-    roofs = rooflines(st, l2["dim"])
+    roofs = rooflines_l2(st, l2["dim"], "l2_1m_d128")
     # the roofline reported is the one of the kernel that takes longest
     dom = max(roofs, key=lambda name: roofs[name]["launch_ms"])
     roof = dict(roofs[dom], kernel=dom)
     cpu = None
     if args.cpu_queries > 0:
-        log("cpu baseline (oracle brute force) ...")
-        cpu = cpu_baseline(args, l2data, np)
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args, l2data, dnadata, np)
     line = {
         "metric": METRIC,
         "value": l2["qps"],
@@ -414,25 +740,36 @@ def main():
         "p50_ms": pct(l2["per_step_ms"], 50),
         "p99_ms": pct(l2["per_step_ms"], 99),
         "latency_note": "batched: every query of a step completes with the step (makespan)",
-        "stage_ms": l2["stats"]["ms_stage"],
-        "counters": {k: l2["stats"][k] for k in ("node_tests", "tile_pairs", "candidates", "verified", "results",
-                                                 "bound_evals")},
+        "value_note": "queries and index resident in HBM, answers left in device memory; host_to_host "
+                      "hands queries over in pinned host memory and returns answers to host memory",
+        "dist_evals_per_s": l2["dist_evals_per_s"],
+        "host_to_host": l2.get("host_to_host"),
+        "plain": l2.get("plain"),
+        "fp32_selection": l2.get("fp32_selection"),
+        "stage_ms": st["ms_stage"],
+        "counters": {k: st[k] for k in ("node_tests", "tile_pairs", "own_pairs", "candidates", "verified",
+                                        "results", "bound_evals", "wide_queries", "bound_violations")},
         "build_s": l2["build_s"],
         "tuned": l2["tuned"],
-        "plain_qps": l2.get("plain_qps"),
-        "plain_queries": l2.get("plain_queries"),
         "roofline": roof,
         "rooflines": roofs,
         "cpu_baseline": cpu,
     }
     if dna:
+        dst = dna["stats"]
         line["dna_500k"] = {"queries_per_s": dna["qps"], "ms_per_step": dna["ms_per_step"],
                             "p50_ms": pct(dna["per_step_ms"], 50), "p99_ms": pct(dna["per_step_ms"], 99),
                             "queries": dna["nq"], "radius": 8, "build_s": dna["build_s"],
-                            "stage_ms": dna["stats"]["ms_stage"],
-                            "counters": {k: dna["stats"][k] for k in ("node_tests", "leaf_pairs", "candidates",
-                                                                      "verified", "results")},
-                            "plain_qps": dna.get("plain_qps"), "plain_queries": dna.get("plain_queries")}
+                            "dist_evals_per_s": dna["dist_evals_per_s"], "stage_ms": dst["ms_stage"],
+                            "counters": {k: dst[k] for k in ("leaf_pairs", "own_pairs", "filter_objects",
+                                                             "candidates", "verified", "results", "wide_queries")},
+                            "host_to_host": dna.get("host_to_host"), "plain": dna.get("plain"),
+                            "rooflines": rooflines_dna(dst, 8, "dna_500k")}
+    if c4:
+        line["l2_4m_d96"] = {k: v for k, v in c4.items() if k != "stats"}
+        line["l2_4m_d96"]["stage_ms"] = c4["stats"]["ms_stage"]
+        line["l2_4m_d96"]["counters"] = {k: c4["stats"][k] for k in ("own_pairs", "candidates", "verified",
+                                                                     "bound_violations")}
     print(json.dumps(line), flush=True)
 
 

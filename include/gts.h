@@ -9,7 +9,7 @@
  *   MkNNQ(q, k) = k objects no farther from q than any other   (Definition 2)
  *
  * for the Euclidean metric on float32 vectors and the Levenshtein (edit)
- * metric on byte strings, with streamed insertions and deletions (Sec. 4.3).
+ * metric on byte strings, with streamed insertions and deletions (Sec. 4.4).
  *
  * Conventions for every call:
  *   - Plain pointers only.  Each gts_objects says whether its arrays live in
@@ -59,6 +59,21 @@ typedef int32_t gts_status;
 #define GTS_MODE_BATCHED 0  /* whole batch through shared tiles (default)      */
 #define GTS_MODE_PLAIN 1    /* one query per workgroup, every stage fused      */
 
+/* Arithmetic of L2 candidate selection in the batched form (the paper fixes
+ * no precision; answers are the same under both, the float32 distances of
+ * the answers are computed the same way):
+ *   GTS_BF16_GUARDED: bf16 MFMA tiles with float32 accumulation estimate
+ *     d^2 for every (query, object) pair of the surviving leaves; a proven
+ *     bound on the estimate's error decides which pairs cannot be answers,
+ *     and only the others get a float32 direct-difference distance.
+ *   GTS_FP32: Lemma 1 on the float32 pivot table (every object of the
+ *     surviving leaves, all global pivots) selects the candidates, and every
+ *     candidate gets its float32 direct-difference distance.
+ * Edit distance is integer throughout and ignores the setting. */
+#define GTS_PRECISION_DEFAULT 0  /* the index's setting (build: GTS_BF16_GUARDED) */
+#define GTS_BF16_GUARDED 1
+#define GTS_FP32 2
+
 /* A set of objects (or queries).
  *   L2:   vecs = [n][dim] float32 row-major, finite values.
  *   EDIT: chars = concatenated bytes, offsets = [n + 1] int64 start offsets
@@ -82,9 +97,16 @@ typedef struct {
                                 rule h = ceil(log_F(n + 1)) - 2 (Sec. 4.2)      */
     int32_t max_strlen;      /* EDIT: longest accepted string (default 255)    */
     int64_t cache_limit;     /* streamed inserts held in the cache list before
-                                the index is rebuilt (Sec. 4.3); default 4096  */
+                                the index is rebuilt (Sec. 4.4); default 4096  */
     int64_t mem_budget_bytes;/* device bytes for a query batch's intermediate
                                 data; 0 = 1/4 of free device memory            */
+    int32_t precision;       /* GTS_BF16_GUARDED (0 = this) or GTS_FP32         */
+    int32_t reserved0;       /* must be 0                                       */
+    const char *tune_cache;  /* NULL, or a text file of tuned launch settings:
+                                read at build, rewritten when the index's
+                                default query context finishes tuning, keyed
+                                by device, metric, dimension, pivots, fanout
+                                and batch size (answers never depend on it)  */
 } gts_build_opts;
 
 /* Per-call query options (NULL -> defaults). */
@@ -92,6 +114,9 @@ typedef struct {
     int32_t mode;            /* GTS_MODE_BATCHED or GTS_MODE_PLAIN             */
     int32_t result_location; /* GTS_HOST or GTS_DEVICE; default: the queries'  */
     int64_t mem_budget_bytes;/* overrides the index's budget when > 0          */
+    int32_t precision;       /* GTS_PRECISION_DEFAULT, GTS_BF16_GUARDED or
+                                GTS_FP32 (batched L2; overrides the index's)   */
+    int32_t reserved0;       /* must be 0                                       */
 } gts_query_opts;
 
 /* Answers in CSR form: the answer of query i is entries
@@ -126,6 +151,20 @@ typedef struct {
     int64_t tuning;          /* 1 while the query context is still trying
                                 settings (answers are exact either way)        */
     int64_t bound_evals;     /* exact distances computed for the kNN bounds   */
+    int64_t wide_queries;    /* queries whose candidates one whole workgroup
+                                verified (L2: more than 1024; edit: more than
+                                its LDS sort holds)                            */
+    int64_t bound_violations;/* L2, bf16 selection: rechecked candidates whose
+                                float32 distance fell outside the interval the
+                                proven error bound gave them (always 0 unless
+                                the bound is wrong)                            */
+    int64_t own_pairs;       /* batched: (query, object) pairs inside the
+                                surviving (query, leaf) pairs -- the method's
+                                own filtering work, before the tile rounding  */
+    int64_t filter_objects;  /* objects read by the pivot-table object filters
+                                (once per surviving (leaf, 64-query tile))     */
+    int64_t sweep_grid_per_cu; /* L2 bf16 path: MFMA sweep workgroups per CU
+                                in this call (the second tuned knob)           */
 } gts_stats;
 
 #define GTS_STAGE_PREP 0     /* query -> pivot distances, query tiles          */
@@ -151,7 +190,7 @@ typedef struct {
 typedef struct gts_index gts_index;
 
 /* Build an index over `objs` (ids 0..n-1 in input order).
- * Follows the paper's construction (Sec. 4.2, Algorithms 1-3) with global
+ * Follows the paper's construction (Sec. 4.3, Algorithms 1-3) with global
  * pivots: num_pivots pivots by farthest-first traversal (the first one
  * seeded) and every object's distance to every pivot in a pivot table; a
  * balanced tree of `fanout`-way nodes over leaves of near-equal size, the
@@ -188,14 +227,14 @@ gts_status gts_knn_query(gts_index *idx, const gts_objects *Q, const int32_t *k,
 gts_status gts_search(gts_index *idx, const gts_objects *Q, const float *radius,
                       const int32_t *k, const gts_query_opts *opts, gts_result *out);
 
-/* Streamed insertion (Sec. 4.3): the objects join the cache list, which every
+/* Streamed insertion (Sec. 4.4): the objects join the cache list, which every
  * query scans by brute force; when the cache holds more than cache_limit
  * objects the index is rebuilt over all live objects.  out_ids (host,
  * [objs->n], may be NULL) receives the new ids, which increase and are never
  * reused.  Ids stay below 2^31. */
 gts_status gts_insert(gts_index *idx, const gts_objects *objs, int64_t *out_ids);
 
-/* Streamed deletion (Sec. 4.3): an id in the cache list is removed from it;
+/* Streamed deletion (Sec. 4.4): an id in the cache list is removed from it;
  * an id in the tree is marked and skipped by every later query.  ids: host
  * array [n].  Unknown or already deleted ids are ignored; *n_deleted (may be
  * NULL) receives the number actually deleted. */

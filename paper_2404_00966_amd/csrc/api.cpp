@@ -65,6 +65,14 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         idx->stream = static_cast<hipStream_t>(hip_stream);
         idx->ctx.stream = idx->stream;
         if (opts) idx->opts = *opts;
+        GTS_CHECK(idx->opts.precision == GTS_PRECISION_DEFAULT || idx->opts.precision == GTS_BF16_GUARDED ||
+                      idx->opts.precision == GTS_FP32,
+                  GTS_EINVAL, "precision must be GTS_BF16_GUARDED or GTS_FP32");
+        GTS_CHECK(idx->opts.reserved0 == 0, GTS_EINVAL, "gts_build_opts.reserved0 must be 0");
+        if (idx->opts.precision == GTS_PRECISION_DEFAULT) idx->opts.precision = GTS_BF16_GUARDED;
+        // the path is borrowed: keep a copy
+        if (idx->opts.tune_cache) idx->tune_cache = idx->opts.tune_cache;
+        idx->opts.tune_cache = nullptr;
         if (idx->opts.max_strlen <= 0 || idx->opts.max_strlen > kMaxStrlen) idx->opts.max_strlen = kMaxStrlen;
         if (idx->opts.cache_limit <= 0) idx->opts.cache_limit = 4096;
         if (idx->opts.mem_budget_bytes <= 0) {
@@ -83,6 +91,7 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         idx->cache_host.metric = metric;
         idx->cache_host.dim = h.dim;
         build_tree(idx.get(), h);
+        tune_cache_load(idx.get());
         *out = idx.release();
     });
 }

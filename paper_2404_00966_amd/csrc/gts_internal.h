@@ -11,6 +11,8 @@
 #include <stdexcept>
 #include <string>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gts.h"
@@ -207,40 +209,81 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
 // the searches issued on one stream.  An index has a default context on its
 // own stream; more contexts let searches of one index run concurrently (the
 // index data is only read by a search).
-// Online tuning of the L2 kNN bound window (objects per query whose exact
-// distances bound the k-th distance): a small window is cheap but gives a
-// loose bound and more candidates downstream, a large one the reverse.  The
-// context tries each setting on a few batches, keeps the one with the lowest
-// time per query, and tries again when the batch size moves by more than 4x.
-// Answers do not depend on the setting.
-struct BoundTuner {
-    static constexpr int kChoices = 4;
-    static constexpr int kTrials = 2;         // batches per setting
-    static constexpr int kWindow[kChoices] = {128, 256, 512, 1024};
-    int trial = 0;                            // next trial; kChoices*kTrials: done
-    double ms_per_q[kChoices] = {};
-    int best = 2;
-    int64_t tuned_nq = 0;
-    int pick(int64_t nq)
+// Online tuning of two launch settings of the batched L2 path, which trade
+// work between stages and never change answers:
+//   - the kNN bound window (objects per query whose exact distances bound
+//     the k-th distance): small is cheap but leaves a loose bound and more
+//     candidates downstream, large the reverse;
+//   - the MFMA sweep's persistent grid (workgroups per CU): more overlaps
+//     memory latency, fewer keeps the work-stealing tail short.
+// A context tries each window (kNN batches only) on a few batches with the
+// default grid, then each grid with the best window, and keeps the setting
+// with the lowest time per query.  Settings are remembered per shape key
+// (device, metric, dimension, pivots, fanout, log2 of the batch size, kNN
+// present) in the index's table, which a tune-cache file can preload and
+// which is written back when a key finishes tuning.
+struct TuneSetting {
+    int window = 1;                            // index into LaunchTuner::kWindow
+    int grid = 1;                              // index into LaunchTuner::kGridPerCu
+};
+struct LaunchTuner {
+    static constexpr int kWindows = 4;
+    static constexpr int kGrids = 3;
+    static constexpr int kTrials = 2;          // batches per setting
+    static constexpr int kWindow[kWindows] = {128, 256, 512, 1024};
+    static constexpr int kGridPerCu[kGrids] = {1, 2, 4};
+    std::string key;                           // shape being tuned ("" = none)
+    bool knn = false;
+    int trial = 0;                             // trials done for `key`
+    double ms_per_q[kWindows + kGrids] = {};
+    TuneSetting best;
+    int total() const { return (knn ? kWindows * kTrials : 0) + kGrids * kTrials; }
+    bool tuning() const { return !key.empty() && trial < total(); }
+    // The setting of a call on shape `k`; *trying is set when it is a trial.
+    TuneSetting pick(const std::string &k, bool has_knn, const TuneSetting *known, bool *trying)
     {
-        if (trial >= kChoices * kTrials && (nq > 4 * tuned_nq || 4 * nq < tuned_nq)) {
+        *trying = false;
+        if (known && (key != k || !tuning())) return *known;
+        if (key != k) {
+            key = k;
+            knn = has_knn;
             trial = 0;
+            best = TuneSetting{};
             for (double &v : ms_per_q) v = 0.0;
         }
-        return trial < kChoices * kTrials ? trial % kChoices : best;
-    }
-    void record(int choice, int64_t nq, double ms)
-    {
-        if (trial >= kChoices * kTrials || choice != trial % kChoices) return;
-        ms_per_q[choice] += ms / (double)nq;
-        if (++trial == kChoices * kTrials) {
-            best = 0;
-            for (int c = 1; c < kChoices; c++)
-                if (ms_per_q[c] < ms_per_q[best]) best = c;
-            tuned_nq = nq;
+        if (!tuning()) return best;
+        *trying = true;
+        TuneSetting s = best;
+        const int wt = knn ? kWindows * kTrials : 0;
+        if (trial < wt) {
+            s.window = trial % kWindows;
+            s.grid = 1;
+        } else {
+            s.grid = (trial - wt) % kGrids;
         }
+        return s;
     }
-    bool tuning() const { return trial < kChoices * kTrials; }
+    // Time of the trial call; returns true when `key` has just finished.
+    bool record(double ms_per_query)
+    {
+        if (!tuning()) return false;
+        const int wt = knn ? kWindows * kTrials : 0;
+        if (trial < wt) ms_per_q[trial % kWindows] += ms_per_query;
+        else ms_per_q[kWindows + (trial - wt) % kGrids] += ms_per_query;
+        trial++;
+        if (knn && trial == wt) {
+            best.window = 0;
+            for (int c = 1; c < kWindows; c++)
+                if (ms_per_q[c] < ms_per_q[best.window]) best.window = c;
+        }
+        if (trial == total()) {
+            best.grid = 0;
+            for (int c = 1; c < kGrids; c++)
+                if (ms_per_q[kWindows + c] < ms_per_q[kWindows + best.grid]) best.grid = c;
+            return true;
+        }
+        return false;
+    }
 };
 
 struct QueryCtx {
@@ -251,7 +294,7 @@ struct QueryCtx {
     hipEvent_t ev[9] = {};
     bool timing = false;
     gts_stats stats{};
-    BoundTuner tuner;
+    LaunchTuner tuner;
     QueryCtx() = default;
     QueryCtx(const QueryCtx &) = delete;
     QueryCtx &operator=(const QueryCtx &) = delete;
@@ -278,6 +321,10 @@ struct QueryCtx {
         if (pin) (void)hipHostFree(pin);
     }
 };
+// Tune-cache file: lines "key window grid" (indexes into LaunchTuner's
+// tables); unreadable or malformed lines are ignored.
+void tune_cache_load(gts_index *idx);
+void tune_cache_store(gts_index *idx);
 // Run f, turning exceptions into a status and this thread's error text (the
 // wrapper of every C-ABI entry point).
 gts_status run_guarded(const std::function<void()> &f);
@@ -307,6 +354,9 @@ struct gts_index {
     int64_t rebuilds = 0;
     int32_t num_pivots = 0, fanout = 0;
     gts_build_opts opts{};
+    std::string tune_cache;            // tuned-settings file ("" = none)
+    std::mutex tune_mu;                // guards `tuned` and the file
+    std::map<std::string, gts::TuneSetting> tuned;   // finished settings by shape key
     // Byte alphabet of every string stored so far (EDIT): lut[b] is the code
     // of byte b, or arows - 1 for a byte never stored (such a byte in a query
     // matches nothing).  Codes only grow with inserts; nothing stored depends

@@ -1,15 +1,19 @@
 // Index construction and streamed updates (host orchestration; the distance
 // work runs in GPU kernels).
 //
-// Construction follows Sec. 4.2.  m global pivots are chosen once by
-// farthest-first traversal (Algorithm 2's FFT rule, first pivot seeded) and
-// every object's distance to every one of them is kept in a pivot table.  The
-// tree is built layer by layer (Algorithm 1): each node picks its own pivots
-// among its objects (FFT again), orders its objects by nearest node pivot and
-// distance, and hands them out equal-count to its F children, the last child
-// taking the remainder (Algorithm 3).  Every node keeps the box [min, max] of
-// its objects' distances to every global pivot, which is what the query-time
-// filters test (Lemma 1 on all pivots at once).
+// Construction follows Sec. 4.3 with global pivots.  m pivots are chosen once
+// by farthest-first traversal (the FFT rule of Algorithm 2, first pivot
+// seeded) and every object's distance to every one of them is kept in a
+// pivot table.  The tree has the paper's shape (fanout F, equal-count leaves
+// from the leaf size or the height rule of Sec. 4.2), but the order of the
+// objects comes from K farthest-first centres run on the GPU: every object
+// joins the cell of its nearest centre, cells follow a nearest-neighbour
+// chain of their centres, objects inside a cell follow their distance to the
+// centre, and each equal-count leaf boundary moves to a cell boundary within
+// half a leaf.  A node covers its F children's runs.  Every node keeps the box
+// [min, max] of its objects' distances to every global pivot, which is what
+// the query-time filters test (Lemma 1 on all pivots at once); every leaf
+// keeps a pivot of its own and its covering radius.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -633,7 +637,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
 }
 
 // ---------------------------------------------------------------------------
-// Streamed updates (Sec. 4.3).
+// Streamed updates (Sec. 4.4).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -766,7 +770,7 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n)
     return done;
 }
 
-// Rebuild over every live object (Sec. 4.3: when the cache list exceeds its
+// Rebuild over every live object (Sec. 4.4: when the cache list exceeds its
 // limit the whole index is reconstructed from the index and the cache).
 void rebuild(gts_index *idx)
 {

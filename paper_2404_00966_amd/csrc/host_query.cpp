@@ -18,7 +18,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "gts_internal.h"
 #include "kernels.h"
@@ -54,8 +58,11 @@ template <class T> T *wsp(QueryCtx *cx, int slot, size_t count)
     return cx->ws[slot].as<T>();
 }
 
-// Small device counters: [0] candidate count, [1] item count, [2] work counter
+// Small device counters (32-bit words): [0, 1] the 64-bit candidate count,
+// [2] the edit leaf-item count, [4, 7) the sweep's work-list counts
 constexpr int kSmallWords = 16;
+constexpr int kSmallItems = 2;
+constexpr int kSmallSweep = 4;
 
 // Pinned host staging of one search call: device-to-host the permutation
 // (nq int32), the small counters, the group's segment offsets, counts and
@@ -220,6 +227,8 @@ struct Batch {
     int max_qlen = 0;          // longest query string (EDIT)
     float max_radius = 0.f;    // largest range radius
     int64_t ntiles_all = 0;    // query tiles of the whole batch
+    int precision = GTS_BF16_GUARDED;   // L2 candidate selection (batched form)
+    int sweep_grid_per_cu = 2;          // MFMA sweep workgroups per CU (tuned)
 };
 
 void rec(QueryCtx *cx, int i)
@@ -262,10 +271,14 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint32_t *small = wsp<uint32_t>(cx, W_SMALL, kSmallWords);
     unsigned long long *counters = cx->ws[W_COUNTERS].as<unsigned long long>();
     k::fill_u32(small, kSmallWords, 0u, st);
+    k::CandCount *ccount = reinterpret_cast<k::CandCount *>(small);
     k::Cand *cands = wsp<k::Cand>(cx, W_CANDS, cap);
     const uint32_t *tomb = d.tomb.as<uint32_t>();
 
     const bool plain = b.mode == GTS_MODE_PLAIN || (l2 && d.dim > kMaxMfmaDim);
+    // float32 selection: Lemma 1 on the pivot table instead of bf16 tiles
+    const bool sel32 = l2 && !plain && b.precision == GTS_FP32;
+    int64_t n_wide = 0;
     rec(cx, 2);
     if (plain) {
         const int grid = (int)std::min<int64_t>(ng, 1024);
@@ -278,7 +291,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         pa.tomb = tomb;
         pa.ids = d.ids.as<uint32_t>();
         pa.out = cands;
-        pa.out_count = small + 0;
+        pa.out_count = ccount;
         pa.out_cap = cap;
         pa.counters = counters;
         pa.delta = (float)((d.dim + 8) * 5.9604645e-8);
@@ -303,34 +316,42 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             k::edit_leaf_ball(oe, qe, qlen, t.leaf_first.as<int32_t>(), d.leafR.as<float>(), d.leaf_cell.as<int32_t>(),
                               d.cell_leaf.as<int32_t>(), d.n_centres,
                               cx->ws[W_QCELLS].as<int32_t>() + q0 * k::kQueryCells, cx->ws[W_QCNT].as<int32_t>() + q0,
-                              T, ng, ntiles, b.max_qlen, mask, items, small + 1, item_cap, t.n_leaves, st);
+                              T, ng, ntiles, b.max_qlen, mask, items, small + kSmallItems, item_cap, t.n_leaves, st);
         }
         if (l2 && d.lpad > 0)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
-                         d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, st);
+                         d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, t.leaf_cnt.as<int32_t>(), counters, st);
         k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
                        d.slab_leaf_hi.as<int32_t>(), d.n_slabs};
         k::SweepWork sw{};
-        if (l2) {
+        if (sel32) {
+            // the (leaf, tile) work list of the float32 object filter
+            items = wsp<int32_t>(cx, W_ITEMS, (size_t)item_cap * 2);
+            k::mask_items(mask, t.n_leaves, ntiles, items, small + kSmallItems, item_cap, st);
+        } else if (l2) {
             // the sweep's work list (timed with the node stage, so that the
             // candidate stage is the MFMA sweep alone)
             const int64_t pairs = d.n_slabs * ntiles;
             const int64_t nitems = d.n_slabs * ((ntiles + k::kSweepItemTiles - 1) / k::kSweepItemTiles);
             sw = k::SweepWork{wsp<int32_t>(cx, W_PAIR_TILE, pairs), wsp<uint64_t>(cx, W_PAIR_MASK, pairs),
-                              wsp<int4>(cx, W_SWEEP_ITEMS, nitems), small + 2};
+                              wsp<int4>(cx, W_SWEEP_ITEMS, nitems), small + kSmallSweep};
             k::slab_items(sv, mask, ntiles, sw, st);
         }
         rec(cx, 3);
-        if (l2) {
+        if (sel32) {
+            k::l2_objfilter(tv, items, small + kSmallItems, item_cap, mask, ntiles, QP, thr, ng, d.PT.as<float>(), d.n,
+                            tomb, cands, ccount, cap, counters, st);
+        } else if (l2) {
             int dev = 0, cus = 256;
             GTS_HIP(hipGetDevice(&dev));
             GTS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
             const float *tqe = cx->ws[W_TQE].as<float>() + q0;
-            k::mfma_sweep(ov, sv, qv, tqe, ng, ntiles, tomb, sw, cands, small + 0, cap, counters, cus * 2, st);
+            k::mfma_sweep(ov, sv, qv, tqe, ng, ntiles, tomb, sw, cands, ccount, cap, counters,
+                          cus * b.sweep_grid_per_cu, st);
         } else {
             int32_t *qlen = cx->ws[W_QLEN].as<int32_t>() + q0;
-            k::edit_objfilter(tv, items, small + 1, item_cap, mask, ntiles, QP, thr, qlen, ng, d.PTa.as<uint8_t>(),
-                              d.soff.as<int32_t>(), tomb, cands, small + 0, cap, st);
+            k::edit_objfilter(tv, items, small + kSmallItems, item_cap, mask, ntiles, QP, thr, qlen, ng, d.PTa.as<uint8_t>(),
+                              d.soff.as<int32_t>(), tomb, cands, ccount, cap, counters, st);
         }
         rec(cx, 4);
     }
@@ -341,10 +362,10 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             // emission cutoff: radius (range) or the widened bound T (kNN)
             float *cut = cx->ws[W_CUT].as<float>() + q0;
             k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
-                             cut, cands, small + 0, cap, st);
+                             cut, cands, ccount, cap, st);
         } else {
             k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
-                               c.live.as<uint32_t>(), c.count, base, cands, small + 0, cap, st);
+                               c.live.as<uint32_t>(), c.count, base, cands, ccount, cap, st);
         }
     }
     // ---- group by query ----------------------------------------------------
@@ -356,28 +377,30 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     int64_t *qoff = wsp<int64_t>(cx, W_QOFF64, ng + 1);
     k::fill_u32(qcount, ng, 0u, st);
     k::fill_u32(cursor, ng, 0u, st);
-    k::group_hist(cands, small + 0, cap, qcount, st);
+    k::group_hist(cands, ccount, cap, qcount, st);
     k::scan_u32(qcount, ng, qoff, st);
     int64_t gcap = std::max<int64_t>((int64_t)(cx->ws[W_GROUPED].bytes / sizeof(k::Cand)),
                                      std::min<int64_t>(cap, (int64_t)1 << 20));
     k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, gcap);
-    k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, gcap, st);
+    k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, gcap, st);
     rec(cx, 5);
     uint32_t *h_small = reinterpret_cast<uint32_t *>(pin + pl.small);
     int64_t *h_qoff_pin = reinterpret_cast<int64_t *>(pin + pl.qoff);
     GTS_HIP(hipMemcpyAsync(h_small, small, kSmallWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
-    const int64_t ncand = h_small[0];
-    if (ncand > cap) return false;
-    if (!plain && !l2 && (int64_t)h_small[1] > t.n_leaves * ntiles) fail(GTS_EDEVICE, "item list overflow");
+    const uint64_t ncand_all = *reinterpret_cast<const uint64_t *>(h_small);
+    if (ncand_all > (uint64_t)cap) return false;
+    const int64_t ncand = (int64_t)ncand_all;
+    if (!plain && (!l2 || sel32) && (int64_t)h_small[kSmallItems] > t.n_leaves * ntiles)
+        fail(GTS_EDEVICE, "item list overflow");
     cx->stats.candidates += ncand;
-    cx->stats.leaf_pairs += plain ? 0 : (int64_t)h_small[1];
+    cx->stats.leaf_pairs += plain || l2 ? 0 : (int64_t)h_small[kSmallItems];
     const int64_t *h_qoff = h_qoff_pin;   // read in place (no fresh host pages per call)
     if (ncand > gcap) {
         grouped = wsp<k::Cand>(cx, W_GROUPED, ncand);
         k::fill_u32(cursor, ng, 0u, st);
-        k::group_scatter(cands, small + 0, cap, qoff, cursor, grouped, ncand, st);
+        k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, ncand, st);
     }
     // segments too long for LDS sort in power-of-two scratch runs; the lists
     // are written straight into the pinned staging
@@ -391,6 +414,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         const int64_t ns = h_qoff[q + 1] - h_qoff[q];
         big[q] = -1;
         if (ns > sort_cap) {
+            if (!l2) n_wide++;
             int64_t p = 1;
             while (p < ns) p <<= 1;
             big[q] = scratch_words;
@@ -416,7 +440,9 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         dblk = wsp<int32_t>(cx, W_BLKQ, n_blk);
         GTS_HIP(hipMemcpyAsync(dblk, blk_q, n_blk * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
-    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, st);
+    if (l2) n_wide += n_blk;
+    cx->stats.wide_queries += n_wide;
+    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, !plain && !sel32, st);
     else k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
@@ -465,11 +491,79 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
 
 }  // namespace
 
+namespace {
+
+// "arch/cus|metric|dim|pivots|fanout|log2(nq)|knn": the shape a tuned
+// setting belongs to
+std::string tune_key(const gts_index *idx, int64_t nq, bool knn)
+{
+    static std::mutex mu;
+    static std::map<int, std::string> arch;
+    int dev = 0;
+    GTS_HIP(hipGetDevice(&dev));
+    std::string a;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = arch.find(dev);
+        if (it == arch.end()) {
+            hipDeviceProp_t p;
+            GTS_HIP(hipGetDeviceProperties(&p, dev));
+            std::string name = p.gcnArchName;
+            name = name.substr(0, name.find(':'));
+            it = arch.emplace(dev, name + "/" + std::to_string(p.multiProcessorCount)).first;
+        }
+        a = it->second;
+    }
+    int lg = 0;
+    while (((int64_t)1 << (lg + 1)) <= nq) lg++;
+    const IndexData &d = idx->data;
+    return a + "|" + std::to_string(d.metric) + "|" + std::to_string(d.dim) + "|" + std::to_string(d.m) + "|" +
+           std::to_string(d.tree.fanout) + "|" + std::to_string(lg) + "|" + (knn ? "1" : "0");
+}
+
+}  // namespace
+
+void tune_cache_load(gts_index *idx)
+{
+    if (idx->tune_cache.empty()) return;
+    FILE *f = std::fopen(idx->tune_cache.c_str(), "r");
+    if (!f) return;
+    char key[512];
+    int w = 0, g = 0;
+    std::lock_guard<std::mutex> lk(idx->tune_mu);
+    while (std::fscanf(f, "%511s %d %d", key, &w, &g) == 3)
+        if (w >= 0 && w < LaunchTuner::kWindows && g >= 0 && g < LaunchTuner::kGrids)
+            idx->tuned[key] = TuneSetting{w, g};
+    std::fclose(f);
+}
+
+// (caller holds tune_mu)  Entries of other shapes already in the file are
+// kept; the file is replaced in one rename.
+void tune_cache_store(gts_index *idx)
+{
+    if (idx->tune_cache.empty()) return;
+    std::map<std::string, TuneSetting> all;
+    if (FILE *f = std::fopen(idx->tune_cache.c_str(), "r")) {
+        char key[512];
+        int w = 0, g = 0;
+        while (std::fscanf(f, "%511s %d %d", key, &w, &g) == 3)
+            if (w >= 0 && w < LaunchTuner::kWindows && g >= 0 && g < LaunchTuner::kGrids) all[key] = TuneSetting{w, g};
+        std::fclose(f);
+    }
+    for (const auto &e : idx->tuned) all[e.first] = e.second;
+    const std::string tmp = idx->tune_cache + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;   // an unwritable cache only loses the remembered settings
+    for (const auto &e : all) std::fprintf(f, "%s %d %d\n", e.first.c_str(), e.second.window, e.second.grid);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), idx->tune_cache.c_str());
+}
+
 void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *kin,
             const gts_query_opts *opts, gts_result *out)
 {
     const double t_start = now_ms();
-    int tune_choice = -1;   // the bound window tried in this call (L2 kNN)
+    bool tune_trial = false;   // this call tries a tuner setting
     GTS_CHECK(out != nullptr, GTS_EINVAL, "null result");
     GTS_CHECK(Q != nullptr, GTS_EINVAL, "null queries");
     hipStream_t st = cx->stream;
@@ -482,6 +576,31 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     GTS_CHECK(b.nq < ((int64_t)1 << 31), GTS_ENOTSUP, "too many queries in one call");
     b.mode = opts ? opts->mode : GTS_MODE_BATCHED;
     GTS_CHECK(b.mode == GTS_MODE_BATCHED || b.mode == GTS_MODE_PLAIN, GTS_EINVAL, "bad mode");
+    b.precision = opts && opts->precision != GTS_PRECISION_DEFAULT ? opts->precision : idx->opts.precision;
+    if (b.precision == GTS_PRECISION_DEFAULT) b.precision = GTS_BF16_GUARDED;
+    GTS_CHECK(b.precision == GTS_BF16_GUARDED || b.precision == GTS_FP32, GTS_EINVAL, "bad precision");
+    GTS_CHECK(!opts || opts->reserved0 == 0, GTS_EINVAL, "gts_query_opts.reserved0 must be 0");
+    // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
+    std::string tkey;
+    TuneSetting tset;
+    if (d.metric == GTS_L2_F32 && b.mode == GTS_MODE_BATCHED && b.precision == GTS_BF16_GUARDED && d.lpad > 0 &&
+        d.dim <= kMaxMfmaDim && b.nq > 0) {
+        bool knn = false;
+        for (int64_t q = 0; q < b.nq && !knn; q++) knn = kin && kin[q] > 0;
+        tkey = tune_key(idx, b.nq, knn);
+        TuneSetting known;
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(idx->tune_mu);
+            auto it = idx->tuned.find(tkey);
+            if (it != idx->tuned.end()) {
+                known = it->second;
+                have = true;
+            }
+        }
+        tset = cx->tuner.pick(tkey, knn, have ? &known : nullptr, &tune_trial);
+        b.sweep_grid_per_cu = LaunchTuner::kGridPerCu[tset.grid];
+    }
     const int rloc = opts && (opts->result_location == GTS_HOST || opts->result_location == GTS_DEVICE)
                          ? opts->result_location
                          : Q->location;
@@ -727,8 +846,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                 near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
                 k::leaf_near(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.lpad, d.ksteps, qv.Q16t, nq, near, st);
             }
-            tune_choice = cx->tuner.pick(nq);
-            const int window = BoundTuner::kWindow[tune_choice];
+            const int window = LaunchTuner::kWindow[tset.window];
             cx->stats.bound_window = window;
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
                           d.dp, qv.Q32, kq, nq, d.tomb.as<uint32_t>(), window, base, counters, st);
@@ -917,12 +1035,20 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     cx->stats.tile_pairs = (int64_t)hc[2];
     cx->stats.verified = (int64_t)hc[3];
     cx->stats.bound_evals = (int64_t)hc[4];
+    cx->stats.bound_violations = (int64_t)hc[k::CNT_BOUND_VIOL];
+    cx->stats.own_pairs = (int64_t)hc[k::CNT_OWN_PAIRS];
+    cx->stats.filter_objects = (int64_t)hc[k::CNT_FILTER_OBJS];
     cx->stats.results = out->total;
     for (int i = 0; i < 8; i++) cx->stats.ms_stage[i] = stage_ms[i];
     cx->stats.groups = (int64_t)groups.size();
     cx->stats.ms_total = now_ms() - t_start;
-    if (tune_choice >= 0) cx->tuner.record(tune_choice, nq, cx->stats.ms_total);
+    if (tune_trial && cx->tuner.record(cx->stats.ms_total / (double)nq)) {
+        std::lock_guard<std::mutex> lk(idx->tune_mu);
+        idx->tuned[tkey] = cx->tuner.best;
+        tune_cache_store(idx);
+    }
     cx->stats.tuning = cx->tuner.tuning() ? 1 : 0;
+    cx->stats.sweep_grid_per_cu = b.sweep_grid_per_cu;
 }
 
 void free_result(gts_result *r)

@@ -1,8 +1,8 @@
 // Build-time clustering that orders the objects before they are cut into
 // leaves.
 //
-// The centres come from farthest-first traversal (the selection rule the
-// method uses for pivots, Sec. 4.1, run to many more centres): centre j + 1 is
+// The centres come from farthest-first traversal (the pivot selection rule of
+// Algorithm 2, Sec. 4.3, run to many more centres): centre j + 1 is
 // the object farthest from centres 0..j.  One launch per centre; each launch
 // reads the previous argmax from device memory and leaves its own argmax
 // there, so the K launches run back to back without host round trips.

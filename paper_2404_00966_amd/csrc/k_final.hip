@@ -55,11 +55,10 @@ __device__ __forceinline__ int query_runs(int32_t q)
 // counts once however the producer interleaved them; the order inside a
 // query's group is free (verification sorts by (distance, id)).
 constexpr int kSortRuns = 16;
-__global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
+__global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, const CandCount *__restrict__ count,
                                                     int64_t cap, uint32_t *__restrict__ qcount)
 {
-    int64_t n = *count;
-    if (n > cap) n = cap;
+    int64_t n = (int64_t)(*count > (CandCount)cap ? (CandCount)cap : *count);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
         const int64_t i = b0 + dev::lane_id();
@@ -74,7 +73,7 @@ __global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, 
     }
 }
 
-void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st)
+void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, hipStream_t st)
 {
     hipLaunchKernelGGL(k_group_hist, dim3(2048), dim3(256), 0, st, c, count, cap, qcount);
     check_launch(__func__);
@@ -138,13 +137,12 @@ void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
     check_launch(__func__);
 }
 
-__global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ c, const uint32_t *__restrict__ count,
+__global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ c, const CandCount *__restrict__ count,
                                                        int64_t cap, const int64_t *__restrict__ qoff,
                                                        uint32_t *__restrict__ cursor, Cand *__restrict__ grouped,
                                                        int64_t grouped_cap)
 {
-    int64_t n = *count;
-    if (n > cap) n = cap;
+    int64_t n = (int64_t)(*count > (CandCount)cap ? (CandCount)cap : *count);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = dev::lane_id();
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
@@ -175,7 +173,7 @@ __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ 
     }
 }
 
-void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
+void group_scatter(const Cand *c, const CandCount *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
                    Cand *grouped, int64_t grouped_cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped,
@@ -240,13 +238,17 @@ struct RecheckCtx {
     float qnn, qerr, base, ub;
     int k;
     bool sel;                                // ub in force (kNN)
+    bool est;                                // candidates carry bf16 estimates
 };
 
 template <bool kShort, class Emit>
 __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View &o, const RecheckCtx &rc,
                                               float delta, float eps_a, float eps_b, float eps_c, const Cand *g,
-                                              int i0, int i1, int32_t *ring, long long *verified, Emit &emit)
+                                              int i0, int i1, int32_t *ring, long long *verified, long long *viol,
+                                              Emit &emit)
 {
+    // ring[0, kRing): positions; ring[kRing, 2 kRing): their bf16 estimates
+    uint32_t *ring_est = reinterpret_cast<uint32_t *>(ring + kRing);
     const int lane = threadIdx.x & 63, grp = lane >> 4, sl = lane & 15;
     const int nu = (i1 - i0 + 63) >> 6;
     int head = 0, tail = 0;                      // ring cursors (wave-uniform)
@@ -255,12 +257,14 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         int32_t p[4];
+        uint32_t ev[4];
         bool nd[4];
 #pragma unroll
         for (int uu = 0; uu < 4; uu++) {
             const int j = 4 * uu + grp;
             nd[uu] = j < cnt;
             p[uu] = nd[uu] ? ring[(head + j) & (kRing - 1)] : 0;
+            ev[uu] = nd[uu] && sl == 0 ? ring_est[(head + j) & (kRing - 1)] : 0u;
         }
         uint32_t idv[4];
         float acc[4];
@@ -309,6 +313,17 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             const bool mine = nd[uu] && sl == 0;
             const float d = sqrtf(acc[uu]);
             if (mine) (*verified)++;
+            if (mine && rc.est) {
+                // invariant of the bf16 selection: the exact distance lies in
+                // the candidate's interval (up to the float32 error of d)
+                Cand c;
+                c.q = 0;
+                c.pos = p[uu];
+                c.val = ev[uu];
+                float lo, hi;
+                l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                if (d < lo * (1.f - 2.f * delta) || d > hi * (1.f + 2.f * delta)) (*viol)++;
+            }
             emit(mine && (rc.k > 0 || d <= rc.base), ((uint64_t)__float_as_uint(d) << 32) | idv[uu]);
         }
     };
@@ -336,7 +351,10 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
         }
         emit(v && c.pos < 0, c.val);                 // known distance (cache list)
         const uint64_t m = dev::ballot(need);
-        if (need) ring[(tail + dev::lanes_below(m)) & (kRing - 1)] = c.pos;
+        if (need) {
+            ring[(tail + dev::lanes_below(m)) & (kRing - 1)] = c.pos;
+            ring_est[(tail + dev::lanes_below(m)) & (kRing - 1)] = (uint32_t)c.val;
+        }
         tail += __popcll(m);
         while (tail - head >= 16) {
             batch(16);
@@ -355,7 +373,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
 // (s_keys, kSortCapL2) or in the query's scratch run.
 template <bool kShort>
 __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
-                                float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring)
+                                float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring, bool est)
 {
     __shared__ int s_n;
     const int64_t seg0 = a.qoff[q];
@@ -374,7 +392,8 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     rc.base = a.base[q];
     rc.k = k;
     rc.ub = INFINITY;
-    rc.sel = k > 0 && ns > k && !big;
+    rc.est = est;
+    rc.sel = est && k > 0 && ns > k && !big;
     if (threadIdx.x == 0) s_n = 0;
     if (rc.sel) {
         for (int i = threadIdx.x; i < ns; i += blockDim.x) {
@@ -428,7 +447,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
 #pragma unroll
         for (int t = 0; t < 8; t++) rc.qr[t] = sl + 16 * t < o.dp ? rc.qrow[sl + 16 * t] : 0.f;
     }
-    long long verified = 0;
+    long long verified = 0, viol = 0;
     auto emit = [&](bool keep, uint64_t key) __attribute__((always_inline)) {
         const uint64_t m = dev::ballot(keep);
         if (m) {
@@ -441,10 +460,12 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     const int nw = (int)(blockDim.x >> 6);
     for (int c0 = wave * 64 * kChunk; c0 < ns; c0 += nw * 64 * kChunk)
         recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
-                              &verified, emit);
+                              &verified, &viol, emit);
     __syncthreads();
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
+    for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
     if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
+    if (lane == 0 && viol) count_add(a.counters, CNT_BOUND_VIOL, (unsigned long long)viol);
     const int nk = s_n;
     sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
@@ -484,7 +505,7 @@ __device__ void wave_bitonic_sort(uint64_t *a, int n)
 // LDS run and sorted there.
 template <bool kShort>
 __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
-                               float eps_b, float eps_c, int64_t q, uint64_t *keys, int32_t *ring)
+                               float eps_b, float eps_c, int64_t q, uint64_t *keys, int32_t *ring, bool est)
 {
     const int lane = threadIdx.x & 63;
     const int64_t seg0 = a.qoff[q];
@@ -498,7 +519,8 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
     rc.base = a.base[q];
     rc.k = k;
     rc.ub = INFINITY;
-    rc.sel = k > 0 && ns > k;
+    rc.est = est;
+    rc.sel = est && k > 0 && ns > k;
     if (rc.sel) {
         uint32_t hv[kChunk];
 #pragma unroll
@@ -531,16 +553,18 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 #pragma unroll
         for (int t = 0; t < 8; t++) rc.qr[t] = sl + 16 * t < o.dp ? rc.qrow[sl + 16 * t] : 0.f;
     }
-    long long verified = 0;
+    long long verified = 0, viol = 0;
     int nk = 0;
     auto emit = [&](bool keep, uint64_t key) __attribute__((always_inline)) {
         const uint64_t m = dev::ballot(keep);
         if (keep) keys[nk + dev::lanes_below(m)] = key;
         nk += __popcll(m);
     };
-    recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, emit);
+    recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, &viol, emit);
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
+    for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
     if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
+    if (lane == 0 && viol) count_add(a.counters, CNT_BOUND_VIOL, (unsigned long long)viol);
     const int P = dev::next_pow2(nk > 1 ? nk : 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -559,14 +583,14 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 template <bool kShort>
 __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
                                                    float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
-                                                   int n_blk)
+                                                   int n_blk, int est)
 {
     __shared__ uint64_t s_mem[kSortCapL2];
-    __shared__ int32_t s_ring[4][kRing];
+    __shared__ int32_t s_ring[4][2 * kRing];
     static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
     if ((int)blockIdx.x < n_blk) {
         verify_l2_block<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
-                                s_ring[threadIdx.x >> 6]);
+                                s_ring[threadIdx.x >> 6], est != 0);
         return;
     }
     // wave mode: past the workgroup-mode blocks (rounded up to 8), XCD x
@@ -579,11 +603,12 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     if (q >= a.nq) return;
     const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
     if (ns > kWaveSortCap) return;
-    verify_l2_wave<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave]);
+    verify_l2_wave<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
+                           est != 0);
 }
 
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               hipStream_t st)
+               bool est, hipStream_t st)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
@@ -592,10 +617,10 @@ void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float de
     const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
     if (o.dp <= 128)
         hipLaunchKernelGGL(k_verify_l2<true>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q,
-                           n_blk);
+                           n_blk, est ? 1 : 0);
     else
         hipLaunchKernelGGL(k_verify_l2<false>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c,
-                           blk_q, n_blk);
+                           blk_q, n_blk, est ? 1 : 0);
     check_launch(__func__);
 }
 

@@ -166,7 +166,9 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
                                                    int64_t n_leaves, int64_t ngroups, const uint4 *__restrict__ Q16t,
                                                    const float *__restrict__ qn, const float *__restrict__ qe,
                                                    const float *__restrict__ T, int64_t nq, int ntiles,
-                                                   uint64_t *__restrict__ leaf_mask, float eps_a, float eps_b)
+                                                   uint64_t *__restrict__ leaf_mask, float eps_a, float eps_b,
+                                                   const int32_t *__restrict__ leaf_cnt,
+                                                   unsigned long long *__restrict__ counters)
 {
     __shared__ uint16_t s_bits[4][64][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -240,16 +242,21 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
             }
     }
     __syncthreads();
+    unsigned long long own = 0;   // (query, object) pairs of the surviving (query, leaf) pairs
     if (live && my_leaf < n_leaves && box_m) {
         const uint64_t m = (uint64_t)s_bits[wave][lane][0] | ((uint64_t)s_bits[wave][lane][1] << 16) |
                            ((uint64_t)s_bits[wave][lane][2] << 32) | ((uint64_t)s_bits[wave][lane][3] << 48);
         leaf_mask[(size_t)my_leaf * ntiles + tile] = box_m & m;
+        own = (unsigned long long)__popcll(box_m & m) * (unsigned long long)leaf_cnt[my_leaf];
     }
+    for (int o2 = 32; o2 > 0; o2 >>= 1) own += __shfl_xor(own, o2, 64);
+    if (lane == 0 && own) count_add(counters, CNT_OWN_PAIRS, own);
 }
 
 void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
                int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
-               int ntiles, uint64_t *leaf_mask, hipStream_t st)
+               int ntiles, uint64_t *leaf_mask, const int32_t *leaf_cnt, unsigned long long *counters,
+               hipStream_t st)
 {
     if (nq == 0 || n_leaves == 0) return;
     require(ksteps >= 1 && ksteps <= 4, "leaf_ball: rows wider than 128 floats");
@@ -262,7 +269,7 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
 #define LB(KS)                                                                                                 \
     hipLaunchKernelGGL(k_leaf_ball<KS>, dim3(grid), dim3(256), 0, st, reinterpret_cast<const uint4 *>(PL16t), pln, \
                        ple, leafR, n_leaves, ngroups, reinterpret_cast<const uint4 *>(Q16t), qn, qe, T, nq, ntiles, \
-                       leaf_mask, eps_a, eps_b)
+                       leaf_mask, eps_a, eps_b, leaf_cnt, counters)
     switch (ksteps) {
     case 1: LB(1); break;
     case 2: LB(2); break;

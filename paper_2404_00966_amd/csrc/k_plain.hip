@@ -71,8 +71,8 @@ __device__ int32_t *tree_frontier(const TreeView &t, const float *s_qp, float th
 
 __device__ __forceinline__ void emit_verified(const PlainArgs &a, int64_t q, uint32_t dbits, uint32_t id)
 {
-    const uint32_t idx = atomicAdd(a.out_count, 1u);
-    if (idx < a.out_cap) {
+    const CandCount idx = atomicAdd(a.out_count, (CandCount)1);
+    if ((int64_t)idx < a.out_cap) {
         Cand cd;
         cd.q = (int32_t)q;
         cd.pos = -1;

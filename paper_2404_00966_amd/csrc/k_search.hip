@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     const float *__restrict__ slab_nmax, int64_t n, const uint32_t *__restrict__ tomb,
     const int32_t *__restrict__ pair_tile, const uint64_t *__restrict__ pair_mask, const int4 *__restrict__ items,
     const uint32_t *__restrict__ item_count, uint32_t *__restrict__ work, Cand *__restrict__ cands,
-    uint32_t *__restrict__ cand_count, int64_t cand_cap, float eps_a, float eps_b, float eps_c,
+    CandCount *__restrict__ cand_count, int64_t cand_cap, float eps_a, float eps_b, float eps_c,
     unsigned long long *__restrict__ counters)
 {
     constexpr int kRowsPerWave = 16 * RT;
@@ -423,8 +423,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
     auto flush = [&]() {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)nb);
+        CandCount base = 0;
+        if (lane == 0) base = atomicAdd(cand_count, (CandCount)nb);
         base = __shfl(base, 0, 64);
         // whole 16-byte records (one dwordx4 store per lane), so the flushed
         // run is written as full lines
@@ -561,8 +561,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma_sweep(
                     if (nb + tot > kCandBuf) flush();
                     if (tot > kCandBuf) {
                         // more than a buffer at once (at most 64 x 16): direct
-                        uint32_t base = 0;
-                        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)tot);
+                        CandCount base = 0;
+                        if (lane == 0) base = atomicAdd(cand_count, (CandCount)tot);
                         base = __shfl(base, 0, 64);
                         int j = 0;
 #pragma unroll
@@ -615,7 +615,7 @@ void slab_items(const SlabView &s, const uint64_t *leaf_mask, int ntiles, const 
 }
 
 void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
-                const uint32_t *tomb, const SweepWork &w, Cand *cands, uint32_t *cand_count, int64_t cand_cap,
+                const uint32_t *tomb, const SweepWork &w, Cand *cands, CandCount *cand_count, int64_t cand_cap,
                 unsigned long long *counters, int grid_blocks, hipStream_t st)
 {
     if (nq == 0 || s.n_slabs == 0) return;
@@ -659,9 +659,11 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
                                                         const uint8_t *__restrict__ PTa,
                                                         const int32_t *__restrict__ soff,
                                                         const uint32_t *__restrict__ tomb, Cand *__restrict__ cands,
-                                                        uint32_t *__restrict__ cand_count, int64_t cand_cap)
+                                                        CandCount *__restrict__ cand_count, int64_t cand_cap,
+                                                        unsigned long long *__restrict__ counters)
 {
     __shared__ int2 s_buf[4][kObjBuf];
+    unsigned long long staged = 0, own = 0;   // wave-uniform work counts
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int2 *buf = s_buf[wave];
@@ -669,8 +671,8 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
     auto flush = [&]() {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(cand_count, (uint32_t)nb);
+        CandCount base = 0;
+        if (lane == 0) base = atomicAdd(cand_count, (CandCount)nb);
         base = __shfl(base, 0, 64);
         for (int i = lane; i < nb; i += 64) {
             const int64_t idx = (int64_t)base + i;
@@ -695,6 +697,8 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
         if (mask == 0ull) continue;
         const int64_t q = (int64_t)tile * 64 + lane;
         const bool act = ((mask >> lane) & 1ull) && q < nq;
+        staged += (unsigned long long)leaf_cnt[leaf];
+        own += (unsigned long long)__popcll(dev::ballot(act)) * (unsigned long long)leaf_cnt[leaf];
         int qp[MP];
         int th = -1, ql = 0;
         if (act) {
@@ -748,8 +752,8 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
             if (total == 0) continue;
             if (nb + total > kObjBuf) flush();
             if (total > kObjBuf) {   // more than the buffer holds: straight to memory
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(cand_count, (uint32_t)total);
+                CandCount base = 0;
+                if (lane == 0) base = atomicAdd(cand_count, (CandCount)total);
                 base = __shfl(base, 0, 64);
                 int at = before;
                 for (uint64_t m2 = mine; m2; m2 &= m2 - 1ull, at++) {
@@ -771,19 +775,21 @@ __global__ __launch_bounds__(256) void k_edit_objfilter(const int32_t *__restric
         }
     }
     if (nb) flush();
+    if (lane == 0 && staged) count_add(counters, CNT_FILTER_OBJS, staged);
+    if (lane == 0 && own) count_add(counters, CNT_OWN_PAIRS, own);
 }
 
 void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,
                     const uint64_t *leaf_mask, int ntiles, const float *QP, const float *thr, const int32_t *qlen,
                     int64_t nq, const uint8_t *PTa, const int32_t *soff, const uint32_t *tomb, Cand *cands,
-                    uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
+                    CandCount *cand_count, int64_t cand_cap, unsigned long long *counters, hipStream_t st)
 {
     if (nq == 0) return;
     const unsigned blocks = 2048;
 #define OF(MP)                                                                                                  \
     hipLaunchKernelGGL(k_edit_objfilter<MP>, dim3(blocks), dim3(256), 0, st, items, item_count, item_cap,        \
                        leaf_mask, ntiles, t.leaf_first, t.leaf_cnt, QP, thr, qlen, nq, PTa, soff, tomb, cands, \
-                       cand_count, cand_cap)
+                       cand_count, cand_cap, counters)
     if (t.mpad == 8) OF(8);
     else if (t.mpad == 16) OF(16);
     else OF(32);
@@ -792,14 +798,14 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
 }
 
 // ---------------------------------------------------------------------------
-// Cache list (Sec. 4.3): brute force over every live cached object.
+// Cache list (Sec. 4.4): brute force over every live cached object.
 // ---------------------------------------------------------------------------
 // L2: 16 lanes per (query, slot) pair, float32 direct difference.
 // cut[q]: range radius, or for kNN the widened bound T (any summation order)
 __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp, const float *__restrict__ C32,
                                 const uint32_t *__restrict__ cids, const uint32_t *__restrict__ clive,
                                 int64_t ncache, const float *__restrict__ base, Cand *__restrict__ cands,
-                                uint32_t *__restrict__ cand_count, int64_t cand_cap)
+                                CandCount *__restrict__ cand_count, int64_t cand_cap)
 {
     const int64_t pair = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int sl = threadIdx.x & 15;
@@ -820,8 +826,8 @@ __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int d
     if (sl == 0 && inb && clive[c]) {
         const float d = sqrtf(acc);
         if (d <= base[q]) {
-            uint32_t idx = atomicAdd(cand_count, 1u);
-            if (idx < cand_cap) {
+            const CandCount idx = atomicAdd(cand_count, (CandCount)1);
+            if ((int64_t)idx < cand_cap) {
                 Cand cd;
                 cd.q = (int32_t)q;
                 cd.pos = -1;
@@ -833,7 +839,7 @@ __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int d
 }
 
 void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
-                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, uint32_t *cand_count,
+                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
                    int64_t cand_cap, hipStream_t st)
 {
     if (nq == 0 || ncache == 0) return;
@@ -847,7 +853,7 @@ void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const
 __global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const uint8_t *__restrict__ cchars, int cstride,
                                   const int32_t *__restrict__ clen, const uint32_t *__restrict__ cids,
                                   const uint32_t *__restrict__ clive, int64_t ncache, const float *__restrict__ base,
-                                  Cand *__restrict__ cands, uint32_t *__restrict__ cand_count, int64_t cand_cap)
+                                  Cand *__restrict__ cands, CandCount *__restrict__ cand_count, int64_t cand_cap)
 {
     const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pair >= nq * ncache) return;
@@ -859,8 +865,8 @@ __global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const ui
     if (abs(plen - tl) > cut) return;
     const int d = dev::myers_any(qv.peq + (size_t)q * o.rows * 4, plen, cchars + (size_t)c * cstride, tl, cut, o.lut);
     if (d <= cut) {
-        uint32_t idx = atomicAdd(cand_count, 1u);
-        if (idx < cand_cap) {
+        const CandCount idx = atomicAdd(cand_count, (CandCount)1);
+        if ((int64_t)idx < cand_cap) {
             Cand cd;
             cd.q = (int32_t)q;
             cd.pos = -1;
@@ -872,7 +878,7 @@ __global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const ui
 
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
                      const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
-                     const float *base, Cand *cands, uint32_t *cand_count, int64_t cand_cap, hipStream_t st)
+                     const float *base, Cand *cands, CandCount *cand_count, int64_t cand_cap, hipStream_t st)
 {
     if (nq == 0 || ncache == 0) return;
     const int64_t threads = nq * ncache;

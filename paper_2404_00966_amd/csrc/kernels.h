@@ -9,7 +9,16 @@ namespace gts {
 namespace k {
 
 // Slots of the device counters behind gts_stats.
-enum { CNT_NODE_TESTS = 0, CNT_LEAF_PAIRS = 1, CNT_TILE_PAIRS = 2, CNT_VERIFIED = 3, CNT_BOUND_EVALS = 4 };
+enum {
+    CNT_NODE_TESTS = 0,
+    CNT_LEAF_PAIRS = 1,
+    CNT_TILE_PAIRS = 2,
+    CNT_VERIFIED = 3,
+    CNT_BOUND_EVALS = 4,
+    CNT_BOUND_VIOL = 5,    // rechecked L2 candidates whose exact distance left their bf16 interval (must stay 0)
+    CNT_OWN_PAIRS = 6,     // (query, object) pairs of the surviving (query, leaf) pairs (batched)
+    CNT_FILTER_OBJS = 7    // objects staged by the pivot-table object filters (one read per (leaf, tile) item)
+};
 constexpr int kCounters = 8;
 // Each counter is striped over kStripes words a cache line apart: a
 // workgroup adds to stripe blockIdx.x % kStripes, so thousands of
@@ -39,6 +48,14 @@ struct alignas(16) Cand {
     uint64_t val;
 };
 static_assert(sizeof(Cand) == 16, "a candidate is one 16-byte record");
+
+// Candidate slots are reserved with one 64-bit atomic add per wave.  Every
+// attempt counts, also past the buffer's capacity (only slots below it are
+// written), so the count that reaches the host is the number of candidates
+// the group produced: more than the capacity means "split and run again".
+// With 32 bits a group making 2^32 or more attempts would wrap and look as
+// if it fit.
+using CandCount = unsigned long long;
 
 // ---- preparation (k_prep.hip) ---------------------------------------------
 void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, int stride, int ksteps,
@@ -129,7 +146,7 @@ struct SweepWork {
 // The sweep's work list from the leaf masks (resets w.counts).
 void slab_items(const SlabView &s, const uint64_t *leaf_mask, int ntiles, const SweepWork &w, hipStream_t st);
 void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const float *tqe, int64_t nq, int ntiles,
-                const uint32_t *tomb, const SweepWork &w, Cand *cands, uint32_t *cand_count, int64_t cand_cap,
+                const uint32_t *tomb, const SweepWork &w, Cand *cands, CandCount *cand_count, int64_t cand_cap,
                 unsigned long long *counters, int grid_blocks, hipStream_t st);
 
 // Edit-distance object filtering over (leaf, tile) items: length and pivot
@@ -137,15 +154,26 @@ void mfma_sweep(const L2View &o, const SlabView &s, const QueryL2 &qv, const flo
 void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,
                     const uint64_t *leaf_mask, int ntiles, const float *QP, const float *thr, const int32_t *qlen,
                     int64_t nq, const uint8_t *PTa, const int32_t *soff, const uint32_t *tomb, Cand *cands,
-                    uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+                    CandCount *cand_count, int64_t cand_cap, unsigned long long *counters, hipStream_t st);
+
+// ---- float32 L2 selection (k_filter32.hip) ---------------------------------
+// (leaf, tile) pairs whose mask keeps a query, leaf-major, as int32 pairs.
+void mask_items(const uint64_t *leaf_mask, int64_t n_leaves, int ntiles, int32_t *items, uint32_t *item_count,
+                int64_t item_cap, hipStream_t st);
+// Lemma 1 over the float32 pivot table PT[mpad][n] for every object of the
+// listed (leaf, tile) items; candidates carry no estimate (val = 0).
+void l2_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_count, int64_t item_cap,
+                  const uint64_t *leaf_mask, int ntiles, const float *QP, const float *thr, int64_t nq, const float *PT,
+                  int64_t n, const uint32_t *tomb, Cand *cands, CandCount *cand_count, int64_t cand_cap,
+                  unsigned long long *counters, hipStream_t st);
 
 // Brute-force scan of the cache list; emits verified entries with d <= base.
 void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
-                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, uint32_t *cand_count,
+                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
                    int64_t cand_cap, hipStream_t st);
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
                      const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
-                     const float *base, Cand *cands, uint32_t *cand_count, int64_t cand_cap, hipStream_t st);
+                     const float *base, Cand *cands, CandCount *cand_count, int64_t cand_cap, hipStream_t st);
 // Largest distance from each leaf's first object to the leaf's objects.
 void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_t *leaf_cnt, int64_t n_leaves,
                       float *leafR, hipStream_t st);
@@ -217,11 +245,11 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
                     int64_t n_leaves, hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
-void group_hist(const Cand *c, const uint32_t *count, int64_t cap, uint32_t *qcount, hipStream_t st);
+void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, hipStream_t st);
 void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st);  // out[n+1]
 // Writes only entries below grouped_cap (a larger candidate count is
 // scattered again into a larger buffer).
-void group_scatter(const Cand *c, const uint32_t *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
+void group_scatter(const Cand *c, const CandCount *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
                    Cand *grouped, int64_t grouped_cap, hipStream_t st);
 
 struct VerifyArgs {
@@ -238,8 +266,11 @@ struct VerifyArgs {
     unsigned long long *counters;
 };
 // blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
+// est: the tree-position candidates carry bf16 estimates of d^2 (the bf16
+// selection); without them every candidate is rechecked and kept for the
+// final (distance, id) cut.
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               hipStream_t st);
+               bool est, hipStream_t st);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
@@ -276,7 +307,8 @@ void home_sort(const int32_t *home, int stride, int64_t nq, int64_t n_keys, uint
                int32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t st);
 void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const float *leafR, int64_t n_leaves,
                int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
-               int ntiles, uint64_t *leaf_mask, hipStream_t st);
+               int ntiles, uint64_t *leaf_mask, const int32_t *leaf_cnt, unsigned long long *counters,
+               hipStream_t st);
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
                 unsigned long long *counters, hipStream_t st);
@@ -297,7 +329,7 @@ struct PlainArgs {
     const uint32_t *tomb;
     const uint32_t *ids;       // [n] id per position
     Cand *out;
-    uint32_t *out_count;
+    CandCount *out_count;     // 64-bit reservation counter (attempts may exceed 2^32)
     int64_t out_cap;
     unsigned long long *counters;
     float delta, pt_max;

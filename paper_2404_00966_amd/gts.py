@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgts.so")
 L2_F32, EDIT_U8 = 1, 2
 HOST, DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
+PRECISION_DEFAULT, BF16_GUARDED, FP32 = 0, 1, 2
 STAGES = ("prep", "bound", "nodes", "cands", "group", "verify", "output", "plain")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
@@ -38,11 +39,13 @@ class _Objects(C.Structure):
 
 class _BuildOpts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("leaf_size", C.c_int32), ("max_strlen", C.c_int32),
-                ("cache_limit", C.c_int64), ("mem_budget_bytes", C.c_int64)]
+                ("cache_limit", C.c_int64), ("mem_budget_bytes", C.c_int64), ("precision", C.c_int32),
+                ("reserved0", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 class _QueryOpts(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("result_location", C.c_int32), ("mem_budget_bytes", C.c_int64)]
+    _fields_ = [("mode", C.c_int32), ("result_location", C.c_int32), ("mem_budget_bytes", C.c_int64),
+                ("precision", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -56,7 +59,8 @@ class _Stats(C.Structure):
                 ("tile_pairs", C.c_int64), ("candidates", C.c_int64), ("verified", C.c_int64),
                 ("results", C.c_int64), ("ms_total", C.c_double), ("ms_stage", C.c_double * 8),
                 ("groups", C.c_int64), ("bound_window", C.c_int64), ("tuning", C.c_int64),
-                ("bound_evals", C.c_int64)]
+                ("bound_evals", C.c_int64), ("wide_queries", C.c_int64), ("bound_violations", C.c_int64),
+                ("own_pairs", C.c_int64), ("filter_objects", C.c_int64), ("sweep_grid_per_cu", C.c_int64)]
 
 
 class _Info(C.Structure):
@@ -203,12 +207,13 @@ class Index:
     """A GTS index in GPU memory (see include/gts.h for the semantics)."""
 
     def __init__(self, objects, metric=L2_F32, num_pivots=8, fanout=8, leaf_size=0, seed=0, cache_limit=0,
-                 mem_budget_bytes=0, max_strlen=0, stream=None):
+                 mem_budget_bytes=0, max_strlen=0, stream=None, precision=PRECISION_DEFAULT, tune_cache=None):
         L = library()
         self.metric = metric
         keep = _Keep()
         o = _objects(objects, metric, keep)
-        opts = _BuildOpts(seed, leaf_size, max_strlen, cache_limit, mem_budget_bytes)
+        opts = _BuildOpts(seed, leaf_size, max_strlen, cache_limit, mem_budget_bytes, precision, 0,
+                          None if tune_cache is None else os.fsencode(tune_cache))
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self._stream = stream
@@ -229,7 +234,8 @@ class Index:
             pass
 
     # -- queries ------------------------------------------------------------
-    def search(self, queries, radius=None, k=None, mode=MODE_BATCHED, result="auto", mem_budget_bytes=0):
+    def search(self, queries, radius=None, k=None, mode=MODE_BATCHED, result="auto", mem_budget_bytes=0,
+               precision=PRECISION_DEFAULT):
         """Mixed batch: query i is kNN when k[i] > 0, else range with radius[i]."""
         L = library()
         keep = _Keep()
@@ -242,7 +248,7 @@ class Index:
             rloc = o.location
         else:
             rloc = DEVICE if result == "device" else HOST
-        qo = _QueryOpts(mode, rloc, mem_budget_bytes)
+        qo = _QueryOpts(mode, rloc, mem_budget_bytes, precision, 0)
         res = _Result()
         _check(L.gts_search(self._h, C.byref(o), None if r_arr is None else r_arr.ctypes.data,
                             None if k_arr is None else k_arr.ctypes.data, C.byref(qo), C.byref(res)))

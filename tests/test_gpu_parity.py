@@ -332,3 +332,104 @@ def test_empty_batch_and_errors(gts):
     with pytest.raises(gts.GtsError):
         gts.Index(_dev(X), gts.L2_F32, num_pivots=0, fanout=4)
     idx.close()
+
+
+def test_candidate_count_beyond_32_bits(gts):
+    """4,096 range queries whose radius admits every one of 2^20 objects make
+    exactly 2^32 candidate reservations in the first group: a 32-bit count
+    would wrap to 0 and pass the budget check with empty answers.  The
+    64-bit count sees the overflow, the batch splits down to 64-query tiles,
+    and a budget too small for one tile's candidates is an ENOMEM error."""
+    n, dim, nq = 1 << 20, 16, 4096
+    rng = np.random.default_rng(32)
+    X = rng.uniform(-1.0, 1.0, size=(n, dim)).astype(np.float32)
+    Q = rng.uniform(-1.0, 1.0, size=(nq, dim)).astype(np.float32)
+    _say("candidate count beyond 32 bits")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=4, fanout=16, leaf_size=256, seed=3)
+    with pytest.raises(gts.GtsError) as e:
+        idx.range(_dev(Q), 1.0e4, mem_budget_bytes=256 << 20)
+    assert e.value.status == gts.ENOMEM
+    # the same radius on a few queries fits and returns every object
+    res = idx.range(_dev(Q[:3]), 1.0e4).to_lists()
+    assert all(len(ids) == n for ids, _ in res)
+    idx.close()
+
+
+def test_edit_two_stage_budget_gives_same_answers(gts):
+    d = synth.dna_families(77, 60, 150, 60, 100, 0.05, 6)
+    chars, off = d["objects"]
+    qc, qo = d["queries"]
+    nq = len(qo) - 1
+    _say(f"edit two_stage_budget nq={nq}")
+    idx = gts.Index((_dev(chars), _dev(off)), gts.EDIT_U8, num_pivots=6, fanout=6, seed=5)
+    k = np.array([0, 5] * (nq // 2) + [0] * (nq % 2), np.int32)
+    radius = np.full(nq, 7.0, np.float32)
+    Qd = (_dev(qc), _dev(qo))
+    big = idx.search(Qd, radius=radius, k=k).to_lists()
+    assert idx.stats()["groups"] == 1
+    cands = idx.stats()["candidates"]
+    small = idx.search(Qd, radius=radius, k=k, mem_budget_bytes=40 * max(cands // 4, 1)).to_lists()
+    assert idx.stats()["groups"] > 1
+    idx.close()
+    for (a, b), (c, e) in zip(big, small):
+        assert np.array_equal(a, c) and np.array_equal(b, e)
+    objs = O.ObjectSet(strings=(chars, off))
+    for q in range(nq):
+        qs = O.ObjectSet(strings=(qc[qo[q]:qo[q + 1]], np.array([0, qo[q + 1] - qo[q]], np.int64)))
+        ref = O.knn_bf(objs, qs, 5)[0] if k[q] else O.range_bf(objs, qs, 7.0)[0]
+        check_exact([small[q]], [ref])
+
+
+def test_l2_planted_boundary_and_duplicates(gts):
+    """Objects planted at float64 distance r * (1 + s) from each query for
+    s in [-1e-6, 1e-6] (the bf16 estimates' error is far larger than those
+    gaps), exact copies of the queries and duplicated objects: the bf16
+    selection, the float32 selection and the plain form return identical
+    answers, the oracle agrees within its tolerance, and no rechecked
+    candidate left its bf16 interval."""
+    base = synth.gaussian_mixture(91, 20000, 64, 20, -5.0, 5.0, 1.0, 64, 0)
+    X0, Q = base["objects"], base["range_queries"]
+    rng = np.random.default_rng(92)
+    r = 6.0
+    planted = []
+    for q in Q.astype(np.float64):
+        for s in (-1e-6, -3e-7, -1e-7, 0.0, 1e-7, 3e-7, 1e-6):
+            for _ in range(3):
+                u = rng.standard_normal(64)
+                u /= np.linalg.norm(u)
+                planted.append(q + r * (1.0 + s) * u)
+        planted.append(q)                       # distance 0
+    P = np.asarray(planted).astype(np.float32)
+    X = np.concatenate([X0, P, P[:200], X0[:300]]).astype(np.float32)   # duplicates
+    _say(f"planted boundary n={len(X)}")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=8, fanout=8, leaf_size=64, seed=9)
+    Qd = _dev(np.concatenate([Q, Q]))
+    k = np.array([0] * len(Q) + [45] * len(Q), np.int32)
+    radius = np.full(2 * len(Q), r, np.float32)
+    a = idx.search(Qd, radius=radius, k=k).to_lists()
+    st = idx.stats()
+    assert st["bound_violations"] == 0 and st["verified"] > 0
+    b = idx.search(Qd, radius=radius, k=k, precision=gts.FP32).to_lists()
+    c = idx.search(Qd, radius=radius, k=k, mode=gts.MODE_PLAIN).to_lists()
+    idx.close()
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+        assert np.array_equal(x[0], z[0]) and np.array_equal(x[1], z[1])
+    objs = O.ObjectSet(vecs=X)
+    check_range(a[:len(Q)], O.range_bf(objs, O.ObjectSet(vecs=Q), r), X, Q, r)
+    check_knn(a[len(Q):], O.knn_bf(objs, O.ObjectSet(vecs=Q), 45), X, Q, 45)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_l2_precision_fp32_matches_oracle(gts, mode):
+    d = synth.gaussian_mixture(95, 8000, 48, 12, -5.0, 5.0, 1.0, 150, 150)
+    X = d["objects"]
+    Q = np.concatenate([d["range_queries"], d["knn_queries"]])
+    _say(f"precision fp32 mode={mode}")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=8, fanout=8, leaf_size=64, seed=2, precision=gts.FP32)
+    k = np.array([0] * 150 + [17] * 150, np.int32)
+    res = idx.search(_dev(Q), radius=np.full(300, 5.5, np.float32), k=k, mode=_mode(gts, mode)).to_lists()
+    idx.close()
+    objs = O.ObjectSet(vecs=X)
+    check_range(res[:150], O.range_bf(objs, O.ObjectSet(vecs=Q[:150]), 5.5), X, Q[:150], 5.5)
+    check_knn(res[150:], O.knn_bf(objs, O.ObjectSet(vecs=Q[150:]), 17), X, Q[150:], 17)

@@ -48,10 +48,10 @@ def test_struct_layouts_match_header_sizes():
 
     # sizes follow from the header's field lists (natural alignment, x86-64)
     assert ctypes.sizeof(gts._Objects) == 40
-    assert ctypes.sizeof(gts._BuildOpts) == 32
-    assert ctypes.sizeof(gts._QueryOpts) == 16
+    assert ctypes.sizeof(gts._BuildOpts) == 48
+    assert ctypes.sizeof(gts._QueryOpts) == 24
     assert ctypes.sizeof(gts._Result) == 64
-    assert ctypes.sizeof(gts._Stats) == 7 * 8 + 8 + 64 + 4 * 8
+    assert ctypes.sizeof(gts._Stats) == 7 * 8 + 8 + 64 + 9 * 8
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):

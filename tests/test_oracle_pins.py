@@ -203,7 +203,7 @@ def test_worked_example_structure():
 
 @pytest.mark.parametrize("n,nc", [(10, 2), (1, 2), (2, 2), (100, 3), (10_000, 8), (4097, 16), (255, 4)])
 def test_height_rule_and_node_count(n, nc):
-    # h = ceil(log_Nc(n + 1)) - 2, floored at 0 (Sec. 4.2); nodes = (Nc^(h+1)-1)/(Nc-1) (Sec. 4.4)
+    # h = ceil(log_Nc(n + 1)) - 2, floored at 0 (Sec. 4.2); nodes = (Nc^(h+1)-1)/(Nc-1) (Sec. 4.5)
     e = 0
     while nc ** e < n + 1:
         e += 1
