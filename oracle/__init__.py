@@ -23,7 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-L2, EDIT = 1, 2
+L2, EDIT, ANGULAR = 1, 2, 3
 
 
 class _Set(C.Structure):
@@ -52,6 +52,8 @@ def lib():
         L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_l2.restype = C.c_double
         L.orc_l2.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+        L.orc_angular.restype = C.c_double
+        L.orc_angular.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_edit.restype = C.c_int32
         L.orc_edit.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         L.orc_pair_distances.argtypes = [P(_Set), P(_Set), C.c_void_p]
@@ -92,7 +94,7 @@ class ObjectSet:
     (L2) or packed strings (chars uint8, offsets int64 [n+1]) (edit), with
     optional int64 external ids (default 0..n-1)."""
 
-    def __init__(self, vecs=None, strings=None, ids=None):
+    def __init__(self, vecs=None, strings=None, ids=None, angular=False):
         if (vecs is None) == (strings is None):
             raise ValueError("give exactly one of vecs / strings")
         s = _Set()
@@ -102,7 +104,7 @@ class ObjectSet:
             if v.ndim != 2:
                 raise ValueError("vecs must be 2-D")
             self._keep.append(v)
-            s.metric, s.dim, s.n = L2, v.shape[1], v.shape[0]
+            s.metric, s.dim, s.n = (ANGULAR if angular else L2), v.shape[1], v.shape[0]
             s.vecs = v.ctypes.data
         else:
             chars = np.ascontiguousarray(strings[0], dtype=np.uint8)
@@ -148,6 +150,14 @@ def l2(x, y) -> float:
     y = np.ascontiguousarray(y, dtype=np.float32)
     assert x.shape == y.shape
     return lib().orc_l2(_ptr(x), _ptr(y), x.shape[0])
+
+
+def angular(x, y) -> float:
+    """Angle between nonzero vectors x and y (radians, float64)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    assert x.shape == y.shape
+    return lib().orc_angular(_ptr(x), _ptr(y), x.shape[0])
 
 
 def edit(a: bytes, b: bytes) -> int:

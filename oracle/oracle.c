@@ -35,10 +35,10 @@
 /* Object sets                                                              */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_L2 = 1, ORC_EDIT = 2 };
+enum { ORC_L2 = 1, ORC_EDIT = 2, ORC_ANGULAR = 3 };
 
 typedef struct {
-    int32_t metric;          /* ORC_L2 or ORC_EDIT                           */
+    int32_t metric;          /* ORC_L2, ORC_EDIT or ORC_ANGULAR              */
     int32_t dim;             /* L2: vector length                            */
     int64_t n;               /* number of objects                            */
     const float *vecs;       /* L2: [n][dim] row-major                       */
@@ -56,7 +56,6 @@ typedef struct {
 
 static int64_t set_id(const orc_set *s, int64_t i) { return s->ids ? s->ids[i] : i; }
 
-/* Euclidean distance: sqrt(sum_i (x_i - y_i)^2) with every step in double. */
 /* Threads of the brute-force loops (timing on a given core count; results
  * do not depend on it).  Returns the count now in force. */
 int32_t orc_set_threads(int32_t n)
@@ -70,6 +69,7 @@ int32_t orc_set_threads(int32_t n)
 #endif
 }
 
+/* Euclidean distance: sqrt(sum_i (x_i - y_i)^2) with every step in double. */
 double orc_l2(const float *x, const float *y, int32_t dim)
 {
     double acc = 0.0;
@@ -78,6 +78,32 @@ double orc_l2(const float *x, const float *y, int32_t dim)
         acc += diff * diff;
     }
     return sqrt(acc);
+}
+
+/* Angular distance, the metric of cosine similarity on directions: the angle
+ * theta in [0, pi] between nonzero x and y, theta = arccos(x.y / (|x| |y|)).
+ * With the unit vectors u = x/|x| and v = y/|y|, |u - v| = 2 sin(theta/2) and
+ * |u + v| = 2 cos(theta/2), so theta = 2 atan2(|u - v|, |u + v|); every step
+ * in double.  (The half-angle form keeps full relative precision for angles
+ * near 0 and pi, where arccos of a rounded cosine does not.)  A zero vector
+ * has no direction: the result is NaN. */
+double orc_angular(const float *x, const float *y, int32_t dim)
+{
+    double nx = 0.0, ny = 0.0;
+    for (int32_t i = 0; i < dim; i++) {
+        nx += (double)x[i] * (double)x[i];
+        ny += (double)y[i] * (double)y[i];
+    }
+    nx = sqrt(nx);
+    ny = sqrt(ny);
+    if (nx == 0.0 || ny == 0.0) return NAN;
+    double dm = 0.0, dp = 0.0;
+    for (int32_t i = 0; i < dim; i++) {
+        const double u = (double)x[i] / nx, v = (double)y[i] / ny;
+        dm += (u - v) * (u - v);
+        dp += (u + v) * (u + v);
+    }
+    return 2.0 * atan2(sqrt(dm), sqrt(dp));
 }
 
 /* Levenshtein distance by the Wagner-Fischer table, kept as two rows.
@@ -111,6 +137,8 @@ static double set_dist(const orc_set *A, int64_t i, const orc_set *B, int64_t j)
 {
     if (A->metric == ORC_L2)
         return orc_l2(A->vecs + (size_t)i * A->dim, B->vecs + (size_t)j * B->dim, A->dim);
+    if (A->metric == ORC_ANGULAR)
+        return orc_angular(A->vecs + (size_t)i * A->dim, B->vecs + (size_t)j * B->dim, A->dim);
     return (double)orc_edit(A->chars + A->offsets[i], A->offsets[i + 1] - A->offsets[i],
                             B->chars + B->offsets[j], B->offsets[j + 1] - B->offsets[j]);
 }

@@ -54,6 +54,74 @@ def test_l2_axioms_random_triples():
 
 
 # --------------------------------------------------------------------------
+# Angular metric (cosine similarity on directions)
+# --------------------------------------------------------------------------
+
+def test_angular_closed_forms():
+    s3 = np.sqrt(3.0)
+    cases = [
+        ([1, 0], [0, 1], np.pi / 2),             # orthogonal
+        ([1, 0], [-2, 0], np.pi),                # opposite
+        ([1, 2, 3], [2, 4, 6], 0.0),             # same direction, other length
+        ([3, 0, 0], [3, 0, 0], 0.0),             # identical
+        ([1, 0], [1, 1], np.pi / 4),
+        ([1, 0], [0.5, s3 / 2], np.pi / 3),
+        ([1, 0], [-0.5, s3 / 2], 2 * np.pi / 3),
+        ([0, 0, 5], [1, 0, 0], np.pi / 2),
+    ]
+    for x, y, want in cases:
+        assert abs(O.angular(np.float32(x), np.float32(y)) - want) <= 1e-7, (x, y)
+    assert np.isnan(O.angular(np.zeros(3, np.float32), np.ones(3, np.float32)))
+
+
+def test_angular_matches_library_routines():
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((200, 24)).astype(np.float32)
+    Q = rng.standard_normal((15, 24)).astype(np.float32)
+    got = O.pair_distances(O.ObjectSet(vecs=X, angular=True), O.ObjectSet(vecs=Q, angular=True))
+    # scipy's cosine distance is 1 - cos(theta); random directions in 24-d are
+    # far from 0 and pi, where arccos is well conditioned
+    ref = np.arccos(1.0 - cdist(Q.astype(np.float64), X.astype(np.float64), "cosine"))
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+    # near-duplicate directions, where arccos of a rounded cosine fails: the
+    # small angle is the norm of the perpendicular offset over the length
+    x = np.zeros(8, np.float32)
+    x[0] = 1.0
+    y = x.copy()
+    y[1] = np.float32(1e-6)
+    want = np.arctan(np.float64(y[1]))          # tan(theta) = |offset| / |x|
+    assert abs(O.angular(x, y) - want) <= 1e-12 * want
+
+
+def test_angular_axioms_random_triples():
+    rng = np.random.default_rng(16)
+    for _ in range(300):
+        a, b, c = (rng.standard_normal(10).astype(np.float32) for _ in range(3))
+        ab, bc, ac = O.angular(a, b), O.angular(b, c), O.angular(a, c)
+        assert 0 <= ab <= np.pi and ab == O.angular(b, a)
+        assert O.angular(a, a) == 0.0
+        assert ac <= ab + bc + 1e-12
+        assert O.angular(a, np.float32(3.5) * a) < 1e-7      # scale invariance
+
+
+def test_angular_brute_force_and_tree_agree():
+    d = synth.gaussian_mixture(17, 3000, 12, 8, -3.0, 3.0, 1.0, 40, 40)
+    objs = O.ObjectSet(vecs=d["objects"], angular=True)
+    rq = O.ObjectSet(vecs=d["range_queries"], angular=True)
+    kq = O.ObjectSet(vecs=d["knn_queries"], angular=True)
+    D = O.pair_distances(objs, rq)
+    r = float(np.float32(np.sort(D.ravel())[1200]))
+    bf = O.range_bf(objs, rq, r)
+    for q in range(rq.n):
+        want = np.nonzero(D[q] <= r)[0]
+        order = np.lexsort((want, D[q][want]))
+        assert np.array_equal(bf[q][0], want[order])
+    tree = O.GtsTree(objs, nc=6, seed=3)
+    _same(tree.range(rq, r)[0], bf)
+    _same(tree.knn(kq, 9)[0], O.knn_bf(objs, kq, 9))
+
+
+# --------------------------------------------------------------------------
 # Edit metric
 # --------------------------------------------------------------------------
 
