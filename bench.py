@@ -92,10 +92,22 @@ def traffic(workload, kernel):
     global _TRAFFIC
     if _TRAFFIC is None:
         _TRAFFIC = profile_traffic()
-    e = _TRAFFIC.get(workload, {}).get(kernel)
+    e = _profile_entry(workload, kernel)
     if not e or e.get("source_sha16") != source_sha16(kernel):
         return None
     return e.get("bytes")
+
+
+def _profile_entry(workload, kernel):
+    """A profile's entry for `kernel`, from a summary whose workload label
+    (workloads joined by '+') names `workload`."""
+    global _TRAFFIC
+    if _TRAFFIC is None:
+        _TRAFFIC = profile_traffic()
+    for wl, ks in _TRAFFIC.items():
+        if workload in wl.split("+") and kernel in ks:
+            return ks[kernel]
+    return None
 
 
 def timed_steps(fn, steps, warmup):
@@ -172,7 +184,8 @@ def run_l2(args, gts, synth, torch, np):
     idx.set_timing(False)
     out = {"qps": nq * args.steps / total, "ms_per_step": ms, "per_step_ms": per, "build_s": build_s,
            "stats": st, "nq": nq, "r": r, "k": w["k"], "n": d["n"], "dim": w["dim"], "m": w["pivots"],
-           "tuned": {"bound_window": st["bound_window"], "tuning_calls": tune_calls},
+           "tuned": {"bound_window": st["bound_window"], "sweep_grid_per_cu": st["sweep_grid_per_cu"],
+                     "tuning_calls": tune_calls},
            "dist_evals_per_s": dist_evals(st, w["pivots"]) / (ms * 1e-3)}
     if args.side_steps > 0:
         # PCIe included: queries from pinned host memory, answers to host memory
@@ -341,7 +354,7 @@ def cpu_baseline(args, l2data, dnadata, np):
 
         chars, off = dnadata["objects"]
         qc, qo = dnadata["queries"]
-        md = max(1, args.cpu_dna_queries)
+        md = args.cpu_dna_queries if args.cpu_dna_queries > 0 else cores   # one round of the cores
         sc, so = synth.strings_from_bytes([qc[qo[i]:qo[i + 1]].tobytes() for i in range(md)])
         eo = O.ObjectSet(strings=(chars, off))
         t = time.perf_counter()
@@ -559,10 +572,7 @@ def rooflines_dna(st, mpad, workload):
                                     "(mpad + 8) B per staged object + 16 B per candidate",
                                     traffic(workload, "k_edit_objfilter"))
     t = st["ms_stage"]["verify"]
-    global _TRAFFIC
-    if _TRAFFIC is None:
-        _TRAFFIC = profile_traffic()
-    e = _TRAFFIC.get(workload, {}).get("k_verify_edit", {})
+    e = _profile_entry(workload, "k_verify_edit") or {}
     insts = e.get("valu_insts") if e.get("source_sha16") == source_sha16("k_verify_edit") else None
     a = insts * 64 / (t * 1e-3) / 1e12 if insts and t > 0 else None
     out["k_verify_edit"] = _roof("alu", a, VALU_PEAK_TOPS, "T lane-ops/s", insts, t,
@@ -653,7 +663,7 @@ def main():
     ap.add_argument("--side-steps", type=int, default=2,
                     help="steps of the host-to-host, plain and float32-selection legs (0: skip them)")
     ap.add_argument("--cpu-queries", type=int, default=800, help="L2 queries of the all-core oracle sample")
-    ap.add_argument("--cpu-dna-queries", type=int, default=8)
+    ap.add_argument("--cpu-dna-queries", type=int, default=0, help="DNA oracle queries (0: one per core)")
     ap.add_argument("--skip-dna", action="store_true")
     ap.add_argument("--skip-c4", action="store_true", help="skip the 4M x 96 kNN leg")
     ap.add_argument("--calibrate-copy", action="store_true", help="run one 256 MiB device copy first (profiling)")

@@ -50,6 +50,9 @@ typedef int32_t gts_status;
 /* Metrics (Sec. 3: any metric; the paper evaluates L2 and edit distance). */
 #define GTS_L2_F32 1      /* Euclidean distance on float32 vectors            */
 #define GTS_EDIT_U8 2     /* Levenshtein distance, unit costs, on byte strings */
+#define GTS_COSINE_F32 3  /* angular distance of cosine similarity: the angle
+                             arccos(x.y / (|x| |y|)) in radians, in [0, pi],
+                             between nonzero float32 vectors (directions)    */
 
 /* Where an array lives. */
 #define GTS_HOST 0
@@ -116,8 +119,16 @@ typedef struct {
     int64_t mem_budget_bytes;/* overrides the index's budget when > 0          */
     int32_t precision;       /* GTS_PRECISION_DEFAULT, GTS_BF16_GUARDED or
                                 GTS_FP32 (batched L2; overrides the index's)   */
-    int32_t reserved0;       /* must be 0                                       */
+    int32_t flags;           /* GTS_QF_* bits (0: none)                         */
 } gts_query_opts;
+
+/* gts_query_opts.flags */
+#define GTS_QF_CHECK_BOUND 1 /* L2, bf16 selection: test every rechecked
+                                candidate's float32 distance against the
+                                interval the proven bf16 error bound gave it
+                                and count failures in gts_stats.
+                                bound_violations (a self-check; answers do not
+                                change, verification slows by about a third) */
 
 /* Answers in CSR form: the answer of query i is entries
  * offsets[i] .. offsets[i+1] of ids / dist.  Owned by the library. */
@@ -154,10 +165,10 @@ typedef struct {
     int64_t wide_queries;    /* queries whose candidates one whole workgroup
                                 verified (L2: more than 1024; edit: more than
                                 its LDS sort holds)                            */
-    int64_t bound_violations;/* L2, bf16 selection: rechecked candidates whose
-                                float32 distance fell outside the interval the
-                                proven error bound gave them (always 0 unless
-                                the bound is wrong)                            */
+    int64_t bound_violations;/* L2, bf16 selection with GTS_QF_CHECK_BOUND:
+                                rechecked candidates whose float32 distance
+                                fell outside the interval the proven error
+                                bound gave them (0 unless the bound is wrong) */
     int64_t own_pairs;       /* batched: (query, object) pairs inside the
                                 surviving (query, leaf) pairs -- the method's
                                 own filtering work, before the tile rounding  */

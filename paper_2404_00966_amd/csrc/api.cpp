@@ -56,7 +56,11 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
     return guarded([&] {
         GTS_CHECK(out != nullptr, GTS_EINVAL, "null output handle");
         GTS_CHECK(objs != nullptr, GTS_EINVAL, "null objects");
-        GTS_CHECK(metric == GTS_L2_F32 || metric == GTS_EDIT_U8, GTS_EINVAL, "unknown metric");
+        GTS_CHECK(metric == GTS_L2_F32 || metric == GTS_EDIT_U8 || metric == GTS_COSINE_F32, GTS_EINVAL,
+                  "unknown metric");
+        // the angular metric is an L2 index over unit vectors
+        const bool angular = metric == GTS_COSINE_F32;
+        if (angular) metric = GTS_L2_F32;
         GTS_CHECK(num_pivots >= 1 && num_pivots <= kMaxPivots, GTS_EINVAL, "num_pivots must be in [1, 32]");
         GTS_CHECK(fanout >= 2 && fanout <= 64, GTS_EINVAL, "fanout must be in [2, 64]");
         GTS_CHECK(objs->n >= 1, GTS_EINVAL, "an index needs at least one object");
@@ -84,7 +88,8 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         idx->fanout = fanout;
         idx->data.max_strlen = idx->opts.max_strlen;
         HostObjects h;
-        read_objects(objs, metric, metric == GTS_L2_F32 ? objs->dim : 0, idx->opts.max_strlen, &h);
+        idx->angular = angular;
+        read_objects(objs, metric, metric == GTS_L2_F32 ? objs->dim : 0, idx->opts.max_strlen, &h, angular);
         for (int64_t i = 0; i < h.count(); i++) h.ids[i] = (uint32_t)i;
         GTS_CHECK(h.count() < ((int64_t)1 << 31), GTS_ENOTSUP, "at most 2^31-1 objects");
         idx->next_id = h.count();
@@ -133,7 +138,7 @@ gts_status gts_insert(gts_index *idx, const gts_objects *objs, int64_t *out_ids)
     return guarded([&] {
         GTS_CHECK(idx != nullptr, GTS_EINVAL, "null index");
         HostObjects h;
-        read_objects(objs, idx->data.metric, idx->data.dim, idx->opts.max_strlen, &h);
+        read_objects(objs, idx->data.metric, idx->data.dim, idx->opts.max_strlen, &h, idx->angular);
         insert_objects(idx, h, out_ids);
     });
 }
@@ -189,7 +194,7 @@ gts_status gts_get_info(const gts_index *idx, gts_index_info *out)
         GTS_CHECK(idx != nullptr && out != nullptr, GTS_EINVAL, "null argument");
         const IndexData &d = idx->data;
         std::memset(out, 0, sizeof(*out));
-        out->metric = d.metric;
+        out->metric = idx->angular ? GTS_COSINE_F32 : d.metric;
         out->dim = d.dim;
         out->num_pivots = d.m;
         out->fanout = d.tree.fanout;

@@ -49,6 +49,14 @@ __device__ __forceinline__ int wave_excl_scan(int v, int *total)
     return x - v;
 }
 
+// The distance an L2 computation reports: the Euclidean distance itself, or
+// for the angular metric (both vectors of unit length) the angle between
+// them, 2 asin(d / 2), which is monotone in d.
+__device__ __forceinline__ float out_dist(float d, bool angular)
+{
+    return angular ? 2.f * asinf(fminf(0.5f * d, 1.f)) : d;
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll

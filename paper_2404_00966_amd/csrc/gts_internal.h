@@ -334,8 +334,11 @@ void free_result(gts_result *r);
 void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *k,
             const gts_query_opts *opts, gts_result *out);
 // Copy a user object set (host or device) into host memory with fresh ids
-// starting at first_id; validates values and lengths.
-void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out);
+// starting at first_id; validates values and lengths.  angular: the rows are
+// scaled to unit length (norm in double, rounded to float); a zero row has no
+// direction and is an EINVAL error.
+void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out,
+                  bool angular = false);
 
 }  // namespace gts
 
@@ -353,6 +356,9 @@ struct gts_index {
     int64_t n_deleted_tree = 0;
     int64_t rebuilds = 0;
     int32_t num_pivots = 0, fanout = 0;
+    // GTS_COSINE_F32: the index is an L2 index over unit vectors; distances
+    // are reported as angles 2 asin(d / 2) and radii converted to chords
+    bool angular = false;
     gts_build_opts opts{};
     std::string tune_cache;            // tuned-settings file ("" = none)
     std::mutex tune_mu;                // guards `tuned` and the file

@@ -37,7 +37,7 @@ enum Ws {
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
     W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV, W_POSOF, W_HOMEC, W_PLEN, W_POFF, W_PCHARS,
-    W_COUNT
+    W_BADQ, W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
 
@@ -162,7 +162,8 @@ double now_ms()
 // ---------------------------------------------------------------------------
 // Reading user objects (host or device) into host memory, with validation.
 // ---------------------------------------------------------------------------
-void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out)
+void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out,
+                  bool angular)
 {
     GTS_CHECK(o != nullptr, GTS_EINVAL, "null object set");
     GTS_CHECK(o->n >= 0, GTS_EINVAL, "negative object count");
@@ -179,6 +180,15 @@ void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max
         out->vecs.resize((size_t)n * dim);
         GTS_HIP(hipMemcpy(out->vecs.data(), o->vecs, out->vecs.size() * sizeof(float), kind));
         for (float v : out->vecs) GTS_CHECK(std::isfinite(v), GTS_EINVAL, "non-finite vector value");
+        if (angular)
+            for (int64_t i = 0; i < n; i++) {
+                float *x = out->vecs.data() + (size_t)i * dim;
+                double s = 0.0;
+                for (int j = 0; j < dim; j++) s += (double)x[j] * (double)x[j];
+                const double nrm = std::sqrt(s);
+                GTS_CHECK(nrm > 0.0 && std::isfinite(nrm), GTS_EINVAL, "a zero vector has no direction (angular metric)");
+                for (int j = 0; j < dim; j++) x[j] = (float)((double)x[j] / nrm);
+            }
     } else {
         if (n == 0) return;
         GTS_CHECK(o->offsets != nullptr, GTS_EINVAL, "null string offsets");
@@ -229,6 +239,7 @@ struct Batch {
     int64_t ntiles_all = 0;    // query tiles of the whole batch
     int precision = GTS_BF16_GUARDED;   // L2 candidate selection (batched form)
     int sweep_grid_per_cu = 2;          // MFMA sweep workgroups per CU (tuned)
+    bool check_bound = false;           // count bf16 interval violations
 };
 
 void rec(QueryCtx *cx, int i)
@@ -298,6 +309,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         pa.pt_max = d.pt_max;
         pa.leaf_piv32 = l2 && d.lpad > 0 ? d.PL32.as<float>() : nullptr;
         pa.leafR = l2 && d.lpad > 0 ? d.leafR.as<float>() : nullptr;
+        pa.angular = idx->angular ? 1 : 0;
         rec(cx, 3);
         if (l2) k::plain_l2(tv, ov, d.P32.as<float>(), d.m, d.PT.as<float>(), qv.Q32, pa, st);
         else k::plain_edit(tv, oe, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, d.PTe.as<uint8_t>(), qe, pa, st);
@@ -362,7 +374,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             // emission cutoff: radius (range) or the widened bound T (kNN)
             float *cut = cx->ws[W_CUT].as<float>() + q0;
             k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
-                             cut, cands, ccount, cap, st);
+                             cut, cands, ccount, cap, idx->angular, st);
         } else {
             k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
                                c.live.as<uint32_t>(), c.count, base, cands, ccount, cap, st);
@@ -387,8 +399,12 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint32_t *h_small = reinterpret_cast<uint32_t *>(pin + pl.small);
     int64_t *h_qoff_pin = reinterpret_cast<int64_t *>(pin + pl.qoff);
     GTS_HIP(hipMemcpyAsync(h_small, small, kSmallWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    uint32_t *h_bad = h_small + 32;   // (the small-counter region of the staging holds 64 words)
+    *h_bad = 0;
+    if (idx->angular && l2) GTS_HIP(hipMemcpyAsync(h_bad, cx->ws[W_BADQ].p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
+    GTS_CHECK(*h_bad == 0, GTS_EINVAL, "a query vector is zero or non-finite: it has no direction (angular metric)");
     const uint64_t ncand_all = *reinterpret_cast<const uint64_t *>(h_small);
     if (ncand_all > (uint64_t)cap) return false;
     const int64_t ncand = (int64_t)ncand_all;
@@ -434,7 +450,8 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     // ---- verify, select, order ------------------------------------------------
     uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(ncand, 1));
     uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
-    k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters};
+    k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters,
+                     idx->angular ? 1 : 0};
     int32_t *dblk = nullptr;
     if (n_blk > 0) {
         dblk = wsp<int32_t>(cx, W_BLKQ, n_blk);
@@ -442,7 +459,9 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     }
     if (l2) n_wide += n_blk;
     cx->stats.wide_queries += n_wide;
-    if (l2) k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, !plain && !sel32, st);
+    if (l2)
+        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, !plain && !sel32,
+                     b.check_bound, st);
     else k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
@@ -579,7 +598,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     b.precision = opts && opts->precision != GTS_PRECISION_DEFAULT ? opts->precision : idx->opts.precision;
     if (b.precision == GTS_PRECISION_DEFAULT) b.precision = GTS_BF16_GUARDED;
     GTS_CHECK(b.precision == GTS_BF16_GUARDED || b.precision == GTS_FP32, GTS_EINVAL, "bad precision");
-    GTS_CHECK(!opts || opts->reserved0 == 0, GTS_EINVAL, "gts_query_opts.reserved0 must be 0");
+    GTS_CHECK(!opts || (opts->flags & ~GTS_QF_CHECK_BOUND) == 0, GTS_EINVAL, "unknown gts_query_opts.flags bits");
+    b.check_bound = opts && (opts->flags & GTS_QF_CHECK_BOUND);
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;
@@ -618,7 +638,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             GTS_CHECK(radius != nullptr, GTS_EINVAL, "radius array required for range queries");
             const float r = radius[q];
             GTS_CHECK(std::isfinite(r) && r >= 0.f, GTS_EINVAL, "radius must be finite and >= 0");
-            hbase[q] = r;
+            // angular: the chord between unit vectors at angle r, 2 sin(r / 2)
+            hbase[q] = idx->angular ? (float)(2.0 * std::sin(std::min((double)r, M_PI) / 2.0)) : r;
             b.max_radius = std::max(b.max_radius, r);
         }
     }
@@ -626,7 +647,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     cx->stats.nq = nq;
     std::memset(out, 0, sizeof(*out));
     out->nq = nq;
-    out->metric = d.metric;
+    out->metric = idx->angular ? GTS_COSINE_F32 : d.metric;
     out->location = rloc;
     double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cx->timing && !cx->ev[0])
@@ -667,6 +688,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         float *Q32 = wsp<float>(cx, W_Q32, (size_t)nqpad * d.dp);
         GTS_HIP(hipMemsetAsync(Q32, 0, (size_t)nqpad * d.dp * sizeof(float), st));
         rows_to_device(Q32, d.dp, Q->vecs, d.dim, nq, Q->location == GTS_DEVICE, st);
+        if (idx->angular) {
+            uint32_t *bad = wsp<uint32_t>(cx, W_BADQ, 1);
+            k::fill_u32(bad, 1, 0u, st);
+            k::normalize_rows(Q32, nq, d.dim, d.dp, bad, st);
+        }
         uint16_t *Q16 = wsp<uint16_t>(cx, W_Q16, (size_t)nqpad * d.ksteps * 32);
         float *qn = wsp<float>(cx, W_QN, nqpad);
         float *qerr = wsp<float>(cx, W_QE, nqpad);

@@ -202,8 +202,17 @@ __device__ void sort_and_emit(uint64_t *keys, int nk, int64_t cap, int k, uint64
 // d <= r, kNN queries keep everything; keys are sorted by (d, id).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr, const L2View &o, float eps_a,
-                                            float eps_b, float eps_c, float delta, float *lo, float *hi)
+                                            float eps_b, float eps_c, float delta, float *lo, float *hi,
+                                            bool angular = false)
 {
+    if (c.pos < 0 && angular) {
+        // a cache entry's key holds its angle, not d: no interval (always kept,
+        // never tightens the bound; the k-th upper end of the others still
+        // bounds the k-th distance)
+        *lo = 0.f;
+        *hi = INFINITY;
+        return;
+    }
     if (c.pos < 0) {
         const float d = __uint_as_float((uint32_t)(c.val >> 32));
         *lo = d * (1.f - 2.f * delta);
@@ -241,7 +250,7 @@ struct RecheckCtx {
     bool est;                                // candidates carry bf16 estimates
 };
 
-template <bool kShort, class Emit>
+template <bool kShort, bool kCheck, class Emit>
 __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View &o, const RecheckCtx &rc,
                                               float delta, float eps_a, float eps_b, float eps_c, const Cand *g,
                                               int i0, int i1, int32_t *ring, long long *verified, long long *viol,
@@ -264,7 +273,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             const int j = 4 * uu + grp;
             nd[uu] = j < cnt;
             p[uu] = nd[uu] ? ring[(head + j) & (kRing - 1)] : 0;
-            ev[uu] = nd[uu] && sl == 0 ? ring_est[(head + j) & (kRing - 1)] : 0u;
+            ev[uu] = kCheck && nd[uu] && sl == 0 ? ring_est[(head + j) & (kRing - 1)] : 0u;
         }
         uint32_t idv[4];
         float acc[4];
@@ -313,7 +322,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             const bool mine = nd[uu] && sl == 0;
             const float d = sqrtf(acc[uu]);
             if (mine) (*verified)++;
-            if (mine && rc.est) {
+            if (kCheck && mine && rc.est) {
                 // invariant of the bf16 selection: the exact distance lies in
                 // the candidate's interval (up to the float32 error of d)
                 Cand c;
@@ -321,10 +330,11 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
                 c.pos = p[uu];
                 c.val = ev[uu];
                 float lo, hi;
-                l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi, a.angular != 0);
                 if (d < lo * (1.f - 2.f * delta) || d > hi * (1.f + 2.f * delta)) (*viol)++;
             }
-            emit(mine && (rc.k > 0 || d <= rc.base), ((uint64_t)__float_as_uint(d) << 32) | idv[uu]);
+            emit(mine && (rc.k > 0 || d <= rc.base),
+                 ((uint64_t)__float_as_uint(dev::out_dist(d, a.angular != 0)) << 32) | idv[uu]);
         }
     };
     // one 64-candidate step at a time, the next step's candidates loading
@@ -346,14 +356,14 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
         bool need = v && c.pos >= 0;
         if (need && rc.sel && rc.ub < INFINITY) {
             float lo, hi;
-            l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            l2_interval(c, rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi, a.angular != 0);
             need = lo <= rc.ub;
         }
         emit(v && c.pos < 0, c.val);                 // known distance (cache list)
         const uint64_t m = dev::ballot(need);
         if (need) {
             ring[(tail + dev::lanes_below(m)) & (kRing - 1)] = c.pos;
-            ring_est[(tail + dev::lanes_below(m)) & (kRing - 1)] = (uint32_t)c.val;
+            if (kCheck) ring_est[(tail + dev::lanes_below(m)) & (kRing - 1)] = (uint32_t)c.val;
         }
         tail += __popcll(m);
         while (tail - head >= 16) {
@@ -371,7 +381,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
 // recheck chunks of 64 * kChunk candidates in turn; kept keys are compacted
 // per wave (one LDS atomic reserves the wave's slots) and sorted in LDS
 // (s_keys, kSortCapL2) or in the query's scratch run.
-template <bool kShort>
+template <bool kShort, bool kCheck>
 __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
                                 float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring, bool est)
 {
@@ -398,7 +408,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     if (rc.sel) {
         for (int i = threadIdx.x; i < ns; i += blockDim.x) {
             float lo, hi;
-            l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+            l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi, a.angular != 0);
             s_keys[i] = (uint64_t)__float_as_uint(hi);
         }
         // the k-th smallest hi (hi >= 0: float order = bit order) by a radix
@@ -459,8 +469,8 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     };
     const int nw = (int)(blockDim.x >> 6);
     for (int c0 = wave * 64 * kChunk; c0 < ns; c0 += nw * 64 * kChunk)
-        recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
-                              &verified, &viol, emit);
+        recheck_chunk<kShort, kCheck>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
+                                      &verified, &viol, emit);
     __syncthreads();
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
     for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
@@ -503,7 +513,7 @@ __device__ void wave_bitonic_sort(uint64_t *a, int n)
 // each lane holds in registers), bounds the answer set; then one chunk of
 // rechecks (above).  Kept keys are compacted with ballots into the wave's
 // LDS run and sorted there.
-template <bool kShort>
+template <bool kShort, bool kCheck>
 __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
                                float eps_b, float eps_c, int64_t q, uint64_t *keys, int32_t *ring, bool est)
 {
@@ -529,7 +539,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
             hv[u] = 0xffffffffu;
             if (i < ns) {
                 float lo, hi;
-                l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi);
+                l2_interval(g[i], rc.qnn, rc.qerr, o, eps_a, eps_b, eps_c, delta, &lo, &hi, a.angular != 0);
                 hv[u] = __float_as_uint(hi);
             }
         }
@@ -560,7 +570,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
         if (keep) keys[nk + dev::lanes_below(m)] = key;
         nk += __popcll(m);
     };
-    recheck_chunk<kShort>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, &viol, emit);
+    recheck_chunk<kShort, kCheck>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, &viol, emit);
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
     for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
     if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
@@ -580,7 +590,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 // blk_q (more than kWaveSortCap candidates) one each, the rest take four
 // queries each, one per wave, skipping those; the long workgroups start first
 // and overlap the bulk of the work.
-template <bool kShort>
+template <bool kShort, bool kCheck>
 __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
                                                    float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
                                                    int n_blk, int est)
@@ -589,7 +599,7 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     __shared__ int32_t s_ring[4][2 * kRing];
     static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
     if ((int)blockIdx.x < n_blk) {
-        verify_l2_block<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
+        verify_l2_block<kShort, kCheck>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
                                 s_ring[threadIdx.x >> 6], est != 0);
         return;
     }
@@ -603,24 +613,30 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     if (q >= a.nq) return;
     const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
     if (ns > kWaveSortCap) return;
-    verify_l2_wave<kShort>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
+    verify_l2_wave<kShort, kCheck>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
                            est != 0);
 }
 
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, hipStream_t st)
+               bool est, bool check, hipStream_t st)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
     const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
-    if (o.dp <= 128)
-        hipLaunchKernelGGL(k_verify_l2<true>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q,
-                           n_blk, est ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_verify_l2<false>, dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c,
-                           blk_q, n_blk, est ? 1 : 0);
+#define VL(S, C)                                                                                              \
+    hipLaunchKernelGGL((k_verify_l2<S, C>), dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q, \
+                       n_blk, est ? 1 : 0)
+    const bool chk = check && est;
+    if (o.dp <= 128) {
+        if (chk) VL(true, true);
+        else VL(true, false);
+    } else {
+        if (chk) VL(false, true);
+        else VL(false, false);
+    }
+#undef VL
     check_launch(__func__);
 }
 

@@ -108,7 +108,7 @@ __device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, c
         if (sl == 0 && c < nc) {
             (*verified)++;
             const float d = sqrtf(acc);
-            if (d <= cut) emit_verified(a, q, __float_as_uint(d), a.ids[p]);
+            if (d <= cut) emit_verified(a, q, __float_as_uint(dev::out_dist(d, a.angular != 0)), a.ids[p]);
         }
     }
 }

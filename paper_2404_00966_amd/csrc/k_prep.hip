@@ -198,6 +198,34 @@ void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t n
     check_launch(__func__);
 }
 
+// Unit rows for the angular metric: one wave per row, the squared norm
+// summed in double over the lanes, every coordinate divided by the norm in
+// double and rounded to float (within one rounding of the true unit vector).
+__global__ __launch_bounds__(256) void k_normalize_rows(float *__restrict__ X, int64_t rows, int dim, int stride,
+                                                        uint32_t *__restrict__ bad)
+{
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (r >= rows) return;
+    float *x = X + (size_t)r * stride;
+    double acc = 0.0;
+    for (int i = lane; i < dim; i += 64) acc += (double)x[i] * (double)x[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    const double nrm = sqrt(acc);
+    const bool ok = nrm > 0.0 && nrm < INFINITY;
+    for (int i = lane; i < dim; i += 64) x[i] = ok ? (float)((double)x[i] / nrm) : 0.f;
+    if (!ok && lane == 0) atomicOr(bad, 1u);
+}
+
+void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st)
+{
+    if (rows == 0) return;
+    hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, X, rows, dim, stride,
+                       bad);
+    check_launch(__func__);
+}
+
 // out[q] = a[q] + b[q] for q < n, -inf for n <= q < npad (padding rows of a
 // query tile never pass a threshold).
 __global__ void k_sum_pad(const float *__restrict__ a, const float *__restrict__ b, int64_t n, int64_t npad,

@@ -805,7 +805,7 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
 __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp, const float *__restrict__ C32,
                                 const uint32_t *__restrict__ cids, const uint32_t *__restrict__ clive,
                                 int64_t ncache, const float *__restrict__ base, Cand *__restrict__ cands,
-                                CandCount *__restrict__ cand_count, int64_t cand_cap)
+                                CandCount *__restrict__ cand_count, int64_t cand_cap, int angular)
 {
     const int64_t pair = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int sl = threadIdx.x & 15;
@@ -831,7 +831,7 @@ __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int d
                 Cand cd;
                 cd.q = (int32_t)q;
                 cd.pos = -1;
-                cd.val = ((uint64_t)__float_as_uint(d) << 32) | cids[c];
+                cd.val = ((uint64_t)__float_as_uint(dev::out_dist(d, angular != 0)) << 32) | cids[c];
                 cands[idx] = cd;
             }
         }
@@ -840,12 +840,12 @@ __global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int d
 
 void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
                    const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
-                   int64_t cand_cap, hipStream_t st)
+                   int64_t cand_cap, bool angular, hipStream_t st)
 {
     if (nq == 0 || ncache == 0) return;
     const int64_t threads = nq * ncache * 16;
     hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Q32, nq, dp, C32,
-                       cids, clive, ncache, base, cands, cand_count, cand_cap);
+                       cids, clive, ncache, base, cands, cand_count, cand_cap, angular ? 1 : 0);
     check_launch(__func__);
 }
 

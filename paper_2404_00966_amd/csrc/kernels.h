@@ -70,6 +70,9 @@ void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, const uint8
 void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t nq, int mpad, int is_edit,
                 float delta, float pt_max, float *T, float *thr, float *cut, hipStream_t st);
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+// Rows scaled to unit length in place (norm in double, result rounded to
+// float); a row with zero or non-finite norm becomes zero and sets *bad.
+void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
 void sum_pad(const float *a, const float *b, int64_t n, int64_t npad, float *out, hipStream_t st);
 
 // ---- tree and candidates (k_search.hip) ------------------------------------
@@ -170,7 +173,7 @@ void l2_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_
 // Brute-force scan of the cache list; emits verified entries with d <= base.
 void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
                    const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
-                   int64_t cand_cap, hipStream_t st);
+                   int64_t cand_cap, bool angular, hipStream_t st);
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
                      const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
                      const float *base, Cand *cands, CandCount *cand_count, int64_t cand_cap, hipStream_t st);
@@ -264,13 +267,16 @@ struct VerifyArgs {
     uint64_t *out_keys;        // same index space as grouped
     uint32_t *out_count;       // [nq]
     unsigned long long *counters;
+    int angular;               // L2 on unit vectors: keys carry the angle 2 asin(d/2)
 };
 // blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
 // est: the tree-position candidates carry bf16 estimates of d^2 (the bf16
 // selection); without them every candidate is rechecked and kept for the
 // final (distance, id) cut.
+// check: count rechecked candidates whose float32 distance leaves their
+// bf16 interval (CNT_BOUND_VIOL).
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, hipStream_t st);
+               bool est, bool check, hipStream_t st);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
@@ -335,6 +341,7 @@ struct PlainArgs {
     float delta, pt_max;
     const float *leaf_piv32;   // [n_leaves][dp] leaf pivot vectors (L2; null: no leaf test)
     const float *leafR;        // [n_leaves] largest pivot distance in the leaf
+    int angular;               // L2 on unit vectors: keys carry the angle 2 asin(d/2)
 };
 void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const float *PT, const float *Q32,
               const PlainArgs &a, hipStream_t st);

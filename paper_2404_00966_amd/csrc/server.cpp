@@ -22,6 +22,20 @@
 namespace gts {
 namespace {
 
+// Angular indexes: a query request with a zero vector is refused at submission
+// (in a batch it would fail every request admitted with it).  The search scales
+// queries to unit length itself.
+void check_directions(const gts_index *idx, const HostObjects &h)
+{
+    if (!idx->angular) return;
+    for (int64_t i = 0; i < h.count(); i++) {
+        double s = 0.0;
+        for (int j = 0; j < h.dim; j++) s += (double)h.vecs[(size_t)i * h.dim + j] * h.vecs[(size_t)i * h.dim + j];
+        GTS_CHECK(s > 0.0, GTS_EINVAL, "a zero vector has no direction (angular metric)");
+    }
+}
+
+
 double now_ms()
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -341,13 +355,15 @@ gts_status gts_server_submit(gts_server *s, const gts_request *req, uint64_t *ti
         case GTS_REQ_RANGE:
             GTS_CHECK(std::isfinite(req->radius) && req->radius >= 0.f, GTS_EINVAL, "radius must be finite and >= 0");
             read_objects(&req->objects, d.metric, d.dim, q.idx->opts.max_strlen, &r->objs);
+            check_directions(q.idx, r->objs);
             break;
         case GTS_REQ_KNN:
             GTS_CHECK(req->k >= 1, GTS_EINVAL, "k must be >= 1");
             read_objects(&req->objects, d.metric, d.dim, q.idx->opts.max_strlen, &r->objs);
+            check_directions(q.idx, r->objs);
             break;
         case GTS_REQ_INSERT:
-            read_objects(&req->objects, d.metric, d.dim, q.idx->opts.max_strlen, &r->objs);
+            read_objects(&req->objects, d.metric, d.dim, q.idx->opts.max_strlen, &r->objs, q.idx->angular);
             break;
         case GTS_REQ_DELETE:
             GTS_CHECK(req->n_ids >= 0 && (req->ids != nullptr || req->n_ids == 0), GTS_EINVAL, "bad delete ids");

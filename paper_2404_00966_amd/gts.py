@@ -17,9 +17,10 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgts.so")
 
-L2_F32, EDIT_U8 = 1, 2
+L2_F32, EDIT_U8, COSINE_F32 = 1, 2, 3
 HOST, DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
+QF_CHECK_BOUND = 1
 PRECISION_DEFAULT, BF16_GUARDED, FP32 = 0, 1, 2
 STAGES = ("prep", "bound", "nodes", "cands", "group", "verify", "output", "plain")
 
@@ -45,7 +46,7 @@ class _BuildOpts(C.Structure):
 
 class _QueryOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("result_location", C.c_int32), ("mem_budget_bytes", C.c_int64),
-                ("precision", C.c_int32), ("reserved0", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -157,7 +158,7 @@ def _objects(data, metric, keep: _Keep) -> _Objects:
     """torch tensor / numpy array (L2: [n, dim] float32) or (chars, offsets)
     pair (EDIT) -> gts_objects.  CUDA tensors are passed as device pointers."""
     o = _Objects()
-    if metric == L2_F32:
+    if metric != EDIT_U8:
         t = data if isinstance(data, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(data))
         t = t.to(torch.float32).contiguous()
         if t.dim() != 2:
@@ -235,7 +236,7 @@ class Index:
 
     # -- queries ------------------------------------------------------------
     def search(self, queries, radius=None, k=None, mode=MODE_BATCHED, result="auto", mem_budget_bytes=0,
-               precision=PRECISION_DEFAULT):
+               precision=PRECISION_DEFAULT, flags=0):
         """Mixed batch: query i is kNN when k[i] > 0, else range with radius[i]."""
         L = library()
         keep = _Keep()
@@ -248,7 +249,7 @@ class Index:
             rloc = o.location
         else:
             rloc = DEVICE if result == "device" else HOST
-        qo = _QueryOpts(mode, rloc, mem_budget_bytes, precision, 0)
+        qo = _QueryOpts(mode, rloc, mem_budget_bytes, precision, flags)
         res = _Result()
         _check(L.gts_search(self._h, C.byref(o), None if r_arr is None else r_arr.ctypes.data,
                             None if k_arr is None else k_arr.ctypes.data, C.byref(qo), C.byref(res)))
@@ -256,7 +257,7 @@ class Index:
             dev = torch.device("cuda") if rloc == DEVICE else torch.device("cpu")
             off = torch.empty(nq + 1, dtype=torch.int64, device=dev)
             ids = torch.empty(max(res.total, 0), dtype=torch.int64, device=dev)
-            dt = torch.float32 if self.metric == L2_F32 else torch.int32
+            dt = torch.int32 if self.metric == EDIT_U8 else torch.float32
             dist = torch.empty(max(res.total, 0), dtype=dt, device=dev)
             if rloc == DEVICE:
                 torch.cuda.current_stream().synchronize()
@@ -382,7 +383,7 @@ class Server:
                 tot = int(res.total)
                 ids = np.ctypeslib.as_array(C.cast(res.ids, C.POINTER(C.c_int64)), (tot,)).copy() if tot else \
                     np.zeros(0, np.int64)
-                if res.metric == L2_F32:
+                if res.metric != EDIT_U8:
                     dist = np.ctypeslib.as_array(C.cast(res.dist_f32, C.POINTER(C.c_float)), (tot,)).copy() \
                         if tot else np.zeros(0, np.float32)
                 else:

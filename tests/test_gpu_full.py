@@ -57,7 +57,7 @@ def test_l2_1m_d128_full_batch():
     Q = torch.from_numpy(np.concatenate([KQ, RQ])).cuda()
     k = np.array([w["k"]] * len(KQ) + [0] * len(RQ), np.int32)
     radius = np.full(len(KQ) + len(RQ), r, np.float32)
-    res = idx.search(Q, radius=radius, k=k, result="device").to_lists()
+    res = idx.search(Q, radius=radius, k=k, result="device", flags=gts.QF_CHECK_BOUND).to_lists()
     st = idx.stats()
     print(f"[stats] batched {st}", flush=True)
     assert st["results"] == sum(len(a) for a, _ in res)
@@ -124,7 +124,7 @@ def test_l2_4m_d96_knn_bf16():
     idx = gts.Index(torch.from_numpy(X).cuda(), gts.L2_F32, num_pivots=w["pivots"], fanout=w["fanout"],
                     leaf_size=w["leaf"], seed=w["seed"])
     Qd = torch.from_numpy(KQ).cuda()
-    res = idx.knn(Qd, w["k"], result="device").to_lists()
+    res = idx.knn(Qd, w["k"], result="device", flags=gts.QF_CHECK_BOUND).to_lists()
     st = idx.stats()
     print(f"[stats] batched {st}", flush=True)
     assert st["bound_violations"] == 0

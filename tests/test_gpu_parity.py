@@ -406,9 +406,11 @@ def test_l2_planted_boundary_and_duplicates(gts):
     Qd = _dev(np.concatenate([Q, Q]))
     k = np.array([0] * len(Q) + [45] * len(Q), np.int32)
     radius = np.full(2 * len(Q), r, np.float32)
-    a = idx.search(Qd, radius=radius, k=k).to_lists()
+    a = idx.search(Qd, radius=radius, k=k, flags=gts.QF_CHECK_BOUND).to_lists()
     st = idx.stats()
     assert st["bound_violations"] == 0 and st["verified"] > 0
+    assert np.array_equal(np.concatenate([x[0] for x in a]),
+                          np.concatenate([x[0] for x in idx.search(Qd, radius=radius, k=k).to_lists()]))
     b = idx.search(Qd, radius=radius, k=k, precision=gts.FP32).to_lists()
     c = idx.search(Qd, radius=radius, k=k, mode=gts.MODE_PLAIN).to_lists()
     idx.close()
