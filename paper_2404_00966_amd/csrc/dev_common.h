@@ -308,5 +308,45 @@ __device__ __forceinline__ int next_pow2(int v)
     return p;
 }
 
+// Bitonic sort of n (a power of two) keys in LDS by one wave (lanes in
+// lockstep: a wave barrier orders the passes).
+__device__ inline void wave_bitonic_sort(uint64_t *a, int n)
+{
+    const int lane = threadIdx.x & 63;
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i < (n >> 1); i += 64) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sort keys[0, nk) by the workgroup (padded with ~0 to a power of two within
+// cap), then write the first min(k, nk) (k > 0) or all nk to out and the
+// count to *out_count_q.
+__device__ inline void sort_and_emit(uint64_t *keys, int nk, int64_t cap, int k, uint64_t *out, uint32_t *out_count_q)
+{
+    const int P = next_pow2(nk > 1 ? nk : 1);
+    for (int i = nk + threadIdx.x; i < P && i < cap; i += blockDim.x) keys[i] = ~0ull;
+    bitonic_sort(keys, P);
+    const int nout = (k > 0 && k < nk) ? k : nk;
+    for (int j = threadIdx.x; j < nout; j += blockDim.x) out[j] = keys[j];
+    if (threadIdx.x == 0) *out_count_q = (uint32_t)nout;
+}
+
 }  // namespace dev
 }  // namespace gts

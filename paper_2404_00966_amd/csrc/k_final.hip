@@ -183,15 +183,6 @@ void group_scatter(const Cand *c, const CandCount *count, int64_t cap, const int
 
 // Sort the keys of one query (in LDS or, for a large segment, in its
 // power-of-two scratch run) and write the first `keep` to out.
-__device__ void sort_and_emit(uint64_t *keys, int nk, int64_t cap, int k, uint64_t *out, uint32_t *out_count_q)
-{
-    const int P = dev::next_pow2(nk > 1 ? nk : 1);
-    for (int i = nk + threadIdx.x; i < P && i < cap; i += blockDim.x) keys[i] = ~0ull;
-    dev::bitonic_sort(keys, P);
-    const int nout = (k > 0 && k < nk) ? k : nk;
-    for (int j = threadIdx.x; j < nout; j += blockDim.x) out[j] = keys[j];
-    if (threadIdx.x == 0) *out_count_q = (uint32_t)nout;
-}
 
 // ---------------------------------------------------------------------------
 // L2: per query, one workgroup.  kNN queries first keep only candidates
@@ -477,35 +468,9 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
     if (lane == 0 && viol) count_add(a.counters, CNT_BOUND_VIOL, (unsigned long long)viol);
     const int nk = s_n;
-    sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
+    dev::sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
 
-// Bitonic sort of n (a power of two) keys in LDS by one wave (lanes in
-// lockstep: a wave barrier orders the passes).
-__device__ void wave_bitonic_sort(uint64_t *a, int n)
-{
-    const int lane = threadIdx.x & 63;
-    for (int size = 2; size <= n; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int i = lane; i < (n >> 1); i += 64) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t x = a[lo], y = a[hi];
-                if ((x > y) == up) {
-                    a[lo] = y;
-                    a[hi] = x;
-                }
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // One wave for query q (at most kWaveSortCap candidates).  kNN: the k-th
 // smallest upper interval end over the candidates, found by a 32-step
@@ -580,7 +545,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int i = nk + lane; i < P; i += 64) keys[i] = ~0ull;
-    wave_bitonic_sort(keys, P);
+    dev::wave_bitonic_sort(keys, P);
     const int nout = (k > 0 && k < nk) ? k : nk;
     for (int j = lane; j < nout; j += 64) a.out_keys[seg0 + j] = keys[j];
     if (lane == 0) a.out_count[q] = (uint32_t)nout;
@@ -700,7 +665,7 @@ __global__ __launch_bounds__(256) void k_verify_edit(VerifyArgs a, EditView o, Q
     __syncthreads();
     if (verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
     const int nk = s_n;
-    sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
+    dev::sort_and_emit(keys, nk, cap, k, a.out_keys + seg0, a.out_count + q);
 }
 
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st)
