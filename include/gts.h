@@ -275,6 +275,37 @@ gts_status gts_set_timing(gts_index *idx, int32_t enable);
 /* Message of the last failure on this thread ("" if none). */
 const char *gts_last_error(void);
 
+/* ---- No-allocation search --------------------------------------------------
+ * For callers that cannot allocate memory during a query: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ *
+ * The same answers as gts_search in the batched form (same conventions,
+ * same kernels), but every intermediate buffer comes from one fixed device
+ * array inside the library (GTS_NOALLOC_SCRATCH_BYTES, held by each GPU the
+ * library runs on until the process ends), the pinned host staging was made
+ * when the index was built, and the answers go to the caller's device
+ * buffers: the call makes no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating runtime call.
+ *   Q:            device queries (location GTS_DEVICE), at most
+ *                 GTS_NOALLOC_MAX_QUERIES of them; radius / k as gts_search
+ *                 (host arrays).
+ *   opts:         may be NULL; mode must be GTS_MODE_BATCHED.
+ *   out_offsets:  device int64 [Q->n + 1], CSR offsets of the answers.
+ *   out_ids:      device int64 [out_capacity] object ids.
+ *   out_dist:     device [out_capacity] float (L2) or int32 (EDIT) distances.
+ *   out_total:    host int64: the number of answers, also on failure when
+ *                 they exceed out_capacity (GTS_ENOMEM: retry with a larger
+ *                 buffer).
+ * GTS_ENOMEM also when the batch's intermediate data exceed the array (split
+ * the batch).  Calls share the array: this process serialises them; calls
+ * that overlap on one GPU from several threads wait for each other.  Stage
+ * timing is not recorded and gts_get_stats reports the other calls. */
+#define GTS_NOALLOC_SCRATCH_BYTES (128ll << 20)
+#define GTS_NOALLOC_MAX_QUERIES 2048
+gts_status gts_search_noalloc(gts_index *idx, const gts_objects *Q, const float *radius, const int32_t *k,
+                              const gts_query_opts *opts, int64_t *out_offsets, int64_t *out_ids, void *out_dist,
+                              int64_t out_capacity, int64_t *out_total);
+
 /* ---- Serving: continuous batching over resident indexes -------------------
  *
  * A server owns worker threads over a set of built indexes (it does not own

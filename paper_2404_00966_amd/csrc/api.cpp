@@ -68,6 +68,12 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         auto idx = std::make_unique<gts_index>();
         idx->stream = static_cast<hipStream_t>(hip_stream);
         idx->ctx.stream = idx->stream;
+        // the no-allocation search's context: same stream, pinned staging
+        // for its largest batch made now (that call allocates nothing)
+        idx->ctx_na.stream = idx->stream;
+        GTS_CHECK(idx->ctx_na.pinned(staging_bytes(kNoAllocMaxQueries)) != nullptr, GTS_ENOMEM,
+                  "pinned staging of the no-allocation search");
+        idx->ctx_na.pin_fixed = true;
         if (opts) idx->opts = *opts;
         GTS_CHECK(idx->opts.precision == GTS_PRECISION_DEFAULT || idx->opts.precision == GTS_BF16_GUARDED ||
                       idx->opts.precision == GTS_FP32,

@@ -57,23 +57,26 @@ constexpr int kWaveSortCap = 1024;  // L2: per-query keys verified and sorted by
 constexpr int kWorkspaceSlots = 64;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 
-// Device buffer owned by the index (hipMalloc / hipFree).
+// Device buffer owned by the index (hipMalloc / hipFree), or a view of
+// memory owned elsewhere (owned = false: never freed here).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; owned = o.owned; o.p = nullptr; o.bytes = 0; }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
     void alloc(size_t b) {
         if (b <= bytes && p) return;
@@ -286,8 +289,28 @@ struct LaunchTuner {
     }
 };
 
+// Bump allocation over a fixed device region (the no-allocation entry
+// point's scratch array): buffers are carved in order, 256-byte aligned, and
+// the whole region is reused by the next call.
+struct Arena {
+    uint8_t *base = nullptr;
+    size_t size = 0, used = 0;
+    size_t left() const { return size > align(used) ? size - align(used) : 0; }
+    static size_t align(size_t v) { return (v + 255) / 256 * 256; }
+    void *take(size_t bytes)
+    {
+        const size_t at = align(used);
+        if (at + bytes > size)
+            fail(GTS_ENOMEM, "the no-allocation scratch (" + std::to_string(size) + " bytes) cannot hold this batch's "
+                             "intermediate data; use a smaller batch");
+        used = at + bytes;
+        return base + at;
+    }
+};
+
 struct QueryCtx {
     hipStream_t stream = nullptr;
+    Arena *arena = nullptr;            // set: every workspace buffer is carved from it
     DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
     void *pin = nullptr;               // pinned host staging for small device-to-host reads
     size_t pin_bytes = 0;
@@ -298,9 +321,11 @@ struct QueryCtx {
     QueryCtx() = default;
     QueryCtx(const QueryCtx &) = delete;
     QueryCtx &operator=(const QueryCtx &) = delete;
+    bool pin_fixed = false;            // the staging was sized at set-up and never grows
     // at least `bytes` of pinned host memory (grown, never shrunk)
     void *pinned(size_t bytes)
     {
+        if (bytes > pin_bytes && pin_fixed) return nullptr;
         if (bytes > pin_bytes) {
             if (pin) (void)hipHostFree(pin);
             pin = nullptr;
@@ -330,9 +355,26 @@ void tune_cache_store(gts_index *idx);
 gts_status run_guarded(const std::function<void()> &f);
 // Release a result allocated by search.
 void free_result(gts_result *r);
-// Queries.
+// Caller-owned device output of the no-allocation search: CSR offsets
+// [nq + 1], ids and distances [capacity]; *total receives the answer count
+// (also when it exceeds the capacity, which is an ENOMEM failure).
+struct NoAllocOut {
+    int64_t *offsets;
+    int64_t *ids;
+    void *dist;
+    int64_t capacity;
+    int64_t *total;
+};
+// Largest batch of the no-allocation search (its pinned staging is sized for
+// it when the index is built).
+constexpr int64_t kNoAllocMaxQueries = 2048;
+// Pinned staging bytes a search of nq queries needs.
+size_t staging_bytes(int64_t nq);
+// Queries.  With na set, cx->arena must be set: every intermediate buffer
+// comes from the arena, the answers go to na's buffers, and the call
+// allocates no device or pinned memory.
 void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *k,
-            const gts_query_opts *opts, gts_result *out);
+            const gts_query_opts *opts, gts_result *out, const NoAllocOut *na = nullptr);
 // Copy a user object set (host or device) into host memory with fresh ids
 // starting at first_id; validates values and lengths.  angular: the rows are
 // scaled to unit length (norm in double, rounded to float); a zero row has no
@@ -372,4 +414,6 @@ struct gts_index {
     int32_t arows = 1;
     // the default query context (on `stream`)
     gts::QueryCtx ctx;
+    // the no-allocation search's context (on `stream`; pinned staging made at build)
+    gts::QueryCtx ctx_na;
 };

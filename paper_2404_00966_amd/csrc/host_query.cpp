@@ -54,8 +54,20 @@ namespace {
 
 template <class T> T *wsp(QueryCtx *cx, int slot, size_t count)
 {
-    cx->ws[slot].alloc(std::max<size_t>(count * sizeof(T), 64));
-    return cx->ws[slot].as<T>();
+    const size_t need = std::max<size_t>(count * sizeof(T), 64);
+    DevBuf &b = cx->ws[slot];
+    if (cx->arena) {
+        // no-allocation search: a view carved from the arena
+        if (!b.p || b.bytes < need) {
+            b.release();
+            b.p = cx->arena->take(need);
+            b.bytes = need;
+            b.owned = false;
+        }
+        return b.as<T>();
+    }
+    b.alloc(need);
+    return b.as<T>();
 }
 
 // Small device counters (32-bit words): [0, 1] the 64-bit candidate count,
@@ -391,8 +403,10 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     k::fill_u32(cursor, ng, 0u, st);
     k::group_hist(cands, ccount, cap, qcount, st);
     k::scan_u32(qcount, ng, qoff, st);
-    int64_t gcap = std::max<int64_t>((int64_t)(cx->ws[W_GROUPED].bytes / sizeof(k::Cand)),
-                                     std::min<int64_t>(cap, (int64_t)1 << 20));
+    // (no-allocation search: sized for every candidate the group may keep)
+    int64_t gcap = cx->arena ? cap
+                             : std::max<int64_t>((int64_t)(cx->ws[W_GROUPED].bytes / sizeof(k::Cand)),
+                                                 std::min<int64_t>(cap, (int64_t)1 << 20));
     k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, gcap);
     k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, gcap, st);
     rec(cx, 5);
@@ -466,12 +480,15 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
     // every candidate (an upper bound of the answers) unless that is large
-    if (direct && ncand * (int64_t)(sizeof(int64_t) + sizeof(float)) <= ((int64_t)256 << 20))
+    if (direct && !cx->arena && ncand * (int64_t)(sizeof(int64_t) + sizeof(float)) <= ((int64_t)256 << 20))
         go->pre = result_alloc(b.nq, ncand, result_on_device);
 
     // ---- counts of this group; its CSR piece unless the keys stay -----------
     go->direct = direct;
-    if (direct && go->pre.p && result_on_device) {
+    if (cx->arena) {
+        // no-allocation search: the caller's buffers take the result on the device
+        go->total = -1;
+    } else if (direct && go->pre.p && result_on_device) {
         // the whole result is assembled on the device: no counts to the host
         go->total = -1;
     } else {
@@ -578,8 +595,10 @@ void tune_cache_store(gts_index *idx)
     if (ok) std::rename(tmp.c_str(), idx->tune_cache.c_str());
 }
 
+size_t staging_bytes(int64_t nq) { return PinLayout(nq).bytes; }
+
 void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *radius, const int32_t *kin,
-            const gts_query_opts *opts, gts_result *out)
+            const gts_query_opts *opts, gts_result *out, const NoAllocOut *na)
 {
     const double t_start = now_ms();
     bool tune_trial = false;   // this call tries a tuner setting
@@ -642,6 +661,18 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             hbase[q] = idx->angular ? (float)(2.0 * std::sin(std::min((double)r, M_PI) / 2.0)) : r;
             b.max_radius = std::max(b.max_radius, r);
         }
+    }
+    if (na) {
+        GTS_CHECK(cx->arena != nullptr, GTS_EINVAL, "no-allocation search without its arena");
+        GTS_CHECK(nq <= kNoAllocMaxQueries, GTS_EINVAL,
+                  "the no-allocation search takes at most " + std::to_string(kNoAllocMaxQueries) + " queries");
+        GTS_CHECK(nq == 0 || Q->location == GTS_DEVICE, GTS_EINVAL, "the no-allocation search takes device queries");
+        GTS_CHECK(b.mode == GTS_MODE_BATCHED, GTS_EINVAL, "the no-allocation search runs the batched form");
+        GTS_CHECK(na->offsets != nullptr && na->total != nullptr && na->capacity >= 0, GTS_EINVAL,
+                  "no-allocation output buffers");
+        GTS_CHECK(na->capacity == 0 || (na->ids != nullptr && na->dist != nullptr), GTS_EINVAL,
+                  "no-allocation output buffers");
+        cx->timing = false;   // events would be created on first use
     }
     cx->stats = gts_stats{};
     cx->stats.nq = nq;
@@ -904,6 +935,27 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     if (budget <= 0) budget = (int64_t)1 << 32;
     const int64_t per_cand = 2 * (int64_t)sizeof(k::Cand) + (int64_t)sizeof(uint64_t);
     int64_t cap = std::max<int64_t>(budget / per_cand, 1024);
+    if (cx->arena && nq > 0) {
+        // what the group needs besides its per-candidate buffers (candidates,
+        // grouped copy, sorted keys, long-segment sort space: 56 bytes each)
+        const int64_t ntl = (nq + kQTile - 1) / kQTile;
+        const Tree &tr = d.tree;
+        size_t reserve = (size_t)1 << 20;
+        auto add = [&](size_t bytes) { reserve += Arena::align(std::max<size_t>(bytes, 64)); };
+        add(kSmallWords * sizeof(uint32_t));
+        add((size_t)tr.n_leaves * ntl * sizeof(uint64_t));           // leaf masks
+        add((size_t)tr.n_leaves * ntl * 2 * sizeof(int32_t));       // (leaf, tile) items
+        add((size_t)d.n_slabs * ntl * sizeof(int32_t));              // sweep pairs
+        add((size_t)d.n_slabs * ntl * sizeof(uint64_t));
+        add((size_t)d.n_slabs * ((ntl + k::kSweepItemTiles - 1) / k::kSweepItemTiles) * sizeof(int4));
+        for (int i = 0; i < 4; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
+        for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
+        add((size_t)nq * sizeof(int32_t));
+        const size_t left = cx->arena->left();
+        GTS_CHECK(left >= reserve + (size_t)56 * 1024, GTS_ENOMEM,
+                  "the no-allocation scratch cannot hold this batch's work lists; use a smaller batch");
+        cap = std::min<int64_t>(cap, (int64_t)((left - reserve) / 56));
+    }
     std::vector<GroupOut> groups;
     std::vector<std::pair<int64_t, int64_t>> todo;  // (q0, ng), processed front to back
     if (nq > 0) todo.push_back({0, nq});
@@ -919,6 +971,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             groups.push_back(std::move(go));
             continue;
         }
+        GTS_CHECK(!cx->arena, GTS_ENOMEM,
+                  "the batch's candidates exceed the no-allocation scratch; use a smaller batch");
         // split into halves of whole 64-query tiles
         const int64_t blocks = (ng + kQTile - 1) / kQTile;
         GTS_CHECK(blocks > 1, GTS_ENOMEM,
@@ -930,7 +984,35 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
 
     // ---- final CSR (caller's query order) ------------------------------------------------
     unsigned long long *hc = reinterpret_cast<unsigned long long *>(pin + pl.counters);
-    if (groups.size() == 1 && groups[0].total < 0) {
+    if (na) {
+        // no-allocation search: caller-order counts, their scan straight into
+        // the caller's offsets, a capacity check, then the keys in place
+        int64_t *htot = reinterpret_cast<int64_t *>(pin + pl.offs);
+        if (groups.empty()) {
+            k::fill_u32(reinterpret_cast<uint32_t *>(na->offsets), 2 * (nq + 1), 0u, st);
+        } else {
+            uint32_t *cc = wsp<uint32_t>(cx, W_TMP2, nq);
+            const int32_t *dperm = permuted ? cx->ws[W_PERM].as<int32_t>() : nullptr;
+            k::perm_counts(cx->ws[W_OUTCNT].as<uint32_t>(), dperm, nq, cc, st);
+            k::scan_u32(cc, nq, na->offsets, st);
+        }
+        GTS_HIP(hipMemcpyAsync(htot, na->offsets + nq, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(hc, counters, k::kCounterWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        const int64_t total = *htot;
+        *na->total = total;
+        GTS_CHECK(total <= na->capacity, GTS_ENOMEM,
+                  "the answers (" + std::to_string(total) + ") exceed the output capacity (" +
+                      std::to_string(na->capacity) + ")");
+        if (total > 0) {
+            const int32_t *dperm = permuted ? cx->ws[W_PERM].as<int32_t>() : nullptr;
+            k::emit_result(cx->ws[W_OUTKEYS].as<uint64_t>(), cx->ws[W_QOFF64].as<int64_t>(),
+                           cx->ws[W_OUTCNT].as<uint32_t>(), dperm, na->offsets, nq, l2 ? 0 : 1, na->ids,
+                           static_cast<float *>(na->dist), static_cast<int32_t *>(na->dist), st);
+            GTS_HIP(hipStreamSynchronize(st));
+        }
+        out->total = total;
+    } else if (groups.size() == 1 && groups[0].total < 0) {
         // one group, result on the device, storage made while verify ran:
         // caller-order counts, their scan (the result's offsets) and the keys
         // written in place, then one synchronisation for the total

@@ -103,7 +103,7 @@ EXPORTS = ("gts_build_index", "gts_range_query", "gts_knn_query", "gts_search", 
            "gts_result_copy", "gts_result_free", "gts_destroy", "gts_get_info", "gts_get_stats",
            "gts_set_timing", "gts_last_error", "gts_server_create", "gts_server_submit", "gts_server_replay",
            "gts_server_poll", "gts_server_release", "gts_server_flush", "gts_server_get_stats",
-           "gts_server_destroy")
+           "gts_server_destroy", "gts_search_noalloc")
 
 _lib = None
 
@@ -137,6 +137,8 @@ def library():
         L.gts_server_flush.argtypes = [C.c_void_p]
         L.gts_server_get_stats.argtypes = [C.c_void_p, P(_ServerStats)]
         L.gts_server_destroy.argtypes = [C.c_void_p]
+        L.gts_search_noalloc.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, C.c_void_p, P(_QueryOpts),
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
         L.gts_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "gts_last_error":
@@ -266,6 +268,31 @@ class Index:
         finally:
             L.gts_result_free(C.byref(res))
         return Result(off, ids, dist)
+
+    def search_noalloc(self, queries, radius=None, k=None, capacity=None, precision=PRECISION_DEFAULT):
+        """gts_search_noalloc: device queries, answers written into output
+        tensors allocated here (the library call itself allocates nothing).
+        Returns (Result, total).  capacity defaults to 64 answers per query."""
+        L = library()
+        keep = _Keep()
+        o = _objects(queries, self.metric, keep)
+        nq = o.n
+        r_arr = None if radius is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(radius, np.float32), (nq,)))
+        k_arr = None if k is None else np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+        cap = 64 * max(nq, 1) if capacity is None else int(capacity)
+        dev = torch.device("cuda")
+        off = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+        ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+        dt = torch.int32 if self.metric == EDIT_U8 else torch.float32
+        dist = torch.empty(max(cap, 1), dtype=dt, device=dev)
+        total = C.c_int64(0)
+        qo = _QueryOpts(MODE_BATCHED, DEVICE, 0, precision, 0)
+        torch.cuda.current_stream().synchronize()
+        _check(L.gts_search_noalloc(self._h, C.byref(o), None if r_arr is None else r_arr.ctypes.data,
+                                    None if k_arr is None else k_arr.ctypes.data, C.byref(qo), off.data_ptr(),
+                                    ids.data_ptr(), dist.data_ptr(), cap, C.byref(total)))
+        return Result(off, ids[:total.value], dist[:total.value]), total.value
 
     def range(self, queries, radius, **kw):
         return self.search(queries, radius=radius, k=None, **kw)
