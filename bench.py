@@ -182,6 +182,11 @@ def run_l2(args, gts, synth, torch, np):
     ref = idx.search(Q, radius=radius, k=k, result="device")
     st = idx.stats()
     idx.set_timing(False)
+    # one call with the bf16 bound self-check (untimed): every rechecked
+    # candidate's float32 distance against its proven interval
+    idx.search(Q, radius=radius, k=k, result="device", flags=gts.QF_CHECK_BOUND)
+    st["bound_violations"] = idx.stats()["bound_violations"]
+    st["bound_checked"] = idx.stats()["verified"]
     out = {"qps": nq * args.steps / total, "ms_per_step": ms, "per_step_ms": per, "build_s": build_s,
            "stats": st, "nq": nq, "r": r, "k": w["k"], "n": d["n"], "dim": w["dim"], "m": w["pivots"],
            "tuned": {"bound_window": st["bound_window"], "sweep_grid_per_cu": st["sweep_grid_per_cu"],
@@ -193,7 +198,8 @@ def run_l2(args, gts, synth, torch, np):
         out["host_to_host"] = {"qps": nq * args.side_steps / th, "ms_per_step": th * 1e3 / args.side_steps,
                                "p99_ms": pct(perh, 99)}
         # the same whole batch in the plain form and with float32 selection
-        for name, kw in (("plain", {"mode": gts.MODE_PLAIN}), ("fp32_selection", {"precision": gts.FP32})):
+        for name, kw in (("plain", {"mode": gts.MODE_PLAIN}), ("fp32_selection", {"precision": gts.FP32}),
+                         ("no_prune", {"flags": gts.QF_NO_PRUNE})):
             res = []
             tp, _ = timed_steps(lambda: res.append(idx.search(Q, radius=radius, k=k, result="device", **kw)),
                                 args.side_steps, 1)
@@ -270,6 +276,9 @@ def run_l4m(args, gts, synth, torch, np):
     ref = idx.knn(Q, w["k"], result="device")
     st = idx.stats()
     idx.set_timing(False)
+    idx.knn(Q, w["k"], result="device", flags=gts.QF_CHECK_BOUND)
+    st["bound_violations"] = idx.stats()["bound_violations"]
+    st["bound_checked"] = idx.stats()["verified"]
     out = {"qps": nq * steps / total, "ms_per_step": total * 1e3 / steps, "p99_ms": pct(per, 99), "nq": nq,
            "k": w["k"], "stats": st}
     for name, kw in (("fp32_selection", {"precision": gts.FP32}), ("plain", {"mode": gts.MODE_PLAIN})):
@@ -288,6 +297,114 @@ def run_l4m(args, gts, synth, torch, np):
     out["max_rel_err_vs_f64"] = worst
     out["rel_err_sample"] = "every answer of 64 random queries"
     return out
+
+
+def run_update_sweep(args, gts, synth, torch, np):
+    """Update cost against the cache-list limit (the paper's Table 5 set-up
+    on synthetic data): per limit, U updates, each deleting a random live
+    object, inserting it back (fresh id) and running one random range query;
+    the index rebuilds whenever the cache list exceeds its limit.  Then the
+    batch update: 10% of the objects deleted and inserted back in one
+    gts_update_batch call (direct reconstruction)."""
+    radii = json.load(open(os.path.join(ROOT, "oracle", "radii.json")))
+    out = {}
+    sets = {}
+    d = synth.gaussian_mixture(966101, args.update_n, 128, 100, -5.0, 5.0, 1.0, 256, 0)
+    sets["l2_d128"] = (gts.L2_F32, d["objects"], d["range_queries"], radii["l2_1m_d128"]["radius_f32"],
+                       dict(num_pivots=16, fanout=16, leaf_size=256))
+    dd = synth.dna_families(966102, max(1, args.update_n // 500), 500, 64, 128, 0.05, 1)
+    sets["dna"] = (gts.EDIT_U8, dd["objects"], dd["queries"], 8.0, dict(num_pivots=8, fanout=8))
+    rng = np.random.default_rng(966103)
+    for name, (metric, objs, queries, r, kw) in sets.items():
+        if metric == gts.L2_F32:
+            n = len(objs)
+            obj = lambda i: objs[i:i + 1]
+            qsel = lambda j: torch.from_numpy(queries[j:j + 1]).cuda()
+            nqs = len(queries)
+            dev_objs = torch.from_numpy(objs).cuda()
+        else:
+            chars, off = objs
+            n = len(off) - 1
+            obj = lambda i: (chars[off[i]:off[i + 1]], np.array([0, off[i + 1] - off[i]], np.int64))
+            qc, qo = queries
+            qsel = lambda j: (torch.from_numpy(qc[qo[j]:qo[j + 1]]).cuda(),
+                              torch.from_numpy(np.array([0, qo[j + 1] - qo[j]], np.int64)).cuda())
+            nqs = len(qo) - 1
+            dev_objs = (torch.from_numpy(chars).cuda(), torch.from_numpy(off).cuda())
+        rows = []
+        for limit in args.update_limits:
+            idx = gts.Index(dev_objs, metric, cache_limit=limit, seed=7, **kw)
+            row_of = list(range(n))          # id -> source row
+            live = list(range(n))
+            t = time.perf_counter()
+            for u in range(args.update_count):
+                j = int(rng.integers(0, len(live)))
+                victim = live[j]
+                idx.delete([victim])
+                src = row_of[victim]
+                nid = int(idx.insert(obj(src))[0])
+                live[j] = nid
+                if nid >= len(row_of):
+                    row_of.extend([0] * (nid + 1 - len(row_of)))
+                row_of[nid] = src
+                idx.range(qsel(int(rng.integers(0, nqs))), r, result="device")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            rows.append({"cache_limit": limit, "updates": args.update_count,
+                         "ms_per_update": el * 1e3 / args.update_count, "rebuilds": idx.info()["rebuilds"]})
+            log(f"update sweep {name}: {rows[-1]}")
+            idx.close()
+        # batch update: 10% deleted and inserted back in one call
+        idx = gts.Index(dev_objs, metric, seed=7, **kw)
+        gone = rng.choice(n, n // 10, replace=False)
+        if metric == gts.L2_F32:
+            back = objs[gone]
+        else:
+            back = synth.strings_from_bytes([chars[off[i]:off[i + 1]].tobytes() for i in gone])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        idx.update_batch(back, gone)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t
+        t = time.perf_counter()
+        idx2 = gts.Index(dev_objs, metric, seed=7, **kw)
+        torch.cuda.synchronize()
+        tbuild = time.perf_counter() - t
+        idx.close()
+        idx2.close()
+        out[name] = {"n": n, "sweep": rows, "batch_update_10pct_s": tb, "build_s": tbuild}
+    return out
+
+
+def run_fanout_sweep(args, gts, synth, torch, np):
+    """The cost model's preferred fanout against measured throughput (the
+    paper's node-capacity experiment on the 1M x 128 workload): per fanout,
+    build, settle the tuner, time the mixed batch; beside it the model cost
+    of a range query (sigma^2 from a seeded sample, r the workload radius)."""
+    w = synth.WORKLOADS["l2_1m_d128"]
+    r = json.load(open(os.path.join(ROOT, "oracle", "radii.json")))["l2_1m_d128"]["radius_f32"]
+    d = synth.make_workload("l2_1m_d128", queries=args.queries)
+    X = torch.from_numpy(d["objects"]).cuda()
+    Q = torch.from_numpy(np.concatenate([d["knn_queries"], d["range_queries"]])).cuda()
+    nk, nr = len(d["knn_queries"]), len(d["range_queries"])
+    k = np.array([w["k"]] * nk + [0] * nr, np.int32)
+    radius = np.full(nk + nr, r, np.float32)
+    best, costs = gts.choose_fanout(d["objects"], gts.L2_F32, r)
+    rows = []
+    for F in args.fanouts:
+        t = time.perf_counter()
+        idx = gts.Index(X, gts.L2_F32, num_pivots=w["pivots"], fanout=F, leaf_size=w["leaf"], seed=w["seed"])
+        build_s = time.perf_counter() - t
+        for _ in range(16):
+            idx.search(Q, radius=radius, k=k, result="device")
+            if idx.stats()["tuning"] == 0:
+                break
+        total, per = timed_steps(lambda: idx.search(Q, radius=radius, k=k, result="device"), args.steps, 1)
+        rows.append({"fanout": F, "levels": idx.info()["levels"], "build_s": build_s,
+                     "qps": (nk + nr) * args.steps / total, "model_cost": float(costs[F - 2])})
+        log(f"fanout sweep: {rows[-1]}")
+        idx.close()
+    return {"model_choice": best, "rows": rows, "radius": r}
 
 
 def cpu_model():
@@ -654,6 +771,26 @@ def pmc_summary(dirs, workload, last, command):
     return "\n".join(lines)
 
 
+def stats_summary(d, title, command, top):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics: {title}", "", "Command (repository root, one MI355X):", "", "```",
+             *command, "```", "", "| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"]
+        m = re.search(r"(k_[A-Za-z0-9_]+(<[^>]*>)?)", name)
+        short = m.group(1) if m else name.split("(")[0][-60:]
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:,.1f} | {float(r['MinNs']) / 1e3:,.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:,.1f} | {float(r['TotalDurationNs']) / 1e6:,.2f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -672,6 +809,17 @@ def main():
     ap.add_argument("--pmc-workload", default="l2_1m_d128")
     ap.add_argument("--pmc-last", type=int, default=2)
     ap.add_argument("--pmc-command", action="append", default=[])
+    ap.add_argument("--stats-summary", metavar="DIR", help="summarise a rocprofv3 --stats run in DIR (no GPU work)")
+    ap.add_argument("--stats-title", default="bench.py")
+    ap.add_argument("--stats-top", type=int, default=40)
+    ap.add_argument("--update-sweep", action="store_true",
+                    help="update cost against the cache-list limit and the batch update, instead of the benchmark")
+    ap.add_argument("--update-n", type=int, default=100000, help="objects of the update-sweep sets")
+    ap.add_argument("--update-count", type=int, default=1000)
+    ap.add_argument("--update-limits", type=int, nargs="+", default=[16, 64, 256, 1024, 4096])
+    ap.add_argument("--fanout-sweep", action="store_true",
+                    help="measured throughput against the cost model's fanout choice, instead of the benchmark")
+    ap.add_argument("--fanouts", type=int, nargs="+", default=[4, 8, 16, 32, 64])
     ap.add_argument("--serving", action="store_true", help="run the serving mix instead of the batch benchmark")
     ap.add_argument("--serve-rate", type=float, default=50000.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-s", type=float, default=4.0, help="measured trace length, s")
@@ -682,6 +830,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(args.pmc_summary, args.pmc_workload, args.pmc_last, args.pmc_command))
+        return
+    if args.stats_summary:
+        print(stats_summary(args.stats_summary, args.stats_title, args.pmc_command, args.stats_top))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path; "
@@ -697,6 +848,28 @@ def main():
     gts.library()
     if args.calibrate_copy:
         calibrate_copy(torch)
+    if args.fanout_sweep:
+        fs = run_fanout_sweep(args, gts, synth, torch, np)
+        best = max(fs["rows"], key=lambda r: r["qps"])
+        line = {"metric": "queries/s against the fanout (1M x 128 mixed batch)", "value": best["qps"],
+                "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": None,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/f32",
+                "data": "synthetic (seeded Gaussian mixture)",
+                "config": {"workload": "fanout_sweep_l2_1m_d128", "fanouts": args.fanouts}, "fanout_sweep": fs}
+        print(json.dumps(line), flush=True)
+        return
+    if args.update_sweep:
+        us = run_update_sweep(args, gts, synth, torch, np)
+        best = min(us["l2_d128"]["sweep"], key=lambda r: r["ms_per_update"])
+        line = {"metric": "ms per streamed update (delete + reinsert + one range query), best cache-list limit",
+                "value": best["ms_per_update"], "unit": "ms", "n_gpus": 1, "steps": args.update_count, "warmup": 0,
+                "ms_per_step": best["ms_per_update"], "higher_is_better": False, "scaling": "weak",
+                "vs_baseline": None, "dtype": "bf16-mfma/f32 (L2), int32 (edit)",
+                "data": "synthetic (seeded mixture / DNA families)",
+                "config": {"workload": "update_sweep", "n": args.update_n, "limits": args.update_limits},
+                "update_sweep": us}
+        print(json.dumps(line), flush=True)
+        return
     if args.serving:
         sv = run_serving(args, gts, synth, torch, np)
         m = sv["measured"]
@@ -756,9 +929,11 @@ def main():
         "host_to_host": l2.get("host_to_host"),
         "plain": l2.get("plain"),
         "fp32_selection": l2.get("fp32_selection"),
+        "no_prune": l2.get("no_prune"),
         "stage_ms": st["ms_stage"],
         "counters": {k: st[k] for k in ("node_tests", "tile_pairs", "own_pairs", "candidates", "verified",
-                                        "results", "bound_evals", "wide_queries", "bound_violations")},
+                                        "results", "bound_evals", "wide_queries", "bound_violations",
+                                        "bound_checked")},
         "build_s": l2["build_s"],
         "tuned": l2["tuned"],
         "roofline": roof,
@@ -779,7 +954,7 @@ def main():
         line["l2_4m_d96"] = {k: v for k, v in c4.items() if k != "stats"}
         line["l2_4m_d96"]["stage_ms"] = c4["stats"]["ms_stage"]
         line["l2_4m_d96"]["counters"] = {k: c4["stats"][k] for k in ("own_pairs", "candidates", "verified",
-                                                                     "bound_violations")}
+                                                                     "bound_violations", "bound_checked")}
     print(json.dumps(line), flush=True)
 
 

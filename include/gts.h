@@ -129,6 +129,11 @@ typedef struct {
                                 and count failures in gts_stats.
                                 bound_violations (a self-check; answers do not
                                 change, verification slows by about a third) */
+#define GTS_QF_NO_PRUNE 2    /* L2 batched: a control without the tree -- every
+                                (leaf, query) pair kept, so the selection tiles
+                                cover every object for every query, as a dense
+                                distance table would (kNN radii still come from
+                                the nearest leaves' objects).  Same answers.  */
 
 /* Answers in CSR form: the answer of query i is entries
  * offsets[i] .. offsets[i+1] of ids / dist.  Owned by the library. */
@@ -250,6 +255,34 @@ gts_status gts_insert(gts_index *idx, const gts_objects *objs, int64_t *out_ids)
  * array [n].  Unknown or already deleted ids are ignored; *n_deleted (may be
  * NULL) receives the number actually deleted. */
 gts_status gts_delete(gts_index *idx, const int64_t *ids, int64_t n, int64_t *n_deleted);
+
+/* Batch update (Sec. 4.4, batch updates): for bulk changes the index is
+ * reconstructed directly instead of going through the cache list.  The ids
+ * del_ids (host array [n_del]; unknown or deleted ids are ignored) are
+ * deleted, the objects objs (may be NULL) are inserted with fresh ids
+ * (out_ids, host [objs->n], may be NULL), and the index is rebuilt over every
+ * live object, the cache list included (which ends empty).  *n_deleted (may
+ * be NULL) receives the number of ids actually deleted. */
+gts_status gts_update_batch(gts_index *idx, const gts_objects *objs, const int64_t *del_ids, int64_t n_del,
+                            int64_t *out_ids, int64_t *n_deleted);
+
+/* Cost model of a range query (Sec. 5.3, Eq. 2-3) over n objects with node
+ * capacity (fanout) F:
+ *   cost(F) = sum_{i=1..L} i^2 * ceil(F^i p^i / C) * log2(F)^2,
+ * L = ceil(log_F n) layers, p = 1 - 2 sigma^2 / r^2 (the Chebyshev lower
+ * bound of the probability that a pivot fails to prune an object; sigma^2
+ * the variance of object-to-pivot distances, r the radius) clamped to
+ * [0, 1], C the GPU's concurrency (threads in flight), each layer at least
+ * one round.  NaN for n < 1, F < 2 or C <= 0.  Pure host arithmetic. */
+double gts_cost_model(int64_t n, int32_t fanout, double sigma2, double radius, double concurrency);
+
+/* The fanout in [2, 64] the cost model prefers for an object set (or a
+ * sample of one; n is taken as objs->n): sigma^2 from the distances of up to
+ * 2,048 seeded sample objects to one seeded sample pivot, radius r (for
+ * GTS_COSINE_F32 an angle), concurrency C (<= 0: CUs x 2,048 of the current
+ * device).  costs (may be NULL): [63] model cost of fanouts 2..64. */
+gts_status gts_choose_fanout(const gts_objects *objs, int32_t metric, float radius, double concurrency,
+                             int32_t *fanout, double *costs);
 
 /* Copy a result into caller-provided buffers (same location kind as each
  * pointer: dst_location GTS_HOST or GTS_DEVICE); any pointer may be NULL. */

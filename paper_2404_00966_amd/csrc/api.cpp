@@ -149,6 +149,21 @@ gts_status gts_insert(gts_index *idx, const gts_objects *objs, int64_t *out_ids)
     });
 }
 
+gts_status gts_update_batch(gts_index *idx, const gts_objects *objs, const int64_t *del_ids, int64_t n_del,
+                            int64_t *out_ids, int64_t *n_deleted)
+{
+    return guarded([&] {
+        GTS_CHECK(idx != nullptr, GTS_EINVAL, "null index");
+        GTS_CHECK(n_del >= 0, GTS_EINVAL, "negative count");
+        GTS_CHECK(del_ids != nullptr || n_del == 0, GTS_EINVAL, "null ids");
+        HostObjects h;
+        h.metric = idx->data.metric;
+        h.dim = idx->data.dim;
+        if (objs) read_objects(objs, idx->data.metric, idx->data.dim, idx->opts.max_strlen, &h, idx->angular);
+        update_batch(idx, h, del_ids, n_del, out_ids, n_deleted);
+    });
+}
+
 gts_status gts_delete(gts_index *idx, const int64_t *ids, int64_t n, int64_t *n_deleted)
 {
     return guarded([&] {

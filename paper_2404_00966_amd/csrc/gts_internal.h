@@ -54,7 +54,7 @@ constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
 constexpr int kSortCap = 2048;      // edit distance: per-query keys sorted in LDS (more: global scratch)
 constexpr int kSortCapL2 = 4096;    // L2: per-query keys sorted in LDS (more: global scratch)
 constexpr int kWaveSortCap = 1024;  // L2: per-query keys verified and sorted by one wave
-constexpr int kWorkspaceSlots = 64;   // named query buffers of an index
+constexpr int kWorkspaceSlots = 72;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 
 // Device buffer owned by the index (hipMalloc / hipFree), or a view of
@@ -207,7 +207,11 @@ void rows_to_device(float *dst, int dp, const float *src, int dim, int64_t n, bo
 void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars);
 // Streamed updates.
 void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids);
-int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n);
+// upload = false: host bookkeeping only (a rebuild follows).
+int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload = true);
+// Batch update: deletions, insertions (fresh ids into out_ids), one rebuild.
+void update_batch(gts_index *idx, const HostObjects &ins, const int64_t *del, int64_t n_del, int64_t *out_ids,
+                  int64_t *n_deleted);
 // Per-stream query state: the workspace, timing events and statistics of
 // the searches issued on one stream.  An index has a default context on its
 // own stream; more contexts let searches of one index run concurrently (the
@@ -411,6 +415,7 @@ struct gts_index {
     // on them, every match table is built at query time.
     bool alpha[256] = {};
     gts::DevBuf lut;                   // uint8 [256]
+    gts::DevBuf upd_buf;               // upload space of delete batches (grown, reused)
     int32_t arows = 1;
     // the default query context (on `stream`)
     gts::QueryCtx ctx;

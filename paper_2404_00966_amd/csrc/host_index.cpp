@@ -726,12 +726,14 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     if (c.n_live > limit) rebuild(idx);
 }
 
-int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n)
+int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
 {
     hipStream_t st = idx->stream;
     CacheList &c = idx->cache;
     int64_t done = 0;
-    bool tree_changed = false;
+    // the device words this batch changes: (word index, new value) pairs,
+    // applied by one scatter launch (cache-list live flags and tombstone words)
+    std::vector<uint32_t> live_at, tomb_at;
     for (int64_t i = 0; i < n; i++) {
         const int64_t id = ids[i];
         if (id < 0 || id >= idx->next_id) continue;
@@ -740,9 +742,7 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n)
             if (c.h_live[s]) {
                 c.h_live[s] = 0;
                 c.n_live--;
-                const uint32_t zero = 0;
-                GTS_HIP(hipMemcpyAsync(c.live.as<uint32_t>() + s, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
-                GTS_HIP(hipStreamSynchronize(st));
+                live_at.push_back((uint32_t)s);
                 idx->slot_of_id[id] = -1;
                 done++;
             }
@@ -753,21 +753,73 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n)
             if (!idx->h_tomb[p]) {
                 idx->h_tomb[p] = 1;
                 idx->n_deleted_tree++;
-                tree_changed = true;
+                tomb_at.push_back((uint32_t)(p >> 5));
                 done++;
             }
         }
     }
-    if (tree_changed) {
-        const IndexData &d = idx->data;
-        const int64_t words = (std::max(d.npad, d.n) + 31) / 32 + 1;
-        std::vector<uint32_t> bits(words, 0u);
-        for (int64_t p = 0; p < d.n; p++)
-            if (idx->h_tomb[p]) bits[p >> 5] |= 1u << (p & 31);
-        GTS_HIP(hipMemcpyAsync(d.tomb.p, bits.data(), words * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        GTS_HIP(hipStreamSynchronize(st));
+    if (!upload || (live_at.empty() && tomb_at.empty())) return done;
+    std::sort(tomb_at.begin(), tomb_at.end());
+    tomb_at.erase(std::unique(tomb_at.begin(), tomb_at.end()), tomb_at.end());
+    const IndexData &d = idx->data;
+    // [live slots | tombstone words | values]; one transfer, then the scatters
+    const size_t nl = live_at.size(), nt = tomb_at.size();
+    std::vector<uint32_t> pack(2 * (nl + nt));
+    for (size_t i = 0; i < nl; i++) {
+        pack[i] = live_at[i];
+        pack[nl + nt + i] = 0u;
     }
+    for (size_t i = 0; i < nt; i++) {
+        const int64_t w = tomb_at[i];
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; b++) {
+            const int64_t p = w * 32 + b;
+            if (p < d.n && idx->h_tomb[p]) bits |= 1u << b;
+        }
+        pack[nl + i] = (uint32_t)w;
+        pack[2 * nl + nt + i] = bits;
+    }
+    DevBuf &dp = idx->upd_buf;
+    dp.alloc(pack.size() * sizeof(uint32_t));
+    GTS_HIP(hipMemcpyAsync(dp.p, pack.data(), pack.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    const uint32_t *dpk = dp.as<uint32_t>();
+    if (nl) k::scatter_u32(c.live.as<uint32_t>(), dpk, dpk + nl + nt, (int64_t)nl, st);
+    if (nt) k::scatter_u32(d.tomb.as<uint32_t>(), dpk + nl, dpk + 2 * nl + nt, (int64_t)nt, st);
+    GTS_HIP(hipStreamSynchronize(st));
     return done;
+}
+
+// Batch updates (Sec. 4.4): for bulk changes the index is reconstructed
+// directly instead of going through the cache list.  Deletions are marked,
+// the new objects take fresh ids, and one rebuild covers every live object
+// of the tree, the cache list and the batch.
+void update_batch(gts_index *idx, const HostObjects &ins, const int64_t *del, int64_t n_del, int64_t *out_ids,
+                  int64_t *n_deleted)
+{
+    const int64_t n = ins.count();
+    GTS_CHECK(idx->next_id + n < ((int64_t)1 << 31), GTS_ENOTSUP, "id space exhausted (ids stay below 2^31)");
+    const int64_t done = delete_ids(idx, del, n_del, false);
+    if (n_deleted) *n_deleted = done;
+    HostObjects &ch = idx->cache_host;
+    ch.metric = idx->data.metric;
+    ch.dim = idx->data.dim;
+    if ((int64_t)idx->slot_of_id.size() < idx->next_id + n) idx->slot_of_id.resize(idx->next_id + n, -1);
+    if ((int64_t)idx->pos_of_id.size() < idx->next_id + n) idx->pos_of_id.resize(idx->next_id + n, -1);
+    for (int64_t i = 0; i < n; i++) {
+        const uint32_t id = (uint32_t)idx->next_id++;
+        if (out_ids) out_ids[i] = id;
+        if (ins.metric == GTS_L2_F32) {
+            ch.vecs.insert(ch.vecs.end(), ins.vecs.begin() + i * ins.dim, ins.vecs.begin() + (i + 1) * ins.dim);
+        } else {
+            ch.chars.insert(ch.chars.end(), ins.chars.begin() + ins.offsets[i], ins.chars.begin() + ins.offsets[i + 1]);
+            ch.offsets.push_back((int64_t)ch.chars.size());
+        }
+        ch.ids.push_back(id);
+        idx->cache.h_ids.push_back(id);
+        idx->cache.h_live.push_back(1);
+    }
+    if (ins.metric != GTS_L2_F32 && n) alphabet_add(idx, ins.chars);
+    rebuild(idx);
 }
 
 // Rebuild over every live object (Sec. 4.4: when the cache list exceeds its

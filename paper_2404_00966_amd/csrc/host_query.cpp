@@ -252,6 +252,7 @@ struct Batch {
     int precision = GTS_BF16_GUARDED;   // L2 candidate selection (batched form)
     int sweep_grid_per_cu = 2;          // MFMA sweep workgroups per CU (tuned)
     bool check_bound = false;           // count bf16 interval violations
+    bool no_prune = false;              // L2 control: every (leaf, query) pair kept
 };
 
 void rec(QueryCtx *cx, int i)
@@ -330,7 +331,9 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         uint64_t *mask = wsp<uint64_t>(cx, W_MASK, (size_t)t.n_leaves * ntiles);
         int32_t *items = nullptr;
         const int64_t item_cap = t.n_leaves * ntiles;
-        if (l2) {
+        if (l2 && b.no_prune) {
+            k::fill_u32(reinterpret_cast<uint32_t *>(mask), (int64_t)2 * t.n_leaves * ntiles, 0xffffffffu, st);
+        } else if (l2) {
             k::leaf_box(tv, QP, thr, ng, ntiles, mask, counters, st);
         } else {
             // leaves of the cells that passed (cell masks of the whole batch,
@@ -342,7 +345,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
                               cx->ws[W_QCELLS].as<int32_t>() + q0 * k::kQueryCells, cx->ws[W_QCNT].as<int32_t>() + q0,
                               T, ng, ntiles, b.max_qlen, mask, items, small + kSmallItems, item_cap, t.n_leaves, st);
         }
-        if (l2 && d.lpad > 0)
+        if (l2 && d.lpad > 0 && !b.no_prune)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
                          d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, t.leaf_cnt.as<int32_t>(), counters, st);
         k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
@@ -617,8 +620,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     b.precision = opts && opts->precision != GTS_PRECISION_DEFAULT ? opts->precision : idx->opts.precision;
     if (b.precision == GTS_PRECISION_DEFAULT) b.precision = GTS_BF16_GUARDED;
     GTS_CHECK(b.precision == GTS_BF16_GUARDED || b.precision == GTS_FP32, GTS_EINVAL, "bad precision");
-    GTS_CHECK(!opts || (opts->flags & ~GTS_QF_CHECK_BOUND) == 0, GTS_EINVAL, "unknown gts_query_opts.flags bits");
+    GTS_CHECK(!opts || (opts->flags & ~(GTS_QF_CHECK_BOUND | GTS_QF_NO_PRUNE)) == 0, GTS_EINVAL,
+              "unknown gts_query_opts.flags bits");
     b.check_bound = opts && (opts->flags & GTS_QF_CHECK_BOUND);
+    b.no_prune = opts && (opts->flags & GTS_QF_NO_PRUNE);
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;

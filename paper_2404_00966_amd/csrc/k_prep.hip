@@ -226,6 +226,20 @@ void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, 
     check_launch(__func__);
 }
 
+__global__ void k_scatter_u32(uint32_t *__restrict__ dst, const uint32_t *__restrict__ at,
+                              const uint32_t *__restrict__ val, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[at[i]] = val[i];
+}
+
+void scatter_u32(uint32_t *dst, const uint32_t *at, const uint32_t *val, int64_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_scatter_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, at, val, n);
+    check_launch(__func__);
+}
+
 // out[q] = a[q] + b[q] for q < n, -inf for n <= q < npad (padding rows of a
 // query tile never pass a threshold).
 __global__ void k_sum_pad(const float *__restrict__ a, const float *__restrict__ b, int64_t n, int64_t npad,

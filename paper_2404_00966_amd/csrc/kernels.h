@@ -70,6 +70,8 @@ void build_peq(const uint8_t *chars, const int64_t *off, int64_t nq, const uint8
 void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t nq, int mpad, int is_edit,
                 float delta, float pt_max, float *T, float *thr, float *cut, hipStream_t st);
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+// dst[at[i]] = val[i] for i < n (the changed words of a delete batch)
+void scatter_u32(uint32_t *dst, const uint32_t *at, const uint32_t *val, int64_t n, hipStream_t st);
 // Rows scaled to unit length in place (norm in double, result rounded to
 // float); a row with zero or non-finite norm becomes zero and sets *bad.
 void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgts.so")
 L2_F32, EDIT_U8, COSINE_F32 = 1, 2, 3
 HOST, DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
-QF_CHECK_BOUND = 1
+QF_CHECK_BOUND, QF_NO_PRUNE = 1, 2
 PRECISION_DEFAULT, BF16_GUARDED, FP32 = 0, 1, 2
 STAGES = ("prep", "bound", "nodes", "cands", "group", "verify", "output", "plain")
 
@@ -103,7 +103,7 @@ EXPORTS = ("gts_build_index", "gts_range_query", "gts_knn_query", "gts_search", 
            "gts_result_copy", "gts_result_free", "gts_destroy", "gts_get_info", "gts_get_stats",
            "gts_set_timing", "gts_last_error", "gts_server_create", "gts_server_submit", "gts_server_replay",
            "gts_server_poll", "gts_server_release", "gts_server_flush", "gts_server_get_stats",
-           "gts_server_destroy", "gts_search_noalloc")
+           "gts_server_destroy", "gts_update_batch", "gts_cost_model", "gts_choose_fanout", "gts_search_noalloc")
 
 _lib = None
 
@@ -123,6 +123,10 @@ def library():
         L.gts_knn_query.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, P(_QueryOpts), P(_Result)]
         L.gts_insert.argtypes = [C.c_void_p, P(_Objects), C.c_void_p]
         L.gts_delete.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.gts_cost_model.restype = C.c_double
+        L.gts_cost_model.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_double]
+        L.gts_choose_fanout.argtypes = [P(_Objects), C.c_int32, C.c_float, C.c_double, P(C.c_int32), C.c_void_p]
+        L.gts_update_batch.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, C.c_int64, C.c_void_p, P(C.c_int64)]
         L.gts_result_copy.argtypes = [P(_Result), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gts_result_free.argtypes = [P(_Result)]
         L.gts_destroy.argtypes = [C.c_void_p]
@@ -141,7 +145,7 @@ def library():
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
         L.gts_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name != "gts_last_error":
+            if name not in ("gts_last_error", "gts_cost_model"):
                 getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -204,6 +208,22 @@ class Result:
         ids = self.ids.cpu().numpy()
         dist = self.dist.cpu().numpy()
         return [(ids[off[q]:off[q + 1]], dist[off[q]:off[q + 1]]) for q in range(len(off) - 1)]
+
+
+def cost_model(n, fanout, sigma2, radius, concurrency):
+    """gts_cost_model: the range-query cost bound of the paper's cost model."""
+    return library().gts_cost_model(int(n), int(fanout), float(sigma2), float(radius), float(concurrency))
+
+
+def choose_fanout(objects, metric, radius, concurrency=0.0):
+    """gts_choose_fanout: (best fanout, model costs of fanouts 2..64)."""
+    keep = _Keep()
+    o = _objects(objects, metric, keep)
+    best = C.c_int32(0)
+    costs = np.zeros(63, np.float64)
+    _check(library().gts_choose_fanout(C.byref(o), metric, float(radius), float(concurrency), C.byref(best),
+                                       costs.ctypes.data))
+    return best.value, costs
 
 
 class Index:
@@ -313,6 +333,20 @@ class Index:
         n = C.c_int64(0)
         _check(library().gts_delete(self._h, a.ctypes.data if a.size else None, a.size, C.byref(n)))
         return n.value
+
+    def update_batch(self, objects=None, delete_ids=()):
+        """Delete ids and insert objects together, then rebuild (returns the
+        new ids and the number of ids deleted)."""
+        keep = _Keep()
+        o = _objects(objects, self.metric, keep) if objects is not None else None
+        n_new = o.n if o is not None else 0
+        ids = np.zeros(max(n_new, 1), np.int64)
+        d = np.ascontiguousarray(np.asarray(delete_ids, np.int64).reshape(-1))
+        nd = C.c_int64(0)
+        _check(library().gts_update_batch(self._h, C.byref(o) if o is not None else None,
+                                          d.ctypes.data if d.size else None, d.size, ids.ctypes.data,
+                                          C.byref(nd)))
+        return ids[:n_new], nd.value
 
     # -- inspection ----------------------------------------------------------
     def info(self):

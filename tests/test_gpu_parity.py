@@ -435,3 +435,91 @@ def test_l2_precision_fp32_matches_oracle(gts, mode):
     objs = O.ObjectSet(vecs=X)
     check_range(res[:150], O.range_bf(objs, O.ObjectSet(vecs=Q[:150]), 5.5), X, Q[:150], 5.5)
     check_knn(res[150:], O.knn_bf(objs, O.ObjectSet(vecs=Q[150:]), 17), X, Q[150:], 17)
+
+
+@pytest.mark.parametrize("metric", ["l2", "edit"])
+def test_batch_update_rebuilds_and_matches_oracle(gts, metric):
+    """The batch update of Sec. 4.4: 10% of the objects deleted and inserted
+    back (fresh ids) in one call, with streamed inserts already waiting in
+    the cache list; the index is rebuilt and answers match the oracle over
+    the live set."""
+    rng = np.random.default_rng(60)
+    if metric == "l2":
+        d = synth.gaussian_mixture(61, 6000, 24, 10, -5.0, 5.0, 1.0, 80, 80)
+        X = d["objects"]
+        Q = np.concatenate([d["range_queries"], d["knn_queries"]])
+        idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=6, fanout=6, leaf_size=48, seed=2, cache_limit=100000)
+        objs_all = [X[i] for i in range(len(X))]
+    else:
+        dd = synth.dna_families(62, 30, 100, 50, 90, 0.05, 3)
+        chars, off = dd["objects"]
+        qc, qo = dd["queries"]
+        idx = gts.Index((_dev(chars), _dev(off)), gts.EDIT_U8, num_pivots=5, fanout=5, seed=3, cache_limit=100000)
+        objs_all = [chars[off[i]:off[i + 1]].tobytes() for i in range(len(off) - 1)]
+    n0 = len(objs_all)
+    _say(f"batch update {metric} n={n0}")
+    # a few streamed inserts first (they sit in the cache list)
+    pre = objs_all[:25]
+    pre_ids = idx.insert(np.stack(pre) if metric == "l2" else synth.strings_from_bytes(pre))
+    assert idx.info()["n_cache"] == 25
+    gone = rng.choice(n0, n0 // 10, replace=False)
+    back = [objs_all[i] for i in gone]
+    new_ids, nd = idx.update_batch(np.stack(back) if metric == "l2" else synth.strings_from_bytes(back), gone)
+    assert nd == len(gone) and len(new_ids) == len(gone)
+    info = idx.info()
+    assert info["n_cache"] == 0 and info["rebuilds"] == 1 and info["n_live"] == n0 + 25
+    live = {i: objs_all[i] for i in range(n0) if i not in set(gone.tolist())}
+    live.update({int(i): o for i, o in zip(pre_ids, pre)})
+    live.update({int(i): o for i, o in zip(new_ids, back)})
+    ids = np.array(sorted(live), np.int64)
+    if metric == "l2":
+        Xl = np.stack([live[int(i)] for i in ids]).astype(np.float32)
+        oset = O.ObjectSet(vecs=Xl, ids=ids)
+        r = 5.0
+        k = np.array([0] * 80 + [14] * 80, np.int32)
+        res = idx.search(_dev(Q), radius=np.full(160, r, np.float32), k=k).to_lists()
+        row = {int(i): j for j, i in enumerate(ids)}
+        check_range(res[:80], O.range_bf(oset, O.ObjectSet(vecs=Q[:80]), r), Xl, Q[:80], r, id_to_row=row)
+        check_knn(res[80:], O.knn_bf(oset, O.ObjectSet(vecs=Q[80:]), 14), Xl, Q[80:], 14, id_to_row=row)
+    else:
+        sc, so = synth.strings_from_bytes([live[int(i)] for i in ids])
+        oset = O.ObjectSet(strings=(sc, so), ids=ids)
+        nq = len(qo) - 1
+        k = np.array([0, 4] * (nq // 2) + [0] * (nq % 2), np.int32)
+        res = idx.search((_dev(qc), _dev(qo)), radius=np.full(nq, 6.0, np.float32), k=k).to_lists()
+        for q in range(nq):
+            qs = O.ObjectSet(strings=(qc[qo[q]:qo[q + 1]], np.array([0, qo[q + 1] - qo[q]], np.int64)))
+            ref = O.knn_bf(oset, qs, 4)[0] if k[q] else O.range_bf(oset, qs, 6.0)[0]
+            check_exact([res[q]], [ref])
+    idx.close()
+
+
+def test_no_prune_control_gives_same_answers(gts):
+    """GTS_QF_NO_PRUNE (every (leaf, query) pair kept, the dense control)
+    returns the answers of the pruned search; it computes more tiles."""
+    d = synth.gaussian_mixture(71, 20000, 96, 20, -5.0, 5.0, 1.0, 200, 200)
+    X = d["objects"]
+    Q = np.concatenate([d["range_queries"], d["knn_queries"]])
+    _say("no-prune control")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=8, fanout=8, leaf_size=64, seed=4)
+    k = np.array([0] * 200 + [10] * 200, np.int32)
+    radius = np.full(400, 9.0, np.float32)
+    a = idx.search(_dev(Q), radius=radius, k=k).to_lists()
+    tiles_pruned = idx.stats()["tile_pairs"]
+    b = idx.search(_dev(Q), radius=radius, k=k, flags=gts.QF_NO_PRUNE).to_lists()
+    tiles_dense = idx.stats()["tile_pairs"]
+    idx.close()
+    assert tiles_dense > tiles_pruned
+    for x, y in zip(a, b):
+        assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+
+
+def test_choose_fanout_from_a_sample(gts):
+    d = synth.make_workload("l2_10k_d16")
+    _say("choose fanout")
+    best, costs = gts.choose_fanout(d["objects"], gts.L2_F32, 2.0, concurrency=1e5)
+    assert 2 <= best <= 64 and np.all(np.isfinite(costs))
+    assert costs[best - 2] == costs.min()
+    dd = synth.dna_families(81, 10, 20, 40, 60, 0.05, 0)
+    best_e, costs_e = gts.choose_fanout(dd["objects"], gts.EDIT_U8, 6.0, concurrency=1e5)
+    assert 2 <= best_e <= 64 and costs_e[best_e - 2] == costs_e.min()
