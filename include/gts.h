@@ -181,6 +181,9 @@ typedef struct {
                                 (once per surviving (leaf, 64-query tile))     */
     int64_t sweep_grid_per_cu; /* L2 bf16 path: MFMA sweep workgroups per CU
                                 in this call (the second tuned knob)           */
+    int64_t group_retries;   /* query groups whose candidates overflowed the
+                                memory budget and were split again (sized
+                                from the attempt's counts)                     */
 } gts_stats;
 
 #define GTS_STAGE_PREP 0     /* query -> pivot distances, query tiles          */

@@ -231,7 +231,7 @@ gts_status gts_get_info(const gts_index *idx, gts_index_info *out)
         int64_t bytes = 0;
         for (const DevBuf *b : {&d.X32, &d.X16t, &d.xn, &d.xe, &d.P32, &d.PT, &d.slab_emax, &d.slab_nmax,
                                 &d.slab_leaf_lo, &d.slab_leaf_hi, &d.chars, &d.soff, &d.PTe, &d.PTa, &d.pchars,
-                                &d.poff, &d.ids, &d.tomb, &d.tree.box_aos, &d.tree.box_lo, &d.tree.box_hi,
+                                &d.poff, &d.ids, &d.tomb, &d.del_ep, &d.tree.box_aos, &d.tree.box_lo, &d.tree.box_hi,
                                 &d.tree.leaf_first, &d.tree.leaf_cnt})
             bytes += (int64_t)b->bytes;
         out->device_bytes = bytes;

@@ -154,7 +154,10 @@ struct IndexData {
     // both
     float pt_max = 0.f;          // largest pivot-table value
     DevBuf ids;                  // uint32 [n] id at each position
-    DevBuf tomb;                 // uint32 [(n+31)/32] deleted positions
+    DevBuf tomb;                 // uint32 [tomb_words] deleted positions (bit per position)
+    DevBuf del_ep;               // uint32 [32 tomb_words] epoch of the update that deleted the
+                                 // position (0xffffffff: live)
+    int64_t tomb_words = 0;
     Tree tree;
 };
 
@@ -165,7 +168,9 @@ struct CacheList {
     DevBuf chars;                 // uint8 [cap * kMaxStrlen] (EDIT, fixed slots)
     DevBuf slen;                  // int32 [cap]
     DevBuf ids;                   // uint32 [cap]
-    DevBuf live;                  // uint32 [cap] 1 = live
+    DevBuf ins_ep, del_ep;        // uint32 [cap] epochs of the slot's insert and delete
+                                  // (del_ep 0xffffffff: live)
+    DevBuf cp;                    // float [cap][mpad] distances to the global pivots
     std::vector<uint32_t> h_ids;
     std::vector<uint8_t> h_live;
     int64_t n_live = 0;           // live cached objects
@@ -192,8 +197,9 @@ struct HostObjects {
     }
 };
 
-// Build the tree and all device tables of `idx` over `objs` (ids given).
-void build_tree(gts_index *idx, const HostObjects &objs);
+// Build the tree and all device tables of `idx` over `objs` (ids given);
+// objs becomes the index's host mirror (moved from).
+void build_tree(gts_index *idx, HostObjects &objs);
 // Rebuild over every live object (tree and cache), keeping ids.
 void rebuild(gts_index *idx);
 // Copy n rows of dim floats (src, packed) into device rows of dp floats
@@ -312,9 +318,25 @@ struct Arena {
     }
 };
 
+// What a server batch sees of an index that keeps changing while it runs.
+// Every update has an epoch (the index's counter after the update); a query
+// admitted at epoch e sees the tree positions not deleted by updates of
+// epoch <= e and the cache slots inserted, and not deleted, by them.  The
+// batch reads the cache slots below cache_count only (later inserts go to
+// higher slots); producers run on the tombstones of the earliest epoch of the
+// batch, the kNN bounds on those of the latest, and each candidate is then
+// checked against its own query's epoch.
+struct SnapView {
+    bool on = false;
+    std::vector<uint32_t> qep;         // epoch of each query (caller order)
+    int64_t cache_count = 0;
+    uint32_t e_min = 0, e_max = 0;
+};
+
 struct QueryCtx {
     hipStream_t stream = nullptr;
     Arena *arena = nullptr;            // set: every workspace buffer is carved from it
+    SnapView view;                     // on: the search follows these epochs (server batches)
     DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
     void *pin = nullptr;               // pinned host staging for small device-to-host reads
     size_t pin_bytes = 0;
@@ -393,12 +415,14 @@ struct gts_index {
     hipStream_t stream = nullptr;
     gts::IndexData data;
     gts::CacheList cache;
-    gts::HostObjects host;             // objects of the tree, by position
+    gts::HostObjects host;             // objects of the tree, in the order they were built from
+    std::vector<int32_t> host_row;     // position -> row of `host`
     gts::HostObjects cache_host;       // objects of the cache list, by slot
     std::vector<uint8_t> h_tomb;       // host mirror of the tombstones
     std::vector<int64_t> pos_of_id;    // id -> tree position (-1: not in tree)
     std::vector<int64_t> slot_of_id;   // id -> cache slot (-1: not in cache)
     int64_t next_id = 0;
+    uint32_t epoch = 0;                // updates applied so far (each insert or delete call: one)
     int64_t n_deleted_tree = 0;
     int64_t rebuilds = 0;
     int32_t num_pivots = 0, fanout = 0;

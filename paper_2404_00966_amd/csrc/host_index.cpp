@@ -125,23 +125,14 @@ void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars)
     upload(idx->lut, lut, idx->stream);
 }
 
-void build_tree(gts_index *idx, const HostObjects &objs)
+namespace {
+
+// Tree shape: levels, node ids of the leaves, node count (Eq. 1 numbering).
+void tree_shape(gts_index *idx, int64_t n)
 {
-    hipStream_t st = idx->stream;
-    IndexData &d = idx->data;
-    Tree &t = d.tree;
-    StageClock clock;
-    const int64_t n = objs.count();
-    GTS_CHECK(n >= 1, GTS_EINVAL, "an index needs at least one object");
-    GTS_CHECK(n < (int64_t)1 << 31, GTS_ENOTSUP, "at most 2^31-1 objects per index");
-    const int m = idx->num_pivots;
+    Tree &t = idx->data.tree;
     const int F = idx->fanout;
-    const bool l2 = objs.metric == GTS_L2_F32;
-    d.metric = objs.metric;
-    d.n = n;
-    d.m = m;
-    t.mpad = pad_pivots(m);
-    const int mpad = t.mpad;
+    t.mpad = pad_pivots(idx->num_pivots);
     t.fanout = F;
     t.levels = choose_levels(n, F, idx->opts.leaf_size);
     {
@@ -160,20 +151,262 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         t.n_leaves *= F;
         t.n_nodes += t.n_leaves;
     }
+}
 
-    // ---- objects on the device in input order (temporary) -----------------
-    DevBuf in_x, in_chars, in_off, piv_buf, piv_off, dist_buf;
-    if (l2) {
-        d.dim = objs.dim;
-        d.dp = (objs.dim + 3) / 4 * 4;
-        d.ksteps = (objs.dim + 31) / 32;
-        in_x.alloc((size_t)n * d.dp * sizeof(float));
-        rows_to_device(in_x.as<float>(), d.dp, objs.vecs.data(), objs.dim, n, false, st);
-    } else {
-        alphabet_add(idx, objs.chars);
-        upload(in_chars, objs.chars, st);
-        upload(in_off, objs.offsets, st);
+// Nearest-neighbour chain over K centres from their distance matrix dk
+// [K][K]: rank[c] = place of centre c on the chain (centre 0 first).
+void centre_chain(const std::vector<float> &dk, int K, std::vector<int32_t> &rank, std::vector<int32_t> &by_rank)
+{
+    rank.assign(K, -1);
+    by_rank.assign(K, 0);
+    int at = 0;
+    rank[0] = 0;
+    for (int r = 1; r < K; r++) {
+        int best = -1;
+        for (int c = 0; c < K; c++)
+            if (rank[c] < 0 && (best < 0 || dk[(size_t)at * K + c] < dk[(size_t)at * K + best])) best = c;
+        rank[best] = r;
+        by_rank[r] = best;
+        at = best;
     }
+}
+
+// Leaf cuts: equal-count boundaries, each moved to the nearest cell boundary
+// (a position whose cell differs from the previous one's) within half a
+// leaf.  bnd ascending; cut[L] = n.
+std::vector<int64_t> leaf_cuts(const std::vector<int64_t> &bnd, int64_t n, int64_t L)
+{
+    std::vector<int64_t> cut(L + 1, 0);
+    cut[L] = n;
+    for (int64_t i = 1; i < L; i++) {
+        const int64_t ideal = (int64_t)((long double)i * n / L);
+        int64_t c = std::max(ideal, cut[i - 1]);
+        auto it = std::lower_bound(bnd.begin(), bnd.end(), ideal);
+        int64_t best = -1;
+        if (it != bnd.end()) best = *it;
+        if (it != bnd.begin() && (best < 0 || ideal - *(it - 1) < best - ideal)) best = *(it - 1);
+        if (best >= 0 && 2 * std::llabs(best - ideal) * L <= n && best > cut[i - 1]) c = best;
+        cut[i] = std::min(c, n);
+    }
+    return cut;
+}
+
+// ---------------------------------------------------------------------------
+// L2: every n-sized step on the device.  Global pivots by farthest-first
+// traversal over all objects (the FFT rule, first pivot seeded) and the
+// pivot table from their rows; K farthest-first centres over a strided
+// sample of the objects, every object into the cell of its nearest centre
+// (bf16 MFMA search; the cells only order the objects), cells along the
+// nearest-neighbour chain of their centres and objects inside a cell by
+// distance to the centre (a stable device radix sort); the leaf cuts on the
+// host from the cell of each position; then the object table, pivot table,
+// node boxes, slab summaries and leaf pivots formed in leaf order in HBM.
+// perm[p] = input row of position p.
+// ---------------------------------------------------------------------------
+void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::vector<int32_t> &perm)
+{
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    Tree &t = d.tree;
+    const int64_t n = objs.count();
+    const int m = d.m, mpad = t.mpad;
+    d.dim = objs.dim;
+    d.dp = (objs.dim + 3) / 4 * 4;
+    d.ksteps = (objs.dim + 31) / 32;
+    const int dp = d.dp;
+    const bool mfma = d.dim <= kMaxMfmaDim;
+    DevBuf in_x;
+    in_x.alloc((size_t)n * dp * sizeof(float));
+    rows_to_device(in_x.as<float>(), dp, objs.vecs.data(), objs.dim, n, false, st);
+    clock.mark("upload");
+
+    // ---- global pivots and the pivot table (input order) --------------------
+    uint64_t rng = idx->opts.seed ? idx->opts.seed : 0x2404009660ULL;
+    const int64_t first = (int64_t)(splitmix64(&rng) % (uint64_t)n);
+    DevBuf keys, dcent, mind, nearc;
+    {
+        std::vector<uint64_t> hk((size_t)m + 1, 0ull);
+        hk[0] = (uint64_t)(0xffffffffu - (uint32_t)first);
+        upload(keys, hk, st);
+    }
+    dcent.alloc((size_t)std::max(m, 1) * sizeof(int32_t));
+    mind.alloc((size_t)n * sizeof(float));
+    nearc.alloc((size_t)n * sizeof(int32_t));
+    k::fft_centers_l2(in_x.as<float>(), n, dp, m, keys.as<uint64_t>(), dcent.as<int32_t>(), mind.as<float>(),
+                      nearc.as<int32_t>(), st);
+    d.P32.alloc((size_t)std::max(m, 1) * dp * sizeof(float));
+    k::gather_rows(in_x.as<float>(), dp, dcent.as<int32_t>(), m, d.P32.as<float>(), st);
+    DevBuf pt_in;
+    pt_in.alloc((size_t)mpad * n * sizeof(float));
+    k::dist_l2_pivots(in_x.as<float>(), n, d.P32.as<float>(), m, mpad, dp, pt_in.as<float>(), n, 1, st);
+    clock.mark("global pivots + table");
+
+    // ---- cells: farthest-first centres, nearest centre of every object -----
+    const int K = (int)std::max<int64_t>(1, std::min<int64_t>({t.n_leaves / 8, (int64_t)kMaxCentres, n}));
+    const int64_t S = mfma ? std::min<int64_t>(n, std::max<int64_t>(16384, 32 * (int64_t)K)) : n;
+    DevBuf sx, dsidx;
+    std::vector<int32_t> sidx;
+    const float *fx = in_x.as<float>();
+    if (S < n) {
+        sidx.resize(S);
+        for (int64_t s = 0; s < S; s++) sidx[s] = (int32_t)((long double)s * n / S);
+        upload(dsidx, sidx, st);
+        sx.alloc((size_t)S * dp * sizeof(float));
+        k::gather_rows(in_x.as<float>(), dp, dsidx.as<int32_t>(), S, sx.as<float>(), st);
+        fx = sx.as<float>();
+    }
+    uint64_t crng = (idx->opts.seed ? idx->opts.seed : 0x2404009660ULL) ^ 0x5bd1e9955bd1e995ULL;
+    const int64_t first_centre = (int64_t)(splitmix64(&crng) % (uint64_t)S);
+    DevBuf ckeys, ccent, cmind, cnear;
+    {
+        std::vector<uint64_t> hk((size_t)K + 1, 0ull);
+        hk[0] = (uint64_t)(0xffffffffu - (uint32_t)first_centre);
+        upload(ckeys, hk, st);
+    }
+    ccent.alloc((size_t)K * sizeof(int32_t));
+    cmind.alloc((size_t)S * sizeof(float));
+    cnear.alloc((size_t)S * sizeof(int32_t));
+    k::fft_centers_l2(fx, S, dp, K, ckeys.as<uint64_t>(), ccent.as<int32_t>(), cmind.as<float>(),
+                      cnear.as<int32_t>(), st);
+    std::vector<int32_t> cent(K);
+    GTS_HIP(hipMemcpyAsync(cent.data(), ccent.p, (size_t)K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    if (S < n)
+        for (int c = 0; c < K; c++) cent[c] = sidx[cent[c]];
+    DevBuf dcentres, cx;
+    upload(dcentres, cent, st);
+    const int64_t Kp = (K + 63) / 64 * 64;
+    cx.alloc((size_t)Kp * dp * sizeof(float));
+    GTS_HIP(hipMemsetAsync(cx.p, 0, (size_t)Kp * dp * sizeof(float), st));
+    k::gather_rows(in_x.as<float>(), dp, dcentres.as<int32_t>(), K, cx.as<float>(), st);
+    const int32_t *cell = cnear.as<int32_t>();
+    int cstride = 1;
+    DevBuf c16, cn, ce, x16, xn_in, xe_in, near8;
+    if (S < n) {
+        // nearest centre by bf16 MFMA estimates (padding centres never win)
+        c16.alloc((size_t)Kp * d.ksteps * 32 * sizeof(uint16_t));
+        cn.alloc((size_t)Kp * sizeof(float));
+        ce.alloc((size_t)Kp * sizeof(float));
+        k::rows_bf16(cx.as<float>(), K, Kp, d.dim, dp, d.ksteps, c16.as<uint16_t>(), cn.as<float>(), ce.as<float>(),
+                     INFINITY, st);
+        const int64_t n16 = (n + 15) / 16 * 16;
+        x16.alloc((size_t)n16 * d.ksteps * 32 * sizeof(uint16_t));
+        xn_in.alloc((size_t)n16 * sizeof(float));
+        xe_in.alloc((size_t)n16 * sizeof(float));
+        k::rows_bf16(in_x.as<float>(), n, n16, d.dim, dp, d.ksteps, x16.as<uint16_t>(), xn_in.as<float>(),
+                     xe_in.as<float>(), 0.f, st);
+        near8.alloc((size_t)n16 * k::kNearLeaves * sizeof(int32_t));
+        k::leaf_near(c16.as<uint16_t>(), cn.as<float>(), Kp, d.ksteps, x16.as<uint16_t>(), n, near8.as<int32_t>(), st);
+        cell = near8.as<int32_t>();
+        cstride = k::kNearLeaves;
+    }
+    DevBuf cdist;
+    cdist.alloc((size_t)n * sizeof(float));
+    k::centre_dist(in_x.as<float>(), dp, n, cell, cstride, cx.as<float>(), cdist.as<float>(), st);
+    clock.mark("centres");
+    // centre-to-centre distances, then the chain (host, K x K)
+    std::vector<float> dk((size_t)K * K);
+    {
+        DevBuf ddk;
+        ddk.alloc(dk.size() * sizeof(float));
+        k::dist_l2_pivots(cx.as<float>(), K, cx.as<float>(), K, K, dp, ddk.as<float>(), K, 1, st);
+        GTS_HIP(hipMemcpyAsync(dk.data(), ddk.p, dk.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<int32_t> rank, by_rank;
+    centre_chain(dk, K, rank, by_rank);
+    // the leaf order: (cell rank, distance to the centre, input row)
+    DevBuf drank, okey, operm, stmp;
+    upload(drank, rank, st);
+    okey.alloc((size_t)n * sizeof(uint32_t));
+    operm.alloc((size_t)n * sizeof(int32_t));
+    const size_t sb = k::sort_pairs_bytes(n);
+    stmp.alloc(sb);
+    k::cell_order(cdist.as<float>(), cell, cstride, drank.as<int32_t>(), K, n, okey.as<uint32_t>(),
+                  operm.as<int32_t>(), stmp.p, sb, st);
+    std::vector<uint32_t> prank(n);
+    perm.resize(n);
+    GTS_HIP(hipMemcpyAsync(prank.data(), okey.p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipMemcpyAsync(perm.data(), operm.p, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    std::vector<int64_t> bnd;   // positions where a new cell starts
+    for (int64_t p = 1; p < n; p++)
+        if (prank[p] != prank[p - 1]) bnd.push_back(p);
+    const std::vector<int64_t> cut = leaf_cuts(bnd, n, t.n_leaves);
+    std::vector<int32_t> lf(t.n_leaves), lc(t.n_leaves);
+    for (int64_t j = 0; j < t.n_leaves; j++) {
+        lf[j] = (int32_t)cut[j];
+        lc[j] = (int32_t)(cut[j + 1] - cut[j]);
+    }
+    upload(t.leaf_first, lf, st);
+    upload(t.leaf_cnt, lc, st);
+    clock.mark("partition");
+
+    // ---- tables in leaf order -------------------------------------------------
+    d.npad = (n + kSlab - 1) / kSlab * kSlab;
+    d.n_slabs = d.npad / kSlab;
+    d.X32.alloc((size_t)d.npad * dp * sizeof(float));
+    GTS_HIP(hipMemsetAsync(d.X32.p, 0, (size_t)d.npad * dp * sizeof(float), st));
+    k::gather_rows(in_x.as<float>(), dp, operm.as<int32_t>(), n, d.X32.as<float>(), st);
+    d.PT.alloc((size_t)mpad * n * sizeof(float));
+    k::gather_pt(pt_in.as<float>(), operm.as<int32_t>(), n, m, mpad, d.PT.as<float>(), st);
+    t.box_aos.alloc((size_t)t.n_nodes * 2 * mpad * sizeof(float));
+    t.box_lo.alloc((size_t)mpad * t.n_nodes * sizeof(float));
+    t.box_hi.alloc((size_t)mpad * t.n_nodes * sizeof(float));
+    k::node_boxes(d.PT.as<float>(), n, m, mpad, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
+                  t.leaf0, t.n_nodes, t.fanout, t.levels, t.box_aos.as<float>(), t.box_lo.as<float>(),
+                  t.box_hi.as<float>(), st);
+    DevBuf ptmax;
+    ptmax.alloc(sizeof(uint32_t));
+    k::fill_u32(ptmax.as<uint32_t>(), 1, 0u, st);
+    k::max_f32(d.PT.as<float>(), (int64_t)m * n, ptmax.as<uint32_t>(), st);
+    clock.mark("boxes");
+    d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
+    d.xn.alloc((size_t)d.npad * sizeof(float));
+    d.xe.alloc((size_t)d.npad * sizeof(float));
+    k::rows_bf16(d.X32.as<float>(), n, d.npad, d.dim, dp, d.ksteps, d.X16t.as<uint16_t>(), d.xn.as<float>(),
+                 d.xe.as<float>(), INFINITY, st);
+    d.slab_emax.alloc((size_t)d.n_slabs * sizeof(float));
+    d.slab_nmax.alloc((size_t)d.n_slabs * sizeof(float));
+    d.slab_leaf_lo.alloc((size_t)d.n_slabs * sizeof(int32_t));
+    d.slab_leaf_hi.alloc((size_t)d.n_slabs * sizeof(int32_t));
+    k::slab_summary(d.xn.as<float>(), d.xe.as<float>(), n, t.leaf_first.as<int32_t>(), t.n_leaves, d.n_slabs,
+                    d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
+                    d.slab_leaf_hi.as<int32_t>(), st);
+    // leaf pivots: the leaf's object nearest its centroid and the largest
+    // distance from it to the leaf's objects (double, widened by 1e-6)
+    d.lpad = (t.n_leaves + 63) / 64 * 64;
+    DevBuf cen;
+    cen.alloc((size_t)t.n_leaves * d.dim * sizeof(double));
+    d.PL32.alloc((size_t)d.lpad * dp * sizeof(float));
+    d.leafR.alloc((size_t)d.lpad * sizeof(float));
+    k::leaf_pivots(d.X32.as<float>(), dp, d.dim, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
+                   d.lpad, cen.as<double>(), d.PL32.as<float>(), d.leafR.as<float>(), st);
+    d.PL16t.alloc((size_t)d.lpad * d.ksteps * 32 * sizeof(uint16_t));
+    d.pln.alloc((size_t)d.lpad * sizeof(float));
+    d.ple.alloc((size_t)d.lpad * sizeof(float));
+    k::rows_bf16(d.PL32.as<float>(), d.lpad, d.lpad, d.dim, dp, d.ksteps, d.PL16t.as<uint16_t>(), d.pln.as<float>(),
+                 d.ple.as<float>(), INFINITY, st);
+    k::mark_empty(t.leaf_cnt.as<int32_t>(), t.n_leaves, d.lpad, d.pln.as<float>(), st);
+    uint32_t pm = 0;
+    GTS_HIP(hipMemcpyAsync(&pm, ptmax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    std::memcpy(&d.pt_max, &pm, sizeof(float));
+    clock.mark("layouts + leaf pivots");
+}
+
+void build_edit(gts_index *idx, const HostObjects &objs, StageClock &clock, std::vector<int32_t> &perm32)
+{
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    Tree &t = d.tree;
+    const int64_t n = objs.count();
+    const int m = d.m, mpad = t.mpad, F = t.fanout;
+    // ---- objects on the device in input order (temporary) -----------------
+    DevBuf in_chars, in_off, piv_buf, piv_off, dist_buf;
+    alphabet_add(idx, objs.chars);
+    upload(in_chars, objs.chars, st);
+    upload(in_off, objs.offsets, st);
 
     clock.mark("upload");
     // ---- pivots by farthest-first traversal -------------------------------
@@ -185,12 +418,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
     int64_t next = (int64_t)(splitmix64(&rng) % (uint64_t)n);
     for (int i = 0; i < m; i++) {
         piv[i] = next;
-        if (l2) {
-            piv_buf.alloc((size_t)d.dp * sizeof(float));
-            GTS_HIP(hipMemcpyAsync(piv_buf.p, in_x.as<float>() + (size_t)next * d.dp, d.dp * sizeof(float),
-                                   hipMemcpyDeviceToDevice, st));
-            k::dist_l2_pivots(in_x.as<float>(), n, piv_buf.as<float>(), 1, 1, d.dp, dist_buf.as<float>(), 0, 1, st);
-        } else {
+        {
             const int64_t a = objs.offsets[next], b = objs.offsets[next + 1];
             std::vector<uint8_t> pc(objs.chars.begin() + a, objs.chars.begin() + b);
             std::vector<int32_t> po{0, (int32_t)(b - a)};
@@ -237,11 +465,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         d_cent.alloc((size_t)K * sizeof(int32_t));
         d_mind.alloc((size_t)n * sizeof(float));
         d_near.alloc((size_t)n * sizeof(int32_t));
-        if (l2)
-            k::fft_centers_l2(in_x.as<float>(), n, d.dp, K, d_keys.as<uint64_t>(), d_cent.as<int32_t>(),
-                              d_mind.as<float>(), d_near.as<int32_t>(), st);
-        else
-            k::fft_centers_edit(in_chars.as<uint8_t>(), in_off.as<int64_t>(), n, idx->lut.as<uint8_t>(), idx->arows,
+        k::fft_centers_edit(in_chars.as<uint8_t>(), in_off.as<int64_t>(), n, idx->lut.as<uint8_t>(), idx->arows,
                                 K, d_keys.as<uint64_t>(), d_cent.as<int32_t>(), d_mind.as<float>(),
                                 d_near.as<int32_t>(), st);
         std::vector<int32_t> cent(K), nearc(n);
@@ -256,14 +480,7 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         d_dk.alloc(dk.size() * sizeof(float));
         std::vector<uint8_t> cc;
         std::vector<int64_t> coff{0};
-        if (l2) {
-            std::vector<float> cx((size_t)K * d.dp, 0.f);
-            for (int c = 0; c < K; c++)
-                std::copy(objs.vecs.begin() + (size_t)cent[c] * d.dim, objs.vecs.begin() + (size_t)(cent[c] + 1) * d.dim,
-                          cx.begin() + (size_t)c * d.dp);
-            upload(d_cx, cx, st);
-            k::dist_l2_pivots(d_cx.as<float>(), K, d_cx.as<float>(), K, K, d.dp, d_dk.as<float>(), K, 1, st);
-        } else {
+        {
             for (int c = 0; c < K; c++) {
                 cc.insert(cc.end(), objs.chars.begin() + objs.offsets[cent[c]],
                           objs.chars.begin() + objs.offsets[cent[c] + 1]);
@@ -280,21 +497,9 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         }
         GTS_HIP(hipMemcpyAsync(dk.data(), d_dk.p, dk.size() * sizeof(float), hipMemcpyDeviceToHost, st));
         GTS_HIP(hipStreamSynchronize(st));
-        std::vector<int32_t> rank(K, -1), by_rank(K);
+        std::vector<int32_t> rank, by_rank;
+        centre_chain(dk, K, rank, by_rank);
         {
-            int at = 0;
-            rank[0] = 0;
-            by_rank[0] = 0;
-            for (int r = 1; r < K; r++) {
-                int best = -1;
-                for (int c = 0; c < K; c++)
-                    if (rank[c] < 0 && (best < 0 || dk[(size_t)at * K + c] < dk[(size_t)at * K + best])) best = c;
-                rank[best] = r;
-                by_rank[r] = best;
-                at = best;
-            }
-        }
-        if (!l2) {
             // centre strings in chain order (queries look up their nearest one)
             std::vector<uint8_t> rc;
             std::vector<int32_t> ro{0};
@@ -350,23 +555,12 @@ void build_tree(gts_index *idx, const HostObjects &objs)
         for (int64_t p = 1; p < n; p++)
             if (nearc[perm[p]] != nearc[perm[p - 1]]) bnd.push_back(p);
         const int64_t L = t.n_leaves;
-        std::vector<int64_t> cut(L + 1, 0);
-        cut[L] = n;
-        for (int64_t i = 1; i < L; i++) {
-            const int64_t ideal = (int64_t)((long double)i * n / L);
-            int64_t c = std::max(ideal, cut[i - 1]);
-            auto it = std::lower_bound(bnd.begin(), bnd.end(), ideal);
-            int64_t best = -1;
-            if (it != bnd.end()) best = *it;
-            if (it != bnd.begin() && (best < 0 || ideal - *(it - 1) < best - ideal)) best = *(it - 1);
-            if (best >= 0 && 2 * std::llabs(best - ideal) * L <= n && best > cut[i - 1]) c = best;
-            cut[i] = std::min(c, n);
-        }
+        const std::vector<int64_t> cut = leaf_cuts(bnd, n, L);
         for (int64_t j2 = 0; j2 < L; j2++) {
             nfirst[t.leaf0 + j2] = cut[j2];
             ncnt[t.leaf0 + j2] = cut[j2 + 1] - cut[j2];
         }
-        if (!l2) {
+        {
             // per cell: covering radius, pivot box and length range; per leaf:
             // the cells it spans
             std::vector<float> cR(K, -INFINITY), cbox((size_t)K * 2 * mpad);
@@ -474,164 +668,89 @@ void build_tree(gts_index *idx, const HostObjects &objs)
     upload(t.leaf_cnt, lc, st);
 
     clock.mark("boxes");
-    // ---- objects, pivot table and ids in leaf order ------------------------
-    HostObjects &h = idx->host;
+    // ---- strings, pivot table in leaf order ---------------------------------
+    HostObjects h;   // the strings in leaf order (the host mirror keeps input order)
     h.metric = objs.metric;
     h.dim = objs.dim;
-    h.clear();
     for (int64_t p = 0; p < n; p++) h.append_from(objs, perm[p]);
-    std::vector<uint32_t> pid(n);
-    for (int64_t p = 0; p < n; p++) pid[p] = h.ids[p];
-    upload(d.ids, pid, st);
     d.pt_max = 0.f;
     for (float x : PTin) d.pt_max = std::max(d.pt_max, x);
-
-    if (l2) {
-        d.npad = (n + kSlab - 1) / kSlab * kSlab;
-        d.n_slabs = d.npad / kSlab;
-        d.X32.alloc((size_t)d.npad * d.dp * sizeof(float));
-        GTS_HIP(hipMemsetAsync(d.X32.p, 0, (size_t)d.npad * d.dp * sizeof(float), st));
-        rows_to_device(d.X32.as<float>(), d.dp, h.vecs.data(), d.dim, n, false, st);
-        d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
-        d.xn.alloc((size_t)d.npad * sizeof(float));
-        d.xe.alloc((size_t)d.npad * sizeof(float));
-        k::rows_bf16(d.X32.as<float>(), n, d.npad, d.dim, d.dp, d.ksteps, d.X16t.as<uint16_t>(), d.xn.as<float>(),
-                     d.xe.as<float>(), INFINITY, st);
-        std::vector<float> pt((size_t)mpad * n, 0.f);
-        for (int i = 0; i < m; i++)
-            for (int64_t p = 0; p < n; p++) pt[(size_t)i * n + p] = PTin[(size_t)i * n + perm[p]];
-        upload(d.PT, pt, st);
-        std::vector<float> pv((size_t)std::max(m, 1) * d.dp, 0.f);
-        for (int i = 0; i < m; i++)
-            std::copy(objs.vecs.begin() + piv[i] * d.dim, objs.vecs.begin() + (piv[i] + 1) * d.dim,
-                      pv.begin() + (size_t)i * d.dp);
-        upload(d.P32, pv, st);
-        // slab summaries: largest bf16 error and norm, leaves overlapping
-        std::vector<float> hxn(n), hxe(n);
-        GTS_HIP(hipMemcpyAsync(hxn.data(), d.xn.p, n * sizeof(float), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipMemcpyAsync(hxe.data(), d.xe.p, n * sizeof(float), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipStreamSynchronize(st));
-        std::vector<float> se(d.n_slabs, 0.f), sn(d.n_slabs, 0.f);
-        std::vector<int32_t> sl(d.n_slabs, 0), sh(d.n_slabs, -1);
+    std::vector<int32_t> soff(n + 1);
+    for (int64_t p = 0; p <= n; p++) soff[p] = (int32_t)h.offsets[p];
+    upload(d.chars, h.chars, st);
+    upload(d.soff, soff, st);
+    std::vector<uint8_t> pte((size_t)mpad * n, 0), pta((size_t)n * mpad, 0);
+    for (int i = 0; i < m; i++)
         for (int64_t p = 0; p < n; p++) {
-            const int64_t s = p / kSlab;
-            se[s] = std::max(se[s], hxe[p]);
-            sn[s] = std::max(sn[s], std::sqrt(hxn[p]));
+            const uint8_t v = (uint8_t)PTin[(size_t)i * n + perm[p]];
+            pte[(size_t)i * n + p] = v;
+            pta[(size_t)p * mpad + i] = v;
         }
-        for (int64_t s = 0; s < d.n_slabs; s++) {
-            // rounding of the summaries themselves: a relative margin
-            se[s] = se[s] * 1.0001f + 1e-30f;
-            sn[s] = sn[s] * 1.0001f;
-            const int64_t a = s * kSlab, b = std::min<int64_t>(n, a + kSlab);   // [a, b)
-            int64_t l0 = std::upper_bound(lf.begin(), lf.end(), (int32_t)a) - lf.begin() - 1;
-            int64_t l1 = std::upper_bound(lf.begin(), lf.end(), (int32_t)(b - 1)) - lf.begin() - 1;
-            sl[s] = (int32_t)std::max<int64_t>(0, l0);
-            sh[s] = (int32_t)std::max<int64_t>(0, l1);
-        }
-        upload(d.slab_emax, se, st);
-        upload(d.slab_nmax, sn, st);
-        upload(d.slab_leaf_lo, sl, st);
-        upload(d.slab_leaf_hi, sh, st);
-        // leaf pivots: the leaf's object nearest its centroid, and the largest
-        // distance from it to the leaf's objects (computed in double, then
-        // widened by a relative 1e-6 so it bounds the true value)
-        d.lpad = (t.n_leaves + 63) / 64 * 64;
-        std::vector<float> pl((size_t)d.lpad * d.dp, 0.f);
-        std::vector<float> R(d.lpad, -INFINITY);
-        std::vector<uint8_t> empty(d.lpad, 1);
-        std::vector<double> cen(d.dim);
-        for (int64_t j = 0; j < t.n_leaves; j++) {
-            const int64_t a = lf[j], cnt = lc[j];
-            if (cnt == 0) continue;
-            std::fill(cen.begin(), cen.end(), 0.0);
-            for (int64_t p = a; p < a + cnt; p++)
-                for (int c = 0; c < d.dim; c++) cen[c] += h.vecs[(size_t)p * d.dim + c];
-            for (int c = 0; c < d.dim; c++) cen[c] /= (double)cnt;
-            int64_t best = a;
-            double bd = INFINITY;
-            for (int64_t p = a; p < a + cnt; p++) {
-                double s2 = 0.0;
-                for (int c = 0; c < d.dim; c++) {
-                    const double df = h.vecs[(size_t)p * d.dim + c] - cen[c];
-                    s2 += df * df;
-                }
-                if (s2 < bd) {
-                    bd = s2;
-                    best = p;
-                }
-            }
-            double rmax = 0.0;
-            for (int64_t p = a; p < a + cnt; p++) {
-                double s2 = 0.0;
-                for (int c = 0; c < d.dim; c++) {
-                    const double df = (double)h.vecs[(size_t)p * d.dim + c] - (double)h.vecs[(size_t)best * d.dim + c];
-                    s2 += df * df;
-                }
-                rmax = std::max(rmax, std::sqrt(s2));
-            }
-            R[j] = (float)(rmax * (1.0 + 1e-6)) + 1e-30f;
-            empty[j] = 0;
-            std::copy(h.vecs.begin() + best * d.dim, h.vecs.begin() + (best + 1) * d.dim, pl.begin() + (size_t)j * d.dp);
-        }
-        upload(d.PL32, pl, st);
-        upload(d.leafR, R, st);
-        d.PL16t.alloc((size_t)d.lpad * d.ksteps * 32 * sizeof(uint16_t));
-        d.pln.alloc((size_t)d.lpad * sizeof(float));
-        d.ple.alloc((size_t)d.lpad * sizeof(float));
-        k::rows_bf16(d.PL32.as<float>(), d.lpad, d.lpad, d.dim, d.dp, d.ksteps, d.PL16t.as<uint16_t>(), d.pln.as<float>(),
-                     d.ple.as<float>(), INFINITY, st);
-        std::vector<float> hpln(d.lpad);
-        GTS_HIP(hipMemcpyAsync(hpln.data(), d.pln.p, d.lpad * sizeof(float), hipMemcpyDeviceToHost, st));
-        GTS_HIP(hipStreamSynchronize(st));
-        for (int64_t j = 0; j < d.lpad; j++)
-            if (empty[j]) hpln[j] = INFINITY;   // never a nearest leaf
-        upload(d.pln, hpln, st);
-    } else {
-        std::vector<int32_t> soff(n + 1);
-        for (int64_t p = 0; p <= n; p++) soff[p] = (int32_t)h.offsets[p];
-        upload(d.chars, h.chars, st);
-        upload(d.soff, soff, st);
-        std::vector<uint8_t> pte((size_t)mpad * n, 0), pta((size_t)n * mpad, 0);
-        for (int i = 0; i < m; i++)
-            for (int64_t p = 0; p < n; p++) {
-                const uint8_t v = (uint8_t)PTin[(size_t)i * n + perm[p]];
-                pte[(size_t)i * n + p] = v;
-                pta[(size_t)p * mpad + i] = v;
-            }
-        upload(d.PTe, pte, st);
-        upload(d.PTa, pta, st);
-        std::vector<uint8_t> pc;
-        std::vector<int32_t> po{0};
-        d.pivot_str.clear();
-        for (int i = 0; i < m; i++) {
-            const int64_t a = objs.offsets[piv[i]], b = objs.offsets[piv[i] + 1];
-            pc.insert(pc.end(), objs.chars.begin() + a, objs.chars.begin() + b);
-            po.push_back((int32_t)pc.size());
-            d.pivot_str.emplace_back(objs.chars.begin() + a, objs.chars.begin() + b);
-        }
-        upload(d.pchars, pc, st);
-        upload(d.poff, po, st);
-        d.npad = n;
-        // leaf pivots: the first object of each leaf; R_L from the GPU
-        d.lpad = t.n_leaves;
-        d.leafR.alloc((size_t)t.n_leaves * sizeof(float));
-        k::EditView ev{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), n, idx->lut.as<uint8_t>(), idx->arows};
-        k::leaf_radius_edit(ev, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
-                            d.leafR.as<float>(), st);
-        GTS_HIP(hipStreamSynchronize(st));
+    upload(d.PTe, pte, st);
+    upload(d.PTa, pta, st);
+    std::vector<uint8_t> pc;
+    std::vector<int32_t> po{0};
+    d.pivot_str.clear();
+    for (int i = 0; i < m; i++) {
+        const int64_t a = objs.offsets[piv[i]], b = objs.offsets[piv[i] + 1];
+        pc.insert(pc.end(), objs.chars.begin() + a, objs.chars.begin() + b);
+        po.push_back((int32_t)pc.size());
+        d.pivot_str.emplace_back(objs.chars.begin() + a, objs.chars.begin() + b);
     }
-
+    upload(d.pchars, pc, st);
+    upload(d.poff, po, st);
+    d.npad = n;
+    // leaf pivots: the first object of each leaf; R_L from the GPU
+    d.lpad = t.n_leaves;
+    d.leafR.alloc((size_t)t.n_leaves * sizeof(float));
+    k::EditView ev{d.chars.as<uint8_t>(), d.soff.as<int32_t>(), n, idx->lut.as<uint8_t>(), idx->arows};
+    k::leaf_radius_edit(ev, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
+                        d.leafR.as<float>(), st);
+    GTS_HIP(hipStreamSynchronize(st));
+    perm32.assign(perm.begin(), perm.end());
     clock.mark("layouts + leaf pivots");
-    // ---- tombstones and id maps --------------------------------------------
+}
+
+}  // namespace
+
+void build_tree(gts_index *idx, HostObjects &objs)
+{
+    hipStream_t st = idx->stream;
+    IndexData &d = idx->data;
+    StageClock clock;
+    const int64_t n = objs.count();
+    GTS_CHECK(n >= 1, GTS_EINVAL, "an index needs at least one object");
+    GTS_CHECK(n < (int64_t)1 << 31, GTS_ENOTSUP, "at most 2^31-1 objects per index");
+    d.metric = objs.metric;
+    d.n = n;
+    d.m = idx->num_pivots;
+    tree_shape(idx, n);
+    std::vector<int32_t> perm;   // input row of each position
+    if (objs.metric == GTS_L2_F32) build_l2(idx, objs, clock, perm);
+    else build_edit(idx, objs, clock, perm);
+
+    // ---- ids in leaf order, tombstones, id maps, host mirror ----------------
+    std::vector<uint32_t> pid(n);
+    uint32_t max_id = 0;
+    for (int64_t p = 0; p < n; p++) {
+        pid[p] = objs.ids[perm[p]];
+        max_id = std::max(max_id, pid[p]);
+    }
+    upload(d.ids, pid, st);
     const int64_t words = (std::max(d.npad, n) + 31) / 32 + 1;
+    d.tomb_words = words;
     d.tomb.alloc((size_t)words * sizeof(uint32_t));
     k::fill_u32(d.tomb.as<uint32_t>(), words, 0u, st);
+    d.del_ep.alloc((size_t)words * 32 * sizeof(uint32_t));
+    k::fill_u32(d.del_ep.as<uint32_t>(), words * 32, 0xffffffffu, st);
     idx->h_tomb.assign(n, 0);
     idx->n_deleted_tree = 0;
-    uint32_t max_id = 0;
-    for (uint32_t id : h.ids) max_id = std::max(max_id, id);
     idx->pos_of_id.assign(std::max<int64_t>((int64_t)max_id + 1, idx->next_id), -1);
-    for (int64_t p = 0; p < n; p++) idx->pos_of_id[h.ids[p]] = p;
+    for (int64_t p = 0; p < n; p++) idx->pos_of_id[pid[p]] = p;
+    // the objects stay in input order on the host; host_row[p] is the row of
+    // the object at position p
+    idx->host = std::move(objs);
+    idx->host_row = std::move(perm);
     GTS_HIP(hipStreamSynchronize(st));
     clock.mark("tombstones + maps");
 }
@@ -661,17 +780,26 @@ void cache_reserve(gts_index *idx, int64_t need)
     else grow(c.chars, (size_t)kMaxStrlen);
     grow(c.slen, sizeof(int32_t));
     grow(c.ids, sizeof(uint32_t));
-    grow(c.live, sizeof(uint32_t));
+    grow(c.ins_ep, sizeof(uint32_t));
+    grow(c.del_ep, sizeof(uint32_t));
+    grow(c.cp, (size_t)d.tree.mpad * sizeof(float));
     c.cap = cap;
 }
 
 }  // namespace
+
+static uint32_t next_epoch(gts_index *idx)
+{
+    GTS_CHECK(idx->epoch < 0xfffffff0u, GTS_ENOTSUP, "update epochs exhausted (2^32 updates on one index)");
+    return ++idx->epoch;
+}
 
 void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
 {
     const int64_t n = objs.count();
     if (n == 0) return;
     GTS_CHECK(idx->next_id + n < ((int64_t)1 << 31), GTS_ENOTSUP, "id space exhausted (ids stay below 2^31)");
+    const uint32_t e = next_epoch(idx);
     hipStream_t st = idx->stream;
     CacheList &c = idx->cache;
     const IndexData &d = idx->data;
@@ -679,7 +807,7 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     HostObjects &ch = idx->cache_host;
     ch.metric = d.metric;
     ch.dim = d.dim;
-    std::vector<uint32_t> nid(n), live(n, 1u);
+    std::vector<uint32_t> nid(n);
     std::vector<int32_t> len(n, 0);
     for (int64_t i = 0; i < n; i++) {
         nid[i] = (uint32_t)idx->next_id++;
@@ -701,7 +829,21 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     }
     GTS_HIP(hipMemcpyAsync(c.slen.as<int32_t>() + s0, len.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
     GTS_HIP(hipMemcpyAsync(c.ids.as<uint32_t>() + s0, nid.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    GTS_HIP(hipMemcpyAsync(c.live.as<uint32_t>() + s0, live.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    k::fill_u32(c.ins_ep.as<uint32_t>() + s0, n, e, st);
+    k::fill_u32(c.del_ep.as<uint32_t>() + s0, n, 0xffffffffu, st);
+    // the new slots' distances to the global pivots (the cache scan's Lemma 1)
+    const int mpad = d.tree.mpad;
+    float *cp = c.cp.as<float>() + (size_t)s0 * mpad;
+    if (d.metric == GTS_L2_F32) {
+        k::dist_l2_pivots(c.X32.as<float>() + (size_t)s0 * d.dp, n, d.P32.as<float>(), d.m, mpad, d.dp, cp, 1, mpad,
+                          st);
+    } else {
+        DevBuf sc, so;
+        upload(sc, objs.chars.empty() ? std::vector<uint8_t>(1, 0) : objs.chars, st);
+        upload(so, objs.offsets, st);
+        k::dist_edit_pivots_f32(sc.as<uint8_t>(), so.as<int64_t>(), n, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(),
+                                d.m, mpad, cp, 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
+    }
     GTS_HIP(hipStreamSynchronize(st));
     if ((int64_t)idx->slot_of_id.size() < idx->next_id) idx->slot_of_id.resize(idx->next_id, -1);
     if ((int64_t)idx->pos_of_id.size() < idx->next_id) idx->pos_of_id.resize(idx->next_id, -1);
@@ -730,10 +872,12 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
 {
     hipStream_t st = idx->stream;
     CacheList &c = idx->cache;
+    const uint32_t e = next_epoch(idx);
     int64_t done = 0;
-    // the device words this batch changes: (word index, new value) pairs,
-    // applied by one scatter launch (cache-list live flags and tombstone words)
-    std::vector<uint32_t> live_at, tomb_at;
+    // the device words this batch changes, applied by scatter launches: the
+    // deletion epochs of cache slots and tree positions, and the tombstone
+    // words of those positions
+    std::vector<uint32_t> slot_at, pos_at, tomb_at;
     for (int64_t i = 0; i < n; i++) {
         const int64_t id = ids[i];
         if (id < 0 || id >= idx->next_id) continue;
@@ -742,7 +886,7 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
             if (c.h_live[s]) {
                 c.h_live[s] = 0;
                 c.n_live--;
-                live_at.push_back((uint32_t)s);
+                slot_at.push_back((uint32_t)s);
                 idx->slot_of_id[id] = -1;
                 done++;
             }
@@ -753,22 +897,23 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
             if (!idx->h_tomb[p]) {
                 idx->h_tomb[p] = 1;
                 idx->n_deleted_tree++;
+                pos_at.push_back((uint32_t)p);
                 tomb_at.push_back((uint32_t)(p >> 5));
                 done++;
             }
         }
     }
-    if (!upload || (live_at.empty() && tomb_at.empty())) return done;
+    if (!upload || (slot_at.empty() && pos_at.empty())) return done;
     std::sort(tomb_at.begin(), tomb_at.end());
     tomb_at.erase(std::unique(tomb_at.begin(), tomb_at.end()), tomb_at.end());
     const IndexData &d = idx->data;
-    // [live slots | tombstone words | values]; one transfer, then the scatters
-    const size_t nl = live_at.size(), nt = tomb_at.size();
-    std::vector<uint32_t> pack(2 * (nl + nt));
-    for (size_t i = 0; i < nl; i++) {
-        pack[i] = live_at[i];
-        pack[nl + nt + i] = 0u;
-    }
+    // [slots | positions | tombstone words | their values]; one transfer
+    const size_t ns = slot_at.size(), np = pos_at.size(), nt = tomb_at.size(), na = ns + np + nt;
+    std::vector<uint32_t> pack(2 * na);
+    std::copy(slot_at.begin(), slot_at.end(), pack.begin());
+    std::copy(pos_at.begin(), pos_at.end(), pack.begin() + ns);
+    std::copy(tomb_at.begin(), tomb_at.end(), pack.begin() + ns + np);
+    std::fill(pack.begin() + na, pack.begin() + na + ns + np, e);
     for (size_t i = 0; i < nt; i++) {
         const int64_t w = tomb_at[i];
         uint32_t bits = 0;
@@ -776,15 +921,15 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
             const int64_t p = w * 32 + b;
             if (p < d.n && idx->h_tomb[p]) bits |= 1u << b;
         }
-        pack[nl + i] = (uint32_t)w;
-        pack[2 * nl + nt + i] = bits;
+        pack[na + ns + np + i] = bits;
     }
     DevBuf &dp = idx->upd_buf;
     dp.alloc(pack.size() * sizeof(uint32_t));
     GTS_HIP(hipMemcpyAsync(dp.p, pack.data(), pack.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     const uint32_t *dpk = dp.as<uint32_t>();
-    if (nl) k::scatter_u32(c.live.as<uint32_t>(), dpk, dpk + nl + nt, (int64_t)nl, st);
-    if (nt) k::scatter_u32(d.tomb.as<uint32_t>(), dpk + nl, dpk + 2 * nl + nt, (int64_t)nt, st);
+    if (ns) k::scatter_u32(c.del_ep.as<uint32_t>(), dpk, dpk + na, (int64_t)ns, st);
+    if (np) k::scatter_u32(d.del_ep.as<uint32_t>(), dpk + ns, dpk + na + ns, (int64_t)np, st);
+    if (nt) k::scatter_u32(d.tomb.as<uint32_t>(), dpk + ns + np, dpk + na + ns + np, (int64_t)nt, st);
     GTS_HIP(hipStreamSynchronize(st));
     return done;
 }
@@ -830,8 +975,8 @@ void rebuild(gts_index *idx)
     all.metric = idx->data.metric;
     all.dim = idx->host.dim ? idx->host.dim : idx->cache_host.dim;
     const HostObjects &h = idx->host;
-    for (int64_t p = 0; p < h.count(); p++)
-        if (!idx->h_tomb[p]) all.append_from(h, p);
+    for (int64_t p = 0; p < (int64_t)idx->host_row.size(); p++)
+        if (!idx->h_tomb[p]) all.append_from(h, idx->host_row[p]);
     const HostObjects &ch = idx->cache_host;
     for (int64_t s = 0; s < ch.count(); s++)
         if (idx->cache.h_live[s]) all.append_from(ch, s);

@@ -37,7 +37,7 @@ enum Ws {
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
     W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV, W_POSOF, W_HOMEC, W_PLEN, W_POFF, W_PCHARS,
-    W_BADQ, W_COUNT
+    W_BADQ, W_QEP, W_PQEP, W_TMIN, W_TMAX, W_TILEW, W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
 
@@ -162,6 +162,10 @@ struct GroupOut {
     int64_t total = 0;
     bool direct = false;           // sorted keys left in the workspace (W_OUTKEYS, W_QOFF64, W_OUTCNT)
     ResultMem pre;                 // direct: result storage for every candidate, allocated while verify runs
+    // a group whose candidates overflowed: how many it produced, and the
+    // (query, object) pairs of each of its query tiles (empty: unknown)
+    uint64_t attempts = 0;
+    std::vector<unsigned long long> tile_work;
 };
 
 double now_ms()
@@ -253,6 +257,12 @@ struct Batch {
     int sweep_grid_per_cu = 2;          // MFMA sweep workgroups per CU (tuned)
     bool check_bound = false;           // count bf16 interval violations
     bool no_prune = false;              // L2 control: every (leaf, query) pair kept
+    // what the batch sees (server batches: see SnapView)
+    const uint32_t *tomb_prod = nullptr;    // tombstones of the candidate producers
+    const uint32_t *tomb_bound = nullptr;   // tombstones of the kNN bounds
+    const uint32_t *qep = nullptr;          // [nq] admission epochs (null: all at e_now)
+    uint32_t e_now = 0;
+    int64_t cache_count = 0;                // cache slots to scan
 };
 
 void rec(QueryCtx *cx, int i)
@@ -297,7 +307,9 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     k::fill_u32(small, kSmallWords, 0u, st);
     k::CandCount *ccount = reinterpret_cast<k::CandCount *>(small);
     k::Cand *cands = wsp<k::Cand>(cx, W_CANDS, cap);
-    const uint32_t *tomb = d.tomb.as<uint32_t>();
+    const uint32_t *tomb = b.tomb_prod;
+    const uint32_t *qep = b.qep ? b.qep + q0 : nullptr;
+    const uint32_t *del_ep = b.qep ? d.del_ep.as<uint32_t>() : nullptr;
 
     const bool plain = b.mode == GTS_MODE_PLAIN || (l2 && d.dim > kMaxMfmaDim);
     // float32 selection: Lemma 1 on the pivot table instead of bf16 tiles
@@ -384,15 +396,16 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     }
     // cache list: brute force, already verified
     const CacheList &c = idx->cache;
-    if (c.n_live > 0) {
+    if (b.cache_count > 0) {
+        k::CacheScan cs{c.ids.as<uint32_t>(), c.ins_ep.as<uint32_t>(), c.del_ep.as<uint32_t>(), c.cp.as<float>(),
+                        b.cache_count, d.m, mpad, qep, b.e_now, QP, (float)((d.dim + 8) * 5.9604645e-8)};
         if (l2) {
             // emission cutoff: radius (range) or the widened bound T (kNN)
             float *cut = cx->ws[W_CUT].as<float>() + q0;
-            k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), c.ids.as<uint32_t>(), c.live.as<uint32_t>(), c.count,
-                             cut, cands, ccount, cap, idx->angular, st);
+            k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), cs, T, cut, cands, ccount, cap, idx->angular, st);
         } else {
-            k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), c.ids.as<uint32_t>(),
-                               c.live.as<uint32_t>(), c.count, base, cands, ccount, cap, st);
+            k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), cs, base, cands,
+                               ccount, cap, st);
         }
     }
     // ---- group by query ----------------------------------------------------
@@ -404,14 +417,14 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     int64_t *qoff = wsp<int64_t>(cx, W_QOFF64, ng + 1);
     k::fill_u32(qcount, ng, 0u, st);
     k::fill_u32(cursor, ng, 0u, st);
-    k::group_hist(cands, ccount, cap, qcount, st);
+    k::group_hist(cands, ccount, cap, qcount, del_ep, qep, st);
     k::scan_u32(qcount, ng, qoff, st);
     // (no-allocation search: sized for every candidate the group may keep)
     int64_t gcap = cx->arena ? cap
                              : std::max<int64_t>((int64_t)(cx->ws[W_GROUPED].bytes / sizeof(k::Cand)),
                                                  std::min<int64_t>(cap, (int64_t)1 << 20));
     k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, gcap);
-    k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, gcap, st);
+    k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, gcap, del_ep, qep, st);
     rec(cx, 5);
     uint32_t *h_small = reinterpret_cast<uint32_t *>(pin + pl.small);
     int64_t *h_qoff_pin = reinterpret_cast<int64_t *>(pin + pl.qoff);
@@ -423,7 +436,21 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     GTS_HIP(hipStreamSynchronize(st));
     GTS_CHECK(*h_bad == 0, GTS_EINVAL, "a query vector is zero or non-finite: it has no direction (angular metric)");
     const uint64_t ncand_all = *reinterpret_cast<const uint64_t *>(h_small);
-    if (ncand_all > (uint64_t)cap) return false;
+    if (ncand_all > (uint64_t)cap) {
+        // too many candidates for the budget: report the attempt and each
+        // tile's share of the work, which sizes the smaller groups
+        go->attempts = ncand_all;
+        if (!plain) {
+            unsigned long long *tw = wsp<unsigned long long>(cx, W_TILEW, ntiles);
+            k::fill_u32(reinterpret_cast<uint32_t *>(tw), 2 * (int64_t)ntiles, 0u, st);
+            k::tile_pairs(cx->ws[W_MASK].as<uint64_t>(), t.n_leaves, ntiles, t.leaf_cnt.as<int32_t>(), tw, st);
+            go->tile_work.resize(ntiles);
+            GTS_HIP(hipMemcpyAsync(go->tile_work.data(), tw, (size_t)ntiles * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
+            GTS_HIP(hipStreamSynchronize(st));
+        }
+        return false;
+    }
     const int64_t ncand = (int64_t)ncand_all;
     if (!plain && (!l2 || sel32) && (int64_t)h_small[kSmallItems] > t.n_leaves * ntiles)
         fail(GTS_EDEVICE, "item list overflow");
@@ -433,7 +460,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     if (ncand > gcap) {
         grouped = wsp<k::Cand>(cx, W_GROUPED, ncand);
         k::fill_u32(cursor, ng, 0u, st);
-        k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, ncand, st);
+        k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, ncand, del_ep, qep, st);
     }
     // segments too long for LDS sort in power-of-two scratch runs; the lists
     // are written straight into the pinned staging
@@ -764,6 +791,37 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                                 cx->ws[W_QP].as<float>(), 1, mpad, idx->lut.as<uint8_t>(), idx->arows, st);
         qe = k::QueryEdit{qc, qo, peq};
     }
+    // ---- what the batch sees ------------------------------------------------------
+    // Outside a server batch every query sees the index as it is now.  A
+    // server batch spans updates: its queries carry admission epochs, the
+    // producers run on the tombstones of the earliest epoch (a superset of
+    // every query's live set, each candidate checked against its query's
+    // epoch when grouped), the kNN bounds on those of the latest (a subset:
+    // the k-th distance over it bounds every query's), and it scans the cache
+    // slots filled at its admission.
+    // (a server batch reads none of the update counters: the scheduler
+    // changes them while the batch runs)
+    b.tomb_prod = b.tomb_bound = d.tomb.as<uint32_t>();
+    const SnapView &sv = cx->view;
+    if (!sv.on) {
+        b.e_now = idx->epoch;
+        b.cache_count = idx->cache.n_live > 0 ? idx->cache.count : 0;
+    } else if (nq > 0) {
+        GTS_CHECK((int64_t)sv.qep.size() == nq && sv.e_min <= sv.e_max, GTS_EINVAL, "inconsistent admission epochs");
+        uint32_t *qep = wsp<uint32_t>(cx, W_QEP, nqpad);
+        GTS_HIP(hipMemcpyAsync(qep, sv.qep.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        uint32_t *tmin = wsp<uint32_t>(cx, W_TMIN, d.tomb_words);
+        k::tomb_bits(d.del_ep.as<uint32_t>(), d.n, sv.e_min, tmin, d.tomb_words, st);
+        b.tomb_prod = b.tomb_bound = tmin;
+        if (sv.e_max != sv.e_min) {
+            uint32_t *tmax = wsp<uint32_t>(cx, W_TMAX, d.tomb_words);
+            k::tomb_bits(d.del_ep.as<uint32_t>(), d.n, sv.e_max, tmax, d.tomb_words, st);
+            b.tomb_bound = tmax;
+        }
+        b.qep = qep;
+        b.cache_count = sv.cache_count;
+    }
+
     // ---- home leaves and query order ----------------------------------------------
     // Queries are grouped into tiles by their home (nearest leaf pivot for L2,
     // nearest cluster centre in chain order for edit distance) so that a
@@ -806,7 +864,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         int32_t *piv = wsp<int32_t>(cx, W_PIV, (size_t)2 * nq);
         k::edit_pivot(oe, qe, nq, cv, piv, piv + nq, st);
         if (b.any_knn)
-            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 512, base, home, piv,
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 512, base, home, piv,
                           d.cell_leaf.as<int32_t>(), st);
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, 1, delta, d.pt_max, cx->ws[W_T].as<float>(),
                       cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
@@ -854,6 +912,12 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         int32_t *pnear = near ? wsp<int32_t>(cx, W_PNEAR, (size_t)nqpad * k::kNearLeaves) : nullptr;
         k::permute_queries(dperm, nq, base, pb, kq, pk, cx->ws[W_QP].as<float>(), pqp, mpad, l2 ? qv.Q32 : nullptr,
                            pq32, d.dp, near, pnear, k::kNearLeaves, st);
+        if (b.qep) {
+            uint32_t *pq = wsp<uint32_t>(cx, W_PQEP, nqpad);
+            k::gather_i32(reinterpret_cast<const int32_t *>(b.qep), dperm, nq, 1, reinterpret_cast<int32_t *>(pq), st);
+            std::swap(cx->ws[W_QEP], cx->ws[W_PQEP]);
+            b.qep = cx->ws[W_QEP].as<uint32_t>();
+        }
         std::swap(cx->ws[W_BASE], cx->ws[W_PBASE]);
         std::swap(cx->ws[W_KQ], cx->ws[W_PKQ]);
         std::swap(cx->ws[W_QP], cx->ws[W_PQP]);
@@ -911,13 +975,13 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             const int window = LaunchTuner::kWindow[tset.window];
             cx->stats.bound_window = window;
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
-                          d.dp, qv.Q32, kq, nq, d.tomb.as<uint32_t>(), window, base, counters, st);
+                          d.dp, qv.Q32, kq, nq, b.tomb_bound, window, base, counters, st);
         } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
-            k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, st);
+            k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 256, base, home, st);
         } else {
-            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, d.tomb.as<uint32_t>(), 256, base, home, nullptr,
+            k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 256, base, home, nullptr,
                           nullptr, st);
         }
     }
@@ -978,13 +1042,38 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         }
         GTS_CHECK(!cx->arena, GTS_ENOMEM,
                   "the batch's candidates exceed the no-allocation scratch; use a smaller batch");
-        // split into halves of whole 64-query tiles
         const int64_t blocks = (ng + kQTile - 1) / kQTile;
         GTS_CHECK(blocks > 1, GTS_ENOMEM,
                   "the memory budget cannot hold the candidates of 64 queries; raise mem_budget_bytes");
-        const int64_t half = (blocks / 2) * kQTile;
-        todo.insert(todo.begin(), {q0 + half, ng - half});
-        todo.insert(todo.begin(), {q0, half});
+        cx->stats.group_retries++;
+        std::vector<std::pair<int64_t, int64_t>> parts;
+        unsigned long long work = 0;
+        for (unsigned long long w : go.tile_work) work += w;
+        if ((int64_t)go.tile_work.size() == blocks && work > 0) {
+            // consecutive tiles whose estimated candidates (the attempt's
+            // count shared in proportion to each tile's pairs in surviving
+            // leaves) fill three quarters of the budget
+            const long double per = (long double)go.attempts / (long double)work;
+            const long double target = 0.75L * (long double)cap;
+            int64_t t0 = 0;
+            long double acc = 0.0L;
+            for (int64_t tt = 0; tt < blocks; tt++) {
+                const long double c = per * (long double)go.tile_work[tt];
+                if (tt > t0 && acc + c > target) {
+                    parts.push_back({t0, tt});
+                    t0 = tt;
+                    acc = 0.0L;
+                }
+                acc += c;
+            }
+            parts.push_back({t0, blocks});
+        }
+        if (parts.size() < 2) parts = {{0, blocks / 2}, {blocks / 2, blocks}};   // halves
+        for (size_t i = parts.size(); i-- > 0;) {
+            const int64_t a = q0 + parts[i].first * kQTile;
+            const int64_t e = std::min(q0 + ng, q0 + parts[i].second * kQTile);
+            todo.insert(todo.begin(), {a, e - a});
+        }
     }
 
     // ---- final CSR (caller's query order) ------------------------------------------------

@@ -10,8 +10,10 @@ namespace k {
 
 // Runs of equal query among a wave's 64 consecutive candidates (the sweep
 // writes each lane's hits of one tile next to each other): the first lane of
-// a run makes one atomic for the whole run.  *head_lane = first lane of this
-// lane's run; returns the run length at its first lane, 0 elsewhere.
+// a run makes one atomic for the whole run.  Invalid lanes (the tail of the
+// list, candidates left out by their query's epoch) may sit anywhere and end
+// a run.  *head_lane = first lane of this lane's run; returns the run length
+// at its first lane, 0 elsewhere.
 __device__ __forceinline__ int query_run(int32_t q, bool valid, int *head_lane)
 {
     const int lane = dev::lane_id();
@@ -19,12 +21,12 @@ __device__ __forceinline__ int query_run(int32_t q, bool valid, int *head_lane)
     const bool head = valid && (lane == 0 || prev != q);
     // both ballots by the whole wave, before any lane leaves
     const uint64_t hm = dev::ballot(head);
-    const int nvalid = __popcll(dev::ballot(valid));          // valid lanes form a prefix
+    const uint64_t stop = hm | ~dev::ballot(valid);           // a run ends before either
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    *head_lane = 63 - __clzll((long long)(hm & upto));
+    *head_lane = (hm & upto) ? 63 - __clzll((long long)(hm & upto)) : lane;
     if (!head) return 0;
-    const uint64_t after = hm & ~upto;
-    const int end = after ? __ffsll((long long)after) - 1 : nvalid;
+    const uint64_t after = stop & ~upto;
+    const int end = after ? __ffsll((long long)after) - 1 : 64;
     return end - lane;
 }
 
@@ -55,14 +57,32 @@ __device__ __forceinline__ int query_runs(int32_t q)
 // counts once however the producer interleaved them; the order inside a
 // query's group is free (verification sorts by (distance, id)).
 constexpr int kSortRuns = 16;
+// Admission epochs (qep non-null): a tree candidate is dropped when its
+// position was deleted at or before its query's epoch (del_ep[pos] <=
+// qep[q]); the producers ran on the tombstones of the batch's earliest epoch.
+__device__ __forceinline__ bool gone_at(const Cand &c, const uint32_t *del_ep, const uint32_t *qep)
+{
+    return qep != nullptr && c.q >= 0 && c.pos >= 0 && del_ep[c.pos] <= qep[c.q];
+}
+
 __global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, const CandCount *__restrict__ count,
-                                                    int64_t cap, uint32_t *__restrict__ qcount)
+                                                    int64_t cap, uint32_t *__restrict__ qcount,
+                                                    const uint32_t *__restrict__ del_ep,
+                                                    const uint32_t *__restrict__ qep)
 {
     int64_t n = (int64_t)(*count > (CandCount)cap ? (CandCount)cap : *count);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); b0 < n; b0 += stride) {
         const int64_t i = b0 + dev::lane_id();
-        const int32_t q0 = i < n ? c[i].q : -1;
+        int32_t q0 = -1;
+        if (i < n) {
+            if (qep) {
+                const Cand ci = c[i];
+                q0 = gone_at(ci, del_ep, qep) ? -1 : ci.q;
+            } else {
+                q0 = c[i].q;
+            }
+        }
         const int32_t q = query_runs(q0) > kSortRuns
                               ? (int32_t)(uint32_t)(wave_sort64((uint64_t)(uint32_t)q0 << 32) >> 32)
                               : q0;
@@ -73,9 +93,10 @@ __global__ __launch_bounds__(256) void k_group_hist(const Cand *__restrict__ c, 
     }
 }
 
-void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, hipStream_t st)
+void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, const uint32_t *del_ep,
+                const uint32_t *qep, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_group_hist, dim3(2048), dim3(256), 0, st, c, count, cap, qcount);
+    hipLaunchKernelGGL(k_group_hist, dim3(2048), dim3(256), 0, st, c, count, cap, qcount, del_ep, qep);
     check_launch(__func__);
 }
 
@@ -140,7 +161,8 @@ void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st)
 __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ c, const CandCount *__restrict__ count,
                                                        int64_t cap, const int64_t *__restrict__ qoff,
                                                        uint32_t *__restrict__ cursor, Cand *__restrict__ grouped,
-                                                       int64_t grouped_cap)
+                                                       int64_t grouped_cap, const uint32_t *__restrict__ del_ep,
+                                                       const uint32_t *__restrict__ qep)
 {
     int64_t n = (int64_t)(*count > (CandCount)cap ? (CandCount)cap : *count);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -152,6 +174,7 @@ __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ 
         c0.pos = 0;
         c0.val = 0;
         if (i < n) c0 = c[i];
+        if (gone_at(c0, del_ep, qep)) c0.q = -1;
         // sort the wave's candidates by query, then take each record from
         // the lane that loaded it
         Cand cd = c0;
@@ -174,10 +197,10 @@ __global__ __launch_bounds__(256) void k_group_scatter(const Cand *__restrict__ 
 }
 
 void group_scatter(const Cand *c, const CandCount *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
-                   Cand *grouped, int64_t grouped_cap, hipStream_t st)
+                   Cand *grouped, int64_t grouped_cap, const uint32_t *del_ep, const uint32_t *qep, hipStream_t st)
 {
     hipLaunchKernelGGL(k_group_scatter, dim3(2048), dim3(256), 0, st, c, count, cap, qoff, cursor, grouped,
-                       grouped_cap);
+                       grouped_cap, del_ep, qep);
     check_launch(__func__);
 }
 

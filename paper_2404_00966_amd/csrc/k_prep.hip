@@ -240,6 +240,54 @@ void scatter_u32(uint32_t *dst, const uint32_t *at, const uint32_t *val, int64_t
     check_launch(__func__);
 }
 
+// Tombstone bitmap of one epoch: bit p of bits[] is set iff position p was
+// deleted by an update of epoch e or earlier (del_ep[p] <= e; a live position
+// holds 0xffffffff).  One lane per position, the wave's 64 decisions made
+// into two words by one ballot; words past n hold zeros.
+__global__ void k_tomb_bits(const uint32_t *__restrict__ del_ep, int64_t n, uint32_t e, uint32_t *__restrict__ bits,
+                            int64_t words)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool dead = p < n && del_ep[p] <= e;
+    const uint64_t m = dev::ballot(dead);
+    const int lane = dev::lane_id();
+    const int64_t w0 = (p - lane) >> 5;   // first of this wave's two words
+    if (lane == 0 && w0 < words) bits[w0] = (uint32_t)m;
+    if (lane == 32 && w0 + 1 < words) bits[w0 + 1] = (uint32_t)(m >> 32);
+}
+
+void tomb_bits(const uint32_t *del_ep, int64_t n, uint32_t e, uint32_t *bits, int64_t words, hipStream_t st)
+{
+    if (words == 0) return;
+    const int64_t threads = (words * 32 + 255) / 256 * 256;
+    hipLaunchKernelGGL(k_tomb_bits, dim3((unsigned)(threads / 256)), dim3(256), 0, st, del_ep, n, e, bits, words);
+    check_launch(__func__);
+}
+
+// Work of each query tile: out[t] += sum over leaves of (queries of the
+// tile that keep the leaf) x (objects of the leaf), from the (leaf, tile)
+// masks [n_leaves][ntiles].  out must start at zero.
+__global__ void k_tile_pairs(const uint64_t *__restrict__ mask, int64_t n_leaves, int ntiles,
+                             const int32_t *__restrict__ leaf_cnt, unsigned long long *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_leaves * ntiles) return;
+    const int64_t leaf = i / ntiles;
+    const int t = (int)(i - leaf * ntiles);
+    const uint64_t m = mask[i];
+    if (m) atomicAdd(&out[t], (unsigned long long)__popcll(m) * (unsigned long long)leaf_cnt[leaf]);
+}
+
+void tile_pairs(const uint64_t *mask, int64_t n_leaves, int ntiles, const int32_t *leaf_cnt, unsigned long long *out,
+                hipStream_t st)
+{
+    const int64_t n = n_leaves * ntiles;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_tile_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mask, n_leaves, ntiles,
+                       leaf_cnt, out);
+    check_launch(__func__);
+}
+
 // out[q] = a[q] + b[q] for q < n, -inf for n <= q < npad (padding rows of a
 // query tile never pass a threshold).
 __global__ void k_sum_pad(const float *__restrict__ a, const float *__restrict__ b, int64_t n, int64_t npad,

@@ -800,69 +800,135 @@ void edit_objfilter(const TreeView &t, const int32_t *items, const uint32_t *ite
 // ---------------------------------------------------------------------------
 // Cache list (Sec. 4.4): brute force over every live cached object.
 // ---------------------------------------------------------------------------
-// L2: 16 lanes per (query, slot) pair, float32 direct difference.
-// cut[q]: range radius, or for kNN the widened bound T (any summation order)
-__global__ void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp, const float *__restrict__ C32,
-                                const uint32_t *__restrict__ cids, const uint32_t *__restrict__ clive,
-                                int64_t ncache, const float *__restrict__ base, Cand *__restrict__ cands,
-                                CandCount *__restrict__ cand_count, int64_t cand_cap, int angular)
+// Visibility of a cache slot to a query admitted at epoch e: inserted by an
+// update of epoch e or earlier and not deleted by one of them.
+__device__ __forceinline__ bool slot_visible(const uint32_t *cins, const uint32_t *cdel, int64_t s, uint32_t e)
 {
-    const int64_t pair = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    const int sl = threadIdx.x & 15;
-    const bool inb = pair < nq * ncache;
-    const int64_t q = inb ? pair / ncache : 0;
-    const int64_t c = inb ? pair % ncache : 0;
-    float acc = 0.f;
-    if (inb && clive[c]) {
-        const float *x = Q32 + (size_t)q * dp;
-        const float *y = C32 + (size_t)c * dp;
-        for (int i = sl; i < dp; i += 16) {
-            float d = x[i] - y[i];
-            acc = fmaf(d, d, acc);
+    return cins[s] <= e && cdel[s] > e;
+}
+
+// Lemma 1 against a cache slot with its global pivot distances cp (kept
+// since its insertion): the slot is beyond t from a query with pivot
+// distances qp when |qp_i - cp_i| exceeds t for some pivot.  L2 compares
+// float32 distances, each within a relative delta of the true one, so the
+// test keeps a margin of 2 delta (qp_i + cp_i + t); edit distances are exact.
+__device__ __forceinline__ bool slot_far(const float *qp, const float *cp, int i, float t, float delta)
+{
+    const float a = qp[i], c = cp[i];
+    return fabsf(a - c) > t + 2.f * delta * (a + c + t);
+}
+
+// L2: a workgroup stages a tile of ts slot rows in LDS (row stride dp + 16
+// floats, so the four 16-lane groups of a wave read different banks) and
+// runs a share of the call's queries against it, 16 lanes per (query, slot)
+// pair: first Lemma 1 on the global pivots (a pivot or two per lane), then
+// for the slots that remain the same strided float32 sum as every other
+// exact distance.  T[q]: the widened bound of the pivot test; cut[q]: the
+// emission cutoff (range radius, or for kNN the widened bound).
+__global__ __launch_bounds__(256) void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp,
+                                                       const float *__restrict__ C32, CacheScan cs, int ts,
+                                                       int staged, int64_t qchunks, const float *__restrict__ T,
+                                                       const float *__restrict__ cut, Cand *__restrict__ cands,
+                                                       CandCount *__restrict__ cand_count, int64_t cand_cap,
+                                                       int angular)
+{
+    extern __shared__ float s_rows[];
+    const int stride = dp + 16;
+    // blocks in tile-major order: a tile's query shares run side by side
+    const int64_t tile = blockIdx.x / qchunks, chunk = blockIdx.x - tile * qchunks;
+    const int64_t s0 = tile * ts;
+    const int ns = (int)min<int64_t>(ts, cs.count - s0);
+    if (staged) {
+        for (int i = threadIdx.x; i < ns * dp; i += blockDim.x) {
+            const int j = i / dp, c = i - j * dp;
+            s_rows[j * stride + c] = C32[(size_t)(s0 + j) * dp + c];
         }
+        __syncthreads();
     }
+    const int sl = threadIdx.x & 15, g = threadIdx.x >> 4, gw = g & 3;
+    const int64_t qper = (nq + qchunks - 1) / qchunks;
+    const int64_t q0 = chunk * qper, q1 = min<int64_t>(nq, q0 + qper);
+    for (int64_t q = q0; q < q1; q++) {
+        const float *x = Q32 + (size_t)q * dp;
+        const uint32_t e = cs.qep ? cs.qep[q] : cs.e_now;
+        const float cq = cut[q], tq = T[q];
+        const float *qp = cs.QP + (size_t)q * cs.mpad;
+        // the same trip count in every lane: the group ballots and shuffles
+        // below run with the whole wave active
+        for (int j0 = 0; j0 < ns; j0 += 16) {
+            const int j = j0 + g;
+            bool vis = j < ns && slot_visible(cs.ins_ep, cs.del_ep, s0 + j, e);
+            bool far = false;
+            if (vis && cs.cp)
+                for (int i = sl; i < cs.m; i += 16) far = far || slot_far(qp, cs.cp + (size_t)(s0 + j) * cs.mpad, i, tq, cs.delta);
+            far = ((dev::ballot(far) >> (16 * gw)) & 0xffffull) != 0ull;
+            vis = vis && !far;
+            float acc = 0.f;
+            if (vis) {
+                const float *y = staged ? s_rows + j * stride : C32 + (size_t)(s0 + j) * dp;
+                for (int i = sl; i < dp; i += 16) {
+                    const float d = x[i] - y[i];
+                    acc = fmaf(d, d, acc);
+                }
+            }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-    if (sl == 0 && inb && clive[c]) {
-        const float d = sqrtf(acc);
-        if (d <= base[q]) {
-            const CandCount idx = atomicAdd(cand_count, (CandCount)1);
-            if ((int64_t)idx < cand_cap) {
-                Cand cd;
-                cd.q = (int32_t)q;
-                cd.pos = -1;
-                cd.val = ((uint64_t)__float_as_uint(dev::out_dist(d, angular != 0)) << 32) | cids[c];
-                cands[idx] = cd;
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            if (sl == 0 && vis) {
+                const float d = sqrtf(acc);
+                if (d <= cq) {
+                    const CandCount idx = atomicAdd(cand_count, (CandCount)1);
+                    if ((int64_t)idx < cand_cap) {
+                        Cand cd;
+                        cd.q = (int32_t)q;
+                        cd.pos = -1;
+                        cd.val = ((uint64_t)__float_as_uint(dev::out_dist(d, angular != 0)) << 32) | cs.ids[s0 + j];
+                        cands[idx] = cd;
+                    }
+                }
             }
         }
     }
 }
 
-void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
-                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
-                   int64_t cand_cap, bool angular, hipStream_t st)
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *T,
+                   const float *cut, Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st)
 {
-    if (nq == 0 || ncache == 0) return;
-    const int64_t threads = nq * ncache * 16;
-    hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Q32, nq, dp, C32,
-                       cids, clive, ncache, base, cands, cand_count, cand_cap, angular ? 1 : 0);
+    if (nq == 0 || cs.count == 0) return;
+    // rows wider than 48 KB of LDS (12,272 floats) are read through the cache
+    const int64_t stride = dp + 16;
+    const int64_t fit = ((int64_t)48 << 10) / (stride * (int64_t)sizeof(float));
+    const bool staged = fit >= 1;
+    const int ts = staged ? (int)std::min<int64_t>(64, fit) : 64;
+    const int64_t tiles = (cs.count + ts - 1) / ts;
+    // each tile's rows are staged once per query share: one share when the
+    // tiles alone fill the chip, more (of at least 16 queries) when they do not
+    const int64_t qchunks = std::max<int64_t>(1, std::min<int64_t>((nq + 15) / 16, 2048 / std::max<int64_t>(tiles, 1)));
+    require(tiles * qchunks < ((int64_t)1 << 31), "cache_scan_l2: launch too large");
+    hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)(tiles * qchunks)), dim3(256),
+                       staged ? (size_t)ts * stride * sizeof(float) : 0, st, Q32, nq, dp, C32, cs, ts, staged ? 1 : 0,
+                       qchunks, T, cut, cands, cand_count, cand_cap, angular ? 1 : 0);
     check_launch(__func__);
 }
 
-// EDIT: one lane per (query, slot) pair, query as the pattern.
+// EDIT: one lane per (query, slot) pair, query as the pattern; length and
+// pivot tests first (exact integers).
 __global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const uint8_t *__restrict__ cchars, int cstride,
-                                  const int32_t *__restrict__ clen, const uint32_t *__restrict__ cids,
-                                  const uint32_t *__restrict__ clive, int64_t ncache, const float *__restrict__ base,
+                                  const int32_t *__restrict__ clen, CacheScan cs, const float *__restrict__ base,
                                   Cand *__restrict__ cands, CandCount *__restrict__ cand_count, int64_t cand_cap)
 {
     const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= nq * ncache) return;
-    const int64_t q = pair / ncache, c = pair % ncache;
-    if (!clive[c]) return;
+    if (pair >= nq * cs.count) return;
+    const int64_t q = pair / cs.count, c = pair % cs.count;
+    if (!slot_visible(cs.ins_ep, cs.del_ep, c, cs.qep ? cs.qep[q] : cs.e_now)) return;
     const int cut = (int)floorf(fminf(base[q], 1e6f));
     const int plen = (int)(qv.off[q + 1] - qv.off[q]);
     const int tl = clen[c];
     if (abs(plen - tl) > cut) return;
+    if (cs.cp) {
+        const float *qp = cs.QP + (size_t)q * cs.mpad, *cp = cs.cp + (size_t)c * cs.mpad;
+        for (int i = 0; i < cs.m; i++)
+            if (fabsf(qp[i] - cp[i]) > (float)cut) return;
+    }
     const int d = dev::myers_any(qv.peq + (size_t)q * o.rows * 4, plen, cchars + (size_t)c * cstride, tl, cut, o.lut);
     if (d <= cut) {
         const CandCount idx = atomicAdd(cand_count, (CandCount)1);
@@ -870,20 +936,21 @@ __global__ void k_cache_scan_edit(QueryEdit qv, EditView o, int64_t nq, const ui
             Cand cd;
             cd.q = (int32_t)q;
             cd.pos = -1;
-            cd.val = ((uint64_t)(uint32_t)d << 32) | cids[c];
+            cd.val = ((uint64_t)(uint32_t)d << 32) | cs.ids[c];
             cands[idx] = cd;
         }
     }
 }
 
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
-                     const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
-                     const float *base, Cand *cands, CandCount *cand_count, int64_t cand_cap, hipStream_t st)
+                     const int32_t *clen, const CacheScan &cs, const float *base, Cand *cands, CandCount *cand_count,
+                     int64_t cand_cap, hipStream_t st)
 {
-    if (nq == 0 || ncache == 0) return;
-    const int64_t threads = nq * ncache;
+    if (nq == 0 || cs.count == 0) return;
+    const int64_t threads = nq * cs.count;
+    require((threads + 255) / 256 < ((int64_t)1 << 31), "cache_scan_edit: launch too large");
     hipLaunchKernelGGL(k_cache_scan_edit, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, qv, o, nq,
-                       cchars, cstride, clen, cids, clive, ncache, base, cands, cand_count, cand_cap);
+                       cchars, cstride, clen, cs, base, cands, cand_count, cand_cap);
     check_launch(__func__);
 }
 

@@ -112,6 +112,46 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint32_t *
     }
 }
 
+size_t sort_pairs_bytes(int64_t n)
+{
+    const int64_t ranges = std::max<int64_t>(1, (n + kRangeItems - 1) / kRangeItems);
+    return (size_t)n * (sizeof(uint32_t) + sizeof(int32_t)) + (size_t)kRadix * ranges * sizeof(uint32_t) +
+           ((size_t)kRadix * ranges + 1) * sizeof(int64_t) + 1024;
+}
+
+void sort_pairs_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *tmp, size_t tmp_bytes, hipStream_t st)
+{
+    if (n == 0 || bits <= 0) return;
+    require(bits <= 32, "sort_pairs_u32: at most 32 key bits");
+    require(tmp_bytes >= sort_pairs_bytes(n), "sort_pairs_u32: workspace too small");
+    const int64_t ranges = std::max<int64_t>(1, (n + kRangeItems - 1) / kRangeItems);
+    uint8_t *t = static_cast<uint8_t *>(tmp);
+    uint32_t *k2 = reinterpret_cast<uint32_t *>(t);
+    int32_t *v2 = reinterpret_cast<int32_t *>(k2 + n);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(v2 + n);
+    int64_t *start = reinterpret_cast<int64_t *>(
+        (reinterpret_cast<uintptr_t>(hist + (size_t)kRadix * ranges) + 7) & ~(uintptr_t)7);
+    uint32_t *kbuf[2] = {keys, k2};
+    int32_t *vbuf[2] = {vals, v2};
+    const int passes = (bits + 7) / 8;
+    int cur = 0;
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)ranges), dim3(kSortThreads), 0, st, kbuf[cur], n, 8 * p,
+                           ranges, hist);
+        check_launch("sort_pairs_u32(hist)");
+        scan_u32(hist, kRadix * ranges, start, st);
+        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)ranges), dim3(kSortThreads), 0, st, kbuf[cur], vbuf[cur], n,
+                           8 * p, ranges, start, kbuf[cur ^ 1], vbuf[cur ^ 1]);
+        check_launch("sort_pairs_u32(scatter)");
+        cur ^= 1;
+    }
+    if (cur == 1) {
+        // an odd number of passes leaves the result in the workspace
+        GTS_HIP(hipMemcpyAsync(keys, k2, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+        GTS_HIP(hipMemcpyAsync(vals, v2, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    }
+}
+
 static int key_bits(int64_t n_keys)
 {
     int b = 1;

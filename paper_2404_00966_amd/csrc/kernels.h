@@ -72,6 +72,12 @@ void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t n
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 // dst[at[i]] = val[i] for i < n (the changed words of a delete batch)
 void scatter_u32(uint32_t *dst, const uint32_t *at, const uint32_t *val, int64_t n, hipStream_t st);
+// bits[w] (w < words): bit b set iff position 32 w + b < n has del_ep <= e.
+void tomb_bits(const uint32_t *del_ep, int64_t n, uint32_t e, uint32_t *bits, int64_t words, hipStream_t st);
+// out[t] += sum over leaves l of popcount(mask[l][t]) * leaf_cnt[l] (the
+// (query, object) pairs a tile's surviving leaves hold); out zeroed first.
+void tile_pairs(const uint64_t *mask, int64_t n_leaves, int ntiles, const int32_t *leaf_cnt, unsigned long long *out,
+                hipStream_t st);
 // Rows scaled to unit length in place (norm in double, result rounded to
 // float); a row with zero or non-finite norm becomes zero and sets *bad.
 void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
@@ -172,13 +178,26 @@ void l2_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_
                   int64_t n, const uint32_t *tomb, Cand *cands, CandCount *cand_count, int64_t cand_cap,
                   unsigned long long *counters, hipStream_t st);
 
-// Brute-force scan of the cache list; emits verified entries with d <= base.
-void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const uint32_t *cids,
-                   const uint32_t *clive, int64_t ncache, const float *base, Cand *cands, CandCount *cand_count,
-                   int64_t cand_cap, bool angular, hipStream_t st);
+// Brute-force scans of the cache list; they emit verified entries with
+// d <= cut (L2) or d <= floor(base) (edit distance).  Slot s is seen by a
+// query of epoch e iff ins_ep[s] <= e < del_ep[s]; e = qep[q], or e_now for
+// every query when qep is null.  With cp set, Lemma 1 on the global pivots
+// (cp: the slots' pivot distances, QP: the queries') skips slots first.
+struct CacheScan {
+    const uint32_t *ids, *ins_ep, *del_ep;   // [count]
+    const float *cp;                          // [count][mpad] (null: no pivot test)
+    int64_t count;
+    int m, mpad;
+    const uint32_t *qep;                      // [nq] admission epochs (null: e_now)
+    uint32_t e_now;
+    const float *QP;                          // [nq][mpad]
+    float delta;                              // L2: relative float32 error of a distance
+};
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *T,
+                   const float *cut, Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st);
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
-                     const int32_t *clen, const uint32_t *cids, const uint32_t *clive, int64_t ncache,
-                     const float *base, Cand *cands, CandCount *cand_count, int64_t cand_cap, hipStream_t st);
+                     const int32_t *clen, const CacheScan &cs, const float *base, Cand *cands, CandCount *cand_count,
+                     int64_t cand_cap, hipStream_t st);
 // Largest distance from each leaf's first object to the leaf's objects.
 void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_t *leaf_cnt, int64_t n_leaves,
                       float *leafR, hipStream_t st);
@@ -190,6 +209,36 @@ void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, in
                     int32_t *near, hipStream_t st);
 void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const uint8_t *lut, int arows, int K,
                       uint64_t *keys, int32_t *centers, float *mind, int32_t *near, hipStream_t st);
+// ---- device steps of the L2 build (k_build.hip) ----
+// dst row p <- src row perm[p] (rows of dp floats, dp a multiple of 4).
+void gather_rows(const float *src, int dp, const int32_t *perm, int64_t n, float *dst, hipStream_t st);
+// Pivot table [mpad][n] into the order perm (rows m..mpad-1 zero).
+void gather_pt(const float *src, const int32_t *perm, int64_t n, int m, int mpad, float *dst, hipStream_t st);
+// out[o] = squared float32 distance of row o to centre row C[cell[o * stride]].
+void centre_dist(const float *X, int dp, int64_t n, const int32_t *cell, int stride, const float *C, float *out,
+                 hipStream_t st);
+// Leaf order: perm sorted by (rank[cell[o * stride]], cdist[o], o); key
+// returns each position's cell rank.  tmp holds sort_pairs_bytes(n).
+void cell_order(const float *cdist, const int32_t *cell, int stride, const int32_t *rank, int n_cells, int64_t n,
+                uint32_t *key, int32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t st);
+// Node boxes from the leaf-order pivot table: box_aos [n_nodes][2 mpad]
+// (lo then hi), box_lo / box_hi [mpad][n_nodes].
+void node_boxes(const float *PT, int64_t n, int m, int mpad, const int32_t *leaf_first, const int32_t *leaf_cnt,
+                int64_t n_leaves, int64_t leaf0, int64_t n_nodes, int F, int levels, float *box_aos, float *box_lo,
+                float *box_hi, hipStream_t st);
+// Per 256-row slab: largest bf16 rounding error and norm (with margins) and
+// the first and last leaf overlapping it.
+void slab_summary(const float *xn, const float *xe, int64_t n, const int32_t *leaf_first, int64_t n_leaves,
+                  int64_t n_slabs, float *emax, float *nmax, int32_t *sl, int32_t *sh, hipStream_t st);
+// Leaf pivots: per leaf the object nearest its mean (rows into PL32 [lpad][dp])
+// and the largest distance from it (leafR, widened); cen: [n_leaves][dim]
+// doubles of scratch.  Empty leaves and j >= n_leaves: zero row, R = -inf.
+void leaf_pivots(const float *X32, int dp, int dim, const int32_t *leaf_first, const int32_t *leaf_cnt,
+                 int64_t n_leaves, int64_t lpad, double *cen, float *PL32, float *leafR, hipStream_t st);
+// pln[j] = +inf for j >= n_leaves and empty leaves.
+void mark_empty(const int32_t *leaf_cnt, int64_t n_leaves, int64_t lpad, float *pln, hipStream_t st);
+// *out = max(*out, max x) over non-negative floats, as float bits.
+void max_f32(const float *x, int64_t n, uint32_t *out, hipStream_t st);
 // Cells (the clusters that order the leaves, in chain order): centre
 // strings, covering radius, box over the global pivot distances and the
 // string-length range of each.
@@ -250,12 +299,15 @@ void edit_leaf_ball(const EditView &o, const QueryEdit &qv, const int32_t *qlen,
                     int64_t n_leaves, hipStream_t st);
 
 // ---- grouping, verification, output (k_final.hip) ---------------------------
-void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, hipStream_t st);
+// Admission epochs (qep non-null, indexed by the candidates' query): tree
+// candidates with del_ep[pos] <= qep[q] are left out of the groups.
+void group_hist(const Cand *c, const CandCount *count, int64_t cap, uint32_t *qcount, const uint32_t *del_ep,
+                const uint32_t *qep, hipStream_t st);
 void scan_u32(const uint32_t *in, int64_t n, int64_t *out, hipStream_t st);  // out[n+1]
 // Writes only entries below grouped_cap (a larger candidate count is
 // scattered again into a larger buffer).
 void group_scatter(const Cand *c, const CandCount *count, int64_t cap, const int64_t *qoff, uint32_t *cursor,
-                   Cand *grouped, int64_t grouped_cap, hipStream_t st);
+                   Cand *grouped, int64_t grouped_cap, const uint32_t *del_ep, const uint32_t *qep, hipStream_t st);
 
 struct VerifyArgs {
     const Cand *grouped;       // candidates grouped by query
@@ -321,6 +373,10 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
                 unsigned long long *counters, hipStream_t st);
 void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st);
+// Stable sort of n (key, value) pairs by the low `bits` bits of the keys, in
+// place (least significant 8-bit digit first); tmp holds sort_pairs_bytes(n).
+size_t sort_pairs_bytes(int64_t n);
+void sort_pairs_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *tmp, size_t tmp_bytes, hipStream_t st);
 void gather_i32(const int32_t *src, const int32_t *perm, int64_t rows, int width, int32_t *dst, hipStream_t st);
 void gather_strings(const uint8_t *src, const int64_t *src_off, const int32_t *perm, int64_t n, const int64_t *dst_off,
                     uint8_t *dst, hipStream_t st);

@@ -2,13 +2,20 @@
 // over resident indexes (gts_server_* in include/gts.h).
 //
 // Per index: one scheduler thread and L lane threads.  The scheduler takes
-// the index's FIFO in order.  An update at its head waits until no batch of
-// the index is in flight, then runs alone (so every query sees exactly the
-// updates submitted before it).  Queries at its head are admitted together,
-// up to the batch limit and stopping at the next update, into one mixed
-// gts_search batch handed to a free lane; each lane owns a HIP stream and a
-// query workspace (QueryCtx), so batches overlap on the device.  Answers of a
-// batch are split back into per-request host CSR completions.
+// the index's FIFO in order.  Every update gets the next epoch of the index
+// and applies at once, while batches run: a deletion only stamps epochs
+// (tombstones and cache slots) and an insertion fills cache slots above
+// those the running batches read.  A query request is admitted at the
+// index's current epoch and sees exactly the updates submitted before it
+// (Sec. 4.4: the index and the cache list, less the marked objects, as of
+// its admission).  Queries at the head are admitted together, with the
+// updates between them applied in order, up to the batch limit, into one
+// mixed gts_search batch handed to a free lane; each lane owns a HIP stream
+// and a query workspace (QueryCtx), so batches overlap on the device.  Only
+// an update that moves memory the batches read -- a cache list that must
+// grow, a rebuild, new bytes in an edit index's alphabet -- waits until no
+// batch of the index is in flight.  Answers of a batch are split back into
+// per-request host CSR completions.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -71,9 +78,33 @@ struct Lane {
     QueryCtx ctx;
     std::thread th;
     std::vector<std::unique_ptr<Request>> batch;
+    std::vector<uint32_t> epoch;   // admission epoch of each request of the batch
+    int64_t cache_count = 0;       // cache slots filled when the batch was closed
     int64_t batch_no = -1;
     bool has_work = false;
 };
+
+bool is_update(const Request &r)
+{
+    return r.req.kind == GTS_REQ_INSERT || r.req.kind == GTS_REQ_DELETE;
+}
+
+// An update that moves or rewrites memory a running batch reads waits for
+// the index's batches to finish: an insertion that grows the cache arrays,
+// one that triggers the rebuild, or one that adds bytes to an edit index's
+// alphabet (the match tables of running batches use the old codes).
+bool update_needs_drain(const gts_index *idx, const Request &r)
+{
+    if (r.req.kind != GTS_REQ_INSERT) return false;
+    const int64_t n = r.objs.count();
+    const CacheList &c = idx->cache;
+    const int64_t limit = idx->opts.cache_limit > 0 ? idx->opts.cache_limit : 4096;
+    if (c.count + n > c.cap || c.n_live + n > limit) return true;
+    if (idx->data.metric != GTS_L2_F32)
+        for (uint8_t ch : r.objs.chars)
+            if (!idx->alpha[ch]) return true;
+    return false;
+}
 
 }  // namespace
 }  // namespace gts
@@ -142,7 +173,7 @@ void publish(Completion *c)
     c->pub.new_ids = c->new_ids.empty() ? nullptr : c->new_ids.data();
 }
 
-// One update, alone on the index (no batch in flight).
+// One update, on the scheduler's thread.
 void run_update(gts_server *s, IndexQueue &q, std::unique_ptr<Request> r)
 {
     const double t0 = now_ms();
@@ -206,6 +237,20 @@ void run_batch(gts_server *s, IndexQueue &q, Lane &lane)
     qo.mem_budget_bytes = s->opts.mem_budget_bytes > 0
                               ? s->opts.mem_budget_bytes
                               : std::max<int64_t>(q.idx->opts.mem_budget_bytes / s->opts.lanes_per_index, 1 << 20);
+    // admission epochs per query
+    SnapView &v = lane.ctx.view;
+    v.on = true;
+    v.qep.clear();
+    v.qep.reserve(nq);
+    v.e_min = 0xffffffffu;
+    v.e_max = 0;
+    for (size_t i = 0; i < lane.batch.size(); i++) {
+        const uint32_t e = lane.epoch[i];
+        v.qep.insert(v.qep.end(), (size_t)lane.batch[i]->objs.count(), e);
+        v.e_min = std::min(v.e_min, e);
+        v.e_max = std::max(v.e_max, e);
+    }
+    v.cache_count = lane.cache_count;
     gts_result res{};
     const gts_status st = run_guarded([&] { search(q.idx, &lane.ctx, &Q, radius.data(), kk.data(), &qo, &res); });
     const std::string err = st == GTS_OK ? std::string() : std::string(gts_last_error());
@@ -241,6 +286,7 @@ void run_batch(gts_server *s, IndexQueue &q, Lane &lane)
     s->batch_queries += nq;
     for (size_t i = 0; i < out.size(); i++) finish(s, out[i], true, lane.batch[i]->objs.count());
     lane.batch.clear();
+    lane.epoch.clear();
     lane.has_work = false;
     q.inflight--;
     s->cv.notify_all();
@@ -266,8 +312,8 @@ void scheduler_loop(gts_server *s, IndexQueue *q)
         Lane *free_lane = nullptr;
         s->cv.wait(g, [&] {
             if (q->fifo.empty()) return s->stop;
-            const bool update = q->fifo.front()->req.kind == GTS_REQ_INSERT || q->fifo.front()->req.kind == GTS_REQ_DELETE;
-            if (update) return q->inflight == 0;
+            const Request &h = *q->fifo.front();
+            if (is_update(h)) return q->inflight == 0 || !update_needs_drain(q->idx, h);
             free_lane = nullptr;
             for (auto &l : q->lanes)
                 if (!l->has_work) {
@@ -277,23 +323,35 @@ void scheduler_loop(gts_server *s, IndexQueue *q)
             return free_lane != nullptr;
         });
         if (q->fifo.empty()) return;   // stopping, nothing left
-        const int kind = q->fifo.front()->req.kind;
-        if (kind == GTS_REQ_INSERT || kind == GTS_REQ_DELETE) {
+        if (is_update(*q->fifo.front())) {
             std::unique_ptr<Request> r = std::move(q->fifo.front());
             q->fifo.pop_front();
             g.unlock();
             run_update(s, *q, std::move(r));
             continue;
         }
+        // queries at the head, each at the epoch of the updates before it;
+        // updates between them apply in order unless one must wait for the
+        // running batches (then the batch closes before it)
         int64_t nq = 0;
         while (!q->fifo.empty()) {
             Request *r = q->fifo.front().get();
-            if (r->req.kind != GTS_REQ_RANGE && r->req.kind != GTS_REQ_KNN) break;
+            if (is_update(*r)) {
+                if (update_needs_drain(q->idx, *r)) break;
+                std::unique_ptr<Request> u = std::move(q->fifo.front());
+                q->fifo.pop_front();
+                g.unlock();
+                run_update(s, *q, std::move(u));
+                g.lock();
+                continue;
+            }
             if (nq > 0 && nq + r->objs.count() > max_q) break;
             nq += r->objs.count();
+            free_lane->epoch.push_back(q->idx->epoch);
             free_lane->batch.push_back(std::move(q->fifo.front()));
             q->fifo.pop_front();
         }
+        free_lane->cache_count = q->idx->cache.count;
         free_lane->batch_no = s->next_batch++;
         free_lane->has_work = true;
         q->inflight++;

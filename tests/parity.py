@@ -87,5 +87,11 @@ def check_exact(gpu, ref):
     """Edit distance: identical ids and distances."""
     assert len(gpu) == len(ref)
     for q, ((gi, gd), (ri, rd)) in enumerate(zip(gpu, ref)):
-        assert np.array_equal(np.asarray(gi), ri), (q, gi[:8], ri[:8])
+        gi = np.asarray(gi)
+        if not np.array_equal(gi, ri):
+            extra = sorted(set(gi.tolist()) - set(ri.tolist()))
+            missing = sorted(set(ri.tolist()) - set(gi.tolist()))
+            raise AssertionError(f"query {q}: {len(gi)} ids vs {len(ri)} expected; extra {extra[:12]}, "
+                                 f"missing {missing[:12]}; got {list(zip(gi.tolist(), np.asarray(gd).tolist()))[:40]}, "
+                                 f"expected {list(zip(ri.tolist(), rd.tolist()))[:40]}")
         assert np.array_equal(np.asarray(gd).astype(np.int64), rd.astype(np.int64)), (q, gd[:8], rd[:8])

@@ -87,7 +87,7 @@ def test_server_stream_matches_oracle_and_alone(gts):
                 expect = len(set(dele) & live[ix])
                 live[ix] -= set(dele)
                 t = srv.submit(("delete", ix, np.array(dele, np.int64)))
-                meta[t] = ("delete", ix, expect)
+                meta[t] = ("delete", ix, expect, dele)
         else:
             ix = 0 if u < 0.72 else 1
             m = int(rng.integers(1, 9))
@@ -143,7 +143,15 @@ def test_server_stream_matches_oracle_and_alone(gts):
             objs = O.ObjectSet(strings=synth.strings_from_bytes([allS[i] for i in snap]), ids=snap)
             qs = O.ObjectSet(strings=q)
             ref = O.range_bf(objs, qs, par) if kind == "range" else O.knn_bf(objs, qs, par)
-            check_exact(c["answers"], ref)
+            try:
+                check_exact(c["answers"], ref)
+            except AssertionError as e:
+                # the updates of this index around the request, and its batch
+                hist = [(u, meta[u][0], meta[u][2] if meta[u][0] == "insert" else meta[u][3])
+                        for u in sorted(meta) if meta[u][0] in ("insert", "delete") and meta[u][1] == ix]
+                mates = sorted(u for u, cc in comps.items() if cc["batch"] == c["batch"])
+                raise AssertionError(f"ticket {t} ({kind}, {par}) batch {c['batch']} with {mates}; "
+                                     f"updates {hist}: {e}") from None
     # alone vs in the mix: requests submitted after the last update of their
     # index see the final state; rerun them alone and compare bit for bit
     last_update = {0: 0, 1: 0}
