@@ -7,7 +7,8 @@ Thin ctypes wrapper over ``oracle.c`` (built as ``liboracle.so`` by
 ``oracle/build.py``).  Everything here is marshalling; the arithmetic is in the
 C file, which states what it follows in the paper:
 
-* ``l2``/``edit``: the two metrics (FP64 direct difference; Wagner-Fischer).
+* ``l2``/``l1``/``angular``/``edit``: the metrics (FP64 direct difference,
+  FP64 sum of absolute differences, FP64 half-angle form; Wagner-Fischer).
 * ``range_bf``/``knn_bf``: Definitions 1 and 2 by brute force, answers sorted
   by (distance, id), kNN answers are the first min(k, n) in that order.
 * ``GtsTree``: a GTS-literal index (Algorithms 1-3) and its batched range and
@@ -23,7 +24,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-L2, EDIT, ANGULAR = 1, 2, 3
+L2, EDIT, ANGULAR, L1 = 1, 2, 3, 4
 
 
 class _Set(C.Structure):
@@ -54,6 +55,8 @@ def lib():
         L.orc_l2.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_angular.restype = C.c_double
         L.orc_angular.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+        L.orc_l1.restype = C.c_double
+        L.orc_l1.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_edit.restype = C.c_int32
         L.orc_edit.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         L.orc_pair_distances.argtypes = [P(_Set), P(_Set), C.c_void_p]
@@ -91,10 +94,11 @@ def _ptr(a):
 
 class ObjectSet:
     """A borrowed view of objects for the oracle: float32 vectors [n, dim]
-    (L2) or packed strings (chars uint8, offsets int64 [n+1]) (edit), with
-    optional int64 external ids (default 0..n-1)."""
+    (L2, or L1 with l1=True, or the angular metric with angular=True) or
+    packed strings (chars uint8, offsets int64 [n+1]) (edit), with optional
+    int64 external ids (default 0..n-1)."""
 
-    def __init__(self, vecs=None, strings=None, ids=None, angular=False):
+    def __init__(self, vecs=None, strings=None, ids=None, angular=False, l1=False):
         if (vecs is None) == (strings is None):
             raise ValueError("give exactly one of vecs / strings")
         s = _Set()
@@ -104,7 +108,7 @@ class ObjectSet:
             if v.ndim != 2:
                 raise ValueError("vecs must be 2-D")
             self._keep.append(v)
-            s.metric, s.dim, s.n = (ANGULAR if angular else L2), v.shape[1], v.shape[0]
+            s.metric, s.dim, s.n = (ANGULAR if angular else L1 if l1 else L2), v.shape[1], v.shape[0]
             s.vecs = v.ctypes.data
         else:
             chars = np.ascontiguousarray(strings[0], dtype=np.uint8)
@@ -150,6 +154,14 @@ def l2(x, y) -> float:
     y = np.ascontiguousarray(y, dtype=np.float32)
     assert x.shape == y.shape
     return lib().orc_l2(_ptr(x), _ptr(y), x.shape[0])
+
+
+def l1(x, y) -> float:
+    """Manhattan distance sum |x_i - y_i| (float64)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    assert x.shape == y.shape
+    return lib().orc_l1(_ptr(x), _ptr(y), x.shape[0])
 
 
 def angular(x, y) -> float:

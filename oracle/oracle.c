@@ -9,6 +9,7 @@
  *
  *  1. The metrics themselves (Sec. 3, problem statement):
  *       - Euclidean distance, direct-difference form, summed in index order;
+ *       - Manhattan (L1) distance, summed in index order;
  *       - Levenshtein distance with unit-cost insertion, deletion and
  *         replacement (the paper's string examples), by the full
  *         Wagner-Fischer dynamic programme.
@@ -35,10 +36,10 @@
 /* Object sets                                                              */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_L2 = 1, ORC_EDIT = 2, ORC_ANGULAR = 3 };
+enum { ORC_L2 = 1, ORC_EDIT = 2, ORC_ANGULAR = 3, ORC_L1 = 4 };
 
 typedef struct {
-    int32_t metric;          /* ORC_L2, ORC_EDIT or ORC_ANGULAR              */
+    int32_t metric;          /* ORC_L2, ORC_EDIT, ORC_ANGULAR or ORC_L1      */
     int32_t dim;             /* L2: vector length                            */
     int64_t n;               /* number of objects                            */
     const float *vecs;       /* L2: [n][dim] row-major                       */
@@ -78,6 +79,15 @@ double orc_l2(const float *x, const float *y, int32_t dim)
         acc += diff * diff;
     }
     return sqrt(acc);
+}
+
+/* Manhattan (L1) distance, the metric of the paper's colour-histogram data:
+ * sum_i |x_i - y_i| with every step in double, summed in index order. */
+double orc_l1(const float *x, const float *y, int32_t dim)
+{
+    double acc = 0.0;
+    for (int32_t i = 0; i < dim; i++) acc += fabs((double)x[i] - (double)y[i]);
+    return acc;
 }
 
 /* Angular distance, the metric of cosine similarity on directions: the angle
@@ -139,6 +149,8 @@ static double set_dist(const orc_set *A, int64_t i, const orc_set *B, int64_t j)
         return orc_l2(A->vecs + (size_t)i * A->dim, B->vecs + (size_t)j * B->dim, A->dim);
     if (A->metric == ORC_ANGULAR)
         return orc_angular(A->vecs + (size_t)i * A->dim, B->vecs + (size_t)j * B->dim, A->dim);
+    if (A->metric == ORC_L1)
+        return orc_l1(A->vecs + (size_t)i * A->dim, B->vecs + (size_t)j * B->dim, A->dim);
     return (double)orc_edit(A->chars + A->offsets[i], A->offsets[i + 1] - A->offsets[i],
                             B->chars + B->offsets[j], B->offsets[j + 1] - B->offsets[j]);
 }

@@ -54,6 +54,65 @@ def test_l2_axioms_random_triples():
 
 
 # --------------------------------------------------------------------------
+# L1 metric (Manhattan; the paper's colour histograms)
+# --------------------------------------------------------------------------
+
+def test_l1_closed_forms():
+    assert O.l1([0, 0], [3, 4]) == 7.0
+    assert O.l1([1, 2, 3], [1, 2, 3]) == 0.0
+    assert O.l1([1, 0, 0, 0], [0, 1, 0, 0]) == 2.0
+    # one coordinate apart: the absolute difference of that coordinate
+    assert O.l1([0.5, 7.0], [0.5, -1.25]) == 8.25
+    x = np.array([0.5, -1.25, 3.0], np.float32)
+    y = np.array([-2.0, 4.0, 1.0], np.float32)
+    assert O.l1(x, y) == O.l1(y, x) == 2.5 + 5.25 + 2.0
+    assert O.l1(x + 8, y + 8) == pytest.approx(O.l1(x, y), rel=1e-15)
+
+
+def test_l1_matches_float64_library_routine_and_norm_bounds():
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((300, 37)).astype(np.float32) * 3
+    Q = rng.standard_normal((20, 37)).astype(np.float32) * 3
+    ref = cdist(Q.astype(np.float64), X.astype(np.float64), "cityblock")
+    got = O.pair_distances(O.ObjectSet(vecs=X, l1=True), O.ObjectSet(vecs=Q, l1=True))
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+    # |v|_2 <= |v|_1 <= sqrt(D) |v|_2
+    l2 = O.pair_distances(O.ObjectSet(vecs=X), O.ObjectSet(vecs=Q))
+    assert np.all(l2 <= got * (1 + 1e-12)) and np.all(got <= np.sqrt(37) * l2 * (1 + 1e-12))
+
+
+def test_l1_axioms_random_triples():
+    rng = np.random.default_rng(16)
+    for _ in range(200):
+        a, b, c = (rng.standard_normal(16).astype(np.float32) for _ in range(3))
+        ab, bc, ac = O.l1(a, b), O.l1(b, c), O.l1(a, c)
+        assert ab >= 0 and ab == O.l1(b, a)
+        assert ac <= ab + bc + 1e-12
+
+
+def test_l1_brute_force_and_tree_agree():
+    d = synth.gaussian_mixture(18, 3000, 12, 8, -3.0, 3.0, 1.0, 40, 40)
+    objs = O.ObjectSet(vecs=d["objects"], l1=True)
+    rq = O.ObjectSet(vecs=d["range_queries"], l1=True)
+    kq = O.ObjectSet(vecs=d["knn_queries"], l1=True)
+    D = O.pair_distances(objs, rq)
+    r = float(np.float32(np.sort(D.ravel())[1200]))
+    bf = O.range_bf(objs, rq, r)
+    for q in range(rq.n):
+        want = np.nonzero(D[q] <= r)[0]
+        order = np.lexsort((want, D[q][want]))
+        assert np.array_equal(bf[q][0], want[order])
+    kb = O.knn_bf(objs, kq, 9)
+    Dk = O.pair_distances(objs, kq)
+    for q in range(kq.n):
+        order = np.lexsort((np.arange(objs.n), Dk[q]))[:9]
+        assert np.array_equal(kb[q][0], order)
+    tree = O.GtsTree(objs, nc=6, seed=3)
+    _same(tree.range(rq, r)[0], bf)
+    _same(tree.knn(kq, 9)[0], kb)
+
+
+# --------------------------------------------------------------------------
 # Angular metric (cosine similarity on directions)
 # --------------------------------------------------------------------------
 
