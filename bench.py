@@ -600,6 +600,7 @@ def run_serving(args, gts, synth, torch, np):
         log(f"{phase}: {st}")
     out["build_s"] = build_s
     out["rebuilds"] = [il2.info()["rebuilds"], idna.info()["rebuilds"]]
+    out["rebuild_ms"] = [il2.info()["rebuild_ms"], idna.info()["rebuild_ms"]]
     il2.close()
     idna.close()
     return out

@@ -8,8 +8,9 @@
  *   MRQ(q, r)   = { o in O : d(q, o) <= r }                    (Definition 1)
  *   MkNNQ(q, k) = k objects no farther from q than any other   (Definition 2)
  *
- * for the Euclidean metric on float32 vectors and the Levenshtein (edit)
- * metric on byte strings, with streamed insertions and deletions (Sec. 4.4).
+ * for the Euclidean, Manhattan and angular metrics on float32 vectors and
+ * the Levenshtein (edit) metric on byte strings, with streamed insertions and
+ * deletions (Sec. 4.4).
  *
  * Conventions for every call:
  *   - Plain pointers only.  Each gts_objects says whether its arrays live in
@@ -53,6 +54,9 @@ typedef int32_t gts_status;
 #define GTS_COSINE_F32 3  /* angular distance of cosine similarity: the angle
                              arccos(x.y / (|x| |y|)) in radians, in [0, pi],
                              between nonzero float32 vectors (directions)    */
+#define GTS_L1_F32 4      /* Manhattan distance sum_i |x_i - y_i| on float32
+                             vectors (the paper's colour histograms); always
+                             selected on the float32 pivot table (no bf16)   */
 
 /* Where an array lives. */
 #define GTS_HOST 0
@@ -202,8 +206,12 @@ typedef struct {
     int64_t n_live;          /* live objects (tree + cache)                      */
     int64_t n_cache;         /* live objects in the cache list                   */
     int64_t n_nodes, n_leaves, n_slabs;
-    int64_t rebuilds;        /* rebuilds triggered by the cache limit            */
+    int64_t rebuilds;        /* rebuilds triggered by the cache limit or by a
+                                tree more than half deleted                     */
     int64_t device_bytes;    /* device memory held by the index                  */
+    double rebuild_ms;       /* wall time spent in those rebuilds                */
+    int64_t epoch;           /* updates applied so far (each insert or delete
+                                call counts one)                                */
 } gts_index_info;
 
 typedef struct gts_index gts_index;

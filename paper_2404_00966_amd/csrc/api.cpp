@@ -56,11 +56,13 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
     return guarded([&] {
         GTS_CHECK(out != nullptr, GTS_EINVAL, "null output handle");
         GTS_CHECK(objs != nullptr, GTS_EINVAL, "null objects");
-        GTS_CHECK(metric == GTS_L2_F32 || metric == GTS_EDIT_U8 || metric == GTS_COSINE_F32, GTS_EINVAL,
-                  "unknown metric");
-        // the angular metric is an L2 index over unit vectors
+        GTS_CHECK(metric == GTS_L2_F32 || metric == GTS_EDIT_U8 || metric == GTS_COSINE_F32 || metric == GTS_L1_F32,
+                  GTS_EINVAL, "unknown metric");
+        // the angular metric is an L2 index over unit vectors; the Manhattan
+        // metric is the vector index with L1 distances
         const bool angular = metric == GTS_COSINE_F32;
-        if (angular) metric = GTS_L2_F32;
+        const bool l1 = metric == GTS_L1_F32;
+        if (angular || l1) metric = GTS_L2_F32;
         GTS_CHECK(num_pivots >= 1 && num_pivots <= kMaxPivots, GTS_EINVAL, "num_pivots must be in [1, 32]");
         GTS_CHECK(fanout >= 2 && fanout <= 64, GTS_EINVAL, "fanout must be in [2, 64]");
         GTS_CHECK(objs->n >= 1, GTS_EINVAL, "an index needs at least one object");
@@ -95,13 +97,23 @@ gts_status gts_build_index(const gts_objects *objs, int32_t metric, int32_t num_
         idx->data.max_strlen = idx->opts.max_strlen;
         HostObjects h;
         idx->angular = angular;
-        read_objects(objs, metric, metric == GTS_L2_F32 ? objs->dim : 0, idx->opts.max_strlen, &h, angular);
+        idx->l1 = l1;
+        DevBuf rows;   // vector objects given in device memory stay there
+        const bool on_device = metric == GTS_L2_F32 && objs->location == GTS_DEVICE;
+        GTS_CHECK(objs->n < ((int64_t)1 << 31), GTS_ENOTSUP, "at most 2^31-1 objects");
+        if (on_device) {
+            read_rows_device(objs, objs->dim, angular, idx->stream, &rows);
+            h.metric = metric;
+            h.dim = objs->dim;
+            h.ids.resize(objs->n);
+        } else {
+            read_objects(objs, metric, metric == GTS_L2_F32 ? objs->dim : 0, idx->opts.max_strlen, &h, angular);
+        }
         for (int64_t i = 0; i < h.count(); i++) h.ids[i] = (uint32_t)i;
-        GTS_CHECK(h.count() < ((int64_t)1 << 31), GTS_ENOTSUP, "at most 2^31-1 objects");
         idx->next_id = h.count();
         idx->cache_host.metric = metric;
         idx->cache_host.dim = h.dim;
-        build_tree(idx.get(), h);
+        build_tree(idx.get(), h, on_device ? &rows : nullptr);
         tune_cache_load(idx.get());
         *out = idx.release();
     });
@@ -215,7 +227,7 @@ gts_status gts_get_info(const gts_index *idx, gts_index_info *out)
         GTS_CHECK(idx != nullptr && out != nullptr, GTS_EINVAL, "null argument");
         const IndexData &d = idx->data;
         std::memset(out, 0, sizeof(*out));
-        out->metric = idx->angular ? GTS_COSINE_F32 : d.metric;
+        out->metric = idx->angular ? GTS_COSINE_F32 : idx->l1 ? GTS_L1_F32 : d.metric;
         out->dim = d.dim;
         out->num_pivots = d.m;
         out->fanout = d.tree.fanout;
@@ -235,6 +247,8 @@ gts_status gts_get_info(const gts_index *idx, gts_index_info *out)
                                 &d.tree.leaf_first, &d.tree.leaf_cnt})
             bytes += (int64_t)b->bytes;
         out->device_bytes = bytes;
+        out->rebuild_ms = idx->rebuild_ms;
+        out->epoch = idx->epoch;
     });
 }
 

@@ -57,6 +57,21 @@ __device__ __forceinline__ float out_dist(float d, bool angular)
     return angular ? 2.f * asinf(fminf(0.5f * d, 1.f)) : d;
 }
 
+// One term of a direct-difference vector distance and the distance from the
+// summed terms: (a - b)^2 and the square root for L2, |a - b| and the sum
+// itself for L1 (Manhattan).
+template <bool L1> __device__ __forceinline__ float dterm(float acc, float a, float b)
+{
+    const float d = a - b;
+    return L1 ? acc + fabsf(d) : fmaf(d, d, acc);
+}
+template <bool L1> __device__ __forceinline__ float dfinish(float acc) { return L1 ? acc : sqrtf(acc); }
+__device__ __forceinline__ float dterm_rt(bool l1, float acc, float a, float b)
+{
+    return l1 ? dterm<true>(acc, a, b) : dterm<false>(acc, a, b);
+}
+__device__ __forceinline__ float dfinish_rt(bool l1, float acc) { return l1 ? acc : sqrtf(acc); }
+
 __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll

@@ -170,7 +170,7 @@ struct CacheList {
     DevBuf ids;                   // uint32 [cap]
     DevBuf ins_ep, del_ep;        // uint32 [cap] epochs of the slot's insert and delete
                                   // (del_ep 0xffffffff: live)
-    DevBuf cp;                    // float [cap][mpad] distances to the global pivots
+    DevBuf cp;                    // float [cap][mpad] distances to the global pivots (edit)
     std::vector<uint32_t> h_ids;
     std::vector<uint8_t> h_live;
     int64_t n_live = 0;           // live cached objects
@@ -198,10 +198,14 @@ struct HostObjects {
 };
 
 // Build the tree and all device tables of `idx` over `objs` (ids given);
-// objs becomes the index's host mirror (moved from).
-void build_tree(gts_index *idx, HostObjects &objs);
-// Rebuild over every live object (tree and cache), keeping ids.
-void rebuild(gts_index *idx);
+// objs becomes the index's host mirror (moved from).  A vector index may take
+// its rows from `rows` (n rows of dp floats on the device, moved from) instead
+// of objs.vecs.
+void build_tree(gts_index *idx, HostObjects &objs, DevBuf *rows = nullptr);
+// Rebuild over every live object (tree and cache), keeping ids; for a vector
+// index, n_extra more rows already on the device (extra_rows, dp floats each)
+// with their ids join.
+void rebuild(gts_index *idx, DevBuf *extra_rows = nullptr, int64_t n_extra = 0, const uint32_t *extra_ids = nullptr);
 // Copy n rows of dim floats (src, packed) into device rows of dp floats
 // (dp >= dim; the dp - dim padding columns become zero).  Host sources are
 // copied as one contiguous transfer (packed to the padded width on the host
@@ -213,8 +217,11 @@ void rows_to_device(float *dst, int dp, const float *src, int dim, int64_t n, bo
 void alphabet_add(gts_index *idx, const std::vector<uint8_t> &chars);
 // Streamed updates.
 void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids);
-// upload = false: host bookkeeping only (a rebuild follows).
+// upload = false: host bookkeeping only (a rebuild follows).  A delete that
+// leaves more than half of the tree's positions deleted rebuilds the index.
 int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload = true);
+// More than half of the tree deleted once `more` further positions are.
+bool tree_mostly_deleted(const gts_index *idx, int64_t more = 0);
 // Batch update: deletions, insertions (fresh ids into out_ids), one rebuild.
 void update_batch(gts_index *idx, const HostObjects &ins, const int64_t *del, int64_t n_del, int64_t *out_ids,
                   int64_t *n_deleted);
@@ -407,6 +414,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
 // direction and is an EINVAL error.
 void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max_strlen, HostObjects *out,
                   bool angular = false);
+// Vector objects already on the device into rows of dp floats (dim rounded
+// up to 4, zero padding) on the device, validated there (finite; angular:
+// scaled to unit length, a zero row an EINVAL error).
+void read_rows_device(const gts_objects *o, int32_t dim, bool angular, hipStream_t st, DevBuf *rows);
 
 }  // namespace gts
 
@@ -425,10 +436,14 @@ struct gts_index {
     uint32_t epoch = 0;                // updates applied so far (each insert or delete call: one)
     int64_t n_deleted_tree = 0;
     int64_t rebuilds = 0;
+    double rebuild_ms = 0.0;
     int32_t num_pivots = 0, fanout = 0;
     // GTS_COSINE_F32: the index is an L2 index over unit vectors; distances
     // are reported as angles 2 asin(d / 2) and radii converted to chords
     bool angular = false;
+    // GTS_L1_F32: the vector index under the Manhattan metric (no bf16 MFMA
+    // tables; candidates from the float32 pivot table, float32 distances)
+    bool l1 = false;
     gts_build_opts opts{};
     std::string tune_cache;            // tuned-settings file ("" = none)
     std::mutex tune_mu;                // guards `tuned` and the file

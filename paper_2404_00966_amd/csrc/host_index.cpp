@@ -203,7 +203,7 @@ std::vector<int64_t> leaf_cuts(const std::vector<int64_t> &bnd, int64_t n, int64
 // node boxes, slab summaries and leaf pivots formed in leaf order in HBM.
 // perm[p] = input row of position p.
 // ---------------------------------------------------------------------------
-void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::vector<int32_t> &perm)
+void build_l2(gts_index *idx, const HostObjects &objs, DevBuf *rows, StageClock &clock, std::vector<int32_t> &perm)
 {
     hipStream_t st = idx->stream;
     IndexData &d = idx->data;
@@ -214,10 +214,17 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     d.dp = (objs.dim + 3) / 4 * 4;
     d.ksteps = (objs.dim + 31) / 32;
     const int dp = d.dp;
-    const bool mfma = d.dim <= kMaxMfmaDim;
+    const bool l1 = idx->l1;                 // Manhattan: no bf16 tables at all
+    const bool mfma = d.dim <= kMaxMfmaDim && !l1;
+    // the rows in input order, on the device (given, or uploaded from the host)
     DevBuf in_x;
-    in_x.alloc((size_t)n * dp * sizeof(float));
-    rows_to_device(in_x.as<float>(), dp, objs.vecs.data(), objs.dim, n, false, st);
+    if (rows) {
+        in_x = std::move(*rows);
+        GTS_CHECK(in_x.bytes >= (size_t)n * dp * sizeof(float), GTS_EINVAL, "build: device rows too short");
+    } else {
+        in_x.alloc((size_t)n * dp * sizeof(float));
+        rows_to_device(in_x.as<float>(), dp, objs.vecs.data(), objs.dim, n, false, st);
+    }
     clock.mark("upload");
 
     // ---- global pivots and the pivot table (input order) --------------------
@@ -233,17 +240,21 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     mind.alloc((size_t)n * sizeof(float));
     nearc.alloc((size_t)n * sizeof(int32_t));
     k::fft_centers_l2(in_x.as<float>(), n, dp, m, keys.as<uint64_t>(), dcent.as<int32_t>(), mind.as<float>(),
-                      nearc.as<int32_t>(), st);
+                      nearc.as<int32_t>(), st, l1);
     d.P32.alloc((size_t)std::max(m, 1) * dp * sizeof(float));
     k::gather_rows(in_x.as<float>(), dp, dcent.as<int32_t>(), m, d.P32.as<float>(), st);
     DevBuf pt_in;
     pt_in.alloc((size_t)mpad * n * sizeof(float));
-    k::dist_l2_pivots(in_x.as<float>(), n, d.P32.as<float>(), m, mpad, dp, pt_in.as<float>(), n, 1, st);
+    k::dist_l2_pivots(in_x.as<float>(), n, d.P32.as<float>(), m, mpad, dp, pt_in.as<float>(), n, 1, st, l1);
     clock.mark("global pivots + table");
 
     // ---- cells: farthest-first centres, nearest centre of every object -----
     const int K = (int)std::max<int64_t>(1, std::min<int64_t>({t.n_leaves / 8, (int64_t)kMaxCentres, n}));
-    const int64_t S = mfma ? std::min<int64_t>(n, std::max<int64_t>(16384, 32 * (int64_t)K)) : n;
+    // the centres come from a strided sample unless the rows are too wide for
+    // either nearest-centre search (then the traversal runs over every object
+    // and gives each its nearest centre itself)
+    const bool sampled = mfma || (int64_t)dp * sizeof(float) <= ((int64_t)48 << 10);
+    const int64_t S = sampled ? std::min<int64_t>(n, std::max<int64_t>(16384, 32 * (int64_t)K)) : n;
     DevBuf sx, dsidx;
     std::vector<int32_t> sidx;
     const float *fx = in_x.as<float>();
@@ -267,7 +278,7 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     cmind.alloc((size_t)S * sizeof(float));
     cnear.alloc((size_t)S * sizeof(int32_t));
     k::fft_centers_l2(fx, S, dp, K, ckeys.as<uint64_t>(), ccent.as<int32_t>(), cmind.as<float>(),
-                      cnear.as<int32_t>(), st);
+                      cnear.as<int32_t>(), st, l1);
     std::vector<int32_t> cent(K);
     GTS_HIP(hipMemcpyAsync(cent.data(), ccent.p, (size_t)K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
@@ -282,7 +293,12 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     const int32_t *cell = cnear.as<int32_t>();
     int cstride = 1;
     DevBuf c16, cn, ce, x16, xn_in, xe_in, near8;
-    if (S < n) {
+    if (S < n && !mfma) {
+        // exact float32 nearest centre (Manhattan, or rows wider than 128)
+        near8.alloc((size_t)n * sizeof(int32_t));
+        k::nearest_centre(in_x.as<float>(), dp, n, cx.as<float>(), K, l1, near8.as<int32_t>(), st);
+        cell = near8.as<int32_t>();
+    } else if (S < n) {
         // nearest centre by bf16 MFMA estimates (padding centres never win)
         c16.alloc((size_t)Kp * d.ksteps * 32 * sizeof(uint16_t));
         cn.alloc((size_t)Kp * sizeof(float));
@@ -302,14 +318,14 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     }
     DevBuf cdist;
     cdist.alloc((size_t)n * sizeof(float));
-    k::centre_dist(in_x.as<float>(), dp, n, cell, cstride, cx.as<float>(), cdist.as<float>(), st);
+    k::centre_dist(in_x.as<float>(), dp, n, cell, cstride, cx.as<float>(), cdist.as<float>(), st, l1);
     clock.mark("centres");
     // centre-to-centre distances, then the chain (host, K x K)
     std::vector<float> dk((size_t)K * K);
     {
         DevBuf ddk;
         ddk.alloc(dk.size() * sizeof(float));
-        k::dist_l2_pivots(cx.as<float>(), K, cx.as<float>(), K, K, dp, ddk.as<float>(), K, 1, st);
+        k::dist_l2_pivots(cx.as<float>(), K, cx.as<float>(), K, K, dp, ddk.as<float>(), K, 1, st, l1);
         GTS_HIP(hipMemcpyAsync(dk.data(), ddk.p, dk.size() * sizeof(float), hipMemcpyDeviceToHost, st));
         GTS_HIP(hipStreamSynchronize(st));
     }
@@ -361,18 +377,20 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     k::fill_u32(ptmax.as<uint32_t>(), 1, 0u, st);
     k::max_f32(d.PT.as<float>(), (int64_t)m * n, ptmax.as<uint32_t>(), st);
     clock.mark("boxes");
-    d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
-    d.xn.alloc((size_t)d.npad * sizeof(float));
-    d.xe.alloc((size_t)d.npad * sizeof(float));
-    k::rows_bf16(d.X32.as<float>(), n, d.npad, d.dim, dp, d.ksteps, d.X16t.as<uint16_t>(), d.xn.as<float>(),
-                 d.xe.as<float>(), INFINITY, st);
-    d.slab_emax.alloc((size_t)d.n_slabs * sizeof(float));
-    d.slab_nmax.alloc((size_t)d.n_slabs * sizeof(float));
-    d.slab_leaf_lo.alloc((size_t)d.n_slabs * sizeof(int32_t));
-    d.slab_leaf_hi.alloc((size_t)d.n_slabs * sizeof(int32_t));
-    k::slab_summary(d.xn.as<float>(), d.xe.as<float>(), n, t.leaf_first.as<int32_t>(), t.n_leaves, d.n_slabs,
-                    d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
-                    d.slab_leaf_hi.as<int32_t>(), st);
+    if (!l1) {
+        d.X16t.alloc((size_t)d.npad * d.ksteps * 32 * sizeof(uint16_t));
+        d.xn.alloc((size_t)d.npad * sizeof(float));
+        d.xe.alloc((size_t)d.npad * sizeof(float));
+        k::rows_bf16(d.X32.as<float>(), n, d.npad, d.dim, dp, d.ksteps, d.X16t.as<uint16_t>(), d.xn.as<float>(),
+                     d.xe.as<float>(), INFINITY, st);
+        d.slab_emax.alloc((size_t)d.n_slabs * sizeof(float));
+        d.slab_nmax.alloc((size_t)d.n_slabs * sizeof(float));
+        d.slab_leaf_lo.alloc((size_t)d.n_slabs * sizeof(int32_t));
+        d.slab_leaf_hi.alloc((size_t)d.n_slabs * sizeof(int32_t));
+        k::slab_summary(d.xn.as<float>(), d.xe.as<float>(), n, t.leaf_first.as<int32_t>(), t.n_leaves, d.n_slabs,
+                        d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
+                        d.slab_leaf_hi.as<int32_t>(), st);
+    }
     // leaf pivots: the leaf's object nearest its centroid and the largest
     // distance from it to the leaf's objects (double, widened by 1e-6)
     d.lpad = (t.n_leaves + 63) / 64 * 64;
@@ -381,13 +399,15 @@ void build_l2(gts_index *idx, const HostObjects &objs, StageClock &clock, std::v
     d.PL32.alloc((size_t)d.lpad * dp * sizeof(float));
     d.leafR.alloc((size_t)d.lpad * sizeof(float));
     k::leaf_pivots(d.X32.as<float>(), dp, d.dim, t.leaf_first.as<int32_t>(), t.leaf_cnt.as<int32_t>(), t.n_leaves,
-                   d.lpad, cen.as<double>(), d.PL32.as<float>(), d.leafR.as<float>(), st);
-    d.PL16t.alloc((size_t)d.lpad * d.ksteps * 32 * sizeof(uint16_t));
-    d.pln.alloc((size_t)d.lpad * sizeof(float));
-    d.ple.alloc((size_t)d.lpad * sizeof(float));
-    k::rows_bf16(d.PL32.as<float>(), d.lpad, d.lpad, d.dim, dp, d.ksteps, d.PL16t.as<uint16_t>(), d.pln.as<float>(),
-                 d.ple.as<float>(), INFINITY, st);
-    k::mark_empty(t.leaf_cnt.as<int32_t>(), t.n_leaves, d.lpad, d.pln.as<float>(), st);
+                   d.lpad, cen.as<double>(), d.PL32.as<float>(), d.leafR.as<float>(), st, l1);
+    if (!l1) {
+        d.PL16t.alloc((size_t)d.lpad * d.ksteps * 32 * sizeof(uint16_t));
+        d.pln.alloc((size_t)d.lpad * sizeof(float));
+        d.ple.alloc((size_t)d.lpad * sizeof(float));
+        k::rows_bf16(d.PL32.as<float>(), d.lpad, d.lpad, d.dim, dp, d.ksteps, d.PL16t.as<uint16_t>(), d.pln.as<float>(),
+                     d.ple.as<float>(), INFINITY, st);
+        k::mark_empty(t.leaf_cnt.as<int32_t>(), t.n_leaves, d.lpad, d.pln.as<float>(), st);
+    }
     uint32_t pm = 0;
     GTS_HIP(hipMemcpyAsync(&pm, ptmax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
@@ -713,7 +733,7 @@ void build_edit(gts_index *idx, const HostObjects &objs, StageClock &clock, std:
 
 }  // namespace
 
-void build_tree(gts_index *idx, HostObjects &objs)
+void build_tree(gts_index *idx, HostObjects &objs, DevBuf *rows)
 {
     hipStream_t st = idx->stream;
     IndexData &d = idx->data;
@@ -726,7 +746,7 @@ void build_tree(gts_index *idx, HostObjects &objs)
     d.m = idx->num_pivots;
     tree_shape(idx, n);
     std::vector<int32_t> perm;   // input row of each position
-    if (objs.metric == GTS_L2_F32) build_l2(idx, objs, clock, perm);
+    if (objs.metric == GTS_L2_F32) build_l2(idx, objs, rows, clock, perm);
     else build_edit(idx, objs, clock, perm);
 
     // ---- ids in leaf order, tombstones, id maps, host mirror ----------------
@@ -747,9 +767,14 @@ void build_tree(gts_index *idx, HostObjects &objs)
     idx->n_deleted_tree = 0;
     idx->pos_of_id.assign(std::max<int64_t>((int64_t)max_id + 1, idx->next_id), -1);
     for (int64_t p = 0; p < n; p++) idx->pos_of_id[pid[p]] = p;
-    // the objects stay in input order on the host; host_row[p] is the row of
-    // the object at position p
+    // the host mirror keeps the objects' ids (and an edit index its strings)
+    // in input order; host_row[p] is the row of the object at position p.
+    // Vector rows live on the device only.
     idx->host = std::move(objs);
+    if (d.metric == GTS_L2_F32) {
+        idx->host.vecs.clear();
+        idx->host.vecs.shrink_to_fit();
+    }
     idx->host_row = std::move(perm);
     GTS_HIP(hipStreamSynchronize(st));
     clock.mark("tombstones + maps");
@@ -782,11 +807,16 @@ void cache_reserve(gts_index *idx, int64_t need)
     grow(c.ids, sizeof(uint32_t));
     grow(c.ins_ep, sizeof(uint32_t));
     grow(c.del_ep, sizeof(uint32_t));
-    grow(c.cp, (size_t)d.tree.mpad * sizeof(float));
+    if (d.metric != GTS_L2_F32) grow(c.cp, (size_t)d.tree.mpad * sizeof(float));
     c.cap = cap;
 }
 
 }  // namespace
+
+bool tree_mostly_deleted(const gts_index *idx, int64_t more)
+{
+    return 2 * (idx->n_deleted_tree + more) > idx->data.n;
+}
 
 static uint32_t next_epoch(gts_index *idx)
 {
@@ -831,13 +861,11 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     GTS_HIP(hipMemcpyAsync(c.ids.as<uint32_t>() + s0, nid.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     k::fill_u32(c.ins_ep.as<uint32_t>() + s0, n, e, st);
     k::fill_u32(c.del_ep.as<uint32_t>() + s0, n, 0xffffffffu, st);
-    // the new slots' distances to the global pivots (the cache scan's Lemma 1)
-    const int mpad = d.tree.mpad;
-    float *cp = c.cp.as<float>() + (size_t)s0 * mpad;
-    if (d.metric == GTS_L2_F32) {
-        k::dist_l2_pivots(c.X32.as<float>() + (size_t)s0 * d.dp, n, d.P32.as<float>(), d.m, mpad, d.dp, cp, 1, mpad,
-                          st);
-    } else {
+    // edit distance: the new slots' distances to the global pivots (the
+    // cache scan's Lemma 1; for L2 the scan is a dense distance tile)
+    if (d.metric != GTS_L2_F32) {
+        const int mpad = d.tree.mpad;
+        float *cp = c.cp.as<float>() + (size_t)s0 * mpad;
         DevBuf sc, so;
         upload(sc, objs.chars.empty() ? std::vector<uint8_t>(1, 0) : objs.chars, st);
         upload(so, objs.offsets, st);
@@ -850,9 +878,7 @@ void insert_objects(gts_index *idx, const HostObjects &objs, int64_t *out_ids)
     for (int64_t i = 0; i < n; i++) {
         ch.metric = objs.metric;
         ch.dim = objs.dim;
-        if (objs.metric == GTS_L2_F32) {
-            ch.vecs.insert(ch.vecs.end(), objs.vecs.begin() + i * objs.dim, objs.vecs.begin() + (i + 1) * objs.dim);
-        } else {
+        if (objs.metric != GTS_L2_F32) {   // (vector rows stay on the device)
             ch.chars.insert(ch.chars.end(), objs.chars.begin() + objs.offsets[i],
                             objs.chars.begin() + objs.offsets[i + 1]);
             ch.offsets.push_back((int64_t)ch.chars.size());
@@ -931,6 +957,10 @@ int64_t delete_ids(gts_index *idx, const int64_t *ids, int64_t n, bool upload)
     if (np) k::scatter_u32(d.del_ep.as<uint32_t>(), dpk + ns, dpk + na + ns, (int64_t)np, st);
     if (nt) k::scatter_u32(d.tomb.as<uint32_t>(), dpk + ns + np, dpk + na + ns + np, (int64_t)nt, st);
     GTS_HIP(hipStreamSynchronize(st));
+    // a tree that is mostly tombstones is rebuilt from its live objects (its
+    // boxes and radii still cover the deleted ones, and a kNN bound window
+    // may hold fewer live objects than k)
+    if (tree_mostly_deleted(idx) && idx->data.n - idx->n_deleted_tree + c.n_live >= 1) rebuild(idx);
     return done;
 }
 
@@ -945,43 +975,91 @@ void update_batch(gts_index *idx, const HostObjects &ins, const int64_t *del, in
     GTS_CHECK(idx->next_id + n < ((int64_t)1 << 31), GTS_ENOTSUP, "id space exhausted (ids stay below 2^31)");
     const int64_t done = delete_ids(idx, del, n_del, false);
     if (n_deleted) *n_deleted = done;
+    if ((int64_t)idx->slot_of_id.size() < idx->next_id + n) idx->slot_of_id.resize(idx->next_id + n, -1);
+    if ((int64_t)idx->pos_of_id.size() < idx->next_id + n) idx->pos_of_id.resize(idx->next_id + n, -1);
+    std::vector<uint32_t> new_ids(n);
+    for (int64_t i = 0; i < n; i++) {
+        new_ids[i] = (uint32_t)idx->next_id++;
+        if (out_ids) out_ids[i] = new_ids[i];
+    }
+    if (idx->data.metric == GTS_L2_F32) {
+        // the new rows join the rebuild on the device
+        DevBuf rows;
+        rows.alloc((size_t)std::max<int64_t>(n, 1) * idx->data.dp * sizeof(float));
+        rows_to_device(rows.as<float>(), idx->data.dp, ins.vecs.data(), ins.dim, n, false, idx->stream);
+        rebuild(idx, &rows, n, new_ids.data());
+        return;
+    }
     HostObjects &ch = idx->cache_host;
     ch.metric = idx->data.metric;
     ch.dim = idx->data.dim;
-    if ((int64_t)idx->slot_of_id.size() < idx->next_id + n) idx->slot_of_id.resize(idx->next_id + n, -1);
-    if ((int64_t)idx->pos_of_id.size() < idx->next_id + n) idx->pos_of_id.resize(idx->next_id + n, -1);
     for (int64_t i = 0; i < n; i++) {
-        const uint32_t id = (uint32_t)idx->next_id++;
-        if (out_ids) out_ids[i] = id;
-        if (ins.metric == GTS_L2_F32) {
-            ch.vecs.insert(ch.vecs.end(), ins.vecs.begin() + i * ins.dim, ins.vecs.begin() + (i + 1) * ins.dim);
-        } else {
-            ch.chars.insert(ch.chars.end(), ins.chars.begin() + ins.offsets[i], ins.chars.begin() + ins.offsets[i + 1]);
-            ch.offsets.push_back((int64_t)ch.chars.size());
-        }
-        ch.ids.push_back(id);
-        idx->cache.h_ids.push_back(id);
+        ch.chars.insert(ch.chars.end(), ins.chars.begin() + ins.offsets[i], ins.chars.begin() + ins.offsets[i + 1]);
+        ch.offsets.push_back((int64_t)ch.chars.size());
+        ch.ids.push_back(new_ids[i]);
+        idx->cache.h_ids.push_back(new_ids[i]);
         idx->cache.h_live.push_back(1);
     }
-    if (ins.metric != GTS_L2_F32 && n) alphabet_add(idx, ins.chars);
+    if (n) alphabet_add(idx, ins.chars);
     rebuild(idx);
 }
 
 // Rebuild over every live object (Sec. 4.4: when the cache list exceeds its
 // limit the whole index is reconstructed from the index and the cache).
-void rebuild(gts_index *idx)
+void rebuild(gts_index *idx, DevBuf *extra_rows, int64_t n_extra, const uint32_t *extra_ids)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     HostObjects all;
     all.metric = idx->data.metric;
     all.dim = idx->host.dim ? idx->host.dim : idx->cache_host.dim;
     const HostObjects &h = idx->host;
-    for (int64_t p = 0; p < (int64_t)idx->host_row.size(); p++)
-        if (!idx->h_tomb[p]) all.append_from(h, idx->host_row[p]);
-    const HostObjects &ch = idx->cache_host;
-    for (int64_t s = 0; s < ch.count(); s++)
-        if (idx->cache.h_live[s]) all.append_from(ch, s);
-    GTS_CHECK(all.count() >= 1, GTS_EINVAL, "cannot rebuild an index with no live objects");
-    build_tree(idx, all);
+    const CacheList &cl = idx->cache;
+    if (idx->data.metric == GTS_L2_F32) {
+        // vector rows never leave the device: the live tree rows, the live
+        // cache rows and the batch's new rows are gathered there
+        IndexData &d = idx->data;
+        hipStream_t st = idx->stream;
+        std::vector<int32_t> tree_pos, slots;
+        for (int64_t p = 0; p < (int64_t)idx->host_row.size(); p++)
+            if (!idx->h_tomb[p]) {
+                tree_pos.push_back((int32_t)p);
+                all.ids.push_back(h.ids[idx->host_row[p]]);
+            }
+        for (int64_t s = 0; s < cl.count; s++)
+            if (cl.h_live[s]) {
+                slots.push_back((int32_t)s);
+                all.ids.push_back(cl.h_ids[s]);
+            }
+        for (int64_t i = 0; i < n_extra; i++) all.ids.push_back(extra_ids[i]);
+        const int64_t n = all.count();
+        GTS_CHECK(n >= 1, GTS_EINVAL, "cannot rebuild an index with no live objects");
+        DevBuf rows, dpos, dslot;
+        const size_t row_bytes = (size_t)d.dp * sizeof(float);
+        rows.alloc((size_t)n * row_bytes);
+        const int64_t a = (int64_t)tree_pos.size(), b = (int64_t)slots.size();
+        if (a) {
+            upload(dpos, tree_pos, st);
+            k::gather_rows(d.X32.as<float>(), d.dp, dpos.as<int32_t>(), a, rows.as<float>(), st);
+        }
+        if (b) {
+            upload(dslot, slots, st);
+            k::gather_rows(cl.X32.as<float>(), d.dp, dslot.as<int32_t>(), b, rows.as<float>() + (size_t)a * d.dp,
+                           st);
+        }
+        if (n_extra)
+            GTS_HIP(hipMemcpyAsync(rows.as<float>() + (size_t)(a + b) * d.dp, extra_rows->p, (size_t)n_extra * row_bytes,
+                                   hipMemcpyDeviceToDevice, st));
+        GTS_HIP(hipStreamSynchronize(st));
+        build_tree(idx, all, &rows);
+    } else {
+        for (int64_t p = 0; p < (int64_t)idx->host_row.size(); p++)
+            if (!idx->h_tomb[p]) all.append_from(h, idx->host_row[p]);
+        const HostObjects &ch = idx->cache_host;
+        for (int64_t s = 0; s < ch.count(); s++)
+            if (cl.h_live[s]) all.append_from(ch, s);
+        GTS_CHECK(all.count() >= 1, GTS_EINVAL, "cannot rebuild an index with no live objects");
+        build_tree(idx, all);
+    }
     CacheList &c = idx->cache;
     c.count = 0;
     c.n_live = 0;
@@ -990,6 +1068,7 @@ void rebuild(gts_index *idx)
     idx->cache_host.clear();
     std::fill(idx->slot_of_id.begin(), idx->slot_of_id.end(), -1);
     idx->rebuilds++;
+    idx->rebuild_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace gts

@@ -227,6 +227,27 @@ void read_objects(const gts_objects *o, int32_t metric, int32_t dim, int32_t max
     out->ids.resize(n);
 }
 
+void read_rows_device(const gts_objects *o, int32_t dim, bool angular, hipStream_t st, DevBuf *rows)
+{
+    GTS_CHECK(o != nullptr && o->location == GTS_DEVICE, GTS_EINVAL, "device rows expected");
+    GTS_CHECK(o->dim == dim && dim >= 1, GTS_EINVAL, "dimension mismatch");
+    const int64_t n = o->n;
+    GTS_CHECK(n >= 1 && o->vecs != nullptr, GTS_EINVAL, "null vectors");
+    const int dp = (dim + 3) / 4 * 4;
+    rows->alloc((size_t)n * dp * sizeof(float));
+    rows_to_device(rows->as<float>(), dp, o->vecs, dim, n, true, st);
+    DevBuf flags;
+    flags.alloc(2 * sizeof(uint32_t));
+    k::fill_u32(flags.as<uint32_t>(), 2, 0u, st);
+    k::check_finite(rows->as<float>(), n, dim, dp, flags.as<uint32_t>(), st);
+    if (angular) k::normalize_rows(rows->as<float>(), n, dim, dp, flags.as<uint32_t>() + 1, st);
+    uint32_t h[2] = {0u, 0u};
+    GTS_HIP(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    GTS_HIP(hipStreamSynchronize(st));
+    GTS_CHECK(h[0] == 0, GTS_EINVAL, "non-finite vector value");
+    GTS_CHECK(h[1] == 0, GTS_EINVAL, "a zero vector has no direction (angular metric)");
+}
+
 namespace k {
 void require(bool ok, const char *what)
 {
@@ -313,7 +334,8 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
 
     const bool plain = b.mode == GTS_MODE_PLAIN || (l2 && d.dim > kMaxMfmaDim);
     // float32 selection: Lemma 1 on the pivot table instead of bf16 tiles
-    const bool sel32 = l2 && !plain && b.precision == GTS_FP32;
+    // (the Manhattan metric always selects on the float32 pivot table)
+    const bool sel32 = l2 && !plain && (b.precision == GTS_FP32 || idx->l1);
     int64_t n_wide = 0;
     rec(cx, 2);
     if (plain) {
@@ -335,6 +357,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         pa.leaf_piv32 = l2 && d.lpad > 0 ? d.PL32.as<float>() : nullptr;
         pa.leafR = l2 && d.lpad > 0 ? d.leafR.as<float>() : nullptr;
         pa.angular = idx->angular ? 1 : 0;
+        pa.l1 = idx->l1 ? 1 : 0;
         rec(cx, 3);
         if (l2) k::plain_l2(tv, ov, d.P32.as<float>(), d.m, d.PT.as<float>(), qv.Q32, pa, st);
         else k::plain_edit(tv, oe, d.pchars.as<uint8_t>(), d.poff.as<int32_t>(), d.m, d.PTe.as<uint8_t>(), qe, pa, st);
@@ -357,7 +380,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
                               cx->ws[W_QCELLS].as<int32_t>() + q0 * k::kQueryCells, cx->ws[W_QCNT].as<int32_t>() + q0,
                               T, ng, ntiles, b.max_qlen, mask, items, small + kSmallItems, item_cap, t.n_leaves, st);
         }
-        if (l2 && d.lpad > 0 && !b.no_prune)
+        if (l2 && d.lpad > 0 && !b.no_prune && !idx->l1)
             k::leaf_ball(d.PL16t.as<uint16_t>(), d.pln.as<float>(), d.ple.as<float>(), d.leafR.as<float>(), t.n_leaves,
                          d.ksteps, qv.Q16t, qv.qn, qv.qe, T, ng, ntiles, mask, t.leaf_cnt.as<int32_t>(), counters, st);
         k::SlabView sv{d.slab_emax.as<float>(), d.slab_nmax.as<float>(), d.slab_leaf_lo.as<int32_t>(),
@@ -397,12 +420,13 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     // cache list: brute force, already verified
     const CacheList &c = idx->cache;
     if (b.cache_count > 0) {
-        k::CacheScan cs{c.ids.as<uint32_t>(), c.ins_ep.as<uint32_t>(), c.del_ep.as<uint32_t>(), c.cp.as<float>(),
-                        b.cache_count, d.m, mpad, qep, b.e_now, QP, (float)((d.dim + 8) * 5.9604645e-8)};
+        k::CacheScan cs{c.ids.as<uint32_t>(), c.ins_ep.as<uint32_t>(), c.del_ep.as<uint32_t>(),
+                        l2 ? nullptr : c.cp.as<float>(), b.cache_count, d.m, mpad, qep, b.e_now, QP};
         if (l2) {
             // emission cutoff: radius (range) or the widened bound T (kNN)
             float *cut = cx->ws[W_CUT].as<float>() + q0;
-            k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), cs, T, cut, cands, ccount, cap, idx->angular, st);
+            k::cache_scan_l2(qv.Q32, ng, d.dp, c.X32.as<float>(), cs, cut, cands, ccount, cap, idx->angular, st,
+                             idx->l1);
         } else {
             k::cache_scan_edit(qe, oe, ng, c.chars.as<uint8_t>(), kMaxStrlen, c.slen.as<int32_t>(), cs, base, cands,
                                ccount, cap, st);
@@ -505,7 +529,7 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     cx->stats.wide_queries += n_wide;
     if (l2)
         k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, !plain && !sel32,
-                     b.check_bound, st);
+                     b.check_bound, st, idx->l1);
     else k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
@@ -654,7 +678,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;
-    if (d.metric == GTS_L2_F32 && b.mode == GTS_MODE_BATCHED && b.precision == GTS_BF16_GUARDED && d.lpad > 0 &&
+    if (d.metric == GTS_L2_F32 && !idx->l1 && b.mode == GTS_MODE_BATCHED && b.precision == GTS_BF16_GUARDED &&
+        d.lpad > 0 &&
         d.dim <= kMaxMfmaDim && b.nq > 0) {
         bool knn = false;
         for (int64_t q = 0; q < b.nq && !knn; q++) knn = kin && kin[q] > 0;
@@ -710,7 +735,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     cx->stats.nq = nq;
     std::memset(out, 0, sizeof(*out));
     out->nq = nq;
-    out->metric = idx->angular ? GTS_COSINE_F32 : d.metric;
+    out->metric = idx->angular ? GTS_COSINE_F32 : idx->l1 ? GTS_L1_F32 : d.metric;
     out->location = rloc;
     double stage_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cx->timing && !cx->ev[0])
@@ -760,7 +785,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         float *qn = wsp<float>(cx, W_QN, nqpad);
         float *qerr = wsp<float>(cx, W_QE, nqpad);
         k::rows_bf16(Q32, nq, nqpad, d.dim, d.dp, d.ksteps, Q16, qn, qerr, 0.f, st);
-        k::dist_l2_pivots(Q32, nq, d.P32.as<float>(), d.m, mpad, d.dp, cx->ws[W_QP].as<float>(), 1, mpad, st);
+        k::dist_l2_pivots(Q32, nq, d.P32.as<float>(), d.m, mpad, d.dp, cx->ws[W_QP].as<float>(), 1, mpad, st,
+                          idx->l1);
         qv = k::QueryL2{Q32, Q16, qn, qerr};
     } else if (nq > 0) {
         GTS_CHECK(Q->offsets != nullptr, GTS_EINVAL, "null query offsets");
@@ -877,7 +903,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     // the nearest-leaf search and the leaf-window kNN bound run on bf16 MFMA
     // fragments of at most kMaxMfmaDim coordinates; wider rows use the tree
     // descent bound and keep the caller's order
-    const bool leaf_mfma = l2 && d.lpad > 0 && d.dim <= kMaxMfmaDim;
+    const bool leaf_mfma = l2 && d.lpad > 0 && d.dim <= kMaxMfmaDim && !idx->l1;
     if (nq > 1 && leaf_mfma) {
         // home = nearest leaf pivot; the order comes from a device sort
         near = wsp<int32_t>(cx, W_NEAR, (size_t)nqpad * k::kNearLeaves);
@@ -979,7 +1005,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
-            k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 256, base, home, st);
+            k::bound_l2(tv, ov, qv, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 256, base, home, st, idx->l1);
         } else {
             k::bound_edit(tv, oe, qe, cx->ws[W_QP].as<float>(), kq, nq, b.tomb_bound, 256, base, home, nullptr,
                           nullptr, st);
@@ -988,7 +1014,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     if (nq > 0)
         k::thresholds(base, cx->ws[W_QP].as<float>(), kq, nq, mpad, l2 ? 0 : 1, delta, d.pt_max,
                       cx->ws[W_T].as<float>(), cx->ws[W_THR].as<float>(), wsp<float>(cx, W_CUT, nqpad), st);
-    if (l2) k::sum_pad(cx->ws[W_T].as<float>(), qv.qe, nq, nqpad, wsp<float>(cx, W_TQE, nqpad), st);
+    if (l2 && !idx->l1) k::sum_pad(cx->ws[W_T].as<float>(), qv.qe, nq, nqpad, wsp<float>(cx, W_TQE, nqpad), st);
     rec(cx, 2);
     if (cx->timing && nq > 0) {
         GTS_HIP(hipStreamSynchronize(st));

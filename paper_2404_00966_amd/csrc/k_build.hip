@@ -5,6 +5,7 @@
 //
 //   k_gather_rows    : rows into a new order (float4 copies)
 //   k_gather_pt      : pivot-table columns into leaf order
+//   k_nearest_centre : every object's nearest centre (exact float32)
 //   k_centre_dist    : squared distance of each object to its cell's centre
 //   k_cell_keys      : per position, the chain rank of the object's cell
 //   k_leaf_boxes     : per leaf, per pivot row, min and max of the table
@@ -60,10 +61,11 @@ void gather_pt(const float *src, const int32_t *perm, int64_t n, int m, int mpad
     check_launch(__func__);
 }
 
-// out[o] = ||x_o - c_{cell[o * stride]}||^2 (float32; it orders the objects
-// inside a cell, nothing more), 16 lanes per object.
+// out[o] = ||x_o - c_{cell[o * stride]}||^2 (L1: the Manhattan distance;
+// float32, it orders the objects inside a cell, nothing more), 16 lanes per
+// object.
 __global__ void k_centre_dist(const float *__restrict__ X, int dp, int64_t n, const int32_t *__restrict__ cell,
-                              int stride, const float *__restrict__ C, float *__restrict__ out)
+                              int stride, const float *__restrict__ C, float *__restrict__ out, int l1)
 {
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int sl = threadIdx.x & 15;
@@ -72,10 +74,7 @@ __global__ void k_centre_dist(const float *__restrict__ X, int dp, int64_t n, co
     if (ok) {
         const float *x = X + (size_t)o * dp;
         const float *c = C + (size_t)cell[o * stride] * dp;
-        for (int i = sl; i < dp; i += 16) {
-            const float d = x[i] - c[i];
-            acc = fmaf(d, d, acc);
-        }
+        for (int i = sl; i < dp; i += 16) acc = dev::dterm_rt(l1 != 0, acc, x[i], c[i]);
     }
 #pragma unroll
     for (int s = 8; s > 0; s >>= 1) acc += __shfl_xor(acc, s, 16);
@@ -83,11 +82,55 @@ __global__ void k_centre_dist(const float *__restrict__ X, int dp, int64_t n, co
 }
 
 void centre_dist(const float *X, int dp, int64_t n, const int32_t *cell, int stride, const float *C, float *out,
-                 hipStream_t st)
+                 hipStream_t st, bool l1)
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_centre_dist, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, st, X, dp, n, cell, stride,
-                       C, out);
+                       C, out, l1 ? 1 : 0);
+    check_launch(__func__);
+}
+
+// Nearest centre of every object by exact float32 distances (the Manhattan
+// metric, or rows wider than the bf16 search takes): one thread per object,
+// the centres streaming through LDS `per` rows at a time (at most 48 KB);
+// the first of equal distances wins.  near[o] = centre number.
+__global__ __launch_bounds__(256) void k_nearest_centre(const float *__restrict__ X, int dp, int64_t n,
+                                                        const float *__restrict__ C, int K, int per, int l1,
+                                                        int32_t *__restrict__ near)
+{
+    extern __shared__ float s_c[];   // [per][dp]
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float *x = X + (size_t)(o < n ? o : 0) * dp;
+    float best = INFINITY;
+    int arg = 0;
+    for (int c0 = 0; c0 < K; c0 += per) {
+        const int rows = min(per, K - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < rows * dp; i += blockDim.x) s_c[i] = C[(size_t)c0 * dp + i];
+        __syncthreads();
+        for (int r = 0; r < rows; r++) {
+            const float *c = s_c + r * dp;
+            float acc = 0.f;
+            if (l1)
+                for (int i = 0; i < dp; i++) acc = dev::dterm<true>(acc, x[i], c[i]);
+            else
+                for (int i = 0; i < dp; i++) acc = dev::dterm<false>(acc, x[i], c[i]);
+            if (acc < best) {
+                best = acc;
+                arg = c0 + r;
+            }
+        }
+    }
+    if (o < n) near[o] = arg;
+}
+
+void nearest_centre(const float *X, int dp, int64_t n, const float *C, int K, bool l1, int32_t *near, hipStream_t st)
+{
+    if (n == 0) return;
+    require((int64_t)dp * sizeof(float) <= ((int64_t)48 << 10), "nearest_centre: rows wider than 48 KB");
+    const int per = (int)std::min<int64_t>(16, ((int64_t)48 << 10) / ((int64_t)dp * sizeof(float)));
+    hipLaunchKernelGGL(k_nearest_centre, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                       (size_t)per * dp * sizeof(float), st, X, dp, n, C, K, per, l1 ? 1 : 0, near);
     check_launch(__func__);
 }
 
@@ -287,13 +330,14 @@ __global__ __launch_bounds__(256) void k_leaf_centroid(const float *__restrict__
 // Per leaf j < lpad: the object nearest the centroid (squared distance in
 // double, coordinates in order; the first position wins ties), its row into
 // PL32 and the largest distance from it to the leaf's objects, in double,
-// widened by a relative 1e-6 so that the float bounds the true value.  An
+// widened by a relative 1e-6 so that the float bounds the true value (l1:
+// Manhattan distances throughout).  An
 // empty leaf (or j >= n_leaves) gets a zero row and R = -inf.
 __global__ __launch_bounds__(256) void k_leaf_pivot(const float *__restrict__ X32, int dp, int dim,
                                                     const int32_t *__restrict__ leaf_first,
                                                     const int32_t *__restrict__ leaf_cnt, int64_t n_leaves,
                                                     const double *__restrict__ cen, float *__restrict__ PL32,
-                                                    float *__restrict__ leafR)
+                                                    float *__restrict__ leafR, int l1)
 {
     __shared__ double s_v[256];
     __shared__ int32_t s_p[256];
@@ -314,7 +358,7 @@ __global__ __launch_bounds__(256) void k_leaf_pivot(const float *__restrict__ X3
         double s2 = 0.0;
         for (int c = 0; c < dim; c++) {
             const double df = (double)x[c] - ce[c];
-            s2 += df * df;
+            s2 += l1 ? fabs(df) : df * df;
         }
         if (s2 < bv) {   // u ascends within a thread: the first minimum stays
             bv = s2;
@@ -344,9 +388,9 @@ __global__ __launch_bounds__(256) void k_leaf_pivot(const float *__restrict__ X3
         double s2 = 0.0;
         for (int c = 0; c < dim; c++) {
             const double df = (double)x[c] - (double)y[c];
-            s2 += df * df;
+            s2 += l1 ? fabs(df) : df * df;
         }
-        rmax = fmax(rmax, sqrt(s2));
+        rmax = fmax(rmax, l1 ? s2 : sqrt(s2));
     }
     s_v[threadIdx.x] = rmax;
     __syncthreads();
@@ -367,13 +411,13 @@ __global__ void k_mark_empty(const int32_t *__restrict__ leaf_cnt, int64_t n_lea
 }
 
 void leaf_pivots(const float *X32, int dp, int dim, const int32_t *leaf_first, const int32_t *leaf_cnt,
-                 int64_t n_leaves, int64_t lpad, double *cen, float *PL32, float *leafR, hipStream_t st)
+                 int64_t n_leaves, int64_t lpad, double *cen, float *PL32, float *leafR, hipStream_t st, bool l1)
 {
     hipLaunchKernelGGL(k_leaf_centroid, dim3((unsigned)n_leaves), dim3(256), 0, st, X32, dp, dim, leaf_first, leaf_cnt,
                        cen);
     check_launch("leaf_pivots(centroid)");
     hipLaunchKernelGGL(k_leaf_pivot, dim3((unsigned)lpad), dim3(256), 0, st, X32, dp, dim, leaf_first, leaf_cnt,
-                       n_leaves, cen, PL32, leafR);
+                       n_leaves, cen, PL32, leafR, l1 ? 1 : 0);
     check_launch("leaf_pivots(pivot)");
 }
 

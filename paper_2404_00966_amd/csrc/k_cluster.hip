@@ -51,7 +51,7 @@ __device__ __forceinline__ void block_max_atomic(uint64_t v, uint64_t *dst)
 // left in keys[j]; nearest-centre bookkeeping; argmax into keys[j + 1].
 __global__ __launch_bounds__(256) void k_fft_step_l2(const float *__restrict__ X, int64_t n, int dp, int j,
                                                      uint64_t *__restrict__ keys, int32_t *__restrict__ centers,
-                                                     float *__restrict__ mind, int32_t *__restrict__ near)
+                                                     float *__restrict__ mind, int32_t *__restrict__ near, int l1)
 {
     const int64_t c = key_index(keys[j]);
     if (blockIdx.x == 0 && threadIdx.x == 0) centers[j] = (int32_t)c;
@@ -61,15 +61,24 @@ __global__ __launch_bounds__(256) void k_fft_step_l2(const float *__restrict__ X
         const float4 *x = reinterpret_cast<const float4 *>(X + (size_t)o * dp);
         const float4 *y = reinterpret_cast<const float4 *>(X + (size_t)c * dp);
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        for (int i = 0; i < dp / 4; i++) {
-            const float4 u = x[i], v = y[i];
-            const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
-            a0 = fmaf(d0, d0, a0);
-            a1 = fmaf(d1, d1, a1);
-            a2 = fmaf(d2, d2, a2);
-            a3 = fmaf(d3, d3, a3);
+        if (l1) {
+            for (int i = 0; i < dp / 4; i++) {
+                const float4 u = x[i], v = y[i];
+                a0 = dev::dterm<true>(a0, u.x, v.x);
+                a1 = dev::dterm<true>(a1, u.y, v.y);
+                a2 = dev::dterm<true>(a2, u.z, v.z);
+                a3 = dev::dterm<true>(a3, u.w, v.w);
+            }
+        } else {
+            for (int i = 0; i < dp / 4; i++) {
+                const float4 u = x[i], v = y[i];
+                a0 = dev::dterm<false>(a0, u.x, v.x);
+                a1 = dev::dterm<false>(a1, u.y, v.y);
+                a2 = dev::dterm<false>(a2, u.z, v.z);
+                a3 = dev::dterm<false>(a3, u.w, v.w);
+            }
         }
-        const float d = (a0 + a1) + (a2 + a3);
+        const float d = (a0 + a1) + (a2 + a3);   // squared for L2 (the order is the same)
         float m = mind[o];
         if (j == 0 || d < m) {
             m = d;
@@ -121,11 +130,12 @@ __global__ __launch_bounds__(256) void k_fft_step_edit(const uint8_t *__restrict
 }
 
 void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, int32_t *centers, float *mind,
-                    int32_t *near, hipStream_t st)
+                    int32_t *near, hipStream_t st, bool l1)
 {
     const unsigned grid = (unsigned)((n + 255) / 256);
     for (int j = 0; j < K; j++)
-        hipLaunchKernelGGL(k_fft_step_l2, dim3(grid), dim3(256), 0, st, X, n, dp, j, keys, centers, mind, near);
+        hipLaunchKernelGGL(k_fft_step_l2, dim3(grid), dim3(256), 0, st, X, n, dp, j, keys, centers, mind, near,
+                           l1 ? 1 : 0);
     check_launch(__func__);
 }
 

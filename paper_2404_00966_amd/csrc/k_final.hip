@@ -264,7 +264,7 @@ struct RecheckCtx {
     bool est;                                // candidates carry bf16 estimates
 };
 
-template <bool kShort, bool kCheck, class Emit>
+template <bool kShort, bool kCheck, bool kL1, class Emit>
 __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View &o, const RecheckCtx &rc,
                                               float delta, float eps_a, float eps_b, float eps_c, const Cand *g,
                                               int i0, int i1, int32_t *ring, long long *verified, long long *viol,
@@ -306,10 +306,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             for (int uu = 0; uu < 4; uu++) {
                 acc[uu] = 0.f;
 #pragma unroll
-                for (int t = 0; t < 8; t++) {
-                    const float df = rc.qr[t] - xv[uu][t];
-                    acc[uu] = fmaf(df, df, acc[uu]);
-                }
+                for (int t = 0; t < 8; t++) acc[uu] = dev::dterm<kL1>(acc[uu], rc.qr[t], xv[uu][t]);
             }
         } else {
             const float *x[4];
@@ -321,10 +318,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             for (int d = sl; d < o.dp; d += 16) {
                 const float qd = rc.qrow[d];
 #pragma unroll
-                for (int uu = 0; uu < 4; uu++) {
-                    const float df = qd - x[uu][d];
-                    acc[uu] = fmaf(df, df, acc[uu]);
-                }
+                for (int uu = 0; uu < 4; uu++) acc[uu] = dev::dterm<kL1>(acc[uu], qd, x[uu][d]);
             }
         }
 #pragma unroll
@@ -334,7 +328,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
 #pragma unroll
         for (int uu = 0; uu < 4; uu++) {
             const bool mine = nd[uu] && sl == 0;
-            const float d = sqrtf(acc[uu]);
+            const float d = dev::dfinish<kL1>(acc[uu]);
             if (mine) (*verified)++;
             if (kCheck && mine && rc.est) {
                 // invariant of the bf16 selection: the exact distance lies in
@@ -395,7 +389,7 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
 // recheck chunks of 64 * kChunk candidates in turn; kept keys are compacted
 // per wave (one LDS atomic reserves the wave's slots) and sorted in LDS
 // (s_keys, kSortCapL2) or in the query's scratch run.
-template <bool kShort, bool kCheck>
+template <bool kShort, bool kCheck, bool kL1>
 __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
                                 float eps_b, float eps_c, int64_t q, uint64_t *s_keys, int32_t *ring, bool est)
 {
@@ -483,7 +477,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
     };
     const int nw = (int)(blockDim.x >> 6);
     for (int c0 = wave * 64 * kChunk; c0 < ns; c0 += nw * 64 * kChunk)
-        recheck_chunk<kShort, kCheck>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
+        recheck_chunk<kShort, kCheck, kL1>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
                                       &verified, &viol, emit);
     __syncthreads();
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
@@ -501,7 +495,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
 // each lane holds in registers), bounds the answer set; then one chunk of
 // rechecks (above).  Kept keys are compacted with ballots into the wave's
 // LDS run and sorted there.
-template <bool kShort, bool kCheck>
+template <bool kShort, bool kCheck, bool kL1>
 __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, float eps_a,
                                float eps_b, float eps_c, int64_t q, uint64_t *keys, int32_t *ring, bool est)
 {
@@ -558,7 +552,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
         if (keep) keys[nk + dev::lanes_below(m)] = key;
         nk += __popcll(m);
     };
-    recheck_chunk<kShort, kCheck>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, &viol, emit);
+    recheck_chunk<kShort, kCheck, kL1>(a, o, rc, delta, eps_a, eps_b, eps_c, g, 0, ns, ring, &verified, &viol, emit);
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
     for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
     if (lane == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
@@ -578,7 +572,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 // blk_q (more than kWaveSortCap candidates) one each, the rest take four
 // queries each, one per wave, skipping those; the long workgroups start first
 // and overlap the bulk of the work.
-template <bool kShort, bool kCheck>
+template <bool kShort, bool kCheck, bool kL1>
 __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
                                                    float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
                                                    int n_blk, int est)
@@ -587,7 +581,7 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     __shared__ int32_t s_ring[4][2 * kRing];
     static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
     if ((int)blockIdx.x < n_blk) {
-        verify_l2_block<kShort, kCheck>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
+        verify_l2_block<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
                                 s_ring[threadIdx.x >> 6], est != 0);
         return;
     }
@@ -601,28 +595,33 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
     if (q >= a.nq) return;
     const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
     if (ns > kWaveSortCap) return;
-    verify_l2_wave<kShort, kCheck>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
+    verify_l2_wave<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
                            est != 0);
 }
 
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st)
+               bool est, bool check, hipStream_t st, bool l1)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
     const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
-#define VL(S, C)                                                                                              \
-    hipLaunchKernelGGL((k_verify_l2<S, C>), dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, blk_q, \
-                       n_blk, est ? 1 : 0)
+#define VL(S, C, M)                                                                                           \
+    hipLaunchKernelGGL((k_verify_l2<S, C, M>), dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, \
+                       blk_q, n_blk, est ? 1 : 0)
     const bool chk = check && est;
-    if (o.dp <= 128) {
-        if (chk) VL(true, true);
-        else VL(true, false);
+    if (l1) {
+        // Manhattan: no bf16 estimates, every candidate takes its float32 distance
+        require(!est, "verify_l2: the L1 metric has no bf16 selection");
+        if (o.dp <= 128) VL(true, false, true);
+        else VL(false, false, true);
+    } else if (o.dp <= 128) {
+        if (chk) VL(true, true, false);
+        else VL(true, false, false);
     } else {
-        if (chk) VL(false, true);
-        else VL(false, false);
+        if (chk) VL(false, true, false);
+        else VL(false, false, false);
     }
 #undef VL
     check_launch(__func__);

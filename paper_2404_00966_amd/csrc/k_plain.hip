@@ -87,6 +87,7 @@ __device__ __forceinline__ void emit_verified(const PlainArgs &a, int64_t q, uin
 // cut: the emission cutoff -- the radius for range queries; for kNN queries
 // the bound widened to cover any float32 summation order (the final top-k
 // is taken when the answers are sorted).
+template <bool L1>
 __device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, const float *qrow, float cut,
                                const int32_t *s_cand, int nc, long long *verified)
 {
@@ -98,22 +99,19 @@ __device__ void plain_flush_l2(const L2View &o, const PlainArgs &a, int64_t q, c
         if (c < nc) {
             p = s_cand[c];
             const float *x = o.X32 + (size_t)p * o.dp;
-            for (int d = sl; d < o.dp; d += 16) {
-                const float df = qrow[d] - x[d];
-                acc = fmaf(df, df, acc);
-            }
+            for (int d = sl; d < o.dp; d += 16) acc = dev::dterm<L1>(acc, qrow[d], x[d]);
         }
 #pragma unroll
         for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
         if (sl == 0 && c < nc) {
             (*verified)++;
-            const float d = sqrtf(acc);
+            const float d = dev::dfinish<L1>(acc);
             if (d <= cut) emit_verified(a, q, __float_as_uint(dev::out_dist(d, a.angular != 0)), a.ids[p]);
         }
     }
 }
 
-template <int MP>
+template <int MP, bool L1>
 __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, const float *__restrict__ P32,
                                                           int m, const float *__restrict__ PT,
                                                           const float *__restrict__ Q32, PlainArgs a)
@@ -132,14 +130,12 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
                 const float *p = P32 + (size_t)threadIdx.x * o.dp;
                 float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
                 for (int c = 0; c < o.dp; c += 4) {
-                    float d0 = qrow[c] - p[c], d1 = qrow[c + 1] - p[c + 1];
-                    float d2 = qrow[c + 2] - p[c + 2], d3 = qrow[c + 3] - p[c + 3];
-                    a0 = fmaf(d0, d0, a0);
-                    a1 = fmaf(d1, d1, a1);
-                    a2 = fmaf(d2, d2, a2);
-                    a3 = fmaf(d3, d3, a3);
+                    a0 = dev::dterm<L1>(a0, qrow[c], p[c]);
+                    a1 = dev::dterm<L1>(a1, qrow[c + 1], p[c + 1]);
+                    a2 = dev::dterm<L1>(a2, qrow[c + 2], p[c + 2]);
+                    a3 = dev::dterm<L1>(a3, qrow[c + 3], p[c + 3]);
                 }
-                acc = sqrtf((a0 + a1) + (a2 + a3));
+                acc = dev::dfinish<L1>((a0 + a1) + (a2 + a3));
             }
             s_qp[threadIdx.x] = acc;
         }
@@ -167,15 +163,12 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
                 float acc = 0.f;
                 if (e < nf) {
                     const float *pv = a.leaf_piv32 + (size_t)(node - t.leaf0) * o.dp;
-                    for (int dd = sl; dd < o.dp; dd += 16) {
-                        const float df = qrow[dd] - pv[dd];
-                        acc = fmaf(df, df, acc);
-                    }
+                    for (int dd = sl; dd < o.dp; dd += 16) acc = dev::dterm<L1>(acc, qrow[dd], pv[dd]);
                 }
 #pragma unroll
                 for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
                 bool pass = false;
-                if (e < nf) pass = sqrtf(acc) * (1.f - 2.f * a.delta) - a.leafR[node - t.leaf0] <= T;
+                if (e < nf) pass = dev::dfinish<L1>(acc) * (1.f - 2.f * a.delta) - a.leafR[node - t.leaf0] <= T;
                 block_push(sl == 0 && pass, node, other, &s_nf);
             }
             __syncthreads();
@@ -191,7 +184,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
                 __syncthreads();
                 const int nc = s_nc;
                 if (nc + kPlainBlock > kPlainCand) {
-                    plain_flush_l2(o, a, q, qrow, cut, s_cand, nc, &verified);
+                    plain_flush_l2<L1>(o, a, q, qrow, cut, s_cand, nc, &verified);
                     __syncthreads();
                     if (threadIdx.x == 0) s_nc = 0;
                     __syncthreads();
@@ -210,7 +203,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain_l2(TreeView t, L2View o, 
             }
         }
         __syncthreads();
-        plain_flush_l2(o, a, q, qrow, cut, s_cand, s_nc, &verified);
+        plain_flush_l2<L1>(o, a, q, qrow, cut, s_cand, s_nc, &verified);
         __syncthreads();
     }
     if (threadIdx.x % 16 == 0 && verified) count_add(a.counters, CNT_VERIFIED, (unsigned long long)verified);
@@ -222,11 +215,17 @@ void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const
               const PlainArgs &a, hipStream_t st)
 {
     if (a.nq == 0) return;
-#define PL(MP) \
-    hipLaunchKernelGGL(k_plain_l2<MP>, dim3((unsigned)a.grid), dim3(kPlainBlock), 0, st, t, o, P32, m, PT, Q32, a)
-    if (t.mpad == 8) PL(8);
-    else if (t.mpad == 16) PL(16);
-    else PL(32);
+#define PL(MP, L1) \
+    hipLaunchKernelGGL((k_plain_l2<MP, L1>), dim3((unsigned)a.grid), dim3(kPlainBlock), 0, st, t, o, P32, m, PT, Q32, a)
+    if (a.l1) {
+        if (t.mpad == 8) PL(8, true);
+        else if (t.mpad == 16) PL(16, true);
+        else PL(32, true);
+    } else {
+        if (t.mpad == 8) PL(8, false);
+        else if (t.mpad == 16) PL(16, false);
+        else PL(32, false);
+    }
 #undef PL
     check_launch(__func__);
 }

@@ -64,7 +64,8 @@ void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, in
 // then a 16-lane reduction.  Columns i in [m, mpad) get 0.
 __global__ __launch_bounds__(256) void k_dist_l2_pivots(const float *__restrict__ X, int64_t rows,
                                                         const float *__restrict__ P, int m, int mpad, int stride,
-                                                        float *__restrict__ out, int64_t s_piv, int64_t s_row)
+                                                        float *__restrict__ out, int64_t s_piv, int64_t s_row,
+                                                        int l1)
 {
     const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int sl = threadIdx.x & 15;
@@ -75,23 +76,23 @@ __global__ __launch_bounds__(256) void k_dist_l2_pivots(const float *__restrict_
     if (ok && i < m) {
         const float *x = X + (size_t)r * stride;
         const float *p = P + (size_t)i * stride;
-        for (int c = sl; c < stride; c += 16) {
-            const float df = x[c] - p[c];
-            acc = fmaf(df, df, acc);
-        }
+        if (l1)
+            for (int c = sl; c < stride; c += 16) acc = dev::dterm<true>(acc, x[c], p[c]);
+        else
+            for (int c = sl; c < stride; c += 16) acc = dev::dterm<false>(acc, x[c], p[c]);
     }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-    if (ok && sl == 0) out[(size_t)i * s_piv + (size_t)r * s_row] = i < m ? sqrtf(acc) : 0.f;
+    if (ok && sl == 0) out[(size_t)i * s_piv + (size_t)r * s_row] = i < m ? dev::dfinish_rt(l1 != 0, acc) : 0.f;
 }
 
 void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpad, int stride, float *out,
-                    int64_t s_piv, int64_t s_row, hipStream_t st)
+                    int64_t s_piv, int64_t s_row, hipStream_t st, bool l1)
 {
     if (rows == 0) return;
     const int64_t threads = rows * mpad * 16;
     hipLaunchKernelGGL(k_dist_l2_pivots, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, rows, P, m,
-                       mpad, stride, out, s_piv, s_row);
+                       mpad, stride, out, s_piv, s_row, l1 ? 1 : 0);
     check_launch(__func__);
 }
 
@@ -195,6 +196,24 @@ void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t n
     if (nq == 0) return;
     hipLaunchKernelGGL(k_thresholds, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, base, QP, kq, nq, mpad,
                        is_edit, delta, pt_max, T, thr, cut);
+    check_launch(__func__);
+}
+
+// *bad |= 1 when any of the first dim values of the rows is not finite.
+__global__ void k_check_finite(const float *__restrict__ X, int64_t rows, int dim, int stride, uint32_t *__restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * dim) return;
+    const int64_t r = i / dim;
+    const int c = (int)(i - r * dim);
+    if (!isfinite(X[(size_t)r * stride + c])) atomicOr(bad, 1u);
+}
+
+void check_finite(const float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st)
+{
+    const int64_t n = rows * dim;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, rows, dim, stride, bad);
     check_launch(__func__);
 }
 

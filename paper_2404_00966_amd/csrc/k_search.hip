@@ -172,7 +172,7 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
                                               int64_t nq, const uint32_t *__restrict__ tomb, int win,
                                               float *__restrict__ tq, int32_t *__restrict__ home,
                                               const int32_t *__restrict__ piv,
-                                              const int32_t *__restrict__ cell_leaf)
+                                              const int32_t *__restrict__ cell_leaf, int l1)
 {
     __shared__ float s_d[kWinMax];
     const int64_t q = blockIdx.x;
@@ -218,15 +218,24 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
                     const float4 *x = reinterpret_cast<const float4 *>(o.X32 + (size_t)p * o.dp);
                     const float4 *y = reinterpret_cast<const float4 *>(ql.Q32 + (size_t)q * o.dp);
                     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                    for (int c = 0; c < o.dp / 4; c++) {
-                        float4 u = x[c], v = y[c];
-                        float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
-                        a0 = fmaf(d0, d0, a0);
-                        a1 = fmaf(d1, d1, a1);
-                        a2 = fmaf(d2, d2, a2);
-                        a3 = fmaf(d3, d3, a3);
+                    if (l1) {
+                        for (int c = 0; c < o.dp / 4; c++) {
+                            const float4 u = x[c], v = y[c];
+                            a0 = dev::dterm<true>(a0, u.x, v.x);
+                            a1 = dev::dterm<true>(a1, u.y, v.y);
+                            a2 = dev::dterm<true>(a2, u.z, v.z);
+                            a3 = dev::dterm<true>(a3, u.w, v.w);
+                        }
+                    } else {
+                        for (int c = 0; c < o.dp / 4; c++) {
+                            const float4 u = x[c], v = y[c];
+                            a0 = dev::dterm<false>(a0, u.x, v.x);
+                            a1 = dev::dterm<false>(a1, u.y, v.y);
+                            a2 = dev::dterm<false>(a2, u.z, v.z);
+                            a3 = dev::dterm<false>(a3, u.w, v.w);
+                        }
                     }
-                    d = sqrtf((a0 + a1) + (a2 + a3));
+                    d = dev::dfinish_rt(l1 != 0, (a0 + a1) + (a2 + a3));
                 } else {
                     const int32_t s0 = oe.soff[p];
                     const int tl = oe.soff[p + 1] - s0;
@@ -244,14 +253,14 @@ __global__ __launch_bounds__(64) void k_bound(TreeView t, L2View o, QueryL2 ql, 
 }
 
 void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
-              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st)
+              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st, bool l1)
 {
     if (nq == 0) return;
     EditView oe{};
     QueryEdit qe{};
 #define BL(MP) \
     hipLaunchKernelGGL((k_bound<MP, false>), dim3((unsigned)nq), dim3(64), 0, st, t, o, qv, oe, qe, QP, kq, nq, tomb, win, tq, \
-                       home, nullptr, nullptr)
+                       home, nullptr, nullptr, l1 ? 1 : 0)
     if (t.mpad == 8) BL(8);
     else if (t.mpad == 16) BL(16);
     else BL(32);
@@ -268,7 +277,7 @@ void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const
     QueryL2 ql{};
 #define BE(MP) \
     hipLaunchKernelGGL((k_bound<MP, true>), dim3((unsigned)nq), dim3(64), 0, st, t, ol, ql, o, qv, QP, kq, nq, tomb, win, tq, \
-                       home, piv, cell_leaf)
+                       home, piv, cell_leaf, 0)
     if (t.mpad == 8) BE(8);
     else if (t.mpad == 16) BE(16);
     else BE(32);
@@ -807,106 +816,95 @@ __device__ __forceinline__ bool slot_visible(const uint32_t *cins, const uint32_
     return cins[s] <= e && cdel[s] > e;
 }
 
-// Lemma 1 against a cache slot with its global pivot distances cp (kept
-// since its insertion): the slot is beyond t from a query with pivot
-// distances qp when |qp_i - cp_i| exceeds t for some pivot.  L2 compares
-// float32 distances, each within a relative delta of the true one, so the
-// test keeps a margin of 2 delta (qp_i + cp_i + t); edit distances are exact.
-__device__ __forceinline__ bool slot_far(const float *qp, const float *cp, int i, float t, float delta)
-{
-    const float a = qp[i], c = cp[i];
-    return fabsf(a - c) > t + 2.f * delta * (a + c + t);
-}
-
-// L2: a workgroup stages a tile of ts slot rows in LDS (row stride dp + 16
-// floats, so the four 16-lane groups of a wave read different banks) and
-// runs a share of the call's queries against it, 16 lanes per (query, slot)
-// pair: first Lemma 1 on the global pivots (a pivot or two per lane), then
-// for the slots that remain the same strided float32 sum as every other
-// exact distance.  T[q]: the widened bound of the pivot test; cut[q]: the
-// emission cutoff (range radius, or for kNN the widened bound).
+// L2: the cache scan is a dense (query x slot) distance tile, 64 queries x
+// 64 slots per workgroup, each thread holding a 4 x 4 block of squared
+// distances in registers.  The coordinates stream through LDS 32 at a time,
+// stored dimension-major ([d][64 rows]) so that a thread reads its four
+// query values (shared by the 16 threads of its row group: one broadcast)
+// and its four slot values (consecutive across the 16 threads: no bank
+// conflict) as float4.  Each pair accumulates (q_d - x_d)^2 in coordinate
+// order (a float32 direct-difference sum, within (D + 1) 2^-24 relative of
+// the exact distance; for L1 the sum of |q_d - x_d| in the same order);
+// cut[q]: the emission cutoff (range radius, or for kNN the widened bound).
+constexpr int kCacheTile = 64;
+constexpr int kCacheChunk = 32;
+template <bool L1>
 __global__ __launch_bounds__(256) void k_cache_scan_l2(const float *__restrict__ Q32, int64_t nq, int dp,
-                                                       const float *__restrict__ C32, CacheScan cs, int ts,
-                                                       int staged, int64_t qchunks, const float *__restrict__ T,
-                                                       const float *__restrict__ cut, Cand *__restrict__ cands,
-                                                       CandCount *__restrict__ cand_count, int64_t cand_cap,
-                                                       int angular)
+                                                       const float *__restrict__ C32, CacheScan cs,
+                                                       int64_t qtiles, const float *__restrict__ cut,
+                                                       Cand *__restrict__ cands, CandCount *__restrict__ cand_count,
+                                                       int64_t cand_cap, int angular)
 {
-    extern __shared__ float s_rows[];
-    const int stride = dp + 16;
-    // blocks in tile-major order: a tile's query shares run side by side
-    const int64_t tile = blockIdx.x / qchunks, chunk = blockIdx.x - tile * qchunks;
-    const int64_t s0 = tile * ts;
-    const int ns = (int)min<int64_t>(ts, cs.count - s0);
-    if (staged) {
-        for (int i = threadIdx.x; i < ns * dp; i += blockDim.x) {
-            const int j = i / dp, c = i - j * dp;
-            s_rows[j * stride + c] = C32[(size_t)(s0 + j) * dp + c];
+    __shared__ float4 s_q[kCacheChunk][kCacheTile / 4];
+    __shared__ float4 s_x[kCacheChunk][kCacheTile / 4];
+    const int64_t st = blockIdx.x / qtiles, qt = blockIdx.x - st * qtiles;
+    const int64_t s0 = st * kCacheTile, q0 = qt * kCacheTile;
+    const int ns = (int)min<int64_t>(kCacheTile, cs.count - s0), nqt = (int)min<int64_t>(kCacheTile, nq - q0);
+    const int tq = threadIdx.x >> 4, tx = threadIdx.x & 15;   // rows 4 tq.., 4 tx..
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = 0.f;
+    float *sq = reinterpret_cast<float *>(s_q), *sx = reinterpret_cast<float *>(s_x);
+    for (int d0 = 0; d0 < dp; d0 += kCacheChunk) {
+        // 64 rows x 32 coordinates of each side, transposed into LDS
+        for (int e = threadIdx.x; e < kCacheTile * kCacheChunk; e += blockDim.x) {
+            const int r = e / kCacheChunk, c = e - r * kCacheChunk, d = d0 + c;
+            sq[c * kCacheTile + r] = r < nqt && d < dp ? Q32[(size_t)(q0 + r) * dp + d] : 0.f;
+            sx[c * kCacheTile + r] = r < ns && d < dp ? C32[(size_t)(s0 + r) * dp + d] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < kCacheChunk; c++) {
+            const float4 qv = s_q[c][tq], xv = s_x[c][tx];
+            const float qa[4] = {qv.x, qv.y, qv.z, qv.w}, xa[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = dev::dterm<L1>(acc[i][j], qa[i], xa[j]);
         }
         __syncthreads();
     }
-    const int sl = threadIdx.x & 15, g = threadIdx.x >> 4, gw = g & 3;
-    const int64_t qper = (nq + qchunks - 1) / qchunks;
-    const int64_t q0 = chunk * qper, q1 = min<int64_t>(nq, q0 + qper);
-    for (int64_t q = q0; q < q1; q++) {
-        const float *x = Q32 + (size_t)q * dp;
-        const uint32_t e = cs.qep ? cs.qep[q] : cs.e_now;
-        const float cq = cut[q], tq = T[q];
-        const float *qp = cs.QP + (size_t)q * cs.mpad;
-        // the same trip count in every lane: the group ballots and shuffles
-        // below run with the whole wave active
-        for (int j0 = 0; j0 < ns; j0 += 16) {
-            const int j = j0 + g;
-            bool vis = j < ns && slot_visible(cs.ins_ep, cs.del_ep, s0 + j, e);
-            bool far = false;
-            if (vis && cs.cp)
-                for (int i = sl; i < cs.m; i += 16) far = far || slot_far(qp, cs.cp + (size_t)(s0 + j) * cs.mpad, i, tq, cs.delta);
-            far = ((dev::ballot(far) >> (16 * gw)) & 0xffffull) != 0ull;
-            vis = vis && !far;
-            float acc = 0.f;
-            if (vis) {
-                const float *y = staged ? s_rows + j * stride : C32 + (size_t)(s0 + j) * dp;
-                for (int i = sl; i < dp; i += 16) {
-                    const float d = x[i] - y[i];
-                    acc = fmaf(d, d, acc);
-                }
-            }
 #pragma unroll
-            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-            if (sl == 0 && vis) {
-                const float d = sqrtf(acc);
-                if (d <= cq) {
-                    const CandCount idx = atomicAdd(cand_count, (CandCount)1);
-                    if ((int64_t)idx < cand_cap) {
-                        Cand cd;
-                        cd.q = (int32_t)q;
-                        cd.pos = -1;
-                        cd.val = ((uint64_t)__float_as_uint(dev::out_dist(d, angular != 0)) << 32) | cs.ids[s0 + j];
-                        cands[idx] = cd;
-                    }
+    for (int i = 0; i < 4; i++) {
+        const int qi = 4 * tq + i;
+        if (qi >= nqt) continue;
+        const int64_t q = q0 + qi;
+        const uint32_t e = cs.qep ? cs.qep[q] : cs.e_now;
+        const float cq = cut[q];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int sj = 4 * tx + j;
+            if (sj >= ns) continue;
+            const int64_t s = s0 + sj;
+            const float d = dev::dfinish<L1>(acc[i][j]);
+            if (d <= cq && slot_visible(cs.ins_ep, cs.del_ep, s, e)) {
+                const CandCount idx = atomicAdd(cand_count, (CandCount)1);
+                if ((int64_t)idx < cand_cap) {
+                    Cand cd;
+                    cd.q = (int32_t)q;
+                    cd.pos = -1;
+                    cd.val = ((uint64_t)__float_as_uint(dev::out_dist(d, angular != 0)) << 32) | cs.ids[s];
+                    cands[idx] = cd;
                 }
             }
         }
     }
 }
 
-void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *T,
-                   const float *cut, Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st)
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *cut,
+                   Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st, bool l1)
 {
     if (nq == 0 || cs.count == 0) return;
-    // rows wider than 48 KB of LDS (12,272 floats) are read through the cache
-    const int64_t stride = dp + 16;
-    const int64_t fit = ((int64_t)48 << 10) / (stride * (int64_t)sizeof(float));
-    const bool staged = fit >= 1;
-    const int ts = staged ? (int)std::min<int64_t>(64, fit) : 64;
-    const int64_t tiles = (cs.count + ts - 1) / ts;
-    // each tile's rows are staged once per query share: one share when the
-    // tiles alone fill the chip, more (of at least 16 queries) when they do not
-    const int64_t qchunks = std::max<int64_t>(1, std::min<int64_t>((nq + 15) / 16, 2048 / std::max<int64_t>(tiles, 1)));
-    require(tiles * qchunks < ((int64_t)1 << 31), "cache_scan_l2: launch too large");
-    hipLaunchKernelGGL(k_cache_scan_l2, dim3((unsigned)(tiles * qchunks)), dim3(256),
-                       staged ? (size_t)ts * stride * sizeof(float) : 0, st, Q32, nq, dp, C32, cs, ts, staged ? 1 : 0,
-                       qchunks, T, cut, cands, cand_count, cand_cap, angular ? 1 : 0);
+    const int64_t stiles = (cs.count + kCacheTile - 1) / kCacheTile, qtiles = (nq + kCacheTile - 1) / kCacheTile;
+    require(stiles * qtiles < ((int64_t)1 << 31), "cache_scan_l2: launch too large");
+    if (l1)
+        hipLaunchKernelGGL(k_cache_scan_l2<true>, dim3((unsigned)(stiles * qtiles)), dim3(256), 0, st, Q32, nq, dp,
+                           C32, cs, qtiles, cut, cands, cand_count, cand_cap, 0);
+    else
+        hipLaunchKernelGGL(k_cache_scan_l2<false>, dim3((unsigned)(stiles * qtiles)), dim3(256), 0, st, Q32, nq, dp,
+                           C32, cs, qtiles, cut, cands, cand_count, cand_cap, angular ? 1 : 0);
     check_launch(__func__);
 }
 

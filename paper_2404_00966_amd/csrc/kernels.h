@@ -60,8 +60,9 @@ using CandCount = unsigned long long;
 // ---- preparation (k_prep.hip) ---------------------------------------------
 void rows_bf16(const float *X, int64_t rows_valid, int64_t rows_pad, int dim, int stride, int ksteps,
                uint16_t *frag, float *norm2, float *err, float pad_norm2, hipStream_t st);
+// l1: Manhattan distances instead of Euclidean (the same summation order).
 void dist_l2_pivots(const float *X, int64_t rows, const float *P, int m, int mpad, int stride, float *out,
-                    int64_t s_piv, int64_t s_row, hipStream_t st);
+                    int64_t s_piv, int64_t s_row, hipStream_t st, bool l1 = false);
 void dist_edit_pivots_f32(const uint8_t *chars, const int64_t *off, int64_t rows, const uint8_t *pchars,
                           const int32_t *poff, int m, int mpad, float *out, int64_t s_piv, int64_t s_row,
                           const uint8_t *lut, int arows, hipStream_t st);
@@ -78,6 +79,8 @@ void tomb_bits(const uint32_t *del_ep, int64_t n, uint32_t e, uint32_t *bits, in
 // (query, object) pairs a tile's surviving leaves hold); out zeroed first.
 void tile_pairs(const uint64_t *mask, int64_t n_leaves, int ntiles, const int32_t *leaf_cnt, unsigned long long *out,
                 hipStream_t st);
+// *bad |= 1 when a value among the first dim of each row is not finite.
+void check_finite(const float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
 // Rows scaled to unit length in place (norm in double, result rounded to
 // float); a row with zero or non-finite norm becomes zero and sets *bad.
 void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
@@ -129,7 +132,7 @@ struct QueryEdit {
 };
 
 void bound_l2(const TreeView &t, const L2View &o, const QueryL2 &qv, const float *QP, const int32_t *kq,
-              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st);
+              int64_t nq, const uint32_t *tomb, int win, float *tq, int32_t *home, hipStream_t st, bool l1 = false);
 // piv/cell_leaf (may be null): a query with a pivot centre h takes its window
 // from the first object of cell h instead of its home leaf.
 void bound_edit(const TreeView &t, const EditView &o, const QueryEdit &qv, const float *QP, const int32_t *kq,
@@ -181,8 +184,9 @@ void l2_objfilter(const TreeView &t, const int32_t *items, const uint32_t *item_
 // Brute-force scans of the cache list; they emit verified entries with
 // d <= cut (L2) or d <= floor(base) (edit distance).  Slot s is seen by a
 // query of epoch e iff ins_ep[s] <= e < del_ep[s]; e = qep[q], or e_now for
-// every query when qep is null.  With cp set, Lemma 1 on the global pivots
-// (cp: the slots' pivot distances, QP: the queries') skips slots first.
+// every query when qep is null.  Edit distance: with cp set, Lemma 1 on the
+// global pivots (cp: the slots' pivot distances, QP: the queries') skips
+// slots before their distance.
 struct CacheScan {
     const uint32_t *ids, *ins_ep, *del_ep;   // [count]
     const float *cp;                          // [count][mpad] (null: no pivot test)
@@ -191,10 +195,10 @@ struct CacheScan {
     const uint32_t *qep;                      // [nq] admission epochs (null: e_now)
     uint32_t e_now;
     const float *QP;                          // [nq][mpad]
-    float delta;                              // L2: relative float32 error of a distance
 };
-void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *T,
-                   const float *cut, Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st);
+void cache_scan_l2(const float *Q32, int64_t nq, int dp, const float *C32, const CacheScan &cs, const float *cut,
+                   Cand *cands, CandCount *cand_count, int64_t cand_cap, bool angular, hipStream_t st,
+                   bool l1 = false);
 void cache_scan_edit(const QueryEdit &qv, const EditView &o, int64_t nq, const uint8_t *cchars, int cstride,
                      const int32_t *clen, const CacheScan &cs, const float *base, Cand *cands, CandCount *cand_count,
                      int64_t cand_cap, hipStream_t st);
@@ -206,7 +210,7 @@ void leaf_radius_edit(const EditView &o, const int32_t *leaf_first, const int32_
 // centre j, mind[o] the (squared, for L2) distance of object o to its nearest
 // centre and near[o] that centre's number.
 void fft_centers_l2(const float *X, int64_t n, int dp, int K, uint64_t *keys, int32_t *centers, float *mind,
-                    int32_t *near, hipStream_t st);
+                    int32_t *near, hipStream_t st, bool l1 = false);
 void fft_centers_edit(const uint8_t *chars, const int64_t *off, int64_t n, const uint8_t *lut, int arows, int K,
                       uint64_t *keys, int32_t *centers, float *mind, int32_t *near, hipStream_t st);
 // ---- device steps of the L2 build (k_build.hip) ----
@@ -216,7 +220,10 @@ void gather_rows(const float *src, int dp, const int32_t *perm, int64_t n, float
 void gather_pt(const float *src, const int32_t *perm, int64_t n, int m, int mpad, float *dst, hipStream_t st);
 // out[o] = squared float32 distance of row o to centre row C[cell[o * stride]].
 void centre_dist(const float *X, int dp, int64_t n, const int32_t *cell, int stride, const float *C, float *out,
-                 hipStream_t st);
+                 hipStream_t st, bool l1 = false);
+// near[o] = number of the nearest of the K centre rows C [K][dp] (exact
+// float32 distances, first of equals; l1: Manhattan).
+void nearest_centre(const float *X, int dp, int64_t n, const float *C, int K, bool l1, int32_t *near, hipStream_t st);
 // Leaf order: perm sorted by (rank[cell[o * stride]], cdist[o], o); key
 // returns each position's cell rank.  tmp holds sort_pairs_bytes(n).
 void cell_order(const float *cdist, const int32_t *cell, int stride, const int32_t *rank, int n_cells, int64_t n,
@@ -234,7 +241,8 @@ void slab_summary(const float *xn, const float *xe, int64_t n, const int32_t *le
 // and the largest distance from it (leafR, widened); cen: [n_leaves][dim]
 // doubles of scratch.  Empty leaves and j >= n_leaves: zero row, R = -inf.
 void leaf_pivots(const float *X32, int dp, int dim, const int32_t *leaf_first, const int32_t *leaf_cnt,
-                 int64_t n_leaves, int64_t lpad, double *cen, float *PL32, float *leafR, hipStream_t st);
+                 int64_t n_leaves, int64_t lpad, double *cen, float *PL32, float *leafR, hipStream_t st,
+                 bool l1 = false);
 // pln[j] = +inf for j >= n_leaves and empty leaves.
 void mark_empty(const int32_t *leaf_cnt, int64_t n_leaves, int64_t lpad, float *pln, hipStream_t st);
 // *out = max(*out, max x) over non-negative floats, as float bits.
@@ -322,6 +330,7 @@ struct VerifyArgs {
     uint32_t *out_count;       // [nq]
     unsigned long long *counters;
     int angular;               // L2 on unit vectors: keys carry the angle 2 asin(d/2)
+    int l1;                    // vectors under the Manhattan (L1) metric
 };
 // blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
 // est: the tree-position candidates carry bf16 estimates of d^2 (the bf16
@@ -330,7 +339,7 @@ struct VerifyArgs {
 // check: count rechecked candidates whose float32 distance leaves their
 // bf16 interval (CNT_BOUND_VIOL).
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st);
+               bool est, bool check, hipStream_t st, bool l1 = false);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
@@ -400,6 +409,7 @@ struct PlainArgs {
     const float *leaf_piv32;   // [n_leaves][dp] leaf pivot vectors (L2; null: no leaf test)
     const float *leafR;        // [n_leaves] largest pivot distance in the leaf
     int angular;               // L2 on unit vectors: keys carry the angle 2 asin(d/2)
+    int l1;                    // vectors under the Manhattan (L1) metric
 };
 void plain_l2(const TreeView &t, const L2View &o, const float *P32, int m, const float *PT, const float *Q32,
               const PlainArgs &a, hipStream_t st);

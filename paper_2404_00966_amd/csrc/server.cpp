@@ -91,10 +91,21 @@ bool is_update(const Request &r)
 
 // An update that moves or rewrites memory a running batch reads waits for
 // the index's batches to finish: an insertion that grows the cache arrays,
-// one that triggers the rebuild, or one that adds bytes to an edit index's
-// alphabet (the match tables of running batches use the old codes).
+// an insertion or deletion that triggers a rebuild, or an insertion that adds
+// bytes to an edit index's alphabet (the match tables of running batches use
+// the old codes).
 bool update_needs_drain(const gts_index *idx, const Request &r)
 {
+    if (r.req.kind == GTS_REQ_DELETE) {
+        // a delete that leaves the tree mostly deleted rebuilds it (counted
+        // generously: a repeated id counts twice)
+        int64_t more = 0;
+        for (int64_t id : r.ids)
+            if (id >= 0 && id < (int64_t)idx->pos_of_id.size() && idx->pos_of_id[id] >= 0 &&
+                !idx->h_tomb[idx->pos_of_id[id]])
+                more++;
+        return tree_mostly_deleted(idx, more);
+    }
     if (r.req.kind != GTS_REQ_INSERT) return false;
     const int64_t n = r.objs.count();
     const CacheList &c = idx->cache;
@@ -273,7 +284,7 @@ void run_batch(gts_server *s, IndexQueue &q, Lane &lane)
             c->pub.result.nq = n;
             c->pub.result.total = b - a;
             c->pub.result.location = GTS_HOST;
-            c->pub.result.metric = d.metric;
+            c->pub.result.metric = q.idx->angular ? GTS_COSINE_F32 : q.idx->l1 ? GTS_L1_F32 : d.metric;
         }
         c->pub.t_done_ms = t1;
         publish(c);

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgts.so")
 
-L2_F32, EDIT_U8, COSINE_F32 = 1, 2, 3
+L2_F32, EDIT_U8, COSINE_F32, L1_F32 = 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 MODE_BATCHED, MODE_PLAIN = 0, 1
 QF_CHECK_BOUND, QF_NO_PRUNE = 1, 2
@@ -70,7 +70,7 @@ class _Info(C.Structure):
                 ("levels", C.c_int32), ("max_strlen", C.c_int32), ("n_indexed", C.c_int64),
                 ("n_live", C.c_int64), ("n_cache", C.c_int64), ("n_nodes", C.c_int64),
                 ("n_leaves", C.c_int64), ("n_slabs", C.c_int64), ("rebuilds", C.c_int64),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("rebuild_ms", C.c_double), ("epoch", C.c_int64)]
 
 
 REQ_RANGE, REQ_KNN, REQ_INSERT, REQ_DELETE = 1, 2, 3, 4

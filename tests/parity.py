@@ -8,6 +8,8 @@ Tolerances:
     may differ only by objects whose float64 distance lies within 1e-5 * r of
     the radius (range) or within 1e-5 * d_k of the oracle's k-th distance
     (kNN).  Answers are in (distance, id) order.
+  * L1 (Manhattan): as L2 with the relative tolerance max(1e-5, (D + 2) 2^-24)
+    (L1_TOL_FOR(D)).
   * angular (cosine): the same with the tolerance ANGULAR_TOL(theta) =
     (1e-5 * theta + 1e-6) / cos(theta / 2): the library measures the float32
     chord d between unit vectors rounded to float (each within one rounding,
@@ -24,6 +26,15 @@ REL = 1e-5
 
 def L2_TOL(d):
     return REL * d
+
+
+def L1_TOL_FOR(dim):
+    """Manhattan: every |x_i - y_i| is within one float32 rounding and any
+    float32 summation order of D terms adds at most (D - 1) 2^-24 of the sum
+    (the cache-list tile sums in coordinate order); for D beyond about 160
+    that exceeds the L2 tolerance, so the tolerance is the larger of the two."""
+    rel = max(REL, (dim + 2) * 2.0 ** -24)
+    return lambda d: rel * d
 
 
 def ANGULAR_TOL(t):
