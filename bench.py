@@ -827,7 +827,7 @@ def main():
     ap.add_argument("--serve-warmup-s", type=float, default=1.0)
     ap.add_argument("--serve-update-max", type=int, default=1000)
     ap.add_argument("--serve-lanes", type=int, default=2)
-    ap.add_argument("--serve-cache", type=int, default=1 << 20, help="cache list limit of the serving indexes")
+    ap.add_argument("--serve-cache", type=int, default=131072, help="cache list limit of the serving indexes")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(args.pmc_summary, args.pmc_workload, args.pmc_last, args.pmc_command))

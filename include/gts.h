@@ -319,6 +319,49 @@ gts_status gts_set_timing(gts_index *idx, int32_t enable);
 /* Message of the last failure on this thread ("" if none). */
 const char *gts_last_error(void);
 
+/* ---- Search plans: a fixed-shape batch replayed as one HIP graph ----------
+ * Batched processing (Sec. 5.1) of a query stream of a fixed shape: every
+ * launch runs nq queries of a vector index (L2, L1 or angular) through the
+ * whole batched pipeline -- pivot distances, home order, kNN bound, node and
+ * object filters, candidate grouping, verification, answer assembly -- as
+ * one hipGraph with fixed-capacity intermediate buffers and device-side
+ * counts: no host synchronisation, allocation or host read inside a launch.
+ *
+ * gts_plan_create records the graph; the plan allocates its own
+ * intermediate space (mem_budget_bytes from opts, or 1 GiB) and takes the
+ * caller's device buffers in io, whose addresses the graph holds: they are
+ * the caller's, and must stay allocated, at the same addresses, until the
+ * plan is destroyed.  The caller writes queries [nq][dim] float32 (row-major),
+ * radius [nq] (used where k == 0) and k [nq] (0: range query) before a
+ * launch, and reads after it (in stream order): offsets [nq + 1] (CSR;
+ * offsets[nq] is the number of answers, also when it exceeds the capacity),
+ * ids and float distances [answer_capacity] (may be NULL when the capacity is
+ * 0), and status (0: the launch's answers are complete; otherwise a sum of
+ * GTS_PLAN_* flags, and the answers are not to be used).  gts_plan_launch
+ * enqueues the graph on `hip_stream` (the index's own stream when NULL);
+ * after an update or rebuild of the index it records the graph again first
+ * (which waits for the device).  A plan is not re-entrant: launches of one
+ * plan must not overlap, and the index must not be searched or updated while
+ * one runs.  Edit-distance indexes: GTS_ENOTSUP. */
+#define GTS_PLAN_BAD_INPUT 1       /* a negative k, or a negative or NaN radius */
+#define GTS_PLAN_BAD_QUERY 2       /* a non-finite query value, or (angular) a zero query vector */
+#define GTS_PLAN_CANDIDATES 4      /* the candidates exceed the plan's intermediate space */
+#define GTS_PLAN_ANSWERS 8         /* the answers exceed answer_capacity */
+typedef struct gts_plan gts_plan;
+typedef struct gts_plan_io {
+    const float *queries;          /* device, [nq][dim] */
+    const float *radius;           /* device, [nq] */
+    const int32_t *k;              /* device, [nq] */
+    int64_t *offsets;              /* device, [nq + 1] */
+    int64_t *ids;                  /* device, [answer_capacity] */
+    float *dist;                   /* device, [answer_capacity] */
+    int32_t *status;               /* device, [1] */
+} gts_plan_io;
+gts_status gts_plan_create(gts_index *idx, int64_t nq, int64_t answer_capacity, const gts_query_opts *opts,
+                           const gts_plan_io *io, gts_plan **out);
+gts_status gts_plan_launch(gts_plan *plan, void *hip_stream);
+gts_status gts_plan_destroy(gts_plan *plan);
+
 /* ---- No-allocation search --------------------------------------------------
  * For callers that cannot allocate memory during a query: code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation.

@@ -54,7 +54,7 @@ constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
 constexpr int kSortCap = 2048;      // edit distance: per-query keys sorted in LDS (more: global scratch)
 constexpr int kSortCapL2 = 4096;    // L2: per-query keys sorted in LDS (more: global scratch)
 constexpr int kWaveSortCap = 1024;  // L2: per-query keys verified and sorted by one wave
-constexpr int kWorkspaceSlots = 72;   // named query buffers of an index
+constexpr int kWorkspaceSlots = 80;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 
 // Device buffer owned by the index (hipMalloc / hipFree), or a view of
@@ -344,6 +344,12 @@ struct QueryCtx {
     hipStream_t stream = nullptr;
     Arena *arena = nullptr;            // set: every workspace buffer is carved from it
     SnapView view;                     // on: the search follows these epochs (server batches)
+    // graph mode (search plans, being recorded into a hipGraph): device
+    // radius / k arrays, no host reads or synchronisation, fixed-capacity
+    // buffers from the arena, device-side verification plan; failures are
+    // flags in the device word gstatus
+    bool graph = false;
+    uint32_t *gstatus = nullptr;
     DevBuf ws[kWorkspaceSlots];        // grown on demand, reused across calls
     void *pin = nullptr;               // pinned host staging for small device-to-host reads
     size_t pin_bytes = 0;

@@ -89,7 +89,9 @@ void rows_to_device(float *dst, int dp, const float *src, int dim, int64_t n, bo
 {
     if (n == 0) return;
     if (src_on_device) {
-        if (dp != dim) GTS_HIP(hipMemsetAsync(dst, 0, (size_t)n * dp * sizeof(float), st));
+        // (a fill kernel rather than a memset: this copy may be recorded
+        // into a graph)
+        if (dp != dim) k::fill_u32(reinterpret_cast<uint32_t *>(dst), (int64_t)n * dp, 0u, st);
         GTS_HIP(hipMemcpy2DAsync(dst, dp * sizeof(float), src, dim * sizeof(float), dim * sizeof(float), n,
                                  hipMemcpyDeviceToDevice, st));
     } else if (dp == dim) {

@@ -37,7 +37,7 @@ enum Ws {
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
     W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV, W_POSOF, W_HOMEC, W_PLEN, W_POFF, W_PCHARS,
-    W_BADQ, W_QEP, W_PQEP, W_TMIN, W_TMAX, W_TILEW, W_COUNT
+    W_BADQ, W_QEP, W_PQEP, W_TMIN, W_TMAX, W_TILEW, W_VNEED, W_VFLAG, W_VNOFF, W_VFOFF, W_NBLK, W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
 
@@ -278,6 +278,7 @@ struct Batch {
     int sweep_grid_per_cu = 2;          // MFMA sweep workgroups per CU (tuned)
     bool check_bound = false;           // count bf16 interval violations
     bool no_prune = false;              // L2 control: every (leaf, query) pair kept
+    bool check_q = false;               // the query rows were checked on the device (flag in W_BADQ)
     // what the batch sees (server batches: see SnapView)
     const uint32_t *tomb_prod = nullptr;    // tombstones of the candidate producers
     const uint32_t *tomb_bound = nullptr;   // tombstones of the kNN bounds
@@ -450,15 +451,39 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     k::Cand *grouped = wsp<k::Cand>(cx, W_GROUPED, gcap);
     k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, gcap, del_ep, qep, st);
     rec(cx, 5);
+    if (cx->graph) {
+        // no host reads: fixed capacities, the verification plan made on the
+        // device, the candidate overflow a status flag
+        GTS_CHECK(l2 && !plain, GTS_ENOTSUP, "search plans run the batched vector form");
+        k::plan_status(cx->gstatus, nullptr, ccount, cap, nullptr, 0, st);
+        int64_t *big_off = wsp<int64_t>(cx, W_BIGOFF, ng + 1);
+        uint64_t *scratch = wsp<uint64_t>(cx, W_SCRATCH, 2 * cap);
+        int32_t *dblk = wsp<int32_t>(cx, W_BLKQ, ng + 1);
+        int32_t *nblk = wsp<int32_t>(cx, W_NBLK, 1);
+        k::verify_plan(qoff, ng, kSortCapL2, kWaveSortCap, wsp<uint32_t>(cx, W_VNEED, ng + 1),
+                       wsp<uint32_t>(cx, W_VFLAG, ng + 1), wsp<int64_t>(cx, W_VNOFF, ng + 1),
+                       wsp<int64_t>(cx, W_VFOFF, ng + 1), big_off, dblk, nblk, st);
+        uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(cap, 1));
+        uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
+        k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count,
+                         counters, idx->angular ? 1 : 0};
+        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, 0, !sel32, b.check_bound, st, idx->l1,
+                     nblk);
+        go->direct = direct;
+        go->total = -1;
+        return true;
+    }
     uint32_t *h_small = reinterpret_cast<uint32_t *>(pin + pl.small);
     int64_t *h_qoff_pin = reinterpret_cast<int64_t *>(pin + pl.qoff);
     GTS_HIP(hipMemcpyAsync(h_small, small, kSmallWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     uint32_t *h_bad = h_small + 32;   // (the small-counter region of the staging holds 64 words)
     *h_bad = 0;
-    if (idx->angular && l2) GTS_HIP(hipMemcpyAsync(h_bad, cx->ws[W_BADQ].p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    if (b.check_q) GTS_HIP(hipMemcpyAsync(h_bad, cx->ws[W_BADQ].p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     GTS_HIP(hipStreamSynchronize(st));
-    GTS_CHECK(*h_bad == 0, GTS_EINVAL, "a query vector is zero or non-finite: it has no direction (angular metric)");
+    GTS_CHECK(*h_bad == 0, GTS_EINVAL,
+              idx->angular ? "a query vector is zero or non-finite: it has no direction (angular metric)"
+                           : "non-finite query value");
     const uint64_t ncand_all = *reinterpret_cast<const uint64_t *>(h_small);
     if (ncand_all > (uint64_t)cap) {
         // too many candidates for the budget: report the attempt and each
@@ -678,8 +703,8 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;
-    if (d.metric == GTS_L2_F32 && !idx->l1 && b.mode == GTS_MODE_BATCHED && b.precision == GTS_BF16_GUARDED &&
-        d.lpad > 0 &&
+    if (d.metric == GTS_L2_F32 && !idx->l1 && !cx->graph && b.mode == GTS_MODE_BATCHED &&
+        b.precision == GTS_BF16_GUARDED && d.lpad > 0 &&
         d.dim <= kMaxMfmaDim && b.nq > 0) {
         bool knn = false;
         for (int64_t q = 0; q < b.nq && !knn; q++) knn = kin && kin[q] > 0;
@@ -701,10 +726,18 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
                          ? opts->result_location
                          : Q->location;
     const int64_t nq = b.nq;
-    // per-query kind, radius, k
-    std::vector<int32_t> hk(nq, 0);
-    std::vector<float> hbase(nq, 0.f);
-    for (int64_t q = 0; q < nq; q++) {
+    // per-query kind, radius, k (a graph-mode search reads them on the device)
+    const bool gmode = cx->graph;
+    std::vector<int32_t> hk(gmode ? 0 : nq, 0);
+    std::vector<float> hbase(gmode ? 0 : nq, 0.f);
+    if (gmode) {
+        GTS_CHECK(na != nullptr && cx->arena != nullptr && cx->gstatus != nullptr, GTS_EINVAL,
+                  "graph-mode search without its fixed buffers");
+        GTS_CHECK(d.metric == GTS_L2_F32, GTS_ENOTSUP, "search plans take vector indexes");
+        GTS_CHECK(radius != nullptr && kin != nullptr, GTS_EINVAL, "graph-mode search needs radius and k arrays");
+        b.any_knn = true;   // (unknown on the host: the kNN stages run, k = 0 queries skip them)
+    }
+    for (int64_t q = 0; q < (gmode ? 0 : nq); q++) {
         const int kk = kin ? kin[q] : 0;
         if (kin && kk < 0) fail(GTS_EINVAL, "k must be >= 1");
         if (kk > 0) {
@@ -721,11 +754,11 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     }
     if (na) {
         GTS_CHECK(cx->arena != nullptr, GTS_EINVAL, "no-allocation search without its arena");
-        GTS_CHECK(nq <= kNoAllocMaxQueries, GTS_EINVAL,
+        GTS_CHECK(gmode || nq <= kNoAllocMaxQueries, GTS_EINVAL,
                   "the no-allocation search takes at most " + std::to_string(kNoAllocMaxQueries) + " queries");
         GTS_CHECK(nq == 0 || Q->location == GTS_DEVICE, GTS_EINVAL, "the no-allocation search takes device queries");
         GTS_CHECK(b.mode == GTS_MODE_BATCHED, GTS_EINVAL, "the no-allocation search runs the batched form");
-        GTS_CHECK(na->offsets != nullptr && na->total != nullptr && na->capacity >= 0, GTS_EINVAL,
+        GTS_CHECK(na->offsets != nullptr && (gmode || na->total != nullptr) && na->capacity >= 0, GTS_EINVAL,
                   "no-allocation output buffers");
         GTS_CHECK(na->capacity == 0 || (na->ids != nullptr && na->dist != nullptr), GTS_EINVAL,
                   "no-allocation output buffers");
@@ -759,7 +792,9 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     int32_t *home = wsp<int32_t>(cx, W_HOME, nqpad);
     unsigned long long *counters = wsp<unsigned long long>(cx, W_COUNTERS, k::kCounterWords);
     k::fill_u32(reinterpret_cast<uint32_t *>(counters), 2 * k::kCounterWords, 0u, st);
-    if (nq > 0) {
+    if (nq > 0 && gmode) {
+        k::query_params(radius, kin, nq, idx->angular, base, kq, cx->gstatus, st);
+    } else if (nq > 0) {
         GTS_HIP(hipMemcpyAsync(base, hbase.data(), nq * sizeof(float), hipMemcpyHostToDevice, st));
         GTS_HIP(hipMemcpyAsync(kq, hk.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
@@ -774,12 +809,17 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             for (int64_t i = 0; i < nq * d.dim; i++)
                 GTS_CHECK(std::isfinite(Q->vecs[i]), GTS_EINVAL, "non-finite query value");
         float *Q32 = wsp<float>(cx, W_Q32, (size_t)nqpad * d.dp);
-        GTS_HIP(hipMemsetAsync(Q32, 0, (size_t)nqpad * d.dp * sizeof(float), st));
+        k::fill_u32(reinterpret_cast<uint32_t *>(Q32), (int64_t)nqpad * d.dp, 0u, st);
         rows_to_device(Q32, d.dp, Q->vecs, d.dim, nq, Q->location == GTS_DEVICE, st);
-        if (idx->angular) {
+        if (idx->angular || Q->location == GTS_DEVICE) {
+            // device queries are checked on the device (a non-finite value
+            // is flagged and replaced by zero, so that no later kernel sees
+            // it); the flag is read with the first candidate counts
             uint32_t *bad = wsp<uint32_t>(cx, W_BADQ, 1);
             k::fill_u32(bad, 1, 0u, st);
-            k::normalize_rows(Q32, nq, d.dim, d.dp, bad, st);
+            if (Q->location == GTS_DEVICE) k::check_finite(Q32, nq, d.dim, d.dp, bad, st);
+            if (idx->angular) k::normalize_rows(Q32, nq, d.dim, d.dp, bad, st);
+            b.check_q = true;
         }
         uint16_t *Q16 = wsp<uint16_t>(cx, W_Q16, (size_t)nqpad * d.ksteps * 32);
         float *qn = wsp<float>(cx, W_QN, nqpad);
@@ -1046,6 +1086,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         for (int i = 0; i < 4; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
         for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
         add((size_t)nq * sizeof(int32_t));
+        if (gmode) {   // the device-side verification plan
+            for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
+            for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
+        }
         const size_t left = cx->arena->left();
         GTS_CHECK(left >= reserve + (size_t)56 * 1024, GTS_ENOMEM,
                   "the no-allocation scratch cannot hold this batch's work lists; use a smaller batch");
@@ -1054,7 +1098,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     std::vector<GroupOut> groups;
     std::vector<std::pair<int64_t, int64_t>> todo;  // (q0, ng), processed front to back
     if (nq > 0) todo.push_back({0, nq});
-    if (permuted)   // the order was made on the device: its copy lands by the next sync
+    if (permuted && !gmode)   // the order was made on the device: its copy lands by the next sync
         GTS_HIP(hipMemcpyAsync(pin + pl.perm, cx->ws[W_PERM].p, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     while (!todo.empty()) {
         auto [q0, ng] = todo.front();
@@ -1108,6 +1152,21 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         // no-allocation search: caller-order counts, their scan straight into
         // the caller's offsets, a capacity check, then the keys in place
         int64_t *htot = reinterpret_cast<int64_t *>(pin + pl.offs);
+        if (gmode) {
+            // a recorded graph: counts, their scan into the caller's offsets
+            // (offsets[nq] = the answers), the keys written below the
+            // capacity, then the status word; nothing read on the host
+            uint32_t *cc = wsp<uint32_t>(cx, W_TMP2, nq);
+            const int32_t *dperm = permuted ? cx->ws[W_PERM].as<int32_t>() : nullptr;
+            k::perm_counts(cx->ws[W_OUTCNT].as<uint32_t>(), dperm, nq, cc, st);
+            k::scan_u32(cc, nq, na->offsets, st);
+            k::emit_result(cx->ws[W_OUTKEYS].as<uint64_t>(), cx->ws[W_QOFF64].as<int64_t>(),
+                           cx->ws[W_OUTCNT].as<uint32_t>(), dperm, na->offsets, nq, 0, na->ids,
+                           static_cast<float *>(na->dist), nullptr, st, na->capacity);
+            k::plan_status(cx->gstatus, cx->ws[W_BADQ].as<uint32_t>(), nullptr, 0, na->offsets + nq, na->capacity, st);
+            out->total = -1;
+            return;
+        }
         if (groups.empty()) {
             k::fill_u32(reinterpret_cast<uint32_t *>(na->offsets), 2 * (nq + 1), 0u, st);
         } else {

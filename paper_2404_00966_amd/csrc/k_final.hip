@@ -575,21 +575,25 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 template <bool kShort, bool kCheck, bool kL1>
 __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
                                                    float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
-                                                   int n_blk, int est)
+                                                   int n_blk_arg, const int32_t *__restrict__ n_blk_dev,
+                                                   int blk_slots, int est)
 {
     __shared__ uint64_t s_mem[kSortCapL2];
     __shared__ int32_t s_ring[4][2 * kRing];
     static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
-    if ((int)blockIdx.x < n_blk) {
-        verify_l2_block<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
-                                s_ring[threadIdx.x >> 6], est != 0);
+    // workgroup mode: the first blk_slots blocks (a multiple of 8), of which
+    // the first n_blk take the listed queries (n_blk from the host, or read
+    // on the device when the list was made there)
+    const int n_blk = n_blk_dev ? *n_blk_dev : n_blk_arg;
+    if ((int)blockIdx.x < blk_slots) {
+        if ((int)blockIdx.x < n_blk)
+            verify_l2_block<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
+                                                 s_ring[threadIdx.x >> 6], est != 0);
         return;
     }
-    // wave mode: past the workgroup-mode blocks (rounded up to 8), XCD x
-    // takes the x-th contiguous eighth of the 4-query blocks
+    // wave mode: XCD x takes the x-th contiguous eighth of the 4-query blocks
     const int wave = threadIdx.x >> 6;
-    const int nb8 = (n_blk + 7) & ~7;
-    if ((int)blockIdx.x < nb8) return;
+    const int nb8 = blk_slots;
     const int64_t w = blockIdx.x - nb8, per = (gridDim.x - nb8) >> 3;
     const int64_t q = ((w & 7) * per + (w >> 3)) * 4 + wave;
     if (q >= a.nq) return;
@@ -600,16 +604,18 @@ __global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, Query
 }
 
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st, bool l1)
+               bool est, bool check, hipStream_t st, bool l1, const int32_t *n_blk_dev)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
-    const unsigned grid = (unsigned)(((n_blk + 7) & ~7) + ((a.nq + 3) / 4 + 7) / 8 * 8);
+    // a list made on the device may name any query: a slot for each
+    const int blk_slots = n_blk_dev ? (int)((a.nq + 7) & ~7ll) : ((n_blk + 7) & ~7);
+    const unsigned grid = (unsigned)(blk_slots + ((a.nq + 3) / 4 + 7) / 8 * 8);
 #define VL(S, C, M)                                                                                           \
     hipLaunchKernelGGL((k_verify_l2<S, C, M>), dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, \
-                       blk_q, n_blk, est ? 1 : 0)
+                       blk_q, n_blk, n_blk_dev, blk_slots, est ? 1 : 0)
     const bool chk = check && est;
     if (l1) {
         // Manhattan: no bf16 estimates, every candidate takes its float32 distance
@@ -699,6 +705,53 @@ void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bo
 }
 
 // ---------------------------------------------------------------------------
+// Verification plan on the device (graph-replayed searches, which read no
+// counts on the host): per query its candidate count from the grouping
+// offsets; queries beyond the LDS sort get a power-of-two run of the scratch
+// (offsets by a scan), queries beyond one wave's share go to the workgroup
+// list (compacted by a scan of flags).
+// ---------------------------------------------------------------------------
+__global__ void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap,
+                              uint32_t *__restrict__ need, uint32_t *__restrict__ flag)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= ng) return;
+    const int64_t ns = qoff[q + 1] - qoff[q];
+    uint32_t p = 0;
+    if (ns > sort_cap) {
+        p = 1;
+        while ((int64_t)p < ns) p <<= 1;
+    }
+    need[q] = p;
+    flag[q] = ns > wave_cap ? 1u : 0u;
+}
+
+__global__ void k_verify_lists(const uint32_t *__restrict__ need, const int64_t *__restrict__ need_off,
+                               const uint32_t *__restrict__ flag, const int64_t *__restrict__ flag_off, int64_t ng,
+                               int64_t *__restrict__ big_off, int32_t *__restrict__ blk_q, int32_t *__restrict__ n_blk)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) *n_blk = (int32_t)flag_off[ng];
+    if (q >= ng) return;
+    big_off[q] = need[q] ? need_off[q] : -1;
+    if (flag[q]) blk_q[flag_off[q]] = (int32_t)q;
+}
+
+void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap, uint32_t *need, uint32_t *flag,
+                 int64_t *need_off, int64_t *flag_off, int64_t *big_off, int32_t *blk_q, int32_t *n_blk,
+                 hipStream_t st)
+{
+    const unsigned g = (unsigned)((ng + 256) / 256);
+    hipLaunchKernelGGL(k_verify_need, dim3(g), dim3(256), 0, st, qoff, ng, sort_cap, wave_cap, need, flag);
+    check_launch("verify_plan(need)");
+    scan_u32(need, ng, need_off, st);
+    scan_u32(flag, ng, flag_off, st);
+    hipLaunchKernelGGL(k_verify_lists, dim3(g), dim3(256), 0, st, need, need_off, flag, flag_off, ng, big_off, blk_q,
+                       n_blk);
+    check_launch("verify_plan(lists)");
+}
+
+// ---------------------------------------------------------------------------
 // CSR assembly.
 // ---------------------------------------------------------------------------
 __global__ void k_csr_write(const uint64_t *__restrict__ out_keys, const int64_t *__restrict__ qoff,
@@ -736,12 +789,13 @@ void perm_counts(const uint32_t *out_count, const int32_t *perm, int64_t nq, uin
 __global__ void k_emit_result(const uint64_t *__restrict__ out_keys, const int64_t *__restrict__ qoff,
                               const uint32_t *__restrict__ out_count, const int32_t *__restrict__ perm,
                               const int64_t *__restrict__ dst_off, int64_t nq, int is_edit, int64_t *__restrict__ ids,
-                              float *__restrict__ dist_f, int32_t *__restrict__ dist_i)
+                              float *__restrict__ dist_f, int32_t *__restrict__ dist_i, int64_t cap)
 {
     const int64_t i = blockIdx.x;
     if (i >= nq) return;
-    const uint32_t cnt = out_count[i];
     const int64_t src = qoff[i], dst = dst_off[perm ? perm[i] : i];
+    // cap >= 0: only entries below the output capacity are written
+    const uint32_t cnt = cap < 0 ? out_count[i] : (uint32_t)max<int64_t>(0, min<int64_t>(out_count[i], cap - dst));
     for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
         const uint64_t key = out_keys[src + j];
         ids[dst + j] = (int64_t)(uint32_t)key;
@@ -753,11 +807,11 @@ __global__ void k_emit_result(const uint64_t *__restrict__ out_keys, const int64
 
 void emit_result(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int32_t *perm,
                  const int64_t *dst_off, int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i,
-                 hipStream_t st)
+                 hipStream_t st, int64_t cap)
 {
     if (nq == 0) return;
     hipLaunchKernelGGL(k_emit_result, dim3((unsigned)nq), dim3(64), 0, st, out_keys, qoff, out_count, perm, dst_off,
-                       nq, is_edit, ids, dist_f, dist_i);
+                       nq, is_edit, ids, dist_f, dist_i, cap);
     check_launch(__func__);
 }
 

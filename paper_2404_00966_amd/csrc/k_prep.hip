@@ -199,21 +199,82 @@ void thresholds(const float *base, const float *QP, const int32_t *kq, int64_t n
     check_launch(__func__);
 }
 
-// *bad |= 1 when any of the first dim values of the rows is not finite.
-__global__ void k_check_finite(const float *__restrict__ X, int64_t rows, int dim, int stride, uint32_t *__restrict__ bad)
+// *bad |= 1 when any of the first dim values of the rows is not finite;
+// such a value is replaced by zero, so that no later kernel reads it.
+__global__ void k_check_finite(float *__restrict__ X, int64_t rows, int dim, int stride, uint32_t *__restrict__ bad)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * dim) return;
     const int64_t r = i / dim;
     const int c = (int)(i - r * dim);
-    if (!isfinite(X[(size_t)r * stride + c])) atomicOr(bad, 1u);
+    float *x = X + (size_t)r * stride + c;
+    if (!isfinite(*x)) {
+        *x = 0.f;
+        atomicOr(bad, 1u);
+    }
 }
 
-void check_finite(const float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st)
+void check_finite(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st)
 {
     const int64_t n = rows * dim;
     if (n == 0) return;
     hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, rows, dim, stride, bad);
+    check_launch(__func__);
+}
+
+// Per-query parameters of a graph-replayed search from device arrays: kq =
+// k (>= 1: kNN), base = the range radius (the chord 2 sin(r / 2) for the
+// angular metric) where k == 0; a negative k or a negative or NaN radius
+// sets bit 1 of *status (that query is then run as a range query of radius 0).
+__global__ void k_query_params(const float *__restrict__ radius, const int32_t *__restrict__ k, int64_t nq,
+                               int angular, float *__restrict__ base, int32_t *__restrict__ kq,
+                               uint32_t *__restrict__ status)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int kk = k[q];
+    bool bad = kk < 0;
+    float b = 0.f;
+    if (kk <= 0) {
+        const float r = radius[q];
+        if (!(r >= 0.f) || !isfinite(r)) bad = true;
+        else b = angular ? (float)(2.0 * sin(fmin((double)r, 3.141592653589793) / 2.0)) : r;
+    }
+    kq[q] = kk > 0 ? kk : 0;
+    base[q] = b;
+    if (bad) atomicOr(status, 1u);
+}
+
+void query_params(const float *radius, const int32_t *k, int64_t nq, bool angular, float *base, int32_t *kq,
+                  uint32_t *status, hipStream_t st)
+{
+    if (nq == 0) return;
+    hipLaunchKernelGGL(k_query_params, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, radius, k, nq,
+                       angular ? 1 : 0, base, kq, status);
+    check_launch(__func__);
+}
+
+// The status word of a graph-replayed search, after its last kernel: bit 2
+// for a bad query (a non-finite value, or a zero vector of the angular
+// metric), bit 4 when the candidates exceeded their space, bit 8 when the
+// answers exceeded the output capacity.
+__global__ void k_plan_status(uint32_t *__restrict__ status, const uint32_t *__restrict__ bad_query,
+                              const unsigned long long *__restrict__ cand_count, int64_t cand_cap,
+                              const int64_t *__restrict__ total, int64_t answer_cap)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t s = *status;
+    if (bad_query && *bad_query) s |= 2u;
+    if (cand_count && *cand_count > (unsigned long long)cand_cap) s |= 4u;
+    if (total && *total > answer_cap) s |= 8u;
+    *status = s;
+}
+
+void plan_status(uint32_t *status, const uint32_t *bad_query, const unsigned long long *cand_count, int64_t cand_cap,
+                 const int64_t *total, int64_t answer_cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan_status, dim3(1), dim3(64), 0, st, status, bad_query, cand_count, cand_cap, total,
+                       answer_cap);
     check_launch(__func__);
 }
 

@@ -80,7 +80,13 @@ void tomb_bits(const uint32_t *del_ep, int64_t n, uint32_t e, uint32_t *bits, in
 void tile_pairs(const uint64_t *mask, int64_t n_leaves, int ntiles, const int32_t *leaf_cnt, unsigned long long *out,
                 hipStream_t st);
 // *bad |= 1 when a value among the first dim of each row is not finite.
-void check_finite(const float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
+void check_finite(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
+// Graph-replayed searches: per-query parameters from device arrays (bit 1 of
+// *status on bad input) and the final status word (see gts_plan_* in gts.h).
+void query_params(const float *radius, const int32_t *k, int64_t nq, bool angular, float *base, int32_t *kq,
+                  uint32_t *status, hipStream_t st);
+void plan_status(uint32_t *status, const uint32_t *bad_query, const unsigned long long *cand_count, int64_t cand_cap,
+                 const int64_t *total, int64_t answer_cap, hipStream_t st);
 // Rows scaled to unit length in place (norm in double, result rounded to
 // float); a row with zero or non-finite norm becomes zero and sets *bad.
 void normalize_rows(float *X, int64_t rows, int dim, int stride, uint32_t *bad, hipStream_t st);
@@ -339,7 +345,13 @@ struct VerifyArgs {
 // check: count rechecked candidates whose float32 distance leaves their
 // bf16 interval (CNT_BOUND_VIOL).
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st, bool l1 = false);
+               bool est, bool check, hipStream_t st, bool l1 = false, const int32_t *n_blk_dev = nullptr);
+// The verification plan made on the device: big_off (-1 or the query's
+// scratch run), the workgroup list blk_q and its length *n_blk; need / flag
+// [ng] and need_off / flag_off [ng + 1] are workspace.
+void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap, uint32_t *need, uint32_t *flag,
+                 int64_t *need_off, int64_t *flag_off, int64_t *big_off, int32_t *blk_q, int32_t *n_blk,
+                 hipStream_t st);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
@@ -351,7 +363,7 @@ void perm_counts(const uint32_t *out_count, const int32_t *perm, int64_t nq, uin
 // keys from out_keys[qoff[i]] to ids / dist at dst_off[caller query].
 void emit_result(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int32_t *perm,
                  const int64_t *dst_off, int64_t nq, int is_edit, int64_t *ids, float *dist_f, int32_t *dist_i,
-                 hipStream_t st);
+                 hipStream_t st, int64_t cap = -1);
 
 // CSR assembly: ids[res_off[q] + j] and dist from out_keys[qoff[q] + j].
 void csr_write(const uint64_t *out_keys, const int64_t *qoff, const uint32_t *out_count, const int64_t *res_off,

@@ -100,11 +100,20 @@ class _ServerStats(C.Structure):
                 ("max_ms", C.c_double), ("span_ms", C.c_double)]
 
 
+class _PlanIO(C.Structure):
+    _fields_ = [("queries", C.c_void_p), ("radius", C.c_void_p), ("k", C.c_void_p), ("offsets", C.c_void_p),
+                ("ids", C.c_void_p), ("dist", C.c_void_p), ("status", C.c_void_p)]
+
+
+PLAN_BAD_INPUT, PLAN_BAD_QUERY, PLAN_CANDIDATES, PLAN_ANSWERS = 1, 2, 4, 8
+
+
 EXPORTS = ("gts_build_index", "gts_range_query", "gts_knn_query", "gts_search", "gts_insert", "gts_delete",
            "gts_result_copy", "gts_result_free", "gts_destroy", "gts_get_info", "gts_get_stats",
            "gts_set_timing", "gts_last_error", "gts_server_create", "gts_server_submit", "gts_server_replay",
            "gts_server_poll", "gts_server_release", "gts_server_flush", "gts_server_get_stats",
-           "gts_server_destroy", "gts_update_batch", "gts_cost_model", "gts_choose_fanout", "gts_search_noalloc")
+           "gts_server_destroy", "gts_update_batch", "gts_cost_model", "gts_choose_fanout", "gts_search_noalloc",
+           "gts_plan_create", "gts_plan_launch", "gts_plan_destroy")
 
 _lib = None
 
@@ -144,6 +153,9 @@ def library():
         L.gts_server_destroy.argtypes = [C.c_void_p]
         L.gts_search_noalloc.argtypes = [C.c_void_p, P(_Objects), C.c_void_p, C.c_void_p, P(_QueryOpts),
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.gts_plan_create.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(_QueryOpts), P(_PlanIO), P(C.c_void_p)]
+        L.gts_plan_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.gts_plan_destroy.argtypes = [C.c_void_p]
         L.gts_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("gts_last_error", "gts_cost_model"):
@@ -364,6 +376,58 @@ class Index:
 
     def set_timing(self, on=True):
         _check(library().gts_set_timing(self._h, 1 if on else 0))
+
+
+class Plan:
+    """gts_plan_*: a batched search of nq device queries on a vector index,
+    recorded once into a HIP graph and replayed.  The plan's input tensors
+    (queries [nq, dim], radius [nq], k [nq]; k == 0 marks a range query) are
+    filled in place before launch(); the answers (offsets, ids, dist) and the
+    status word are read after it, in stream order."""
+
+    def __init__(self, index, nq, capacity, precision=PRECISION_DEFAULT, mem_budget_bytes=0, flags=0):
+        L = library()
+        dim = index.info()["dim"]
+        dev = torch.device("cuda")
+        self.index = index
+        self.nq, self.capacity = int(nq), int(capacity)
+        self.queries = torch.zeros((self.nq, dim), dtype=torch.float32, device=dev)
+        self.radius = torch.zeros(self.nq, dtype=torch.float32, device=dev)
+        self.k = torch.zeros(self.nq, dtype=torch.int32, device=dev)
+        self.offsets = torch.zeros(self.nq + 1, dtype=torch.int64, device=dev)
+        self.ids = torch.zeros(max(self.capacity, 1), dtype=torch.int64, device=dev)
+        self.dist = torch.zeros(max(self.capacity, 1), dtype=torch.float32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        io = _PlanIO(self.queries.data_ptr(), self.radius.data_ptr(), self.k.data_ptr(), self.offsets.data_ptr(),
+                     self.ids.data_ptr(), self.dist.data_ptr(), self.status.data_ptr())
+        qo = _QueryOpts(MODE_BATCHED, DEVICE, int(mem_budget_bytes), precision, int(flags))
+        torch.cuda.current_stream().synchronize()
+        h = C.c_void_p()
+        _check(L.gts_plan_create(index._h, self.nq, self.capacity, C.byref(qo), C.byref(io), C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(library().gts_plan_launch(self._h, s.cuda_stream))
+
+    def result(self):
+        """(Result, status) of the last launch (waits for the current stream)."""
+        torch.cuda.current_stream().synchronize()
+        st = int(self.status.item())
+        total = int(self.offsets[-1].item())
+        n = min(total, self.capacity)
+        return Result(self.offsets.clone(), self.ids[:n].clone(), self.dist[:n].clone()), st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().gts_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -67,7 +67,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     structs = {"gts_objects": gts._Objects, "gts_build_opts": gts._BuildOpts, "gts_query_opts": gts._QueryOpts,
                "gts_result": gts._Result, "gts_stats": gts._Stats, "gts_index_info": gts._Info,
                "gts_request": gts._Request, "gts_completion": gts._Completion,
-               "gts_server_opts": gts._ServerOpts, "gts_server_stats": gts._ServerStats}
+               "gts_server_opts": gts._ServerOpts, "gts_server_stats": gts._ServerStats,
+               "gts_plan_io": gts._PlanIO}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gts.h"', "int main(void) {"]
     expect = []
     for cname, cls in structs.items():
