@@ -192,6 +192,19 @@ def run_l2(args, gts, synth, torch, np):
            "tuned": {"bound_window": st["bound_window"], "sweep_grid_per_cu": st["sweep_grid_per_cu"],
                      "tuning_calls": tune_calls},
            "dist_evals_per_s": dist_evals(st, w["pivots"]) / (ms * 1e-3)}
+    # the same batch as one recorded HIP graph (gts_plan_*): every stage on
+    # the device, no host synchronisation inside a step
+    total_ans = int(ref.offsets[-1])
+    plan = gts.Plan(idx, nq, capacity=total_ans + total_ans // 4 + 1024)
+    plan.queries.copy_(Q)
+    plan.radius.copy_(torch.from_numpy(radius).cuda())
+    plan.k.copy_(torch.from_numpy(k).cuda())
+    tg, perg = timed_steps(plan.launch, args.steps, args.warmup)
+    got, gst = plan.result()
+    out["graph_plan"] = {"qps": nq * args.steps / tg, "ms_per_step": tg * 1e3 / args.steps,
+                         "p50_ms": pct(perg, 50), "status": gst, "same_answers": same_answers(ref, got)}
+    log(f"l2 graph plan: {out['graph_plan']}")
+    plan.close()
     if args.side_steps > 0:
         # PCIe included: queries from pinned host memory, answers to host memory
         th, perh = timed_steps(lambda: idx.search(Qh, radius=radius, k=k, result="host"), args.side_steps, 1)
@@ -928,6 +941,7 @@ def main():
                       "hands queries over in pinned host memory and returns answers to host memory",
         "dist_evals_per_s": l2["dist_evals_per_s"],
         "host_to_host": l2.get("host_to_host"),
+        "graph_plan": l2.get("graph_plan"),
         "plain": l2.get("plain"),
         "fp32_selection": l2.get("fp32_selection"),
         "no_prune": l2.get("no_prune"),

@@ -188,6 +188,8 @@ typedef struct {
     int64_t group_retries;   /* query groups whose candidates overflowed the
                                 memory budget and were split again (sized
                                 from the attempt's counts)                     */
+    int64_t max_query_candidates; /* largest candidate set of one query
+                                (0 when a recorded graph ran the call)       */
 } gts_stats;
 
 #define GTS_STAGE_PREP 0     /* query -> pivot distances, query tiles          */

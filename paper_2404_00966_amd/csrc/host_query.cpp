@@ -37,7 +37,7 @@ enum Ws {
     W_FRONTIER, W_BIGOFF, W_CURSOR, W_COUNTERS, W_RES_IDS, W_RES_DIST, W_RES_OFF, W_NEAR, W_TMP, W_PERM,
     W_TMP2, W_RES_IDS2, W_RES_DIST2, W_OFF_ORIG, W_CUT, W_TQE, W_QCELLS0, W_QCNT0, W_QCELLS, W_QCNT, W_ORDER, W_PAIR_TILE, W_PAIR_MASK, W_SWEEP_ITEMS, W_BLKQ,
     W_SORT_TMP, W_HOME2, W_PBASE, W_PKQ, W_PQP, W_PQ32, W_PNEAR, W_PIV, W_POSOF, W_HOMEC, W_PLEN, W_POFF, W_PCHARS,
-    W_BADQ, W_QEP, W_PQEP, W_TMIN, W_TMAX, W_TILEW, W_VNEED, W_VFLAG, W_VNOFF, W_VFOFF, W_NBLK, W_COUNT
+    W_BADQ, W_QEP, W_PQEP, W_TMIN, W_TMAX, W_TILEW, W_VNEED, W_VFLAG, W_VNOFF, W_NBLK, W_VCUR, W_COUNT
 };
 static_assert(W_COUNT <= kWorkspaceSlots, "too few workspace slots in QueryCtx");
 
@@ -458,17 +458,18 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         k::plan_status(cx->gstatus, nullptr, ccount, cap, nullptr, 0, st);
         int64_t *big_off = wsp<int64_t>(cx, W_BIGOFF, ng + 1);
         uint64_t *scratch = wsp<uint64_t>(cx, W_SCRATCH, 2 * cap);
-        int32_t *dblk = wsp<int32_t>(cx, W_BLKQ, ng + 1);
+        int32_t *dord = wsp<int32_t>(cx, W_BLKQ, ng + 1);
         int32_t *nblk = wsp<int32_t>(cx, W_NBLK, 1);
-        k::verify_plan(qoff, ng, kSortCapL2, kWaveSortCap, wsp<uint32_t>(cx, W_VNEED, ng + 1),
-                       wsp<uint32_t>(cx, W_VFLAG, ng + 1), wsp<int64_t>(cx, W_VNOFF, ng + 1),
-                       wsp<int64_t>(cx, W_VFOFF, ng + 1), big_off, dblk, nblk, st);
+        k::verify_plan(qoff, ng, kSortCapL2, wsp<uint32_t>(cx, W_VNEED, ng + 1), wsp<int64_t>(cx, W_VNOFF, ng + 1),
+                       wsp<uint32_t>(cx, W_VFLAG, 2 * kVerifyClasses), big_off, dord, nblk, st);
         uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(cap, 1));
         uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
         k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count,
                          counters, idx->angular ? 1 : 0};
-        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, 0, !sel32, b.check_bound, st, idx->l1,
-                     nblk);
+        uint32_t *vcur = wsp<uint32_t>(cx, W_VCUR, k::kVerifyCursorWords);
+        k::fill_u32(vcur, k::kVerifyCursorWords, 0u, st);
+        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dord, 0, !sel32, b.check_bound, st, idx->l1,
+                     nblk, vcur);
         go->direct = direct;
         go->total = -1;
         return true;
@@ -514,13 +515,15 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     // segments too long for LDS sort in power-of-two scratch runs; the lists
     // are written straight into the pinned staging
     int64_t *big = reinterpret_cast<int64_t *>(pin + pl.big);
-    int32_t *blk_q = reinterpret_cast<int32_t *>(pin + pl.blk);   // L2: queries beyond one wave's share
+    int32_t *ord = reinterpret_cast<int32_t *>(pin + pl.blk);     // L2: the verification order
     int64_t n_blk = 0;
     int64_t scratch_words = 0;
     bool any_big = false;
     const int64_t sort_cap = l2 ? kSortCapL2 : kSortCap;
+    int64_t cls_at[kVerifyClasses] = {};   // L2: queries per verification class, then class cursors
     for (int64_t q = 0; q < ng; q++) {
         const int64_t ns = h_qoff[q + 1] - h_qoff[q];
+        cx->stats.max_query_candidates = std::max(cx->stats.max_query_candidates, ns);
         big[q] = -1;
         if (ns > sort_cap) {
             if (!l2) n_wide++;
@@ -530,7 +533,19 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
             scratch_words += p;
             any_big = true;
         }
-        if (l2 && ns > kWaveSortCap) blk_q[n_blk++] = (int32_t)q;
+        if (l2) cls_at[verify_class(ns)]++;
+    }
+    if (l2) {
+        // the order: workgroup queries first, then the wave queries by
+        // decreasing class, each class in query (home) order
+        n_blk = cls_at[0];
+        int64_t at = 0;
+        for (int c = 0; c < kVerifyClasses; c++) {
+            const int64_t n = cls_at[c];
+            cls_at[c] = at;
+            at += n;
+        }
+        for (int64_t q = 0; q < ng; q++) ord[cls_at[verify_class(h_qoff[q + 1] - h_qoff[q])]++] = (int32_t)q;
     }
     int64_t *big_off = nullptr;
     uint64_t *scratch = nullptr;
@@ -545,17 +560,21 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
     k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters,
                      idx->angular ? 1 : 0};
-    int32_t *dblk = nullptr;
-    if (n_blk > 0) {
-        dblk = wsp<int32_t>(cx, W_BLKQ, n_blk);
-        GTS_HIP(hipMemcpyAsync(dblk, blk_q, n_blk * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    int32_t *dord = nullptr;
+    if (l2) {
+        dord = wsp<int32_t>(cx, W_BLKQ, ng);
+        GTS_HIP(hipMemcpyAsync(dord, ord, ng * sizeof(int32_t), hipMemcpyHostToDevice, st));
     }
     if (l2) n_wide += n_blk;
     cx->stats.wide_queries += n_wide;
-    if (l2)
-        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dblk, (int)n_blk, !plain && !sel32,
-                     b.check_bound, st, idx->l1);
-    else k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
+    if (l2) {
+        uint32_t *vcur = wsp<uint32_t>(cx, W_VCUR, k::kVerifyCursorWords);
+        k::fill_u32(vcur, k::kVerifyCursorWords, 0u, st);
+        k::verify_l2(va, ov, qv, (float)((d.dim + 8) * 5.9604645e-8), dord, (int)n_blk, !plain && !sel32,
+                     b.check_bound, st, idx->l1, nullptr, vcur);
+    } else {
+        k::verify_edit(va, oe, qe, !b.any_knn && b.max_radius <= 63.f, st);
+    }
     rec(cx, 6);
     // the host waits for verify next: allocate the result meanwhile, sized for
     // every candidate (an upper bound of the answers) unless that is large
@@ -703,9 +722,19 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;
-    if (d.metric == GTS_L2_F32 && !idx->l1 && !cx->graph && b.mode == GTS_MODE_BATCHED &&
-        b.precision == GTS_BF16_GUARDED && d.lpad > 0 &&
-        d.dim <= kMaxMfmaDim && b.nq > 0) {
+    const bool tunable = d.metric == GTS_L2_F32 && !idx->l1 && b.mode == GTS_MODE_BATCHED &&
+                         b.precision == GTS_BF16_GUARDED && d.lpad > 0 && d.dim <= kMaxMfmaDim && b.nq > 0;
+    if (tunable && cx->graph) {
+        // a recorded graph takes the settings eager calls of its shape have
+        // settled on (the kNN key: its queries may hold kNN), else the defaults
+        const std::string gkey = tune_key(idx, b.nq, true);
+        {
+            std::lock_guard<std::mutex> lk(idx->tune_mu);
+            auto it = idx->tuned.find(gkey);
+            if (it != idx->tuned.end()) tset = it->second;
+        }
+        b.sweep_grid_per_cu = LaunchTuner::kGridPerCu[tset.grid];
+    } else if (tunable) {
         bool knn = false;
         for (int64_t q = 0; q < b.nq && !knn; q++) knn = kin && kin[q] > 0;
         tkey = tune_key(idx, b.nq, knn);
@@ -1090,6 +1119,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
             for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
         }
+        add((size_t)k::kVerifyCursorWords * sizeof(uint32_t));   // the verification's work-queue cursors
         const size_t left = cx->arena->left();
         GTS_CHECK(left >= reserve + (size_t)56 * 1024, GTS_ENOMEM,
                   "the no-allocation scratch cannot hold this batch's work lists; use a smaller batch");

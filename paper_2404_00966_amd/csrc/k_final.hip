@@ -246,14 +246,16 @@ __device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr
 // while the current one is decided: cache entries, whose distance is already
 // known, are kept at once; a kNN candidate whose lower interval end exceeds
 // the bound ub is dropped; the positions that need a recheck go through a
-// ring of 128 entries in LDS, and every 16 of them make a batch: 16 lanes
-// per candidate, four candidates per 16-lane group, rows and ids all
+// ring of 128 entries in LDS, and every kBatch of them make a batch: 16 lanes
+// per candidate, kBatch / 4 candidates per 16-lane group, rows and ids all
 // requested before any is used, the same strided float32 sum as every other
 // exact L2 distance here (the query slice in registers when the row has at
 // most 128 floats).  emit(keep, key) takes every lane's decision and is
 // called by the whole wave.
-constexpr int kChunk = kWaveSortCap / 64;    // 64-candidate steps per block-mode chunk
+constexpr int kWaveSteps = kVerifyBlockMin / 64;   // 64-candidate steps of a wave-mode query
 constexpr int kRing = 128;
+constexpr int kBatch = 24;                   // rechecks in flight per wave (six per 16-lane group)
+static_assert(kBatch % 4 == 0 && kBatch + 64 <= kRing, "recheck batch");
 
 struct RecheckCtx {
     const float *qrow;
@@ -279,54 +281,55 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int32_t p[4];
-        uint32_t ev[4];
-        bool nd[4];
+        constexpr int U = kBatch / 4;
+        int32_t p[U];
+        uint32_t ev[U];
+        bool nd[U];
 #pragma unroll
-        for (int uu = 0; uu < 4; uu++) {
+        for (int uu = 0; uu < U; uu++) {
             const int j = 4 * uu + grp;
             nd[uu] = j < cnt;
             p[uu] = nd[uu] ? ring[(head + j) & (kRing - 1)] : 0;
             ev[uu] = kCheck && nd[uu] && sl == 0 ? ring_est[(head + j) & (kRing - 1)] : 0u;
         }
-        uint32_t idv[4];
-        float acc[4];
+        uint32_t idv[U];
+        float acc[U];
 #pragma unroll
-        for (int uu = 0; uu < 4; uu++) idv[uu] = nd[uu] && sl == 0 ? a.ids[p[uu]] : 0u;
+        for (int uu = 0; uu < U; uu++) idv[uu] = nd[uu] && sl == 0 ? a.ids[p[uu]] : 0u;
         if (kShort) {
-            float xv[4][8];
+            float xv[U][8];
 #pragma unroll
-            for (int uu = 0; uu < 4; uu++) {
+            for (int uu = 0; uu < U; uu++) {
                 const float *x = o.X32 + (size_t)p[uu] * o.dp;
 #pragma unroll
                 for (int t = 0; t < 8; t++) xv[uu][t] = nd[uu] && sl + 16 * t < o.dp ? x[sl + 16 * t] : 0.f;
             }
             // coordinates beyond dp are zero on both sides: fmaf(0, 0, acc) == acc
 #pragma unroll
-            for (int uu = 0; uu < 4; uu++) {
+            for (int uu = 0; uu < U; uu++) {
                 acc[uu] = 0.f;
 #pragma unroll
                 for (int t = 0; t < 8; t++) acc[uu] = dev::dterm<kL1>(acc[uu], rc.qr[t], xv[uu][t]);
             }
         } else {
-            const float *x[4];
+            const float *x[U];
 #pragma unroll
-            for (int uu = 0; uu < 4; uu++) {
+            for (int uu = 0; uu < U; uu++) {
                 acc[uu] = 0.f;
                 x[uu] = nd[uu] ? o.X32 + (size_t)p[uu] * o.dp : rc.qrow;
             }
             for (int d = sl; d < o.dp; d += 16) {
                 const float qd = rc.qrow[d];
 #pragma unroll
-                for (int uu = 0; uu < 4; uu++) acc[uu] = dev::dterm<kL1>(acc[uu], qd, x[uu][d]);
+                for (int uu = 0; uu < U; uu++) acc[uu] = dev::dterm<kL1>(acc[uu], qd, x[uu][d]);
             }
         }
 #pragma unroll
-        for (int uu = 0; uu < 4; uu++)
+        for (int uu = 0; uu < U; uu++)
 #pragma unroll
             for (int off = 8; off > 0; off >>= 1) acc[uu] += __shfl_xor(acc[uu], off, 16);
 #pragma unroll
-        for (int uu = 0; uu < 4; uu++) {
+        for (int uu = 0; uu < U; uu++) {
             const bool mine = nd[uu] && sl == 0;
             const float d = dev::dfinish<kL1>(acc[uu]);
             if (mine) (*verified)++;
@@ -374,9 +377,9 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
             if (kCheck) ring_est[(tail + dev::lanes_below(m)) & (kRing - 1)] = (uint32_t)c.val;
         }
         tail += __popcll(m);
-        while (tail - head >= 16) {
-            batch(16);
-            head += 16;
+        while (tail - head >= kBatch) {
+            batch(kBatch);
+            head += kBatch;
         }
     }
     if (tail > head) batch(tail - head);
@@ -385,8 +388,8 @@ __device__ __forceinline__ void recheck_chunk(const VerifyArgs &a, const L2View 
 // One workgroup for query q (more candidates than one wave takes).  kNN:
 // the k-th smallest upper interval end, found by a 32-step binary search
 // over the float bits with block-wide counts of the values held in LDS,
-// bounds the answer set (when the candidates fit the LDS run).  The waves
-// recheck chunks of 64 * kChunk candidates in turn; kept keys are compacted
+// bounds the answer set (when the candidates fit the LDS run).  Each wave
+// rechecks an equal share of whole 64-candidate steps; kept keys are compacted
 // per wave (one LDS atomic reserves the wave's slots) and sorted in LDS
 // (s_keys, kSortCapL2) or in the query's scratch run.
 template <bool kShort, bool kCheck, bool kL1>
@@ -475,10 +478,13 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
             if (keep) keys[slot0 + dev::lanes_below(m)] = key;
         }
     };
+    // the candidates split evenly over the waves (whole 64-candidate steps)
     const int nw = (int)(blockDim.x >> 6);
-    for (int c0 = wave * 64 * kChunk; c0 < ns; c0 += nw * 64 * kChunk)
-        recheck_chunk<kShort, kCheck, kL1>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, min(ns, c0 + 64 * kChunk), ring,
-                                      &verified, &viol, emit);
+    const int steps = (ns + 63) >> 6, per = (steps + nw - 1) / nw;
+    const int c0 = min(ns, 64 * per * wave), c1 = min(ns, 64 * per * (wave + 1));
+    if (c0 < c1)
+        recheck_chunk<kShort, kCheck, kL1>(a, o, rc, delta, eps_a, eps_b, eps_c, g, c0, c1, ring, &verified, &viol,
+                                           emit);
     __syncthreads();
     for (int o2 = 32; o2 > 0; o2 >>= 1) verified += __shfl_xor(verified, o2, 64);
     for (int o2 = 32; o2 > 0; o2 >>= 1) viol += __shfl_xor(viol, o2, 64);
@@ -489,7 +495,7 @@ __device__ void verify_l2_block(const VerifyArgs &a, const L2View &o, const Quer
 }
 
 
-// One wave for query q (at most kWaveSortCap candidates).  kNN: the k-th
+// One wave for query q (at most kVerifyBlockMin candidates).  kNN: the k-th
 // smallest upper interval end over the candidates, found by a 32-step
 // binary search over the float bits (counting with ballots over the values
 // each lane holds in registers), bounds the answer set; then one chunk of
@@ -514,9 +520,9 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
     rc.est = est;
     rc.sel = est && k > 0 && ns > k;
     if (rc.sel) {
-        uint32_t hv[kChunk];
+        uint32_t hv[kWaveSteps];
 #pragma unroll
-        for (int u = 0; u < kChunk; u++) {
+        for (int u = 0; u < kWaveSteps; u++) {
             const int i = lane + 64 * u;
             hv[u] = 0xffffffffu;
             if (i < ns) {
@@ -533,7 +539,7 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
             const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
             int c = 0;
 #pragma unroll
-            for (int u = 0; u < kChunk; u++)
+            for (int u = 0; u < kWaveSteps; u++)
                 if (u < nu) c += __popcll(dev::ballot(hv[u] <= mid));
             if (c >= k) hi_v = mid;
             else lo_v = mid + 1u;
@@ -568,54 +574,73 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
     if (lane == 0) a.out_count[q] = (uint32_t)nout;
 }
 
-// One launch for both forms: workgroups [0, n_blk) take the queries of
-// blk_q (more than kWaveSortCap candidates) one each, the rest take four
-// queries each, one per wave, skipping those; the long workgroups start first
-// and overlap the bulk of the work.
+// One persistent launch for both forms.  First the queries of the order's
+// head (more than kVerifyBlockMin candidates), a whole workgroup each, dealt
+// to the workgroups in turn.  Then each wave takes the rest on its own from
+// a work queue, kVerifyChunk consecutive queries per grab, so a wave that
+// finishes early goes on at once (a workgroup's LDS is held until its last
+// wave ends) and the longest queries, which come first, start first.  The
+// queue is split over the XCDs (chunk c belongs to queue c mod nx, nx =
+// min(8, workgroups), workgroup b serving queue b mod nx; workgroups are
+// dealt to the XCDs round robin), each cursor on its own 128-byte line: a
+// single cursor taken by every wave of the chip serialised the grabs.
+// Every grab is made without lane-divergent control flow (all lanes issue
+// the atomic, lane 0 adding 1; the chunk is lane 0's value in a scalar
+// register), so the exit test is a scalar branch of the whole wave.
 template <bool kShort, bool kCheck, bool kL1>
-__global__ __launch_bounds__(256) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
-                                                   float eps_b, float eps_c, const int32_t *__restrict__ blk_q,
-                                                   int n_blk_arg, const int32_t *__restrict__ n_blk_dev,
-                                                   int blk_slots, int est)
+__global__ __launch_bounds__(256, 4) void k_verify_l2(VerifyArgs a, L2View o, QueryL2 qv, float delta, float eps_a,
+                                                      float eps_b, float eps_c, const int32_t *__restrict__ order,
+                                                      int n_blk_arg, const int32_t *__restrict__ n_blk_dev,
+                                                      uint32_t *__restrict__ ctr, int est)
 {
     __shared__ uint64_t s_mem[kSortCapL2];
     __shared__ int32_t s_ring[4][2 * kRing];
     static_assert(4 * kWaveSortCap <= kSortCapL2, "wave runs must fit the workgroup's LDS");
-    // workgroup mode: the first blk_slots blocks (a multiple of 8), of which
-    // the first n_blk take the listed queries (n_blk from the host, or read
-    // on the device when the list was made there)
-    const int n_blk = n_blk_dev ? *n_blk_dev : n_blk_arg;
-    if ((int)blockIdx.x < blk_slots) {
-        if ((int)blockIdx.x < n_blk)
-            verify_l2_block<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, blk_q[blockIdx.x], s_mem,
-                                                 s_ring[threadIdx.x >> 6], est != 0);
-        return;
+    const int n_blk = __builtin_amdgcn_readfirstlane(n_blk_dev ? *n_blk_dev : n_blk_arg);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int it = blockIdx.x; it < n_blk; it += gridDim.x) {
+        verify_l2_block<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, order[it], s_mem, s_ring[wave],
+                                             est != 0);
+        __syncthreads();
     }
-    // wave mode: XCD x takes the x-th contiguous eighth of the 4-query blocks
-    const int wave = threadIdx.x >> 6;
-    const int nb8 = blk_slots;
-    const int64_t w = blockIdx.x - nb8, per = (gridDim.x - nb8) >> 3;
-    const int64_t q = ((w & 7) * per + (w >> 3)) * 4 + wave;
-    if (q >= a.nq) return;
-    const int ns = (int)(a.qoff[q + 1] - a.qoff[q]);
-    if (ns > kWaveSortCap) return;
-    verify_l2_wave<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, q, s_mem + wave * kWaveSortCap, s_ring[wave],
-                           est != 0);
+    const int n_wave = (int)a.nq - n_blk;
+    const int nx = gridDim.x < 8 ? (int)gridDim.x : 8;
+    const int x = (int)(blockIdx.x % nx);
+    uint32_t *cur = ctr + x * kVerifyCursorStride;
+    for (;;) {
+        const uint32_t got = atomicAdd(cur, lane == 0 ? 1u : 0u);
+        const int j = __builtin_amdgcn_readfirstlane((int)got);
+        const int64_t first = ((int64_t)j * nx + x) * kVerifyChunk;
+        if (first >= n_wave) break;
+        const int last = (int)min<int64_t>(first + kVerifyChunk, n_wave);
+        for (int it = (int)first; it < last; it++) {
+            // the wave's LDS run and ring are reused: the last query's reads
+            // come before this one's writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            verify_l2_wave<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, order[n_blk + it],
+                                                s_mem + wave * kWaveSortCap, s_ring[wave], est != 0);
+        }
+    }
 }
 
-void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st, bool l1, const int32_t *n_blk_dev)
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *order, int n_blk,
+               bool est, bool check, hipStream_t st, bool l1, const int32_t *n_blk_dev, uint32_t *ctr)
 {
     if (a.nq == 0) return;
     const float u = 5.9604645e-8f;
     const int D = o.ksteps * 32;
     const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
-    // a list made on the device may name any query: a slot for each
-    const int blk_slots = n_blk_dev ? (int)((a.nq + 7) & ~7ll) : ((n_blk + 7) & ~7);
-    const unsigned grid = (unsigned)(blk_slots + ((a.nq + 3) / 4 + 7) / 8 * 8);
+    // persistent: four workgroups per CU (the LDS holds four), fewer for a
+    // small batch
+    int dev = 0, cus = 256;
+    GTS_HIP(hipGetDevice(&dev));
+    GTS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)cus, (a.nq + 3) / 4));
 #define VL(S, C, M)                                                                                           \
     hipLaunchKernelGGL((k_verify_l2<S, C, M>), dim3(grid), dim3(256), 0, st, a, o, qv, delta, eps_a, eps_b, eps_c, \
-                       blk_q, n_blk, n_blk_dev, blk_slots, est ? 1 : 0)
+                       order, n_blk, n_blk_dev, ctr, est ? 1 : 0)
     const bool chk = check && est;
     if (l1) {
         // Manhattan: no bf16 estimates, every candidate takes its float32 distance
@@ -708,11 +733,13 @@ void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bo
 // Verification plan on the device (graph-replayed searches, which read no
 // counts on the host): per query its candidate count from the grouping
 // offsets; queries beyond the LDS sort get a power-of-two run of the scratch
-// (offsets by a scan), queries beyond one wave's share go to the workgroup
-// list (compacted by a scan of flags).
+// (offsets by a scan); the verification order lists the queries by
+// verify_class (class sizes counted with atomics, then each query placed at
+// its class's base plus an atomic cursor: the order inside a class varies
+// from run to run, the answers do not).
 // ---------------------------------------------------------------------------
-__global__ void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap,
-                              uint32_t *__restrict__ need, uint32_t *__restrict__ flag)
+__global__ void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int64_t sort_cap,
+                              uint32_t *__restrict__ need, uint32_t *__restrict__ cls)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ng) return;
@@ -723,31 +750,32 @@ __global__ void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int6
         while ((int64_t)p < ns) p <<= 1;
     }
     need[q] = p;
-    flag[q] = ns > wave_cap ? 1u : 0u;
+    atomicAdd(&cls[verify_class(ns)], 1u);
 }
 
-__global__ void k_verify_lists(const uint32_t *__restrict__ need, const int64_t *__restrict__ need_off,
-                               const uint32_t *__restrict__ flag, const int64_t *__restrict__ flag_off, int64_t ng,
-                               int64_t *__restrict__ big_off, int32_t *__restrict__ blk_q, int32_t *__restrict__ n_blk)
+__global__ void k_verify_lists(const int64_t *__restrict__ qoff, const uint32_t *__restrict__ need,
+                               const int64_t *__restrict__ need_off, uint32_t *__restrict__ cls, int64_t ng,
+                               int64_t *__restrict__ big_off, int32_t *__restrict__ order, int32_t *__restrict__ n_blk)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0) *n_blk = (int32_t)flag_off[ng];
+    if (q == 0) *n_blk = (int32_t)cls[0];
     if (q >= ng) return;
     big_off[q] = need[q] ? need_off[q] : -1;
-    if (flag[q]) blk_q[flag_off[q]] = (int32_t)q;
+    const int c = verify_class(qoff[q + 1] - qoff[q]);
+    uint32_t base = 0;
+    for (int j = 0; j < c; j++) base += cls[j];
+    order[base + atomicAdd(&cls[kVerifyClasses + c], 1u)] = (int32_t)q;
 }
 
-void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap, uint32_t *need, uint32_t *flag,
-                 int64_t *need_off, int64_t *flag_off, int64_t *big_off, int32_t *blk_q, int32_t *n_blk,
-                 hipStream_t st)
+void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off, uint32_t *cls,
+                 int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st)
 {
     const unsigned g = (unsigned)((ng + 256) / 256);
-    hipLaunchKernelGGL(k_verify_need, dim3(g), dim3(256), 0, st, qoff, ng, sort_cap, wave_cap, need, flag);
+    fill_u32(cls, 2 * kVerifyClasses, 0u, st);
+    hipLaunchKernelGGL(k_verify_need, dim3(g), dim3(256), 0, st, qoff, ng, sort_cap, need, cls);
     check_launch("verify_plan(need)");
     scan_u32(need, ng, need_off, st);
-    scan_u32(flag, ng, flag_off, st);
-    hipLaunchKernelGGL(k_verify_lists, dim3(g), dim3(256), 0, st, need, need_off, flag, flag_off, ng, big_off, blk_q,
-                       n_blk);
+    hipLaunchKernelGGL(k_verify_lists, dim3(g), dim3(256), 0, st, qoff, need, need_off, cls, ng, big_off, order, n_blk);
     check_launch("verify_plan(lists)");
 }
 

@@ -287,14 +287,19 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
 // live distance bounds the k-th nearest neighbour distance from above.
 //
 // One workgroup per query.  The queries arrive sorted by home leaf, so
-// neighbouring queries read the same leaves: consecutive queries go to the
-// same XCD (workgroups are dealt to the 8 XCDs round robin), where the second
-// read of a leaf hits that XCD's L2.  The window plan is one wave-wide scan;
+// neighbouring queries read the same leaves: runs of consecutive queries go
+// to the same XCD (workgroups are dealt to the 8 XCDs round robin), where the
+// second read of a leaf hits that XCD's L2, and the runs are dealt to the
+// XCDs in turn so each gets its share of every part of the query order.  The window plan is one wave-wide scan;
 // object rows and tombstone words of kBoundUnroll objects per 16-lane group
 // are loaded before any of them is used.
 // ---------------------------------------------------------------------------
 constexpr int kWinObj = 2048;
 constexpr int kBoundUnroll = 4;
+#ifndef GTS_BOUND_RUN
+#define GTS_BOUND_RUN 64
+#endif
+constexpr int64_t kBoundRun = GTS_BOUND_RUN;   // consecutive queries per run dealt to one XCD
 
 __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ near,
                                                     const int32_t *__restrict__ leaf_first,
@@ -307,10 +312,10 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
     __shared__ float s_d[kWinObj];
     __shared__ int s_first[kNearLeaves], s_start[kNearLeaves + 1];
     __shared__ int s_nl;
-    // gridDim.x is a multiple of 8: XCD x (= blockIdx.x % 8) takes the x-th
-    // contiguous eighth of the queries
-    const int64_t per = gridDim.x >> 3;
-    const int64_t q = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // runs of kBoundRun consecutive queries are dealt to the XCDs in turn
+    // (gridDim.x is a multiple of 8 kBoundRun)
+    const int64_t i = blockIdx.x >> 3, run = (i / kBoundRun) * 8 + (blockIdx.x & 7);
+    const int64_t q = run * kBoundRun + i % kBoundRun;
     if (q >= nq) return;
     const int k = kq[q];
     if (k <= 0) return;
@@ -396,7 +401,7 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
 {
     if (nq == 0) return;
     require(dp <= 128, "bound_near: rows wider than 128 floats");
-    const unsigned grid = (unsigned)((nq + 7) / 8 * 8);
+    const unsigned grid = (unsigned)((nq + 8 * kBoundRun - 1) / (8 * kBoundRun) * (8 * kBoundRun));
     hipLaunchKernelGGL(k_bound_near, dim3(grid), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
                        kq, nq, tomb, target, tq, counters);
     check_launch(__func__);

@@ -338,20 +338,27 @@ struct VerifyArgs {
     int angular;               // L2 on unit vectors: keys carry the angle 2 asin(d/2)
     int l1;                    // vectors under the Manhattan (L1) metric
 };
-// blk_q: [n_blk] the queries with more than kWaveSortCap candidates.
+// order: [nq] every query once, the n_blk queries with more than
+// kVerifyBlockMin candidates first (a whole workgroup each), then the others
+// (one wave each) in the order they should start; n_blk from the host, or
+// read from *n_blk_dev when the order was made on the device.  ctr:
+// kVerifyCursorWords words, zero before the launch (the work-queue cursors).
 // est: the tree-position candidates carry bf16 estimates of d^2 (the bf16
 // selection); without them every candidate is rechecked and kept for the
 // final (distance, id) cut.
 // check: count rechecked candidates whose float32 distance leaves their
 // bf16 interval (CNT_BOUND_VIOL).
-void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *blk_q, int n_blk,
-               bool est, bool check, hipStream_t st, bool l1 = false, const int32_t *n_blk_dev = nullptr);
+constexpr int kVerifyChunk = 1;                 // wave-mode queries per grab
+constexpr int kVerifyCursorStride = 32;         // words between the work-queue cursors (128 bytes)
+constexpr int kVerifyCursorWords = 8 * kVerifyCursorStride;
+void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *order, int n_blk,
+               bool est, bool check, hipStream_t st, bool l1, const int32_t *n_blk_dev, uint32_t *ctr);
 // The verification plan made on the device: big_off (-1 or the query's
-// scratch run), the workgroup list blk_q and its length *n_blk; need / flag
-// [ng] and need_off / flag_off [ng + 1] are workspace.
-void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, int64_t wave_cap, uint32_t *need, uint32_t *flag,
-                 int64_t *need_off, int64_t *flag_off, int64_t *big_off, int32_t *blk_q, int32_t *n_blk,
-                 hipStream_t st);
+// scratch run) and the verification order with its workgroup count *n_blk
+// (queries by verify_class; within a class in no fixed order); need [ng],
+// need_off [ng + 1] and cls [2 kVerifyClasses] are workspace.
+void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off, uint32_t *cls,
+                 int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 

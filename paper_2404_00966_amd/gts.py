@@ -62,7 +62,7 @@ class _Stats(C.Structure):
                 ("groups", C.c_int64), ("bound_window", C.c_int64), ("tuning", C.c_int64),
                 ("bound_evals", C.c_int64), ("wide_queries", C.c_int64), ("bound_violations", C.c_int64),
                 ("own_pairs", C.c_int64), ("filter_objects", C.c_int64), ("sweep_grid_per_cu", C.c_int64),
-                ("group_retries", C.c_int64)]
+                ("group_retries", C.c_int64), ("max_query_candidates", C.c_int64)]
 
 
 class _Info(C.Structure):

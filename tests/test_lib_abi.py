@@ -51,7 +51,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(gts._BuildOpts) == 48
     assert ctypes.sizeof(gts._QueryOpts) == 24
     assert ctypes.sizeof(gts._Result) == 64
-    assert ctypes.sizeof(gts._Stats) == 7 * 8 + 8 + 64 + 10 * 8
+    assert ctypes.sizeof(gts._Stats) == 7 * 8 + 8 + 64 + 11 * 8
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):
