@@ -296,10 +296,7 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
 // ---------------------------------------------------------------------------
 constexpr int kWinObj = 2048;
 constexpr int kBoundUnroll = 4;
-#ifndef GTS_BOUND_RUN
-#define GTS_BOUND_RUN 64
-#endif
-constexpr int64_t kBoundRun = GTS_BOUND_RUN;   // consecutive queries per run dealt to one XCD
+constexpr int64_t kBoundRun = 64;   // consecutive queries per run dealt to one XCD
 
 __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ near,
                                                     const int32_t *__restrict__ leaf_first,
