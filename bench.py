@@ -50,6 +50,8 @@ KERNEL_SOURCES = {
     "k_mfma_sweep": ["k_search.hip"],
     "k_bound_near": ["k_leaf.hip"],
     "k_leaf_box": ["k_search.hip"],
+    "k_leaf_ball": ["k_leaf.hip"],
+    "k_leaf_near": ["k_leaf.hip"],
     "k_l2_objfilter": ["k_filter32.hip"],
     "k_edit_objfilter": ["k_search.hip"],
     "k_verify_edit": ["k_final.hip"],
@@ -175,6 +177,10 @@ def run_l2(args, gts, synth, torch, np):
         if idx.stats()["tuning"] == 0:
             break
     log(f"tuning finished after {tune_calls} calls")
+    # one call with the bf16 bound self-check (untimed): every rechecked
+    # candidate's float32 distance against its proven interval
+    idx.search(Q, radius=radius, k=k, result="device", flags=gts.QF_CHECK_BOUND)
+    check = idx.stats()
     total, per = timed_steps(lambda: idx.search(Q, radius=radius, k=k, result="device"), args.steps, args.warmup)
     ms = total * 1e3 / args.steps
     # one more step with stage timing on, for the stage split and the roofline
@@ -182,11 +188,8 @@ def run_l2(args, gts, synth, torch, np):
     ref = idx.search(Q, radius=radius, k=k, result="device")
     st = idx.stats()
     idx.set_timing(False)
-    # one call with the bf16 bound self-check (untimed): every rechecked
-    # candidate's float32 distance against its proven interval
-    idx.search(Q, radius=radius, k=k, result="device", flags=gts.QF_CHECK_BOUND)
-    st["bound_violations"] = idx.stats()["bound_violations"]
-    st["bound_checked"] = idx.stats()["verified"]
+    st["bound_violations"] = check["bound_violations"]
+    st["bound_checked"] = check["verified"]
     out = {"qps": nq * args.steps / total, "ms_per_step": ms, "per_step_ms": per, "build_s": build_s,
            "stats": st, "nq": nq, "r": r, "k": w["k"], "n": d["n"], "dim": w["dim"], "m": w["pivots"],
            "tuned": {"bound_window": st["bound_window"], "sweep_grid_per_cu": st["sweep_grid_per_cu"],
@@ -194,17 +197,18 @@ def run_l2(args, gts, synth, torch, np):
            "dist_evals_per_s": dist_evals(st, w["pivots"]) / (ms * 1e-3)}
     # the same batch as one recorded HIP graph (gts_plan_*): every stage on
     # the device, no host synchronisation inside a step
-    total_ans = int(ref.offsets[-1])
-    plan = gts.Plan(idx, nq, capacity=total_ans + total_ans // 4 + 1024)
-    plan.queries.copy_(Q)
-    plan.radius.copy_(torch.from_numpy(radius).cuda())
-    plan.k.copy_(torch.from_numpy(k).cuda())
-    tg, perg = timed_steps(plan.launch, args.steps, args.warmup)
-    got, gst = plan.result()
-    out["graph_plan"] = {"qps": nq * args.steps / tg, "ms_per_step": tg * 1e3 / args.steps,
-                         "p50_ms": pct(perg, 50), "status": gst, "same_answers": same_answers(ref, got)}
-    log(f"l2 graph plan: {out['graph_plan']}")
-    plan.close()
+    if not args.no_graph:
+        total_ans = int(ref.offsets[-1])
+        plan = gts.Plan(idx, nq, capacity=total_ans + total_ans // 4 + 1024)
+        plan.queries.copy_(Q)
+        plan.radius.copy_(torch.from_numpy(radius).cuda())
+        plan.k.copy_(torch.from_numpy(k).cuda())
+        tg, perg = timed_steps(plan.launch, args.steps, args.warmup)
+        got, gst = plan.result()
+        out["graph_plan"] = {"qps": nq * args.steps / tg, "ms_per_step": tg * 1e3 / args.steps,
+                             "p50_ms": pct(perg, 50), "status": gst, "same_answers": same_answers(ref, got)}
+        log(f"l2 graph plan: {out['graph_plan']}")
+        plan.close()
     if args.side_steps > 0:
         # PCIe included: queries from pinned host memory, answers to host memory
         th, perh = timed_steps(lambda: idx.search(Qh, radius=radius, k=k, result="host"), args.side_steps, 1)
@@ -752,9 +756,11 @@ def pmc_summary(dirs, workload, last, command):
     copy_bytes = 268435456.0
     factor = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        vals = [v for _, v in per.get(("copy", c), [])]
+        # the calibration copy is the first copy dispatch of the run
+        # (--calibrate-copy runs before anything else touches the device)
+        vals = sorted(per.get(("copy", c), []))
         if vals:
-            factor[c] = copy_bytes / (max(vals) * 1024.0)
+            factor[c] = copy_bytes / (vals[0][1] * 1024.0)
     kernels = {}
     for (k, c), vals in sorted(per.items()):
         if k == "copy" or k not in KERNEL_SOURCES:
@@ -780,6 +786,15 @@ def pmc_summary(dirs, workload, last, command):
         lines.append(f"| `{k}` | {e['dispatches']} | {fk if fk is None else f'{fk:,.1f}'} | "
                      f"{wk if wk is None else f'{wk:,.1f}'} | {b if b is None else f'{b / 1e6:,.1f}'} | "
                      f"{vi if vi is None else f'{vi:,.0f}'} |")
+    other = sorted({c for e in kernels.values() for c in e
+                    if c not in ("source_sha16", "dispatches", "fetch_kib", "write_kib", "valu_insts", "bytes")})
+    if other:
+        lines += ["", "Other counters per launch (same averaging):", "",
+                  "| kernel | " + " | ".join(other) + " |", "|---|" + "---:|" * len(other)]
+        for k, e in sorted(kernels.items()):
+            if any(c in e for c in other):
+                lines.append(f"| `{k}` | " + " | ".join("" if e.get(c) is None else f"{e[c]:,.0f}" for c in other)
+                             + " |")
     lines += ["", "```json", json.dumps({"workload": workload, "copy_factor": factor, "kernels": kernels}, indent=1),
               "```", ""]
     return "\n".join(lines)
@@ -817,6 +832,7 @@ def main():
     ap.add_argument("--cpu-dna-queries", type=int, default=0, help="DNA oracle queries (0: one per core)")
     ap.add_argument("--skip-dna", action="store_true")
     ap.add_argument("--skip-c4", action="store_true", help="skip the 4M x 96 kNN leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg (profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run one 256 MiB device copy first (profiling)")
     ap.add_argument("--pmc-summary", nargs="+", metavar="DIR",
                     help="summarise rocprofv3 counter runs in DIR... (no GPU work)")

@@ -577,13 +577,14 @@ __device__ void verify_l2_wave(const VerifyArgs &a, const L2View &o, const Query
 // One persistent launch for both forms.  First the queries of the order's
 // head (more than kVerifyBlockMin candidates), a whole workgroup each, dealt
 // to the workgroups in turn.  Then each wave takes the rest on its own from
-// a work queue, kVerifyChunk consecutive queries per grab, so a wave that
-// finishes early goes on at once (a workgroup's LDS is held until its last
-// wave ends) and the longest queries, which come first, start first.  The
-// queue is split over the XCDs (chunk c belongs to queue c mod nx, nx =
-// min(8, workgroups), workgroup b serving queue b mod nx; workgroups are
-// dealt to the XCDs round robin), each cursor on its own 128-byte line: a
-// single cursor taken by every wave of the chip serialised the grabs.
+// a work queue, one query per grab, so a wave that finishes early goes on
+// at once (a workgroup's LDS is held until its last wave ends) and the
+// longest queries, which come first, start first.  The queue is split over
+// the XCDs (runs of kVerifyRun consecutive queries dealt to the nx =
+// min(8, workgroups) queues in turn, workgroup b serving queue b mod nx;
+// workgroups are dealt to the XCDs round robin), each cursor on its own
+// 128-byte line: a single cursor taken by every wave of the chip serialised
+// the grabs.
 // Every grab is made without lane-divergent control flow (all lanes issue
 // the atomic, lane 0 adding 1; the chunk is lane 0's value in a scalar
 // register), so the exit test is a scalar branch of the whole wave.
@@ -609,19 +610,19 @@ __global__ __launch_bounds__(256, 4) void k_verify_l2(VerifyArgs a, L2View o, Qu
     uint32_t *cur = ctr + x * kVerifyCursorStride;
     for (;;) {
         const uint32_t got = atomicAdd(cur, lane == 0 ? 1u : 0u);
-        const int j = __builtin_amdgcn_readfirstlane((int)got);
-        const int64_t first = ((int64_t)j * nx + x) * kVerifyChunk;
-        if (first >= n_wave) break;
-        const int last = (int)min<int64_t>(first + kVerifyChunk, n_wave);
-        for (int it = (int)first; it < last; it++) {
-            // the wave's LDS run and ring are reused: the last query's reads
-            // come before this one's writes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            verify_l2_wave<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, order[n_blk + it],
-                                                s_mem + wave * kWaveSortCap, s_ring[wave], est != 0);
-        }
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)got);
+        // this queue's j-th query: runs of kVerifyRun consecutive queries of
+        // the order belong to one queue (neighbours share candidate rows in
+        // the XCD's L2), the runs dealt to the queues in turn
+        const int64_t it = ((j / kVerifyRun) * nx + x) * kVerifyRun + j % kVerifyRun;
+        if (it >= n_wave) break;
+        // the wave's LDS run and ring are reused: the last query's reads
+        // come before this one's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        verify_l2_wave<kShort, kCheck, kL1>(a, o, qv, delta, eps_a, eps_b, eps_c, order[n_blk + it],
+                                            s_mem + wave * kWaveSortCap, s_ring[wave], est != 0);
     }
 }
 

@@ -348,7 +348,7 @@ struct VerifyArgs {
 // final (distance, id) cut.
 // check: count rechecked candidates whose float32 distance leaves their
 // bf16 interval (CNT_BOUND_VIOL).
-constexpr int kVerifyChunk = 1;                 // wave-mode queries per grab
+constexpr int kVerifyRun = 64;                  // consecutive wave-mode queries of one XCD queue
 constexpr int kVerifyCursorStride = 32;         // words between the work-queue cursors (128 bytes)
 constexpr int kVerifyCursorWords = 8 * kVerifyCursorStride;
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *order, int n_blk,
