@@ -196,6 +196,8 @@ typedef struct {
 #define GTS_STAGE_BOUND 1    /* kNN radius bound                               */
 #define GTS_STAGE_NODES 2    /* node filtering                                  */
 #define GTS_STAGE_CANDS 3    /* object filtering / tile distances + compaction  */
+/* GTS_STAGE_GROUP: grouping candidates by query, and the host's planning of
+ * the verification after it; GTS_STAGE_VERIFY: from the verification launch. */
 #define GTS_STAGE_GROUP 4    /* grouping candidates by query                    */
 #define GTS_STAGE_VERIFY 5   /* exact verification, selection and sorting       */
 #define GTS_STAGE_OUTPUT 6   /* CSR assembly                                    */

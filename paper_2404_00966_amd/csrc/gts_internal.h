@@ -54,16 +54,6 @@ constexpr int kMaxStrlen = 255;     // longest string (pivot table is uint8)
 constexpr int kSortCap = 2048;      // edit distance: per-query keys sorted in LDS (more: global scratch)
 constexpr int kSortCapL2 = 4096;    // L2: per-query keys sorted in LDS (more: global scratch)
 constexpr int kWaveSortCap = 1024;  // L2: per-query keys one wave's LDS run holds
-constexpr int kVerifyBlockMin = 512; // L2: queries with more candidates are verified by a whole workgroup
-static_assert(kVerifyBlockMin <= kWaveSortCap, "a wave verifies at most its LDS run");
-// L2 verification order: class 0 = the workgroup queries, then the wave
-// queries by decreasing candidate count (classes 1..4), so the longest
-// start first.
-__host__ __device__ inline int verify_class(int64_t ns)
-{
-    return ns > kVerifyBlockMin ? 0 : ns > 256 ? 1 : ns > 128 ? 2 : ns > 64 ? 3 : 4;
-}
-constexpr int kVerifyClasses = 5;
 constexpr int kWorkspaceSlots = 80;   // named query buffers of an index
 constexpr int kMaxCentres = 2048;      // farthest-first centres that order the leaves
 

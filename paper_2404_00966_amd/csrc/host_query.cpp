@@ -460,8 +460,10 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         uint64_t *scratch = wsp<uint64_t>(cx, W_SCRATCH, 2 * cap);
         int32_t *dord = wsp<int32_t>(cx, W_BLKQ, ng + 1);
         int32_t *nblk = wsp<int32_t>(cx, W_NBLK, 1);
-        k::verify_plan(qoff, ng, kSortCapL2, wsp<uint32_t>(cx, W_VNEED, ng + 1), wsp<int64_t>(cx, W_VNOFF, ng + 1),
-                       wsp<uint32_t>(cx, W_VFLAG, 2 * kVerifyClasses), big_off, dord, nblk, st);
+        uint32_t *vneed = wsp<uint32_t>(cx, W_VNEED, ng + 1), *vcls = wsp<uint32_t>(cx, W_VFLAG, k::kVerifyPlanWords);
+        int64_t *vnoff = wsp<int64_t>(cx, W_VNOFF, ng + 1);
+        k::verify_plan_count(qoff, ng, kSortCapL2, vneed, vnoff, vcls, st);
+        k::verify_plan_lists(qoff, ng, vneed, vnoff, vcls, big_off, dord, nblk, st);
         uint64_t *out_keys = wsp<uint64_t>(cx, W_OUTKEYS, std::max<int64_t>(cap, 1));
         uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
         k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count,
@@ -480,7 +482,23 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint32_t *h_bad = h_small + 32;   // (the small-counter region of the staging holds 64 words)
     *h_bad = 0;
     if (b.check_q) GTS_HIP(hipMemcpyAsync(h_bad, cx->ws[W_BADQ].p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    // L2: the verification plan's counts on the device (scratch needs, class
+    // sizes, the largest candidate set), read with the candidate count; the
+    // edit path plans on the host from the segment offsets
+    uint32_t *vneed = nullptr, *vcls = nullptr;
+    int64_t *vnoff = nullptr;
+    uint32_t *h_vcls = h_small + 40;           // kVerifyPlanWords words of the staging's small region
+    int64_t *h_vneed = reinterpret_cast<int64_t *>(h_small + 56);
+    if (l2) {
+        vneed = wsp<uint32_t>(cx, W_VNEED, ng + 1);
+        vcls = wsp<uint32_t>(cx, W_VFLAG, k::kVerifyPlanWords);
+        vnoff = wsp<int64_t>(cx, W_VNOFF, ng + 1);
+        k::verify_plan_count(qoff, ng, kSortCapL2, vneed, vnoff, vcls, st);
+        GTS_HIP(hipMemcpyAsync(h_vcls, vcls, k::kVerifyPlanWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        GTS_HIP(hipMemcpyAsync(h_vneed, vnoff + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    } else {
+        GTS_HIP(hipMemcpyAsync(h_qoff_pin, qoff, (ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    }
     GTS_HIP(hipStreamSynchronize(st));
     GTS_CHECK(*h_bad == 0, GTS_EINVAL,
               idx->angular ? "a query vector is zero or non-finite: it has no direction (angular metric)"
@@ -512,47 +530,45 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
         k::fill_u32(cursor, ng, 0u, st);
         k::group_scatter(cands, ccount, cap, qoff, cursor, grouped, ncand, del_ep, qep, st);
     }
-    // segments too long for LDS sort in power-of-two scratch runs; the lists
-    // are written straight into the pinned staging
-    int64_t *big = reinterpret_cast<int64_t *>(pin + pl.big);
-    int32_t *ord = reinterpret_cast<int32_t *>(pin + pl.blk);     // L2: the verification order
+    // segments too long for LDS sort in power-of-two scratch runs (L2: the
+    // offsets, the verification order and its workgroup count made on the
+    // device from the counts above; edit: on the host, into the pinned
+    // staging)
     int64_t n_blk = 0;
-    int64_t scratch_words = 0;
-    bool any_big = false;
-    const int64_t sort_cap = l2 ? kSortCapL2 : kSortCap;
-    int64_t cls_at[kVerifyClasses] = {};   // L2: queries per verification class, then class cursors
-    for (int64_t q = 0; q < ng; q++) {
-        const int64_t ns = h_qoff[q + 1] - h_qoff[q];
-        cx->stats.max_query_candidates = std::max(cx->stats.max_query_candidates, ns);
-        big[q] = -1;
-        if (ns > sort_cap) {
-            if (!l2) n_wide++;
-            int64_t p = 1;
-            while (p < ns) p <<= 1;
-            big[q] = scratch_words;
-            scratch_words += p;
-            any_big = true;
-        }
-        if (l2) cls_at[verify_class(ns)]++;
-    }
-    if (l2) {
-        // the order: workgroup queries first, then the wave queries by
-        // decreasing class, each class in query (home) order
-        n_blk = cls_at[0];
-        int64_t at = 0;
-        for (int c = 0; c < kVerifyClasses; c++) {
-            const int64_t n = cls_at[c];
-            cls_at[c] = at;
-            at += n;
-        }
-        for (int64_t q = 0; q < ng; q++) ord[cls_at[verify_class(h_qoff[q + 1] - h_qoff[q])]++] = (int32_t)q;
-    }
     int64_t *big_off = nullptr;
     uint64_t *scratch = nullptr;
-    if (any_big) {
-        big_off = wsp<int64_t>(cx, W_BIGOFF, ng);
-        GTS_HIP(hipMemcpyAsync(big_off, big, ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        scratch = wsp<uint64_t>(cx, W_SCRATCH, scratch_words);
+    int32_t *dord = nullptr;
+    if (l2) {
+        n_blk = (int64_t)h_vcls[0];
+        cx->stats.max_query_candidates = std::max<int64_t>(cx->stats.max_query_candidates, h_vcls[2 * k::kVerifyClasses]);
+        const int64_t need = *h_vneed;
+        big_off = wsp<int64_t>(cx, W_BIGOFF, ng + 1);
+        if (need > 0) scratch = wsp<uint64_t>(cx, W_SCRATCH, need);
+        dord = wsp<int32_t>(cx, W_BLKQ, ng + 1);
+        k::verify_plan_lists(qoff, ng, vneed, vnoff, vcls, big_off, dord, nullptr, st);
+    } else {
+        const int64_t *h_qoff = h_qoff_pin;   // read in place (no fresh host pages per call)
+        int64_t *big = reinterpret_cast<int64_t *>(pin + pl.big);
+        int64_t scratch_words = 0;
+        bool any_big = false;
+        for (int64_t q = 0; q < ng; q++) {
+            const int64_t ns = h_qoff[q + 1] - h_qoff[q];
+            cx->stats.max_query_candidates = std::max(cx->stats.max_query_candidates, ns);
+            big[q] = -1;
+            if (ns > kSortCap) {
+                n_wide++;
+                int64_t p = 1;
+                while (p < ns) p <<= 1;
+                big[q] = scratch_words;
+                scratch_words += p;
+                any_big = true;
+            }
+        }
+        if (any_big) {
+            big_off = wsp<int64_t>(cx, W_BIGOFF, ng);
+            GTS_HIP(hipMemcpyAsync(big_off, big, ng * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            scratch = wsp<uint64_t>(cx, W_SCRATCH, scratch_words);
+        }
     }
 
     // ---- verify, select, order ------------------------------------------------
@@ -560,13 +576,11 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     uint32_t *out_count = wsp<uint32_t>(cx, W_OUTCNT, ng + 1);
     k::VerifyArgs va{grouped, qoff, big_off, scratch, kq, base, d.ids.as<uint32_t>(), ng, out_keys, out_count, counters,
                      idx->angular ? 1 : 0};
-    int32_t *dord = nullptr;
-    if (l2) {
-        dord = wsp<int32_t>(cx, W_BLKQ, ng);
-        GTS_HIP(hipMemcpyAsync(dord, ord, ng * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    }
     if (l2) n_wide += n_blk;
     cx->stats.wide_queries += n_wide;
+    // (the verification stage's clock starts here: the planning above,
+    // between the grouping and this launch, counts to the grouping)
+    rec(cx, 8);
     if (l2) {
         uint32_t *vcur = wsp<uint32_t>(cx, W_VCUR, k::kVerifyCursorWords);
         k::fill_u32(vcur, k::kVerifyCursorWords, 0u, st);
@@ -610,14 +624,14 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
     rec(cx, 7);
     if (cx->timing) GTS_HIP(hipStreamSynchronize(st));
     if (cx->timing) {
-        float ms;
-        const int stage_of[] = {-1, -1, -1, GTS_STAGE_NODES, GTS_STAGE_CANDS, GTS_STAGE_GROUP, GTS_STAGE_VERIFY,
-                                GTS_STAGE_OUTPUT};
-        for (int i = 3; i <= 7; i++) {
-            GTS_HIP(hipEventElapsedTime(&ms, cx->ev[i - 1], cx->ev[i]));
-            int s = stage_of[i];
-            if (plain && i == 4) s = GTS_STAGE_PLAIN;
-            stage_ms[s] += ms;
+        // (event 8 marks the verification launch, after the host's planning)
+        const int from[] = {2, 3, 4, 8, 6}, to[] = {3, 4, 8, 6, 7};
+        const int stage[] = {GTS_STAGE_NODES, plain ? GTS_STAGE_PLAIN : GTS_STAGE_CANDS, GTS_STAGE_GROUP,
+                             GTS_STAGE_VERIFY, GTS_STAGE_OUTPUT};
+        for (int i = 0; i < 5; i++) {
+            float ms;
+            GTS_HIP(hipEventElapsedTime(&ms, cx->ev[from[i]], cx->ev[to[i]]));
+            stage_ms[stage[i]] += ms;
         }
     }
     return true;
@@ -1069,8 +1083,13 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             }
             const int window = LaunchTuner::kWindow[tset.window];
             cx->stats.bound_window = window;
+            // bf16 MFMA bounds over block-shared windows; the exact window
+            // kernel takes the queries those leave unbounded
+            k::bound_mfma(d.X16t.as<uint16_t>(), d.xn.as<float>(), d.xe.as<float>(), d.n, d.ksteps, near,
+                          d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), qv.Q16t, qv.qn, qv.qe, kq,
+                          nq, b.tomb_bound, base, counters, st);
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
-                          d.dp, qv.Q32, kq, nq, b.tomb_bound, window, base, counters, st);
+                          d.dp, qv.Q32, kq, nq, b.tomb_bound, window, base, counters, st, true);
         } else if (l2) {
             k::L2View ov{d.X32.as<float>(), d.xn.as<float>(), d.xe.as<float>(), d.X16t.as<uint16_t>(), d.n, d.npad,
                          d.dim, d.dp, d.ksteps};
@@ -1115,10 +1134,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
         for (int i = 0; i < 4; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
         for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
         add((size_t)nq * sizeof(int32_t));
-        if (gmode) {   // the device-side verification plan
-            for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
-            for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
-        }
+        // the device-side verification plan (need, class counts, order; need
+        // offsets, scratch offsets)
+        for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(uint32_t));
+        for (int i = 0; i < 3; i++) add((size_t)(nq + 1) * sizeof(int64_t));
         add((size_t)k::kVerifyCursorWords * sizeof(uint32_t));   // the verification's work-queue cursors
         const size_t left = cx->arena->left();
         GTS_CHECK(left >= reserve + (size_t)56 * 1024, GTS_ENOMEM,

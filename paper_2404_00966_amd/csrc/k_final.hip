@@ -253,6 +253,7 @@ __device__ __forceinline__ void l2_interval(const Cand &c, float qnn, float qerr
 // most 128 floats).  emit(keep, key) takes every lane's decision and is
 // called by the whole wave.
 constexpr int kWaveSteps = kVerifyBlockMin / 64;   // 64-candidate steps of a wave-mode query
+static_assert(kVerifyBlockMin <= kWaveSortCap, "a wave verifies at most its LDS run");
 constexpr int kRing = 128;
 constexpr int kBatch = 24;                   // rechecks in flight per wave (six per 16-lane group)
 static_assert(kBatch % 4 == 0 && kBatch + 64 <= kRing, "recheck batch");
@@ -739,45 +740,81 @@ void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bo
 // its class's base plus an atomic cursor: the order inside a class varies
 // from run to run, the answers do not).
 // ---------------------------------------------------------------------------
-__global__ void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int64_t sort_cap,
-                              uint32_t *__restrict__ need, uint32_t *__restrict__ cls)
+__global__ __launch_bounds__(256) void k_verify_need(const int64_t *__restrict__ qoff, int64_t ng, int64_t sort_cap,
+                                                     uint32_t *__restrict__ need, uint32_t *__restrict__ cls)
 {
+    // class counts and the largest count aggregated per wave (one atomic per
+    // class per wave: 20,000 queries on a handful of words serialised)
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= ng) return;
-    const int64_t ns = qoff[q + 1] - qoff[q];
-    uint32_t p = 0;
-    if (ns > sort_cap) {
-        p = 1;
-        while ((int64_t)p < ns) p <<= 1;
+    const int lane = threadIdx.x & 63;
+    const bool valid = q < ng;
+    const int64_t ns = valid ? qoff[q + 1] - qoff[q] : 0;
+    if (valid) {
+        uint32_t p = 0;
+        if (ns > sort_cap) {
+            p = 1;
+            while ((int64_t)p < ns) p <<= 1;
+        }
+        need[q] = p;
     }
-    need[q] = p;
-    atomicAdd(&cls[verify_class(ns)], 1u);
+    const int c = valid ? verify_class(ns) : -1;
+#pragma unroll
+    for (int j = 0; j < kVerifyClasses; j++) {
+        const uint64_t m = dev::ballot(c == j);
+        if (lane == 0 && m) atomicAdd(&cls[j], (uint32_t)__popcll(m));   // (result unused)
+    }
+    uint32_t mx = (uint32_t)ns;
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 0 && mx) atomicMax(&cls[2 * kVerifyClasses], mx);
 }
 
-__global__ void k_verify_lists(const int64_t *__restrict__ qoff, const uint32_t *__restrict__ need,
-                               const int64_t *__restrict__ need_off, uint32_t *__restrict__ cls, int64_t ng,
-                               int64_t *__restrict__ big_off, int32_t *__restrict__ order, int32_t *__restrict__ n_blk)
+__global__ __launch_bounds__(256) void k_verify_lists(const int64_t *__restrict__ qoff, const uint32_t *__restrict__ need,
+                                                      const int64_t *__restrict__ need_off, uint32_t *__restrict__ cls,
+                                                      int64_t ng, int64_t *__restrict__ big_off,
+                                                      int32_t *__restrict__ order, int32_t *__restrict__ n_blk)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0) *n_blk = (int32_t)cls[0];
-    if (q >= ng) return;
-    big_off[q] = need[q] ? need_off[q] : -1;
-    const int c = verify_class(qoff[q + 1] - qoff[q]);
-    uint32_t base = 0;
-    for (int j = 0; j < c; j++) base += cls[j];
-    order[base + atomicAdd(&cls[kVerifyClasses + c], 1u)] = (int32_t)q;
+    const int lane = threadIdx.x & 63;
+    if (q == 0 && n_blk) *n_blk = (int32_t)cls[0];
+    const bool valid = q < ng;
+    if (valid) big_off[q] = need[q] ? need_off[q] : -1;
+    const int c = valid ? verify_class(qoff[q + 1] - qoff[q]) : -1;
+    // one cursor reservation per class per wave, each lane ranked among the
+    // wave's lanes of its class
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t slot = -1;
+#pragma unroll
+    for (int j = 0; j < kVerifyClasses; j++) {
+        const uint64_t m = dev::ballot(c == j);
+        if (!m) continue;
+        // (every lane issues the atomic, lane 0 with the count: no
+        // lane-divergent control flow around the cross-lane read)
+        uint32_t base = 0;
+        for (int i = 0; i < j; i++) base += cls[i];
+        const uint32_t got = atomicAdd(&cls[kVerifyClasses + j], lane == 0 ? (uint32_t)__popcll(m) : 0u);
+        const uint32_t at = base + (uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+        if (c == j) slot = (int32_t)(at + (uint32_t)__popcll(m & below));
+    }
+    if (valid) order[slot] = (int32_t)q;
 }
 
-void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off, uint32_t *cls,
-                 int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st)
+void verify_plan_count(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off,
+                       uint32_t *cls, hipStream_t st)
 {
     const unsigned g = (unsigned)((ng + 256) / 256);
-    fill_u32(cls, 2 * kVerifyClasses, 0u, st);
+    fill_u32(cls, kVerifyPlanWords, 0u, st);
     hipLaunchKernelGGL(k_verify_need, dim3(g), dim3(256), 0, st, qoff, ng, sort_cap, need, cls);
-    check_launch("verify_plan(need)");
+    check_launch("verify_plan_count");
     scan_u32(need, ng, need_off, st);
-    hipLaunchKernelGGL(k_verify_lists, dim3(g), dim3(256), 0, st, qoff, need, need_off, cls, ng, big_off, order, n_blk);
-    check_launch("verify_plan(lists)");
+}
+
+void verify_plan_lists(const int64_t *qoff, int64_t ng, const uint32_t *need, const int64_t *need_off, uint32_t *cls,
+                       int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st)
+{
+    const unsigned g = (unsigned)((ng + 256) / 256);
+    hipLaunchKernelGGL(k_verify_lists, dim3(g), dim3(256), 0, st, qoff, need, need_off, cls, ng, big_off, order,
+                       n_blk);
+    check_launch("verify_plan_lists");
 }
 
 // ---------------------------------------------------------------------------

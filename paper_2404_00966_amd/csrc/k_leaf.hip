@@ -304,7 +304,8 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
                                                     int dp, const float *__restrict__ Q32,
                                                     const int32_t *__restrict__ kq, int64_t nq,
                                                     const uint32_t *__restrict__ tomb, int target,
-                                                    float *__restrict__ tq, unsigned long long *__restrict__ counters)
+                                                    float *__restrict__ tq, unsigned long long *__restrict__ counters,
+                                                    int only_unbounded)
 {
     __shared__ float s_d[kWinObj];
     __shared__ int s_first[kNearLeaves], s_start[kNearLeaves + 1];
@@ -316,6 +317,7 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
     if (q >= nq) return;
     const int k = kq[q];
     if (k <= 0) return;
+    if (only_unbounded && tq[q] < INFINITY) return;   // bounded by the MFMA kernel
     // the window: a prefix of the nearest leaves; each condition that ends it
     // (a missing leaf, more than kWinObj objects, max(k, target) reached) is
     // monotone along the list, so lane i is in the window iff it passes all
@@ -394,13 +396,235 @@ __global__ __launch_bounds__(256) void k_bound_near(const int32_t *__restrict__ 
 
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
-                unsigned long long *counters, hipStream_t st)
+                unsigned long long *counters, hipStream_t st, bool only_unbounded)
 {
     if (nq == 0) return;
     require(dp <= 128, "bound_near: rows wider than 128 floats");
     const unsigned grid = (unsigned)((nq + 8 * kBoundRun - 1) / (8 * kBoundRun) * (8 * kBoundRun));
     hipLaunchKernelGGL(k_bound_near, dim3(grid), dim3(256), 0, st, near, leaf_first, leaf_cnt, X32, dp, Q32,
-                       kq, nq, tomb, target, tq, counters);
+                       kq, nq, tomb, target, tq, counters, only_unbounded ? 1 : 0);
+    check_launch(__func__);
+}
+
+// ---------------------------------------------------------------------------
+// kNN radius bound by bf16 MFMA.  One workgroup per 16-query block of the
+// home order.  The block's window is a set of distinct whole 16-row groups of
+// the leaf order: the groups covering the leaves of its kNN queries'
+// nearest-leaf lists, list position by list position (every query's nearest
+// leaf first), at most kMbGroups of them.  Every kNN query of the block whose
+// nearest leaf lies wholly in the window gets
+// the bf16 estimate of its squared distance to every live object of the
+// window (its own nearest leaves and its neighbours'), turned into the upper
+// end of the estimate's proven interval (the same bound as the candidate
+// selection); the k-th smallest upper end is at least the k-th smallest true
+// distance over the window, whose objects are live objects of the index, so
+// it bounds the k-th nearest neighbour distance from above.  A query whose
+// nearest leaf is not in the window, or whose window holds fewer than k live
+// objects, gets +inf (the exact kernel then takes it).  The window's group list: per list entry its leaf's group
+// range, kept at the leaf's first occurrence (a scan gives each kept range
+// its place), then each group kept at its first occurrence (neighbouring
+// leaves share their boundary group; an object counted twice would make the
+// k-th value too small).
+// ---------------------------------------------------------------------------
+constexpr int kMbGroups = 64;                 // 16-row groups per window
+constexpr int kMbRows = 16 * kMbGroups;
+constexpr int kMbEntries = 16 * kNearLeaves;  // (list position, query) entries of a block
+constexpr int kMbWaves = 8;                   // waves per workgroup
+constexpr int kMbBatch = 2;                   // groups whose loads a wave issues together
+static_assert(kMbGroups % (kMbWaves * kMbBatch) == 0, "whole batches of groups");
+static_assert(kMbEntries == 128, "two waves hold the entries");
+
+template <int KS>
+__global__ __launch_bounds__(64 * kMbWaves) void k_bound_mfma(const uint4 *__restrict__ X16t, const float *__restrict__ xn,
+                                                    const float *__restrict__ xe, int64_t n,
+                                                    const int32_t *__restrict__ near,
+                                                    const int32_t *__restrict__ leaf_first,
+                                                    const int32_t *__restrict__ leaf_cnt,
+                                                    const uint4 *__restrict__ Q16t, const float *__restrict__ qn,
+                                                    const float *__restrict__ qe, const int32_t *__restrict__ kq,
+                                                    int64_t nq, const uint32_t *__restrict__ tomb, float eps_a,
+                                                    float eps_b, float eps_c, float *__restrict__ tq,
+                                                    unsigned long long *__restrict__ counters)
+{
+    __shared__ int32_t s_leaf[kMbEntries], s_glo[kMbEntries], s_first[kMbEntries];
+    __shared__ uint8_t s_full[kMbEntries];
+    __shared__ int32_t s_grp[kMbGroups];
+    __shared__ int s_tot[2];
+    __shared__ float s_hi[16][kMbRows + 1];
+    const int64_t blk = blockIdx.x;
+    const int t = (int)threadIdx.x, wave = t >> 6, lane = t & 63;
+    // entry t = (list position t / 16, query t % 16): its leaf's group range
+    int gn = 0;
+    if (t < kMbEntries) {
+        const int j = t >> 4, c = t & 15;
+        const int64_t q = blk * 16 + c;
+        int32_t leaf = -1;
+        int glo = 0;
+        if (q < nq && kq[q] > 0) {
+            leaf = near[q * kNearLeaves + j];
+            const int cnt = leaf >= 0 ? leaf_cnt[leaf] : 0;
+            if (cnt > 0) {
+                const int first = leaf_first[leaf];
+                glo = first >> 4;
+                gn = ((first + cnt - 1) >> 4) - glo + 1;
+            } else {
+                leaf = -1;
+            }
+        }
+        s_leaf[t] = leaf;
+        s_glo[t] = glo;
+    }
+    __syncthreads();
+    int off = 0;
+    if (t < kMbEntries) {
+        const int32_t leaf = s_leaf[t];
+        int fst = t;                           // the first entry holding this leaf
+        for (int i = t - 1; i >= 0 && leaf >= 0; i--)
+            if (s_leaf[i] == leaf) fst = i;
+        if (fst != t) gn = 0;
+        s_first[t] = fst;
+        int tot;
+        off = dev::wave_excl_scan(gn, &tot);
+        if (lane == 0) s_tot[wave] = tot;
+    }
+    __syncthreads();
+    const int total = s_tot[0] + s_tot[1];
+    if (total == 0) {
+        // no leaf in any list of the block (uniform): its kNN queries, if
+        // any, go to the exact kernel
+        if (t < 16 && blk * 16 + t < nq && kq[blk * 16 + t] > 0) tq[blk * 16 + t] = INFINITY;
+        return;
+    }
+    if (t < kMbEntries) {
+        if (wave == 1) off += s_tot[0];
+        const int glo = s_glo[t];
+        for (int u = 0; u < gn && off + u < kMbGroups; u++) s_grp[off + u] = glo + u;
+        // a leaf's groups are all in the window when its first entry's
+        // range ended inside it
+        s_full[t] = s_leaf[t] >= 0 && gn > 0 && off + gn <= kMbGroups ? 1 : 0;
+    }
+    const int ng = total < kMbGroups ? total : kMbGroups;
+    __syncthreads();
+    int32_t my_grp = -1;
+    if (t < ng) {
+        my_grp = s_grp[t];
+        for (int i = 0; i < t; i++)
+            if (s_grp[i] == my_grp) my_grp = -1;
+    }
+    __syncthreads();
+    if (t < kMbGroups) s_grp[t] = t < ng ? my_grp : -1;
+    __syncthreads();
+    // estimates: wave w takes groups w, w + 8, ...; the loads of
+    // kMbBatch groups are issued before any of them is used.  Lane
+    // (rgrp, col) holds rows 4 rgrp + e of a group for query col.
+    const int col = lane & 15, rgrp = lane >> 4;
+    const int64_t qc = blk * 16 + col;
+    uint4 B[KS];
+#pragma unroll
+    for (int s2 = 0; s2 < KS; s2++) B[s2] = Q16t[(blk * KS + s2) * 64 + lane];
+    const float qnn = qn[qc], qerr = qe[qc];   // (the query arrays are padded to whole 64-query tiles)
+    for (int gb = wave; gb < kMbGroups; gb += kMbWaves * kMbBatch) {
+        uint4 A[kMbBatch][KS];
+        float xnv[kMbBatch][4], xev[kMbBatch][4];
+        uint32_t lv[kMbBatch];                 // live bits of the lane's 4 rows
+#pragma unroll
+        for (int bb = 0; bb < kMbBatch; bb++) {
+            const int32_t g = s_grp[gb + bb * kMbWaves];
+            lv[bb] = 0u;
+#pragma unroll
+            for (int s2 = 0; s2 < KS; s2++)
+                A[bb][s2] = g >= 0 ? X16t[((int64_t)g * KS + s2) * 64 + lane] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t row = (int64_t)(g >= 0 ? g : 0) * 16 + 4 * rgrp + e;
+                xnv[bb][e] = g >= 0 ? xn[row] : 0.f;
+                xev[bb][e] = g >= 0 ? xe[row] : 0.f;
+                if (g >= 0 && row < n && !((tomb[row >> 5] >> (row & 31)) & 1u)) lv[bb] |= 1u << e;
+            }
+        }
+#pragma unroll
+        for (int bb = 0; bb < kMbBatch; bb++) {
+            floatx4_t acc = {-0.5f * xnv[bb][0], -0.5f * xnv[bb][1], -0.5f * xnv[bb][2], -0.5f * xnv[bb][3]};
+#pragma unroll
+            for (int s2 = 0; s2 < KS; s2++)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(A[bb][s2]), frag(B[s2]), acc, 0, 0, 0);
+            const int gi = gb + bb * kMbWaves;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float est = fmaf(-2.f, acc[e], qnn);
+                const float eps = eps_a * (qnn + xnv[bb][e]) + eps_b * sqrtf(qnn * xnv[bb][e]) + eps_c * fabsf(est);
+                const float hi = sqrtf(fmaxf(est + eps, 0.f)) + qerr + xev[bb][e];
+                s_hi[col][gi * 16 + 4 * rgrp + e] = (lv[bb] >> e) & 1u ? hi : INFINITY;
+            }
+        }
+    }
+    __syncthreads();
+    // per query the k-th smallest upper end: wave w takes queries 2w and
+    // 2w + 1, each lane kMbRows / 64 values; the smallest v with
+    // #{hi <= v} >= k by a binary search over the float bits (hi >= 0: float
+    // order = bit order)
+    unsigned long long evals = 0;
+    for (int cq = 0; cq < 16 / kMbWaves; cq++) {
+        const int c = (16 / kMbWaves) * wave + cq;
+        const int64_t q = blk * 16 + c;
+        const int k = q < nq ? kq[q] : 0;     // (uniform over the wave)
+        if (k <= 0) continue;
+        // a query whose nearest leaf is not wholly in the window has no
+        // good bound here: the exact kernel takes it
+        const int32_t l0 = s_leaf[c];          // entry (position 0, query c)
+        if (l0 < 0 || !s_full[s_first[c]]) {
+            if (lane == 0) tq[q] = INFINITY;
+            continue;
+        }
+        uint32_t hvb[kMbRows / 64];
+        int live = 0;
+#pragma unroll
+        for (int u = 0; u < kMbRows / 64; u++) {
+            hvb[u] = __float_as_uint(s_hi[c][lane + 64 * u]);
+            live += __popcll(dev::ballot(hvb[u] < 0x7f800000u));
+        }
+        float b = INFINITY;
+        if (k <= live) {
+            uint32_t lo_v = 0u, hi_v = 0x7f800000u;
+            while (lo_v < hi_v) {
+                const uint32_t mid = lo_v + ((hi_v - lo_v) >> 1);
+                int cnt = 0;
+#pragma unroll
+                for (int u = 0; u < kMbRows / 64; u++) cnt += __popcll(dev::ballot(hvb[u] <= mid));
+                if (cnt >= k) hi_v = mid;
+                else lo_v = mid + 1u;
+            }
+            b = __uint_as_float(lo_v);
+        }
+        if (lane == 0) tq[q] = b;
+        evals += (unsigned long long)live;
+    }
+    if (lane == 0 && evals) count_add(counters, CNT_BOUND_EVALS, evals);
+}
+
+void bound_mfma(const uint16_t *X16t, const float *xn, const float *xe, int64_t n, int ksteps, const int32_t *near,
+                const int32_t *leaf_first, const int32_t *leaf_cnt, const uint16_t *Q16t, const float *qn,
+                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, float *tq,
+                unsigned long long *counters, hipStream_t st)
+{
+    if (nq == 0) return;
+    require(ksteps >= 1 && ksteps <= 4, "bound_mfma: rows wider than 128 floats");
+    const float u = 5.9604645e-8f;
+    const int D = ksteps * 32;
+    const float eps_a = 2.f * (D + 8) * u, eps_b = 2.f * (4 * D + 8) * u, eps_c = 8.f * u;
+    const unsigned grid = (unsigned)((nq + 15) / 16);
+#define BM(KS)                                                                                                 \
+    hipLaunchKernelGGL(k_bound_mfma<KS>, dim3(grid), dim3(64 * kMbWaves), 0, st,                                \
+                       reinterpret_cast<const uint4 *>(X16t), xn,                                                \
+                       xe, n, near, leaf_first, leaf_cnt, reinterpret_cast<const uint4 *>(Q16t), qn, qe, kq, nq,   \
+                       tomb, eps_a, eps_b, eps_c, tq, counters)
+    switch (ksteps) {
+    case 1: BM(1); break;
+    case 2: BM(2); break;
+    case 3: BM(3); break;
+    default: BM(4); break;
+    }
+#undef BM
     check_launch(__func__);
 }
 

@@ -8,6 +8,17 @@
 namespace gts {
 namespace k {
 
+// L2 verification: queries with more than kVerifyBlockMin candidates are
+// verified by a whole workgroup; the verification order takes them first
+// (class 0), then the others by decreasing candidate count (classes 1..4),
+// so the longest start first.
+constexpr int kVerifyBlockMin = 512;
+constexpr int kVerifyClasses = 5;
+__host__ __device__ inline int verify_class(int64_t ns)
+{
+    return ns > kVerifyBlockMin ? 0 : ns > 256 ? 1 : ns > 128 ? 2 : ns > 64 ? 3 : 4;
+}
+
 // Slots of the device counters behind gts_stats.
 enum {
     CNT_NODE_TESTS = 0,
@@ -353,12 +364,19 @@ constexpr int kVerifyCursorStride = 32;         // words between the work-queue 
 constexpr int kVerifyCursorWords = 8 * kVerifyCursorStride;
 void verify_l2(const VerifyArgs &a, const L2View &o, const QueryL2 &qv, float delta, const int32_t *order, int n_blk,
                bool est, bool check, hipStream_t st, bool l1, const int32_t *n_blk_dev, uint32_t *ctr);
-// The verification plan made on the device: big_off (-1 or the query's
-// scratch run) and the verification order with its workgroup count *n_blk
-// (queries by verify_class; within a class in no fixed order); need [ng],
-// need_off [ng + 1] and cls [2 kVerifyClasses] are workspace.
-void verify_plan(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off, uint32_t *cls,
-                 int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st);
+// The verification plan made on the device, in two steps.  Counts: need
+// [ng] (each query's power-of-two scratch run, 0 when its keys fit the LDS
+// sort), need_off [ng + 1] (their scan; need_off[ng] the scratch words),
+// cls [kVerifyPlanWords] (cleared here): the queries per verify_class, then
+// the classes' cursors, then the largest candidate count.  Lists: big_off
+// (-1 or the query's scratch run) and the verification order (queries by
+// class; within a class in no fixed order), *n_blk (may be null) the
+// workgroup count.
+constexpr int kVerifyPlanWords = 2 * kVerifyClasses + 1;
+void verify_plan_count(const int64_t *qoff, int64_t ng, int64_t sort_cap, uint32_t *need, int64_t *need_off,
+                       uint32_t *cls, hipStream_t st);
+void verify_plan_lists(const int64_t *qoff, int64_t ng, const uint32_t *need, const int64_t *need_off, uint32_t *cls,
+                       int64_t *big_off, int32_t *order, int32_t *n_blk, hipStream_t st);
 // band_only: every cutoff floor(base[q]) of the launch is at most 63.
 void verify_edit(const VerifyArgs &a, const EditView &o, const QueryEdit &qv, bool band_only, hipStream_t st);
 
@@ -397,8 +415,18 @@ void leaf_ball(const uint16_t *PL16t, const float *pln, const float *ple, const 
                int ksteps, const uint16_t *Q16t, const float *qn, const float *qe, const float *T, int64_t nq,
                int ntiles, uint64_t *leaf_mask, const int32_t *leaf_cnt, unsigned long long *counters,
                hipStream_t st);
+// only_unbounded: skip the kNN queries whose tq is already finite (bounded
+// by bound_mfma).
 void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *leaf_cnt, const float *X32, int dp,
                 const float *Q32, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
+                unsigned long long *counters, hipStream_t st, bool only_unbounded = false);
+// kNN bound of every kNN query from bf16 MFMA estimates over a window of
+// whole 16-row groups shared by its 16-query block (the groups of the
+// block's nearest leaves): tq = the k-th smallest upper interval end, or
+// +inf when the window holds fewer than k live objects.
+void bound_mfma(const uint16_t *X16t, const float *xn, const float *xe, int64_t n, int ksteps, const int32_t *near,
+                const int32_t *leaf_first, const int32_t *leaf_cnt, const uint16_t *Q16t, const float *qn,
+                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, float *tq,
                 unsigned long long *counters, hipStream_t st);
 void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st);
 // Stable sort of n (key, value) pairs by the low `bits` bits of the keys, in
