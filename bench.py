@@ -206,7 +206,8 @@ def run_l2(args, gts, synth, torch, np):
         tg, perg = timed_steps(plan.launch, args.steps, args.warmup)
         got, gst = plan.result()
         out["graph_plan"] = {"qps": nq * args.steps / tg, "ms_per_step": tg * 1e3 / args.steps,
-                             "p50_ms": pct(perg, 50), "status": gst, "same_answers": same_answers(ref, got)}
+                             "p50_ms": pct(perg, 50), "p99_ms": pct(perg, 99), "status": gst,
+                             "same_answers": same_answers(ref, got)}
         log(f"l2 graph plan: {out['graph_plan']}")
         plan.close()
     if args.side_steps > 0:
@@ -934,14 +935,21 @@ def main():
     if args.cpu_queries > 0:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(args, l2data, dnadata, np)
+    # the headline step is the recorded graph of the batch (gts_plan_*) when
+    # its answers equal the eager call's; the eager call is reported beside it
+    gp = l2.get("graph_plan")
+    use_graph = bool(gp and gp["status"] == 0 and gp["same_answers"])
+    eager = {"qps": l2["qps"], "ms_per_step": l2["ms_per_step"], "p50_ms": pct(l2["per_step_ms"], 50),
+             "p99_ms": pct(l2["per_step_ms"], 99)}
+    head = gp if use_graph else eager
     line = {
         "metric": METRIC,
-        "value": l2["qps"],
+        "value": head["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": l2["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -950,14 +958,18 @@ def main():
         "config": {"workload": "l2_1m_d128", "n": l2["n"], "dim": l2["dim"], "queries": l2["nq"],
                    "knn_k": l2["k"], "knn_queries": l2["nq"] // 2, "range_queries": l2["nq"] // 2,
                    "range_r": l2["r"], "pivots": 16, "fanout": 16, "leaf": 256},
-        "p50_ms": pct(l2["per_step_ms"], 50),
-        "p99_ms": pct(l2["per_step_ms"], 99),
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
         "latency_note": "batched: every query of a step completes with the step (makespan)",
-        "value_note": "queries and index resident in HBM, answers left in device memory; host_to_host "
-                      "hands queries over in pinned host memory and returns answers to host memory",
+        "value_note": ("one step = the whole batch through the recorded graph of a search plan (gts_plan_launch: "
+                       "every stage on the device, no host synchronisation inside the step), answers identical to "
+                       "the eager gts_search call (`eager`)" if use_graph else "one step = one eager gts_search call")
+                      + "; queries and index resident in HBM, answers left in device memory; host_to_host hands "
+                      "queries over in pinned host memory and returns answers to host memory",
         "dist_evals_per_s": l2["dist_evals_per_s"],
+        "eager": eager,
         "host_to_host": l2.get("host_to_host"),
-        "graph_plan": l2.get("graph_plan"),
+        "graph_plan": gp,
         "plain": l2.get("plain"),
         "fp32_selection": l2.get("fp32_selection"),
         "no_prune": l2.get("no_prune"),
