@@ -200,6 +200,23 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
             R[r][e] = leaf < n_leaves ? leafR[leaf] : -INFINITY;
         }
     }
+    // the query blocks' fragments and parameters, all requested before the
+    // first is used (blocks whose pairs all failed the box test skip theirs)
+    uint4 Ball[4][KS];
+    float qnv[4], qev[4], tqv[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const bool use = (box_any >> c) & 1ull;
+        const int64_t q = (int64_t)tile * 64 + 16 * c + col;
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+            Ball[c][s] = use ? Q16t[(((int64_t)tile * 4 + c) * KS + s) * 64 + lane] : make_uint4(0, 0, 0, 0);
+        const bool qv = use && q < nq;
+        qnv[c] = qv ? qn[q] : 0.f;
+        qev[c] = qv ? qe[q] : 0.f;
+        tqv[c] = qv ? T[q] : -INFINITY;
+    }
+#pragma unroll
     for (int c = 0; c < 4; c++) {
         if (!((box_any >> c) & 1ull)) {
             // every pair of this block already failed the box test
@@ -211,15 +228,8 @@ __global__ __launch_bounds__(256) void k_leaf_ball(const uint4 *__restrict__ PL1
             continue;
         }
         const int64_t q = (int64_t)tile * 64 + 16 * c + col;
-        uint4 B[KS];
-#pragma unroll
-        for (int s = 0; s < KS; s++) B[s] = Q16t[(((int64_t)tile * 4 + c) * KS + s) * 64 + lane];
-        float qnn = 0.f, qerr = 0.f, tq = -INFINITY;
-        if (q < nq) {
-            qnn = qn[q];
-            qerr = qe[q];
-            tq = T[q];
-        }
+        const uint4 *B = Ball[c];
+        const float qnn = qnv[c], qerr = qev[c], tq = tqv[c];
         floatx4_t acc[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[r] = floatx4_t{0.f, 0.f, 0.f, 0.f};

@@ -39,12 +39,32 @@ __device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t 
 // fanout when it divides 64 (the chunk then holds whole sibling groups),
 // else 64 with no parent test.
 // ---------------------------------------------------------------------------
+// A box staged as centres and half-widths (c[0..MP), r[0..MP)): the gap is
+// max_i |q_i - c_i| - r_i, one subtraction fewer per pivot than from the
+// bounds.  The halving and the subtractions each round once: the gap is
+// within 4 u (|q| + the largest pivot distance) of the exact one, far inside
+// the test's 2 delta (|q| + the largest pivot distance) margin, so no leaf
+// the exact test keeps is dropped.
+__device__ __forceinline__ void box_to_centre(float *lo_c, float *hi_r)
+{
+    const float lo = *lo_c, hi = *hi_r;
+    float c = 0.f, r;
+    if (!(lo <= hi)) r = -INFINITY;                              // empty: never entered
+    else if (lo == -INFINITY || hi == INFINITY) r = INFINITY;    // unbounded: no constraint
+    else {
+        c = 0.5f * (lo + hi);
+        r = 0.5f * (hi - lo);
+    }
+    *lo_c = c;
+    *hi_r = r;
+}
+
 template <int MP>
 __device__ __forceinline__ float box_gap_lds(const float *bx, const float *qp)
 {
     float g = -INFINITY;
 #pragma unroll
-    for (int i = 0; i < MP; i++) g = fmaxf(g, fmaxf(bx[i] - qp[i], qp[i] - bx[MP + i]));
+    for (int i = 0; i < MP; i++) g = fmaxf(g, fabsf(qp[i] - bx[i]) - bx[MP + i]);
     return g;
 }
 
@@ -95,6 +115,18 @@ __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box,
         }
         if (parents)
             for (int i = threadIdx.x; i < np * 2 * MP; i += blockDim.x) s_par[i] = box[(size_t)par0 * 2 * MP + i];
+        __syncthreads();
+        // bounds to centres and half-widths, in place
+        float *sb = reinterpret_cast<float *>(s_box4);
+        for (int i = threadIdx.x; i < nl * MP; i += blockDim.x) {
+            const int j = i / MP, p = i - j * MP;
+            box_to_centre(sb + j * 2 * MP + p, sb + j * 2 * MP + MP + p);
+        }
+        if (parents)
+            for (int i = threadIdx.x; i < np * MP; i += blockDim.x) {
+                const int j = i / MP, p = i - j * MP;
+                box_to_centre(s_par + j * 2 * MP + p, s_par + j * 2 * MP + MP + p);
+            }
         __syncthreads();
         uint64_t mine = 0;
         for (int pg = 0; pg < np; pg++) {
