@@ -49,6 +49,7 @@ KERNEL_SOURCES = {
     "k_verify_l2": ["k_final.hip"],
     "k_mfma_sweep": ["k_search.hip"],
     "k_bound_near": ["k_leaf.hip"],
+    "k_bound_mfma": ["k_leaf.hip"],
     "k_leaf_box": ["k_search.hip"],
     "k_leaf_ball": ["k_leaf.hip"],
     "k_leaf_near": ["k_leaf.hip"],
@@ -643,9 +644,8 @@ def rooflines_l2(st, dim, workload):
       k_verify_l2: per candidate its 16-byte record and the 8 bytes of its
         norm and rounding error, per float32 recheck one object row (4 * dim
         bytes), per answer its 8-byte key;
-      k_bound_near: the HBM bytes the profiler measured for it (its windows
-        overlap across neighbouring queries, so the rows it computes with are
-        mostly L2 hits), and 3 * dim flop per exact distance."""
+      k_bound_mfma (with k_bound_near for the queries it leaves open): 2 * Dk
+        flop per (query, window object) distance of the kNN bounds."""
     dk = (dim + 31) // 32 * 32
     ms = st["ms_stage"]
     out = {}
@@ -667,15 +667,13 @@ def rooflines_l2(st, dim, workload):
                                "24 B per candidate + 4*dim B per float32 recheck + 8 B per answer",
                                traffic(workload, "k_verify_l2"))
     t = ms["bound"]
-    tb = traffic(workload, "k_bound_near")
-    a = tb / (t * 1e-3) / 1e9 if tb and t > 0 else None
-    out["k_bound_near"] = _roof("hbm", a, HBM_PEAK_GBS, "GB/s", tb, t,
-                                "measured HBM bytes of the launch (profile); null when the profile is stale", tb)
-    fl = 3.0 * dim * st["bound_evals"]
-    af = fl / (t * 1e-3) / 1e12 if t > 0 else None
-    out["k_bound_near"]["fp32"] = {"achieved": af, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                   "frac": af / FP32_PEAK_TFLOPS if af else None, "work_per_launch": fl,
-                                   "work": "3*dim flop per exact distance of the kNN bound windows"}
+    fl = 2.0 * dk * st["bound_evals"]
+    a = fl / (t * 1e-3) / 1e12 if t > 0 else None
+    out["k_bound_mfma"] = _roof("mfma", a, BF16_PEAK_TFLOPS, "TFLOP/s", fl, t,
+                                "2*Dk flop per (query, window object) distance of the kNN bounds (bf16 MFMA over "
+                                "windows shared by 16-query blocks, and the exact windows of the queries those "
+                                "leave open); the stage time covers both kernels",
+                                traffic(workload, "k_bound_mfma"))
     return out
 
 
