@@ -173,7 +173,7 @@ def run_l2(args, gts, synth, torch, np):
     log(f"index built in {build_s:.1f}s: {idx.info()}")
     # let the index's query context settle its tuned knob (untimed)
     tune_calls = 0
-    for tune_calls in range(1, 17):
+    for tune_calls in range(1, 33):
         idx.search(Q, radius=radius, k=k, result="device")
         if idx.stats()["tuning"] == 0:
             break
@@ -285,7 +285,7 @@ def run_l4m(args, gts, synth, torch, np):
     idx = gts.Index(torch.from_numpy(X).cuda(), gts.L2_F32, num_pivots=w["pivots"], fanout=w["fanout"],
                     leaf_size=w["leaf"], seed=w["seed"])
     Q = torch.from_numpy(KQ).cuda()
-    for _ in range(16):
+    for _ in range(32):
         idx.knn(Q, w["k"], result="device")
         if idx.stats()["tuning"] == 0:
             break
@@ -414,7 +414,7 @@ def run_fanout_sweep(args, gts, synth, torch, np):
         t = time.perf_counter()
         idx = gts.Index(X, gts.L2_F32, num_pivots=w["pivots"], fanout=F, leaf_size=w["leaf"], seed=w["seed"])
         build_s = time.perf_counter() - t
-        for _ in range(16):
+        for _ in range(32):
             idx.search(Q, radius=radius, k=k, result="device")
             if idx.stats()["tuning"] == 0:
                 break
