@@ -238,7 +238,7 @@ void update_batch(gts_index *idx, const HostObjects &ins, const int64_t *del, in
 //     memory latency, fewer keeps the work-stealing tail short.
 // A context tries each window (kNN batches only) on a few batches with the
 // default grid, then each grid with the best window, and keeps the setting
-// with the lowest time per query.  Settings are remembered per shape key
+// with the lowest time per query; each shape key keeps its own trials.  Settings are remembered per shape key
 // (device, metric, dimension, pivots, fanout, log2 of the batch size, kNN
 // present) in the index's table, which a tune-cache file can preload and
 // which is written back when a key finishes tuning.
@@ -252,59 +252,72 @@ struct LaunchTuner {
     static constexpr int kTrials = 3;          // batches per setting (the fastest counts)
     static constexpr int kWindow[kWindows] = {128, 256, 512, 1024};
     static constexpr int kGridPerCu[kGrids] = {1, 2, 4};
-    std::string key;                           // shape being tuned ("" = none)
-    bool knn = false;
-    int trial = 0;                             // trials done for `key`
-    double ms_per_q[kWindows + kGrids] = {};
-    TuneSetting best;
-    int total() const { return (knn ? kWindows * kTrials : 0) + kGrids * kTrials; }
-    bool tuning() const { return !key.empty() && trial < total(); }
+    // trials of one shape key; a context tunes several keys at once, so
+    // batches of changing size (a server's) do not restart each other's trials
+    struct Progress {
+        bool knn = false;
+        int trial = 0;                         // trials done
+        double ms_per_q[kWindows + kGrids] = {};
+        TuneSetting best;
+        int total() const { return (knn ? kWindows * kTrials : 0) + kGrids * kTrials; }
+    };
+    std::map<std::string, Progress> keys;      // keys still tuning
+    bool last_tuning = false;                  // the last call's key was still tuning
+    bool tuning() const { return last_tuning; }
     // The setting of a call on shape `k`; *trying is set when it is a trial.
     TuneSetting pick(const std::string &k, bool has_knn, const TuneSetting *known, bool *trying)
     {
         *trying = false;
-        if (known && (key != k || !tuning())) return *known;
-        if (key != k) {
-            key = k;
-            knn = has_knn;
-            trial = 0;
-            best = TuneSetting{};
-            for (double &v : ms_per_q) v = 0.0;
+        last_tuning = false;
+        if (known) {
+            keys.erase(k);
+            return *known;
         }
-        if (!tuning()) return best;
+        auto it = keys.find(k);
+        if (it == keys.end()) {
+            it = keys.emplace(k, Progress{}).first;
+            it->second.knn = has_knn;
+        }
+        Progress &p = it->second;
         *trying = true;
-        TuneSetting s = best;
-        const int wt = knn ? kWindows * kTrials : 0;
-        if (trial < wt) {
-            s.window = trial % kWindows;
+        last_tuning = true;
+        TuneSetting s = p.best;
+        const int wt = p.knn ? kWindows * kTrials : 0;
+        if (p.trial < wt) {
+            s.window = p.trial % kWindows;
             s.grid = 1;
         } else {
-            s.grid = (trial - wt) % kGrids;
+            s.grid = (p.trial - wt) % kGrids;
         }
         return s;
     }
-    // Time of the trial call; returns true when `key` has just finished.
-    bool record(double ms_per_query)
+    // Time of a trial call on key `k`; returns true (and the setting in
+    // *done) when `k` has just finished.
+    bool record(const std::string &k, double ms_per_query, TuneSetting *done)
     {
-        if (!tuning()) return false;
-        const int wt = knn ? kWindows * kTrials : 0;
+        auto it = keys.find(k);
+        if (it == keys.end()) return false;
+        Progress &p = it->second;
+        const int wt = p.knn ? kWindows * kTrials : 0;
         // the fastest trial of each setting (a slow one is noise: the first
         // call of a shape also allocates its workspace)
-        double &best_ms = trial < wt ? ms_per_q[trial % kWindows] : ms_per_q[kWindows + (trial - wt) % kGrids];
+        double &best_ms =
+            p.trial < wt ? p.ms_per_q[p.trial % kWindows] : p.ms_per_q[kWindows + (p.trial - wt) % kGrids];
         if (best_ms == 0.0 || ms_per_query < best_ms) best_ms = ms_per_query;
-        trial++;
-        if (knn && trial == wt) {
-            best.window = 0;
+        p.trial++;
+        if (p.knn && p.trial == wt) {
+            p.best.window = 0;
             for (int c = 1; c < kWindows; c++)
-                if (ms_per_q[c] < ms_per_q[best.window]) best.window = c;
+                if (p.ms_per_q[c] < p.ms_per_q[p.best.window]) p.best.window = c;
         }
-        if (trial == total()) {
-            best.grid = 0;
-            for (int c = 1; c < kGrids; c++)
-                if (ms_per_q[kWindows + c] < ms_per_q[kWindows + best.grid]) best.grid = c;
-            return true;
-        }
-        return false;
+        if (p.trial < p.total()) return false;
+        p.best.grid = 0;
+        for (int c = 1; c < kGrids; c++)
+            if (p.ms_per_q[kWindows + c] < p.ms_per_q[kWindows + p.best.grid]) p.best.grid = c;
+        *done = p.best;
+        keys.erase(it);
+        last_tuning = false;
+        return true;
     }
 };
 

@@ -1087,7 +1087,7 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
             // kernel takes the queries those leave unbounded
             k::bound_mfma(d.X16t.as<uint16_t>(), d.xn.as<float>(), d.xe.as<float>(), d.n, d.ksteps, near,
                           d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), qv.Q16t, qv.qn, qv.qe, kq,
-                          nq, b.tomb_bound, base, counters, st);
+                          nq, b.tomb_bound, window, base, counters, st);
             k::bound_near(near, d.tree.leaf_first.as<int32_t>(), d.tree.leaf_cnt.as<int32_t>(), d.X32.as<float>(),
                           d.dp, qv.Q32, kq, nq, b.tomb_bound, window, base, counters, st, true);
         } else if (l2) {
@@ -1378,9 +1378,10 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     for (int i = 0; i < 8; i++) cx->stats.ms_stage[i] = stage_ms[i];
     cx->stats.groups = (int64_t)groups.size();
     cx->stats.ms_total = now_ms() - t_start;
-    if (tune_trial && cx->tuner.record(cx->stats.ms_total / (double)nq)) {
+    TuneSetting settled;
+    if (tune_trial && cx->tuner.record(tkey, cx->stats.ms_total / (double)nq, &settled)) {
         std::lock_guard<std::mutex> lk(idx->tune_mu);
-        idx->tuned[tkey] = cx->tuner.best;
+        idx->tuned[tkey] = settled;
         tune_cache_store(idx);
     }
     cx->stats.tuning = cx->tuner.tuning() ? 1 : 0;

@@ -429,8 +429,10 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
 // selection); the k-th smallest upper end is at least the k-th smallest true
 // distance over the window, whose objects are live objects of the index, so
 // it bounds the k-th nearest neighbour distance from above.  A query whose
-// nearest leaf is not in the window, or whose window holds fewer than k live
-// objects, gets +inf (the exact kernel then takes it).  The window's group list: per list entry its leaf's group
+// exact-kernel window (the leading leaves of its list) is not wholly in the
+// block's window gets +inf and the exact kernel takes it (its k-th value
+// would otherwise come from the leaves of other queries of the block, which
+// can be far from it).  The window's group list: per list entry its leaf's group
 // range, kept at the leaf's first occurrence (a scan gives each kept range
 // its place), then each group kept at its first occurrence (neighbouring
 // leaves share their boundary group; an object counted twice would make the
@@ -452,11 +454,13 @@ __global__ __launch_bounds__(64 * kMbWaves) void k_bound_mfma(const uint4 *__res
                                                     const int32_t *__restrict__ leaf_cnt,
                                                     const uint4 *__restrict__ Q16t, const float *__restrict__ qn,
                                                     const float *__restrict__ qe, const int32_t *__restrict__ kq,
-                                                    int64_t nq, const uint32_t *__restrict__ tomb, float eps_a,
+                                                    int64_t nq, const uint32_t *__restrict__ tomb, int target,
+                                                    float eps_a,
                                                     float eps_b, float eps_c, float *__restrict__ tq,
                                                     unsigned long long *__restrict__ counters)
 {
     __shared__ int32_t s_leaf[kMbEntries], s_glo[kMbEntries], s_first[kMbEntries];
+    __shared__ int32_t s_rlo[kMbEntries], s_rend[kMbEntries];   // the entry leaf's rows
     __shared__ uint8_t s_full[kMbEntries];
     __shared__ int32_t s_grp[kMbGroups];
     __shared__ int s_tot[2];
@@ -469,20 +473,23 @@ __global__ __launch_bounds__(64 * kMbWaves) void k_bound_mfma(const uint4 *__res
         const int j = t >> 4, c = t & 15;
         const int64_t q = blk * 16 + c;
         int32_t leaf = -1;
-        int glo = 0;
+        int glo = 0, first = 0, cnt = 0;
         if (q < nq && kq[q] > 0) {
             leaf = near[q * kNearLeaves + j];
-            const int cnt = leaf >= 0 ? leaf_cnt[leaf] : 0;
+            cnt = leaf >= 0 ? leaf_cnt[leaf] : 0;
             if (cnt > 0) {
-                const int first = leaf_first[leaf];
+                first = leaf_first[leaf];
                 glo = first >> 4;
                 gn = ((first + cnt - 1) >> 4) - glo + 1;
             } else {
                 leaf = -1;
+                cnt = 0;
             }
         }
         s_leaf[t] = leaf;
         s_glo[t] = glo;
+        s_rlo[t] = q < nq && kq[q] > 0 && near[q * kNearLeaves + j] >= 0 ? first : -1;   // -1: the list ended
+        s_rend[t] = first + cnt;
     }
     __syncthreads();
     int off = 0;
@@ -586,6 +593,30 @@ __global__ __launch_bounds__(64 * kMbWaves) void k_bound_mfma(const uint4 *__res
             if (lane == 0) tq[q] = INFINITY;
             continue;
         }
+        // the exact kernel's window for this query (the prefix of its list
+        // up to max(k, target) objects, at most kWinObj) must lie wholly in
+        // the block's window, which then holds a superset of its objects:
+        // the k-th value is no looser than the exact kernel's but for the
+        // bf16 interval.  Otherwise (the k-th value would come from other
+        // queries' leaves, which can be far away) the exact kernel takes it.
+        const int want = k > target ? k : target;
+        int acc = 0;
+        bool inside = true;
+        for (int j = 0; j < kNearLeaves && acc < want; j++) {
+            const int e = j * 16 + c;
+            if (s_rlo[e] < 0) break;
+            const int cnt = s_rend[e] - s_rlo[e];
+            if (acc + cnt > kWinObj) break;
+            if (cnt > 0 && !s_full[s_first[e]]) {
+                inside = false;
+                break;
+            }
+            acc += cnt;
+        }
+        if (!inside) {
+            if (lane == 0) tq[q] = INFINITY;
+            continue;
+        }
         uint32_t hvb[kMbRows / 64];
         int live = 0;
 #pragma unroll
@@ -614,7 +645,7 @@ __global__ __launch_bounds__(64 * kMbWaves) void k_bound_mfma(const uint4 *__res
 
 void bound_mfma(const uint16_t *X16t, const float *xn, const float *xe, int64_t n, int ksteps, const int32_t *near,
                 const int32_t *leaf_first, const int32_t *leaf_cnt, const uint16_t *Q16t, const float *qn,
-                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, float *tq,
+                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
                 unsigned long long *counters, hipStream_t st)
 {
     if (nq == 0) return;
@@ -627,7 +658,7 @@ void bound_mfma(const uint16_t *X16t, const float *xn, const float *xe, int64_t 
     hipLaunchKernelGGL(k_bound_mfma<KS>, dim3(grid), dim3(64 * kMbWaves), 0, st,                                \
                        reinterpret_cast<const uint4 *>(X16t), xn,                                                \
                        xe, n, near, leaf_first, leaf_cnt, reinterpret_cast<const uint4 *>(Q16t), qn, qe, kq, nq,   \
-                       tomb, eps_a, eps_b, eps_c, tq, counters)
+                       tomb, target, eps_a, eps_b, eps_c, tq, counters)
     switch (ksteps) {
     case 1: BM(1); break;
     case 2: BM(2); break;

@@ -423,10 +423,11 @@ void bound_near(const int32_t *near, const int32_t *leaf_first, const int32_t *l
 // kNN bound of every kNN query from bf16 MFMA estimates over a window of
 // whole 16-row groups shared by its 16-query block (the groups of the
 // block's nearest leaves): tq = the k-th smallest upper interval end, or
-// +inf when the window holds fewer than k live objects.
+// +inf when the window holds fewer than k live objects or not the whole
+// window bound_near would read with the same target.
 void bound_mfma(const uint16_t *X16t, const float *xn, const float *xe, int64_t n, int ksteps, const int32_t *near,
                 const int32_t *leaf_first, const int32_t *leaf_cnt, const uint16_t *Q16t, const float *qn,
-                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, float *tq,
+                const float *qe, const int32_t *kq, int64_t nq, const uint32_t *tomb, int target, float *tq,
                 unsigned long long *counters, hipStream_t st);
 void gather_rows(const float *src, const int32_t *perm, int64_t rows, int dp, float *dst, hipStream_t st);
 // Stable sort of n (key, value) pairs by the low `bits` bits of the keys, in
