@@ -145,6 +145,33 @@ def test_l2_d128_several_tiles_ragged(gts, mode):
     idx.close()
 
 
+def test_knn_bound_small_incoherent_batches(gts):
+    # 200,000 x 128 from a 100-component mixture, leaves of up to 256 rows;
+    # batches of 8-48 kNN queries drawn from anywhere in the space (k 60-100),
+    # so a 16-query block shares its MFMA window with unrelated queries.  The
+    # bound must not take its k-th value from those queries' leaves: every
+    # query keeps a small candidate set (a few per cent of the objects at
+    # most), and the answers match the oracle.
+    d = synth.gaussian_mixture(401, 200_000, 128, 100, -5.0, 5.0, 1.0, 2000, 0)
+    X, pool = d["objects"], d["range_queries"]
+    _say("kNN bound, small incoherent batches on 200000 x 128")
+    idx = gts.Index(_dev(X), gts.L2_F32, num_pivots=16, fanout=16, leaf_size=256, seed=3)
+    rng = np.random.default_rng(9)
+    for nq in (8, 16, 48):
+        for rep in range(6):
+            q = pool[rng.choice(len(pool), nq, replace=False)]
+            k = rng.integers(60, 101, nq).astype(np.int32)
+            res = idx.search(_dev(q), k=k, result="device")
+            worst = int(idx.stats()["max_query_candidates"])
+            assert worst <= 5000, (nq, rep, worst)
+        lists = res.to_lists()
+        objs = O.ObjectSet(vecs=X)
+        for i in range(min(nq, 8)):
+            check_knn([lists[i]], O.knn_bf(objs, O.ObjectSet(vecs=q[i:i + 1]), int(k[i])), X, q[i:i + 1], int(k[i]))
+        _say(f"nq={nq}: largest candidate set {worst}, answers match the oracle")
+    idx.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_edit_dna_families(gts, mode):
     d = synth.dna_families(31337, 60, 80, 64, 128, 0.05, 2)
