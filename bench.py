@@ -799,7 +799,33 @@ def pmc_summary(dirs, workload, last, command):
     return "\n".join(lines)
 
 
-def stats_summary(d, title, command, top):
+def _last_dispatches(d, last, top):
+    """Per kernel, the mean duration of its last `last` dispatches in the
+    run's kernel trace (kernel_trace.csv): with a run whose final calls are
+    the timed steps, the figures of the launches the bench line reports."""
+    per = {}
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                per.setdefault(r["Kernel_Name"], []).append((t0, t1 - t0))
+    rows = []
+    for name, v in per.items():
+        v.sort()
+        tail = [x[1] for x in v[-last:]]
+        rows.append((sum(tail) / len(tail), len(tail), min(tail), max(tail), name))
+    rows.sort(key=lambda r: -r[0] * r[1])
+    lines = ["", f"Last {last} dispatches of each kernel (the timed steps and the stage-timed call "
+             "when they end the run):", "", "| kernel | dispatches | avg (us) | min (us) | max (us) |",
+             "|---|---:|---:|---:|---:|"]
+    for avg, n, lo, hi, name in rows[:top]:
+        m = re.search(r"(k_[A-Za-z0-9_]+(<[^>]*>)?)", name)
+        short = m.group(1) if m else name.split("(")[0][-60:]
+        lines.append(f"| `{short}` | {n} | {avg / 1e3:,.1f} | {lo / 1e3:,.1f} | {hi / 1e3:,.1f} |")
+    return lines
+
+
+def stats_summary(d, title, command, top, last=0):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     rows = []
     for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
@@ -816,6 +842,8 @@ def stats_summary(d, title, command, top):
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:,.1f} | {float(r['MinNs']) / 1e3:,.1f} | "
                      f"{float(r['MaxNs']) / 1e3:,.1f} | {float(r['TotalDurationNs']) / 1e6:,.2f} | "
                      f"{float(r['Percentage']):.1f} |")
+    if last > 0:
+        lines += _last_dispatches(d, last, top)
     return "\n".join(lines) + "\n"
 
 
@@ -841,6 +869,8 @@ def main():
     ap.add_argument("--stats-summary", metavar="DIR", help="summarise a rocprofv3 --stats run in DIR (no GPU work)")
     ap.add_argument("--stats-title", default="bench.py")
     ap.add_argument("--stats-top", type=int, default=40)
+    ap.add_argument("--stats-last", type=int, default=0,
+                    help="also list each kernel's mean over its last N dispatches (kernel trace)")
     ap.add_argument("--update-sweep", action="store_true",
                     help="update cost against the cache-list limit and the batch update, instead of the benchmark")
     ap.add_argument("--update-n", type=int, default=100000, help="objects of the update-sweep sets")
@@ -861,7 +891,7 @@ def main():
         print(pmc_summary(args.pmc_summary, args.pmc_workload, args.pmc_last, args.pmc_command))
         return
     if args.stats_summary:
-        print(stats_summary(args.stats_summary, args.stats_title, args.pmc_command, args.stats_top))
+        print(stats_summary(args.stats_summary, args.stats_title, args.pmc_command, args.stats_top, args.stats_last))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path; "
