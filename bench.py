@@ -7,8 +7,9 @@ Default workload (one step = one mixed batch through the whole search path):
 Reported alongside in the same JSON line:
   dna_500k: 500,000 DNA strings (1,000 families x 500 mutants), 8 pivots,
     fanout 8; 10,000 range queries r = 8 per step;
-  l2_4m_d96: 4,000,000 x 96 (1,000 components, sigma 0.5), 50,000 kNN
-    queries k = 32, bf16-guarded against float32 selection.
+  l2_4m_d96: 4,000,000 x 96 (1,000 components, sigma 0.5), 16 pivots,
+    fanout 2, leaf 512; 50,000 kNN queries k = 32, bf16-guarded against
+    float32 selection.
 
 `value` is the device-resident rate: queries and index in HBM when the timed
 region starts, answers left in device memory.  Each workload also reports
@@ -299,7 +300,8 @@ def run_l4m(args, gts, synth, torch, np):
     st["bound_violations"] = idx.stats()["bound_violations"]
     st["bound_checked"] = idx.stats()["verified"]
     out = {"qps": nq * steps / total, "ms_per_step": total * 1e3 / steps, "p99_ms": pct(per, 99), "nq": nq,
-           "k": w["k"], "stats": st}
+           "k": w["k"], "pivots": w["pivots"], "fanout": w["fanout"], "leaf": w["leaf"],
+           "n_leaves": idx.info()["n_leaves"], "stats": st}
     for name, kw in (("fp32_selection", {"precision": gts.FP32}), ("plain", {"mode": gts.MODE_PLAIN})):
         res = []
         tp, _ = timed_steps(lambda: res.append(idx.knn(Q, w["k"], result="device", **kw)), 1, 1)

@@ -176,11 +176,15 @@ WORKLOADS = {
     "dna_500k": dict(kind="dna", seed=966003, n_seeds=1000, per_seed=500,
                      min_len=64, max_len=128, rate=0.05, queries_per_seed=10,
                      radius=8, pivots=8, fanout=8, leaf=0),
-    # 4M x 96 L2, 1000 components, sigma 0.5; 16 pivots, fanout 16, leaf 256
+    # 4M x 96 L2, 1000 components, sigma 0.5; 16 pivots, fanout 2, leaf 512
+    # (no tree shape is given for this batch: the leaf count, a power of the
+    # fanout, sets the node filter's work; 8,192 leaves of about 490 objects
+    # gave the shortest step of the shapes measured, fanout 16 with leaf 256
+    # making 65,536 leaves of 61)
     "l2_4m_d96": dict(kind="l2", seed=966004, n=4_000_000, dim=96,
                       components=1000, lo=-5.0, hi=5.0, sigma=0.5,
-                      n_range=0, n_knn=50_000, k=32, pivots=16, fanout=16,
-                      leaf=256),
+                      n_range=0, n_knn=50_000, k=32, pivots=16, fanout=2,
+                      leaf=512),
 }
 
 
