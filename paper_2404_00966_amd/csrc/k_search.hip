@@ -26,9 +26,11 @@ __device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t 
 // contains the boxes of its children (minima and maxima over the same
 // objects), so a child can only pass where its parent passes: the walk from
 // the root keeps exactly the leaves whose own box admits the query.  Here
-// the leaves' parents are tested first and the leaves below a parent that no
-// query of the tile passes are not tested at all -- the same masks as the
-// full walk, without its per-level launches.
+// one ancestor level is tested first (the highest whose subtrees hold at
+// most 64 leaves: the parents when the fanout is 16 or 32, the level six up
+// for a binary tree) and the leaves below an ancestor that no query of the
+// tile passes are not tested at all -- the same masks as the full walk,
+// without its per-level launches.
 //
 // Lane = query: a workgroup is four 64-query tiles (one per wave, the pivot
 // distances and threshold of its query in registers) and a range of leaves,
@@ -36,8 +38,9 @@ __device__ __forceinline__ float box_gap(const float *__restrict__ box, int64_t 
 // are read as broadcasts.  One ballot per tested node gives the tile's 64-bit
 // query mask; lane j keeps the mask of the chunk's leaf j and stores it.
 // Writes leaf_mask[leaf][tile] for every leaf and tile.  `group` is the
-// fanout when it divides 64 (the chunk then holds whole sibling groups),
-// else 64 with no parent test.
+// number of leaves below one tested ancestor (a power of the fanout when the
+// fanout divides 64: the chunk then holds whole subtrees), else 64 with no
+// ancestor test; anc0 is the first node of the ancestors' level.
 // ---------------------------------------------------------------------------
 // A box staged as centres and half-widths (c[0..MP), r[0..MP)): the gap is
 // max_i |q_i - c_i| - r_i, one subtraction fewer per pivot than from the
@@ -70,7 +73,8 @@ __device__ __forceinline__ float box_gap_lds(const float *bx, const float *qp)
 
 template <int MP>
 __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box, int64_t leaf0, int64_t n_leaves,
-                                                  int group, bool parents, const float *__restrict__ QP,
+                                                  int group, bool parents, int64_t anc0,
+                                                  const float *__restrict__ QP,
                                                   const float *__restrict__ thr, int64_t nq, int ntiles,
                                                   int64_t leaves_per_blk, int64_t n_split,
                                                   uint64_t *__restrict__ leaf_mask,
@@ -79,7 +83,7 @@ __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box,
     constexpr int kChunkVec = 64 * 2 * MP / 4;              // float4 per chunk of 64 boxes
     constexpr int kPerThread = (kChunkVec + 255) / 256;
     __shared__ float4 s_box4[kChunkVec];
-    __shared__ float s_par[32 * 2 * MP];                    // parents of the chunk (group >= 2)
+    __shared__ float s_par[32 * 2 * MP];                    // ancestors of the chunk (group >= 2)
     const float *s_box = reinterpret_cast<const float *>(s_box4);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tg = blockIdx.x / n_split, sp = blockIdx.x % n_split;
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(256) void k_leaf_box(const float *__restrict__ box,
             const int i = u * 256 + (int)threadIdx.x;
             tv[u] = i < nv ? src[i] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const int64_t par0 = (leaf0 + c0 - 1) / group;      // parent of the chunk's first leaf
+        const int64_t par0 = anc0 + c0 / group;             // ancestor of the chunk's first leaf
 #pragma unroll
         for (int u = 0; u < kPerThread; u++) {
             const int i = u * 256 + (int)threadIdx.x;
@@ -157,13 +161,28 @@ void leaf_box(const TreeView &t, const float *QP, const float *thr, int64_t nq, 
     const int64_t lpb = 64 * per;
     const int64_t n_split = (t.n_leaves + lpb - 1) / lpb;
     const unsigned grid = (unsigned)(tgroups * n_split);
-    // sibling groups align with the 64-leaf chunks when the fanout divides 64
-    // (leaf0 - 1 is a multiple of the fanout)
+    // Leaves are tested below a passing ancestor: the one `up` levels above,
+    // whose `group` = fanout^up leaves (at most 64, aligned with the 64-leaf
+    // chunks when the fanout divides 64) are consecutive, so the chunk's
+    // ancestors are consecutive nodes of their level, the first of them at
+    // anc0.  A leaf's box lies inside every ancestor's box, so a query the
+    // ancestor fails fails each of its leaves: the masks are those of the
+    // leaf test alone.
     const bool parents = t.levels >= 1 && t.fanout >= 2 && 64 % t.fanout == 0;
-    const int group = parents ? t.fanout : 64;
+    int group = 64, up = 0;
+    if (parents) {
+        group = t.fanout;
+        up = 1;
+        while (up < t.levels && (int64_t)group * t.fanout <= 64) {
+            group *= t.fanout;
+            up++;
+        }
+    }
+    int64_t anc0 = t.leaf0;   // first node of the ancestors' level (heap order: parent(i) = (i - 1) / fanout)
+    for (int u = 0; u < up; u++) anc0 = (anc0 - 1) / t.fanout;
 #define LBX(MP)                                                                                                  \
     hipLaunchKernelGGL(k_leaf_box<MP>, dim3(grid), dim3(256), 0, st, t.box_aos, t.leaf0, t.n_leaves, group,     \
-                       parents, QP, thr, nq, ntiles, lpb, n_split, leaf_mask, counters)
+                       parents, anc0, QP, thr, nq, ntiles, lpb, n_split, leaf_mask, counters)
     if (t.mpad == 8) LBX(8);
     else if (t.mpad == 16) LBX(16);
     else LBX(32);
