@@ -641,6 +641,8 @@ bool run_group(gts_index *idx, QueryCtx *cx, const Batch &b, int64_t q0, int64_t
 
 namespace {
 
+constexpr int64_t kTuneMinQueries = 1024;   // smaller batches keep the default launch settings
+
 // "arch/cus|metric|dim|pivots|fanout|log2(nq)|knn": the shape a tuned
 // setting belongs to
 std::string tune_key(const gts_index *idx, int64_t nq, bool knn)
@@ -736,8 +738,12 @@ void search(gts_index *idx, QueryCtx *cx, const gts_objects *Q, const float *rad
     // tuned launch settings of the batched bf16 L2 path (answers never depend on them)
     std::string tkey;
     TuneSetting tset;
+    // (batches under kTuneMinQueries take the defaults: their time is mostly
+    // launch and host work, so trials there measure noise, and a server's
+    // many small batch sizes would each pay for a full set of trials)
     const bool tunable = d.metric == GTS_L2_F32 && !idx->l1 && b.mode == GTS_MODE_BATCHED &&
-                         b.precision == GTS_BF16_GUARDED && d.lpad > 0 && d.dim <= kMaxMfmaDim && b.nq > 0;
+                         b.precision == GTS_BF16_GUARDED && d.lpad > 0 && d.dim <= kMaxMfmaDim &&
+                         b.nq >= kTuneMinQueries;
     if (tunable && cx->graph) {
         // a recorded graph takes the settings eager calls of its shape have
         // settled on (the kNN key: its queries may hold kNN), else the defaults
